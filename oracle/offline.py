@@ -4,7 +4,8 @@ Sec. 4.3 Alg. 2 (LRBMS basis construction) and Sec. 4.4 (offline-online
 decomposition):
   * initial pressure/velocity and time-of-flight (Alg. 2 step 1a-1b);
   * mobility profiles from the time-of-flight (Alg. 2 step 1c), tested on the
-    cell mean of tau so that every profile lies in V_h; T = N_T dt;
+    cell mean of tau so that every profile lies in V_h; T = the simulated
+    horizon (the problem's t_end, else N_T dt);
   * snapshots at training mobilities gamma = sum_q mu_q Lambda^q;
   * local bases per coarse box E: optional unit function 1_E first, then
     Gram-Schmidt in L2(E) with rejection of relative norms <= 1e-8
@@ -219,7 +220,7 @@ def build_offline(grid, prob, params, s0=None):
     bases by Gram-Schmidt or PCA.  Returns a dict with everything."""
     p0, F0 = initial_flow(grid, prob, s0)
     tau = time_of_flight(grid, prob, F0)
-    T = prob.n_steps * prob.dt
+    T = prob.t_end if prob.t_end > 0 else prob.n_steps * prob.dt
     profiles = mobility_profiles(grid, prob, tau, prob.M, T)
     snaps = [fine_pressure(grid, prob, field=training_mobility(profiles, mu)) for mu in params]
     phis = local_bases(grid, prob, snaps)

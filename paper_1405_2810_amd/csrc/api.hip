@@ -1,0 +1,640 @@
+// C ABI of the LRBMS online step (include/lrbms.h): model creation, the four
+// online calls, inspection helpers and error reporting.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "model.h"
+
+namespace lrbms {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return false;
+}
+
+__global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+static int check_problem(const lrbms_problem* p) {
+  if (!p) return (set_error("problem is NULL"), LRBMS_E_ARG);
+  if (p->dim != 2 && p->dim != 3) return (set_error("dim must be 2 or 3"), LRBMS_E_ARG);
+  for (int a = 0; a < 3; ++a) {
+    const int na = (a < p->dim) ? p->n[a] : 1;
+    const int ca = (a < p->dim) ? p->nc[a] : 1;
+    if (a < p->dim && (p->n[a] < 1 || p->len[a] <= 0.0))
+      return (set_error("grid sizes and lengths must be positive"), LRBMS_E_ARG);
+    if (a >= p->dim && (p->n[a] != 1 || p->nc[a] != 1))
+      return (set_error("n[2] and nc[2] must be 1 in 2D"), LRBMS_E_ARG);
+    if (ca < 1 || ca > na) return (set_error("invalid number of coarse boxes"), LRBMS_E_ARG);
+    if (a < p->dim) {
+      if (!p->cuts[a]) return (set_error("cuts missing"), LRBMS_E_ARG);
+      if (p->cuts[a][0] != 0 || p->cuts[a][ca] != na)
+        return (set_error("cuts must start at 0 and end at n"), LRBMS_E_ARG);
+      for (int i = 0; i < ca; ++i)
+        if (p->cuts[a][i + 1] <= p->cuts[a][i])
+          return (set_error("cuts must be strictly increasing"), LRBMS_E_ARG);
+    }
+  }
+  if (!p->perm || !p->poro || !p->bc_type || !p->bc_val || !p->bc_sat || !p->bc_sval || !p->q1 ||
+      !p->q2)
+    return (set_error("problem array missing"), LRBMS_E_ARG);
+  if (!(p->visc_w > 0.0) || !(p->visc_o > 0.0)) return (set_error("viscosities must be > 0"), LRBMS_E_ARG);
+  if (p->relperm != 0 && p->relperm != 1) return (set_error("relperm must be 0 or 1"), LRBMS_E_ARG);
+  if (p->weights != 0 && p->weights != 1) return (set_error("weights must be 0 or 1"), LRBMS_E_ARG);
+  if (!(p->dt > 0.0)) return (set_error("dt must be > 0"), LRBMS_E_ARG);
+  if (!(p->penalty_c > 0.0)) return (set_error("penalty_c must be > 0"), LRBMS_E_ARG);
+  return LRBMS_OK;
+}
+
+template <typename T>
+static bool dev_copy(T** d, const T* h, size_t n, long long& bytes) {
+  if (!hip_ok(hipMalloc(d, std::max<size_t>(n, 1) * sizeof(T)), "hipMalloc")) return false;
+  bytes += (long long)(n * sizeof(T));
+  if (n && h) return hip_ok(hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return true;
+}
+
+template <typename T>
+static bool dev_zero(T** d, size_t n, long long& bytes) {
+  if (!hip_ok(hipMalloc(d, std::max<size_t>(n, 1) * sizeof(T)), "hipMalloc")) return false;
+  bytes += (long long)(n * sizeof(T));
+  return hip_ok(hipMemset(*d, 0, std::max<size_t>(n, 1) * sizeof(T)), "hipMemset");
+}
+
+Model::~Model() {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(d_subs);
+  f(d_ifaces);
+  f(d_perm);
+  f(d_poro);
+  f(d_q1);
+  f(d_q2);
+  f(d_bc_val);
+  f(d_bc_sval);
+  f(d_bc_type);
+  f(d_bc_sat);
+  f(d_phi);
+  f(d_mom);
+  f(d_blocks);
+  f(d_fN);
+  f(d_prof);
+  f(d_gchol);
+  f(d_theta);
+  f(d_partial);
+  f(d_c);
+  f(d_bq);
+  f(d_e);
+  f(d_dq);
+  f(d_tiles);
+  f(d_scratch_sat);
+  f(d_scratch_ph);
+  f(d_status);
+  solver_free(sdev);
+}
+
+// Fill geometry, boxes and interfaces (host side only).
+static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) {
+  Geom& g = M.g;
+  std::memset(&g, 0, sizeof(g));
+  g.dim = p->dim;
+  g.r = p->dim + 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < p->dim ? p->n[a] : 1;
+    g.h[a] = a < p->dim ? p->len[a] / p->n[a] : 1.0;
+    M.nc[a] = a < p->dim ? p->nc[a] : 1;
+  }
+  g.ncell = g.n[0] * g.n[1] * g.n[2];
+  g.vol = 1.0;
+  for (int a = 0; a < p->dim; ++a) g.vol *= g.h[a];
+  g.isv = 1.0 / std::sqrt(g.vol);
+  double he2 = 0.0;
+  for (int a = 0; a < p->dim; ++a) he2 += g.h[a] * g.h[a];
+  g.he = std::sqrt(he2);
+  int off = 0;
+  for (int a = 0; a < 3; ++a) {
+    int cnt = 0;
+    if (a < p->dim) {
+      int e[3] = {g.n[0], g.n[1], g.n[2]};
+      e[a] += 1;
+      cnt = e[0] * e[1] * e[2];
+    }
+    g.nfa[a] = cnt;
+    g.foff[a] = off;
+    off += cnt;
+    double area = 1.0, hf2 = 0.0;
+    for (int b = 0; b < p->dim; ++b)
+      if (b != a) {
+        area *= g.h[b];
+        hf2 += g.h[b] * g.h[b];
+      }
+    g.area[a] = area;
+    g.hf[a] = p->dim > 1 ? std::sqrt(hf2) : 1.0;
+  }
+  g.nface = off;
+  g.visc_w = p->visc_w;
+  g.visc_o = p->visc_o;
+  g.relperm = p->relperm;
+  g.cw = p->corey_w;
+  g.co = p->corey_o;
+  g.pen = p->penalty_c / std::max(p->visc_w, p->visc_o);
+  g.weights = p->weights;
+  g.sat_pen = p->sat_penalty_scale;
+  g.limiter = p->limiter;
+  g.dt = p->dt;
+  // boxes
+  M.subs.clear();
+  long long phi_off = 0, blk = 0;
+  int pn = 0;
+  for (int ez = 0; ez < M.nc[2]; ++ez)
+    for (int ey = 0; ey < M.nc[1]; ++ey)
+      for (int ex = 0; ex < M.nc[0]; ++ex) {
+        Sub s;
+        const int e[3] = {ex, ey, ez};
+        s.nE = 1;
+        for (int a = 0; a < 3; ++a) {
+          s.lo[a] = a < p->dim ? p->cuts[a][e[a]] : 0;
+          s.hi[a] = a < p->dim ? p->cuts[a][e[a] + 1] : 1;
+          s.nE *= s.hi[a] - s.lo[a];
+        }
+        const int id = (int)M.subs.size();
+        s.NE = sizes ? sizes[id] : 0;
+        s.phi_off = phi_off;
+        s.pn_off = pn;
+        s.blk_off = blk;
+        phi_off += (long long)s.NE * g.r * s.nE;
+        pn += s.NE;
+        blk += (long long)s.NE * s.NE;
+        M.subs.push_back(s);
+      }
+  M.n_sub = (int)M.subs.size();
+  M.N = pn;
+  M.phi_len = phi_off;
+  M.ifaces.clear();
+  for (int a = 0; a < p->dim; ++a)
+    for (int ez = 0; ez < M.nc[2]; ++ez)
+      for (int ey = 0; ey < M.nc[1]; ++ey)
+        for (int ex = 0; ex < M.nc[0]; ++ex) {
+          int e[3] = {ex, ey, ez};
+          if (e[a] + 1 >= M.nc[a]) continue;
+          const int lo = ex + M.nc[0] * (ey + M.nc[1] * ez);
+          e[a] += 1;
+          const int hi = e[0] + M.nc[0] * (e[1] + M.nc[1] * e[2]);
+          Iface I;
+          I.axis = a;
+          I.lo = lo;
+          I.hi = hi;
+          I.nf = 1;
+          for (int b = 0; b < 3; ++b)
+            if (b != a) I.nf *= M.subs[lo].hi[b] - M.subs[lo].lo[b];
+          I.blk_off = blk;
+          blk += (long long)M.subs[lo].NE * M.subs[hi].NE;
+          M.ifaces.push_back(I);
+        }
+  M.n_iface = (int)M.ifaces.size();
+  M.nblk = blk;
+  M.max_ne = 0;
+  for (auto& s : M.subs) M.max_ne = std::max(M.max_ne, s.NE);
+  return LRBMS_OK;
+}
+
+static int upload_problem(Model& M, const lrbms_problem* p) {
+  Geom& g = M.g;
+  long long& b = M.dev_bytes;
+  const size_t nc = g.ncell, nf = g.nface;
+  if (!dev_copy(&M.d_perm, p->perm, nc, b) || !dev_copy(&M.d_poro, p->poro, nc, b) ||
+      !dev_copy(&M.d_q1, p->q1, nc, b) || !dev_copy(&M.d_q2, p->q2, nc, b) ||
+      !dev_copy(&M.d_bc_val, p->bc_val, nf, b) || !dev_copy(&M.d_bc_sval, p->bc_sval, nf, b) ||
+      !dev_copy(&M.d_bc_type, p->bc_type, nf, b) || !dev_copy(&M.d_bc_sat, p->bc_sat, nf, b))
+    return LRBMS_E_OOM;
+  g.perm = M.d_perm;
+  g.poro = M.d_poro;
+  g.q1 = M.d_q1;
+  g.q2 = M.d_q2;
+  g.bc_val = M.d_bc_val;
+  g.bc_sval = M.d_bc_sval;
+  g.bc_type = M.d_bc_type;
+  g.bc_sat = M.d_bc_sat;
+  if (!dev_zero(&M.d_mom, (size_t)n_moments(g.dim) * nc, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_scratch_sat, (size_t)g.r * nc, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_scratch_ph, (size_t)g.r * nc, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_status, 1, b)) return LRBMS_E_OOM;
+  return LRBMS_OK;
+}
+
+// Cholesky of a small SPD matrix (row-major, lower factor in place). false if not SPD.
+static bool small_cholesky(std::vector<double>& A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    A[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = s / d;
+    }
+    for (int k = j + 1; k < n; ++k) A[j * n + k] = 0.0;
+  }
+  return true;
+}
+
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles) {
+  Geom& g = M.g;
+  long long& b = M.dev_bytes;
+  if (!dev_copy(&M.d_subs, M.subs.data(), M.subs.size(), b)) return LRBMS_E_OOM;
+  if (!dev_copy(&M.d_ifaces, M.ifaces.data(), M.ifaces.size(), b)) return LRBMS_E_OOM;
+  if (!dev_copy(&M.d_phi, basis, (size_t)M.phi_len, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_blocks, (size_t)M.nblk, b) || !dev_zero(&M.d_fN, (size_t)M.N, b))
+    return LRBMS_E_OOM;
+  // reconstruction tiles (box, first cell)
+  std::vector<int> tiles;
+  for (int s = 0; s < M.n_sub; ++s)
+    for (int c0 = 0; c0 < M.subs[s].nE; c0 += 256) {
+      tiles.push_back(s);
+      tiles.push_back(c0);
+    }
+  M.n_tiles = (int)tiles.size() / 2;
+  if (!dev_copy(&M.d_tiles, tiles.data(), tiles.size(), b)) return LRBMS_E_OOM;
+  // solver
+  if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, M.leaf_max, M.plan)) {
+    set_error("solver symbolic analysis failed");
+    return LRBMS_E_ARG;
+  }
+  if (!solver_upload(M.plan, M.sdev)) {
+    set_error("solver allocation failed");
+    return LRBMS_E_OOM;
+  }
+  b += M.sdev.bytes;
+  // profiles and the affine terms of Sec. 4.4
+  M.nprof = nprof;
+  if (nprof > 0) {
+    const size_t L = (size_t)g.r * g.ncell;
+    std::vector<double> G((size_t)nprof * nprof);
+    for (int i = 0; i < nprof; ++i)
+      for (int j = 0; j < nprof; ++j) {
+        double s = 0.0;
+        for (size_t k = 0; k < L; ++k) s += profiles[i * L + k] * profiles[j * L + k];
+        G[i * nprof + j] = s;
+      }
+    if (!small_cholesky(G, nprof)) {
+      set_error("profile Gram matrix is not positive definite (profiles must be independent)");
+      return LRBMS_E_ARG;
+    }
+    if (!dev_copy(&M.d_prof, profiles, (size_t)nprof * L, b) ||
+        !dev_copy(&M.d_gchol, G.data(), G.size(), b) || !dev_zero(&M.d_theta, (size_t)nprof, b))
+      return LRBMS_E_OOM;
+    M.lsq_blocks = std::min(1024, (g.ncell + 255) / 256);
+    if (!dev_zero(&M.d_partial, (size_t)M.lsq_blocks * nprof, b)) return LRBMS_E_OOM;
+    if (!dev_zero(&M.d_c, (size_t)M.nblk, b) || !dev_zero(&M.d_bq, (size_t)M.nblk * nprof, b) ||
+        !dev_zero(&M.d_e, (size_t)M.N, b) || !dev_zero(&M.d_dq, (size_t)M.N * nprof, b))
+      return LRBMS_E_OOM;
+    hipStream_t st = 0;
+    // c: penalty part (gamma-free), e: gamma-free right-hand side
+    if (!hip_ok(launch_assemble(g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+                                M.d_mom, PART_PEN | PART_RHS_CONST, M.d_c, M.d_e, st),
+                "assemble c, e"))
+      return LRBMS_E_HIP;
+    for (int q = 0; q < nprof; ++q) {
+      if (!hip_ok(launch_moments(g, M.d_prof + (size_t)q * L, GAMMA_FIELD, nullptr, 0, 0, M.d_mom,
+                                 st),
+                  "profile moments"))
+        return LRBMS_E_HIP;
+      if (!hip_ok(launch_assemble(g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+                                  M.d_mom, PART_GAMMA | PART_RHS_GAMMA, M.d_bq + (size_t)q * M.nblk,
+                                  M.d_dq + (size_t)q * M.N, st),
+                  "assemble b_q, d_q"))
+        return LRBMS_E_HIP;
+    }
+    if (!hip_ok(hipStreamSynchronize(st), "affine terms")) return LRBMS_E_HIP;
+  }
+  return LRBMS_OK;
+}
+
+int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double* basis,
+                      int nprof, const double* profiles, lrbms_model** out) {
+  if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
+  *out = nullptr;
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (!sizes || !basis) return (set_error("basis missing"), LRBMS_E_ARG);
+  if (nprof < 0 || nprof > kMaxProfiles || (nprof > 0 && !profiles))
+    return (set_error("invalid profiles"), LRBMS_E_ARG);
+  std::unique_ptr<Model> M(new Model());
+  const int nsub = p->nc[0] * p->nc[1] * (p->dim == 3 ? p->nc[2] : 1);
+  for (int s = 0; s < nsub; ++s)
+    if (sizes[s] < 1 || sizes[s] > 63)
+      return (set_error("local basis sizes must be in 1..63"), LRBMS_E_ARG);
+  setup_layout(*M, p, sizes);
+  if ((rc = upload_problem(*M, p))) return rc;
+  if ((rc = model_finish(*M, basis, nprof, profiles))) return rc;
+  *out = reinterpret_cast<lrbms_model*>(M.release());
+  return LRBMS_OK;
+}
+
+// Local Gram-Schmidt (Alg. 2 step 2e) of global snapshots restricted to every
+// box: optional unit function 1_E first, two passes against the current
+// basis, rejection when the remaining L2(E) norm is <= 1e-8 of the original.
+static void local_gram_schmidt(const Model& M, int nsnap, const double* snaps, int cap, bool unit,
+                               std::vector<int>& sizes, std::vector<double>& basis) {
+  const Geom& g = M.g;
+  const int r = g.r;
+  const size_t L = (size_t)r * g.ncell;
+  sizes.assign(M.n_sub, 0);
+  basis.clear();
+  for (int s = 0; s < M.n_sub; ++s) {
+    const Sub& S = M.subs[s];
+    const int nE = S.nE;
+    std::vector<int> cells(nE);
+    const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+    for (int l = 0; l < nE; ++l) {
+      const int x = S.lo[0] + l % bx, y = S.lo[1] + (l / bx) % by, z = S.lo[2] + l / (bx * by);
+      cells[l] = x + g.n[0] * (y + g.n[1] * z);
+    }
+    std::vector<std::vector<double>> B;
+    const size_t len = (size_t)r * nE;
+    if (unit) {
+      std::vector<double> v(len, 0.0);
+      double nrm = 0.0;
+      for (int l = 0; l < nE; ++l) {
+        v[l] = std::sqrt(g.vol);
+        nrm += v[l] * v[l];
+      }
+      nrm = std::sqrt(nrm);
+      for (auto& x : v) x /= nrm;
+      B.push_back(v);
+    }
+    for (int q = 0; q < nsnap && (int)B.size() < cap; ++q) {
+      std::vector<double> v(len);
+      for (int k = 0; k < r; ++k)
+        for (int l = 0; l < nE; ++l) v[k * nE + l] = snaps[q * L + (size_t)k * g.ncell + cells[l]];
+      double nv = 0.0;
+      for (double x : v) nv += x * x;
+      nv = std::sqrt(nv);
+      if (nv == 0.0) continue;
+      for (int pass = 0; pass < 2; ++pass)
+        for (auto& bb : B) {
+          double dot = 0.0;
+          for (size_t i = 0; i < len; ++i) dot += bb[i] * v[i];
+          for (size_t i = 0; i < len; ++i) v[i] -= dot * bb[i];
+        }
+      double nw = 0.0;
+      for (double x : v) nw += x * x;
+      nw = std::sqrt(nw);
+      if (nw <= 1e-8 * nv) continue;
+      for (auto& x : v) x /= nw;
+      B.push_back(v);
+    }
+    sizes[s] = (int)B.size();
+    for (auto& bb : B) basis.insert(basis.end(), bb.begin(), bb.end());
+  }
+}
+
+}  // namespace lrbms
+
+using namespace lrbms;
+
+static Model* M_(lrbms_model* m) { return reinterpret_cast<Model*>(m); }
+static const Model* M_(const lrbms_model* m) { return reinterpret_cast<const Model*>(m); }
+
+extern "C" {
+
+const char* lrbms_last_error(void) { return g_last_error.c_str(); }
+
+int lrbms_model_create(const lrbms_problem* prob, const int32_t* basis_sizes, const double* basis,
+                       int32_t n_profiles, const double* profiles, lrbms_model** out) {
+  try {
+    return model_create_impl(prob, basis_sizes, basis, n_profiles, profiles, out);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
+                                      const double* snapshots, int32_t ne_cap,
+                                      int32_t unit_functions, int32_t n_profiles,
+                                      const double* profiles, lrbms_model** out) {
+  try {
+    if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
+    *out = nullptr;
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (n_snap < 0 || (n_snap > 0 && !snapshots) || ne_cap < 1 || ne_cap > 63)
+      return (set_error("invalid snapshots or cap"), LRBMS_E_ARG);
+    Model tmp;
+    setup_layout(tmp, prob, nullptr);
+    std::vector<int> sizes;
+    std::vector<double> basis;
+    local_gram_schmidt(tmp, n_snap, snapshots, ne_cap, unit_functions != 0, sizes, basis);
+    for (int s : sizes)
+      if (s < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
+    return model_create_impl(prob, sizes.data(), basis.data(), n_profiles, profiles, out);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_model_get_info(const lrbms_model* m, lrbms_model_info* info) {
+  if (!m || !info) return (set_error("NULL argument"), LRBMS_E_ARG);
+  const Model* M = M_(m);
+  info->dim = M->g.dim;
+  info->r = M->g.r;
+  info->ncell = M->g.ncell;
+  info->nface = M->g.nface;
+  info->n_sub = M->n_sub;
+  info->n_iface = M->n_iface;
+  info->N = M->N;
+  info->n_profiles = M->nprof;
+  info->n_block_entries = M->nblk;
+  info->device_bytes = M->dev_bytes;
+  return LRBMS_OK;
+}
+
+int lrbms_model_export_basis(const lrbms_model* m, int32_t* sizes, double* basis) {
+  if (!m || !sizes || !basis) return (set_error("NULL argument"), LRBMS_E_ARG);
+  const Model* M = M_(m);
+  for (int s = 0; s < M->n_sub; ++s) sizes[s] = M->subs[s].NE;
+  return hip_ok(hipMemcpy(basis, M->d_phi, M->phi_len * sizeof(double), hipMemcpyDeviceToHost),
+                "export basis")
+             ? LRBMS_OK
+             : LRBMS_E_HIP;
+}
+
+int lrbms_model_interfaces(const lrbms_model* m, int32_t* axis, int32_t* lo, int32_t* hi) {
+  if (!m || !axis || !lo || !hi) return (set_error("NULL argument"), LRBMS_E_ARG);
+  const Model* M = M_(m);
+  for (int t = 0; t < M->n_iface; ++t) {
+    axis[t] = M->ifaces[t].axis;
+    lo[t] = M->ifaces[t].lo;
+    hi[t] = M->ifaces[t].hi;
+  }
+  return LRBMS_OK;
+}
+
+int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, void* stream) {
+  if (!m || !d_sat) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = M->g;
+  if (mode != LRBMS_DIRECT && mode != LRBMS_DIRECT_FIT && mode != LRBMS_AFFINE)
+    return (set_error("unknown assembly mode"), LRBMS_E_ARG);
+  if (mode != LRBMS_DIRECT && M->nprof == 0)
+    return (set_error("this mode needs mobility profiles"), LRBMS_E_STATE);
+  const int all = PART_GAMMA | PART_PEN | PART_RHS_CONST | PART_RHS_GAMMA;
+  if (mode == LRBMS_DIRECT) {
+    if (!hip_ok(launch_moments(g, d_sat, GAMMA_SAT, nullptr, 0, 0, M->d_mom, st), "moments"))
+      return LRBMS_E_HIP;
+  } else {
+    if (!hip_ok(launch_lsq(g, d_sat, M->d_prof, M->nprof, M->d_gchol, M->d_partial, M->lsq_blocks,
+                           M->d_theta, st),
+                "least squares"))
+      return LRBMS_E_HIP;
+    if (mode == LRBMS_DIRECT_FIT) {
+      if (!hip_ok(launch_moments(g, M->d_prof, GAMMA_COMBO, M->d_theta, M->nprof,
+                                 (long long)g.r * g.ncell, M->d_mom, st),
+                  "moments"))
+        return LRBMS_E_HIP;
+    }
+  }
+  if (mode == LRBMS_AFFINE) {
+    if (!hip_ok(launch_affine_sum(M->d_c, M->d_bq, M->nblk, M->d_theta, M->nprof, M->d_blocks, st),
+                "affine sum") ||
+        !hip_ok(launch_affine_sum(M->d_e, M->d_dq, M->N, M->d_theta, M->nprof, M->d_fN, st),
+                "affine sum"))
+      return LRBMS_E_HIP;
+  } else {
+    if (!hip_ok(launch_assemble(g, M->d_subs, M->n_sub, M->max_ne, M->d_ifaces, M->n_iface,
+                                M->d_phi, M->d_mom, all, M->d_blocks, M->d_fN, st),
+                "assemble"))
+      return LRBMS_E_HIP;
+  }
+  M->assembled = true;
+  M->last_stream = st;
+  return LRBMS_OK;
+}
+
+int lrbms_online_solve(lrbms_model* m, double* d_pN, void* stream) {
+  if (!m || !d_pN) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (!M->assembled) return (set_error("online_solve called before online_assemble"), LRBMS_E_STATE);
+  hipStream_t st = (hipStream_t)stream;
+  if (!hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, d_pN, M->d_status, st),
+              "reduced solve"))
+    return LRBMS_E_HIP;
+  M->last_stream = st;
+  return LRBMS_OK;
+}
+
+int lrbms_reconstruct_flux(lrbms_model* m, const double* d_pN, const double* d_sat,
+                           double* d_flux, double* d_ph, void* stream) {
+  if (!m || !d_pN || !d_sat || !d_flux) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  hipStream_t st = (hipStream_t)stream;
+  double* ph = d_ph ? d_ph : M->d_scratch_ph;
+  if (!hip_ok(launch_reconstruct(M->g, M->d_subs, M->n_sub, M->d_tiles, M->n_tiles, M->d_phi, d_pN,
+                                 ph, st),
+              "reconstruct") ||
+      !hip_ok(launch_flux(M->g, ph, d_sat, d_flux, st), "flux"))
+    return LRBMS_E_HIP;
+  M->last_stream = st;
+  return LRBMS_OK;
+}
+
+int lrbms_transport_step(lrbms_model* m, const double* d_sat, const double* d_flux,
+                         double* d_sat_out, uint8_t* d_flags, void* stream) {
+  if (!m || !d_sat || !d_flux || !d_sat_out) return (set_error("NULL argument"), LRBMS_E_ARG);
+  if (d_sat_out == d_sat) return (set_error("d_sat_out must not alias d_sat"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = M->g;
+  if (g.limiter) {
+    if (!hip_ok(launch_transport(g, d_sat, d_flux, M->d_scratch_sat, st), "transport") ||
+        !hip_ok(launch_limiter(g, M->d_scratch_sat, d_flux, d_sat_out, d_flags, st), "limiter"))
+      return LRBMS_E_HIP;
+  } else {
+    if (!hip_ok(launch_transport(g, d_sat, d_flux, d_sat_out, st), "transport")) return LRBMS_E_HIP;
+    if (d_flags) {
+      hipLaunchKernelGGL(k_fill_u8, dim3((g.ncell + 255) / 256), dim3(256), 0, st, d_flags,
+                         g.ncell, (uint8_t)0);
+      if (!hip_ok(hipGetLastError(), "fill flags")) return LRBMS_E_HIP;
+    }
+  }
+  M->last_stream = st;
+  return LRBMS_OK;
+}
+
+int lrbms_copy_reduced_system(lrbms_model* m, double* blocks, double* fN) {
+  if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+  if (blocks && !hip_ok(hipMemcpy(blocks, M->d_blocks, M->nblk * sizeof(double),
+                                  hipMemcpyDeviceToHost),
+                        "copy blocks"))
+    return LRBMS_E_HIP;
+  if (fN && !hip_ok(hipMemcpy(fN, M->d_fN, M->N * sizeof(double), hipMemcpyDeviceToHost), "copy f"))
+    return LRBMS_E_HIP;
+  return LRBMS_OK;
+}
+
+int lrbms_copy_theta(lrbms_model* m, double* theta) {
+  if (!m || !theta) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (M->nprof == 0) return (set_error("model has no profiles"), LRBMS_E_STATE);
+  if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+  return hip_ok(hipMemcpy(theta, M->d_theta, M->nprof * sizeof(double), hipMemcpyDeviceToHost),
+                "copy theta")
+             ? LRBMS_OK
+             : LRBMS_E_HIP;
+}
+
+int lrbms_model_status(lrbms_model* m) {
+  if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+  int s = 0;
+  if (!hip_ok(hipMemcpy(&s, M->d_status, sizeof(int), hipMemcpyDeviceToHost), "status"))
+    return LRBMS_E_HIP;
+  if (s) set_error("device reported an error (non-positive pivot in the reduced Cholesky)");
+  return s;
+}
+
+void lrbms_model_destroy(lrbms_model* m) {
+  if (!m) return;
+  Model* M = M_(m);
+  (void)hipStreamSynchronize(M->last_stream);
+  delete M;
+}
+
+int lrbms_build_offline_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
+                              lrbms_model** out) {
+  (void)prob;
+  (void)opts;
+  if (out) *out = nullptr;
+  set_error("lrbms_build_offline_bases: not available in this build");
+  return LRBMS_E_STATE;
+}
+
+}  // extern "C"

@@ -1,0 +1,595 @@
+// Reduced assembly on gfx950.
+//
+// Mobility moments (a1), the Galerkin projection A_N = Phi^T A(gamma) Phi and
+// f_N = Phi^T l(gamma) of the SWIP forms of Sec. 3.2 onto the broken reduced
+// space W_N (Def. coarseScalePressure), the affine sum of eq. reducedSystem
+// and the least-squares fit of eq. leastSquaresFit.
+//
+// Readings of the printed forms used throughout (same as the CPU reference):
+// consistency terms with a minus sign, Neumann term -int v_N w, SWIP mean
+// weights (or the literal ones on request), two-valued mobility on faces
+// (each side of the weighted mean uses its own trace), outward normal and
+// weight 1 on Dirichlet faces, h_f = face diameter, zero gravity.
+//
+// Kernel structure: one workgroup per coarse box builds Y = K_E Phi_E a
+// chunk of cells at a time (threads over (cell, column), coalesced reads of
+// the column-major Phi_E, the 2d-face stencil evaluated from per-cell
+// mobility moments), stages the chunk of Phi_E and Y in LDS and contracts
+// Phi_E^T Y with one output column per thread.  The right-hand side rides
+// along as column N_E.  One workgroup per coarse interface builds the
+// coupling block the same way from the fine faces on the interface.
+#include "common.h"
+
+namespace lrbms {
+
+// ---------------------------------------------------------------------------
+// a1: mobility moments per cell.  gamma is lambda(s_h) (kind GAMMA_SAT), a P1
+// field (GAMMA_FIELD) or sum_q theta_q Lambda^q (GAMMA_COMBO); integrals by the
+// 2-point Gauss rules, which are exact for the quadratic mobility of a P1 state.
+__global__ __launch_bounds__(256) void k_moments(Geom g, const double* __restrict__ src, int kind,
+                                                 const double* __restrict__ theta, int nprof,
+                                                 long long pstride, double* __restrict__ mom) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int d = g.dim, nc = g.ncell;
+  double co[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < g.r; ++k) {
+    if (kind == GAMMA_COMBO) {
+      double v = 0.0;
+      for (int q = 0; q < nprof; ++q) v += theta[q] * src[q * pstride + (long long)k * nc + c];
+      co[k] = v;
+    } else {
+      co[k] = src[(long long)k * nc + c];
+    }
+  }
+  // value of gamma at local point xi (sq holds sqrt(3) xi_a)
+  auto gam = [&](const double sq[3]) {
+    double v = co[0];
+    for (int a = 0; a < d; ++a) v += sq[a] * co[a + 1];
+    v *= g.isv;
+    return kind == GAMMA_SAT ? total_mobility(g, v) : v;
+  };
+  const double gp = 1.0 / kSqrt3;
+  double sq[3];
+  double sum = 0.0;
+  const int nq = 1 << d;
+  for (int p = 0; p < nq; ++p) {
+    for (int a = 0; a < d; ++a) sq[a] = kSqrt3 * (((p >> a) & 1) ? gp : -gp);
+    sum += gam(sq);
+  }
+  mom[c] = sum * g.vol / nq;
+  for (int a = 0; a < d; ++a) {
+    int tax[2], nt = 0;
+    for (int b = 0; b < d; ++b)
+      if (b != a) tax[nt++] = b;
+    const double w = g.area[a] / (1 << nt);
+    for (int dir = 0; dir < 2; ++dir) {
+      double m0 = 0.0, mt[2] = {0.0, 0.0};
+      for (int p = 0; p < (1 << nt); ++p) {
+        double xi[3] = {0.0, 0.0, 0.0};
+        xi[a] = dir ? 1.0 : -1.0;
+        for (int ti = 0; ti < nt; ++ti) xi[tax[ti]] = ((p >> ti) & 1) ? gp : -gp;
+        for (int b = 0; b < d; ++b) sq[b] = kSqrt3 * xi[b];
+        const double v = gam(sq);
+        m0 += v;
+        for (int ti = 0; ti < nt; ++ti) mt[ti] += v * xi[tax[ti]];
+      }
+      const int s = mom_slot(d, a, dir);
+      mom[(long long)s * nc + c] = m0 * w;
+      for (int ti = 0; ti < nt; ++ti) mom[(long long)(s + 1 + ti) * nc + c] = mt[ti] * w;
+    }
+  }
+}
+
+hipError_t launch_moments(const Geom& g, const double* src, int kind, const double* theta,
+                          int nprof, long long prof_stride, double* mom, hipStream_t st) {
+  const int nb = (g.ncell + 255) / 256;
+  hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, st, g, src, kind, theta, nprof,
+                     prof_stride, mom);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Face terms of b_h for one face of a test cell and one trial column.
+//   alpha = +1: the face is on the +a side of the test cell (test cell is the
+//   low-side cell e1), -1: on the -a side.  On a boundary face alpha is also
+//   the sign of the outward normal.  ps / po: trial coefficients on the test
+//   side / the other side (zero when the trial function vanishes there).
+//   ms / mo: moments of gamma on the face from the test side / other side
+//   (m0 = int_f gamma, mt = int_f gamma xi_t).
+// Adds to Y[k] = sum over trial dofs of the face matrix entries (row = test
+// dof k of the test cell).
+struct FaceCtx {
+  int a;
+  double alpha;
+  bool interior;
+  double ks, ko;
+  double ms[3], mo[3];
+};
+
+__device__ __forceinline__ void face_rows(const Geom& g, const FaceCtx& f, const double* ps,
+                                          const double* po, bool gam, bool pen, double* Y) {
+  const int a = f.a, d = g.dim;
+  const double isv = g.isv;
+  const double gf = kSqrt3 * 2.0 / g.h[a] * isv;
+  const double as = f.alpha, ao = -f.alpha;
+  double js, jo, ws, wo, sig, nd;
+  if (f.interior) {
+    js = f.alpha;
+    jo = -f.alpha;
+    const double klo = f.alpha > 0 ? f.ks : f.ko, khi = f.alpha > 0 ? f.ko : f.ks;
+    double wlo, whi;
+    if (g.weights == 0) {
+      wlo = khi / (klo + khi);
+      whi = klo / (klo + khi);
+    } else {
+      wlo = klo / (klo + khi);
+      whi = khi / (klo + khi);
+    }
+    ws = f.alpha > 0 ? wlo : whi;
+    wo = f.alpha > 0 ? whi : wlo;
+    sig = g.pen * 2.0 * klo * khi / (klo + khi);
+    nd = gf;
+  } else {
+    js = 1.0;
+    jo = 0.0;
+    ws = 1.0;
+    wo = 0.0;
+    sig = g.pen * f.ks;
+    nd = f.alpha * gf;
+  }
+  int tax[2], nt = 0;
+  for (int b = 0; b < d; ++b)
+    if (b != a) tax[nt++] = b;
+  if (gam) {
+    // -int {gamma kappa d_n v} [w]: trial normal derivatives against the test trace
+    const double cs = ws * f.ks * nd * ps[a + 1];
+    const double cq = f.interior ? wo * f.ko * nd * po[a + 1] : 0.0;
+    const double A0 = cs * f.ms[0] + (f.interior ? cq * f.mo[0] : 0.0);
+    Y[0] -= js * isv * A0;
+    Y[a + 1] -= js * isv * kSqrt3 * as * A0;
+    for (int ti = 0; ti < nt; ++ti) {
+      const double At = cs * f.ms[1 + ti] + (f.interior ? cq * f.mo[1 + ti] : 0.0);
+      Y[tax[ti] + 1] -= js * isv * kSqrt3 * At;
+    }
+    // -int {gamma kappa d_n w} [v]: test normal derivative against the trial jump
+    double jm = js * (ps[0] * f.ms[0] + kSqrt3 * as * ps[a + 1] * f.ms[0]);
+    for (int ti = 0; ti < nt; ++ti) jm += js * kSqrt3 * ps[tax[ti] + 1] * f.ms[1 + ti];
+    if (f.interior) {
+      jm += jo * (po[0] * f.ms[0] + kSqrt3 * ao * po[a + 1] * f.ms[0]);
+      for (int ti = 0; ti < nt; ++ti) jm += jo * kSqrt3 * po[tax[ti] + 1] * f.ms[1 + ti];
+    }
+    Y[a + 1] -= ws * f.ks * nd * isv * jm;
+  }
+  if (pen) {
+    // sigma_f / h_f int [v][w]
+    const double P = sig / g.hf[a] * (isv * isv) * g.area[a] * js;
+    double J0 = js * (ps[0] + kSqrt3 * as * ps[a + 1]);
+    if (f.interior) J0 += jo * (po[0] + kSqrt3 * ao * po[a + 1]);
+    Y[0] += P * J0;
+    Y[a + 1] += P * kSqrt3 * as * J0;
+    for (int ti = 0; ti < nt; ++ti) {
+      const int t = tax[ti] + 1;
+      Y[t] += P * (js * ps[t] + (f.interior ? jo * po[t] : 0.0));
+    }
+  }
+}
+
+__device__ __forceinline__ void load_moments(const Geom& g, const double* mom, int c, int a,
+                                             int dir, double* m) {
+  const int s = mom_slot(g.dim, a, dir);
+  for (int q = 0; q < g.dim; ++q) m[q] = mom[(long long)(s + q) * g.ncell + c];
+}
+
+// Rows (e, 0..r-1) of K_E Phi for one column of Phi^E (test cell e at box-local
+// index l, box coordinates x).  Trial values outside the box are zero.
+__device__ void cell_rows(const Geom& g, const Sub& S, int e, const int x[3], int l,
+                          const double* __restrict__ col, const double* ps,
+                          const double* __restrict__ mom, int parts, double* Y) {
+  const int d = g.dim, r = g.r;
+  const bool gam = parts & PART_GAMMA, pen = parts & PART_PEN;
+  const double ke = g.perm[e];
+  if (gam) {
+    const double mv = mom[e];
+    for (int a = 0; a < d; ++a) {
+      const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
+      Y[a + 1] += ke * mv * (gf * gf) * ps[a + 1];
+    }
+  }
+  int bstride[3] = {1, S.hi[0] - S.lo[0], (S.hi[0] - S.lo[0]) * (S.hi[1] - S.lo[1])};
+  for (int a = 0; a < d; ++a) {
+    for (int dir = 0; dir < 2; ++dir) {
+      FaceCtx f;
+      f.a = a;
+      f.alpha = dir ? 1.0 : -1.0;
+      f.ks = ke;
+      load_moments(g, mom, e, a, dir, f.ms);
+      int xn[3] = {x[0], x[1], x[2]};
+      xn[a] += dir ? 1 : -1;
+      double po[4] = {0.0, 0.0, 0.0, 0.0};
+      if (xn[a] >= 0 && xn[a] < g.n[a]) {
+        const int en = cell_index(g, xn);
+        f.interior = true;
+        f.ko = g.perm[en];
+        load_moments(g, mom, en, a, 1 - dir, f.mo);
+        if (xn[a] >= S.lo[a] && xn[a] < S.hi[a]) {
+          const int ln = l + (dir ? bstride[a] : -bstride[a]);
+          for (int k = 0; k < r; ++k) po[k] = col[(long long)k * S.nE + ln];
+        }
+        face_rows(g, f, ps, po, gam, pen, Y);
+      } else {
+        int xf[3] = {x[0], x[1], x[2]};
+        xf[a] += dir;
+        const int fid = face_index(g, a, xf);
+        if (g.bc_type[fid] == LRBMS_BC_DIRICHLET) {
+          f.interior = false;
+          f.ko = 0.0;
+          face_rows(g, f, ps, po, gam, pen, Y);
+        }
+      }
+    }
+  }
+}
+
+// l_h(phi_k) of test cell e (sources, Neumann and Dirichlet data).
+__device__ void cell_rhs(const Geom& g, int e, const int x[3], const double* __restrict__ mom,
+                         int parts, double* Y) {
+  const int d = g.dim;
+  if (parts & PART_RHS_CONST) Y[0] += g.q1[e] * g.vol * g.isv;
+  for (int a = 0; a < d; ++a) {
+    for (int dir = 0; dir < 2; ++dir) {
+      int xn[3] = {x[0], x[1], x[2]};
+      xn[a] += dir ? 1 : -1;
+      if (xn[a] >= 0 && xn[a] < g.n[a]) continue;
+      int xf[3] = {x[0], x[1], x[2]};
+      xf[a] += dir;
+      const int fid = face_index(g, a, xf);
+      const int bt = g.bc_type[fid];
+      const double val = g.bc_val[fid];
+      const double al = dir ? 1.0 : -1.0;
+      const double tw0 = g.area[a] * g.isv, twa = tw0 * kSqrt3 * al;   // int_f phi_0, phi_{a+1}
+      if (bt == LRBMS_BC_NEUMANN && (parts & PART_RHS_CONST)) {
+        Y[0] -= val * tw0;
+        Y[a + 1] -= val * twa;
+      } else if (bt == LRBMS_BC_DIRICHLET) {
+        if (parts & PART_RHS_CONST) {
+          const double sg = g.pen * g.perm[e] / g.hf[a];
+          Y[0] += sg * val * tw0;
+          Y[a + 1] += sg * val * twa;
+        }
+        if (parts & PART_RHS_GAMMA) {
+          const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
+          const double m0 = mom[(long long)mom_slot(d, a, dir) * g.ncell + e];
+          Y[a + 1] -= val * g.perm[e] * m0 * (al * gf);
+        }
+      }
+    }
+  }
+}
+
+// Diagonal blocks A[E][E] and f_E: one workgroup per box.
+template <int COLS>
+__global__ __launch_bounds__(256) void k_assemble_diag(Geom g, const Sub* __restrict__ subs,
+                                                       const double* __restrict__ phi,
+                                                       const double* __restrict__ mom, int parts,
+                                                       double* __restrict__ blocks,
+                                                       double* __restrict__ fN, int chunk) {
+  extern __shared__ double lds[];
+  const Sub S = subs[blockIdx.x];
+  const int NE = S.NE, nE = S.nE, r = g.r;
+  const bool want_rhs = (parts & (PART_RHS_CONST | PART_RHS_GAMMA)) && fN != nullptr;
+  const bool want_mat = (parts & (PART_GAMMA | PART_PEN)) && blocks != nullptr;
+  const int ncol = NE + (want_rhs ? 1 : 0);
+  constexpr int stride = COLS + 1;
+  constexpr int NG = 256 / COLS;
+  double* Phil = lds;
+  double* Yl = lds + (size_t)chunk * r * stride;
+  const int j = threadIdx.x % COLS, grp = threadIdx.x / COLS;
+  double acc[COLS];
+#pragma unroll
+  for (int i = 0; i < COLS; ++i) acc[i] = 0.0;
+  const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+  for (int c0 = 0; c0 < nE; c0 += chunk) {
+    const int cc = min(chunk, nE - c0);
+    for (int p = threadIdx.x; p < cc * ncol; p += 256) {
+      const int lc = p % cc, col = p / cc;
+      const int l = c0 + lc;
+      const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
+      const int e = cell_index(g, x);
+      double Y[4] = {0.0, 0.0, 0.0, 0.0};
+      if (col < NE) {
+        const double* cp = phi + S.phi_off + (long long)col * r * nE;
+        double ps[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < r; ++k) ps[k] = cp[(long long)k * nE + l];
+        if (want_mat) cell_rows(g, S, e, x, l, cp, ps, mom, parts, Y);
+        for (int k = 0; k < r; ++k) Phil[(lc * r + k) * stride + col] = ps[k];
+      } else {
+        cell_rhs(g, e, x, mom, parts, Y);
+      }
+      for (int k = 0; k < r; ++k) Yl[(lc * r + k) * stride + col] = Y[k];
+    }
+    __syncthreads();
+    if (j < ncol) {
+      for (int lc = grp; lc < cc; lc += NG) {
+        for (int k = 0; k < r; ++k) {
+          const double y = Yl[(lc * r + k) * stride + j];
+          const double* pr = Phil + (lc * r + k) * stride;
+#pragma unroll
+          for (int i = 0; i < COLS; ++i)
+            if (i < NE) acc[i] += pr[i] * y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // reduce the NG partial sums in a fixed order
+  double* red = lds;
+  if (j < ncol) {
+#pragma unroll
+    for (int i = 0; i < COLS; ++i)
+      if (i < NE) red[(grp * COLS + i) * stride + j] = acc[i];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NE * ncol; idx += 256) {
+    const int i = idx / ncol, jj = idx % ncol;
+    double v = 0.0;
+    for (int q = 0; q < NG; ++q) v += red[(q * COLS + i) * stride + jj];
+    if (jj < NE) {
+      if (want_mat) blocks[S.blk_off + (long long)i * NE + jj] = v;
+    } else {
+      fN[S.pn_off + i] = v;
+    }
+  }
+}
+
+// Coupling block A[lo][hi] of one coarse interface: one workgroup per interface.
+template <int COLS>
+__global__ __launch_bounds__(256) void k_assemble_iface(Geom g, const Sub* __restrict__ subs,
+                                                        const Iface* __restrict__ ifs,
+                                                        const double* __restrict__ phi,
+                                                        const double* __restrict__ mom,
+                                                        int parts, double* __restrict__ blocks,
+                                                        int chunk) {
+  extern __shared__ double lds[];
+  const Iface I = ifs[blockIdx.x];
+  const Sub SL = subs[I.lo], SH = subs[I.hi];
+  const int a = I.axis, r = g.r, d = g.dim;
+  const int NL = SL.NE, NH = SH.NE;
+  constexpr int stride = COLS + 1;
+  constexpr int NG = 256 / COLS;
+  double* Phil = lds;
+  double* Yl = lds + (size_t)chunk * r * stride;
+  int tax[2] = {0, 0}, nt = 0;
+  for (int b = 0; b < d; ++b)
+    if (b != a) tax[nt++] = b;
+  const int ext0 = SL.hi[tax[0]] - SL.lo[tax[0]];
+  const int ncolmax = max(NL, NH);
+  const bool gam = parts & PART_GAMMA, pen = parts & PART_PEN;
+  const int j = threadIdx.x % COLS, grp = threadIdx.x / COLS;
+  const int bxL = SL.hi[0] - SL.lo[0], byL = SL.hi[1] - SL.lo[1];
+  const int bxH = SH.hi[0] - SH.lo[0], byH = SH.hi[1] - SH.lo[1];
+  double acc[COLS];
+#pragma unroll
+  for (int i = 0; i < COLS; ++i) acc[i] = 0.0;
+  for (int q0 = 0; q0 < I.nf; q0 += chunk) {
+    const int cc = min(chunk, I.nf - q0);
+    for (int p = threadIdx.x; p < cc * ncolmax; p += 256) {
+      const int lq = p % cc, col = p / cc;
+      const int q = q0 + lq;
+      int x0[3] = {0, 0, 0}, x1[3];
+      x0[a] = SL.hi[a] - 1;
+      x0[tax[0]] = SL.lo[tax[0]] + (nt > 0 ? q % ext0 : 0);
+      if (nt > 1) x0[tax[1]] = SL.lo[tax[1]] + q / ext0;
+      for (int b = 0; b < 3; ++b) x1[b] = x0[b];
+      x1[a] = SH.lo[a];
+      const int l0 = (x0[0] - SL.lo[0]) + bxL * ((x0[1] - SL.lo[1]) + byL * (x0[2] - SL.lo[2]));
+      const int l1 = (x1[0] - SH.lo[0]) + bxH * ((x1[1] - SH.lo[1]) + byH * (x1[2] - SH.lo[2]));
+      const int e0 = cell_index(g, x0), e1 = cell_index(g, x1);
+      if (col < NH) {
+        const double* cp = phi + SH.phi_off + (long long)col * r * SH.nE;
+        double ps[4] = {0.0, 0.0, 0.0, 0.0}, po[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < r; ++k) po[k] = cp[(long long)k * SH.nE + l1];
+        FaceCtx f;
+        f.a = a;
+        f.alpha = 1.0;
+        f.interior = true;
+        f.ks = g.perm[e0];
+        f.ko = g.perm[e1];
+        load_moments(g, mom, e0, a, 1, f.ms);
+        load_moments(g, mom, e1, a, 0, f.mo);
+        double Y[4] = {0.0, 0.0, 0.0, 0.0};
+        face_rows(g, f, ps, po, gam, pen, Y);
+        for (int k = 0; k < r; ++k) Yl[(lq * r + k) * stride + col] = Y[k];
+      }
+      if (col < NL) {
+        const double* cp = phi + SL.phi_off + (long long)col * r * SL.nE;
+        for (int k = 0; k < r; ++k) Phil[(lq * r + k) * stride + col] = cp[(long long)k * SL.nE + l0];
+      }
+    }
+    __syncthreads();
+    if (j < NH) {
+      for (int lq = grp; lq < cc; lq += NG) {
+        for (int k = 0; k < r; ++k) {
+          const double y = Yl[(lq * r + k) * stride + j];
+          const double* pr = Phil + (lq * r + k) * stride;
+#pragma unroll
+          for (int i = 0; i < COLS; ++i)
+            if (i < NL) acc[i] += pr[i] * y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* red = lds;
+  if (j < NH) {
+#pragma unroll
+    for (int i = 0; i < COLS; ++i)
+      if (i < NL) red[(grp * COLS + i) * stride + j] = acc[i];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NL * NH; idx += 256) {
+    const int i = idx / NH, jj = idx % NH;
+    double v = 0.0;
+    for (int q = 0; q < NG; ++q) v += red[(q * COLS + i) * stride + jj];
+    blocks[I.blk_off + (long long)i * NH + jj] = v;
+  }
+}
+
+template <int COLS>
+static hipError_t launch_assemble_t(const Geom& g, const Sub* d_subs, int n_sub,
+                                    const Iface* d_ifaces, int n_iface, const double* phi,
+                                    const double* mom, int parts, double* blocks, double* fN,
+                                    hipStream_t st) {
+  constexpr int stride = COLS + 1;
+  const size_t budget = 72 * 1024;
+  int chunk = (int)(budget / (sizeof(double) * 2 * g.r * stride));
+  if (chunk < 1) chunk = 1;
+  const size_t lds_chunk = sizeof(double) * 2 * (size_t)chunk * g.r * stride;
+  const size_t lds_red = sizeof(double) * (size_t)(256 / COLS) * COLS * stride;
+  const size_t lds = lds_chunk > lds_red ? lds_chunk : lds_red;
+  hipError_t ea = hipFuncSetAttribute((const void*)k_assemble_diag<COLS>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (ea != hipSuccess) return ea;
+  ea = hipFuncSetAttribute((const void*)k_assemble_iface<COLS>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (ea != hipSuccess) return ea;
+  if (n_sub > 0) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_diag<COLS>), dim3(n_sub), dim3(256), lds, st,
+                       g, d_subs, phi, mom, parts, blocks, fN, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n_iface > 0 && blocks && (parts & (PART_GAMMA | PART_PEN))) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_iface<COLS>), dim3(n_iface), dim3(256), lds,
+                       st, g, d_subs, d_ifaces, phi, mom, parts, blocks, chunk);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_assemble(const Geom& g, const Sub* d_subs, int n_sub, int max_ne,
+                           const Iface* d_ifaces, int n_iface, const double* phi,
+                           const double* mom, int parts, double* blocks, double* fN,
+                           hipStream_t st) {
+  // the right-hand side needs one spare column
+  if (max_ne + 1 <= 16)
+    return launch_assemble_t<16>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
+                                 fN, st);
+  if (max_ne + 1 <= 32)
+    return launch_assemble_t<32>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
+                                 fN, st);
+  return launch_assemble_t<64>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks, fN,
+                               st);
+}
+
+// ---------------------------------------------------------------------------
+// eq. reducedSystem: out = base + sum_q theta_q terms[q] (q in increasing order).
+__global__ __launch_bounds__(256) void k_affine_sum(const double* __restrict__ base,
+                                                    const double* __restrict__ terms, long long n,
+                                                    const double* __restrict__ theta, int nq,
+                                                    double* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = base[i];
+    for (int q = 0; q < nq; ++q) v = v + theta[q] * terms[(long long)q * n + i];
+    out[i] = v;
+  }
+}
+
+hipError_t launch_affine_sum(const double* base, const double* terms, long long n,
+                             const double* theta, int nq, double* out, hipStream_t st) {
+  long long nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_affine_sum, dim3((unsigned)nb), dim3(256), 0, st, base, terms, n, theta,
+                     nq, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// eq. leastSquaresFit: r_q = (Lambda^q, Pi lambda(s))_{L2} with the P1
+// projection Pi lambda(s) evaluated by the 2-point Gauss rule; theta solves
+// G theta = r with the Cholesky factor of the profile Gram matrix G.
+__global__ __launch_bounds__(256) void k_lsq_partial(Geom g, const double* __restrict__ sat,
+                                                     const double* __restrict__ prof, int nprof,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int nc = g.ncell, d = g.dim, r = g.r;
+  double lp[4];  // P1 projection coefficients of lambda(s) on this thread's cell
+  double acc[kMaxProfiles];
+  for (int q = 0; q < nprof; ++q) acc[q] = 0.0;
+  const double gp = 1.0 / kSqrt3;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    double co[4] = {0, 0, 0, 0};
+    for (int k = 0; k < r; ++k) co[k] = sat[(long long)k * nc + c];
+    for (int k = 0; k < r; ++k) lp[k] = 0.0;
+    const int nq = 1 << d;
+    const double w = g.vol / nq;
+    for (int p = 0; p < nq; ++p) {
+      double sq[3];
+      double v = co[0];
+      for (int a = 0; a < d; ++a) {
+        sq[a] = kSqrt3 * (((p >> a) & 1) ? gp : -gp);
+        v += sq[a] * co[a + 1];
+      }
+      const double lam = total_mobility(g, v * g.isv) * w;
+      lp[0] += lam * g.isv;
+      for (int a = 0; a < d; ++a) lp[a + 1] += lam * sq[a] * g.isv;
+    }
+    for (int q = 0; q < nprof; ++q) {
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += prof[(long long)q * r * nc + (long long)k * nc + c] * lp[k];
+      acc[q] += s;
+    }
+  }
+  for (int q = 0; q < nprof; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)blockIdx.x * nprof + q] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_lsq_final(const double* __restrict__ partial, int nblocks, int nprof,
+                            const double* __restrict__ L, double* __restrict__ theta) {
+  __shared__ double rhs[kMaxProfiles];
+  const int q = threadIdx.x;
+  if (q < nprof) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += partial[(long long)b * nprof + q];
+    rhs[q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // forward then backward substitution with the lower Cholesky factor L
+    double y[kMaxProfiles];
+    for (int i = 0; i < nprof; ++i) {
+      double v = rhs[i];
+      for (int k = 0; k < i; ++k) v -= L[i * nprof + k] * y[k];
+      y[i] = v / L[i * nprof + i];
+    }
+    for (int i = nprof - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < nprof; ++k) v -= L[k * nprof + i] * y[k];
+      y[i] = v / L[i * nprof + i];
+    }
+    for (int i = 0; i < nprof; ++i) theta[i] = y[i];
+  }
+}
+
+hipError_t launch_lsq(const Geom& g, const double* sat, const double* prof, int nprof,
+                      const double* gchol, double* partial, int nblocks, double* theta,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_lsq_partial, dim3(nblocks), dim3(256), 0, st, g, sat, prof, nprof,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lsq_final, dim3(1), dim3(64), 0, st, partial, nblocks, nprof, gchol, theta);
+  return hipGetLastError();
+}
+
+}  // namespace lrbms

@@ -1,0 +1,137 @@
+// Internal declarations of the LRBMS gfx950 library: device-side problem
+// description, model layout and the launchers shared by the source files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lrbms.h"
+
+namespace lrbms {
+
+constexpr double kSqrt3 = 1.7320508075688772;
+constexpr int kMaxProfiles = 64;
+
+// Geometry, physics constants and problem arrays, passed by value to kernels.
+struct Geom {
+  int dim, r, n[3], ncell;
+  int nfa[3], foff[3], nface;
+  double h[3], vol, isv, area[3], hf[3], he;
+  double visc_w, visc_o, cw, co;
+  int relperm;
+  double pen;        // penalty_c / max(visc_w, visc_o)
+  int weights;
+  double sat_pen;    // sat_penalty_scale
+  int limiter;
+  double dt;
+  const double *perm, *poro, *q1, *q2, *bc_val, *bc_sval;
+  const int8_t *bc_type, *bc_sat;
+};
+
+// One coarse box E.
+struct Sub {
+  int lo[3], hi[3];
+  int nE, NE;        // cells, local basis size
+  long long phi_off; // offset of Phi^E in the basis array
+  int pn_off;        // offset of the box block in p_N
+  long long blk_off; // offset of the diagonal block in block storage
+};
+
+// One coarse interface between box lo (low side along axis) and box hi.
+struct Iface {
+  int axis, lo, hi, nf;
+  long long blk_off; // offset of A[lo][hi] (N_lo x N_hi, row-major)
+};
+
+// ---- device helpers ---------------------------------------------------------
+__device__ __forceinline__ double clip01(double s) { return fmin(fmax(s, 0.0), 1.0); }
+
+__device__ __forceinline__ void mobilities(const Geom& g, double s, double& lw, double& lo) {
+  const double sc = clip01(s);
+  double krw, kro;
+  if (g.relperm == 0) {
+    krw = sc;
+    kro = 1.0 - sc;
+  } else {
+    krw = (g.cw == 2.0) ? sc * sc : pow(sc, g.cw);
+    const double so = 1.0 - sc;
+    kro = (g.co == 2.0) ? so * so : pow(so, g.co);
+  }
+  lw = krw / g.visc_w;
+  lo = kro / g.visc_o;
+}
+
+__device__ __forceinline__ double total_mobility(const Geom& g, double s) {
+  double lw, lo;
+  mobilities(g, s, lw, lo);
+  return lw + lo;
+}
+
+__device__ __forceinline__ double frac_flow(const Geom& g, double s) {
+  double lw, lo;
+  mobilities(g, s, lw, lo);
+  return lw / (lw + lo);
+}
+
+__device__ __forceinline__ void cell_coords(const Geom& g, int c, int x[3]) {
+  x[0] = c % g.n[0];
+  x[1] = (c / g.n[0]) % g.n[1];
+  x[2] = c / (g.n[0] * g.n[1]);
+}
+
+__device__ __forceinline__ int cell_index(const Geom& g, const int x[3]) {
+  return x[0] + g.n[0] * (x[1] + g.n[1] * x[2]);
+}
+
+// Global face number of the face along axis a at face coordinates x
+// (x[a] in [0, n[a]]).
+__device__ __forceinline__ int face_index(const Geom& g, int a, const int x[3]) {
+  int e0 = g.n[0], e1 = g.n[1];
+  if (a == 0) e0 += 1;
+  if (a == 1) e1 += 1;
+  return g.foff[a] + x[0] + e0 * (x[1] + e1 * x[2]);
+}
+
+// Number of mobility moment slots per cell: int_e gamma, then for every face
+// side (axis a, dir 0 = low face, 1 = high face): int_f gamma and
+// int_f gamma xi_t for the d-1 tangential axes t (in increasing order).
+__host__ __device__ __forceinline__ int n_moments(int dim) { return 1 + 2 * dim * dim; }
+__host__ __device__ __forceinline__ int mom_slot(int dim, int a, int dir) {
+  return 1 + (2 * a + dir) * dim;
+}
+
+// ---- host helpers -------------------------------------------------------------
+void set_error(const std::string& msg);
+bool hip_ok(hipError_t e, const char* what);
+
+// Launchers (defined in the .hip files).
+enum GammaSource { GAMMA_SAT = 0, GAMMA_FIELD = 1, GAMMA_COMBO = 2 };
+enum AsmParts { PART_GAMMA = 1, PART_PEN = 2, PART_RHS_CONST = 4, PART_RHS_GAMMA = 8 };
+
+hipError_t launch_moments(const Geom& g, const double* src, int kind, const double* theta,
+                          int nprof, long long prof_stride, double* mom, hipStream_t st);
+hipError_t launch_assemble(const Geom& g, const Sub* d_subs, int n_sub, int max_ne,
+                           const Iface* d_ifaces, int n_iface, const double* phi,
+                           const double* mom, int parts, double* blocks, double* fN,
+                           hipStream_t st);
+hipError_t launch_affine_sum(const double* base, const double* terms, long long n,
+                             const double* theta, int nq, double* out, hipStream_t st);
+hipError_t launch_lsq(const Geom& g, const double* sat, const double* prof, int nprof,
+                      const double* gchol, double* partial, int nblocks, double* theta,
+                      hipStream_t st);
+hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const int* d_tiles,
+                              int n_tiles, const double* phi, const double* pN, double* ph,
+                              hipStream_t st);
+hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, double* flux,
+                       hipStream_t st);
+hipError_t launch_transport(const Geom& g, const double* sat, const double* flux,
+                            double* sat_bar, hipStream_t st);
+hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
+                          double* sat_out, uint8_t* flags, hipStream_t st);
+hipError_t launch_fine_apply(const Geom& g, const double* mom, const double* x, double* y,
+                             hipStream_t st);
+
+}  // namespace lrbms

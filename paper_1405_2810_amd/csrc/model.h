@@ -1,0 +1,49 @@
+// Host-side model object behind the opaque lrbms_model handle.
+#pragma once
+
+#include "common.h"
+#include "solver.h"
+
+namespace lrbms {
+
+struct Model {
+  Geom g{};
+  int nc[3] = {1, 1, 1};
+  int n_sub = 0, n_iface = 0, N = 0, max_ne = 0;
+  std::vector<Sub> subs;
+  std::vector<Iface> ifaces;
+  long long phi_len = 0, nblk = 0;
+  Sub* d_subs = nullptr;
+  Iface* d_ifaces = nullptr;
+  double *d_perm = nullptr, *d_poro = nullptr, *d_q1 = nullptr, *d_q2 = nullptr;
+  double *d_bc_val = nullptr, *d_bc_sval = nullptr;
+  int8_t *d_bc_type = nullptr, *d_bc_sat = nullptr;
+  double* d_phi = nullptr;      // local bases, per box (N_E, r, n_E)
+  double* d_mom = nullptr;      // mobility moments, n_moments(dim) x ncell
+  double* d_blocks = nullptr;   // A_N in block storage
+  double* d_fN = nullptr;
+  // affine decomposition (Sec. 4.4)
+  int nprof = 0, lsq_blocks = 0;
+  double *d_prof = nullptr, *d_gchol = nullptr, *d_theta = nullptr, *d_partial = nullptr;
+  double *d_c = nullptr, *d_bq = nullptr, *d_e = nullptr, *d_dq = nullptr;
+  // fine-grid scratch
+  int* d_tiles = nullptr;
+  int n_tiles = 0;
+  double* d_scratch_sat = nullptr;
+  double* d_scratch_ph = nullptr;
+  int* d_status = nullptr;
+  // reduced solver
+  int leaf_max = 2;
+  SolverPlan plan;
+  SolverDev sdev;
+  bool assembled = false;
+  hipStream_t last_stream = nullptr;
+  long long dev_bytes = 0;
+  ~Model();
+};
+
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles);
+int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double* basis, int nprof,
+                      const double* profiles, lrbms_model** out);
+
+}  // namespace lrbms

@@ -1,0 +1,363 @@
+// Fine-grid kernels of the online step on gfx950:
+//   pressure reconstruction p_h = sum_i (p_N)_i phi_i      (Alg. 3 step 5b)
+//   face fluxes of the conservative velocity              (Def. velocityDG)
+//   DG upwind explicit Euler saturation step              (Def. saturationDG)
+//   slope limiter                                         (eq. limiterMain)
+// and the matrix-free fine SWIP operator used by the offline snapshot solves.
+//
+// Readings (same as the CPU reference): RT0 on rectangles (one normal flux per
+// face, u_a linear in x_a only); v_N |f| as the flux on Neumann faces; upwind
+// trace taken from the low-side cell when the flux along +axis is >= 0; s_D on
+// saturation Dirichlet faces, the interior trace on other boundary faces;
+// shock detector with |int_f [s]| over inflow faces; the limited state keeps
+// the cell mean and scales the slope by min_i m_i; 2-point Gauss rules.
+//
+// All kernels are one thread per cell or per face with x-fastest indexing, so
+// neighbouring threads touch neighbouring addresses of the SoA arrays.
+#include "common.h"
+
+namespace lrbms {
+
+__device__ __forceinline__ double p1_value(const double* co, int d, const double sq[3], double isv) {
+  double v = co[0];
+  for (int a = 0; a < d; ++a) v += sq[a] * co[a + 1];
+  return v * isv;
+}
+
+// ---------------------------------------------------------------------------
+// p_h on the cells of one tile (box, first cell): coalesced over cells.
+__global__ __launch_bounds__(256) void k_reconstruct(Geom g, const Sub* __restrict__ subs,
+                                                     const int* __restrict__ tiles,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ pN,
+                                                     double* __restrict__ ph) {
+  const int sub = tiles[2 * blockIdx.x], c0 = tiles[2 * blockIdx.x + 1];
+  const Sub S = subs[sub];
+  const int l = c0 + threadIdx.x;
+  if (l >= S.nE) return;
+  const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+  const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
+  const int e = cell_index(g, x);
+  const int r = g.r;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* base = phi + S.phi_off + l;
+  const long long cs = (long long)r * S.nE;
+  for (int i = 0; i < S.NE; ++i) {
+    const double p = pN[S.pn_off + i];
+    for (int k = 0; k < r; ++k) acc[k] += base[i * cs + (long long)k * S.nE] * p;
+  }
+  for (int k = 0; k < r; ++k) ph[(long long)k * g.ncell + e] = acc[k];
+}
+
+hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const int* d_tiles,
+                              int n_tiles, const double* phi, const double* pN, double* ph,
+                              hipStream_t st) {
+  (void)n_sub;
+  hipLaunchKernelGGL(k_reconstruct, dim3(n_tiles), dim3(256), 0, st, g, d_subs, d_tiles, phi, pN,
+                     ph);
+  return hipGetLastError();
+}
+
+// Decode a global face number: axis, face coordinates.
+__device__ __forceinline__ void face_coords(const Geom& g, int fid, int& a, int x[3]) {
+  a = (fid >= g.foff[2] && g.dim == 3) ? 2 : (fid >= g.foff[1] ? 1 : 0);
+  int l = fid - g.foff[a];
+  int e0 = g.n[0], e1 = g.n[1];
+  if (a == 0) e0 += 1;
+  if (a == 1) e1 += 1;
+  x[0] = l % e0;
+  x[1] = (l / e0) % e1;
+  x[2] = l / (e0 * e1);
+}
+
+// int_f lambda(s) over a face of cell c at xi_a = xia (2-point Gauss).
+__device__ __forceinline__ double face_mobility_int(const Geom& g, const double* sat, int c, int a,
+                                                    double xia) {
+  const int d = g.dim, nc = g.ncell;
+  double co[4] = {0, 0, 0, 0};
+  for (int k = 0; k < g.r; ++k) co[k] = sat[(long long)k * nc + c];
+  int tax[2], nt = 0;
+  for (int b = 0; b < d; ++b)
+    if (b != a) tax[nt++] = b;
+  const double gp = 1.0 / kSqrt3;
+  double sum = 0.0;
+  for (int p = 0; p < (1 << nt); ++p) {
+    double sq[3] = {0, 0, 0};
+    sq[a] = kSqrt3 * xia;
+    for (int ti = 0; ti < nt; ++ti) sq[tax[ti]] = kSqrt3 * (((p >> ti) & 1) ? gp : -gp);
+    sum += total_mobility(g, p1_value(co, d, sq, g.isv));
+  }
+  return sum * g.area[a] / (1 << nt);
+}
+
+__global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__ ph,
+                                              const double* __restrict__ sat,
+                                              double* __restrict__ flux) {
+  const int fid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fid >= g.nface) return;
+  int a, x[3];
+  face_coords(g, fid, a, x);
+  const int nc = g.ncell;
+  const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
+  int xl[3] = {x[0], x[1], x[2]};
+  xl[a] -= 1;
+  const bool has_lo = x[a] >= 1, has_hi = x[a] < g.n[a];
+  if (has_lo && has_hi) {
+    const int c0 = cell_index(g, xl), c1 = cell_index(g, x);
+    const double k0 = g.perm[c0], k1 = g.perm[c1];
+    double w0, w1;
+    if (g.weights == 0) {
+      w0 = k1 / (k0 + k1);
+      w1 = k0 / (k0 + k1);
+    } else {
+      w0 = k0 / (k0 + k1);
+      w1 = k1 / (k0 + k1);
+    }
+    const double g0 = face_mobility_int(g, sat, c0, a, 1.0);
+    const double g1 = face_mobility_int(g, sat, c1, a, -1.0);
+    const double p00 = ph[c0], p0a = ph[(long long)(a + 1) * nc + c0];
+    const double p10 = ph[c1], p1a = ph[(long long)(a + 1) * nc + c1];
+    const double jump = g.area[a] * g.isv * ((p00 + kSqrt3 * p0a) - (p10 - kSqrt3 * p1a));
+    const double sig = g.pen * 2.0 * k0 * k1 / (k0 + k1) / g.hf[a];
+    flux[fid] = -(w0 * k0 * g0 * (gf * p0a) + w1 * k1 * g1 * (gf * p1a)) + sig * jump;
+    return;
+  }
+  const double al = has_lo ? 1.0 : -1.0;           // outward normal sign
+  const int c = has_lo ? cell_index(g, xl) : cell_index(g, x);
+  const int bt = g.bc_type[fid];
+  const double val = g.bc_val[fid];
+  double out = 0.0;
+  if (bt == LRBMS_BC_NEUMANN) {
+    out = val * g.area[a];
+  } else if (bt == LRBMS_BC_DIRICHLET) {
+    const double kc = g.perm[c];
+    const double gm = face_mobility_int(g, sat, c, a, al);
+    const double p0 = ph[c], pa = ph[(long long)(a + 1) * nc + c];
+    const double sig = g.pen * kc / g.hf[a];
+    const double trace = g.area[a] * g.isv * (p0 + kSqrt3 * al * pa);
+    out = -kc * gm * (al * gf * pa) + sig * (trace - val * g.area[a]);
+  }
+  flux[fid] = al * out;
+}
+
+hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, double* flux,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_flux, dim3((g.nface + 255) / 256), dim3(256), 0, st, g, ph, sat, flux);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_cell(const Geom& g, const double* s, int c, double* co) {
+  for (int k = 0; k < 4; ++k) co[k] = k < g.r ? s[(long long)k * g.ncell + c] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restrict__ sat,
+                                                   const double* __restrict__ flux,
+                                                   double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.ncell) return;
+  const int d = g.dim, r = g.r, nc = g.ncell;
+  int x[3];
+  cell_coords(g, e, x);
+  double se[4];
+  load_cell(g, sat, e, se);
+  double R[4] = {0.0, 0.0, 0.0, 0.0};
+  R[0] += g.q2[e] * g.vol * g.isv;
+  const double gp = 1.0 / kSqrt3;
+  // volume term int_e u f_w(s) . grad v
+  {
+    double Flo[3], Fhi[3];
+    for (int a = 0; a < d; ++a) {
+      int xf[3] = {x[0], x[1], x[2]};
+      Flo[a] = flux[face_index(g, a, xf)];
+      xf[a] += 1;
+      Fhi[a] = flux[face_index(g, a, xf)];
+    }
+    const int nq = 1 << d;
+    double acc[3] = {0, 0, 0};
+    for (int p = 0; p < nq; ++p) {
+      double xi[3], sq[3];
+      for (int a = 0; a < d; ++a) {
+        xi[a] = ((p >> a) & 1) ? gp : -gp;
+        sq[a] = kSqrt3 * xi[a];
+      }
+      const double fw = frac_flow(g, p1_value(se, d, sq, g.isv));
+      for (int a = 0; a < d; ++a) {
+        const double t = 0.5 * (1.0 + xi[a]);
+        const double ua = ((1.0 - t) * Flo[a] + t * Fhi[a]) / g.area[a];
+        acc[a] += ua * fw * (g.vol / nq);
+      }
+    }
+    for (int a = 0; a < d; ++a) R[a + 1] += (kSqrt3 * 2.0 / g.h[a] * g.isv) * acc[a];
+  }
+  // face terms
+  for (int a = 0; a < d; ++a) {
+    int tax[2], nt = 0;
+    for (int b = 0; b < d; ++b)
+      if (b != a) tax[nt++] = b;
+    const int nq = 1 << nt;
+    const double wq = g.area[a] / nq;
+    for (int dir = 0; dir < 2; ++dir) {
+      int xf[3] = {x[0], x[1], x[2]};
+      xf[a] += dir;
+      const int fid = face_index(g, a, xf);
+      const double F = flux[fid];
+      const double al = dir ? 1.0 : -1.0;   // position of the face in this cell
+      int xn[3] = {x[0], x[1], x[2]};
+      xn[a] += dir ? 1 : -1;
+      const bool interior = xn[a] >= 0 && xn[a] < g.n[a];
+      double sn[4] = {0, 0, 0, 0};
+      double ke = g.perm[e], kn = 0.0;
+      if (interior) {
+        const int en = cell_index(g, xn);
+        load_cell(g, sat, en, sn);
+        kn = g.perm[en];
+      }
+      const bool sd = !interior && g.bc_sat[fid] == 1;
+      const double sval = interior ? 0.0 : g.bc_sval[fid];
+      double sig;
+      if (interior) {
+        const double klo = dir ? ke : kn, khi = dir ? kn : ke;
+        sig = g.sat_pen * (g.pen * 2.0 * klo * khi / (klo + khi)) / g.hf[a];
+      } else {
+        sig = g.sat_pen * (g.pen * ke) / g.hf[a];
+      }
+      double acc[4] = {0, 0, 0, 0};
+      for (int p = 0; p < nq; ++p) {
+        double sqe[3] = {0, 0, 0}, sqn[3] = {0, 0, 0};
+        double xt[2] = {0, 0};
+        sqe[a] = kSqrt3 * al;
+        sqn[a] = -kSqrt3 * al;
+        for (int ti = 0; ti < nt; ++ti) {
+          xt[ti] = ((p >> ti) & 1) ? gp : -gp;
+          sqe[tax[ti]] = kSqrt3 * xt[ti];
+          sqn[tax[ti]] = kSqrt3 * xt[ti];
+        }
+        const double ve = p1_value(se, d, sqe, g.isv);
+        double tot;
+        if (interior) {
+          const double vn = p1_value(sn, d, sqn, g.isv);
+          const double vlo = dir ? ve : vn, vhi = dir ? vn : ve;
+          const double up = (F >= 0.0) ? vlo : vhi;
+          tot = (F / g.area[a]) * frac_flow(g, up) + sig * (vlo - vhi);
+        } else {
+          const double fout = al * F;
+          const double chi = sd ? sval : ve;
+          tot = (fout / g.area[a]) * frac_flow(g, chi) + (sd ? sig * (ve - sval) : 0.0);
+        }
+        // test trace of this cell: isv * {1, sqrt3*al, sqrt3*xi_t}
+        const double tw = tot * wq * g.isv;
+        acc[0] += tw;
+        acc[a + 1] += tw * kSqrt3 * al;
+        for (int ti = 0; ti < nt; ++ti) acc[tax[ti] + 1] += tw * kSqrt3 * xt[ti];
+      }
+      // [v] = +v on the low-side cell (face on its +a side), -v on the high-side cell;
+      // a boundary face has [v] = v
+      const double jv = interior ? al : 1.0;
+      for (int k = 0; k < r; ++k) R[k] -= jv * acc[k];
+    }
+  }
+  const double phi = g.poro[e];
+  for (int k = 0; k < r; ++k) out[(long long)k * nc + e] = se[k] + g.dt * R[k] / phi;
+}
+
+hipError_t launch_transport(const Geom& g, const double* sat, const double* flux, double* sat_bar,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_transport, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat, flux,
+                     sat_bar);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double gradient_scale(double gi, double di) {
+  const bool big = fabs(gi) > 1e-8 && fabs(di) > 1e-8;
+  if (big && gi * di < 0.0) return 0.0;
+  if (big && gi * di > 0.0 && fabs(gi) > fabs(di)) return di / gi;
+  return 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restrict__ sb,
+                                                 const double* __restrict__ flux,
+                                                 double* __restrict__ out,
+                                                 uint8_t* __restrict__ flags) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.ncell) return;
+  const int d = g.dim, r = g.r, nc = g.ncell;
+  int x[3];
+  cell_coords(g, e, x);
+  double se[4];
+  load_cell(g, sb, e, se);
+  const double mean = se[0] * g.isv;
+  bool outside = false;
+  for (int p = 0; p < (1 << d); ++p) {
+    double sq[3];
+    for (int a = 0; a < d; ++a) sq[a] = ((p >> a) & 1) ? kSqrt3 : -kSqrt3;
+    const double v = p1_value(se, d, sq, g.isv);
+    if (v < 0.0 || v > 1.0) outside = true;
+  }
+  const double gp = 1.0 / kSqrt3;
+  double S = 0.0, mmin = 1.0;
+  for (int a = 0; a < d; ++a) {
+    int tax[2], nt = 0;
+    for (int b = 0; b < d; ++b)
+      if (b != a) tax[nt++] = b;
+    const double wq = g.area[a] / (1 << nt);
+    for (int dir = 0; dir < 2; ++dir) {
+      int xf[3] = {x[0], x[1], x[2]};
+      xf[a] += dir;
+      const int fid = face_index(g, a, xf);
+      const double F = flux[fid];
+      const double al = dir ? 1.0 : -1.0;
+      int xn[3] = {x[0], x[1], x[2]};
+      xn[a] += dir ? 1 : -1;
+      const bool interior = xn[a] >= 0 && xn[a] < g.n[a];
+      double sn[4] = {0, 0, 0, 0};
+      if (interior) load_cell(g, sb, cell_index(g, xn), sn);
+      const bool inflow = (al * F) < 0.0;
+      const bool sd = !interior && g.bc_sat[fid] == 1;
+      if (inflow && (interior || sd)) {
+        double J = 0.0;
+        for (int p = 0; p < (1 << nt); ++p) {
+          double sqe[3] = {0, 0, 0}, sqn[3] = {0, 0, 0};
+          sqe[a] = kSqrt3 * al;
+          sqn[a] = -kSqrt3 * al;
+          for (int ti = 0; ti < nt; ++ti) {
+            const double xt = ((p >> ti) & 1) ? gp : -gp;
+            sqe[tax[ti]] = kSqrt3 * xt;
+            sqn[tax[ti]] = kSqrt3 * xt;
+          }
+          const double ve = p1_value(se, d, sqe, g.isv);
+          double jmp;
+          if (interior) {
+            const double vn = p1_value(sn, d, sqn, g.isv);
+            jmp = dir ? (ve - vn) : (vn - ve);   // low side minus high side
+          } else {
+            jmp = ve - g.bc_sval[fid];
+          }
+          J += jmp * wq;
+        }
+        S += fabs(J);
+      }
+      if (interior) {
+        const double ga = kSqrt3 * 2.0 / g.h[a] * g.isv * se[a + 1];
+        const double gi = ga * (al * g.h[a]);
+        const double di = sn[0] * g.isv - mean;
+        mmin = fmin(mmin, gradient_scale(gi, di));
+      }
+    }
+  }
+  S = S / (0.08 * d * sqrt(g.he) * g.vol);
+  const bool flag = (S > 1.0) || outside;
+  out[e] = se[0];
+  for (int k = 1; k < r; ++k) out[(long long)k * nc + e] = flag ? se[k] * mmin : se[k];
+  if (flags) flags[e] = flag ? 1 : 0;
+}
+
+hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
+                          double* sat_out, uint8_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_limiter, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat_bar, flux,
+                     sat_out, flags);
+  return hipGetLastError();
+}
+
+}  // namespace lrbms

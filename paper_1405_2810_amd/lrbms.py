@@ -1,0 +1,271 @@
+"""ctypes binding of liblrbms.so (include/lrbms.h).
+
+Argument marshalling only: every step of the online path runs in the HIP
+kernels of the library.  Device buffers are torch tensors on the GPU (their
+data_ptr is passed through), streams are torch streams (their raw hipStream_t).
+The library must be built (``python -m paper_1405_2810_amd.build`` or
+``__graft_entry__.build()``); importing this module without it fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrbms.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lrbms.h")
+
+DIRECT, DIRECT_FIT, AFFINE = 0, 1, 2
+ERRORS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_OOM", -4: "E_HIP", -5: "E_NOT_SPD",
+          -6: "E_NONFINITE", -7: "E_ADMIT"}
+
+
+class LrbmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem_C(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("len", C.c_double * 3),
+                ("nc", C.c_int32 * 3), ("cuts", C.c_void_p * 3),
+                ("perm", C.c_void_p), ("poro", C.c_void_p),
+                ("visc_w", C.c_double), ("visc_o", C.c_double),
+                ("relperm", C.c_int32), ("corey_w", C.c_double), ("corey_o", C.c_double),
+                ("bc_type", C.c_void_p), ("bc_val", C.c_void_p), ("bc_sat", C.c_void_p),
+                ("bc_sval", C.c_void_p), ("q1", C.c_void_p), ("q2", C.c_void_p),
+                ("penalty_c", C.c_double), ("weights", C.c_int32),
+                ("sat_penalty_scale", C.c_double), ("limiter", C.c_int32), ("dt", C.c_double)]
+
+
+class ModelInfo_C(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("r", C.c_int32), ("ncell", C.c_int32), ("nface", C.c_int32),
+                ("n_sub", C.c_int32), ("n_iface", C.c_int32), ("N", C.c_int32),
+                ("n_profiles", C.c_int32), ("n_block_entries", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1405_2810_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        L.lrbms_last_error.restype = C.c_char_p
+        L.lrbms_model_create.argtypes = [vp, vp, vp, i32, vp, C.POINTER(vp)]
+        L.lrbms_model_create_from_snapshots.argtypes = [vp, i32, vp, i32, i32, i32, vp, C.POINTER(vp)]
+        L.lrbms_model_get_info.argtypes = [vp, vp]
+        L.lrbms_model_export_basis.argtypes = [vp, vp, vp]
+        L.lrbms_model_interfaces.argtypes = [vp, vp, vp, vp]
+        L.lrbms_online_assemble.argtypes = [vp, vp, i32, vp]
+        L.lrbms_online_solve.argtypes = [vp, vp, vp]
+        L.lrbms_reconstruct_flux.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lrbms_transport_step.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lrbms_copy_reduced_system.argtypes = [vp, vp, vp]
+        L.lrbms_copy_theta.argtypes = [vp, vp]
+        L.lrbms_model_status.argtypes = [vp]
+        L.lrbms_model_destroy.argtypes = [vp]
+        L.lrbms_model_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/lrbms.h."""
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(lrbms_\w+)\s*\(", src, re.M)))
+
+
+def _check(rc):
+    if rc < 0:
+        raise LrbmsError(rc, lib().lrbms_last_error().decode())
+    return rc
+
+
+def _ptr(a) -> int:
+    """Address of a numpy array or torch tensor (0 for None)."""
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class ProblemC:
+    """lrbms_problem built from any object with the fields of a problem
+    description (dim, n, L, cuts, perm, poro, visc_w, ...).  Keeps the host
+    arrays alive while the struct is in use."""
+
+    def __init__(self, p):
+        self._keep = []
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(np.asarray(x), dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data
+
+        s = Problem_C()
+        s.dim = int(p.dim)
+        for a in range(3):
+            s.n[a] = int(p.n[a]) if a < p.dim else 1
+            s.len[a] = float(p.L[a]) if a < p.dim else 1.0
+            s.nc[a] = (len(p.cuts[a]) - 1) if a < p.dim else 1
+            s.cuts[a] = arr(p.cuts[a], np.int32) if a < p.dim else None
+        s.perm, s.poro = arr(p.perm, np.float64), arr(p.poro, np.float64)
+        s.visc_w, s.visc_o = float(p.visc_w), float(p.visc_o)
+        s.relperm, s.corey_w, s.corey_o = int(p.relperm), float(p.corey_w), float(p.corey_o)
+        s.bc_type, s.bc_val = arr(p.bc_type, np.int8), arr(p.bc_val, np.float64)
+        s.bc_sat, s.bc_sval = arr(p.bc_sat, np.int8), arr(p.bc_sval, np.float64)
+        s.q1, s.q2 = arr(p.q1, np.float64), arr(p.q2, np.float64)
+        s.penalty_c, s.weights = float(p.penalty_c), int(p.weights)
+        s.sat_penalty_scale, s.limiter, s.dt = float(p.sat_penalty_scale), int(p.limiter), float(p.dt)
+        self.struct = s
+
+    def ref(self):
+        return C.byref(self.struct)
+
+
+class Model:
+    """An LRBMS model resident on the device (opaque lrbms_model handle)."""
+
+    def __init__(self, handle, prob):
+        self._h = handle
+        self.prob = prob
+        info = ModelInfo_C()
+        _check(lib().lrbms_model_get_info(self._h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in ModelInfo_C._fields_}
+
+    # ---- creation ----------------------------------------------------
+    @classmethod
+    def create(cls, prob, sizes: Sequence[int], basis: np.ndarray, profiles=None):
+        pc = ProblemC(prob)
+        sz = np.ascontiguousarray(sizes, dtype=np.int32)
+        bs = np.ascontiguousarray(basis, dtype=np.float64)
+        prof = None if profiles is None or len(profiles) == 0 else \
+            np.ascontiguousarray(np.stack(profiles), dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().lrbms_model_create(pc.ref(), _ptr(sz), _ptr(bs),
+                                        0 if prof is None else prof.shape[0], _ptr(prof), C.byref(h)))
+        return cls(h, prob)
+
+    @classmethod
+    def from_snapshots(cls, prob, snapshots, ne_cap: int, unit_functions=True, profiles=None):
+        pc = ProblemC(prob)
+        sn = np.ascontiguousarray(np.stack(snapshots), dtype=np.float64)
+        prof = None if profiles is None or len(profiles) == 0 else \
+            np.ascontiguousarray(np.stack(profiles), dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().lrbms_model_create_from_snapshots(
+            pc.ref(), sn.shape[0], _ptr(sn), int(ne_cap), int(bool(unit_functions)),
+            0 if prof is None else prof.shape[0], _ptr(prof), C.byref(h)))
+        return cls(h, prob)
+
+    def close(self):
+        if self._h:
+            lib().lrbms_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- online step --------------------------------------------------
+    def assemble(self, sat, mode=DIRECT, stream=None):
+        _check(lib().lrbms_online_assemble(self._h, _ptr(sat), int(mode), _stream(stream)))
+
+    def solve(self, pN, stream=None):
+        _check(lib().lrbms_online_solve(self._h, _ptr(pN), _stream(stream)))
+
+    def reconstruct_flux(self, pN, sat, flux, ph=None, stream=None):
+        _check(lib().lrbms_reconstruct_flux(self._h, _ptr(pN), _ptr(sat), _ptr(flux), _ptr(ph),
+                                            _stream(stream)))
+
+    def transport_step(self, sat, flux, sat_out, flags=None, stream=None):
+        _check(lib().lrbms_transport_step(self._h, _ptr(sat), _ptr(flux), _ptr(sat_out),
+                                          _ptr(flags), _stream(stream)))
+
+    # ---- inspection ---------------------------------------------------
+    def reduced_system(self):
+        blocks = np.empty(self.info["n_block_entries"])
+        f = np.empty(self.info["N"])
+        _check(lib().lrbms_copy_reduced_system(self._h, _ptr(blocks), _ptr(f)))
+        return blocks, f
+
+    def theta(self):
+        t = np.empty(self.info["n_profiles"])
+        _check(lib().lrbms_copy_theta(self._h, _ptr(t)))
+        return t
+
+    def interfaces(self):
+        n = self.info["n_iface"]
+        ax, lo, hi = (np.empty(n, dtype=np.int32) for _ in range(3))
+        _check(lib().lrbms_model_interfaces(self._h, _ptr(ax), _ptr(lo), _ptr(hi)))
+        return ax, lo, hi
+
+    def export_basis(self):
+        sizes = np.empty(self.info["n_sub"], dtype=np.int32)
+        total = 0
+        # the exported length follows from the sizes; query them first
+        tmp = np.empty(1)
+        basis = None
+        cuts = [np.asarray(c) for c in self.prob.cuts]
+        ncells = []
+        for ez in range(len(cuts[2]) - 1 if self.prob.dim == 3 else 1):
+            for ey in range(len(cuts[1]) - 1):
+                for ex in range(len(cuts[0]) - 1):
+                    nz = (cuts[2][ez + 1] - cuts[2][ez]) if self.prob.dim == 3 else 1
+                    ncells.append((cuts[0][ex + 1] - cuts[0][ex]) * (cuts[1][ey + 1] - cuts[1][ey]) * nz)
+        # upper bound: 63 functions per box
+        basis = np.empty(sum(63 * self.info["r"] * n for n in ncells))
+        _check(lib().lrbms_model_export_basis(self._h, _ptr(sizes), _ptr(basis)))
+        total = sum(int(s) * self.info["r"] * n for s, n in zip(sizes, ncells))
+        del tmp
+        return sizes, basis[:total].copy()
+
+    def status(self):
+        return lib().lrbms_model_status(self._h)
+
+    def dense_reduced_matrix(self, blocks: Optional[np.ndarray] = None):
+        """Scatter the block storage into a dense N x N matrix (host)."""
+        if blocks is None:
+            blocks, _ = self.reduced_system()
+        sizes, offs = self.sizes_offsets()
+        N = self.info["N"]
+        A = np.zeros((N, N))
+        pos = 0
+        for E, ne in enumerate(sizes):
+            A[offs[E]:offs[E] + ne, offs[E]:offs[E] + ne] = blocks[pos:pos + ne * ne].reshape(ne, ne)
+            pos += ne * ne
+        ax, lo, hi = self.interfaces()
+        for t in range(len(ax)):
+            nl, nh = sizes[lo[t]], sizes[hi[t]]
+            B = blocks[pos:pos + nl * nh].reshape(nl, nh)
+            A[offs[lo[t]]:offs[lo[t]] + nl, offs[hi[t]]:offs[hi[t]] + nh] = B
+            A[offs[hi[t]]:offs[hi[t]] + nh, offs[lo[t]]:offs[lo[t]] + nl] = B.T
+            pos += nl * nh
+        return A
+
+    def sizes_offsets(self):
+        if not hasattr(self, "_sizes"):
+            self._sizes, _ = self.export_basis()
+            self._offs = np.concatenate([[0], np.cumsum(self._sizes)])
+        return self._sizes, self._offs

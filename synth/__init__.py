@@ -6,7 +6,7 @@ It holds none of the method's arithmetic: no discretization, no mobility, no
 solve.  Both the CPU oracle and the GPU path consume what it produces.
 """
 from .problems import (Problem, CONFIGS, make_problem, gaussian_field,
-                       face_counts, random_saturation, training_params)
+                       face_counts, random_saturation, training_params, smooth_fields)
 
 __all__ = ["Problem", "CONFIGS", "make_problem", "gaussian_field", "face_counts",
-           "random_saturation", "training_params"]
+           "random_saturation", "training_params", "smooth_fields"]

@@ -62,6 +62,7 @@ class Problem:
     basis_method: str = "gs"      # "gs" or "pca"
     pca_eps: float = 1e-4
     unit_functions: bool = True   # put 1_E first in every local basis
+    t_end: float = 0.0            # horizon T of the mobility profiles (0: n_steps * dt)
     seed: int = 0
     name: str = ""
 
@@ -173,6 +174,25 @@ def random_saturation(prob: Problem, rng, lo=0.0, hi=1.0, slope=0.2) -> np.ndarr
     return s
 
 
+def smooth_fields(prob: Problem, count: int, rng, corr: float = 0.3) -> list:
+    """Seeded smooth random P1 fields (SoA, orthonormal cell basis): cell
+    means from a Gaussian field of correlation length ``corr`` times the
+    domain size, small random slopes.  Timing inputs only."""
+    nx, ny, nz = prob.n
+    d = prob.dim
+    vol = float(np.prod(prob.h[:d]))
+    out = []
+    for _ in range(count):
+        shape = (ny, nx) if d == 2 else (nz, ny, nx)
+        hh = (prob.h[1], prob.h[0]) if d == 2 else (prob.h[2], prob.h[1], prob.h[0])
+        g = gaussian_field(shape, hh, corr * max(prob.L[:d]), rng).ravel()
+        f = np.zeros((d + 1) * prob.ncell)
+        f[:prob.ncell] = g * math.sqrt(vol)
+        f[prob.ncell:] = 0.05 * rng.standard_normal(d * prob.ncell) * math.sqrt(vol)
+        out.append(f)
+    return out
+
+
 def training_params(M: int, n_train: int, rng) -> np.ndarray:
     """Training parameters mu in the simplex (sum 1, entries >= 1e-4): first
     the M unit vectors (the profiles themselves), then seeded Dirichlet
@@ -194,26 +214,26 @@ CONFIGS: Dict[str, dict] = {
     # 2D unit square, 64x64, 4x4 coarse boxes, quarter five-spot
     "cfg1": dict(dim=2, n=(64, 64, 1), L=(1.0, 1.0, 1.0), nc=(4, 4, 1), corr=0.1,
                  sigma=1.0, ratio=10.0, steps=20, M=8, n_train=10, ne_cap=10,
-                 wells="quarter5", Q=2.0e-6, dt=1.6, seed=11),
+                 wells="quarter5", Q=2.0e-6, dt=1.6, seed=11, t_end=4.0e4),
     # 2D 256x256, 16x16 coarse boxes
     "cfg2": dict(dim=2, n=(256, 256, 1), L=(1.0, 1.0, 1.0), nc=(16, 16, 1), corr=0.05,
                  sigma=2.0, ratio=5.0, steps=200, M=16, n_train=26, ne_cap=25,
-                 wells="quarter5", Q=1.2e-6, dt=0.2, seed=22),
+                 wells="quarter5", Q=1.2e-6, dt=0.2, seed=22, t_end=8.0e4),
     # 3D layered + channelized 60x220x85 on 600x2200x170 m, 6x22x5 coarse boxes
     "cfg3": dict(dim=3, n=(60, 220, 85), L=(600.0, 2200.0, 170.0), nc=(6, 22, 5),
                  corr=0.1, sigma=3.0, ratio=10.0, steps=100, M=16, n_train=41,
-                 ne_cap=40, wells="five3d", Q=1.0e-2, dt=1.0e4, seed=33,
+                 ne_cap=40, wells="five3d", Q=1.0e-2, dt=1.0e4, seed=33, t_end=2.0e9,
                  channels=True),
     # small cases for tests
     "tiny2d": dict(dim=2, n=(8, 8, 1), L=(1.0, 1.0, 1.0), nc=(2, 2, 1), corr=0.2,
                    sigma=1.0, ratio=10.0, steps=5, M=4, n_train=6, ne_cap=6,
-                   wells="quarter5", Q=5.0e-6, dt=40.0, seed=5),
+                   wells="quarter5", Q=5.0e-6, dt=40.0, seed=5, t_end=1.0e4),
     "small2d": dict(dim=2, n=(32, 24, 1), L=(1.0, 0.75, 1.0), nc=(3, 2, 1), corr=0.1,
                     sigma=1.0, ratio=10.0, steps=10, M=6, n_train=9, ne_cap=8,
-                    wells="quarter5", Q=5.0e-6, dt=2.5, seed=7, uneven=True),
+                    wells="quarter5", Q=5.0e-6, dt=2.5, seed=7, uneven=True, t_end=1.5e4),
     "small3d": dict(dim=3, n=(12, 10, 6), L=(120.0, 100.0, 12.0), nc=(2, 2, 2),
                     corr=0.2, sigma=1.0, ratio=10.0, steps=5, M=5, n_train=8,
-                    ne_cap=8, wells="five3d", Q=1.0e-3, dt=5.0e3, seed=9),
+                    ne_cap=8, wells="five3d", Q=1.0e-3, dt=5.0e3, seed=9, t_end=1.5e7),
 }
 
 
@@ -340,4 +360,5 @@ def make_problem(name: str, seed: Optional[int] = None, **overrides) -> Problem:
                    M=cfg["M"], n_train=cfg["n_train"], ne_cap=cfg["ne_cap"],
                    basis_method=cfg.get("basis_method", "gs"),
                    pca_eps=cfg.get("pca_eps", 1e-4), unit_functions=True,
+                   t_end=cfg.get("t_end", 0.0),
                    seed=seed, name=name)
