@@ -188,6 +188,15 @@ int lrbms_model_interfaces(const lrbms_model* m, int32_t* axis, int32_t* lo, int
  * (host, [n_profiles]).  Synchronizes.                                          */
 int lrbms_copy_theta(lrbms_model* m, double* theta);
 
+/* Host-only inspection of the reduced solver's symbolic analysis (no device
+ * work): the nested-dissection assembly tree, fronts, index maps and the
+ * per-level work lists that the numeric kernels execute, flattened into
+ * int64 records (layout documented in the Python binding).  With buf == NULL
+ * or cap too small only *needed is set.  leaf_max: largest region (in boxes)
+ * that becomes a leaf front.                                                   */
+int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,
+                             int32_t leaf_max, int64_t* buf, int64_t cap, int64_t* needed);
+
 /* Synchronize and return the device status word (0 or a negative LRBMS_E_*). */
 int lrbms_model_status(lrbms_model* m);
 

@@ -628,6 +628,73 @@ void lrbms_model_destroy(lrbms_model* m) {
   delete M;
 }
 
+int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,
+                             int32_t leaf_max, int64_t* buf, int64_t cap, int64_t* needed) {
+  try {
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (!basis_sizes || !needed || leaf_max < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
+    Model tmp;
+    setup_layout(tmp, prob, basis_sizes);
+    SolverPlan plan;
+    if (!build_solver_plan(tmp.g.dim, tmp.nc, tmp.subs, tmp.ifaces, leaf_max, plan))
+      return (set_error("solver symbolic analysis failed"), LRBMS_E_ARG);
+    std::vector<int64_t> o;
+    const int H = plan.nlevels;
+    o.push_back((int64_t)plan.fronts.size());
+    o.push_back(H);
+    o.push_back((int64_t)plan.nodes.size());
+    o.push_back((int64_t)plan.children.size());
+    o.push_back((int64_t)plan.tasks.size());
+    o.push_back(plan.front_doubles);
+    o.push_back(plan.vec_doubles);
+    o.push_back(plan.inv_doubles);
+    o.push_back((int64_t)(plan.flops));
+    for (auto& f : plan.fronts) {
+      int64_t v[11] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
+                       f.nchild, f.n_s_nodes, 0};
+      o.insert(o.end(), v, v + 11);
+    }
+    for (auto& n : plan.nodes) {
+      int64_t v[4] = {n.pos, n.pn_off, n.size, n.pad};
+      o.insert(o.end(), v, v + 4);
+    }
+    for (int c : plan.children) o.push_back(c);
+    for (auto& t : plan.tasks) {
+      int64_t v[9] = {t.so, t.rs, t.cs, t.nr, t.nc, t.dr, t.dc, t.from_front, 0};
+      o.insert(o.end(), v, v + 9);
+    }
+    for (int h = 0; h < H; ++h) {
+      o.push_back((int64_t)plan.level_fronts[h].size());
+      for (int f : plan.level_fronts[h]) o.push_back(f);
+      o.push_back((int64_t)plan.asm_items[h].size());
+      for (auto& it : plan.asm_items[h]) {
+        int64_t v[5] = {it.front, it.col0, it.ncol, it.task_off, it.ntask};
+        o.insert(o.end(), v, v + 5);
+      }
+      o.push_back((int64_t)plan.panel_items[h].size());
+      for (size_t p = 0; p < plan.panel_items[h].size(); ++p) {
+        o.push_back((int64_t)plan.panel_items[h][p].size());
+        for (auto& it : plan.panel_items[h][p]) {
+          int64_t v[4] = {it.front, it.panel, it.row0, it.nrow};
+          o.insert(o.end(), v, v + 4);
+        }
+        o.push_back((int64_t)plan.upd_items[h][p].size());
+        for (auto& it : plan.upd_items[h][p]) {
+          int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
+          o.insert(o.end(), v, v + 4);
+        }
+      }
+    }
+    *needed = (int64_t)o.size();
+    if (buf && cap >= (int64_t)o.size()) std::copy(o.begin(), o.end(), buf);
+    return LRBMS_OK;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
 int lrbms_build_offline_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
                               lrbms_model** out) {
   (void)prob;

@@ -267,6 +267,123 @@ __device__ void cell_rhs(const Geom& g, int e, const int x[3], const double* __r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fine SWIP operator (Def. pressureDG) without assembly, for the offline
+// snapshot solves: y = A(gamma) x on every cell, the right-hand side l(gamma),
+// and the inverse r x r diagonal blocks used as block-Jacobi preconditioner.
+__device__ __noinline__ void fine_rows(const Geom& g, int e, const double* __restrict__ x,
+                          const double* __restrict__ mom, bool with_nbr, const double* ps_in,
+                          double* Y) {
+  const int d = g.dim, r = g.r, nc = g.ncell;
+  int xc[3];
+  cell_coords(g, e, xc);
+  double ps[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < r; ++k) ps[k] = ps_in ? ps_in[k] : x[(long long)k * nc + e];
+  const double ke = g.perm[e];
+  const double mv = mom[e];
+  for (int a = 0; a < d; ++a) {
+    const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
+    Y[a + 1] += ke * mv * (gf * gf) * ps[a + 1];
+  }
+  for (int a = 0; a < d; ++a) {
+    for (int dir = 0; dir < 2; ++dir) {
+      FaceCtx f;
+      f.a = a;
+      f.alpha = dir ? 1.0 : -1.0;
+      f.ks = ke;
+      load_moments(g, mom, e, a, dir, f.ms);
+      int xn[3] = {xc[0], xc[1], xc[2]};
+      xn[a] += dir ? 1 : -1;
+      double po[4] = {0.0, 0.0, 0.0, 0.0};
+      if (xn[a] >= 0 && xn[a] < g.n[a]) {
+        const int en = cell_index(g, xn);
+        f.interior = true;
+        f.ko = g.perm[en];
+        load_moments(g, mom, en, a, 1 - dir, f.mo);
+        if (with_nbr)
+          for (int k = 0; k < r; ++k) po[k] = x[(long long)k * nc + en];
+        face_rows(g, f, ps, po, true, true, Y);
+      } else {
+        int xf[3] = {xc[0], xc[1], xc[2]};
+        xf[a] += dir;
+        if (g.bc_type[face_index(g, a, xf)] == LRBMS_BC_DIRICHLET) {
+          f.interior = false;
+          f.ko = 0.0;
+          face_rows(g, f, ps, po, true, true, Y);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fine_apply(Geom g, const double* __restrict__ mom,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.ncell) return;
+  double Y[4] = {0.0, 0.0, 0.0, 0.0};
+  fine_rows(g, e, x, mom, true, nullptr, Y);
+  for (int k = 0; k < g.r; ++k) y[(long long)k * g.ncell + e] = Y[k];
+}
+
+hipError_t launch_fine_apply(const Geom& g, const double* mom, const double* x, double* y,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_fine_apply, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, mom, x, y);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fine_rhs(Geom g, const double* __restrict__ mom,
+                                                  double* __restrict__ l) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.ncell) return;
+  int xc[3];
+  cell_coords(g, e, xc);
+  double Y[4] = {0.0, 0.0, 0.0, 0.0};
+  cell_rhs(g, e, xc, mom, PART_RHS_CONST | PART_RHS_GAMMA, Y);
+  for (int k = 0; k < g.r; ++k) l[(long long)k * g.ncell + e] = Y[k];
+}
+
+hipError_t launch_fine_rhs(const Geom& g, const double* mom, double* l, hipStream_t st) {
+  hipLaunchKernelGGL(k_fine_rhs, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, mom, l);
+  return hipGetLastError();
+}
+
+// Inverse of the r x r diagonal block of every cell (Gauss-Jordan, no pivoting:
+// the blocks are SPD).
+__global__ __launch_bounds__(256) void k_fine_jacobi(Geom g, const double* __restrict__ mom,
+                                                     double* __restrict__ dinv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.ncell) return;
+  const int r = g.r;
+  double D[4][8];
+  for (int j = 0; j < r; ++j) {
+    double unit[4] = {0.0, 0.0, 0.0, 0.0};
+    unit[j] = 1.0;
+    double Y[4] = {0.0, 0.0, 0.0, 0.0};
+    fine_rows(g, e, nullptr, mom, false, unit, Y);
+    for (int i = 0; i < r; ++i) {
+      D[i][j] = Y[i];
+      D[i][r + j] = (i == j) ? 1.0 : 0.0;
+    }
+  }
+  for (int c = 0; c < r; ++c) {
+    const double piv = D[c][c];
+    for (int j = 0; j < 2 * r; ++j) D[c][j] /= piv;
+    for (int i = 0; i < r; ++i) {
+      if (i == c) continue;
+      const double f = D[i][c];
+      for (int j = 0; j < 2 * r; ++j) D[i][j] -= f * D[c][j];
+    }
+  }
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) dinv[(long long)(i * r + j) * g.ncell + e] = D[i][r + j];
+}
+
+hipError_t launch_fine_jacobi(const Geom& g, const double* mom, double* dinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_fine_jacobi, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, mom, dinv);
+  return hipGetLastError();
+}
+
 // Diagonal blocks A[E][E] and f_E: one workgroup per box.
 template <int COLS>
 __global__ __launch_bounds__(256) void k_assemble_diag(Geom g, const Sub* __restrict__ subs,

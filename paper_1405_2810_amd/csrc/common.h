@@ -133,5 +133,7 @@ hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* fl
                           double* sat_out, uint8_t* flags, hipStream_t st);
 hipError_t launch_fine_apply(const Geom& g, const double* mom, const double* x, double* y,
                              hipStream_t st);
+hipError_t launch_fine_rhs(const Geom& g, const double* mom, double* l, hipStream_t st);
+hipError_t launch_fine_jacobi(const Geom& g, const double* mom, double* dinv, hipStream_t st);
 
 }  // namespace lrbms

@@ -114,6 +114,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.children.clear();
   std::vector<std::map<int, int>> pos(nf);  // node -> position in front
   long long foff = 0, voff = 0, ioff = 0;
+  int noff = 0;
   plan.flops = 0.0;
   for (int p = 0; p < nf; ++p) {
     FrontH& f = F[p];
@@ -137,8 +138,9 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     d.inv_off = ioff;
     ioff += (long long)((d.m + kNB - 1) / kNB) * kNB * kNB;
     d.n_s_nodes = (int)f.S.size();
-    d.node_off = (int)plan.nodes.size();
+    d.node_off = noff;
     d.n_nodes = (int)(f.S.size() + f.U.size());
+    noff += d.n_nodes;
     d.child_off = (int)plan.children.size();
     d.nchild = (int)f.kids.size();
     for (int k : f.kids) plan.children.push_back(k);
@@ -354,10 +356,8 @@ __global__ __launch_bounds__(256) void k_front_panel(const PanelItem* __restrict
   __syncthreads();
   tile_chol_inv(D, Li, nb, status);
   if (it.row0 == c0) {
-    for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
-      const int i = idx % nb, j = idx / nb;
-      if (j <= i) Fp[(c0 + i) + (c0 + j) * ld] = D[i][j];
-    }
+    // Only the inverse of the diagonal tile is kept: the substitutions use it and
+    // the other workgroups of this launch still read the unfactored tile from F.
     double* Ip = Inv + f.inv_off + (long long)it.panel * kNB * kNB;
     for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x)
       Ip[idx] = Li[idx / kNB][idx % kNB];

@@ -57,6 +57,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1405_2810_amd/build.py")
+        # torch ships its own HIP runtime with the same soname as the system one;
+        # loading torch first makes the library bind to that single runtime, so
+        # device pointers and streams are shared with torch tensors.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
         L.lrbms_last_error.restype = C.c_char_p
@@ -269,3 +273,40 @@ class Model:
             self._sizes, _ = self.export_basis()
             self._offs = np.concatenate([[0], np.cumsum(self._sizes)])
         return self._sizes, self._offs
+
+
+def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
+    """Host-only export of the reduced solver's symbolic analysis
+    (lrbms_solver_plan_export), parsed into Python structures."""
+    L = lib()
+    L.lrbms_solver_plan_export.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                           C.c_int64, C.c_void_p]
+    pc = ProblemC(prob)
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    need = np.zeros(1, dtype=np.int64)
+    _check(L.lrbms_solver_plan_export(pc.ref(), _ptr(sz), int(leaf_max), None, 0, _ptr(need)))
+    buf = np.zeros(int(need[0]), dtype=np.int64)
+    _check(L.lrbms_solver_plan_export(pc.ref(), _ptr(sz), int(leaf_max), _ptr(buf), buf.size,
+                                      _ptr(need)))
+    it = iter(buf.tolist())
+    nxt = lambda k: [next(it) for _ in range(k)]
+    nf, H, nn, nch, nt, fd, vd, idd, flops = nxt(9)
+    fronts = [dict(zip(["off", "voff", "inv_off", "m", "u", "node_off", "n_nodes", "child_off",
+                        "nchild", "n_s_nodes", "_"], nxt(11))) for _ in range(nf)]
+    nodes = [dict(zip(["pos", "pn_off", "size", "ppos"], nxt(4))) for _ in range(nn)]
+    children = nxt(nch)
+    tasks = [dict(zip(["so", "rs", "cs", "nr", "nc", "dr", "dc", "from_front", "_"], nxt(9)))
+             for _ in range(nt)]
+    levels = []
+    for _ in range(H):
+        lf = nxt(next(it))
+        asm = [dict(zip(["front", "col0", "ncol", "task_off", "ntask"], nxt(5)))
+               for _ in range(next(it))]
+        panels = []
+        for _ in range(next(it)):
+            pi = [dict(zip(["front", "panel", "row0", "nrow"], nxt(4))) for _ in range(next(it))]
+            ui = [dict(zip(["front", "panel", "ti", "tj"], nxt(4))) for _ in range(next(it))]
+            panels.append((pi, ui))
+        levels.append(dict(fronts=lf, asm=asm, panels=panels))
+    return dict(fronts=fronts, nodes=nodes, children=children, tasks=tasks, levels=levels,
+                front_doubles=fd, vec_doubles=vd, inv_doubles=idd, flops=flops)
