@@ -111,6 +111,7 @@ Model::~Model() {
   f(d_scratch_ph);
   f(d_status);
   solver_free(sdev);
+  assemble_free(asm_layout);
 }
 
 // Fill geometry, boxes and interfaces (host side only).
@@ -277,6 +278,8 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
     }
   M.n_tiles = (int)tiles.size() / 2;
   if (!dev_copy(&M.d_tiles, tiles.data(), tiles.size(), b)) return LRBMS_E_OOM;
+  if (!hip_ok(assemble_prepare(g, M.subs, M.max_ne, M.asm_layout, b), "assembly layout"))
+    return LRBMS_E_OOM;
   // solver
   if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, M.leaf_max, M.plan)) {
     set_error("solver symbolic analysis failed");
@@ -312,7 +315,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
       return LRBMS_E_OOM;
     hipStream_t st = 0;
     // c: penalty part (gamma-free), e: gamma-free right-hand side
-    if (!hip_ok(launch_assemble(g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+    if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
                                 M.d_mom, PART_PEN | PART_RHS_CONST, M.d_c, M.d_e, st),
                 "assemble c, e"))
       return LRBMS_E_HIP;
@@ -321,7 +324,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
                                  st),
                   "profile moments"))
         return LRBMS_E_HIP;
-      if (!hip_ok(launch_assemble(g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+      if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
                                   M.d_mom, PART_GAMMA | PART_RHS_GAMMA, M.d_bq + (size_t)q * M.nblk,
                                   M.d_dq + (size_t)q * M.N, st),
                   "assemble b_q, d_q"))
@@ -526,7 +529,7 @@ int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, voi
                 "affine sum"))
       return LRBMS_E_HIP;
   } else {
-    if (!hip_ok(launch_assemble(g, M->d_subs, M->n_sub, M->max_ne, M->d_ifaces, M->n_iface,
+    if (!hip_ok(launch_assemble(M->asm_layout, g, M->d_subs, M->n_sub, M->max_ne, M->d_ifaces, M->n_iface,
                                 M->d_phi, M->d_mom, all, M->d_blocks, M->d_fN, st),
                 "assemble"))
       return LRBMS_E_HIP;
@@ -645,42 +648,37 @@ int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_siz
     o.push_back(H);
     o.push_back((int64_t)plan.nodes.size());
     o.push_back((int64_t)plan.children.size());
-    o.push_back((int64_t)plan.tasks.size());
+    o.push_back(0);
     o.push_back(plan.front_doubles);
     o.push_back(plan.vec_doubles);
     o.push_back(plan.inv_doubles);
     o.push_back((int64_t)(plan.flops));
     for (auto& f : plan.fronts) {
       int64_t v[11] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
-                       f.nchild, f.n_s_nodes, 0};
+                       f.nchild, f.n_s_nodes, f.npanels};
       o.insert(o.end(), v, v + 11);
     }
     for (auto& n : plan.nodes) {
-      int64_t v[4] = {n.pos, n.pn_off, n.size, n.pad};
+      int64_t v[4] = {n.pos, n.pn_off, n.size, n.ppos};
       o.insert(o.end(), v, v + 4);
     }
     for (int c : plan.children) o.push_back(c);
-    for (auto& t : plan.tasks) {
-      int64_t v[9] = {t.so, t.rs, t.cs, t.nr, t.nc, t.dr, t.dc, t.from_front, 0};
-      o.insert(o.end(), v, v + 9);
-    }
     for (int h = 0; h < H; ++h) {
       o.push_back((int64_t)plan.level_fronts[h].size());
       for (int f : plan.level_fronts[h]) o.push_back(f);
       o.push_back((int64_t)plan.asm_items[h].size());
       for (auto& it : plan.asm_items[h]) {
-        int64_t v[5] = {it.front, it.col0, it.ncol, it.task_off, it.ntask};
-        o.insert(o.end(), v, v + 5);
-      }
-      o.push_back((int64_t)plan.panel_items[h].size());
-      for (size_t p = 0; p < plan.panel_items[h].size(); ++p) {
-        o.push_back((int64_t)plan.panel_items[h][p].size());
-        for (auto& it : plan.panel_items[h][p]) {
-          int64_t v[4] = {it.front, it.panel, it.row0, it.nrow};
-          o.insert(o.end(), v, v + 4);
+        int64_t v[7] = {it.front, it.dr, it.dc, it.nr, it.nc, it.diag, it.nsrc};
+        o.insert(o.end(), v, v + 7);
+        for (int q = 0; q < 3; ++q) {
+          int64_t w[4] = {it.src[q].so, it.src[q].rs, it.src[q].cs, it.src[q].kind};
+          o.insert(o.end(), w, w + 4);
         }
-        o.push_back((int64_t)plan.upd_items[h][p].size());
-        for (auto& it : plan.upd_items[h][p]) {
+      }
+      o.push_back((int64_t)plan.step_items[h].size());
+      for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
+        o.push_back((int64_t)plan.step_items[h][p].size());
+        for (auto& it : plan.step_items[h][p]) {
           int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
           o.insert(o.end(), v, v + 4);
         }

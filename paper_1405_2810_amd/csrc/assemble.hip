@@ -18,6 +18,8 @@
 // Phi_E^T Y with one output column per thread.  The right-hand side rides
 // along as column N_E.  One workgroup per coarse interface builds the
 // coupling block the same way from the fine faces on the interface.
+#include <algorithm>
+
 #include "common.h"
 
 namespace lrbms {
@@ -384,75 +386,225 @@ hipError_t launch_fine_jacobi(const Geom& g, const double* mom, double* dinv, hi
   return hipGetLastError();
 }
 
-// Diagonal blocks A[E][E] and f_E: one workgroup per box.
+// Diagonal blocks A[E][E] and f_E.  One workgroup per (box, chunk of cells):
+//   stencil  the r x r blocks coupling each cell of the chunk to itself and to
+//            its 2d face neighbours, found once per cell by applying the face
+//            terms to unit trial vectors (summed over faces in a fixed order);
+//   apply    Y(cell, :) = K Phi for every (cell, column) pair, coalesced reads
+//            of the column-major Phi^E (neighbours outside the box are zero);
+//   contract partial A_E = Phi_chunk^T Y_chunk with one output column per
+//            thread; the right-hand side rides along as column N_E.
+// The partial blocks are summed over the chunks of a box in a fixed order by
+// k_reduce_diag.
+constexpr int kChunk = 32;
+
+__device__ void cell_stencil(const Geom& g, int e, const int x[3], const double* __restrict__ mom,
+                             int parts, int m, int kp, double* out) {
+  // m = 0: volume term; m = 1 + 2a + dir: face (a, dir).  Column kp of the block
+  // for the own trial dofs (out[0..r)) and, on interior faces, for the
+  // neighbour's trial dofs (out[r..2r)).
+  const int r = g.r;
+  const bool gam = parts & PART_GAMMA, pen = parts & PART_PEN;
+  double unit[4] = {0.0, 0.0, 0.0, 0.0}, zero[4] = {0.0, 0.0, 0.0, 0.0};
+  unit[kp] = 1.0;
+  for (int k = 0; k < 2 * r; ++k) out[k] = 0.0;
+  const double ke = g.perm[e];
+  if (m == 0) {
+    if (gam && kp >= 1) {
+      const int a = kp - 1;
+      const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
+      out[kp] = ke * mom[e] * (gf * gf);
+    }
+    return;
+  }
+  const int a = (m - 1) / 2, dir = (m - 1) % 2;
+  FaceCtx f;
+  f.a = a;
+  f.alpha = dir ? 1.0 : -1.0;
+  f.ks = ke;
+  load_moments(g, mom, e, a, dir, f.ms);
+  int xn[3] = {x[0], x[1], x[2]};
+  xn[a] += dir ? 1 : -1;
+  if (xn[a] >= 0 && xn[a] < g.n[a]) {
+    const int en = cell_index(g, xn);
+    f.interior = true;
+    f.ko = g.perm[en];
+    load_moments(g, mom, en, a, 1 - dir, f.mo);
+    face_rows(g, f, unit, zero, gam, pen, out);
+    face_rows(g, f, zero, unit, gam, pen, out + r);
+  } else {
+    int xf[3] = {x[0], x[1], x[2]};
+    xf[a] += dir;
+    if (g.bc_type[face_index(g, a, xf)] == LRBMS_BC_DIRICHLET) {
+      f.interior = false;
+      f.ko = 0.0;
+      face_rows(g, f, unit, zero, gam, pen, out);
+    }
+  }
+}
+
+template <int COLS>
+__host__ __device__ constexpr int chunk_cells() { return COLS <= 32 ? kChunk : kChunk / 2; }
+
+// Dynamic LDS of the box assembly: stencil blocks, then the Phi and Y staging.
+// The staging area also holds the tree reduction: (256 / cols / 2) * cols rows.
+__host__ __device__ inline size_t diag_lds_doubles(int cols, int r, int d) {
+  const int ch = cols <= 32 ? kChunk : kChunk / 2;
+  const size_t stage = 2 * (size_t)ch * r * (cols + 1);
+  const size_t red = (size_t)(256 / cols / 2) * cols * (cols + 1);
+  return (size_t)ch * (1 + 2 * d) * 2 * r * r + (stage > red ? stage : red);
+}
+
 template <int COLS>
 __global__ __launch_bounds__(256) void k_assemble_diag(Geom g, const Sub* __restrict__ subs,
+                                                       const int* __restrict__ chunks,
                                                        const double* __restrict__ phi,
                                                        const double* __restrict__ mom, int parts,
-                                                       double* __restrict__ blocks,
-                                                       double* __restrict__ fN, int chunk) {
-  extern __shared__ double lds[];
-  const Sub S = subs[blockIdx.x];
-  const int NE = S.NE, nE = S.nE, r = g.r;
-  const bool want_rhs = (parts & (PART_RHS_CONST | PART_RHS_GAMMA)) && fN != nullptr;
-  const bool want_mat = (parts & (PART_GAMMA | PART_PEN)) && blocks != nullptr;
-  const int ncol = NE + (want_rhs ? 1 : 0);
+                                                       double* __restrict__ partial) {
   constexpr int stride = COLS + 1;
   constexpr int NG = 256 / COLS;
-  double* Phil = lds;
-  double* Yl = lds + (size_t)chunk * r * stride;
+  constexpr int CH = chunk_cells<COLS>();
+  extern __shared__ double lds[];
+  __shared__ int cellg[CH], cellx[CH][3], nbl[CH][6];
+  const int sub = chunks[2 * blockIdx.x], c0 = chunks[2 * blockIdx.x + 1];
+  const Sub S = subs[sub];
+  const int NE = S.NE, nE = S.nE, r = g.r, d = g.dim, rr = r * r;
+  const int nm = 1 + 2 * d;
+  double* Kc = lds;                                   // [CH][nm][2][r*r]
+  double* Phil = Kc + (size_t)CH * nm * 2 * rr;       // [CH][r][stride]
+  double* Yl = Phil + (size_t)CH * r * stride;        // [CH][r][stride]
+  auto K = [&](int lc, int m, int side, int k, int kp) -> double& {
+    return Kc[(((size_t)lc * nm + m) * 2 + side) * rr + k * r + kp];
+  };
+  const bool want_rhs = parts & (PART_RHS_CONST | PART_RHS_GAMMA);
+  const bool want_mat = parts & (PART_GAMMA | PART_PEN);
+  const int ncol = NE + (want_rhs ? 1 : 0);
+  const int cc = min(CH, nE - c0);
+  const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+  const int bstride[3] = {1, bx, bx * by};
+  for (int lc = threadIdx.x; lc < cc; lc += blockDim.x) {
+    const int l = c0 + lc;
+    const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
+    cellg[lc] = cell_index(g, x);
+    for (int q = 0; q < 3; ++q) cellx[lc][q] = x[q];
+    for (int a = 0; a < 3; ++a)
+      for (int dir = 0; dir < 2; ++dir) {
+        const int xa = x[a] + (dir ? 1 : -1);
+        nbl[lc][2 * a + dir] = (a < d && xa >= S.lo[a] && xa < S.hi[a])
+                                   ? l + (dir ? bstride[a] : -bstride[a]) : -1;
+      }
+  }
+  __syncthreads();
+  // stencil: items (cell, m, trial dof)
+  if (want_mat) {
+    for (int it = threadIdx.x; it < cc * nm * r; it += blockDim.x) {
+      const int lc = it % cc, m = (it / cc) % nm, kp = it / (cc * nm);
+      const int x[3] = {cellx[lc][0], cellx[lc][1], cellx[lc][2]};
+      double out[8];
+      cell_stencil(g, cellg[lc], x, mom, parts, m, kp, out);
+      for (int k = 0; k < r; ++k) {
+        K(lc, m, 0, k, kp) = out[k];
+        K(lc, m, 1, k, kp) = out[r + k];
+      }
+    }
+  }
+  __syncthreads();
+  // apply: Y = K Phi for every (cell, column)
+  for (int p = threadIdx.x; p < cc * ncol; p += blockDim.x) {
+    const int lc = p % cc, col = p / cc;
+    const int l = c0 + lc;
+    double Y[4] = {0.0, 0.0, 0.0, 0.0};
+    if (col < NE) {
+      const double* cp = phi + S.phi_off + (long long)col * r * nE;
+      double ps[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < r; ++k) ps[k] = cp[(long long)k * nE + l];
+      if (want_mat) {
+        for (int m = 0; m < nm; ++m)
+          for (int k = 0; k < r; ++k) {
+            double v = 0.0;
+            for (int kp = 0; kp < r; ++kp) v += K(lc, m, 0, k, kp) * ps[kp];
+            Y[k] += v;
+          }
+        for (int m = 1; m < nm; ++m) {
+          const int ln = nbl[lc][m - 1];
+          if (ln < 0) continue;
+          double po[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int k = 0; k < r; ++k) po[k] = cp[(long long)k * nE + ln];
+          for (int k = 0; k < r; ++k) {
+            double v = 0.0;
+            for (int kp = 0; kp < r; ++kp) v += K(lc, m, 1, k, kp) * po[kp];
+            Y[k] += v;
+          }
+        }
+      }
+      for (int k = 0; k < r; ++k) Phil[((size_t)lc * r + k) * stride + col] = ps[k];
+    } else {
+      const int x[3] = {cellx[lc][0], cellx[lc][1], cellx[lc][2]};
+      cell_rhs(g, cellg[lc], x, mom, parts, Y);
+    }
+    for (int k = 0; k < r; ++k) Yl[((size_t)lc * r + k) * stride + col] = Y[k];
+  }
+  __syncthreads();
+  // contract: partial(i, j) = sum over the chunk's rows of Phi(row, i) Y(row, j)
   const int j = threadIdx.x % COLS, grp = threadIdx.x / COLS;
   double acc[COLS];
 #pragma unroll
   for (int i = 0; i < COLS; ++i) acc[i] = 0.0;
-  const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
-  for (int c0 = 0; c0 < nE; c0 += chunk) {
-    const int cc = min(chunk, nE - c0);
-    for (int p = threadIdx.x; p < cc * ncol; p += 256) {
-      const int lc = p % cc, col = p / cc;
-      const int l = c0 + lc;
-      const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
-      const int e = cell_index(g, x);
-      double Y[4] = {0.0, 0.0, 0.0, 0.0};
-      if (col < NE) {
-        const double* cp = phi + S.phi_off + (long long)col * r * nE;
-        double ps[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < r; ++k) ps[k] = cp[(long long)k * nE + l];
-        if (want_mat) cell_rows(g, S, e, x, l, cp, ps, mom, parts, Y);
-        for (int k = 0; k < r; ++k) Phil[(lc * r + k) * stride + col] = ps[k];
-      } else {
-        cell_rhs(g, e, x, mom, parts, Y);
-      }
-      for (int k = 0; k < r; ++k) Yl[(lc * r + k) * stride + col] = Y[k];
-    }
-    __syncthreads();
-    if (j < ncol) {
-      for (int lc = grp; lc < cc; lc += NG) {
-        for (int k = 0; k < r; ++k) {
-          const double y = Yl[(lc * r + k) * stride + j];
-          const double* pr = Phil + (lc * r + k) * stride;
-#pragma unroll
-          for (int i = 0; i < COLS; ++i)
-            if (i < NE) acc[i] += pr[i] * y;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // reduce the NG partial sums in a fixed order
-  double* red = lds;
   if (j < ncol) {
+    for (int lc = grp; lc < cc; lc += NG) {
+      for (int k = 0; k < r; ++k) {
+        const double y = Yl[((size_t)lc * r + k) * stride + j];
+        const double* pr = Phil + ((size_t)lc * r + k) * stride;
 #pragma unroll
-    for (int i = 0; i < COLS; ++i)
-      if (i < NE) red[(grp * COLS + i) * stride + j] = acc[i];
+        for (int i = 0; i < COLS; ++i)
+          if (i < NE) acc[i] += pr[i] * y;
+      }
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < NE * ncol; idx += 256) {
+  // fixed-order tree reduction over the NG groups in the staging area
+  double* red = Phil;   // sized for (NG / 2) * COLS * stride doubles (diag_lds_doubles)
+#pragma unroll
+  for (int half = NG / 2; half >= 1; half /= 2) {
+    if (grp >= half && grp < 2 * half && j < ncol) {
+#pragma unroll
+      for (int i = 0; i < COLS; ++i)
+        if (i < NE) red[((size_t)(grp - half) * COLS + i) * stride + j] = acc[i];
+    }
+    __syncthreads();
+    if (grp < half && j < ncol) {
+#pragma unroll
+      for (int i = 0; i < COLS; ++i)
+        if (i < NE) acc[i] += red[((size_t)grp * COLS + i) * stride + j];
+    }
+    __syncthreads();
+  }
+  if (grp == 0 && j < ncol) {
+    double* out = partial + (long long)blockIdx.x * COLS * stride;
+#pragma unroll
+    for (int i = 0; i < COLS; ++i)
+      if (i < NE) out[i * stride + j] = acc[i];
+  }
+}
+
+// Sum the chunk partials of every box in chunk order; write A[E][E] and f_E.
+template <int COLS>
+__global__ __launch_bounds__(256) void k_reduce_diag(const Sub* __restrict__ subs,
+                                                     const int* __restrict__ first_chunk,
+                                                     const double* __restrict__ partial,
+                                                     int has_mat, int has_rhs,
+                                                     double* __restrict__ blocks,
+                                                     double* __restrict__ fN) {
+  constexpr int stride = COLS + 1;
+  const Sub S = subs[blockIdx.x];
+  const int q0 = first_chunk[blockIdx.x], q1 = first_chunk[blockIdx.x + 1];
+  const int NE = S.NE, ncol = NE + (has_rhs ? 1 : 0);
+  for (int idx = threadIdx.x; idx < NE * ncol; idx += blockDim.x) {
     const int i = idx / ncol, jj = idx % ncol;
     double v = 0.0;
-    for (int q = 0; q < NG; ++q) v += red[(q * COLS + i) * stride + jj];
+    for (int q = q0; q < q1; ++q) v += partial[(long long)q * COLS * stride + i * stride + jj];
     if (jj < NE) {
-      if (want_mat) blocks[S.blk_off + (long long)i * NE + jj] = v;
+      if (has_mat) blocks[S.blk_off + (long long)i * NE + jj] = v;
     } else {
       fN[S.pn_off + i] = v;
     }
@@ -553,30 +705,32 @@ __global__ __launch_bounds__(256) void k_assemble_iface(Geom g, const Sub* __res
 }
 
 template <int COLS>
-static hipError_t launch_assemble_t(const Geom& g, const Sub* d_subs, int n_sub,
-                                    const Iface* d_ifaces, int n_iface, const double* phi,
-                                    const double* mom, int parts, double* blocks, double* fN,
-                                    hipStream_t st) {
-  constexpr int stride = COLS + 1;
-  const size_t budget = 72 * 1024;
-  int chunk = (int)(budget / (sizeof(double) * 2 * g.r * stride));
-  if (chunk < 1) chunk = 1;
-  const size_t lds_chunk = sizeof(double) * 2 * (size_t)chunk * g.r * stride;
-  const size_t lds_red = sizeof(double) * (size_t)(256 / COLS) * COLS * stride;
-  const size_t lds = lds_chunk > lds_red ? lds_chunk : lds_red;
-  hipError_t ea = hipFuncSetAttribute((const void*)k_assemble_diag<COLS>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (ea != hipSuccess) return ea;
-  ea = hipFuncSetAttribute((const void*)k_assemble_iface<COLS>,
-                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (ea != hipSuccess) return ea;
-  if (n_sub > 0) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_diag<COLS>), dim3(n_sub), dim3(256), lds, st,
-                       g, d_subs, phi, mom, parts, blocks, fN, chunk);
+static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub* d_subs,
+                                    int n_sub, const Iface* d_ifaces, int n_iface,
+                                    const double* phi, const double* mom, int parts,
+                                    double* blocks, double* fN, hipStream_t st) {
+  const bool has_mat = (parts & (PART_GAMMA | PART_PEN)) && blocks;
+  const bool has_rhs = (parts & (PART_RHS_CONST | PART_RHS_GAMMA)) && fN;
+  const int pdiag = (has_mat ? (PART_GAMMA | PART_PEN) & parts : 0) |
+                    (has_rhs ? (PART_RHS_CONST | PART_RHS_GAMMA) & parts : 0);
+  if (n_sub > 0 && pdiag) {
+    const size_t lds = sizeof(double) * diag_lds_doubles(COLS, g.r, g.dim);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_diag<COLS>), dim3(L.n_chunks), dim3(256), lds,
+                       st, g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce_diag<COLS>), dim3(n_sub), dim3(256), 0, st,
+                       d_subs, L.first_chunk, L.partial, has_mat ? 1 : 0, has_rhs ? 1 : 0, blocks,
+                       fN);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (n_iface > 0 && blocks && (parts & (PART_GAMMA | PART_PEN))) {
+  if (n_iface > 0 && has_mat) {
+    constexpr int stride = COLS + 1;
+    const size_t budget = 72 * 1024;
+    int chunk = (int)(budget / (sizeof(double) * 2 * g.r * stride));
+    if (chunk < 1) chunk = 1;
+    const size_t lds_chunk = sizeof(double) * 2 * (size_t)chunk * g.r * stride;
+    const size_t lds_red = sizeof(double) * (size_t)(256 / COLS) * COLS * stride;
+    const size_t lds = lds_chunk > lds_red ? lds_chunk : lds_red;
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_iface<COLS>), dim3(n_iface), dim3(256), lds,
                        st, g, d_subs, d_ifaces, phi, mom, parts, blocks, chunk);
     return hipGetLastError();
@@ -584,19 +738,83 @@ static hipError_t launch_assemble_t(const Geom& g, const Sub* d_subs, int n_sub,
   return hipSuccess;
 }
 
-hipError_t launch_assemble(const Geom& g, const Sub* d_subs, int n_sub, int max_ne,
-                           const Iface* d_ifaces, int n_iface, const double* phi,
+int assemble_cols(int max_ne) { return max_ne + 1 <= 16 ? 16 : (max_ne + 1 <= 32 ? 32 : 64); }
+
+hipError_t assemble_prepare(const Geom& g, const std::vector<Sub>& subs, int max_ne,
+                            AsmLayout& L, long long& bytes) {
+  std::vector<int> chunks, first(1, 0);
+  const int ch = assemble_cols(max_ne) <= 32 ? kChunk : kChunk / 2;
+  for (size_t s = 0; s < subs.size(); ++s) {
+    for (int c0 = 0; c0 < subs[s].nE; c0 += ch) {
+      chunks.push_back((int)s);
+      chunks.push_back(c0);
+    }
+    first.push_back((int)chunks.size() / 2);
+  }
+  L.n_chunks = (int)chunks.size() / 2;
+  const int cols = assemble_cols(max_ne);
+  hipError_t e;
+  if ((e = hipMalloc(&L.chunks, chunks.size() * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMemcpy(L.chunks, chunks.data(), chunks.size() * sizeof(int),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  if ((e = hipMalloc(&L.first_chunk, first.size() * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMemcpy(L.first_chunk, first.data(), first.size() * sizeof(int),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  const size_t np = (size_t)L.n_chunks * cols * (cols + 1);
+  if ((e = hipMalloc(&L.partial, np * sizeof(double))) != hipSuccess) return e;
+  bytes += (long long)(np * sizeof(double) + (chunks.size() + first.size()) * sizeof(int));
+  // the interface kernel may use more than 64 KB of dynamic LDS
+  const int stride = cols + 1;
+  const size_t budget = 72 * 1024;
+  int chunk = (int)(budget / (sizeof(double) * 2 * g.r * stride));
+  if (chunk < 1) chunk = 1;
+  size_t lds = std::max(sizeof(double) * 2 * (size_t)chunk * g.r * stride,
+                        sizeof(double) * (size_t)(256 / cols) * cols * stride);
+  const int dl = (int)(sizeof(double) * diag_lds_doubles(cols, g.r, g.dim));
+  if (cols == 16)
+    e = hipFuncSetAttribute((const void*)k_assemble_diag<16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+  else if (cols == 32)
+    e = hipFuncSetAttribute((const void*)k_assemble_diag<32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+  else
+    e = hipFuncSetAttribute((const void*)k_assemble_diag<64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dl);
+  if (e != hipSuccess) return e;
+  if (cols == 16)
+    e = hipFuncSetAttribute((const void*)k_assemble_iface<16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  else if (cols == 32)
+    e = hipFuncSetAttribute((const void*)k_assemble_iface<32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  else
+    e = hipFuncSetAttribute((const void*)k_assemble_iface<64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return e;
+}
+
+void assemble_free(AsmLayout& L) {
+  if (L.chunks) (void)hipFree(L.chunks);
+  if (L.first_chunk) (void)hipFree(L.first_chunk);
+  if (L.partial) (void)hipFree(L.partial);
+  L = AsmLayout{};
+}
+
+hipError_t launch_assemble(const AsmLayout& L, const Geom& g, const Sub* d_subs, int n_sub,
+                           int max_ne, const Iface* d_ifaces, int n_iface, const double* phi,
                            const double* mom, int parts, double* blocks, double* fN,
                            hipStream_t st) {
-  // the right-hand side needs one spare column
-  if (max_ne + 1 <= 16)
-    return launch_assemble_t<16>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
+  const int cols = assemble_cols(max_ne);
+  if (cols == 16)
+    return launch_assemble_t<16>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
                                  fN, st);
-  if (max_ne + 1 <= 32)
-    return launch_assemble_t<32>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
+  if (cols == 32)
+    return launch_assemble_t<32>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
                                  fN, st);
-  return launch_assemble_t<64>(g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks, fN,
-                               st);
+  return launch_assemble_t<64>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts, blocks,
+                               fN, st);
 }
 
 // ---------------------------------------------------------------------------

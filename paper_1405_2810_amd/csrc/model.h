@@ -32,6 +32,7 @@ struct Model {
   double* d_scratch_sat = nullptr;
   double* d_scratch_ph = nullptr;
   int* d_status = nullptr;
+  AsmLayout asm_layout;
   // reduced solver
   int leaf_max = 2;
   SolverPlan plan;

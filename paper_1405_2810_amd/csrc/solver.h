@@ -6,43 +6,57 @@
 // bisection of the box grid along its longest axis with one separator slab),
 // builds the assembly tree of fronts (a front = one separator or one small
 // leaf region; its update set U = the boxes adjacent to its region, all of
-// them in ancestor separators) and all index maps.  The numeric phase runs
-// every step on the device, one tree level at a time:
-//   assemble  zero the fronts, add the blocks of A_N, extend-add the
-//             children's update matrices (children in a fixed order);
-//   panel     Cholesky of a NB x NB diagonal tile in LDS, its triangular
-//             inverse, and L = F Linv^T for the tile rows below it;
-//   update    F(ti, tj) -= L(ti) L(tj)^T on the trailing tiles;
-//   forward / backward substitution with the stored tile inverses.
+// them in ancestor separators) and all index maps.
+//
+// Every front is stored dense, column-major, with one extra row at the
+// bottom that carries the right-hand side, so that the forward substitution
+// happens inside the factorization.  The numeric phase runs every step on
+// the device, one tree level at a time:
+//   assemble  one workgroup per destination block of a front (box pair, or the
+//             right-hand-side row against one box): the block of A_N or f_N
+//             plus the children's update blocks, summed in a fixed order and
+//             written once; then one workgroup per front factors its first
+//             diagonal tile;
+//   step      one launch per panel: every tile workgroup forms its rows of L
+//             (F Linv^T, kept in a separate buffer), and applies the trailing
+//             update F(ti,tj) -= L(ti) L(tj)^T; the workgroup of the next
+//             diagonal tile factors it (look-ahead);
+//   backward  one workgroup per front, from the root down, with the stored
+//             tile inverses.
+// Diagonal tiles are factored by a 16-wide blocked Cholesky: the 16 x 16
+// diagonal blocks are factored and inverted in registers by one wave, the
+// panel solves and trailing updates are parallel over the workgroup; the
+// inverse is completed block diagonal by block diagonal.
 #pragma once
 
 #include "common.h"
 
 namespace lrbms {
 
-constexpr int kNB = 64;  // panel / tile width of the dense front kernels
+constexpr int kNB = 64;       // panel / tile width of the dense front kernels
+constexpr int kMaxLd = 8192;  // largest front (rows) handled by the backward sweep
 
 struct FrontD {
-  long long off;    // front storage (column-major, ld = m + u)
-  long long voff;   // front vector workspace
-  long long inv_off;// tile inverses, one kNB x kNB per panel
+  long long off;      // front storage (column-major, lda = m + u + 1, m + u columns)
+  long long voff;     // backward-substitution vector workspace
+  long long inv_off;  // tile inverses, one kNB x kNB per panel
   int m, u;
-  int node_off, n_nodes;   // nodes of S then U: (pos in front, p_N offset, size)
+  int node_off, n_nodes;   // nodes of S then U: (pos in front, p_N offset, size, pos in parent)
   int child_off, nchild;   // children (front ids) in extend-add order
-  int n_s_nodes;
+  int n_s_nodes, npanels;
 };
 
-struct NodeRef { int pos, pn_off, size, pad; };
+struct NodeRef { int pos, pn_off, size, ppos; };
 
-// Strided block add into a front: F[(dr+i) + (dc+j)*ld] += src[so + i*rs + j*cs].
-struct AddTask {
-  long long so;
-  int rs, cs, nr, nc, dr, dc, from_front, pad;
-};
-
-struct AsmItem { int front, col0, ncol, task_off, ntask, pad; };
-struct PanelItem { int front, panel, row0, nrow; };
-struct UpdItem { int front, panel, ti, tj; };
+// One destination block of a front (box pair, or the right-hand-side row against
+// one box) with up to three sources summed in a fixed order: the block of A_N
+// or f_N, then the children's update blocks.  Source element (i, j) is
+// src[so + i*rs + j*cs] in the blocks of A_N (kind 0), the front storage (1) or
+// f_N (2).  diag: a diagonal block, of which only the lower part is formed.
+struct AsmSrc { long long so; int rs, cs, kind, pad; };
+struct AsmItem { int front, dr, dc, nr, nc, diag, nsrc, pad; AsmSrc src[3]; };
+// One tile of the fused panel step; tj = -1: rows only (no trailing columns).
+struct StepItem { int front, panel, ti, tj; };
 
 struct SolverPlan {
   std::vector<FrontD> fronts;
@@ -50,18 +64,14 @@ struct SolverPlan {
   std::vector<int> children;
   std::vector<int> elim;                       // elimination position of every box
   int nlevels = 0;
-  // per level
-  std::vector<std::vector<int>> level_fronts;  // front ids
+  std::vector<std::vector<int>> level_fronts;  // front ids per level (height)
   std::vector<std::vector<AsmItem>> asm_items;
-  std::vector<AddTask> tasks;
-  std::vector<std::vector<std::vector<PanelItem>>> panel_items;  // [level][panel]
-  std::vector<std::vector<std::vector<UpdItem>>> upd_items;      // [level][panel]
+  std::vector<std::vector<std::vector<StepItem>>> step_items;  // [level][panel]
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
-  long long front_bytes_touched = 0;
 };
 
-// Build the plan for a box grid nc[3] with box sizes ne[n_sub] and interfaces.
+// Build the plan for the box grid with box sizes subs[].NE and interfaces.
 bool build_solver_plan(int dim, const int nc[3], const std::vector<Sub>& subs,
                        const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan);
 
@@ -70,12 +80,11 @@ struct SolverDev {
   FrontD* fronts = nullptr;
   NodeRef* nodes = nullptr;
   int* children = nullptr;
-  AddTask* tasks = nullptr;
   std::vector<AsmItem*> asm_items;
-  std::vector<std::vector<PanelItem*>> panel_items;
-  std::vector<std::vector<UpdItem*>> upd_items;
+  std::vector<std::vector<StepItem*>> step_items;
   std::vector<int*> level_fronts;
   double* F = nullptr;
+  double* L = nullptr;
   double* V = nullptr;
   double* Inv = nullptr;
   long long bytes = 0;

@@ -112,7 +112,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.fronts.assign(nf, FrontD{});
   plan.nodes.clear();
   plan.children.clear();
-  std::vector<std::map<int, int>> pos(nf);  // node -> position in front
+  std::vector<std::map<int, int>> pos(nf);  // box -> position in front
   long long foff = 0, voff = 0, ioff = 0;
   int noff = 0;
   plan.flops = 0.0;
@@ -132,11 +132,12 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     d.u = ps - d.m;
     const long long ld = d.m + d.u;
     d.off = foff;
-    foff += ld * ld;
+    foff += (ld + 1) * ld;
     d.voff = voff;
     voff += ld;
+    d.npanels = (d.m + kNB - 1) / kNB;
     d.inv_off = ioff;
-    ioff += (long long)((d.m + kNB - 1) / kNB) * kNB * kNB;
+    ioff += (long long)d.npanels * kNB * kNB;
     d.n_s_nodes = (int)f.S.size();
     d.node_off = noff;
     d.n_nodes = (int)(f.S.size() + f.U.size());
@@ -149,15 +150,16 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   }
   for (int p = 0; p < nf; ++p) {
     FrontH& f = F[p];
+    if (f.kids.size() > 2) return false;
     auto add_ref = [&](int v, bool is_u) {
       NodeRef r;
       r.pos = pos[p].at(v);
       r.pn_off = subs[v].pn_off;
       r.size = subs[v].NE;
-      r.pad = -1;
+      r.ppos = -1;
       if (is_u) {
         if (f.parent < 0 || !pos[f.parent].count(v)) return false;
-        r.pad = pos[f.parent].at(v);
+        r.ppos = pos[f.parent].at(v);
       }
       plan.nodes.push_back(r);
       return true;
@@ -176,99 +178,120 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.nlevels = H;
   plan.level_fronts.assign(H, {});
   for (int p = 0; p < nf; ++p) plan.level_fronts[F[p].height].push_back(p);
-  // assembly items and tasks: one item per (front, column box)
+  // assembly: one item per destination block of every front
   plan.asm_items.assign(H, {});
-  plan.tasks.clear();
   for (int h = 0; h < H; ++h) {
     for (int p : plan.level_fronts[h]) {
       FrontH& f = F[p];
       const FrontD& d = plan.fronts[p];
+      const int ld = d.m + d.u;
+      if (ld + 1 > kMaxLd) return false;
       std::vector<int> order = f.S;
       order.insert(order.end(), f.U.begin(), f.U.end());
+      auto child_src = [&](int k, int v, int w, AsmSrc& s) {
+        // update block (v, w) of child k (w = -1: its update row at box v)
+        const FrontD& dc = plan.fronts[k];
+        const long long ldc = dc.m + dc.u, ldac = ldc + 1;
+        if (!pos[k].count(v) || pos[k][v] < dc.m) return false;
+        if (w >= 0 && (!pos[k].count(w) || pos[k][w] < dc.m)) return false;
+        if (w < 0) {
+          s.so = dc.off + ldc + (long long)pos[k][v] * ldac;
+          s.rs = 0;
+          s.cs = (int)ldac;
+        } else {
+          s.so = dc.off + pos[k][v] + (long long)pos[k][w] * ldac;
+          s.rs = 1;
+          s.cs = (int)ldac;
+        }
+        s.kind = 1;
+        s.pad = 0;
+        return true;
+      };
       for (size_t wi = 0; wi < order.size(); ++wi) {
         const int w = order[wi];
-        AsmItem it;
-        it.front = p;
-        it.col0 = pos[p][w];
-        it.ncol = subs[w].NE;
-        it.task_off = (int)plan.tasks.size();
-        it.pad = 0;
-        if (wi < f.S.size()) {
-          for (size_t vi = wi; vi < order.size(); ++vi) {
-            const int v = order[vi];
-            AddTask t{};
-            t.nr = subs[v].NE;
-            t.nc = subs[w].NE;
-            t.dr = pos[p][v];
-            t.dc = pos[p][w];
-            t.from_front = 0;
+        const bool w_in_s = wi < f.S.size();
+        for (size_t vi = wi; vi < order.size(); ++vi) {
+          const int v = order[vi];
+          AsmItem it{};
+          it.front = p;
+          it.dr = pos[p][v];
+          it.dc = pos[p][w];
+          it.nr = subs[v].NE;
+          it.nc = subs[w].NE;
+          it.diag = v == w;
+          it.nsrc = 0;
+          if (w_in_s) {
+            AsmSrc s{};
+            s.kind = 0;
+            bool have = true;
             if (v == w) {
-              t.so = subs[v].blk_off;
-              t.rs = subs[v].NE;
-              t.cs = 1;
+              s.so = subs[v].blk_off;
+              s.rs = subs[v].NE;
+              s.cs = 1;
             } else if (iface_of.count({v, w})) {
-              const Iface& I = ifaces[iface_of[{v, w}]];   // v = lo, w = hi: A[v][w]
-              t.so = I.blk_off;
-              t.rs = subs[w].NE;
-              t.cs = 1;
+              s.so = ifaces[iface_of[{v, w}]].blk_off;   // v = lo, w = hi: A[v][w]
+              s.rs = subs[w].NE;
+              s.cs = 1;
             } else if (iface_of.count({w, v})) {
-              const Iface& I = ifaces[iface_of[{w, v}]];   // A[v][w] = A[w][v]^T
-              t.so = I.blk_off;
-              t.rs = 1;
-              t.cs = subs[v].NE;
+              s.so = ifaces[iface_of[{w, v}]].blk_off;   // A[v][w] = A[w][v]^T
+              s.rs = 1;
+              s.cs = subs[v].NE;
             } else {
-              continue;
+              have = false;
             }
-            plan.tasks.push_back(t);
+            if (have) it.src[it.nsrc++] = s;
           }
+          for (int k : f.kids) {
+            AsmSrc s{};
+            if (child_src(k, v, w, s)) it.src[it.nsrc++] = s;
+          }
+          plan.asm_items[h].push_back(it);
+        }
+        AsmItem r{};   // right-hand-side row at box w
+        r.front = p;
+        r.dr = ld;
+        r.dc = pos[p][w];
+        r.nr = 1;
+        r.nc = subs[w].NE;
+        r.diag = 0;
+        r.nsrc = 0;
+        if (w_in_s) {
+          AsmSrc s{};
+          s.so = subs[w].pn_off;
+          s.rs = 0;
+          s.cs = 1;
+          s.kind = 2;
+          r.src[r.nsrc++] = s;
         }
         for (int k : f.kids) {
-          const FrontH& fc = F[k];
-          const FrontD& dc = plan.fronts[k];
-          if (!pos[k].count(w) || pos[k][w] < dc.m) continue;   // w not in U of child
-          const long long ldc = dc.m + dc.u;
-          for (int v : fc.U) {
-            if (plan.elim[v] < plan.elim[w]) continue;
-            AddTask t{};
-            t.nr = subs[v].NE;
-            t.nc = subs[w].NE;
-            t.dr = pos[p][v];
-            t.dc = pos[p][w];
-            t.from_front = 1;
-            t.so = dc.off + pos[k][v] + (long long)pos[k][w] * ldc;
-            t.rs = 1;
-            t.cs = (int)ldc;
-            plan.tasks.push_back(t);
-          }
+          AsmSrc s{};
+          if (child_src(k, w, -1, s)) r.src[r.nsrc++] = s;
         }
-        it.ntask = (int)plan.tasks.size() - it.task_off;
-        plan.asm_items[h].push_back(it);
+        plan.asm_items[h].push_back(r);
       }
-      (void)d;
     }
   }
-  // panel and update items
-  plan.panel_items.assign(H, {});
-  plan.upd_items.assign(H, {});
+  // fused panel steps
+  plan.step_items.assign(H, {});
   for (int h = 0; h < H; ++h) {
     int maxp = 0;
-    for (int p : plan.level_fronts[h])
-      maxp = std::max(maxp, (plan.fronts[p].m + kNB - 1) / kNB);
-    plan.panel_items[h].assign(maxp, {});
-    plan.upd_items[h].assign(maxp, {});
+    for (int p : plan.level_fronts[h]) maxp = std::max(maxp, plan.fronts[p].npanels);
+    plan.step_items[h].assign(maxp, {});
     for (int p : plan.level_fronts[h]) {
       const FrontD& d = plan.fronts[p];
       const int ld = d.m + d.u;
-      const int np = (d.m + kNB - 1) / kNB;
-      for (int b = 0; b < np; ++b) {
-        const int c0 = b * kNB, nb = std::min(kNB, d.m - c0);
-        plan.panel_items[h][b].push_back(PanelItem{p, b, c0, nb});
-        for (int r0 = c0 + nb; r0 < ld; r0 += kNB)
-          plan.panel_items[h][b].push_back(PanelItem{p, b, r0, std::min(kNB, ld - r0)});
-        const int cs = c0 + nb;
-        const int nt = (ld - cs + kNB - 1) / kNB;
-        for (int ti = 0; ti < nt; ++ti)
-          for (int tj = 0; tj <= ti; ++tj) plan.upd_items[h][b].push_back(UpdItem{p, b, ti, tj});
+      for (int b = 0; b < d.npanels; ++b) {
+        const int cs = b * kNB + std::min(kNB, d.m - b * kNB);
+        const int nrt = (ld + 1 - cs + kNB - 1) / kNB;
+        const int nct = (ld - cs + kNB - 1) / kNB;
+        for (int ti = 0; ti < nrt; ++ti) {
+          if (nct == 0) {
+            plan.step_items[h][b].push_back(StepItem{p, b, ti, -1});
+            continue;
+          }
+          for (int tj = 0; tj <= std::min(ti, nct - 1); ++tj)
+            plan.step_items[h][b].push_back(StepItem{p, b, ti, tj});
+        }
       }
     }
   }
@@ -277,233 +300,317 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
 
 // ============================ numeric (device) ===============================
 
-__global__ __launch_bounds__(256) void k_front_assemble(const AsmItem* __restrict__ items,
-                                                        const FrontD* __restrict__ fronts,
-                                                        const AddTask* __restrict__ tasks,
-                                                        const double* __restrict__ blocks,
-                                                        double* __restrict__ F) {
-  const AsmItem it = items[blockIdx.x];
-  const FrontD f = fronts[it.front];
-  const long long ld = f.m + f.u;
-  double* Fp = F + f.off;
-  for (long long idx = threadIdx.x; idx < ld * it.ncol; idx += blockDim.x)
-    Fp[(idx % ld) + (it.col0 + idx / ld) * ld] = 0.0;
+typedef double Tile[kNB + 1];
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of the nb x nb lower tile D (LDS) and the inverse Li of its factor.
+// D is overwritten by L; Li is lower triangular, zero elsewhere.  The upper
+// part of D is used as scratch.  Non-positive pivots set the status word and
+// are replaced by 1 so that the results stay finite.
+__device__ void tile_factor(Tile* D, Tile* Li, int nb, int* status) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) Li[idx / kNB][idx % kNB] = 0.0;
   __syncthreads();
-  for (int t = 0; t < it.ntask; ++t) {
-    const AddTask T = tasks[it.task_off + t];
-    const double* src = T.from_front ? F : blocks;
-    for (int idx = threadIdx.x; idx < T.nr * T.nc; idx += blockDim.x) {
-      const int i = idx % T.nr, j = idx / T.nr;
-      Fp[(T.dr + i) + (long long)(T.dc + j) * ld] += src[T.so + (long long)i * T.rs + (long long)j * T.cs];
+  for (int s0 = 0; s0 < nb; s0 += 16) {
+    const int sb = min(16, nb - s0);
+    if (wave == 0) {
+      // lane i < 16 holds row i of the 16 x 16 diagonal block (identity padding)
+      double r[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        r[j] = (lane < sb && j <= lane) ? D[s0 + lane][s0 + j] : (lane == j ? 1.0 : 0.0);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        double dk = readlane_f64(r[k], k);
+        if (!(dk > 0.0) || !isfinite(dk)) {
+          if (lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
+          dk = 1.0;
+        }
+        const double sk = sqrt(dk);
+        if (lane == k) r[k] = sk;
+        else if (lane > k) r[k] = r[k] / sk;
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) {
+          const double ljk = readlane_f64(r[k], j);
+          if (lane >= j) r[j] -= r[k] * ljk;
+        }
+      }
+      // lane j < 16 forms column j of the inverse of the block
+      double c[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double lii = readlane_f64(r[i], i);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+          const double lik = readlane_f64(r[k], i);
+          if (k >= lane) acc += lik * c[k];
+        }
+        c[i] = (i < lane) ? 0.0 : (i == lane ? 1.0 / lii : -acc / lii);
+      }
+      if (lane < sb) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j <= lane) D[s0 + lane][s0 + j] = r[j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i >= lane && i < sb) Li[s0 + i][s0 + lane] = c[i];
+      }
+    }
+    __syncthreads();
+    // rows below the block inside the tile: X = D(rows, block) Linv_block^T
+    const int r0 = s0 + sb, nrow = nb - r0;
+    double v[4];
+    int cnt = 0;
+    for (int idx = tid; idx < nrow * sb; idx += blockDim.x, ++cnt) {
+      const int i = r0 + idx % nrow, k = idx / nrow;
+      double a = 0.0;
+      for (int j = 0; j <= k; ++j) a += D[i][s0 + j] * Li[s0 + k][s0 + j];
+      v[cnt] = a;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int idx = tid; idx < nrow * sb; idx += blockDim.x, ++cnt)
+      D[r0 + idx % nrow][s0 + idx / nrow] = v[cnt];
+    __syncthreads();
+    // trailing update inside the tile
+    for (int idx = tid; idx < nrow * nrow; idx += blockDim.x) {
+      const int i = r0 + idx % nrow, j = r0 + idx / nrow;
+      if (j <= i) {
+        double a = 0.0;
+        for (int k = 0; k < sb; ++k) a += D[i][s0 + k] * D[j][s0 + k];
+        D[i][j] -= a;
+      }
+    }
+    __syncthreads();
+  }
+  // off-diagonal blocks of the inverse, block diagonal by block diagonal:
+  // Linv(I,J) = -Linv(I,I) sum_{K=J}^{I-1} L(I,K) Linv(K,J)
+  const int nblk = (nb + 15) / 16;
+  for (int dd = 1; dd < nblk; ++dd) {
+    const int nbd = nblk - dd;
+    for (int idx = tid; idx < nbd * 256; idx += blockDim.x) {
+      const int J = idx / 256, I = J + dd, i = (idx % 256) / 16, j = idx % 16;
+      const int gi = I * 16 + i, gj = J * 16 + j;
+      double a = 0.0;
+      if (gi < nb && gj < nb)
+        for (int k = J * 16; k < I * 16; ++k) a += D[gi][k] * Li[k][gj];
+      D[J * 16 + j][I * 16 + i] = a;   // transposed, in the unused upper part
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nbd * 256; idx += blockDim.x) {
+      const int J = idx / 256, I = J + dd, i = (idx % 256) / 16, j = idx % 16;
+      const int gi = I * 16 + i, gj = J * 16 + j;
+      if (gi < nb && gj < nb) {
+        double a = 0.0;
+        for (int k = I * 16; k <= gi; ++k) a += Li[gi][k] * D[J * 16 + j][k];
+        Li[gi][gj] = -a;
+      }
     }
     __syncthreads();
   }
 }
 
-// Cholesky of the diagonal tile and its inverse (in LDS), shared by the panel kernel.
-__device__ void tile_chol_inv(double (*D)[kNB + 1], double (*Li)[kNB + 1], int nb, int* status) {
-  for (int k = 0; k < nb; ++k) {
-    if (threadIdx.x == 0) {
-      double dk = D[k][k];
-      if (!(dk > 0.0) || !isfinite(dk)) {
-        atomicMin(status, (int)LRBMS_E_NOT_SPD);
-        dk = 1.0;
-      }
-      D[k][k] = sqrt(dk);
-    }
-    __syncthreads();
-    for (int i = k + 1 + threadIdx.x; i < nb; i += blockDim.x) D[i][k] /= D[k][k];
-    __syncthreads();
-    const int m = nb - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (j <= i) D[i][j] -= D[i][k] * D[j][k];
-    }
-    __syncthreads();
-  }
-  // column j of the inverse of the lower factor (one thread per column)
-  for (int j = threadIdx.x; j < kNB; j += blockDim.x) {
-    for (int i = 0; i < kNB; ++i) Li[i][j] = 0.0;
-    if (j < nb) {
-      Li[j][j] = 1.0 / D[j][j];
-      for (int i = j + 1; i < nb; ++i) {
-        double s = 0.0;
-        for (int k = j; k < i; ++k) s += D[i][k] * Li[k][j];
-        Li[i][j] = -s / D[i][i];
-      }
-    }
-  }
+// Load the nb x nb diagonal tile of `panel` of a front, factor it and store the
+// inverse of its factor.
+__device__ void factor_diag_tile(const FrontD& f, const double* Fp, long long lda, int panel,
+                                 double* Inv, Tile* D, Tile* Li, int* status) {
+  const int c0 = panel * kNB, nb = min(kNB, f.m - c0);
   __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void k_front_panel(const PanelItem* __restrict__ items,
-                                                     const FrontD* __restrict__ fronts,
-                                                     double* __restrict__ F,
-                                                     double* __restrict__ Inv, int* status) {
-  __shared__ double D[kNB][kNB + 1];
-  __shared__ double Li[kNB][kNB + 1];
-  __shared__ double X[kNB][kNB + 1];
-  const PanelItem it = items[blockIdx.x];
-  const FrontD f = fronts[it.front];
-  const long long ld = f.m + f.u;
-  double* Fp = F + f.off;
-  const int c0 = it.panel * kNB;
-  const int nb = min(kNB, f.m - c0);
   for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
     const int i = idx % kNB, j = idx / kNB;
-    D[i][j] = (i < nb && j < nb && j <= i) ? Fp[(c0 + i) + (c0 + j) * ld] : 0.0;
+    D[i][j] = (i < nb && j < nb && j <= i) ? Fp[(c0 + i) + (c0 + j) * lda] : 0.0;
   }
   __syncthreads();
-  tile_chol_inv(D, Li, nb, status);
-  if (it.row0 == c0) {
-    // Only the inverse of the diagonal tile is kept: the substitutions use it and
-    // the other workgroups of this launch still read the unfactored tile from F.
-    double* Ip = Inv + f.inv_off + (long long)it.panel * kNB * kNB;
-    for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x)
-      Ip[idx] = Li[idx / kNB][idx % kNB];
-    return;
-  }
-  // rows below: L = F Linv^T
-  for (int idx = threadIdx.x; idx < it.nrow * nb; idx += blockDim.x) {
-    const int i = idx % it.nrow, j = idx / it.nrow;
-    X[i][j] = Fp[(it.row0 + i) + (c0 + j) * ld];
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < it.nrow * nb; idx += blockDim.x) {
-    const int i = idx % it.nrow, j = idx / it.nrow;
-    double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += X[i][k] * Li[j][k];
-    Fp[(it.row0 + i) + (c0 + j) * ld] = s;
+  tile_factor(D, Li, nb, status);
+  double* Ip = Inv + f.inv_off + (long long)panel * kNB * kNB;
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) Ip[idx] = Li[idx / kNB][idx % kNB];
+}
+
+__global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ items,
+                                                   const FrontD* __restrict__ fronts,
+                                                   const double* __restrict__ blocks,
+                                                   const double* __restrict__ fN,
+                                                   double* __restrict__ F) {
+  const AsmItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const long long lda = f.m + f.u + 1;
+  double* Fp = F + f.off;
+  for (int idx = threadIdx.x; idx < it.nr * it.nc; idx += blockDim.x) {
+    const int i = idx % it.nr, j = idx / it.nr;
+    double v = 0.0;
+    if (!it.diag || j <= i) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (s >= it.nsrc) break;
+        const AsmSrc S = it.src[s];
+        const double* src = S.kind == 0 ? blocks : (S.kind == 1 ? F : fN);
+        v += src[S.so + (long long)i * S.rs + (long long)j * S.cs];
+      }
+    }
+    Fp[(it.dr + i) + (long long)(it.dc + j) * lda] = v;
   }
 }
 
-__global__ __launch_bounds__(256) void k_front_update(const UpdItem* __restrict__ items,
-                                                      const FrontD* __restrict__ fronts,
-                                                      double* __restrict__ F) {
-  __shared__ double A[kNB][kNB + 1];
-  __shared__ double B[kNB][kNB + 1];
-  const UpdItem it = items[blockIdx.x];
-  const FrontD f = fronts[it.front];
-  const int ld = f.m + f.u;
-  double* Fp = F + f.off;
-  const int c0 = it.panel * kNB;
-  const int nb = min(kNB, f.m - c0);
-  const int cs = c0 + nb;
-  const int R0 = cs + it.ti * kNB, C0 = cs + it.tj * kNB;
-  const int nr = min(kNB, ld - R0), ncl = min(kNB, ld - C0);
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-    const int i = idx % kNB, k = idx / kNB;
-    A[i][k] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * ld] : 0.0;
-    B[i][k] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * ld] : 0.0;
-  }
-  __syncthreads();
-  // each thread: a 4x4 sub-block of the 64x64 tile
+__global__ __launch_bounds__(256) void k_front_factor0(const int* __restrict__ list,
+                                                       const FrontD* __restrict__ fronts,
+                                                       const double* __restrict__ F,
+                                                       double* __restrict__ Inv, int* status) {
+  __shared__ Tile D[kNB];
+  __shared__ Tile Li[kNB];
+  const FrontD f = fronts[list[blockIdx.x]];
+  factor_diag_tile(f, F + f.off, f.m + f.u + 1, 0, Inv, D, Li, status);
+}
+
+// out = X Li^T for X, Li in LDS (rows < nr, k < nb); thread = 4 x 4 outputs.
+__device__ __forceinline__ void tile_times_inv_t(Tile* X, Tile* Li, int nb, double acc[4][4]) {
   const int ti = (threadIdx.x % 16) * 4, tj = (threadIdx.x / 16) * 4;
-  double acc[4][4] = {};
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
   for (int k = 0; k < nb; ++k) {
     double a[4], b[4];
-    for (int q = 0; q < 4; ++q) {
-      a[q] = A[ti + q][k];
-      b[q] = B[tj + q][k];
+    for (int p = 0; p < 4; ++p) {
+      a[p] = X[ti + p][k];
+      b[p] = Li[tj + p][k];
+    }
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__ items,
+                                                    const FrontD* __restrict__ fronts,
+                                                    double* __restrict__ F,
+                                                    double* __restrict__ Lb,
+                                                    double* __restrict__ Inv, int* status) {
+  __shared__ Tile Li[kNB];
+  __shared__ Tile A[kNB];
+  __shared__ Tile B[kNB];
+  const StepItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const long long ld = f.m + f.u, lda = ld + 1;
+  double* Fp = F + f.off;
+  double* Lp = Lb + f.off;
+  const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
+  const int R0 = cs + it.ti * kNB, nr = min((long long)kNB, lda - R0);
+  const double* Ip = Inv + f.inv_off + (long long)it.panel * kNB * kNB;
+  const int ti4 = (threadIdx.x % 16) * 4, tj4 = (threadIdx.x / 16) * 4;
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+    const int i = idx % kNB, k = idx / kNB;
+    Li[i][k] = Ip[i * kNB + k];
+    B[i][k] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+  tile_times_inv_t(B, Li, nb, acc);
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) A[ti4 + p][tj4 + q] = acc[p][q];
+  __syncthreads();
+  if (it.tj <= 0) {
+    for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
+      const int i = idx % nr, k = idx / nr;
+      Lp[(R0 + i) + (long long)(c0 + k) * lda] = A[i][k];
+    }
+  }
+  if (it.tj < 0) return;
+  const int C0 = cs + it.tj * kNB, ncl = min((long long)kNB, ld - C0);
+  Tile* Bt = A;
+  if (it.tj != it.ti) {
+    for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+      const int i = idx % kNB, k = idx / kNB;
+      B[i][k] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
+    }
+    __syncthreads();
+    tile_times_inv_t(B, Li, nb, acc);
+    __syncthreads();
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < 4; ++q) B[ti4 + p][tj4 + q] = acc[p][q];
+    __syncthreads();
+    Bt = B;
+  }
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double a[4], b[4];
+    for (int p = 0; p < 4; ++p) {
+      a[p] = A[ti4 + p][k];
+      b[p] = Bt[tj4 + p][k];
     }
     for (int p = 0; p < 4; ++p)
       for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
   }
   for (int p = 0; p < 4; ++p)
     for (int q = 0; q < 4; ++q) {
-      const int i = ti + p, j = tj + q;
-      if (i < nr && j < ncl) Fp[(R0 + i) + (long long)(C0 + j) * ld] -= acc[p][q];
+      const int i = ti4 + p, j = tj4 + q;
+      if (i < nr && j < ncl) Fp[(R0 + i) + (long long)(C0 + j) * lda] -= acc[p][q];
     }
-}
-
-__global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ list,
-                                                       const FrontD* __restrict__ fronts,
-                                                       const NodeRef* __restrict__ nodes,
-                                                       const int* __restrict__ children,
-                                                       const double* __restrict__ F,
-                                                       const double* __restrict__ Inv,
-                                                       double* __restrict__ V,
-                                                       const double* __restrict__ fN) {
-  __shared__ double y[kNB];
-  const FrontD f = fronts[list[blockIdx.x]];
-  const int ld = f.m + f.u;
-  const double* Fp = F + f.off;
-  double* w = V + f.voff;
-  for (int i = threadIdx.x; i < ld; i += blockDim.x) w[i] = 0.0;
-  __syncthreads();
-  for (int n = 0; n < f.n_s_nodes; ++n) {
-    const NodeRef r = nodes[f.node_off + n];
-    for (int i = threadIdx.x; i < r.size; i += blockDim.x) w[r.pos + i] = fN[r.pn_off + i];
-  }
-  __syncthreads();
-  for (int c = 0; c < f.nchild; ++c) {
-    const FrontD fc = fronts[children[f.child_off + c]];
-    const double* wc = V + fc.voff;
-    for (int n = fc.n_s_nodes; n < fc.n_nodes; ++n) {
-      const NodeRef r = nodes[fc.node_off + n];
-      for (int i = threadIdx.x; i < r.size; i += blockDim.x) w[r.pad + i] += wc[r.pos + i];
-    }
-    __syncthreads();
-  }
-  const int np = (f.m + kNB - 1) / kNB;
-  for (int b = 0; b < np; ++b) {
-    const int c0 = b * kNB, nb = min(kNB, f.m - c0);
-    const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
-    if (threadIdx.x < nb) {
-      double s = 0.0;
-      for (int k = 0; k <= (int)threadIdx.x; ++k) s += Li[threadIdx.x * kNB + k] * w[c0 + k];
-      y[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < nb) w[c0 + threadIdx.x] = y[threadIdx.x];
-    for (int rr = c0 + nb + threadIdx.x; rr < ld; rr += blockDim.x) {
-      double s = 0.0;
-      for (int k = 0; k < nb; ++k) s += Fp[rr + (long long)(c0 + k) * ld] * y[k];
-      w[rr] -= s;
-    }
-    __syncthreads();
-  }
+  // look-ahead: this workgroup owns the next diagonal tile
+  if (it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels)
+    factor_diag_tile(f, Fp, lda, it.panel + 1, Inv, A, B, status);
 }
 
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
-                                                        const double* __restrict__ F,
+                                                        const double* __restrict__ Lb,
                                                         const double* __restrict__ Inv,
-                                                        double* __restrict__ V,
                                                         double* __restrict__ pN) {
+  extern __shared__ double w[];   // m + u values
   __shared__ double xb[kNB];
   const FrontD f = fronts[list[blockIdx.x]];
   const int ld = f.m + f.u;
-  const double* Fp = F + f.off;
-  double* w = V + f.voff;
+  const long long lda = ld + 1;
+  const double* Lp = Lb + f.off;
+  for (int i = threadIdx.x; i < f.m; i += blockDim.x) w[i] = Lp[ld + (long long)i * lda];
   for (int n = f.n_s_nodes; n < f.n_nodes; ++n) {
     const NodeRef r = nodes[f.node_off + n];
     for (int i = threadIdx.x; i < r.size; i += blockDim.x) w[r.pos + i] = pN[r.pn_off + i];
   }
   __syncthreads();
-  // z = y_S - L_US^T x_U
+  // z = y_S - L_US^T x_U (row i of L_US^T is contiguous in memory)
   for (int i = threadIdx.x; i < f.m; i += blockDim.x) {
-    double s = 0.0;
-    for (int rr = f.m; rr < ld; ++rr) s += Fp[rr + (long long)i * ld] * w[rr];
-    w[i] -= s;
+    const double* col = Lp + (long long)i * lda;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int rr = f.m;
+    for (; rr + 4 <= ld; rr += 4) {
+      a0 += col[rr] * w[rr];
+      a1 += col[rr + 1] * w[rr + 1];
+      a2 += col[rr + 2] * w[rr + 2];
+      a3 += col[rr + 3] * w[rr + 3];
+    }
+    for (; rr < ld; ++rr) a0 += col[rr] * w[rr];
+    w[i] -= (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
-  const int np = (f.m + kNB - 1) / kNB;
-  for (int b = np - 1; b >= 0; --b) {
+  for (int b = f.npanels - 1; b >= 0; --b) {
     const int c0 = b * kNB, nb = min(kNB, f.m - c0);
     const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
-    if (threadIdx.x < nb) {
+    // xb is read over all kNB entries below (with zero weights past nb), so
+    // the tail must hold zeros, not stale values that might be non-finite.
+    if ((int)threadIdx.x < kNB) {
       double s = 0.0;
       for (int k = threadIdx.x; k < nb; ++k) s += Li[k * kNB + threadIdx.x] * w[c0 + k];
       xb[threadIdx.x] = s;
     }
     __syncthreads();
-    if (threadIdx.x < nb) w[c0 + threadIdx.x] = xb[threadIdx.x];
+    if ((int)threadIdx.x < nb) w[c0 + threadIdx.x] = xb[threadIdx.x];
     for (int i = threadIdx.x; i < c0; i += blockDim.x) {
-      double s = 0.0;
-      for (int k = 0; k < nb; ++k) s += Fp[(c0 + k) + (long long)i * ld] * xb[k];
-      w[i] -= s;
+      const double* col = Lp + c0 + (long long)i * lda;
+      double a[kNB];
+#pragma unroll
+      for (int k = 0; k < kNB; ++k) a[k] = (k < nb) ? col[k] : 0.0;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kNB; k += 2) {
+        s0 += a[k] * xb[k];
+        s1 += a[k + 1] * xb[k + 1];
+      }
+      w[i] -= s0 + s1;
     }
     __syncthreads();
   }
@@ -526,32 +633,32 @@ static bool upload(const std::vector<T>& v, T** out, long long& bytes) {
 bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
   long long& b = dev.bytes;
   if (!upload(plan.fronts, &dev.fronts, b) || !upload(plan.nodes, &dev.nodes, b) ||
-      !upload(plan.children, &dev.children, b) || !upload(plan.tasks, &dev.tasks, b))
+      !upload(plan.children, &dev.children, b))
     return false;
   const int H = plan.nlevels;
   dev.asm_items.assign(H, nullptr);
   dev.level_fronts.assign(H, nullptr);
-  dev.panel_items.assign(H, {});
-  dev.upd_items.assign(H, {});
+  dev.step_items.assign(H, {});
   for (int h = 0; h < H; ++h) {
     if (!upload(plan.asm_items[h], &dev.asm_items[h], b) ||
         !upload(plan.level_fronts[h], &dev.level_fronts[h], b))
       return false;
-    dev.panel_items[h].assign(plan.panel_items[h].size(), nullptr);
-    dev.upd_items[h].assign(plan.upd_items[h].size(), nullptr);
-    for (size_t p = 0; p < plan.panel_items[h].size(); ++p) {
-      if (!upload(plan.panel_items[h][p], &dev.panel_items[h][p], b) ||
-          !upload(plan.upd_items[h][p], &dev.upd_items[h][p], b))
-        return false;
-    }
+    dev.step_items[h].assign(plan.step_items[h].size(), nullptr);
+    for (size_t p = 0; p < plan.step_items[h].size(); ++p)
+      if (!upload(plan.step_items[h][p], &dev.step_items[h][p], b)) return false;
   }
+  int maxld = 1;
+  for (auto& f : plan.fronts) maxld = std::max(maxld, f.m + f.u);
+  if (hipFuncSetAttribute((const void*)k_front_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(double) * maxld)) != hipSuccess)
+    return false;
   auto alloc = [&](double** p, long long n) {
     if (hipMalloc(p, std::max<long long>(n, 1) * sizeof(double)) != hipSuccess) return false;
     b += n * (long long)sizeof(double);
     return hipMemset(*p, 0, std::max<long long>(n, 1) * sizeof(double)) == hipSuccess;
   };
-  return alloc(&dev.F, plan.front_doubles) && alloc(&dev.V, plan.vec_doubles) &&
-         alloc(&dev.Inv, plan.inv_doubles);
+  return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.front_doubles) &&
+         alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles);
 }
 
 void solver_free(SolverDev& dev) {
@@ -561,14 +668,12 @@ void solver_free(SolverDev& dev) {
   f(dev.fronts);
   f(dev.nodes);
   f(dev.children);
-  f(dev.tasks);
   for (auto p : dev.asm_items) f(p);
   for (auto p : dev.level_fronts) f(p);
-  for (auto& v : dev.panel_items)
-    for (auto p : v) f(p);
-  for (auto& v : dev.upd_items)
+  for (auto& v : dev.step_items)
     for (auto p : v) f(p);
   f(dev.F);
+  f(dev.L);
   f(dev.V);
   f(dev.Inv);
   dev = SolverDev{};
@@ -580,29 +685,25 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
   const int H = plan.nlevels;
   for (int h = 0; h < H; ++h) {
     const int na = (int)plan.asm_items[h].size();
-    if (na)
-      hipLaunchKernelGGL(k_front_assemble, dim3(na), dim3(256), 0, st, dev.asm_items[h],
-                         dev.fronts, dev.tasks, blocks, dev.F);
-    for (size_t p = 0; p < plan.panel_items[h].size(); ++p) {
-      const int npi = (int)plan.panel_items[h][p].size();
-      if (npi)
-        hipLaunchKernelGGL(k_front_panel, dim3(npi), dim3(256), 0, st, dev.panel_items[h][p],
-                           dev.fronts, dev.F, dev.Inv, status);
-      const int nu = (int)plan.upd_items[h][p].size();
-      if (nu)
-        hipLaunchKernelGGL(k_front_update, dim3(nu), dim3(256), 0, st, dev.upd_items[h][p],
-                           dev.fronts, dev.F);
+    const int nf = (int)plan.level_fronts[h].size();
+    hipLaunchKernelGGL(k_front_asm, dim3(na), dim3(256), 0, st, dev.asm_items[h], dev.fronts,
+                       blocks, fN, dev.F);
+    hipLaunchKernelGGL(k_front_factor0, dim3(nf), dim3(256), 0, st, dev.level_fronts[h],
+                       dev.fronts, dev.F, dev.Inv, status);
+    for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
+      const int ni = (int)plan.step_items[h][p].size();
+      if (ni)
+        hipLaunchKernelGGL(k_front_step, dim3(ni), dim3(256), 0, st, dev.step_items[h][p],
+                           dev.fronts, dev.F, dev.L, dev.Inv, status);
     }
-  }
-  for (int h = 0; h < H; ++h) {
-    const int n = (int)plan.level_fronts[h].size();
-    hipLaunchKernelGGL(k_front_forward, dim3(n), dim3(256), 0, st, dev.level_fronts[h],
-                       dev.fronts, dev.nodes, dev.children, dev.F, dev.Inv, dev.V, fN);
   }
   for (int h = H - 1; h >= 0; --h) {
     const int n = (int)plan.level_fronts[h].size();
-    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), 0, st, dev.level_fronts[h],
-                       dev.fronts, dev.nodes, dev.F, dev.Inv, dev.V, pN);
+    int maxld = 0;
+    for (int f : plan.level_fronts[h])
+      maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
+    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
+                       dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, pN);
   }
   return hipGetLastError();
 }

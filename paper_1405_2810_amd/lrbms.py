@@ -292,21 +292,20 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
     nxt = lambda k: [next(it) for _ in range(k)]
     nf, H, nn, nch, nt, fd, vd, idd, flops = nxt(9)
     fronts = [dict(zip(["off", "voff", "inv_off", "m", "u", "node_off", "n_nodes", "child_off",
-                        "nchild", "n_s_nodes", "_"], nxt(11))) for _ in range(nf)]
+                        "nchild", "n_s_nodes", "npanels"], nxt(11))) for _ in range(nf)]
     nodes = [dict(zip(["pos", "pn_off", "size", "ppos"], nxt(4))) for _ in range(nn)]
     children = nxt(nch)
-    tasks = [dict(zip(["so", "rs", "cs", "nr", "nc", "dr", "dc", "from_front", "_"], nxt(9)))
-             for _ in range(nt)]
     levels = []
     for _ in range(H):
         lf = nxt(next(it))
-        asm = [dict(zip(["front", "col0", "ncol", "task_off", "ntask"], nxt(5)))
-               for _ in range(next(it))]
-        panels = []
+        asm = []
         for _ in range(next(it)):
-            pi = [dict(zip(["front", "panel", "row0", "nrow"], nxt(4))) for _ in range(next(it))]
-            ui = [dict(zip(["front", "panel", "ti", "tj"], nxt(4))) for _ in range(next(it))]
-            panels.append((pi, ui))
-        levels.append(dict(fronts=lf, asm=asm, panels=panels))
-    return dict(fronts=fronts, nodes=nodes, children=children, tasks=tasks, levels=levels,
+            d = dict(zip(["front", "dr", "dc", "nr", "nc", "diag", "nsrc"], nxt(7)))
+            d["src"] = [dict(zip(["so", "rs", "cs", "kind"], nxt(4))) for _ in range(3)][:d["nsrc"]]
+            asm.append(d)
+        steps = []
+        for _ in range(next(it)):
+            steps.append([dict(zip(["front", "panel", "ti", "tj"], nxt(4))) for _ in range(next(it))])
+        levels.append(dict(fronts=lf, asm=asm, steps=steps))
+    return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,
                 front_doubles=fd, vec_doubles=vd, inv_doubles=idd, flops=flops)

@@ -132,3 +132,32 @@ def test_solve_before_assemble_is_state_error():
         gm.assemble(dev(np.zeros(g.r * g.ncell)), AFFINE)
     assert ei.value.code == -2
     gm.close()
+
+
+@pytest.mark.parametrize("name,ne", [("small2d", 20), ("small2d", 40), ("small3d", 20),
+                                     ("small3d", 40)])
+def test_large_local_bases(name, ne):
+    """Local bases of 20 and 40 functions (the wider assembly variants and
+    multi-panel fronts): reduced system and reduced solve."""
+    import torch
+    from .helpers import synthetic_case
+    log(f"[parity] large bases {name} N_E={ne}")
+    p, g, om = synthetic_case(name, n_snap=ne + 2, cap=ne)
+    gm = gpu_model(p, om)
+    s = _state(p, 31)
+    gm.assemble(dev(s), DIRECT)
+    A_o, f_o = reduced_system(om, s, DIRECT)
+    A_od = A_o.toarray()
+    err = np.abs(gm.dense_reduced_matrix() - A_od).max() / np.abs(A_od).max()
+    _, f_g = gm.reduced_system()
+    e_f = rel_l2(f_g, f_o)
+    log(f"[parity] large bases {name} N_E={ne}: A err {err:.2e} f err {e_f:.2e}")
+    assert err <= TOL_BLOCK
+    assert e_f <= TOL_BLOCK
+    pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
+    gm.solve(pN)
+    assert gm.status() == 0
+    e_p = rel_l2(host(pN), solve_reduced(A_o, f_o))
+    log(f"[parity] large bases {name} N_E={ne}: pN err {e_p:.2e}")
+    assert e_p <= TOL_PN
+    gm.close()

@@ -112,9 +112,10 @@ def test_lsq_exact_in_profile_span(affine_model):
     """If Pi lambda(s) lies in the span of the profiles the fit reproduces it.
     The profiles are piecewise constant, so a saturation that is constant
     per cell with lambda(s_e) equal to a profile combination is built from
-    the inverse of the Corey law on each cell."""
+    the inverse of the Corey law on each cell.  theta is a convex combination,
+    so the target stays inside the range of lambda, as each profile does."""
     p, g, off, m = affine_model
-    theta = np.array([0.3, 0.2] + [0.0] * (len(m.profiles) - 2))
+    theta = np.array([0.6, 0.4] + [0.0] * (len(m.profiles) - 2))
     target = sum(t * q for t, q in zip(theta, m.profiles))       # P1 field (means only)
     lam_cells = target[:g.ncell] / math.sqrt(g.vol)
     # invert lambda(s) = s^2/eta_w + (1-s)^2/eta_o on the branch s >= s*

@@ -45,96 +45,85 @@ def _random_system(p, sizes, rng):
     return A, np.concatenate(blocks), rng.standard_normal(N)
 
 
+def _factor_tile(Fp, m, panel, Inv, f):
+    c0 = panel * NB
+    nb = min(NB, m - c0)
+    D = np.tril(Fp[c0:c0 + nb, c0:c0 + nb])
+    Lt = np.linalg.cholesky(D + np.tril(D, -1).T)
+    pad = np.zeros((NB, NB))
+    pad[:nb, :nb] = np.linalg.inv(Lt)
+    o = f["inv_off"] + panel * NB * NB
+    Inv[o:o + NB * NB] = pad.ravel()
+
+
 def emulate(plan, blocks, fN):
-    """The numeric phase as the device kernels execute it (column-major fronts,
-    lower triangle, tile inverses)."""
+    """The numeric phase as the device kernels execute it: fronts column-major
+    with a right-hand-side row at the bottom, fused panel steps with the L rows
+    in a separate buffer, look-ahead tile factorization, backward sweep."""
     F = np.zeros(plan["front_doubles"])
+    Lb = np.zeros(plan["front_doubles"])
     V = np.zeros(plan["vec_doubles"])
     Inv = np.zeros(plan["inv_doubles"])
-    fr, nodes, tasks, ch = plan["fronts"], plan["nodes"], plan["tasks"], plan["children"]
-    col = lambda f: F[f["off"]:f["off"] + (f["m"] + f["u"]) ** 2].reshape(
-        f["m"] + f["u"], f["m"] + f["u"], order="F")
+    fr, nodes = plan["fronts"], plan["nodes"]
+
+    def view(buf, f):
+        ld = f["m"] + f["u"]
+        return buf[f["off"]:f["off"] + (ld + 1) * ld].reshape(ld + 1, ld, order="F")
+
     for lev in plan["levels"]:
         for it in lev["asm"]:
             f = fr[it["front"]]
-            Fp = col(f)
-            Fp[:, it["col0"]:it["col0"] + it["ncol"]] = 0.0
-            for t in tasks[it["task_off"]:it["task_off"] + it["ntask"]]:
-                src = F if t["from_front"] else blocks
-                i = np.arange(t["nr"])[:, None]
-                j = np.arange(t["nc"])[None, :]
-                Fp[t["dr"]:t["dr"] + t["nr"], t["dc"]:t["dc"] + t["nc"]] += \
-                    src[t["so"] + i * t["rs"] + j * t["cs"]]
-        for pitems, uitems in lev["panels"]:
-            snap = {}
-            for it in pitems:
+            Fp = view(F, f)
+            i = np.arange(it["nr"])[:, None]
+            j = np.arange(it["nc"])[None, :]
+            v = np.zeros((it["nr"], it["nc"]))
+            for S in it["src"]:
+                v = v + {0: blocks, 1: F, 2: fN}[S["kind"]][S["so"] + i * S["rs"] + j * S["cs"]]
+            if it["diag"]:
+                v = np.tril(v)
+            Fp[it["dr"]:it["dr"] + it["nr"], it["dc"]:it["dc"] + it["nc"]] = v
+        for fi in lev["fronts"]:
+            _factor_tile(view(F, fr[fi]), fr[fi]["m"], 0, Inv, fr[fi])
+        for items in lev["steps"]:
+            for it in items:
                 f = fr[it["front"]]
-                Fp = col(f)
-                c0 = it["panel"] * NB
-                nb = min(NB, f["m"] - c0)
-                D = np.tril(Fp[c0:c0 + nb, c0:c0 + nb]).copy()
-                snap.setdefault(it["front"], D)
-            for it in pitems:
-                f = fr[it["front"]]
-                Fp = col(f)
-                c0 = it["panel"] * NB
-                nb = min(NB, f["m"] - c0)
-                Lt = np.linalg.cholesky(snap[it["front"]] + np.tril(snap[it["front"]], -1).T)
-                Li = np.linalg.inv(Lt)
-                if it["row0"] == c0:
-                    pad = np.zeros((NB, NB))
-                    pad[:nb, :nb] = Li
-                    o = f["inv_off"] + it["panel"] * NB * NB
-                    Inv[o:o + NB * NB] = pad.ravel()
-                else:
-                    r0, nr = it["row0"], it["nrow"]
-                    Fp[r0:r0 + nr, c0:c0 + nb] = Fp[r0:r0 + nr, c0:c0 + nb] @ Li.T
-            for it in uitems:
-                f = fr[it["front"]]
-                Fp = col(f)
+                Fp, Lp = view(F, f), view(Lb, f)
                 ld = f["m"] + f["u"]
-                c0 = it["panel"] * NB
+                p = it["panel"]
+                c0 = p * NB
                 nb = min(NB, f["m"] - c0)
                 cs = c0 + nb
-                R0, C0 = cs + it["ti"] * NB, cs + it["tj"] * NB
-                nr, ncl = min(NB, ld - R0), min(NB, ld - C0)
-                Fp[R0:R0 + nr, C0:C0 + ncl] -= Fp[R0:R0 + nr, c0:c0 + nb] @ Fp[C0:C0 + ncl, c0:c0 + nb].T
+                Li = Inv[f["inv_off"] + p * NB * NB:f["inv_off"] + (p + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
+                R0 = cs + it["ti"] * NB
+                nr = min(NB, ld + 1 - R0)
+                A = Fp[R0:R0 + nr, c0:cs] @ Li.T
+                if it["tj"] <= 0:
+                    Lp[R0:R0 + nr, c0:cs] = A
+                if it["tj"] < 0:
+                    continue
+                C0 = cs + it["tj"] * NB
+                ncl = min(NB, ld - C0)
+                Bt = A if it["tj"] == it["ti"] else Fp[C0:C0 + ncl, c0:cs] @ Li.T
+                Fp[R0:R0 + nr, C0:C0 + ncl] -= A @ Bt[:ncl].T
+                if it["ti"] == 0 and it["tj"] == 0 and p + 1 < f["npanels"]:
+                    _factor_tile(Fp, f["m"], p + 1, Inv, f)
     pN = np.zeros_like(fN)
-    for lev in plan["levels"]:
-        for fi in lev["fronts"]:
-            f = fr[fi]
-            ld = f["m"] + f["u"]
-            Fp = col(f)
-            w = np.zeros(ld)
-            for n in nodes[f["node_off"]:f["node_off"] + f["n_s_nodes"]]:
-                w[n["pos"]:n["pos"] + n["size"]] = fN[n["pn_off"]:n["pn_off"] + n["size"]]
-            for c in ch[f["child_off"]:f["child_off"] + f["nchild"]]:
-                fc = fr[c]
-                wc = V[fc["voff"]:fc["voff"] + fc["m"] + fc["u"]]
-                for n in nodes[fc["node_off"] + fc["n_s_nodes"]:fc["node_off"] + fc["n_nodes"]]:
-                    w[n["ppos"]:n["ppos"] + n["size"]] += wc[n["pos"]:n["pos"] + n["size"]]
-            for b in range((f["m"] + NB - 1) // NB):
-                c0, nb = b * NB, min(NB, f["m"] - b * NB)
-                Li = Inv[f["inv_off"] + b * NB * NB:f["inv_off"] + (b + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
-                y = Li @ w[c0:c0 + nb]
-                w[c0:c0 + nb] = y
-                w[c0 + nb:] -= Fp[c0 + nb:, c0:c0 + nb] @ y
-            V[f["voff"]:f["voff"] + ld] = w
     for lev in reversed(plan["levels"]):
         for fi in lev["fronts"]:
             f = fr[fi]
             ld, m = f["m"] + f["u"], f["m"]
-            Fp = col(f)
-            w = V[f["voff"]:f["voff"] + ld].copy()
+            Lp = view(Lb, f)
+            w = np.zeros(ld)
+            w[:m] = Lp[ld, :m]
             for n in nodes[f["node_off"] + f["n_s_nodes"]:f["node_off"] + f["n_nodes"]]:
                 w[n["pos"]:n["pos"] + n["size"]] = pN[n["pn_off"]:n["pn_off"] + n["size"]]
-            w[:m] -= Fp[m:, :m].T @ w[m:]
-            for b in reversed(range((m + NB - 1) // NB)):
+            w[:m] -= Lp[m:ld, :m].T @ w[m:]
+            for b in reversed(range(f["npanels"])):
                 c0, nb = b * NB, min(NB, m - b * NB)
                 Li = Inv[f["inv_off"] + b * NB * NB:f["inv_off"] + (b + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
                 xb = Li.T @ w[c0:c0 + nb]
                 w[c0:c0 + nb] = xb
-                w[:c0] -= Fp[c0:c0 + nb, :c0].T @ xb
+                w[:c0] -= Lp[c0:c0 + nb, :c0].T @ xb
             for n in nodes[f["node_off"]:f["node_off"] + f["n_s_nodes"]]:
                 pN[n["pn_off"]:n["pn_off"] + n["size"]] = w[n["pos"]:n["pos"] + n["size"]]
     return pN
