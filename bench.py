@@ -3,17 +3,31 @@
 A step = one pass of the whole online path over one simulation state:
 mobility + reduced assembly, reduced solve, pressure/flux reconstruction,
 saturation step + limiter, all through the C ABI of liblrbms.so, inputs
-resident in HBM.  Prints one JSON line (see the keys below).
+resident in HBM.  Prints one JSON line on stdout (progress goes to stderr).
 
-Default workload: 2D 256x256 fine cells, 16x16 coarse boxes, log-normal
-permeability (corr. length 0.05, sigma_logk 2), Corey exponents 2, viscosity
-ratio 5, local bases of size <= 25, FP64, plain per-simulation path.
+Default workload: 2D 256x256 fine cells on the unit square, 16x16 coarse
+boxes of 16x16 cells, log-normal permeability (correlation length 0.05,
+sigma_logk 2), Corey exponents 2, viscosity ratio 5, local bases of size 25
+(1_E plus Gram-Schmidt of seeded smooth snapshot fields), FP64, the plain
+per-simulation path (sequential launches on one stream, no graph, no
+batching).
+
+Passes, in order:
+  warm-up      W untimed steps;
+  timed        K steps between two device synchronizations: `value`,
+               `ms_per_step`;
+  latency      K steps with HIP events between the four calls: p50/p99 step
+               latency and the mean time of each call;
+  kernels      K steps with the library's per-kernel event timing switched on:
+               per kernel kind the mean launch time and the algorithmic
+               flops and bytes, hence the roofline of the dominant kernel;
+  cpu_baseline the FP64 CPU oracle's online step on a bounded sample of the
+               same workload (skipped with --no-cpu-baseline).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -23,21 +37,62 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
-
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector (= FP64 matrix) peak
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record of this kernel and workload, if the kernel's source is unchanged
+    since the counters were taken; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    from paper_1405_2810_amd.profiling import source_sha
+    e = rec.get(workload, {}).get(kernel)
+    if not e or e.get("source_sha") != source_sha(kernel):
+        return None
+    return float(e["bytes_per_launch"])
+
+
 def build_model(p, n_snap, cap, seed):
-    """Local bases by Gram-Schmidt of seeded smooth snapshot fields (the
-    library's own host Gram-Schmidt), N_E = cap in every box."""
+    """Local bases by the library's host Gram-Schmidt of seeded smooth
+    snapshot fields, 1_E first, N_E = cap in every box."""
     from synth import smooth_fields
     from paper_1405_2810_amd.lrbms import Model
     snaps = smooth_fields(p, n_snap, np.random.default_rng(seed))
-    return Model.from_snapshots(p, snaps, ne_cap=cap, unit_functions=True)
+    return Model.from_snapshots(p, snaps, ne_cap=cap, unit_functions=True), snaps
+
+
+def cpu_baseline(p, snaps, s0, n_steps: int, mode: str):
+    """The FP64 CPU oracle's online step (same problem, bases built by the
+    oracle from the same snapshots) timed over n_steps from s0."""
+    from oracle.fem import Grid
+    from oracle.offline import local_bases
+    from oracle.online import Model as OModel, online_step, DIRECT as O_DIRECT
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover - threadpoolctl is optional
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    g = Grid(p)
+    phis = local_bases(g, p, snaps, method="gs", cap=p.ne_cap, unit=True)
+    om = OModel(p, phis, None)
+    s = np.asarray(s0, dtype=np.float64).copy()
+    online_step(om, s, O_DIRECT)          # first call: caches, imports
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        s = online_step(om, s, O_DIRECT)["s"]
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_steps} consecutive online steps (DIRECT, a1-a7) of the same workload "
+                      f"from the same initial saturation, after one untimed step; "
+                      f"{dt:.1f} s of CPU time; BLAS threads = {threads}"}
 
 
 def main():
@@ -46,12 +101,25 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="cfg2")
-    ap.add_argument("--mode", default="direct", choices=["direct", "affine"])
+    ap.add_argument("--mode", default="direct", choices=["direct"])
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of 256 MiB (scale of the HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = (256 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}))
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the online step of one "
+              "simulation runs on one device and this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from synth import make_problem, random_saturation
@@ -61,15 +129,15 @@ def main():
     r = p.dim + 1
     log(f"[bench] config {args.config}: building model")
     t0 = time.time()
-    gm = build_model(p, n_snap=p.ne_cap + 4, cap=p.ne_cap, seed=p.seed + 1)
+    gm, snaps = build_model(p, n_snap=p.ne_cap + 4, cap=p.ne_cap, seed=p.seed + 1)
     info = gm.info
     log(f"[bench] model ready in {time.time() - t0:.1f}s: N={info['N']} boxes={info['n_sub']} "
         f"device MB={info['device_bytes'] / 1e6:.1f}")
     mode = DIRECT if args.mode == "direct" else AFFINE
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream()
-    s0 = torch.as_tensor(random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6),
-                         dtype=torch.float64, device=dev)
+    s0_host = random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6)
+    s0 = torch.as_tensor(s0_host, dtype=torch.float64, device=dev)
     s_a = s0.clone()
     s_b = torch.zeros_like(s_a)
     pN = torch.zeros(info["N"], dtype=torch.float64, device=dev)
@@ -98,7 +166,8 @@ def main():
     torch.cuda.synchronize()
     if gm.status() != 0:
         raise RuntimeError("device status error during warm-up")
-    # timed region: K whole steps
+    log(f"[bench] warm-up done ({args.warmup} steps); timing {args.steps} steps")
+    # ---- timed region: K whole steps -------------------------------------
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -107,7 +176,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = wall / args.steps * 1e3
-    # per-call durations and per-step latency with events on the same stream
+    if gm.status() != 0:
+        raise RuntimeError("device status error in the timed region")
+    log(f"[bench] timed: {ms:.3f} ms/step")
+    # ---- latency pass ------------------------------------------------------
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     for i in range(args.steps):
         step(s_a, s_b, evs[i])
@@ -115,14 +187,54 @@ def main():
     torch.cuda.synchronize()
     parts = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(4)] for e in evs])
     lat = parts.sum(axis=1)
-    log(f"[bench] step {ms:.3f} ms; per call (ms) assemble {parts[:, 0].mean():.4f} "
-        f"solve {parts[:, 1].mean():.4f} flux {parts[:, 2].mean():.4f} "
-        f"transport {parts[:, 3].mean():.4f}")
-    # transport roofline: algorithmic bytes per launch pair (Euler + limiter)
-    nc, nf = info["ncell"], info["nface"]
-    tr_bytes = 8 * (2 * r * nc + nf + 2 * nc) + 8 * (2 * r * nc + nf) + nc
-    tr_ms = parts[:, 3].mean()
-    achieved = tr_bytes / (tr_ms * 1e-3) / 1e9
+    log(f"[bench] per call (ms) assemble {parts[:, 0].mean():.4f} solve {parts[:, 1].mean():.4f} "
+        f"flux {parts[:, 2].mean():.4f} transport {parts[:, 3].mean():.4f}")
+    # ---- per-kernel pass ---------------------------------------------------
+    gm.profile_enable(True)
+    for i in range(args.steps):
+        step(s_a, s_b)
+        s_a, s_b = s_b, s_a
+    kstats = gm.profile_read()
+    gm.profile_enable(False)
+    kernels = {}
+    for name, e in kstats.items():
+        avg_ms = e["total_ms"] / e["launches"]
+        gbs = e["bytes"] / (e["total_ms"] * 1e-3) / 1e9 if e["total_ms"] > 0 else 0.0
+        tfs = e["flops"] / (e["total_ms"] * 1e-3) / 1e12 if e["total_ms"] > 0 else 0.0
+        t_hbm = e["bytes"] / (PEAK_HBM_GBS * 1e9)
+        t_alu = e["flops"] / (PEAK_FP64_TFLOPS * 1e12)
+        kernels[name] = {"launches_per_step": e["launches"] / args.steps,
+                         "avg_launch_us": avg_ms * 1e3,
+                         "ms_per_step": e["total_ms"] / args.steps,
+                         "bytes_per_launch": e["bytes"] / e["launches"],
+                         "flops_per_launch": e["flops"] / e["launches"],
+                         "GBs": gbs, "TFLOPs": tfs,
+                         "bound": "hbm" if t_hbm >= t_alu else "alu"}
+    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"[bench]   {name:18s} {k['launches_per_step']:5.1f}/step {k['avg_launch_us']:9.2f} us "
+            f"{k['ms_per_step']:8.4f} ms/step  {k['GBs']:8.1f} GB/s {k['TFLOPs']:7.3f} TF/s "
+            f"({k['bound']})")
+    dom = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
+    kd = kernels[dom]
+    workload = f"{args.config}-{args.mode}"
+    traffic = measured_traffic(dom, workload)
+    if kd["bound"] == "hbm":
+        roof = {"bound": "hbm", "achieved": kd["GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": kd["GBs"] / PEAK_HBM_GBS}
+    else:
+        roof = {"bound": "alu", "achieved": kd["TFLOPs"], "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": kd["TFLOPs"] / PEAK_FP64_TFLOPS}
+    roof["traffic"] = traffic
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = kd["avg_launch_us"]
+    roof["algorithmic_per_launch"] = {"bytes": kd["bytes_per_launch"], "flops": kd["flops_per_launch"]}
+    # ---- CPU oracle baseline ----------------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
+        cpu = cpu_baseline(p, snaps, s0_host, args.cpu_steps, args.mode)
+        log(f"[bench] cpu baseline: {cpu['value']:.3f} solves/s on {cpu['cores']} threads")
+    nc = [len(c) - 1 for c in p.cuts[:p.dim]]
     out = {
         "metric": "online pressure solves/s + p50/p99 latency vs plain GPU path at rel err<=1e-10",
         "value": 1e3 / ms,
@@ -136,17 +248,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 2D {p.n[0]}x{p.n[1]} fine cells, "
-                               f"{len(p.cuts[0]) - 1}x{len(p.cuts[1]) - 1} coarse boxes, "
-                               f"N_E<={p.ne_cap}, online step a1-a7, plain per-simulation path",
-                   "mode": args.mode, "N": info["N"]},
+        "config": {"workload": f"{args.config}: {p.dim}D "
+                               f"{'x'.join(str(v) for v in p.n[:p.dim])} fine cells, "
+                               f"{'x'.join(str(v) for v in nc)} coarse boxes, N_E<={p.ne_cap}, "
+                               f"online step a1-a7 ({args.mode}), plain per-simulation path",
+                   "mode": args.mode, "N": info["N"], "fine_cells": info["ncell"]},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "per_call_ms": {"assemble": float(parts[:, 0].mean()), "solve": float(parts[:, 1].mean()),
                         "flux": float(parts[:, 2].mean()), "transport": float(parts[:, 3].mean())},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "transport_step (k_transport + k_limiter)"},
-        "cpu_baseline": None,
+        "pressure_solves_per_s": 1e3 / float((parts[:, 0] + parts[:, 1]).mean()),
+        "roofline": roof,
+        "kernels": {k: {"avg_launch_us": round(v["avg_launch_us"], 3),
+                        "launches_per_step": v["launches_per_step"],
+                        "GBs": round(v["GBs"], 2), "TFLOPs": round(v["TFLOPs"], 4)}
+                    for k, v in kernels.items()},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

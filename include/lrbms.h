@@ -197,6 +197,26 @@ int lrbms_copy_theta(lrbms_model* m, double* theta);
 int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,
                              int32_t leaf_max, int64_t* buf, int64_t cap, int64_t* needed);
 
+/* Kernel timing, for roofline measurement (off by default).
+ * lrbms_profile_enable synchronizes the model's last stream, clears the
+ * counters and switches timing on (enable != 0) or off.  While on, every
+ * kernel launched by the four online calls is bracketed by a pair of HIP
+ * events on the call's stream (a few microseconds of added gap per launch).
+ * lrbms_profile_read waits for the recorded events and fills up to cap
+ * entries, one per kernel kind that ran: launches, summed device time, and
+ * the algorithmic flops and bytes of those launches (the arithmetic of what
+ * the kernel computes and the data it must read and write once, 8 B per
+ * double, from the model's sizes); *n_out = number of kinds that ran.       */
+typedef struct lrbms_kernel_stat {
+  char name[40];
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} lrbms_kernel_stat;
+int lrbms_profile_enable(lrbms_model* m, int32_t enable);
+int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int32_t* n_out);
+
 /* Synchronize and return the device status word (0 or a negative LRBMS_E_*). */
 int lrbms_model_status(lrbms_model* m);
 

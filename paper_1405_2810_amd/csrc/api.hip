@@ -9,11 +9,98 @@
 #include <vector>
 
 #include "common.h"
+#include "ktimer.h"
 #include "model.h"
 
 namespace lrbms {
 
 static thread_local std::string g_last_error;
+
+// ---- kernel timer ---------------------------------------------------------------
+thread_local KernelTimer* t_timer = nullptr;
+
+const char* kernel_kind_name(int kind) {
+  static const char* const names[KK_COUNT] = {
+      "k_moments",        "k_lsq",          "k_affine_sum",     "k_assemble_diag",
+      "k_reduce_diag",    "k_assemble_iface", "k_front_asm",    "k_front_factor0",
+      "k_front_step",     "k_front_backward", "k_reconstruct",  "k_flux",
+      "k_transport",      "k_limiter"};
+  return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
+}
+
+hipEvent_t KernelTimer::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    failed = true;
+    return nullptr;
+  }
+  return e;
+}
+
+void KernelTimer::reset() {
+  for (auto& r : recs) {
+    if (r.a) pool.push_back(r.a);
+    if (r.b) pool.push_back(r.b);
+  }
+  recs.clear();
+  for (int k = 0; k < KK_COUNT; ++k) n[k] = unit_n[k] = 0, ms[k] = flops[k] = bytes[k] = 0.0;
+  failed = false;
+}
+
+bool KernelTimer::drain() {
+  bool ok = !failed;
+  for (auto& r : recs) {
+    float t = 0.0f;
+    if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      n[r.kind] += 1;
+      ms[r.kind] += t;
+      if (r.flops < 0.0) {
+        unit_n[r.kind] += 1;
+      } else {
+        flops[r.kind] += r.flops;
+        bytes[r.kind] += r.bytes;
+      }
+    } else {
+      ok = false;
+    }
+    if (r.a) pool.push_back(r.a);
+    if (r.b) pool.push_back(r.b);
+  }
+  recs.clear();
+  return ok;
+}
+
+KernelTimer::~KernelTimer() {
+  for (auto& r : recs) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+void ktimer_begin(int kind, hipStream_t st) {
+  KernelTimer* t = t_timer;
+  if (!t) return;
+  t->open = t->take();
+  t->open_kind = kind;
+  if (t->open && hipEventRecord(t->open, st) != hipSuccess) t->failed = true;
+}
+
+void ktimer_end(double flops, double bytes, hipStream_t st) {
+  KernelTimer* t = t_timer;
+  if (!t || t->open_kind < 0) return;
+  hipEvent_t b = t->take();
+  if (b && hipEventRecord(b, st) != hipSuccess) t->failed = true;
+  t->recs.push_back(KernelTimer::Rec{t->open_kind, t->open, b, flops, bytes});
+  t->open = nullptr;
+  t->open_kind = -1;
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
@@ -261,6 +348,45 @@ static bool small_cholesky(std::vector<double>& A, int n) {
   return true;
 }
 
+// Algorithmic flops and bytes (8 B per double) of one launch of each kernel
+// kind whose work does not depend on the launch: the inputs it must read and
+// the outputs it must write once, and the arithmetic of what it computes.
+static void set_unit_figures(Model& M) {
+  const Geom& g = M.g;
+  const double n = g.ncell, r = g.r, d = g.dim, nm = n_moments(g.dim), nf = g.nface;
+  double phi = 0.0, blk = 0.0, asm_fl = 0.0;
+  for (const Sub& S : M.subs) {
+    const double rows = r * S.nE, NE = S.NE;
+    phi += rows * NE;
+    blk += NE * NE;
+    asm_fl += 2.0 * rows * NE * (NE + 1) + 2.0 * (2 * d + 1) * r * rows * NE;
+  }
+  double if_bytes = 0.0, if_fl = 0.0;
+  for (const Iface& I : M.ifaces) {
+    const double NL = M.subs[I.lo].NE, NH = M.subs[I.hi].NE;
+    if_bytes += r * I.nf * (NL + NH) + 2.0 * I.nf * nm + NL * NH;
+    if_fl += 2.0 * r * I.nf * NL * NH + 4.0 * r * r * I.nf * NH;
+  }
+  double red = 0.0;
+  for (const Sub& S : M.subs) red += (double)S.NE * (S.NE + 1);
+  const int cols = M.max_ne + 1 <= 16 ? 16 : (M.max_ne + 1 <= 32 ? 32 : 64);
+  for (int k = 0; k < KK_COUNT; ++k) M.unit_flops[k] = M.unit_bytes[k] = 0.0;
+  M.unit_bytes[KK_MOMENTS] = 8.0 * n * (r + nm + 1);
+  M.unit_bytes[KK_ASM_DIAG] = 8.0 * (phi + nm * n + n + blk + M.N);
+  M.unit_flops[KK_ASM_DIAG] = asm_fl;
+  M.unit_bytes[KK_ASM_REDUCE] = 8.0 * ((double)M.asm_layout.n_chunks * cols * (cols + 1) + red);
+  M.unit_flops[KK_ASM_REDUCE] = (double)M.asm_layout.n_chunks * cols * (cols + 1);
+  M.unit_bytes[KK_ASM_IFACE] = 8.0 * if_bytes;
+  M.unit_flops[KK_ASM_IFACE] = if_fl;
+  M.unit_bytes[KK_LSQ] = 8.0 * (r * n + (double)M.nprof * r * n);
+  M.unit_flops[KK_LSQ] = 2.0 * M.nprof * r * n;
+  M.unit_bytes[KK_RECONSTRUCT] = 8.0 * (phi + M.N + r * n);
+  M.unit_flops[KK_RECONSTRUCT] = 2.0 * phi;
+  M.unit_bytes[KK_FLUX] = 8.0 * (2.0 * r * n + n + nf);
+  M.unit_bytes[KK_TRANSPORT] = 8.0 * (2.0 * r * n + nf + 2.0 * n);
+  M.unit_bytes[KK_LIMITER] = 8.0 * (2.0 * r * n + nf) + n;
+}
+
 int model_finish(Model& M, const double* basis, int nprof, const double* profiles) {
   Geom& g = M.g;
   long long& b = M.dev_bytes;
@@ -332,6 +458,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
     }
     if (!hip_ok(hipStreamSynchronize(st), "affine terms")) return LRBMS_E_HIP;
   }
+  set_unit_figures(M);
   return LRBMS_OK;
 }
 
@@ -500,6 +627,7 @@ int lrbms_model_interfaces(const lrbms_model* m, int32_t* axis, int32_t* lo, int
 int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, void* stream) {
   if (!m || !d_sat) return (set_error("NULL argument"), LRBMS_E_ARG);
   Model* M = M_(m);
+  TimerScope timing(&M->timer);
   hipStream_t st = (hipStream_t)stream;
   const Geom& g = M->g;
   if (mode != LRBMS_DIRECT && mode != LRBMS_DIRECT_FIT && mode != LRBMS_AFFINE)
@@ -542,6 +670,7 @@ int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, voi
 int lrbms_online_solve(lrbms_model* m, double* d_pN, void* stream) {
   if (!m || !d_pN) return (set_error("NULL argument"), LRBMS_E_ARG);
   Model* M = M_(m);
+  TimerScope timing(&M->timer);
   if (!M->assembled) return (set_error("online_solve called before online_assemble"), LRBMS_E_STATE);
   hipStream_t st = (hipStream_t)stream;
   if (!hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, d_pN, M->d_status, st),
@@ -555,6 +684,7 @@ int lrbms_reconstruct_flux(lrbms_model* m, const double* d_pN, const double* d_s
                            double* d_flux, double* d_ph, void* stream) {
   if (!m || !d_pN || !d_sat || !d_flux) return (set_error("NULL argument"), LRBMS_E_ARG);
   Model* M = M_(m);
+  TimerScope timing(&M->timer);
   hipStream_t st = (hipStream_t)stream;
   double* ph = d_ph ? d_ph : M->d_scratch_ph;
   if (!hip_ok(launch_reconstruct(M->g, M->d_subs, M->n_sub, M->d_tiles, M->n_tiles, M->d_phi, d_pN,
@@ -571,6 +701,7 @@ int lrbms_transport_step(lrbms_model* m, const double* d_sat, const double* d_fl
   if (!m || !d_sat || !d_flux || !d_sat_out) return (set_error("NULL argument"), LRBMS_E_ARG);
   if (d_sat_out == d_sat) return (set_error("d_sat_out must not alias d_sat"), LRBMS_E_ARG);
   Model* M = M_(m);
+  TimerScope timing(&M->timer);
   hipStream_t st = (hipStream_t)stream;
   const Geom& g = M->g;
   if (g.limiter) {
@@ -622,6 +753,40 @@ int lrbms_model_status(lrbms_model* m) {
     return LRBMS_E_HIP;
   if (s) set_error("device reported an error (non-positive pivot in the reduced Cholesky)");
   return s;
+}
+
+int lrbms_profile_enable(lrbms_model* m, int32_t enable) {
+  if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+  M->timer.drain();
+  M->timer.reset();
+  M->timer.on = enable != 0;
+  return LRBMS_OK;
+}
+
+int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (!m || !n_out || (cap > 0 && !out)) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  KernelTimer& T = M->timer;
+  const bool ok = T.drain();
+  int cnt = 0;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (T.n[k] == 0) continue;
+    if (cnt < cap) {
+      lrbms_kernel_stat& o = out[cnt];
+      std::memset(&o, 0, sizeof(o));
+      std::snprintf(o.name, sizeof(o.name), "%s", kernel_kind_name(k));
+      o.launches = T.n[k];
+      o.total_ms = T.ms[k];
+      o.flops = T.flops[k] + (double)T.unit_n[k] * M->unit_flops[k];
+      o.bytes = T.bytes[k] + (double)T.unit_n[k] * M->unit_bytes[k];
+    }
+    ++cnt;
+  }
+  *n_out = cnt;
+  if (!ok) return (set_error("kernel timer: an event failed"), LRBMS_E_HIP);
+  return LRBMS_OK;
 }
 
 void lrbms_model_destroy(lrbms_model* m) {

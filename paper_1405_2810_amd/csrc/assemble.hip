@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "ktimer.h"
 
 namespace lrbms {
 
@@ -86,8 +87,10 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, const double* __restric
 hipError_t launch_moments(const Geom& g, const double* src, int kind, const double* theta,
                           int nprof, long long prof_stride, double* mom, hipStream_t st) {
   const int nb = (g.ncell + 255) / 256;
+  ktimer_begin(KK_MOMENTS, st);
   hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, st, g, src, kind, theta, nprof,
                      prof_stride, mom);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 
@@ -715,11 +718,15 @@ static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub
                     (has_rhs ? (PART_RHS_CONST | PART_RHS_GAMMA) & parts : 0);
   if (n_sub > 0 && pdiag) {
     const size_t lds = sizeof(double) * diag_lds_doubles(COLS, g.r, g.dim);
+    ktimer_begin(KK_ASM_DIAG, st);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_diag<COLS>), dim3(L.n_chunks), dim3(256), lds,
                        st, g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
+    ktimer_end(-1.0, -1.0, st);
+    ktimer_begin(KK_ASM_REDUCE, st);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce_diag<COLS>), dim3(n_sub), dim3(256), 0, st,
                        d_subs, L.first_chunk, L.partial, has_mat ? 1 : 0, has_rhs ? 1 : 0, blocks,
                        fN);
+    ktimer_end(-1.0, -1.0, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -731,8 +738,10 @@ static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub
     const size_t lds_chunk = sizeof(double) * 2 * (size_t)chunk * g.r * stride;
     const size_t lds_red = sizeof(double) * (size_t)(256 / COLS) * COLS * stride;
     const size_t lds = lds_chunk > lds_red ? lds_chunk : lds_red;
+    ktimer_begin(KK_ASM_IFACE, st);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_assemble_iface<COLS>), dim3(n_iface), dim3(256), lds,
                        st, g, d_subs, d_ifaces, phi, mom, parts, blocks, chunk);
+    ktimer_end(-1.0, -1.0, st);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -836,8 +845,10 @@ hipError_t launch_affine_sum(const double* base, const double* terms, long long 
   long long nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
+  ktimer_begin(KK_AFFINE_SUM, st);
   hipLaunchKernelGGL(k_affine_sum, dim3((unsigned)nb), dim3(256), 0, st, base, terms, n, theta,
                      nq, out);
+  ktimer_end(2.0 * (double)n * nq, 8.0 * (double)n * (nq + 2), st);
   return hipGetLastError();
 }
 
@@ -919,11 +930,13 @@ __global__ void k_lsq_final(const double* __restrict__ partial, int nblocks, int
 hipError_t launch_lsq(const Geom& g, const double* sat, const double* prof, int nprof,
                       const double* gchol, double* partial, int nblocks, double* theta,
                       hipStream_t st) {
+  ktimer_begin(KK_LSQ, st);
   hipLaunchKernelGGL(k_lsq_partial, dim3(nblocks), dim3(256), 0, st, g, sat, prof, nprof,
                      partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lsq_final, dim3(1), dim3(64), 0, st, partial, nblocks, nprof, gchol, theta);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 

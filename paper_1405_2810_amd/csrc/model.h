@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "ktimer.h"
 #include "solver.h"
 
 namespace lrbms {
@@ -40,6 +41,9 @@ struct Model {
   bool assembled = false;
   hipStream_t last_stream = nullptr;
   long long dev_bytes = 0;
+  // kernel timing and the fixed per-launch algorithmic figures per kernel kind
+  KernelTimer timer;
+  double unit_flops[KK_COUNT] = {}, unit_bytes[KK_COUNT] = {};
   ~Model();
 };
 

@@ -69,6 +69,9 @@ struct SolverPlan {
   std::vector<std::vector<std::vector<StepItem>>> step_items;  // [level][panel]
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
+  // algorithmic flops and bytes of every launch (for the kernel timer)
+  std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]
+  std::vector<std::vector<double>> step_flops, step_bytes;                           // [level][panel]
 };
 
 // Build the plan for the box grid with box sizes subs[].NE and interfaces.

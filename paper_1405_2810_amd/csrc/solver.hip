@@ -2,6 +2,8 @@
 // with nested-dissection ordering of the coarse boxes.  See solver.h.
 #include "solver.h"
 
+#include "ktimer.h"
+
 #include <algorithm>
 #include <map>
 
@@ -293,6 +295,44 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
             plan.step_items[h][b].push_back(StepItem{p, b, ti, tj});
         }
       }
+    }
+  }
+  // algorithmic figures per launch: Cholesky arithmetic of the work each
+  // launch does, and the front entries it must read and write (8 B each)
+  plan.asm_flops.assign(H, 0.0);
+  plan.asm_bytes.assign(H, 0.0);
+  plan.f0_flops.assign(H, 0.0);
+  plan.f0_bytes.assign(H, 0.0);
+  plan.bw_flops.assign(H, 0.0);
+  plan.bw_bytes.assign(H, 0.0);
+  plan.step_flops.assign(H, {});
+  plan.step_bytes.assign(H, {});
+  for (int h = 0; h < H; ++h) {
+    for (const AsmItem& it : plan.asm_items[h]) {
+      const double e = (double)it.nr * it.nc;
+      plan.asm_flops[h] += e * std::max(it.nsrc - 1, 0);
+      plan.asm_bytes[h] += 8.0 * e * (it.nsrc + 1);
+    }
+    plan.step_flops[h].assign(plan.step_items[h].size(), 0.0);
+    plan.step_bytes[h].assign(plan.step_items[h].size(), 0.0);
+    for (int p : plan.level_fronts[h]) {
+      const FrontD& d = plan.fronts[p];
+      const double ld = d.m + d.u;
+      const double nb0 = std::min(kNB, d.m);
+      plan.f0_flops[h] += 2.0 * nb0 * nb0 * nb0 / 3.0;
+      plan.f0_bytes[h] += 8.0 * (nb0 * (nb0 + 1) / 2 + nb0 * nb0);
+      for (int b = 0; b < d.npanels; ++b) {
+        const double nb = std::min(kNB, d.m - b * kNB);
+        const double cs = b * kNB + nb, t = ld - cs;
+        const double nb1 = (b + 1 < d.npanels) ? std::min(kNB, d.m - (int)cs) : 0.0;
+        plan.step_flops[h][b] += (t + 1) * nb * nb + t * (t + 1) * nb + 2.0 * t * nb +
+                                 2.0 * nb1 * nb1 * nb1 / 3.0;
+        plan.step_bytes[h][b] += 8.0 * (2.0 * (t + 1) * nb + t * (t + 1) + 2.0 * t + nb * nb +
+                                        nb1 * nb1);
+      }
+      const double m = d.m, u = d.u;
+      plan.bw_flops[h] += 2.0 * m * u + m * m;
+      plan.bw_bytes[h] += 8.0 * (m * u + m * (m + 1) / 2 + 2.0 * m + u);
     }
   }
   return true;
@@ -686,15 +726,22 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
   for (int h = 0; h < H; ++h) {
     const int na = (int)plan.asm_items[h].size();
     const int nf = (int)plan.level_fronts[h].size();
+    ktimer_begin(KK_FRONT_ASM, st);
     hipLaunchKernelGGL(k_front_asm, dim3(na), dim3(256), 0, st, dev.asm_items[h], dev.fronts,
                        blocks, fN, dev.F);
+    ktimer_end(plan.asm_flops[h], plan.asm_bytes[h], st);
+    ktimer_begin(KK_FRONT_FACTOR0, st);
     hipLaunchKernelGGL(k_front_factor0, dim3(nf), dim3(256), 0, st, dev.level_fronts[h],
                        dev.fronts, dev.F, dev.Inv, status);
+    ktimer_end(plan.f0_flops[h], plan.f0_bytes[h], st);
     for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
       const int ni = (int)plan.step_items[h][p].size();
-      if (ni)
+      if (ni) {
+        ktimer_begin(KK_FRONT_STEP, st);
         hipLaunchKernelGGL(k_front_step, dim3(ni), dim3(256), 0, st, dev.step_items[h][p],
                            dev.fronts, dev.F, dev.L, dev.Inv, status);
+        ktimer_end(plan.step_flops[h][p], plan.step_bytes[h][p], st);
+      }
     }
   }
   for (int h = H - 1; h >= 0; --h) {
@@ -702,8 +749,10 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
     int maxld = 0;
     for (int f : plan.level_fronts[h])
       maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
+    ktimer_begin(KK_FRONT_BACKWARD, st);
     hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
                        dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, pN);
+    ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
   }
   return hipGetLastError();
 }

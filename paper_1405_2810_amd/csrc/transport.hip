@@ -15,6 +15,7 @@
 // All kernels are one thread per cell or per face with x-fastest indexing, so
 // neighbouring threads touch neighbouring addresses of the SoA arrays.
 #include "common.h"
+#include "ktimer.h"
 
 namespace lrbms {
 
@@ -53,8 +54,10 @@ hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const
                               int n_tiles, const double* phi, const double* pN, double* ph,
                               hipStream_t st) {
   (void)n_sub;
+  ktimer_begin(KK_RECONSTRUCT, st);
   hipLaunchKernelGGL(k_reconstruct, dim3(n_tiles), dim3(256), 0, st, g, d_subs, d_tiles, phi, pN,
                      ph);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 
@@ -142,7 +145,9 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
 
 hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, double* flux,
                        hipStream_t st) {
+  ktimer_begin(KK_FLUX, st);
   hipLaunchKernelGGL(k_flux, dim3((g.nface + 255) / 256), dim3(256), 0, st, g, ph, sat, flux);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 
@@ -263,8 +268,10 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
 
 hipError_t launch_transport(const Geom& g, const double* sat, const double* flux, double* sat_bar,
                             hipStream_t st) {
+  ktimer_begin(KK_TRANSPORT, st);
   hipLaunchKernelGGL(k_transport, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat, flux,
                      sat_bar);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 
@@ -355,8 +362,10 @@ __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restric
 
 hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
                           double* sat_out, uint8_t* flags, hipStream_t st) {
+  ktimer_begin(KK_LIMITER, st);
   hipLaunchKernelGGL(k_limiter, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat_bar, flux,
                      sat_out, flags);
+  ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 

@@ -42,6 +42,11 @@ class Problem_C(C.Structure):
                 ("sat_penalty_scale", C.c_double), ("limiter", C.c_int32), ("dt", C.c_double)]
 
 
+class KernelStat_C(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 class ModelInfo_C(C.Structure):
     _fields_ = [("dim", C.c_int32), ("r", C.c_int32), ("ncell", C.c_int32), ("nface", C.c_int32),
                 ("n_sub", C.c_int32), ("n_iface", C.c_int32), ("N", C.c_int32),
@@ -76,6 +81,8 @@ def lib():
         L.lrbms_copy_reduced_system.argtypes = [vp, vp, vp]
         L.lrbms_copy_theta.argtypes = [vp, vp]
         L.lrbms_model_status.argtypes = [vp]
+        L.lrbms_profile_enable.argtypes = [vp, i32]
+        L.lrbms_profile_read.argtypes = [vp, vp, i32, C.POINTER(i32)]
         L.lrbms_model_destroy.argtypes = [vp]
         L.lrbms_model_destroy.restype = None
         _lib = L
@@ -244,6 +251,23 @@ class Model:
         total = sum(int(s) * self.info["r"] * n for s, n in zip(sizes, ncells))
         del tmp
         return sizes, basis[:total].copy()
+
+    def profile_enable(self, on: bool = True):
+        """Switch the per-kernel event timing of the online calls on or off
+        (clears the counters)."""
+        _check(lib().lrbms_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """Per kernel: launches, summed device ms, algorithmic flops and bytes."""
+        arr = (KernelStat_C * 32)()
+        n = C.c_int32(0)
+        _check(lib().lrbms_profile_read(self._h, C.cast(arr, C.c_void_p), 32, C.byref(n)))
+        out = {}
+        for k in range(min(n.value, 32)):
+            e = arr[k]
+            out[e.name.decode()] = {"launches": int(e.launches), "total_ms": float(e.total_ms),
+                                    "flops": float(e.flops), "bytes": float(e.bytes)}
+        return out
 
     def status(self):
         return lib().lrbms_model_status(self._h)
