@@ -341,6 +341,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
 // ============================ numeric (device) ===============================
 
 typedef double Tile[kNB + 1];
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -348,128 +349,157 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// Cholesky of the nb x nb lower tile D (LDS) and the inverse Li of its factor.
-// D is overwritten by L; Li is lower triangular, zero elsewhere.  The upper
-// part of D is used as scratch.  Non-positive pivots set the status word and
-// are replaced by 1 so that the results stay finite.
-__device__ void tile_factor(Tile* D, Tile* Li, int nb, int* status) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < kNB * kNB; idx += blockDim.x) Li[idx / kNB][idx % kNB] = 0.0;
-  __syncthreads();
-  for (int s0 = 0; s0 < nb; s0 += 16) {
-    const int sb = min(16, nb - s0);
-    if (wave == 0) {
-      // lane i < 16 holds row i of the 16 x 16 diagonal block (identity padding)
-      double r[16];
+// 1/sqrt(d): the hardware estimate refined by two Newton steps, which brings
+// it to full double precision.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Orders the LDS accesses of one wave around this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// c += a b for 16 x 16 blocks and an inner dimension of 4 (FP64 MFMA): lane l
+// supplies a(l % 16, l / 16) and b(l / 16, l % 16); element (l / 16 + 4 v, l % 16)
+// of the result is c[v].
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Work buffers of the tile factorization besides the tile itself.
+struct TileAux {
+  double T[16][17];   // one 16 x 16 product of the inverse (wave 1)
+  double cb[2][64];   // pivot column broadcast (wave 0)
+  double dinv[kNB];   // 1 / L(k, k)
+};
+
+// Columns c0 .. c0+15 of the tile, rows c0 .. 63, by wave 0: lane = row,
+// right-looking, the pivot column broadcast through LDS.  Non-positive or
+// non-finite pivots set the status word and are replaced by 1 so that the
+// results stay finite.
+__device__ __noinline__ void panel16(Tile* D, TileAux& A, int c0, int* status) {
+  const int lane = threadIdx.x & 63;
+  const int row = c0 + lane;
+  const bool act = row < kNB;
+  double a[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
-        r[j] = (lane < sb && j <= lane) ? D[s0 + lane][s0 + j] : (lane == j ? 1.0 : 0.0);
+  for (int t = 0; t < 16; ++t) a[t] = (act && c0 + t <= row) ? D[row][c0 + t] : 0.0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        double dk = readlane_f64(r[k], k);
-        if (!(dk > 0.0) || !isfinite(dk)) {
-          if (lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
-          dk = 1.0;
-        }
-        const double sk = sqrt(dk);
-        if (lane == k) r[k] = sk;
-        else if (lane > k) r[k] = r[k] / sk;
-#pragma unroll
-        for (int j = k + 1; j < 16; ++j) {
-          const double ljk = readlane_f64(r[k], j);
-          if (lane >= j) r[j] -= r[k] * ljk;
-        }
-      }
-      // lane j < 16 forms column j of the inverse of the block
-      double c[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const double lii = readlane_f64(r[i], i);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) {
-          const double lik = readlane_f64(r[k], i);
-          if (k >= lane) acc += lik * c[k];
-        }
-        c[i] = (i < lane) ? 0.0 : (i == lane ? 1.0 / lii : -acc / lii);
-      }
-      if (lane < sb) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j <= lane) D[s0 + lane][s0 + j] = r[j];
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (i >= lane && i < sb) Li[s0 + i][s0 + lane] = c[i];
-      }
+  for (int k = 0; k < 16; ++k) {
+    double dk = readlane_f64(a[k], k);
+    if (!(dk > 0.0) || !isfinite(dk)) {
+      if (lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
+      dk = 1.0;
     }
-    __syncthreads();
-    // rows below the block inside the tile: X = D(rows, block) Linv_block^T
-    const int r0 = s0 + sb, nrow = nb - r0;
-    double v[4];
-    int cnt = 0;
-    for (int idx = tid; idx < nrow * sb; idx += blockDim.x, ++cnt) {
-      const int i = r0 + idx % nrow, k = idx / nrow;
-      double a = 0.0;
-      for (int j = 0; j <= k; ++j) a += D[i][s0 + j] * Li[s0 + k][s0 + j];
-      v[cnt] = a;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int idx = tid; idx < nrow * sb; idx += blockDim.x, ++cnt)
-      D[r0 + idx % nrow][s0 + idx / nrow] = v[cnt];
-    __syncthreads();
-    // trailing update inside the tile
-    for (int idx = tid; idx < nrow * nrow; idx += blockDim.x) {
-      const int i = r0 + idx % nrow, j = r0 + idx / nrow;
-      if (j <= i) {
-        double a = 0.0;
-        for (int k = 0; k < sb; ++k) a += D[i][s0 + k] * D[j][s0 + k];
-        D[i][j] -= a;
-      }
-    }
-    __syncthreads();
+    const double y = rsqrt_nr(dk);
+    const double lk = (lane > k) ? a[k] * y : ((lane == k) ? dk * y : 0.0);
+    a[k] = lk;
+    A.cb[k & 1][lane] = lk;
+    if (lane == 0) A.dinv[c0 + k] = y;
+    wave_lds_sync();
+#pragma unroll
+    for (int t = k + 1; t < 16; ++t) a[t] = fma(-lk, A.cb[k & 1][t], a[t]);
   }
-  // off-diagonal blocks of the inverse, block diagonal by block diagonal:
-  // Linv(I,J) = -Linv(I,I) sum_{K=J}^{I-1} L(I,K) Linv(K,J)
-  const int nblk = (nb + 15) / 16;
-  for (int dd = 1; dd < nblk; ++dd) {
-    const int nbd = nblk - dd;
-    for (int idx = tid; idx < nbd * 256; idx += blockDim.x) {
-      const int J = idx / 256, I = J + dd, i = (idx % 256) / 16, j = idx % 16;
-      const int gi = I * 16 + i, gj = J * 16 + j;
-      double a = 0.0;
-      if (gi < nb && gj < nb)
-        for (int k = J * 16; k < I * 16; ++k) a += D[gi][k] * Li[k][gj];
-      D[J * 16 + j][I * 16 + i] = a;   // transposed, in the unused upper part
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nbd * 256; idx += blockDim.x) {
-      const int J = idx / 256, I = J + dd, i = (idx % 256) / 16, j = idx % 16;
-      const int gi = I * 16 + i, gj = J * 16 + j;
-      if (gi < nb && gj < nb) {
-        double a = 0.0;
-        for (int k = I * 16; k <= gi; ++k) a += Li[gi][k] * D[J * 16 + j][k];
-        Li[gi][gj] = -a;
-      }
-    }
-    __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) D[row][c0 + t] = (c0 + t <= row) ? a[t] : 0.0;
   }
 }
 
-// Load the nb x nb diagonal tile of `panel` of a front, factor it and store the
-// inverse of its factor.
-__device__ void factor_diag_tile(const FrontD& f, const double* Fp, long long lda, int panel,
-                                 double* Inv, Tile* D, Tile* Li, int* status) {
-  const int c0 = panel * kNB, nb = min(kNB, f.m - c0);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-    const int i = idx % kNB, j = idx / kNB;
-    D[i][j] = (i < nb && j < nb && j <= i) ? Fp[(c0 + i) + (c0 + j) * lda] : 0.0;
+// D(I, K) -= P(I) P(K)^T for the 16 x 16 blocks of panel J (one wave).
+__device__ __forceinline__ void block_update(Tile* D, int I, int K, int J) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  d4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc)
+    c = mfma16(D[16 * I + r][16 * J + 4 * cc + q], D[16 * K + r][16 * J + 4 * cc + q], c);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) D[16 * I + q + 4 * v][16 * K + r] -= c[v];
+}
+
+// Row block J of X = L^{-1} (one wave): the diagonal block by forward
+// substitution (lane % 16 = column), then X(J, M) = -X(J, J) sum_{K=M}^{J-1}
+// L(J, K) X(K, M) for M < J.
+__device__ __noinline__ void inverse_row_block(Tile* D, Tile* X, TileAux& A, int J) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  const int c0 = 16 * J;
+  double x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k + 1 < i; k += 2) {
+      s0 = fma(D[c0 + i][c0 + k], x[k], s0);
+      s1 = fma(D[c0 + i][c0 + k + 1], x[k + 1], s1);
+    }
+    if (i & 1) s0 = fma(D[c0 + i][c0 + i - 1], x[i - 1], s0);
+    x[i] = ((i == r ? 1.0 : 0.0) - (s0 + s1)) * A.dinv[c0 + i];
   }
-  __syncthreads();
-  tile_factor(D, Li, nb, status);
-  double* Ip = Inv + f.inv_off + (long long)panel * kNB * kNB;
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) Ip[idx] = Li[idx / kNB][idx % kNB];
+  if (lane < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[c0 + i][c0 + lane] = x[i];
+  }
+  wave_lds_sync();
+  for (int M = 0; M < J; ++M) {
+    d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int K = M; K < J; ++K) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+        c = mfma16(D[c0 + r][16 * K + 4 * cc + q], X[16 * K + 4 * cc + q][16 * M + r], c);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A.T[q + 4 * v][r] = c[v];
+    wave_lds_sync();
+    d4 e = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) e = mfma16(X[c0 + r][c0 + 4 * cc + q], A.T[4 * cc + q][r], e);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[c0 + q + 4 * v][16 * M + r] = -e[v];
+    wave_lds_sync();
+  }
+}
+
+// Cholesky factor L of the nb x nb SPD matrix held in the lower part of D
+// (rows and columns nb .. 63 must hold the identity) and Ip = L^{-1} (kNB x kNB
+// row-major, zero outside the lower nb x nb part).  Blocked by 16: wave 0
+// factors panel J+1 right after updating its block column with panel J,
+// while wave 1 forms row block J of the inverse and waves 2-3 apply panel J
+// to the remaining trailing blocks.  D is overwritten by L (its strict upper
+// part is scratch); X receives the inverse.
+__device__ void tile_factor_inv(Tile* D, Tile* X, TileAux& A, double* Ip, int nb, int* status) {
+  const int wave = threadIdx.x >> 6;
+  const int nJ = (nb + 15) >> 4;
+  // step J: panel J (factored in step J-1, or here for J = -1) is applied
+  for (int J = -1; J < nJ; ++J) {
+    if (wave == 0) {
+      if (J + 1 < nJ) {
+        for (int I = J + 1; I < nJ && J >= 0; ++I) block_update(D, I, J + 1, J);
+        wave_lds_sync();
+        panel16(D, A, 16 * (J + 1), status);
+      }
+    } else if (J >= 0) {
+      if (wave == 1) {
+        inverse_row_block(D, X, A, J);
+      } else {
+        int q = 0;
+        for (int I = J + 2; I < nJ; ++I)
+          for (int K = J + 2; K <= I; ++K, ++q)
+            if ((q & 1) == wave - 2) block_update(D, I, K, J);
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+    const int i = idx >> 6, j = idx & 63;
+    Ip[idx] = (i < nb && j < nb && (j >> 4) <= (i >> 4)) ? X[i][j] : 0.0;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ items,
@@ -497,103 +527,143 @@ __global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ i
   }
 }
 
+// First diagonal tile of every front of a level.
 __global__ __launch_bounds__(256) void k_front_factor0(const int* __restrict__ list,
                                                        const FrontD* __restrict__ fronts,
                                                        const double* __restrict__ F,
                                                        double* __restrict__ Inv, int* status) {
   __shared__ Tile D[kNB];
-  __shared__ Tile Li[kNB];
+  __shared__ Tile X[kNB];
+  __shared__ TileAux aux;
   const FrontD f = fronts[list[blockIdx.x]];
-  factor_diag_tile(f, F + f.off, f.m + f.u + 1, 0, Inv, D, Li, status);
+  const long long lda = f.m + f.u + 1;
+  const double* Fp = F + f.off;
+  const int nb = min(kNB, f.m);
+  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+    const int i = idx & 63, j = idx >> 6;
+    D[i][j] = (i < nb && j < nb) ? ((j <= i) ? Fp[i + j * lda] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  tile_factor_inv(D, X, aux, Inv + f.inv_off, nb, status);
 }
 
-// out = X Li^T for X, Li in LDS (rows < nr, k < nb); thread = 4 x 4 outputs.
-__device__ __forceinline__ void tile_times_inv_t(Tile* X, Tile* Li, int nb, double acc[4][4]) {
-  const int ti = (threadIdx.x % 16) * 4, tj = (threadIdx.x / 16) * 4;
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int k = 0; k < nb; ++k) {
-    double a[4], b[4];
-    for (int p = 0; p < 4; ++p) {
-      a[p] = X[ti + p][k];
-      b[p] = Li[tj + p][k];
-    }
-    for (int p = 0; p < 4; ++p)
-      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+// out = X Li^T for the 64 x 64 tiles X, Li in LDS (Li lower triangular, zero
+// outside nb x nb): wave w forms row block w; out[cb] holds column block cb.
+__device__ __forceinline__ void times_inv_t(Tile* Xm, Tile* Li, int nb, d4 out[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+  const int nc = (nb + 3) >> 2;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) out[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nc; ++c) {
+    const double a = Xm[16 * w + r][4 * c + q];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      if (4 * c < 16 * cb + 16) out[cb] = mfma16(a, Li[16 * cb + r][4 * c + q], out[cb]);
   }
 }
 
+// One tile of panel `panel` of a front: the L rows of tile row ti
+// (F rows times L_panel^{-T}, written to the L buffer) and, for tj >= 0, the
+// trailing update F(ti, tj) -= L(ti) L(tj)^T.  The workgroup of tile (0, 0)
+// then factors the next diagonal tile from the values it just formed.
 __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__ items,
                                                     const FrontD* __restrict__ fronts,
                                                     double* __restrict__ F,
                                                     double* __restrict__ Lb,
                                                     double* __restrict__ Inv, int* status) {
-  __shared__ Tile Li[kNB];
-  __shared__ Tile A[kNB];
-  __shared__ Tile B[kNB];
+  __shared__ Tile S0[kNB];
+  __shared__ Tile S1[kNB];
+  __shared__ Tile S2[kNB];
+  __shared__ TileAux aux;
   const StepItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   double* Lp = Lb + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
-  const int R0 = cs + it.ti * kNB, nr = min((long long)kNB, lda - R0);
+  const int R0 = cs + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
   const double* Ip = Inv + f.inv_off + (long long)it.panel * kNB * kNB;
-  const int ti4 = (threadIdx.x % 16) * 4, tj4 = (threadIdx.x / 16) * 4;
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-    const int i = idx % kNB, k = idx / kNB;
-    Li[i][k] = Ip[i * kNB + k];
-    B[i][k] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  const bool upd = it.tj >= 0;
+  const int C0 = cs + (upd ? it.tj : 0) * kNB;
+  const int ncl = upd ? (int)min((long long)kNB, ld - C0) : 0;
+  // loads: L_panel^{-1} (row-major), the panel columns of tile row ti, and the
+  // F tile (ti, tj) this workgroup updates (kept in registers)
+  double fold[16];
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    const int i = idx & 63, k = idx >> 6;
+    S0[idx >> 6][idx & 63] = Ip[idx];
+    S2[i][k] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
+    fold[p] = (upd && i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
   }
   __syncthreads();
-  double acc[4][4];
-  tile_times_inv_t(B, Li, nb, acc);
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) A[ti4 + p][tj4 + q] = acc[p][q];
+  d4 acc[4];
+  times_inv_t(S2, S0, nb, acc);
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
   __syncthreads();
   if (it.tj <= 0) {
-    for (int idx = threadIdx.x; idx < nr * nb; idx += blockDim.x) {
-      const int i = idx % nr, k = idx / nr;
-      Lp[(R0 + i) + (long long)(c0 + k) * lda] = A[i][k];
+    for (int idx = tid; idx < kNB * kNB; idx += 256) {
+      const int i = idx & 63, k = idx >> 6;
+      if (i < nr && k < nb) Lp[(R0 + i) + (long long)(c0 + k) * lda] = S1[i][k];
     }
   }
-  if (it.tj < 0) return;
-  const int C0 = cs + it.tj * kNB, ncl = min((long long)kNB, ld - C0);
-  Tile* Bt = A;
+  if (!upd) return;
+  Tile* Bt = S1;
   if (it.tj != it.ti) {
-    for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-      const int i = idx % kNB, k = idx / kNB;
-      B[i][k] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p;
+      const int i = idx & 63, k = idx >> 6;
+      S2[i][k] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
     }
     __syncthreads();
-    tile_times_inv_t(B, Li, nb, acc);
+    times_inv_t(S2, S0, nb, acc);
     __syncthreads();
-    for (int p = 0; p < 4; ++p)
-      for (int q = 0; q < 4; ++q) B[ti4 + p][tj4 + q] = acc[p][q];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S0[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
     __syncthreads();
-    Bt = B;
+    Bt = S0;
   }
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int k = 0; k < nb; ++k) {
-    double a[4], b[4];
-    for (int p = 0; p < 4; ++p) {
-      a[p] = A[ti4 + p][k];
-      b[p] = Bt[tj4 + p][k];
-    }
-    for (int p = 0; p < 4; ++p)
-      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+  // U = L(ti) L(tj)^T: wave w forms row block w
+  d4 u[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) u[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nc = (nb + 3) >> 2;
+  for (int c = 0; c < nc; ++c) {
+    const double a = S1[16 * w + r][4 * c + q];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) u[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], u[cb]);
   }
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) {
-      const int i = ti4 + p, j = tj4 + q;
-      if (i < nr && j < ncl) Fp[(R0 + i) + (long long)(C0 + j) * lda] -= acc[p][q];
-    }
-  // look-ahead: this workgroup owns the next diagonal tile
-  if (it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels)
-    factor_diag_tile(f, Fp, lda, it.panel + 1, Inv, A, B, status);
+  __syncthreads();   // S2 is free: stage U there for coalesced read-modify-write
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = u[cb][v];
+  __syncthreads();
+  const bool ahead = it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels;
+  const int nb1 = ahead ? min(kNB, f.m - cs) : 0;
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    const int i = idx & 63, k = idx >> 6;
+    const double nv = fold[p] - S2[i][k];
+    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = nv;
+    if (ahead) S0[i][k] = (i < nb1 && k < nb1) ? nv : (i == k ? 1.0 : 0.0);
+  }
+  if (!ahead) return;
+  __syncthreads();
+  tile_factor_inv(S0, S1, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
+                  status);
 }
 
+// Backward substitution L^T x = y of one front per workgroup, from the root
+// down: w = (y_S, x_U); z_S = y_S - L_US^T x_U; then panel by panel from the
+// last, x_b = L_bb^{-T} z_b with the stored tile inverse and
+// z_{<b} -= L_{b,<b}^T x_b.
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
@@ -601,62 +671,70 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
                                                         const double* __restrict__ Inv,
                                                         double* __restrict__ pN) {
   extern __shared__ double w[];   // m + u values
-  __shared__ double xb[kNB];
+  __shared__ double red[4][kNB];
   const FrontD f = fronts[list[blockIdx.x]];
-  const int ld = f.m + f.u;
+  const int ld = f.m + f.u, tid = threadIdx.x;
   const long long lda = ld + 1;
   const double* Lp = Lb + f.off;
-  for (int i = threadIdx.x; i < f.m; i += blockDim.x) w[i] = Lp[ld + (long long)i * lda];
+  for (int i = tid; i < f.m; i += blockDim.x) w[i] = Lp[ld + (long long)i * lda];
   for (int n = f.n_s_nodes; n < f.n_nodes; ++n) {
-    const NodeRef r = nodes[f.node_off + n];
-    for (int i = threadIdx.x; i < r.size; i += blockDim.x) w[r.pos + i] = pN[r.pn_off + i];
+    const NodeRef nr = nodes[f.node_off + n];
+    for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = pN[nr.pn_off + i];
   }
   __syncthreads();
-  // z = y_S - L_US^T x_U (row i of L_US^T is contiguous in memory)
-  for (int i = threadIdx.x; i < f.m; i += blockDim.x) {
+  // z_S = y_S - L_US^T x_U (column i of L is contiguous over its rows)
+  for (int i = tid; i < f.m; i += blockDim.x) {
     const double* col = Lp + (long long)i * lda;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int rr = f.m;
     for (; rr + 4 <= ld; rr += 4) {
-      a0 += col[rr] * w[rr];
-      a1 += col[rr + 1] * w[rr + 1];
-      a2 += col[rr + 2] * w[rr + 2];
-      a3 += col[rr + 3] * w[rr + 3];
+      a0 = fma(col[rr], w[rr], a0);
+      a1 = fma(col[rr + 1], w[rr + 1], a1);
+      a2 = fma(col[rr + 2], w[rr + 2], a2);
+      a3 = fma(col[rr + 3], w[rr + 3], a3);
     }
-    for (; rr < ld; ++rr) a0 += col[rr] * w[rr];
+    for (; rr < ld; ++rr) a0 = fma(col[rr], w[rr], a0);
     w[i] -= (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
+  const int k = tid & 63, g = tid >> 6;
   for (int b = f.npanels - 1; b >= 0; --b) {
     const int c0 = b * kNB, nb = min(kNB, f.m - c0);
     const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
-    // xb is read over all kNB entries below (with zero weights past nb), so
-    // the tail must hold zeros, not stale values that might be non-finite.
-    if ((int)threadIdx.x < kNB) {
-      double s = 0.0;
-      for (int k = threadIdx.x; k < nb; ++k) s += Li[k * kNB + threadIdx.x] * w[c0 + k];
-      xb[threadIdx.x] = s;
+    // x_b(k) = sum_{m >= k} Li(m, k) z_b(m): four partial sums over m
+    double s = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) {
+      const int m = 16 * g + mm;
+      if (m < nb && m >= k) s = fma(Li[m * kNB + k], w[c0 + m], s);
     }
+    red[g][k] = s;
     __syncthreads();
-    if ((int)threadIdx.x < nb) w[c0 + threadIdx.x] = xb[threadIdx.x];
-    for (int i = threadIdx.x; i < c0; i += blockDim.x) {
+    if (tid < kNB) red[0][tid] = (tid < nb) ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])
+                                            : 0.0;
+    __syncthreads();
+    if (tid < nb) w[c0 + tid] = red[0][tid];
+    // z(i) -= sum_k L(c0 + k, i) x_b(k) for i < c0
+    for (int i = tid; i < c0; i += blockDim.x) {
       const double* col = Lp + c0 + (long long)i * lda;
       double a[kNB];
 #pragma unroll
-      for (int k = 0; k < kNB; ++k) a[k] = (k < nb) ? col[k] : 0.0;
-      double s0 = 0.0, s1 = 0.0;
+      for (int kk = 0; kk < kNB; ++kk) a[kk] = (kk < nb) ? col[kk] : 0.0;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int k = 0; k < kNB; k += 2) {
-        s0 += a[k] * xb[k];
-        s1 += a[k + 1] * xb[k + 1];
+      for (int kk = 0; kk < kNB; kk += 4) {
+        s0 = fma(a[kk], red[0][kk], s0);
+        s1 = fma(a[kk + 1], red[0][kk + 1], s1);
+        s2 = fma(a[kk + 2], red[0][kk + 2], s2);
+        s3 = fma(a[kk + 3], red[0][kk + 3], s3);
       }
-      w[i] -= s0 + s1;
+      w[i] -= (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
   }
   for (int n = 0; n < f.n_s_nodes; ++n) {
-    const NodeRef r = nodes[f.node_off + n];
-    for (int i = threadIdx.x; i < r.size; i += blockDim.x) pN[r.pn_off + i] = w[r.pos + i];
+    const NodeRef nr = nodes[f.node_off + n];
+    for (int i = tid; i < nr.size; i += blockDim.x) pN[nr.pn_off + i] = w[nr.pos + i];
   }
 }
 
