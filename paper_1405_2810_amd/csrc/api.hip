@@ -369,13 +369,13 @@ static void set_unit_figures(Model& M) {
   }
   double red = 0.0;
   for (const Sub& S : M.subs) red += (double)S.NE * (S.NE + 1);
-  const int cols = M.max_ne + 1 <= 16 ? 16 : (M.max_ne + 1 <= 32 ? 32 : 64);
+  const int cols = assemble_cols(M.max_ne);
   for (int k = 0; k < KK_COUNT; ++k) M.unit_flops[k] = M.unit_bytes[k] = 0.0;
   M.unit_bytes[KK_MOMENTS] = 8.0 * n * (r + nm + 1);
   M.unit_bytes[KK_ASM_DIAG] = 8.0 * (phi + nm * n + n + blk + M.N);
   M.unit_flops[KK_ASM_DIAG] = asm_fl;
-  M.unit_bytes[KK_ASM_REDUCE] = 8.0 * ((double)M.asm_layout.n_chunks * cols * (cols + 1) + red);
-  M.unit_flops[KK_ASM_REDUCE] = (double)M.asm_layout.n_chunks * cols * (cols + 1);
+  M.unit_bytes[KK_ASM_REDUCE] = 8.0 * ((double)M.asm_layout.n_chunks * cols * cols + red);
+  M.unit_flops[KK_ASM_REDUCE] = (double)M.asm_layout.n_chunks * cols * cols;
   M.unit_bytes[KK_ASM_IFACE] = 8.0 * if_bytes;
   M.unit_flops[KK_ASM_IFACE] = if_fl;
   M.unit_bytes[KK_LSQ] = 8.0 * (r * n + (double)M.nprof * r * n);
@@ -434,7 +434,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
     if (!dev_copy(&M.d_prof, profiles, (size_t)nprof * L, b) ||
         !dev_copy(&M.d_gchol, G.data(), G.size(), b) || !dev_zero(&M.d_theta, (size_t)nprof, b))
       return LRBMS_E_OOM;
-    M.lsq_blocks = std::min(1024, (g.ncell + 255) / 256);
+    M.lsq_blocks = lsq_blocks(g.ncell);
     if (!dev_zero(&M.d_partial, (size_t)M.lsq_blocks * nprof, b)) return LRBMS_E_OOM;
     if (!dev_zero(&M.d_c, (size_t)M.nblk, b) || !dev_zero(&M.d_bq, (size_t)M.nblk * nprof, b) ||
         !dev_zero(&M.d_e, (size_t)M.N, b) || !dev_zero(&M.d_dq, (size_t)M.N * nprof, b))

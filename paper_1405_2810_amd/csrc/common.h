@@ -141,9 +141,9 @@ hipError_t launch_transport(const Geom& g, const double* sat, const double* flux
                             double* sat_bar, hipStream_t st);
 hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
                           double* sat_out, uint8_t* flags, hipStream_t st);
-hipError_t launch_fine_apply(const Geom& g, const double* mom, const double* x, double* y,
-                             hipStream_t st);
-hipError_t launch_fine_rhs(const Geom& g, const double* mom, double* l, hipStream_t st);
-hipError_t launch_fine_jacobi(const Geom& g, const double* mom, double* dinv, hipStream_t st);
+// Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and
+// the number of workgroups of the least-squares projection.
+int assemble_cols(int max_ne);
+int lsq_blocks(int ncell);
 
 }  // namespace lrbms

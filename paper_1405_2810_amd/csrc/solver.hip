@@ -663,7 +663,11 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 // Backward substitution L^T x = y of one front per workgroup, from the root
 // down: w = (y_S, x_U); z_S = y_S - L_US^T x_U; then panel by panel from the
 // last, x_b = L_bb^{-T} z_b with the stored tile inverse and
-// z_{<b} -= L_{b,<b}^T x_b.
+// z_{<b} -= L_{b,<b}^T x_b.  Everything is latency bound, so every thread
+// issues its global loads in unrolled batches before it needs them (a column
+// of L is contiguous over its rows).
+constexpr int kBwBatch = 32;
+
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
@@ -682,44 +686,64 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
     for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = pN[nr.pn_off + i];
   }
   __syncthreads();
-  // z_S = y_S - L_US^T x_U (column i of L is contiguous over its rows)
+  // z_S = y_S - L_US^T x_U
   for (int i = tid; i < f.m; i += blockDim.x) {
     const double* col = Lp + (long long)i * lda;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int rr = f.m;
-    for (; rr + 4 <= ld; rr += 4) {
-      a0 = fma(col[rr], w[rr], a0);
-      a1 = fma(col[rr + 1], w[rr + 1], a1);
-      a2 = fma(col[rr + 2], w[rr + 2], a2);
-      a3 = fma(col[rr + 3], w[rr + 3], a3);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = f.m; r0 < ld; r0 += kBwBatch) {
+      double a[kBwBatch];
+#pragma unroll
+      for (int t = 0; t < kBwBatch; ++t) a[t] = (r0 + t < ld) ? col[r0 + t] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kBwBatch; ++t)
+        acc[t & 3] = fma(a[t], (r0 + t < ld) ? w[r0 + t] : 0.0, acc[t & 3]);
     }
-    for (; rr < ld; ++rr) a0 = fma(col[rr], w[rr], a0);
-    w[i] -= (a0 + a1) + (a2 + a3);
+    w[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
   __syncthreads();
   const int k = tid & 63, g = tid >> 6;
   for (int b = f.npanels - 1; b >= 0; --b) {
     const int c0 = b * kNB, nb = min(kNB, f.m - c0);
     const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
+    // loads first: this thread's part of L_bb^{-1} and its column of the panel rows
+    double li[16], a[kNB];
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) {
+      const int m = 16 * g + mm;
+      li[mm] = (m < nb && m >= k) ? Li[m * kNB + k] : 0.0;
+    }
+    const double* col = Lp + c0 + (long long)tid * lda;
+#pragma unroll
+    for (int kk = 0; kk < kNB; ++kk) a[kk] = (tid < c0 && kk < nb) ? col[kk] : 0.0;
     // x_b(k) = sum_{m >= k} Li(m, k) z_b(m): four partial sums over m
     double s = 0.0;
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) {
       const int m = 16 * g + mm;
-      if (m < nb && m >= k) s = fma(Li[m * kNB + k], w[c0 + m], s);
+      s = fma(li[mm], (m < nb) ? w[c0 + m] : 0.0, s);
     }
     red[g][k] = s;
     __syncthreads();
-    if (tid < kNB) red[0][tid] = (tid < nb) ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])
-                                            : 0.0;
+    if (tid < kNB)
+      red[0][tid] = (tid < nb) ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]) : 0.0;
     __syncthreads();
     if (tid < nb) w[c0 + tid] = red[0][tid];
     // z(i) -= sum_k L(c0 + k, i) x_b(k) for i < c0
-    for (int i = tid; i < c0; i += blockDim.x) {
-      const double* col = Lp + c0 + (long long)i * lda;
-      double a[kNB];
+    if (tid < c0) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int kk = 0; kk < kNB; ++kk) a[kk] = (kk < nb) ? col[kk] : 0.0;
+      for (int kk = 0; kk < kNB; kk += 4) {
+        s0 = fma(a[kk], red[0][kk], s0);
+        s1 = fma(a[kk + 1], red[0][kk + 1], s1);
+        s2 = fma(a[kk + 2], red[0][kk + 2], s2);
+        s3 = fma(a[kk + 3], red[0][kk + 3], s3);
+      }
+      w[tid] -= (s0 + s1) + (s2 + s3);
+    }
+    for (int i = tid + (int)blockDim.x; i < c0; i += blockDim.x) {
+      const double* ci = Lp + c0 + (long long)i * lda;
+#pragma unroll
+      for (int kk = 0; kk < kNB; ++kk) a[kk] = (kk < nb) ? ci[kk] : 0.0;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int kk = 0; kk < kNB; kk += 4) {
