@@ -813,15 +813,15 @@ int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_siz
     o.push_back(H);
     o.push_back((int64_t)plan.nodes.size());
     o.push_back((int64_t)plan.children.size());
-    o.push_back(0);
+    o.push_back(plan.lpan_doubles);
     o.push_back(plan.front_doubles);
     o.push_back(plan.vec_doubles);
     o.push_back(plan.inv_doubles);
     o.push_back((int64_t)(plan.flops));
     for (auto& f : plan.fronts) {
-      int64_t v[11] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
-                       f.nchild, f.n_s_nodes, f.npanels};
-      o.insert(o.end(), v, v + 11);
+      int64_t v[12] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
+                       f.nchild, f.n_s_nodes, f.npanels, f.loff};
+      o.insert(o.end(), v, v + 12);
     }
     for (auto& n : plan.nodes) {
       int64_t v[4] = {n.pos, n.pn_off, n.size, n.ppos};

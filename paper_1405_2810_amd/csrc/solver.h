@@ -38,6 +38,7 @@ constexpr int kMaxLd = 8192;  // largest front (rows) handled by the backward sw
 
 struct FrontD {
   long long off;      // front storage (column-major, lda = m + u + 1, m + u columns)
+  long long loff;     // rows of L below each diagonal tile, panel-major (see lpanel_base)
   long long voff;     // backward-substitution vector workspace
   long long inv_off;  // tile inverses, one kNB x kNB per panel
   int m, u;
@@ -47,6 +48,15 @@ struct FrontD {
 };
 
 struct NodeRef { int pos, pn_off, size, ppos; };
+
+// The L rows below the diagonal tile of panel b of a front (rows cs_b .. ld,
+// cs_b = min(kNB (b + 1), m), the last one the forward-substituted right-hand
+// side) are stored row by row, kNB doubles per row: row r of panel b starts
+// at lpanel_base(f, b) + (r - cs_b) kNB.  All panels before the last are full.
+__host__ __device__ inline long long lpanel_base(const FrontD& f, int b) {
+  const long long ld1 = (long long)f.m + f.u + 1;
+  return f.loff + (long long)kNB * (b * ld1 - 32LL * b * (b + 1));
+}
 
 // One destination block of a front (box pair, or the right-hand-side row against
 // one box) with up to three sources summed in a fixed order: the block of A_N
@@ -67,7 +77,7 @@ struct SolverPlan {
   std::vector<std::vector<int>> level_fronts;  // front ids per level (height)
   std::vector<std::vector<AsmItem>> asm_items;
   std::vector<std::vector<std::vector<StepItem>>> step_items;  // [level][panel]
-  long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0;
+  long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0, lpan_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
   std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]

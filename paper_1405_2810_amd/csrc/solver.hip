@@ -115,7 +115,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.nodes.clear();
   plan.children.clear();
   std::vector<std::map<int, int>> pos(nf);  // box -> position in front
-  long long foff = 0, voff = 0, ioff = 0;
+  long long foff = 0, voff = 0, ioff = 0, loff = 0;
   int noff = 0;
   plan.flops = 0.0;
   for (int p = 0; p < nf; ++p) {
@@ -138,6 +138,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     d.voff = voff;
     voff += ld;
     d.npanels = (d.m + kNB - 1) / kNB;
+    d.loff = loff;
+    for (int b = 0; b < d.npanels; ++b) loff += (long long)kNB * (ld + 1 - std::min(kNB * (b + 1), d.m));
     d.inv_off = ioff;
     ioff += (long long)d.npanels * kNB * kNB;
     d.n_s_nodes = (int)f.S.size();
@@ -174,6 +176,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.front_doubles = foff;
   plan.vec_doubles = voff;
   plan.inv_doubles = ioff;
+  plan.lpan_doubles = loff;
   // levels by height
   int H = 0;
   for (auto& f : F) H = std::max(H, f.height + 1);
@@ -375,41 +378,88 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 
 // Work buffers of the tile factorization besides the tile itself.
 struct TileAux {
-  double T[16][17];   // one 16 x 16 product of the inverse (wave 1)
+  double T[4][16][17];   // one 16 x 16 product of the inverse per wave
   double cb[2][64];   // pivot column broadcast (wave 0)
   double dinv[kNB];   // 1 / L(k, k)
 };
 
+// 1/d: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  return fma(y, e, y);
+}
+
 // Columns c0 .. c0+15 of the tile, rows c0 .. 63, by wave 0: lane = row,
-// right-looking, the pivot column broadcast through LDS.  Non-positive or
-// non-finite pivots set the status word and are replaced by 1 so that the
-// results stay finite.
-__device__ __noinline__ void panel16(Tile* D, TileAux& A, int c0, int* status) {
+// right-looking on unnormalized columns.  At pivot k the raw column k (final
+// since pivot k-1) is broadcast through LDS while the reciprocal of the pivot
+// is formed, and the Schur update uses a(i,k) / d_k, so the serial chain per
+// pivot is the reciprocal and one multiply-add; 1/sqrt(d_k), for the scaling
+// of the stored factor, is computed beside it.  The LDS requests of one wave
+// complete in issue order, so the broadcast needs no wait beyond the use of
+// the loaded values.  Non-positive or non-finite pivots set the status word
+// and are replaced by 1 so that the results stay finite.  With inv, the
+// inverse of the diagonal block is also formed from the registers.
+__device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool inv, int* status) {
   const int lane = threadIdx.x & 63;
   const int row = c0 + lane;
   const bool act = row < kNB;
-  double a[16];
+  double a[16], ys[16], ds[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) a[t] = (act && c0 + t <= row) ? D[row][c0 + t] : 0.0;
+  bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
+    double* cb = A.cb[k & 1];
+    cb[lane] = a[k];
+    __builtin_amdgcn_wave_barrier();
     double dk = readlane_f64(a[k], k);
-    if (!(dk > 0.0) || !isfinite(dk)) {
-      if (lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
-      dk = 1.0;
-    }
-    const double y = rsqrt_nr(dk);
-    const double lk = (lane > k) ? a[k] * y : ((lane == k) ? dk * y : 0.0);
-    a[k] = lk;
-    A.cb[k & 1][lane] = lk;
-    if (lane == 0) A.dinv[c0 + k] = y;
-    wave_lds_sync();
+    const bool ok = (dk > 0.0) && (dk < 1.0e300);
+    bad = bad || !ok;
+    dk = ok ? dk : 1.0;
+    ds[k] = dk;
+    ys[k] = rsqrt_nr(dk);
+    const double mk = a[k] * rcp_nr(dk);
 #pragma unroll
-    for (int t = k + 1; t < 16; ++t) a[t] = fma(-lk, A.cb[k & 1][t], a[t]);
+    for (int t = k + 1; t < 16; ++t) a[t] = fma(-mk, cb[t], a[t]);
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (bad && lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
+  // scale: L(i,k) = a(i,k) / sqrt(d_k) below the diagonal, sqrt(d_k) on it
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    a[k] = (lane > k) ? a[k] * ys[k] : ((lane == k) ? ds[k] * ys[k] : 0.0);
+  if (lane < 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (lane == k) A.dinv[c0 + k] = ys[k];
   }
   if (act) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) D[row][c0 + t] = (c0 + t <= row) ? a[t] : 0.0;
+  }
+  if (inv) {
+    // inverse of the diagonal block from the registers: lane % 16 = column j,
+    // x(i) = (delta_ij - sum_{k<i} L(i,k) x(k)) / L(i,i), L(i,k) read from lane i
+    const int j = lane & 15;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int k = 0; k + 1 < i; k += 2) {
+        s0 = fma(readlane_f64(a[k], i), x[k], s0);
+        s1 = fma(readlane_f64(a[k + 1], i), x[k + 1], s1);
+      }
+      if (i & 1) s0 = fma(readlane_f64(a[i - 1], i), x[i - 1], s0);
+      x[i] = ((i == j ? 1.0 : 0.0) - (s0 + s1)) * ys[i];
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) X[c0 + i][c0 + lane] = x[i];
+    }
   }
 }
 
@@ -424,11 +474,10 @@ __device__ __forceinline__ void block_update(Tile* D, int I, int K, int J) {
   for (int v = 0; v < 4; ++v) D[16 * I + q + 4 * v][16 * K + r] -= c[v];
 }
 
-// Row block J of X = L^{-1} (one wave): the diagonal block by forward
-// substitution (lane % 16 = column), then X(J, M) = -X(J, J) sum_{K=M}^{J-1}
-// L(J, K) X(K, M) for M < J.
-__device__ __noinline__ void inverse_row_block(Tile* D, Tile* X, TileAux& A, int J) {
-  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+// Diagonal block J of X = L^{-1} by one wave from the factor in LDS:
+// forward substitution with lane % 16 = column.
+__device__ __noinline__ void inverse_diag_block(Tile* D, Tile* X, TileAux& A, int J) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
   const int c0 = 16 * J;
   double x[16];
 #pragma unroll
@@ -446,33 +495,38 @@ __device__ __noinline__ void inverse_row_block(Tile* D, Tile* X, TileAux& A, int
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[c0 + i][c0 + lane] = x[i];
   }
-  wave_lds_sync();
-  for (int M = 0; M < J; ++M) {
-    d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int K = M; K < J; ++K) {
+}
+
+// Off-diagonal block X(I, J) = -X(I, I) sum_{K=J}^{I-1} L(I, K) X(K, J), I > J,
+// by one wave with its own 16 x 16 scratch T.
+__device__ __forceinline__ void inverse_offdiag_block(Tile* D, Tile* X, double (*T)[17], int I,
+                                                      int J) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  d4 c = {0.0, 0.0, 0.0, 0.0};
+  for (int K = J; K < I; ++K) {
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc)
-        c = mfma16(D[c0 + r][16 * K + 4 * cc + q], X[16 * K + 4 * cc + q][16 * M + r], c);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) A.T[q + 4 * v][r] = c[v];
-    wave_lds_sync();
-    d4 e = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) e = mfma16(X[c0 + r][c0 + 4 * cc + q], A.T[4 * cc + q][r], e);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[c0 + q + 4 * v][16 * M + r] = -e[v];
-    wave_lds_sync();
+    for (int cc = 0; cc < 4; ++cc)
+      c = mfma16(D[16 * I + r][16 * K + 4 * cc + q], X[16 * K + 4 * cc + q][16 * J + r], c);
   }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) T[q + 4 * v][r] = c[v];
+  wave_lds_sync();
+  d4 e = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) e = mfma16(X[16 * I + r][16 * I + 4 * cc + q], T[4 * cc + q][r], e);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[16 * I + q + 4 * v][16 * J + r] = -e[v];
 }
 
 // Cholesky factor L of the nb x nb SPD matrix held in the lower part of D
 // (rows and columns nb .. 63 must hold the identity) and Ip = L^{-1} (kNB x kNB
 // row-major, zero outside the lower nb x nb part).  Blocked by 16: wave 0
 // factors panel J+1 right after updating its block column with panel J,
-// while wave 1 forms row block J of the inverse and waves 2-3 apply panel J
-// to the remaining trailing blocks.  D is overwritten by L (its strict upper
-// part is scratch); X receives the inverse.
+// while wave 1 inverts diagonal block J and waves 2-3 apply panel J to the
+// remaining trailing blocks; the last diagonal block is inverted by wave 0
+// from its registers.  The off-diagonal blocks of the inverse follow,
+// diagonal by diagonal, over all waves.  D is overwritten by L (its strict
+// upper part is scratch); X receives the inverse.
 __device__ void tile_factor_inv(Tile* D, Tile* X, TileAux& A, double* Ip, int nb, int* status) {
   const int wave = threadIdx.x >> 6;
   const int nJ = (nb + 15) >> 4;
@@ -482,11 +536,11 @@ __device__ void tile_factor_inv(Tile* D, Tile* X, TileAux& A, double* Ip, int nb
       if (J + 1 < nJ) {
         for (int I = J + 1; I < nJ && J >= 0; ++I) block_update(D, I, J + 1, J);
         wave_lds_sync();
-        panel16(D, A, 16 * (J + 1), status);
+        panel16(D, X, A, 16 * (J + 1), J + 2 == nJ, status);
       }
-    } else if (J >= 0) {
+    } else if (J >= 0 && J + 1 < nJ) {
       if (wave == 1) {
-        inverse_row_block(D, X, A, J);
+        inverse_diag_block(D, X, A, J);
       } else {
         int q = 0;
         for (int I = J + 2; I < nJ; ++I)
@@ -494,6 +548,10 @@ __device__ void tile_factor_inv(Tile* D, Tile* X, TileAux& A, double* Ip, int nb
             if ((q & 1) == wave - 2) block_update(D, I, K, J);
       }
     }
+    __syncthreads();
+  }
+  for (int dd = 1; dd < nJ; ++dd) {
+    for (int J = wave; J + dd < nJ; J += 4) inverse_offdiag_block(D, X, A.T[wave], J + dd, J);
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
@@ -579,7 +637,6 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   const FrontD f = fronts[it.front];
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
-  double* Lp = Lb + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
   const int R0 = cs + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
   const double* Ip = Inv + f.inv_off + (long long)it.panel * kNB * kNB;
@@ -606,9 +663,10 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
     for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
   __syncthreads();
   if (it.tj <= 0) {
+    double* Lrow = Lb + lpanel_base(f, it.panel) + (long long)(R0 - cs) * kNB;
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
-      const int i = idx & 63, k = idx >> 6;
-      if (i < nr && k < nb) Lp[(R0 + i) + (long long)(c0 + k) * lda] = S1[i][k];
+      const int i = idx >> 6, k = idx & 63;
+      if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = S1[i][k];
     }
   }
   if (!upd) return;
@@ -663,98 +721,131 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 // Backward substitution L^T x = y of one front per workgroup, from the root
 // down: w = (y_S, x_U); z_S = y_S - L_US^T x_U; then panel by panel from the
 // last, x_b = L_bb^{-T} z_b with the stored tile inverse and
-// z_{<b} -= L_{b,<b}^T x_b.  Everything is latency bound, so every thread
-// issues its global loads in unrolled batches before it needs them (a column
-// of L is contiguous over its rows).
-constexpr int kBwBatch = 32;
-
+// z_{<b} -= L_{b,<b}^T x_b.  L is read row-wise from the panel-major store,
+// lane = column within a panel, so every load is one coalesced row; the loads
+// of a panel's update are issued before x_b is formed.
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
-                                                        const double* __restrict__ Lb,
+                                                        const double* __restrict__ Lpan,
                                                         const double* __restrict__ Inv,
                                                         double* __restrict__ pN) {
   extern __shared__ double w[];   // m + u values
-  __shared__ double red[4][kNB];
+  __shared__ double red[4][4][kNB];
+  __shared__ double xb[kNB];
   const FrontD f = fronts[list[blockIdx.x]];
-  const int ld = f.m + f.u, tid = threadIdx.x;
-  const long long lda = ld + 1;
-  const double* Lp = Lb + f.off;
-  for (int i = tid; i < f.m; i += blockDim.x) w[i] = Lp[ld + (long long)i * lda];
+  const int m = f.m, u = f.u, ld = m + u, np = f.npanels, tid = threadIdx.x;
+  const int k = tid & 63, g = tid >> 6;
+  auto csof = [&](int b) { return min(kNB * (b + 1), m); };
+  // y_S from the right-hand-side rows, x_U from the parent
+  for (int i = tid; i < m; i += blockDim.x) {
+    const int b = i >> 6;
+    w[i] = Lpan[lpanel_base(f, b) + (long long)(ld - csof(b)) * kNB + (i - kNB * b)];
+  }
   for (int n = f.n_s_nodes; n < f.n_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
     for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = pN[nr.pn_off + i];
   }
   __syncthreads();
-  // z_S = y_S - L_US^T x_U
-  for (int i = tid; i < f.m; i += blockDim.x) {
-    const double* col = Lp + (long long)i * lda;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = f.m; r0 < ld; r0 += kBwBatch) {
-      double a[kBwBatch];
+  // z_S = y_S - L_US^T x_U: four panels at a time, rows of U split over the waves
+  for (int p0 = 0; p0 < np && u > 0; p0 += 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = g; r0 < u; r0 += 64) {
+      double a[4][16];
 #pragma unroll
-      for (int t = 0; t < kBwBatch; ++t) a[t] = (r0 + t < ld) ? col[r0 + t] : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int b = p0 + q;
+        const double* Lr = Lpan + lpanel_base(f, b) + (long long)(m - csof(b)) * kNB + k;
 #pragma unroll
-      for (int t = 0; t < kBwBatch; ++t)
-        acc[t & 3] = fma(a[t], (r0 + t < ld) ? w[r0 + t] : 0.0, acc[t & 3]);
+        for (int t = 0; t < 16; ++t) {
+          const int r = r0 + 4 * t;
+          a[q][t] = (b < np && r < u) ? Lr[(long long)r * kNB] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int r = r0 + 4 * t;
+        const double xr = (r < u) ? w[m + r] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] = fma(a[q][t], xr, s[q]);
+      }
     }
-    w[i] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[g][q][k] = s[q];
+    __syncthreads();
+    {
+      const int b = p0 + g;
+      if (b < np && k < min(kNB, m - kNB * b))
+        w[kNB * b + k] -= (red[0][g][k] + red[1][g][k]) + (red[2][g][k] + red[3][g][k]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int k = tid & 63, g = tid >> 6;
-  for (int b = f.npanels - 1; b >= 0; --b) {
-    const int c0 = b * kNB, nb = min(kNB, f.m - c0);
+  for (int b = np - 1; b >= 0; --b) {
+    const int c0 = b * kNB, nb = min(kNB, m - c0);
     const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
-    // loads first: this thread's part of L_bb^{-1} and its column of the panel rows
-    double li[16], a[kNB];
+    // loads first: this thread's part of L_bb^{-1}, and rows c0 + 16 g + t of the
+    // four panels before b (lane = column of that panel)
+    double li[16], a[4][16];
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) {
-      const int m = 16 * g + mm;
-      li[mm] = (m < nb && m >= k) ? Li[m * kNB + k] : 0.0;
+      const int mr = 16 * g + mm;
+      li[mm] = (mr < nb && mr >= k) ? Li[mr * kNB + k] : 0.0;
     }
-    const double* col = Lp + c0 + (long long)tid * lda;
 #pragma unroll
-    for (int kk = 0; kk < kNB; ++kk) a[kk] = (tid < c0 && kk < nb) ? col[kk] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int b2 = b - 1 - q;
+      const double* Lr = Lpan + lpanel_base(f, b2 < 0 ? 0 : b2) + (long long)(c0 - csof(b2 < 0 ? 0 : b2)) * kNB + k;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int kk = 16 * g + t;
+        a[q][t] = (b2 >= 0 && kk < nb) ? Lr[(long long)kk * kNB] : 0.0;
+      }
+    }
     // x_b(k) = sum_{m >= k} Li(m, k) z_b(m): four partial sums over m
     double s = 0.0;
 #pragma unroll
     for (int mm = 0; mm < 16; ++mm) {
-      const int m = 16 * g + mm;
-      s = fma(li[mm], (m < nb) ? w[c0 + m] : 0.0, s);
+      const int mr = 16 * g + mm;
+      s = fma(li[mm], (mr < nb) ? w[c0 + mr] : 0.0, s);
     }
-    red[g][k] = s;
+    red[g][0][k] = s;
     __syncthreads();
-    if (tid < kNB)
-      red[0][tid] = (tid < nb) ? (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]) : 0.0;
+    if (tid < kNB) {
+      const double x = (tid < nb) ? (red[0][0][tid] + red[1][0][tid]) + (red[2][0][tid] + red[3][0][tid]) : 0.0;
+      xb[tid] = x;
+      if (tid < nb) w[c0 + tid] = x;
+    }
     __syncthreads();
-    if (tid < nb) w[c0 + tid] = red[0][tid];
-    // z(i) -= sum_k L(c0 + k, i) x_b(k) for i < c0
-    if (tid < c0) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    // z of panels b-1 .. b-4, then the older ones four at a time
+    for (int p1 = b - 1; p1 >= 0; p1 -= 4) {
+      if (p1 != b - 1) {
 #pragma unroll
-      for (int kk = 0; kk < kNB; kk += 4) {
-        s0 = fma(a[kk], red[0][kk], s0);
-        s1 = fma(a[kk + 1], red[0][kk + 1], s1);
-        s2 = fma(a[kk + 2], red[0][kk + 2], s2);
-        s3 = fma(a[kk + 3], red[0][kk + 3], s3);
+        for (int q = 0; q < 4; ++q) {
+          const int b2 = p1 - q;
+          const double* Lr = Lpan + lpanel_base(f, b2 < 0 ? 0 : b2) + (long long)(c0 - csof(b2 < 0 ? 0 : b2)) * kNB + k;
+#pragma unroll
+          for (int t = 0; t < 16; ++t) {
+            const int kk = 16 * g + t;
+            a[q][t] = (b2 >= 0 && kk < nb) ? Lr[(long long)kk * kNB] : 0.0;
+          }
+        }
       }
-      w[tid] -= (s0 + s1) + (s2 + s3);
-    }
-    for (int i = tid + (int)blockDim.x; i < c0; i += blockDim.x) {
-      const double* ci = Lp + c0 + (long long)i * lda;
+      double z[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < kNB; ++kk) a[kk] = (kk < nb) ? ci[kk] : 0.0;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int t = 0; t < 16; ++t) {
+        const double x = xb[16 * g + t];
 #pragma unroll
-      for (int kk = 0; kk < kNB; kk += 4) {
-        s0 = fma(a[kk], red[0][kk], s0);
-        s1 = fma(a[kk + 1], red[0][kk + 1], s1);
-        s2 = fma(a[kk + 2], red[0][kk + 2], s2);
-        s3 = fma(a[kk + 3], red[0][kk + 3], s3);
+        for (int q = 0; q < 4; ++q) z[q] = fma(a[q][t], x, z[q]);
       }
-      w[i] -= (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[g][q][k] = z[q];
+      __syncthreads();
+      {
+        const int b2 = p1 - g;
+        if (b2 >= 0) w[kNB * b2 + k] -= (red[0][g][k] + red[1][g][k]) + (red[2][g][k] + red[3][g][k]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int n = 0; n < f.n_s_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
@@ -799,7 +890,7 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
     b += n * (long long)sizeof(double);
     return hipMemset(*p, 0, std::max<long long>(n, 1) * sizeof(double)) == hipSuccess;
   };
-  return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.front_doubles) &&
+  return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.lpan_doubles) &&
          alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles);
 }
 

@@ -314,9 +314,9 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
                                       _ptr(need)))
     it = iter(buf.tolist())
     nxt = lambda k: [next(it) for _ in range(k)]
-    nf, H, nn, nch, nt, fd, vd, idd, flops = nxt(9)
+    nf, H, nn, nch, lpd, fd, vd, idd, flops = nxt(9)
     fronts = [dict(zip(["off", "voff", "inv_off", "m", "u", "node_off", "n_nodes", "child_off",
-                        "nchild", "n_s_nodes", "npanels"], nxt(11))) for _ in range(nf)]
+                        "nchild", "n_s_nodes", "npanels", "loff"], nxt(12))) for _ in range(nf)]
     nodes = [dict(zip(["pos", "pn_off", "size", "ppos"], nxt(4))) for _ in range(nn)]
     children = nxt(nch)
     levels = []
@@ -332,4 +332,4 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
             steps.append([dict(zip(["front", "panel", "ti", "tj"], nxt(4))) for _ in range(next(it))])
         levels.append(dict(fronts=lf, asm=asm, steps=steps))
     return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,
-                front_doubles=fd, vec_doubles=vd, inv_doubles=idd, flops=flops)
+                front_doubles=fd, vec_doubles=vd, inv_doubles=idd, lpan_doubles=lpd, flops=flops)

@@ -59,9 +59,10 @@ def _factor_tile(Fp, m, panel, Inv, f):
 def emulate(plan, blocks, fN):
     """The numeric phase as the device kernels execute it: fronts column-major
     with a right-hand-side row at the bottom, fused panel steps with the L rows
-    in a separate buffer, look-ahead tile factorization, backward sweep."""
+    in a separate panel-major store, look-ahead tile factorization, backward
+    sweep reading L row-wise."""
     F = np.zeros(plan["front_doubles"])
-    Lb = np.zeros(plan["front_doubles"])
+    Lb = np.zeros(plan["lpan_doubles"])
     V = np.zeros(plan["vec_doubles"])
     Inv = np.zeros(plan["inv_doubles"])
     fr, nodes = plan["fronts"], plan["nodes"]
@@ -69,6 +70,16 @@ def emulate(plan, blocks, fN):
     def view(buf, f):
         ld = f["m"] + f["u"]
         return buf[f["off"]:f["off"] + (ld + 1) * ld].reshape(ld + 1, ld, order="F")
+
+    def lpanel(f, b):
+        """rows cs_b .. ld of panel b, NB doubles per row (row-major)"""
+        ld1 = f["m"] + f["u"] + 1
+        base = f["loff"] + NB * (b * ld1 - 32 * b * (b + 1))
+        cs = min(NB * (b + 1), f["m"])
+        return buf_rows(base, ld1 - cs), cs
+
+    def buf_rows(base, nrows):
+        return Lb[base:base + nrows * NB].reshape(nrows, NB)
 
     for lev in plan["levels"]:
         for it in lev["asm"]:
@@ -87,7 +98,7 @@ def emulate(plan, blocks, fN):
         for items in lev["steps"]:
             for it in items:
                 f = fr[it["front"]]
-                Fp, Lp = view(F, f), view(Lb, f)
+                Fp = view(F, f)
                 ld = f["m"] + f["u"]
                 p = it["panel"]
                 c0 = p * NB
@@ -98,7 +109,8 @@ def emulate(plan, blocks, fN):
                 nr = min(NB, ld + 1 - R0)
                 A = Fp[R0:R0 + nr, c0:cs] @ Li.T
                 if it["tj"] <= 0:
-                    Lp[R0:R0 + nr, c0:cs] = A
+                    rows, cs_b = lpanel(f, p)
+                    rows[R0 - cs_b:R0 - cs_b + nr, :nb] = A
                 if it["tj"] < 0:
                     continue
                 C0 = cs + it["tj"] * NB
@@ -112,18 +124,25 @@ def emulate(plan, blocks, fN):
         for fi in lev["fronts"]:
             f = fr[fi]
             ld, m = f["m"] + f["u"], f["m"]
-            Lp = view(Lb, f)
             w = np.zeros(ld)
-            w[:m] = Lp[ld, :m]
+            for b in range(f["npanels"]):
+                rows, cs_b = lpanel(f, b)
+                nbb = min(NB, m - b * NB)
+                w[b * NB:b * NB + nbb] = rows[ld - cs_b, :nbb]
             for n in nodes[f["node_off"] + f["n_s_nodes"]:f["node_off"] + f["n_nodes"]]:
                 w[n["pos"]:n["pos"] + n["size"]] = pN[n["pn_off"]:n["pn_off"] + n["size"]]
-            w[:m] -= Lp[m:ld, :m].T @ w[m:]
+            for b in range(f["npanels"]):
+                rows, cs_b = lpanel(f, b)
+                nbb = min(NB, m - b * NB)
+                w[b * NB:b * NB + nbb] -= rows[m - cs_b:ld - cs_b, :nbb].T @ w[m:]
             for b in reversed(range(f["npanels"])):
                 c0, nb = b * NB, min(NB, m - b * NB)
                 Li = Inv[f["inv_off"] + b * NB * NB:f["inv_off"] + (b + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
                 xb = Li.T @ w[c0:c0 + nb]
                 w[c0:c0 + nb] = xb
-                w[:c0] -= Lp[c0:c0 + nb, :c0].T @ xb
+                for b2 in range(b):
+                    rows, cs2 = lpanel(f, b2)
+                    w[b2 * NB:(b2 + 1) * NB] -= rows[c0 - cs2:c0 - cs2 + nb, :].T @ xb
             for n in nodes[f["node_off"]:f["node_off"] + f["n_s_nodes"]]:
                 pN[n["pn_off"]:n["pn_off"] + n["size"]] = w[n["pos"]:n["pos"] + n["size"]]
     return pN
