@@ -174,7 +174,10 @@ class Model:
         h = C.c_void_p()
         _check(lib().lrbms_model_create(pc.ref(), _ptr(sz), _ptr(bs),
                                         0 if prof is None else prof.shape[0], _ptr(prof), C.byref(h)))
-        return cls(h, prob)
+        m = cls(h, prob)
+        m._sizes = sz.copy()
+        m._offs = np.concatenate([[0], np.cumsum(sz)])
+        return m
 
     @classmethod
     def from_snapshots(cls, prob, snapshots, ne_cap: int, unit_functions=True, profiles=None):
@@ -291,6 +294,33 @@ class Model:
             A[offs[hi[t]]:offs[hi[t]] + nh, offs[lo[t]]:offs[lo[t]] + nl] = B.T
             pos += nl * nh
         return A
+
+    def sparse_reduced_matrix(self, blocks: Optional[np.ndarray] = None):
+        """The block storage as a scipy.sparse CSR matrix (host), both
+        triangles of the coupling blocks."""
+        import scipy.sparse as sp
+        if blocks is None:
+            blocks, _ = self.reduced_system()
+        sizes, offs = self.sizes_offsets()
+        rows, cols, vals = [], [], []
+        pos = 0
+        for E, ne in enumerate(sizes):
+            i, j = np.meshgrid(np.arange(ne), np.arange(ne), indexing="ij")
+            rows.append(offs[E] + i.ravel()); cols.append(offs[E] + j.ravel())
+            vals.append(blocks[pos:pos + ne * ne])
+            pos += ne * ne
+        ax, lo, hi = self.interfaces()
+        for t in range(len(ax)):
+            nl, nh = sizes[lo[t]], sizes[hi[t]]
+            i, j = np.meshgrid(np.arange(nl), np.arange(nh), indexing="ij")
+            v = blocks[pos:pos + nl * nh]
+            rows += [offs[lo[t]] + i.ravel(), offs[hi[t]] + j.ravel()]
+            cols += [offs[hi[t]] + j.ravel(), offs[lo[t]] + i.ravel()]
+            vals += [v, v]
+            pos += nl * nh
+        N = self.info["N"]
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                             shape=(N, N))
 
     def sizes_offsets(self):
         if not hasattr(self, "_sizes"):
