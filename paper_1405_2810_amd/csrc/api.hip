@@ -21,8 +21,8 @@ thread_local KernelTimer* t_timer = nullptr;
 
 const char* kernel_kind_name(int kind) {
   static const char* const names[KK_COUNT] = {
-      "k_moments",        "k_lsq",          "k_affine_sum",     "k_assemble_diag",
-      "k_reduce_diag",    "k_assemble_iface", "k_front_asm",    "k_front_factor0",
+      "k_moments",        "k_lsq",          "k_affine_sum",     "k_asm_box",
+      "k_reduce_box",     "k_asm_iface",    "k_front_asm",      "k_front_factor0",
       "k_front_step",     "k_front_backward", "k_reconstruct",  "k_flux",
       "k_transport",      "k_limiter"};
   return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";

@@ -64,8 +64,8 @@ def counters(path: str, counter: str):
 
 KERNEL_SOURCE = {
     "k_moments": "assemble.hip", "k_lsq": "assemble.hip", "k_lsq_partial": "assemble.hip", "k_lsq_final": "assemble.hip",
-    "k_affine_sum": "assemble.hip", "k_assemble_diag": "assemble.hip",
-    "k_reduce_diag": "assemble.hip", "k_assemble_iface": "assemble.hip",
+    "k_affine_sum": "assemble.hip", "k_asm_box": "assemble.hip",
+    "k_reduce_box": "assemble.hip", "k_asm_iface": "assemble.hip",
     "k_front_asm": "solver.hip", "k_front_factor0": "solver.hip", "k_front_step": "solver.hip",
     "k_front_backward": "solver.hip", "k_reconstruct": "transport.hip", "k_flux": "transport.hip",
     "k_transport": "transport.hip", "k_limiter": "transport.hip",
