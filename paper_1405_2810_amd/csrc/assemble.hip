@@ -373,43 +373,56 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   d4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int IT = PC * NEP / 256;             // (cell, column) items per thread and piece
+  constexpr int NB = 2 * D;
   for (int p0 = 0; p0 < cc; p0 += PC) {
-    // apply
-    for (int it = tid; it < PC * NEP; it += 256) {
+    // apply: the Phi values of all items of this thread are loaded first
+    double ps[IT][R], po[IT][NB][R];
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int it = tid + 256 * u;
+      const int lp = it % PC, col = it / PC;
+      const int lc = p0 + lp, l = c0 + lc;
+      const bool live = lc < cc && col < NE;
+      const double* cp = phi + S.phi_off + (long long)col * R * nE;
+      const int bl[3] = {l % ext[0], (l / ext[0]) % ext[1], l / (ext[0] * ext[1])};
+      const int bst[3] = {1, ext[0], ext[0] * ext[1]};
+#pragma unroll
+      for (int k = 0; k < R; ++k) ps[u][k] = live ? cp[(long long)k * nE + l] : 0.0;
+#pragma unroll
+      for (int f = 0; f < NB; ++f) {
+        const int a = f >> 1, dir = f & 1;
+        const int ba = bl[a] + (dir ? 1 : -1);
+        const bool in = live && want_mat && ba >= 0 && ba < ext[a];
+        const int ln = l + (dir ? bst[a] : -bst[a]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) po[u][f][k] = in ? cp[(long long)k * nE + ln] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int it = tid + 256 * u;
       const int lp = it % PC, col = it / PC;
       const int lc = p0 + lp;
-      double Y[R], ps[R];
+      double Y[R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) Y[k] = ps[k] = 0.0;
+      for (int k = 0; k < R; ++k) Y[k] = 0.0;
       if (lc < cc) {
         const int l = c0 + lc;
         if (col < NE) {
-          const double* cp = phi + S.phi_off + (long long)col * R * nE;
-#pragma unroll
-          for (int k = 0; k < R; ++k) ps[k] = cp[(long long)k * nE + l];
           if (want_mat) {
             const double* K = Kst + (size_t)lc * NF * R * R;
 #pragma unroll
             for (int k = 0; k < R; ++k)
 #pragma unroll
-              for (int kp = 0; kp < R; ++kp) Y[k] = fma(K[k * R + kp], ps[kp], Y[k]);
-            int bl[3] = {l % ext[0], (l / ext[0]) % ext[1], l / (ext[0] * ext[1])};
-            const int bst[3] = {1, ext[0], ext[0] * ext[1]};
+              for (int kp = 0; kp < R; ++kp) Y[k] = fma(K[k * R + kp], ps[u][kp], Y[k]);
 #pragma unroll
-            for (int f = 0; f < 2 * D; ++f) {
-              const int a = f >> 1, dir = f & 1;
-              const int ba = bl[a] + (dir ? 1 : -1);
-              if (ba < 0 || ba >= ext[a]) continue;
-              const int ln = l + (dir ? bst[a] : -bst[a]);
-              double po[R];
-#pragma unroll
-              for (int k = 0; k < R; ++k) po[k] = cp[(long long)k * nE + ln];
+            for (int f = 0; f < NB; ++f)
 #pragma unroll
               for (int k = 0; k < R; ++k)
 #pragma unroll
                 for (int kp = 0; kp < R; ++kp)
-                  Y[k] = fma(K[((1 + f) * R + k) * R + kp], po[kp], Y[k]);
-            }
+                  Y[k] = fma(K[((1 + f) * R + k) * R + kp], po[u][f][kp], Y[k]);
           }
         } else if (col == NE && want_rhs) {
           int x[3];
@@ -419,7 +432,7 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        PhiS[(size_t)(lp * R + k) * LDP + col] = ps[k];
+        PhiS[(size_t)(lp * R + k) * LDP + col] = ps[u][k];
         YS[(size_t)(lp * R + k) * LDP + col] = Y[k];
       }
     }

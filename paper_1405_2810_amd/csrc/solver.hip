@@ -569,19 +569,30 @@ __global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ i
   const FrontD f = fronts[it.front];
   const long long lda = f.m + f.u + 1;
   double* Fp = F + f.off;
-  for (int idx = threadIdx.x; idx < it.nr * it.nc; idx += blockDim.x) {
-    const int i = idx % it.nr, j = idx / it.nr;
-    double v = 0.0;
-    if (!it.diag || j <= i) {
+  const int n = it.nr * it.nc;
+  // four elements per thread and pass, every load of a pass issued before its stores
+  for (int base = threadIdx.x; base < n; base += 4 * blockDim.x) {
+    double v[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * (int)blockDim.x;
+      const int i = idx % it.nr, j = idx / it.nr;
+      const bool live = idx < n && (!it.diag || j <= i);
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        if (s >= it.nsrc) break;
         const AsmSrc S = it.src[s];
         const double* src = S.kind == 0 ? blocks : (S.kind == 1 ? F : fN);
-        v += src[S.so + (long long)i * S.rs + (long long)j * S.cs];
+        v[u][s] = (live && s < it.nsrc) ? src[S.so + (long long)i * S.rs + (long long)j * S.cs] : 0.0;
       }
     }
-    Fp[(it.dr + i) + (long long)(it.dc + j) * lda] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = base + u * (int)blockDim.x;
+      if (idx < n) {
+        const int i = idx % it.nr, j = idx / it.nr;
+        Fp[(it.dr + i) + (long long)(it.dc + j) * lda] = (v[u][0] + v[u][1]) + v[u][2];
+      }
+    }
   }
 }
 
@@ -597,9 +608,17 @@ __global__ __launch_bounds__(256) void k_front_factor0(const int* __restrict__ l
   const long long lda = f.m + f.u + 1;
   const double* Fp = F + f.off;
   const int nb = min(kNB, f.m);
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
+  double v[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = threadIdx.x + 256 * p;
     const int i = idx & 63, j = idx >> 6;
-    D[i][j] = (i < nb && j < nb) ? ((j <= i) ? Fp[i + j * lda] : 0.0) : (i == j ? 1.0 : 0.0);
+    v[p] = (i < nb && j < nb) ? ((j <= i) ? Fp[i + j * lda] : 0.0) : (i == j ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = threadIdx.x + 256 * p;
+    D[idx & 63][idx >> 6] = v[p];
   }
   __syncthreads();
   tile_factor_inv(D, X, aux, Inv + f.inv_off, nb, status);
@@ -646,13 +665,21 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   const int ncl = upd ? (int)min((long long)kNB, ld - C0) : 0;
   // loads: L_panel^{-1} (row-major), the panel columns of tile row ti, and the
   // F tile (ti, tj) this workgroup updates (kept in registers)
-  double fold[16];
+  // (all loads are issued before the first LDS store, so their latencies overlap)
+  double fold[16], li[16], bv[16];
+#pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int idx = tid + 256 * p;
     const int i = idx & 63, k = idx >> 6;
-    S0[idx >> 6][idx & 63] = Ip[idx];
-    S2[i][k] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
+    li[p] = Ip[idx];
+    bv[p] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
     fold[p] = (upd && i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    S0[idx >> 6][idx & 63] = li[p];
+    S2[idx & 63][idx >> 6] = bv[p];
   }
   __syncthreads();
   d4 acc[4];
@@ -672,10 +699,17 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   if (!upd) return;
   Tile* Bt = S1;
   if (it.tj != it.ti) {
+    double yv[16];
+#pragma unroll
     for (int p = 0; p < 16; ++p) {
       const int idx = tid + 256 * p;
       const int i = idx & 63, k = idx >> 6;
-      S2[i][k] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
+      yv[p] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p;
+      S2[idx & 63][idx >> 6] = yv[p];
     }
     __syncthreads();
     times_inv_t(S2, S0, nb, acc);
