@@ -104,19 +104,32 @@ typedef struct lrbms_model_info {
   int64_t device_bytes;     /* device memory held by the model                      */
 } lrbms_model_info;
 
-/* Offline options for lrbms_build_offline_bases (Alg. 2 without the greedy loop:
- * TOF profiles, training snapshots, local Gram-Schmidt, optional cap).         */
+/* Offline options for lrbms_build_offline_bases (Alg. 2 without the greedy
+ * selection: time-of-flight profiles, training snapshots, local Gram-Schmidt
+ * with an optional cap).                                                       */
 typedef struct lrbms_offline_opts {
-  int32_t M;                /* number of mobility profiles (>= 3)                   */
-  int32_t n_train;          /* training snapshots: the M profiles, then seeded mixes */
-  int32_t ne_cap;           /* maximum local basis size N_E (<= 63)                 */
+  int32_t M;                /* number of mobility profiles (3 .. 64)                */
+  int32_t n_train;          /* training parameters: rows of the mu array            */
+  int32_t ne_cap;           /* maximum local basis size N_E (1 .. 63)               */
   int32_t unit_functions;   /* 1: put 1_E first in every local basis                */
-  int32_t n_steps;          /* N_T, the profiles use T = N_T * dt                   */
-  uint64_t seed;            /* seed of the training mixes                           */
-  double pcg_rtol;          /* relative residual of the fine snapshot solves        */
-  int32_t pcg_maxit;
-  int32_t keep_profiles;    /* 1: keep the (deduplicated) profiles for AFFINE       */
+  double horizon;           /* T of the profile thresholds (q-1) T/(M-2), > 0       */
+  double pcg_rtol;          /* relative residual of the fine solves (> 0)           */
+  int32_t pcg_maxit;        /* CG iteration limit per fine solve (> 0)              */
+  double tof_tol;           /* relative change that ends the time-of-flight sweeps  */
+  int32_t tof_maxit;        /* sweep limit (> 0)                                    */
+  int32_t keep_profiles;    /* 1: keep the linearly independent profiles (AFFINE,
+                               DIRECT_FIT); 0: a model without profiles             */
 } lrbms_offline_opts;
+
+/* What the offline stage did (filled when the caller passes a non-NULL pointer). */
+typedef struct lrbms_offline_report {
+  int32_t n_solves;         /* fine solves: the initial pressure + n_train snapshots */
+  int32_t pcg_iters_max;    /* largest CG iteration count of one solve              */
+  int64_t pcg_iters_total;
+  double pcg_relres_max;    /* largest final relative residual                      */
+  int32_t tof_sweeps;       /* block-Jacobi sweeps of the time of flight            */
+  int32_t n_profiles_kept;  /* profiles kept in the model                           */
+} lrbms_offline_report;
 
 /* Create a model from given local bases (parity runs use this).
  *  basis_sizes: host [n_sub] N_E per box (1 .. 63)
@@ -139,19 +152,67 @@ int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
                                       int32_t unit_functions, int32_t n_profiles,
                                       const double* profiles, lrbms_model** out);
 
+/* Fine pressure of Def. pressureDG (the SWIP discretisation on the fine grid,
+ * b_h(p_h, v; gamma) = l_h(v; gamma)) solved on the device by conjugate
+ * gradients with cell-block Jacobi preconditioning, x0 = 0.  Also the fine
+ * reference of the online step and the snapshot solver of the offline stage.
+ *  d_field: device [r*ncell]; with kind LRBMS_FIELD_SATURATION the mobility is
+ *           lambda(s) of this saturation, with LRBMS_FIELD_MOBILITY it is the
+ *           field itself (a P1 field, e.g. a training mobility of Alg. 2)
+ *  d_p:     device [r*ncell], receives p_h
+ *  iterations, relres: host outputs (nullable): CG iterations and the final
+ *           relative residual |l - A p| / |l|, from the recursion
+ * Synchronous (default stream); allocates its work arrays per call.
+ * Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP, LRBMS_E_NOT_SPD (a singular
+ * cell block or a non-positive curvature), LRBMS_E_NONFINITE, LRBMS_E_STATE
+ * when maxit iterations end above rtol (d_p then holds the last iterate).    */
+enum { LRBMS_FIELD_SATURATION = 0, LRBMS_FIELD_MOBILITY = 1 };
+int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_t kind,
+                        double rtol, int32_t maxit, double* d_p, int32_t* iterations,
+                        double* relres);
+
+/* Time of flight of eq. timeOfFlight (Sec. 3.6) for the face fluxes d_flux
+ * (device, [nface], oriented along +axis, e.g. from lrbms_reconstruct_flux):
+ * upwind DG P1, the own trace on outflow faces, the neighbour trace on inflow
+ * faces and zero on inflow boundary faces; right-hand side the porosity.
+ * Solved by block-Jacobi sweeps (each cell solves its r x r block with the
+ * upwind traces of the previous sweep), exact after as many sweeps as the
+ * longest upwind chain has cells when the flow has no cycles; stops when the
+ * largest coefficient change is <= tol times the largest coefficient.
+ *  d_tau: device [r*ncell], receives tau;  sweeps: host output (nullable)
+ * Synchronous (default stream).  Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP,
+ * LRBMS_E_NOT_SPD (a cell block is singular, e.g. a cell with no flux at
+ * all), LRBMS_E_NONFINITE, LRBMS_E_STATE when maxit sweeps end unconverged. */
+int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double tol,
+                         int32_t maxit, double* d_tau, int32_t* sweeps);
+
 /* Offline stage on the device (Alg. 2 steps 1-2 without the error-driven
- * selection): initial pressure by a fine SWIP solve (preconditioned CG),
- * velocity (Def. velocityDG), time-of-flight (eq. timeOfFlight, host
- * flow-ordered sweep), M profiles (Alg. 2 step 1c), fine snapshots at the
- * training mobilities, local Gram-Schmidt with 1_E first, cap N_E.
- * Untimed setup; its result is exported with lrbms_model_export_basis.        */
+ * selection): initial pressure at s = 0 by lrbms_fine_pressure, its face
+ * fluxes (Def. velocityDG), the time of flight, the M profiles of Alg. 2
+ * step 1c (Lambda^1 = lambda(0), Lambda^M = lambda(1), Lambda^q = lambda(0)
+ * where the cell mean of tau exceeds (q-1) T/(M-2), else lambda(1)), one
+ * fine snapshot per training mobility gamma = sum_q mu_q Lambda^q (in row
+ * order), then local Gram-Schmidt as in lrbms_model_create_from_snapshots.
+ * With keep_profiles the model keeps the profiles that are linearly
+ * independent of the ones before them (in q order; Gram-Schmidt with a
+ * relative threshold of 1e-12).
+ *  mu:     host [n_train][M] training parameters
+ *  report: host output (nullable)
+ * Untimed setup, synchronous; the bases can be read back with
+ * lrbms_model_export_basis and the profiles with lrbms_model_export_profiles.
+ * Errors: those of lrbms_fine_pressure and lrbms_time_of_flight, and
+ * LRBMS_E_ARG when a box ends with an empty local basis.                     */
 int lrbms_build_offline_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
-                              lrbms_model** out);
+                              const double* mu, lrbms_model** out,
+                              lrbms_offline_report* report);
 
 int lrbms_model_get_info(const lrbms_model* m, lrbms_model_info* info);
 
 /* Copy the bases (host): sizes [n_sub], basis as in lrbms_model_create.       */
 int lrbms_model_export_basis(const lrbms_model* m, int32_t* sizes, double* basis);
+
+/* Copy the model's mobility profiles (host, [n_profiles][r*ncell]).           */
+int lrbms_model_export_profiles(const lrbms_model* m, double* profiles);
 
 /* a) Mobility of d_sat (device, [r*ncell]) and the reduced system A_N, f_N
  *    (kept inside the model in block storage).  mode: LRBMS_DIRECT / _FIT / AFFINE. */

@@ -541,6 +541,196 @@ static void local_gram_schmidt(const Model& M, int nsnap, const double* snaps, i
   }
 }
 
+// Device array owned by a host scope.
+struct DevArray {
+  double* p = nullptr;
+  bool alloc(size_t n) {
+    return hip_ok(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(double)), "hipMalloc");
+  }
+  ~DevArray() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Read and clear the device status word of a scratch model.
+static int take_status(Model& M) {
+  int st = 0;
+  if (!hip_ok(hipMemcpy(&st, M.d_status, sizeof(int), hipMemcpyDeviceToHost), "status")) return LRBMS_E_HIP;
+  if (st && !hip_ok(hipMemset(M.d_status, 0, sizeof(int)), "status")) return LRBMS_E_HIP;
+  return st;
+}
+
+static int fine_solve_checked(Model& M, const double* d_field, int kind, double rtol, int maxit,
+                              double* d_p, int* iters, double* relres) {
+  int rc = fine_solve(M.g, M.d_mom, d_field, kind, rtol, maxit, d_p, M.d_status, iters, relres);
+  const int st = take_status(M);
+  if (st < 0 && (rc == LRBMS_OK || rc == LRBMS_E_STATE)) rc = st;
+  switch (rc) {
+    case LRBMS_OK: break;
+    case LRBMS_E_STATE: set_error("fine pressure: CG did not reach rtol within maxit"); break;
+    case LRBMS_E_NOT_SPD: set_error("fine pressure: singular cell block or non-positive curvature"); break;
+    case LRBMS_E_NONFINITE: set_error("fine pressure: non-finite residual"); break;
+    case LRBMS_E_OOM: set_error("fine pressure: device allocation failed"); break;
+    default: set_error("fine pressure: HIP error"); break;
+  }
+  return rc;
+}
+
+static int tof_checked(Model& M, const double* d_flux, double tol, int maxit, double* d_tau,
+                       int* sweeps) {
+  int rc = tof_solve(M.g, d_flux, tol, maxit, d_tau, M.d_status, sweeps);
+  const int st = take_status(M);
+  if (st < 0 && (rc == LRBMS_OK || rc == LRBMS_E_STATE)) rc = st;
+  switch (rc) {
+    case LRBMS_OK: break;
+    case LRBMS_E_STATE: set_error("time of flight: sweeps did not converge within maxit"); break;
+    case LRBMS_E_NOT_SPD: set_error("time of flight: singular cell block (a cell without flux)"); break;
+    case LRBMS_E_NONFINITE: set_error("time of flight: non-finite values"); break;
+    case LRBMS_E_OOM: set_error("time of flight: device allocation failed"); break;
+    default: set_error("time of flight: HIP error"); break;
+  }
+  return rc;
+}
+
+static double host_total_mobility(const lrbms_problem* p, double s) {
+  const double sc = std::min(std::max(s, 0.0), 1.0);
+  const double krw = p->relperm == 0 ? sc : std::pow(sc, p->corey_w);
+  const double kro = p->relperm == 0 ? 1.0 - sc : std::pow(1.0 - sc, p->corey_o);
+  return krw / p->visc_w + kro / p->visc_o;
+}
+
+// Mobility profiles of Alg. 2 step 1c as P1 fields (mean coefficient only):
+// lambda(0) for q = 1, lambda(1) for q = M, and in between lambda(0) on the
+// cells whose mean time of flight exceeds (q-1) T/(M-2), lambda(1) elsewhere.
+static void mobility_profiles(const Geom& g, const lrbms_problem* p, const std::vector<double>& tau,
+                              int nq, double T, std::vector<double>& prof) {
+  const size_t L = (size_t)g.r * g.ncell;
+  const double sv = std::sqrt(g.vol);
+  const double l0 = host_total_mobility(p, 0.0), l1 = host_total_mobility(p, 1.0);
+  prof.assign((size_t)nq * L, 0.0);
+  for (int q = 1; q <= nq; ++q) {
+    double* f = prof.data() + (size_t)(q - 1) * L;
+    const double thr = (double)(q - 1) * T / (double)(nq - 2);
+    for (int c = 0; c < g.ncell; ++c) {
+      double v;
+      if (q == 1) v = l0;
+      else if (q == nq) v = l1;
+      else v = (tau[c] / sv > thr) ? l0 : l1;
+      f[c] = v * sv;
+    }
+  }
+}
+
+// Indices of the profiles that are linearly independent of the ones before
+// them: two-pass Gram-Schmidt in q order, dropped when the remaining norm is
+// <= 1e-12 of the profile's own norm.
+static std::vector<int> independent_profiles(const std::vector<double>& prof, int nq, size_t L) {
+  std::vector<int> keep;
+  std::vector<std::vector<double>> Q;
+  for (int q = 0; q < nq; ++q) {
+    std::vector<double> w(prof.begin() + (size_t)q * L, prof.begin() + (size_t)(q + 1) * L);
+    double nv = 0.0;
+    for (double x : w) nv += x * x;
+    nv = std::sqrt(nv);
+    if (nv == 0.0) continue;
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& b : Q) {
+        double d = 0.0;
+        for (size_t i = 0; i < L; ++i) d += b[i] * w[i];
+        for (size_t i = 0; i < L; ++i) w[i] -= d * b[i];
+      }
+    double nw = 0.0;
+    for (double x : w) nw += x * x;
+    nw = std::sqrt(nw);
+    if (nw <= 1e-12 * nv) continue;
+    for (auto& x : w) x /= nw;
+    Q.push_back(std::move(w));
+    keep.push_back(q);
+  }
+  return keep;
+}
+
+static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* o,
+                              const double* mu, lrbms_model** out, lrbms_offline_report* rep) {
+  if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
+  *out = nullptr;
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if (!o || !mu) return (set_error("options or training parameters missing"), LRBMS_E_ARG);
+  if (o->M < 3 || o->M > kMaxProfiles) return (set_error("M must be in 3..64"), LRBMS_E_ARG);
+  if (o->n_train < 1) return (set_error("n_train must be >= 1"), LRBMS_E_ARG);
+  if (o->ne_cap < 1 || o->ne_cap > 63) return (set_error("ne_cap must be in 1..63"), LRBMS_E_ARG);
+  if (!(o->horizon > 0.0)) return (set_error("horizon must be > 0"), LRBMS_E_ARG);
+  if (!(o->pcg_rtol > 0.0) || o->pcg_maxit < 1 || !(o->tof_tol >= 0.0) || o->tof_maxit < 1)
+    return (set_error("invalid solver tolerances or iteration limits"), LRBMS_E_ARG);
+  for (long long i = 0; i < (long long)o->n_train * o->M; ++i)
+    if (!std::isfinite(mu[i])) return (set_error("training parameters must be finite"), LRBMS_E_ARG);
+  lrbms_offline_report R{};
+  Model tmp;
+  setup_layout(tmp, p, nullptr);
+  if ((rc = upload_problem(tmp, p))) return rc;
+  const Geom& g = tmp.g;
+  const size_t L = (size_t)g.r * g.ncell;
+  auto note = [&](int it, double rr) {
+    R.n_solves += 1;
+    R.pcg_iters_max = std::max(R.pcg_iters_max, it);
+    R.pcg_iters_total += it;
+    R.pcg_relres_max = std::max(R.pcg_relres_max, rr);
+  };
+  // Alg. 2 step 1a-1b: pressure and velocity at s = 0, time of flight
+  DevArray flux, tau, field, snap;
+  if (!flux.alloc(g.nface) || !tau.alloc(L) || !field.alloc(L) || !snap.alloc(L)) return LRBMS_E_OOM;
+  int it = 0;
+  double rr = 0.0;
+  rc = fine_solve_checked(tmp, tmp.d_scratch_sat, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit,
+                          tmp.d_scratch_ph, &it, &rr);
+  note(it, rr);
+  if (rc) return rc;
+  if (!hip_ok(launch_flux(g, tmp.d_scratch_ph, tmp.d_scratch_sat, flux.p, 0), "initial flux"))
+    return LRBMS_E_HIP;
+  if ((rc = tof_checked(tmp, flux.p, o->tof_tol, o->tof_maxit, tau.p, &R.tof_sweeps))) return rc;
+  std::vector<double> h_tau(L);
+  if (!hip_ok(hipMemcpy(h_tau.data(), tau.p, L * sizeof(double), hipMemcpyDeviceToHost), "tau"))
+    return LRBMS_E_HIP;
+  // Alg. 2 step 1c: profiles
+  std::vector<double> prof;
+  mobility_profiles(g, p, h_tau, o->M, o->horizon, prof);
+  // snapshots at gamma = sum_q mu_q Lambda^q
+  std::vector<double> snaps((size_t)o->n_train * L), gam(L);
+  for (int i = 0; i < o->n_train; ++i) {
+    std::fill(gam.begin(), gam.end(), 0.0);
+    for (int q = 0; q < o->M; ++q) {
+      const double m = mu[(size_t)i * o->M + q];
+      const double* f = prof.data() + (size_t)q * L;
+      for (size_t k = 0; k < L; ++k) gam[k] += m * f[k];
+    }
+    if (!hip_ok(hipMemcpy(field.p, gam.data(), L * sizeof(double), hipMemcpyHostToDevice), "gamma"))
+      return LRBMS_E_HIP;
+    rc = fine_solve_checked(tmp, field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit, snap.p, &it, &rr);
+    note(it, rr);
+    if (rc) return rc;
+    if (!hip_ok(hipMemcpy(snaps.data() + (size_t)i * L, snap.p, L * sizeof(double),
+                          hipMemcpyDeviceToHost),
+                "snapshot"))
+      return LRBMS_E_HIP;
+  }
+  // Alg. 2 step 2e: local bases
+  std::vector<int> sizes;
+  std::vector<double> basis;
+  local_gram_schmidt(tmp, o->n_train, snaps.data(), o->ne_cap, o->unit_functions != 0, sizes, basis);
+  for (int s : sizes)
+    if (s < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
+  std::vector<double> kept;
+  if (o->keep_profiles) {
+    for (int q : independent_profiles(prof, o->M, L))
+      kept.insert(kept.end(), prof.begin() + (size_t)q * L, prof.begin() + (size_t)(q + 1) * L);
+  }
+  R.n_profiles_kept = (int)(kept.size() / L);
+  if (rep) *rep = R;
+  return model_create_impl(p, sizes.data(), basis.data(), R.n_profiles_kept,
+                           kept.empty() ? nullptr : kept.data(), out);
+}
+
 }  // namespace lrbms
 
 using namespace lrbms;
@@ -859,12 +1049,70 @@ int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_siz
 }
 
 int lrbms_build_offline_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
-                              lrbms_model** out) {
-  (void)prob;
-  (void)opts;
-  if (out) *out = nullptr;
-  set_error("lrbms_build_offline_bases: not available in this build");
-  return LRBMS_E_STATE;
+                              const double* mu, lrbms_model** out, lrbms_offline_report* report) {
+  try {
+    return build_offline_impl(prob, opts, mu, out, report);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_t kind,
+                        double rtol, int32_t maxit, double* d_p, int32_t* iterations,
+                        double* relres) {
+  try {
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (!d_field || !d_p) return (set_error("NULL device pointer"), LRBMS_E_ARG);
+    if (kind != LRBMS_FIELD_SATURATION && kind != LRBMS_FIELD_MOBILITY)
+      return (set_error("kind must be LRBMS_FIELD_SATURATION or LRBMS_FIELD_MOBILITY"), LRBMS_E_ARG);
+    if (!(rtol > 0.0) || maxit < 1) return (set_error("rtol must be > 0 and maxit >= 1"), LRBMS_E_ARG);
+    Model tmp;
+    setup_layout(tmp, prob, nullptr);
+    if ((rc = upload_problem(tmp, prob))) return rc;
+    int it = 0;
+    double rr = 0.0;
+    rc = fine_solve_checked(tmp, d_field, kind == LRBMS_FIELD_SATURATION ? GAMMA_SAT : GAMMA_FIELD,
+                            rtol, maxit, d_p, &it, &rr);
+    if (iterations) *iterations = it;
+    if (relres) *relres = rr;
+    return rc;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double tol,
+                         int32_t maxit, double* d_tau, int32_t* sweeps) {
+  try {
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    if (!d_flux || !d_tau) return (set_error("NULL device pointer"), LRBMS_E_ARG);
+    if (!(tol >= 0.0) || maxit < 1) return (set_error("tol must be >= 0 and maxit >= 1"), LRBMS_E_ARG);
+    Model tmp;
+    setup_layout(tmp, prob, nullptr);
+    if ((rc = upload_problem(tmp, prob))) return rc;
+    int sw = 0;
+    rc = tof_checked(tmp, d_flux, tol, maxit, d_tau, &sw);
+    if (sweeps) *sweeps = sw;
+    return rc;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_model_export_profiles(const lrbms_model* m, double* profiles) {
+  if (!m || !profiles) return (set_error("NULL argument"), LRBMS_E_ARG);
+  const Model* M = M_(m);
+  if (M->nprof == 0) return LRBMS_OK;
+  const size_t n = (size_t)M->nprof * M->g.r * M->g.ncell;
+  return hip_ok(hipMemcpy(profiles, M->d_prof, n * sizeof(double), hipMemcpyDeviceToHost),
+                "export profiles")
+             ? LRBMS_OK
+             : LRBMS_E_HIP;
 }
 
 }  // extern "C"

@@ -54,6 +54,21 @@ class ModelInfo_C(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class OfflineOpts_C(C.Structure):
+    _fields_ = [("M", C.c_int32), ("n_train", C.c_int32), ("ne_cap", C.c_int32),
+                ("unit_functions", C.c_int32), ("horizon", C.c_double), ("pcg_rtol", C.c_double),
+                ("pcg_maxit", C.c_int32), ("tof_tol", C.c_double), ("tof_maxit", C.c_int32),
+                ("keep_profiles", C.c_int32)]
+
+
+class OfflineReport_C(C.Structure):
+    _fields_ = [("n_solves", C.c_int32), ("pcg_iters_max", C.c_int32),
+                ("pcg_iters_total", C.c_int64), ("pcg_relres_max", C.c_double),
+                ("tof_sweeps", C.c_int32), ("n_profiles_kept", C.c_int32)]
+
+
+FIELD_SATURATION, FIELD_MOBILITY = 0, 1
+
 _lib = None
 
 
@@ -83,6 +98,11 @@ def lib():
         L.lrbms_model_status.argtypes = [vp]
         L.lrbms_profile_enable.argtypes = [vp, i32]
         L.lrbms_profile_read.argtypes = [vp, vp, i32, C.POINTER(i32)]
+        L.lrbms_build_offline_bases.argtypes = [vp, vp, vp, C.POINTER(vp), vp]
+        L.lrbms_fine_pressure.argtypes = [vp, vp, i32, dbl, i32, vp, C.POINTER(i32),
+                                          C.POINTER(dbl)]
+        L.lrbms_time_of_flight.argtypes = [vp, vp, dbl, i32, vp, C.POINTER(i32)]
+        L.lrbms_model_export_profiles.argtypes = [vp, vp]
         L.lrbms_model_destroy.argtypes = [vp]
         L.lrbms_model_destroy.restype = None
         _lib = L
@@ -191,6 +211,32 @@ class Model:
             0 if prof is None else prof.shape[0], _ptr(prof), C.byref(h)))
         return cls(h, prob)
 
+    @classmethod
+    def build_offline(cls, prob, mu, ne_cap: int, horizon: float, unit_functions=True,
+                      keep_profiles=True, pcg_rtol=1e-13, pcg_maxit=200000, tof_tol=1e-14,
+                      tof_maxit=100000):
+        """Offline stage on the device (lrbms_build_offline_bases); mu is the
+        (n_train, M) array of training parameters.  Returns (model, report)."""
+        pc = ProblemC(prob)
+        mu = np.ascontiguousarray(np.atleast_2d(mu), dtype=np.float64)
+        o = OfflineOpts_C(M=mu.shape[1], n_train=mu.shape[0], ne_cap=int(ne_cap),
+                          unit_functions=int(bool(unit_functions)), horizon=float(horizon),
+                          pcg_rtol=float(pcg_rtol), pcg_maxit=int(pcg_maxit),
+                          tof_tol=float(tof_tol), tof_maxit=int(tof_maxit),
+                          keep_profiles=int(bool(keep_profiles)))
+        rep = OfflineReport_C()
+        h = C.c_void_p()
+        _check(lib().lrbms_build_offline_bases(pc.ref(), C.byref(o), _ptr(mu), C.byref(h),
+                                               C.byref(rep)))
+        m = cls(h, prob)
+        m._sizes = None
+        return m, {f: getattr(rep, f) for f, _ in OfflineReport_C._fields_}
+
+    def export_profiles(self) -> np.ndarray:
+        out = np.empty((self.info["n_profiles"], self.info["r"] * self.info["ncell"]))
+        _check(lib().lrbms_model_export_profiles(self._h, _ptr(out)))
+        return out
+
     def close(self):
         if self._h:
             lib().lrbms_model_destroy(self._h)
@@ -236,11 +282,7 @@ class Model:
         return ax, lo, hi
 
     def export_basis(self):
-        sizes = np.empty(self.info["n_sub"], dtype=np.int32)
-        total = 0
-        # the exported length follows from the sizes; query them first
-        tmp = np.empty(1)
-        basis = None
+        """(sizes, basis) as given to lrbms_model_create."""
         cuts = [np.asarray(c) for c in self.prob.cuts]
         ncells = []
         for ez in range(len(cuts[2]) - 1 if self.prob.dim == 3 else 1):
@@ -248,11 +290,10 @@ class Model:
                 for ex in range(len(cuts[0]) - 1):
                     nz = (cuts[2][ez + 1] - cuts[2][ez]) if self.prob.dim == 3 else 1
                     ncells.append((cuts[0][ex + 1] - cuts[0][ex]) * (cuts[1][ey + 1] - cuts[1][ey]) * nz)
-        # upper bound: 63 functions per box
-        basis = np.empty(sum(63 * self.info["r"] * n for n in ncells))
+        sizes = np.empty(self.info["n_sub"], dtype=np.int32)
+        basis = np.empty(sum(63 * self.info["r"] * n for n in ncells))   # at most 63 per box
         _check(lib().lrbms_model_export_basis(self._h, _ptr(sizes), _ptr(basis)))
-        total = sum(int(s) * self.info["r"] * n for s, n in zip(sizes, ncells))
-        del tmp
+        total = sum(int(k) * self.info["r"] * n for k, n in zip(sizes, ncells))
         return sizes, basis[:total].copy()
 
     def profile_enable(self, on: bool = True):
@@ -327,6 +368,26 @@ class Model:
             self._sizes, _ = self.export_basis()
             self._offs = np.concatenate([[0], np.cumsum(self._sizes)])
         return self._sizes, self._offs
+
+
+def fine_pressure(prob, field, p_out, kind=FIELD_SATURATION, rtol=1e-13, maxit=200000):
+    """Fine SWIP pressure (lrbms_fine_pressure) into the device buffer p_out;
+    returns (iterations, relative residual)."""
+    pc = ProblemC(prob)
+    it, rr = C.c_int32(0), C.c_double(0.0)
+    _check(lib().lrbms_fine_pressure(pc.ref(), _ptr(field), int(kind), float(rtol), int(maxit),
+                                     _ptr(p_out), C.byref(it), C.byref(rr)))
+    return it.value, rr.value
+
+
+def time_of_flight(prob, flux, tau_out, tol=0.0, maxit=100000):
+    """Time of flight (lrbms_time_of_flight) into the device buffer tau_out;
+    returns the number of sweeps."""
+    pc = ProblemC(prob)
+    sw = C.c_int32(0)
+    _check(lib().lrbms_time_of_flight(pc.ref(), _ptr(flux), float(tol), int(maxit), _ptr(tau_out),
+                                      C.byref(sw)))
+    return sw.value
 
 
 def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:

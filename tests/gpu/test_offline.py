@@ -1,0 +1,216 @@
+"""Offline stage on the GPU against the oracle: fine SWIP pressure solves
+(Def. pressureDG), the time of flight (eq. timeOfFlight) and the whole of
+Alg. 2 without the greedy selection (profiles of step 1c, snapshots, local
+Gram-Schmidt of step 2e), all called through the C ABI.
+
+The fine solves are iterative (conjugate gradients to a relative residual
+rtol), the oracle's are direct, so the bound on the pressure difference is
+the one the residual gives: |p - p*| / |p*| <= kappa_2(A) |l - A p| / |l|,
+with the residual of the GPU result taken under the oracle's own operator
+(so a wrong GPU operator shows up as a large residual, not as a loose bound).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synth import make_problem, random_saturation, training_params
+from oracle.fem import Grid
+from oracle.offline import (build_offline, initial_flow, mobility_profiles, subdomain_cells,
+                            training_mobility)
+from oracle.pressure import Mobility, fine_operator
+from oracle.tof import cell_means, time_of_flight
+
+from .helpers import dev, host, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-13
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1405_2810_amd import lrbms
+    return lrbms
+
+
+def _kappa(A):
+    """2-norm condition number of the SPD sparse matrix A."""
+    from scipy.sparse.linalg import eigsh
+    A = A.tocsc()
+    lmax = eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = eigsh(A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    return float(lmax / lmin)
+
+
+def _check_fine(p, g, gam, p_gpu, iters, relres, label):
+    A, l = fine_operator(g, p, gam)
+    from oracle.pressure import solve_spd
+    p_ref = solve_spd(A, l)
+    true_res = np.linalg.norm(l - A @ p_gpu) / np.linalg.norm(l)
+    # the residual that fp64 evaluation can resolve: that of the direct solution
+    floor = np.linalg.norm(l - A @ p_ref) / np.linalg.norm(l)
+    kap = _kappa(A)
+    err = rel_l2(p_gpu, p_ref)
+    log(f"{label}: iters={iters} relres={relres:.2e} true_res={true_res:.2e} "
+        f"floor={floor:.2e} kappa={kap:.2e} err={err:.2e}")
+    assert relres <= RTOL
+    # the CG recursion residual drifts from the true one by rounding that grows
+    # with the iteration count (about eps |A| |p| per step): a wrong operator
+    # would leave a residual of the size of the operator error instead
+    assert true_res <= 10 * RTOL + (10 + iters / 10) * floor
+    assert err <= max(1e-12, 2.0 * kap * true_res)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
+def test_fine_pressure_from_saturation(L, name):
+    p = make_problem(name)
+    g = Grid(p)
+    s = random_saturation(p, np.random.default_rng(101))
+    out = dev(np.zeros(g.r * g.ncell))
+    iters, relres = L.fine_pressure(p, dev(s), out, kind=L.FIELD_SATURATION, rtol=RTOL)
+    _check_fine(p, g, Mobility(g, p, s=s), host(out), iters, relres, f"{name} sat")
+
+
+@pytest.mark.parametrize("name", ["small2d", "small3d"])
+def test_fine_pressure_from_mobility_field(L, name):
+    """A training mobility of Alg. 2 (a mix of time-of-flight profiles)."""
+    p = make_problem(name)
+    g = Grid(p)
+    _, F0 = initial_flow(g, p)
+    tau = time_of_flight(g, p, F0)
+    prof = mobility_profiles(g, p, tau, p.M, p.t_end)
+    mu = training_params(p.M, p.M + 1, np.random.default_rng(5))[-1]
+    fld = training_mobility(prof, mu)
+    out = dev(np.zeros(g.r * g.ncell))
+    iters, relres = L.fine_pressure(p, dev(fld), out, kind=L.FIELD_MOBILITY, rtol=RTOL)
+    _check_fine(p, g, Mobility(g, p, field=fld), host(out), iters, relres, f"{name} field")
+
+
+def test_fine_pressure_iteration_limit(L):
+    p = make_problem("small2d")
+    g = Grid(p)
+    out = dev(np.zeros(g.r * g.ncell))
+    with pytest.raises(L.LrbmsError) as ei:
+        L.fine_pressure(p, dev(np.zeros(g.r * g.ncell)), out, rtol=RTOL, maxit=3)
+    assert ei.value.code == -2 and "maxit" in str(ei.value)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
+def test_time_of_flight(L, name):
+    p = make_problem(name)
+    g = Grid(p)
+    _, F0 = initial_flow(g, p)
+    tau_ref = time_of_flight(g, p, F0)
+    out = dev(np.zeros(g.r * g.ncell))
+    sweeps = L.time_of_flight(p, dev(F0), out, tol=0.0)
+    tau = host(out)
+    err = rel_l2(tau, tau_ref)
+    mean_err = rel_l2(cell_means(g, tau), cell_means(g, tau_ref))
+    log(f"{name}: sweeps={sweeps} tau err={err:.2e} mean err={mean_err:.2e}")
+    assert err <= 1e-10
+    assert np.all(cell_means(g, tau) > 0.0)
+
+
+def test_time_of_flight_without_flow(L):
+    """A cell with no flux at all has a singular block: reported, not faulted."""
+    p = make_problem("tiny2d")
+    g = Grid(p)
+    out = dev(np.zeros(g.r * g.ncell))
+    with pytest.raises(L.LrbmsError) as ei:
+        L.time_of_flight(p, dev(np.zeros(g.nface)), out)
+    assert ei.value.code == -5
+
+
+def _sequential_independent(profiles, rtol=1e-12):
+    """Profiles independent of the ones before them (two-pass Gram-Schmidt)."""
+    Q, keep = [], []
+    for q, v in enumerate(profiles):
+        nv = np.linalg.norm(v)
+        if nv == 0.0:
+            continue
+        w = v.copy()
+        for _ in range(2):
+            for b in Q:
+                w = w - (b @ w) * b
+        if np.linalg.norm(w) <= rtol * nv:
+            continue
+        Q.append(w / np.linalg.norm(w))
+        keep.append(q)
+    return keep
+
+
+def _processed(g, snaps, cells, cap):
+    """Number of snapshots the local Gram-Schmidt of a box looks at before its
+    basis reaches the cap (1_E first)."""
+    r = g.r
+    B = [np.concatenate([np.full(len(cells), 1.0), np.zeros((r - 1) * len(cells))])]
+    B[0] = B[0] / np.linalg.norm(B[0])
+    for i, s in enumerate(snaps):
+        if len(B) >= cap:
+            return i
+        v = np.concatenate([s[k * g.ncell + cells] for k in range(r)])
+        nv = np.linalg.norm(v)
+        w = v.copy()
+        for _ in range(2):
+            for b in B:
+                w = w - (b @ w) * b
+        nw = np.linalg.norm(w)
+        if nv > 0.0 and nw > 1e-8 * nv:
+            B.append(w / nw)
+    return len(snaps)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
+def test_build_offline_bases(L, name):
+    p = make_problem(name)
+    g = Grid(p)
+    params = training_params(p.M, p.n_train, np.random.default_rng(p.seed))
+    ref = build_offline(g, p, params)
+    T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
+    m, rep = L.Model.build_offline(p, params, ne_cap=p.ne_cap, horizon=T, pcg_rtol=RTOL)
+    log(f"{name}: report {rep}")
+    assert rep["n_solves"] == 1 + len(params)
+    assert rep["pcg_relres_max"] <= RTOL
+    # profiles: same fields unless a cell mean of tau sits at a threshold
+    tb = cell_means(g, ref["tau"])
+    thr = np.array([(q - 1) * T / (p.M - 2) for q in range(2, p.M)])
+    near = np.min(np.abs(tb[:, None] - thr[None, :]), axis=1) <= 1e-9 * T
+    log(f"{name}: {int(near.sum())} threshold-adjacent cells")
+    keep = _sequential_independent(ref["profiles"])
+    prof = m.export_profiles()
+    assert rep["n_profiles_kept"] == len(keep) == prof.shape[0] == len(ref["keep"])
+    for j, q in enumerate(keep):
+        a, b = prof[j][:g.ncell], ref["profiles"][q][:g.ncell]
+        assert np.array_equal(a[~near], b[~near]), f"profile {q}"
+        assert not np.any(prof[j][g.ncell:])
+    # snapshot error bound: kappa of the training operators times the residual
+    eps = 0.0
+    for mu, sn in zip(params, ref["snapshots"]):
+        A, l = fine_operator(g, p, Mobility(g, p, field=training_mobility(ref["profiles"], mu)))
+        floor = np.linalg.norm(l - A @ sn) / np.linalg.norm(l)
+        eps = max(eps, 10.0 * _kappa(A) * (RTOL + floor))
+    log(f"{name}: snapshot error bound {eps:.2e}")
+    # local bases: same sizes, orthonormal, 1_E first, and every snapshot the
+    # box looked at lies in the span up to the rejection threshold and the
+    # snapshot error: |(I - P_E) s_E| <= 1e-8 |s_E| + eps |s|
+    sizes, flat = m.export_basis()
+    ref_phis = ref["basis"].phis
+    assert list(sizes) == [ph.shape[0] for ph in ref_phis]
+    off = 0
+    worst = 0.0
+    for E, (cells, phi_ref) in enumerate(zip(subdomain_cells(g, p), ref_phis)):
+        NE, r, nE = phi_ref.shape
+        phi = flat[off:off + NE * r * nE].reshape(NE, r * nE)
+        off += NE * r * nE
+        assert np.abs(phi @ phi.T - np.eye(NE)).max() <= 1e-12
+        unit = np.zeros(r * nE)
+        unit[:nE] = 1.0 / math.sqrt(nE)
+        assert np.abs(phi[0] - unit).max() <= 1e-15
+        for sn in ref["snapshots"][:_processed(g, ref["snapshots"], cells, p.ne_cap)]:
+            v = np.concatenate([sn[k * g.ncell + cells] for k in range(r)])
+            res = np.linalg.norm(v - phi.T @ (phi @ v))
+            bound = 1.01e-8 * np.linalg.norm(v) + eps * np.linalg.norm(sn)
+            worst = max(worst, res / np.linalg.norm(sn))
+            assert res <= bound, (E, res, bound)
+    log(f"{name}: largest |(I-P_E) s_E| / |s| = {worst:.2e} (eps {eps:.1e})")

@@ -39,3 +39,44 @@ def test_null_out_pointer(L):
     lib = L.lib()
     assert lib.lrbms_model_create(None, None, None, 0, None, None) == -1
     assert b"NULL" in lib.lrbms_last_error()
+
+
+def test_offline_arguments_checked_before_device_work(L):
+    p = make_problem("tiny2d")
+    mu = np.eye(4)
+    cases = [dict(mu=np.eye(2), ne_cap=4, horizon=1.0),          # M < 3
+             dict(mu=mu, ne_cap=0, horizon=1.0),                 # cap
+             dict(mu=mu, ne_cap=64, horizon=1.0),
+             dict(mu=mu, ne_cap=4, horizon=0.0),                 # horizon
+             dict(mu=mu, ne_cap=4, horizon=1.0, pcg_rtol=0.0),
+             dict(mu=mu, ne_cap=4, horizon=1.0, tof_maxit=0),
+             dict(mu=np.full((2, 4), np.nan), ne_cap=4, horizon=1.0)]
+    for kw in cases:
+        with pytest.raises(L.LrbmsError) as ei:
+            L.Model.build_offline(p, **kw)
+        assert ei.value.code == -1, kw
+    lib = L.lib()
+    pc = L.ProblemC(p)
+    opts = L.OfflineOpts_C(M=4, n_train=4, ne_cap=4, unit_functions=1, horizon=1.0,
+                           pcg_rtol=1e-12, pcg_maxit=10, tof_tol=0.0, tof_maxit=10,
+                           keep_profiles=1)
+    h = C.c_void_p()
+    assert lib.lrbms_build_offline_bases(pc.ref(), C.byref(opts), None, C.byref(h), None) == -1
+
+
+def test_fine_solver_arguments_checked_before_device_work(L):
+    p = make_problem("tiny2d")
+    with pytest.raises(L.LrbmsError) as ei:
+        L.fine_pressure(p, None, None)
+    assert ei.value.code == -1
+    buf = np.zeros(3 * 64)   # any non-NULL address: rejected before use
+    for kw in (dict(kind=2), dict(rtol=0.0), dict(maxit=0)):
+        with pytest.raises(L.LrbmsError) as ei:
+            L.fine_pressure(p, buf, buf, **kw)
+        assert ei.value.code == -1, kw
+    with pytest.raises(L.LrbmsError) as ei:
+        L.time_of_flight(p, buf, buf, tol=-1.0)
+    assert ei.value.code == -1
+    with pytest.raises(L.LrbmsError) as ei:
+        L.time_of_flight(p, None, buf)
+    assert ei.value.code == -1
