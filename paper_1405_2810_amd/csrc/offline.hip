@@ -17,31 +17,26 @@ namespace lrbms {
 
 constexpr int kBlk = 256;
 
-// Sum over the workgroup in a fixed order (every thread gets the result).
+// Sum / maximum over the workgroup in a fixed order (every thread gets the
+// result): butterfly within each wave, then the four wave results in order.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
   __syncthreads();
-  for (int s = kBlk / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double out = red[0];
+  if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
-  return out;
+  return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __device__ __forceinline__ double block_max(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6;
   __syncthreads();
-  for (int s = kBlk / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  const double out = red[0];
+  if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
-  return out;
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // Neighbour of cell x across face f = 2a + dir, or -1 outside the grid.
@@ -165,141 +160,146 @@ __global__ __launch_bounds__(kBlk) void k_fine_jacobi(Geom g, const double* __re
     for (int j = 0; j < R; ++j) Dinv[(size_t)(i * R + j) * nc + c] = inv[i][j];
 }
 
-// y = A x (one cell per thread) and the block partial of p . y.
-template <int D>
-__global__ __launch_bounds__(kBlk) void k_fine_apply(Geom g, const double* __restrict__ K,
-                                                     const double* __restrict__ x,
-                                                     double* __restrict__ y,
-                                                     double* __restrict__ partial) {
-  constexpr int R = D + 1;
-  __shared__ double red[kBlk];
-  const int nc = g.ncell;
-  const int c = blockIdx.x * kBlk + threadIdx.x;
-  double dot = 0.0;
-  if (c < nc) {
-    int xc[3];
-    cell_coords(g, c, xc);
-    double v[1 + 2 * D][R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) v[0][k] = x[(size_t)k * nc + c];
-#pragma unroll
-    for (int f = 0; f < 2 * D; ++f) {
-      const int n = face_neighbour(g, xc, f);
-#pragma unroll
-      for (int k = 0; k < R; ++k) v[1 + f][k] = (n >= 0) ? x[(size_t)k * nc + n] : 0.0;
-    }
-    double Y[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int f = 0; f < 1 + 2 * D; ++f)
-#pragma unroll
-        for (int kp = 0; kp < R; ++kp) s = fma(K[(size_t)((f * R + k) * R + kp) * nc + c], v[f][kp], s);
-      Y[k] = s;
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      y[(size_t)k * nc + c] = Y[k];
-      dot = fma(v[0][k], Y[k], dot);
-    }
-  }
-  const double b = block_sum(dot, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = b;
-}
+// ---- preconditioned conjugate gradients, two launches per iteration ----------
+// The scalars never leave the device: every workgroup sums the per-workgroup
+// partials of the previous launch itself, in the same fixed order, so all
+// workgroups see identical alpha and beta.  Ap is carried by the recursion
+// A p_new = A z + beta A p_old, so one operator application per iteration
+// serves both the search direction and the curvature p . Ap.  The grid is
+// capped (grid-stride loops) to bound the partial sums.
+constexpr int kCgMaxBlocks = 1024;
 
-// PCG scalars on the device.
-enum { PCG_RZ = 0, PCG_ALPHA, PCG_BETA, PCG_RR, PCG_BB, PCG_FAIL, PCG_NSCAL };
-
-// Sum of n partials in a fixed order.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* red) {
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kBlk) s += p[i];
   return block_sum(s, red);
 }
 
+// Apply the cell's r x r blocks to v (own and face neighbours' coefficients).
 template <int D>
-__global__ __launch_bounds__(kBlk) void k_pcg_init(Geom g, const double* __restrict__ b,
-                                                   const double* __restrict__ Dinv,
-                                                   double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ z, double* __restrict__ p,
-                                                   double* __restrict__ part_rz,
-                                                   double* __restrict__ part_rr) {
+__device__ __forceinline__ void stencil_apply(const Geom& g, const double* __restrict__ K,
+                                              const double* __restrict__ v, int c,
+                                              double (&y)[D + 1]) {
   constexpr int R = D + 1;
-  __shared__ double red[kBlk];
   const int nc = g.ncell;
-  const int c = blockIdx.x * kBlk + threadIdx.x;
+  int xc[3];
+  cell_coords(g, c, xc);
+  double u[1 + 2 * D][R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) u[0][k] = v[(size_t)k * nc + c];
+#pragma unroll
+  for (int f = 0; f < 2 * D; ++f) {
+    const int n = face_neighbour(g, xc, f);
+#pragma unroll
+    for (int k = 0; k < R; ++k) u[1 + f][k] = (n >= 0) ? v[(size_t)k * nc + n] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int f = 0; f < 1 + 2 * D; ++f)
+#pragma unroll
+      for (int kp = 0; kp < R; ++kp) s = fma(K[(size_t)((f * R + k) * R + kp) * nc + c], u[f][kp], s);
+    y[k] = s;
+  }
+}
+
+// x = 0, r = b, z = D^-1 b; partials of r.z and r.r.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_cg_init(Geom g, const double* __restrict__ b,
+                                                  const double* __restrict__ Dinv,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ z,
+                                                  double* __restrict__ part_rz,
+                                                  double* __restrict__ part_rr) {
+  constexpr int R = D + 1;
+  __shared__ double red[4];
+  const int nc = g.ncell;
   double rz = 0.0, rr = 0.0;
-  if (c < nc) {
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
     double rv[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      rv[k] = b[(size_t)k * nc + c];
-      x[(size_t)k * nc + c] = 0.0;
-      r[(size_t)k * nc + c] = rv[k];
-    }
+    for (int k = 0; k < R; ++k) rv[k] = b[(size_t)k * nc + c];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      double s = 0.0;
+      double t = 0.0;
 #pragma unroll
-      for (int j = 0; j < R; ++j) s = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], s);
-      z[(size_t)i * nc + c] = s;
-      p[(size_t)i * nc + c] = s;
-      rz = fma(rv[i], s, rz);
+      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], t);
+      x[(size_t)i * nc + c] = 0.0;
+      r[(size_t)i * nc + c] = rv[i];
+      z[(size_t)i * nc + c] = t;
+      rz = fma(rv[i], t, rz);
       rr = fma(rv[i], rv[i], rr);
     }
   }
   const double a = block_sum(rz, red);
-  const double bsum = block_sum(rr, red);
+  const double bb = block_sum(rr, red);
   if (threadIdx.x == 0) {
     part_rz[blockIdx.x] = a;
-    part_rr[blockIdx.x] = bsum;
+    part_rr[blockIdx.x] = bb;
   }
 }
 
-__global__ __launch_bounds__(kBlk) void k_pcg_init_scalars(const double* __restrict__ part_rz,
-                                                           const double* __restrict__ part_rr,
-                                                           int n, double* __restrict__ sc) {
-  __shared__ double red[kBlk];
-  const double rz = sum_partials(part_rz, n, red);
-  const double rr = sum_partials(part_rr, n, red);
-  if (threadIdx.x == 0) {
-    sc[PCG_RZ] = rz;
-    sc[PCG_RR] = rr;
-    sc[PCG_BB] = rr;
-    sc[PCG_FAIL] = 0.0;
-    sc[PCG_ALPHA] = sc[PCG_BETA] = 0.0;
-  }
-}
-
-__global__ __launch_bounds__(kBlk) void k_pcg_alpha(const double* __restrict__ part_pap, int n,
-                                                    double* __restrict__ sc) {
-  __shared__ double red[kBlk];
-  const double pap = sum_partials(part_pap, n, red);
-  if (threadIdx.x == 0) {
-    const bool ok = pap > 0.0 && isfinite(pap);
-    if (!ok) sc[PCG_FAIL] = 1.0;
-    sc[PCG_ALPHA] = ok ? sc[PCG_RZ] / pap : 0.0;
-  }
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlk) void k_pcg_update1(Geom g, const double* __restrict__ Dinv,
-                                                      double* __restrict__ x,
-                                                      double* __restrict__ r,
-                                                      double* __restrict__ z,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ Ap,
-                                                      const double* __restrict__ sc,
-                                                      double* __restrict__ part_rz,
-                                                      double* __restrict__ part_rr) {
+// beta = (r.z)_new / (r.z)_old (0 on the first iteration); p = z + beta p,
+// Ap = A z + beta Ap; partials of p.Ap.
+template <int D, bool FIRST>
+__global__ __launch_bounds__(kBlk) void k_cg_direction(Geom g, const double* __restrict__ K,
+                                                       const double* __restrict__ z,
+                                                       double* __restrict__ p,
+                                                       double* __restrict__ Ap,
+                                                       const double* __restrict__ rz_new,
+                                                       const double* __restrict__ rz_old,
+                                                       double* __restrict__ part_pap) {
   constexpr int R = D + 1;
-  __shared__ double red[kBlk];
-  const int nc = g.ncell;
-  const int c = blockIdx.x * kBlk + threadIdx.x;
-  const double al = sc[PCG_ALPHA];
-  double rz = 0.0, rr = 0.0;
-  if (c < nc) {
+  __shared__ double red[4];
+  const int nc = g.ncell, nb = gridDim.x;
+  double beta = 0.0;
+  if (!FIRST) {
+    const double num = sum_partials(rz_new, nb, red);
+    const double den = sum_partials(rz_old, nb, red);
+    beta = den != 0.0 ? num / den : 0.0;
+  }
+  double dot = 0.0;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += nb * kBlk) {
+    double w[R];
+    stencil_apply<D>(g, K, z, c, w);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const size_t i = (size_t)k * nc + c;
+      const double pk = FIRST ? z[i] : fma(beta, p[i], z[i]);
+      const double ak = FIRST ? w[k] : fma(beta, Ap[i], w[k]);
+      p[i] = pk;
+      Ap[i] = ak;
+      dot = fma(pk, ak, dot);
+    }
+  }
+  const double t = block_sum(dot, red);
+  if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
+}
+
+// alpha = (r.z) / (p.Ap); x += alpha p, r -= alpha Ap, z = D^-1 r; partials
+// of the new r.z and r.r.  A non-positive or non-finite curvature sets fail.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_cg_update(Geom g, const double* __restrict__ Dinv,
+                                                    double* __restrict__ x, double* __restrict__ r,
+                                                    double* __restrict__ z,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ Ap,
+                                                    const double* __restrict__ rz_cur,
+                                                    const double* __restrict__ part_pap,
+                                                    double* __restrict__ rz_next,
+                                                    double* __restrict__ part_rr,
+                                                    int* __restrict__ fail) {
+  constexpr int R = D + 1;
+  __shared__ double red[4];
+  const int nc = g.ncell, nb = gridDim.x;
+  const double rz = sum_partials(rz_cur, nb, red);
+  const double pap = sum_partials(part_pap, nb, red);
+  const bool ok = pap > 0.0 && isfinite(pap);
+  const double al = ok ? rz / pap : 0.0;
+  if (!ok && blockIdx.x == 0 && threadIdx.x == 0) *fail = 1;
+  double rzn = 0.0, rr = 0.0;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += nb * kBlk) {
     double rv[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -310,41 +310,20 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update1(Geom g, const double* __re
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      double s = 0.0;
+      double t = 0.0;
 #pragma unroll
-      for (int j = 0; j < R; ++j) s = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], s);
-      z[(size_t)i * nc + c] = s;
-      rz = fma(rv[i], s, rz);
+      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], t);
+      z[(size_t)i * nc + c] = t;
+      rzn = fma(rv[i], t, rzn);
       rr = fma(rv[i], rv[i], rr);
     }
   }
-  const double a = block_sum(rz, red);
-  const double bsum = block_sum(rr, red);
+  const double a = block_sum(rzn, red);
+  const double bb = block_sum(rr, red);
   if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = a;
-    part_rr[blockIdx.x] = bsum;
+    rz_next[blockIdx.x] = a;
+    part_rr[blockIdx.x] = bb;
   }
-}
-
-__global__ __launch_bounds__(kBlk) void k_pcg_beta(const double* __restrict__ part_rz,
-                                                   const double* __restrict__ part_rr, int n,
-                                                   double* __restrict__ sc) {
-  __shared__ double red[kBlk];
-  const double rz = sum_partials(part_rz, n, red);
-  const double rr = sum_partials(part_rr, n, red);
-  if (threadIdx.x == 0) {
-    const double old = sc[PCG_RZ];
-    sc[PCG_BETA] = (old != 0.0) ? rz / old : 0.0;
-    sc[PCG_RZ] = rz;
-    sc[PCG_RR] = rr;
-  }
-}
-
-__global__ __launch_bounds__(kBlk) void k_pcg_update2(long long n, const double* __restrict__ z,
-                                                      double* __restrict__ p,
-                                                      const double* __restrict__ sc) {
-  const long long i = blockIdx.x * (long long)kBlk + threadIdx.x;
-  if (i < n) p[i] = fma(sc[PCG_BETA], p[i], z[i]);
 }
 
 // ---- time of flight -----------------------------------------------------------
@@ -493,6 +472,12 @@ struct DevBuf {
 
 static int blocks_for(long long n) { return (int)((n + kBlk - 1) / kBlk); }
 
+static double host_sum(const std::vector<double>& v) {
+  double s = 0.0;
+  for (double x : v) s += x;
+  return s;
+}
+
 template <int D>
 static int fine_solve_t(const Geom& g, double* mom, const double* field, int kind, double rtol,
                         int maxit, double* d_p, int* d_status, int* iters, double* relres) {
@@ -500,44 +485,58 @@ static int fine_solve_t(const Geom& g, double* mom, const double* field, int kin
   const int nc = g.ncell;
   const size_t n = (size_t)R * nc;
   const int nb = blocks_for(nc);
+  const int nbc = std::min(nb, kCgMaxBlocks);
   hipStream_t st = 0;
-  DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, sc;
+  DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, fl;
   if (!K.alloc((size_t)(1 + 2 * D) * R * R * nc) || !Dinv.alloc((size_t)R * R * nc) ||
       !l.alloc(n) || !r.alloc(n) || !z.alloc(n) || !pv.alloc(n) || !Ap.alloc(n) ||
-      !prz.alloc(nb) || !prr.alloc(nb) || !ppap.alloc(nb) || !sc.alloc(PCG_NSCAL))
+      !prz.alloc(2 * (size_t)nbc) || !prr.alloc(nbc) || !ppap.alloc(nbc) || !fl.alloc(1))
     return LRBMS_E_OOM;
+  int* d_fail = reinterpret_cast<int*>(fl.p);
+  if (hipMemset(d_fail, 0, sizeof(int)) != hipSuccess) return LRBMS_E_HIP;
   if (launch_moments(g, field, kind, nullptr, 0, 0, mom, st) != hipSuccess) return LRBMS_E_HIP;
   hipLaunchKernelGGL(k_fine_stencil<D>, dim3(blocks_for((long long)nc * R)), dim3(kBlk), 0, st, g,
                      mom, K.p);
   hipLaunchKernelGGL(k_fine_rhs<D>, dim3(nb), dim3(kBlk), 0, st, g, mom, l.p);
   hipLaunchKernelGGL(k_fine_jacobi<D>, dim3(nb), dim3(kBlk), 0, st, g, K.p, Dinv.p, d_status);
-  hipLaunchKernelGGL(k_pcg_init<D>, dim3(nb), dim3(kBlk), 0, st, g, l.p, Dinv.p, d_p, r.p, z.p,
-                     pv.p, prz.p, prr.p);
-  hipLaunchKernelGGL(k_pcg_init_scalars, dim3(1), dim3(kBlk), 0, st, prz.p, prr.p, nb, sc.p);
+  hipLaunchKernelGGL(k_cg_init<D>, dim3(nbc), dim3(kBlk), 0, st, g, l.p, Dinv.p, d_p, r.p, z.p,
+                     prz.p, prr.p);
+  hipLaunchKernelGGL((k_cg_direction<D, true>), dim3(nbc), dim3(kBlk), 0, st, g, K.p, z.p, pv.p,
+                     Ap.p, prz.p, prz.p, ppap.p);
   if (hipGetLastError() != hipSuccess) return LRBMS_E_HIP;
-  double h[PCG_NSCAL];
+  std::vector<double> h(nbc);
+  if (hipMemcpy(h.data(), prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return LRBMS_E_HIP;
+  const double bb = host_sum(h);
+  double rr = bb;
+  bool conv = !(rr > rtol * rtol * bb);   // zero right-hand side
   int it = 0;
-  bool conv = false;
-  if (hipMemcpy(h, sc.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return LRBMS_E_HIP;
-  conv = !(h[PCG_RR] > rtol * rtol * h[PCG_BB]);   // zero right-hand side
   for (; it < maxit && !conv; ++it) {
-    hipLaunchKernelGGL(k_fine_apply<D>, dim3(nb), dim3(kBlk), 0, st, g, K.p, pv.p, Ap.p, ppap.p);
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kBlk), 0, st, ppap.p, nb, sc.p);
-    hipLaunchKernelGGL(k_pcg_update1<D>, dim3(nb), dim3(kBlk), 0, st, g, Dinv.p, d_p, r.p, z.p,
-                       pv.p, Ap.p, sc.p, prz.p, prr.p);
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kBlk), 0, st, prz.p, prr.p, nb, sc.p);
-    hipLaunchKernelGGL(k_pcg_update2, dim3(blocks_for((long long)n)), dim3(kBlk), 0, st,
-                       (long long)n, z.p, pv.p, sc.p);
-    if ((it + 1) % 20 == 0 || it + 1 == maxit) {
-      if (hipMemcpy(h, sc.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return LRBMS_E_HIP;
-      if (h[PCG_FAIL] != 0.0) return LRBMS_E_NOT_SPD;
-      conv = !(h[PCG_RR] > rtol * rtol * h[PCG_BB]);
+    double* cur = prz.p + (size_t)(it & 1) * nbc;
+    double* nxt = prz.p + (size_t)((it + 1) & 1) * nbc;
+    hipLaunchKernelGGL(k_cg_update<D>, dim3(nbc), dim3(kBlk), 0, st, g, Dinv.p, d_p, r.p, z.p,
+                       pv.p, Ap.p, cur, ppap.p, nxt, prr.p, d_fail);
+    const bool check = (it + 1) % 20 == 0 || it + 1 == maxit;
+    if (check) {
+      int f = 0;
+      if (hipMemcpy(h.data(), prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(&f, d_fail, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return LRBMS_E_HIP;
+      if (f) return LRBMS_E_NOT_SPD;
+      rr = host_sum(h);
+      if (!std::isfinite(rr)) return LRBMS_E_NONFINITE;
+      conv = !(rr > rtol * rtol * bb);
+      if (conv) {
+        ++it;
+        break;
+      }
     }
+    hipLaunchKernelGGL((k_cg_direction<D, false>), dim3(nbc), dim3(kBlk), 0, st, g, K.p, z.p,
+                       pv.p, Ap.p, nxt, cur, ppap.p);
   }
-  if (hipMemcpy(h, sc.p, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return LRBMS_E_HIP;
+  if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) return LRBMS_E_HIP;
   if (iters) *iters = it;
-  if (relres) *relres = h[PCG_BB] > 0.0 ? std::sqrt(h[PCG_RR] / h[PCG_BB]) : 0.0;
-  if (!std::isfinite(h[PCG_RR])) return LRBMS_E_NONFINITE;
+  if (relres) *relres = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
   return conv ? LRBMS_OK : LRBMS_E_STATE;
 }
 
