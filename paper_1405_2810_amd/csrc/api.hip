@@ -560,15 +560,22 @@ static int take_status(Model& M) {
   return st;
 }
 
-static int fine_solve_checked(Model& M, const double* d_field, int kind, double rtol, int maxit,
-                              double* d_p, int* iters, double* relres) {
-  int rc = fine_solve(M.g, M.d_mom, d_field, kind, rtol, maxit, d_p, M.d_status, iters, relres);
+struct FineSolverHandle {
+  FineSolver* s = nullptr;
+  ~FineSolverHandle() {
+    if (s) fine_solver_destroy(s);
+  }
+};
+
+static int fine_solve_checked(Model& M, FineSolver* S, const double* d_field, int kind,
+                              double rtol, int maxit, double* d_p, int* iters, double* relres) {
+  int rc = fine_solver_solve(S, M.d_mom, d_field, kind, rtol, maxit, d_p, M.d_status, iters, relres);
   const int st = take_status(M);
   if (st < 0 && (rc == LRBMS_OK || rc == LRBMS_E_STATE)) rc = st;
   switch (rc) {
     case LRBMS_OK: break;
     case LRBMS_E_STATE: set_error("fine pressure: CG did not reach rtol within maxit"); break;
-    case LRBMS_E_NOT_SPD: set_error("fine pressure: singular cell block or non-positive curvature"); break;
+    case LRBMS_E_NOT_SPD: set_error("fine pressure: singular cell block, non-positive curvature or indefinite preconditioner"); break;
     case LRBMS_E_NONFINITE: set_error("fine pressure: non-finite residual"); break;
     case LRBMS_E_OOM: set_error("fine pressure: device allocation failed"); break;
     default: set_error("fine pressure: HIP error"); break;
@@ -680,9 +687,11 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
   // Alg. 2 step 1a-1b: pressure and velocity at s = 0, time of flight
   DevArray flux, tau, field, snap;
   if (!flux.alloc(g.nface) || !tau.alloc(L) || !field.alloc(L) || !snap.alloc(L)) return LRBMS_E_OOM;
+  FineSolverHandle fs;
+  if (!(fs.s = fine_solver_create(g))) return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
   int it = 0;
   double rr = 0.0;
-  rc = fine_solve_checked(tmp, tmp.d_scratch_sat, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit,
+  rc = fine_solve_checked(tmp, fs.s, tmp.d_scratch_sat, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit,
                           tmp.d_scratch_ph, &it, &rr);
   note(it, rr);
   if (rc) return rc;
@@ -706,7 +715,8 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
     }
     if (!hip_ok(hipMemcpy(field.p, gam.data(), L * sizeof(double), hipMemcpyHostToDevice), "gamma"))
       return LRBMS_E_HIP;
-    rc = fine_solve_checked(tmp, field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit, snap.p, &it, &rr);
+    rc = fine_solve_checked(tmp, fs.s, field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit, snap.p,
+                            &it, &rr);
     note(it, rr);
     if (rc) return rc;
     if (!hip_ok(hipMemcpy(snaps.data() + (size_t)i * L, snap.p, L * sizeof(double),
@@ -1071,10 +1081,14 @@ int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_
     Model tmp;
     setup_layout(tmp, prob, nullptr);
     if ((rc = upload_problem(tmp, prob))) return rc;
+    FineSolverHandle fs;
+    if (!(fs.s = fine_solver_create(tmp.g)))
+      return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
     int it = 0;
     double rr = 0.0;
-    rc = fine_solve_checked(tmp, d_field, kind == LRBMS_FIELD_SATURATION ? GAMMA_SAT : GAMMA_FIELD,
-                            rtol, maxit, d_p, &it, &rr);
+    rc = fine_solve_checked(tmp, fs.s, d_field,
+                            kind == LRBMS_FIELD_SATURATION ? GAMMA_SAT : GAMMA_FIELD, rtol, maxit,
+                            d_p, &it, &rr);
     if (iterations) *iterations = it;
     if (relres) *relres = rr;
     return rc;

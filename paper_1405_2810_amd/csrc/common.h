@@ -141,12 +141,16 @@ hipError_t launch_transport(const Geom& g, const double* sat, const double* flux
                             double* sat_bar, hipStream_t st);
 hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
                           double* sat_out, uint8_t* flags, hipStream_t st);
-// Offline solvers (synchronous, default stream): the fine SWIP pressure by
-// preconditioned CG (mom: moment scratch of the grid, d_status: device
-// status word) and the time of flight by block-Jacobi sweeps.  Return an
-// LRBMS_* code.
-int fine_solve(const Geom& g, double* mom, const double* field, int kind, double rtol, int maxit,
-               double* d_p, int* d_status, int* iters, double* relres);
+// Offline solvers (synchronous, default stream).  FineSolver: the fine SWIP
+// pressure by multigrid-preconditioned CG, its work arrays and coarse
+// hierarchy kept over solves of one problem (mom: moment scratch of the grid,
+// d_status: device status word).  tof_solve: the time of flight by
+// block-Jacobi sweeps.  Return an LRBMS_* code.
+struct FineSolver;
+FineSolver* fine_solver_create(const Geom& g);
+void fine_solver_destroy(FineSolver* S);
+int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
+                      int maxit, double* d_p, int* d_status, int* iters, double* relres);
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps);
 // Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and

@@ -9,6 +9,8 @@
 //     traces of the previous sweep; on a flow without cycles the sweeps are
 //     exact after as many sweeps as the longest upwind path has cells (the
 //     flow-ordered block-triangular structure of the system, Sec. 3.6).
+#include <memory>
+
 #include "common.h"
 #include "ktimer.h"
 #include "swip.h"
@@ -160,14 +162,35 @@ __global__ __launch_bounds__(kBlk) void k_fine_jacobi(Geom g, const double* __re
     for (int j = 0; j < R; ++j) Dinv[(size_t)(i * R + j) * nc + c] = inv[i][j];
 }
 
-// ---- preconditioned conjugate gradients, two launches per iteration ----------
-// The scalars never leave the device: every workgroup sums the per-workgroup
-// partials of the previous launch itself, in the same fixed order, so all
-// workgroups see identical alpha and beta.  Ap is carried by the recursion
-// A p_new = A z + beta A p_old, so one operator application per iteration
-// serves both the search direction and the curvature p . Ap.  The grid is
-// capped (grid-stride loops) to bound the partial sums.
+// ---- multigrid-preconditioned conjugate gradients ----------------------------
+// Preconditioner: one symmetric V-cycle.  Level 0 is the P1 DG space with
+// damped cell-block Jacobi smoothing.  Level 1 is its subspace of cell-wise
+// constants (coefficient 0 of every cell); the Galerkin operator there is the
+// (0,0) entry of the stencil blocks, which only the penalty term produces
+// (piecewise constants have no gradient), so the whole coarse hierarchy is
+// independent of the mobility and is built once per problem.  Coarser levels
+// aggregate 2^d cells (piecewise-constant prolongation, Galerkin operators that
+// stay (2d+1)-point stencils); the coarsest (<= kMgCoarse cells) is solved with
+// its dense inverse.  Pre- and post-smoothing are the same damped Jacobi
+// step, so the V-cycle is symmetric positive definite when the damping keeps
+// the smoother convergent.
+//
+// CG keeps its scalars on the device: every workgroup sums the
+// per-workgroup partials of the previous launch itself, in the same fixed
+// order, so all workgroups see identical alpha and beta.  Ap is carried by
+// the recursion A p_new = A z + beta A p_old.  The grid is capped
+// (grid-stride loops) to bound the partial sums.
 constexpr int kCgMaxBlocks = 1024;
+constexpr int kMgCoarse = 512;
+// Damped Jacobi on the P0 levels (diagonally dominant, so the eigenvalues of
+// D^-1 A lie in [0, 2]); level-0 damping relative to the estimated largest
+// eigenvalue of D^-1 A; over-relaxed coarse corrections, which compensate the
+// weak piecewise-constant prolongation (values chosen by convergence tests on
+// the configured problems; each keeps the V-cycle symmetric positive definite).
+constexpr double kMgOmega = 0.8;
+constexpr double kMgOmega0 = 1.5;
+constexpr double kMgAlpha0 = 1.3;   // level 1 -> level 0
+constexpr double kMgAlpha = 1.7;    // level l+1 -> level l
 
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n, double* red) {
   double s = 0.0;
@@ -175,26 +198,15 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
   return block_sum(s, red);
 }
 
-// Apply the cell's r x r blocks to v (own and face neighbours' coefficients).
-template <int D>
-__device__ __forceinline__ void stencil_apply(const Geom& g, const double* __restrict__ K,
-                                              const double* __restrict__ v, int c,
-                                              double (&y)[D + 1]) {
+// Apply the cell's r x r blocks (rows k0 .. k1-1) to v.
+template <int D, int K0, int K1>
+__device__ __forceinline__ void stencil_rows(const Geom& g, const double* __restrict__ K,
+                                             const double (&u)[1 + 2 * D][D + 1], int c,
+                                             double (&y)[D + 1]) {
   constexpr int R = D + 1;
   const int nc = g.ncell;
-  int xc[3];
-  cell_coords(g, c, xc);
-  double u[1 + 2 * D][R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) u[0][k] = v[(size_t)k * nc + c];
-#pragma unroll
-  for (int f = 0; f < 2 * D; ++f) {
-    const int n = face_neighbour(g, xc, f);
-#pragma unroll
-    for (int k = 0; k < R; ++k) u[1 + f][k] = (n >= 0) ? v[(size_t)k * nc + n] : 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
+  for (int k = K0; k < K1; ++k) {
     double s = 0.0;
 #pragma unroll
     for (int f = 0; f < 1 + 2 * D; ++f)
@@ -204,40 +216,287 @@ __device__ __forceinline__ void stencil_apply(const Geom& g, const double* __res
   }
 }
 
-// x = 0, r = b, z = D^-1 b; partials of r.z and r.r.
+// Coefficients of v on the cell and its face neighbours (zero outside).
 template <int D>
-__global__ __launch_bounds__(kBlk) void k_cg_init(Geom g, const double* __restrict__ b,
-                                                  const double* __restrict__ Dinv,
-                                                  double* __restrict__ x, double* __restrict__ r,
-                                                  double* __restrict__ z,
-                                                  double* __restrict__ part_rz,
-                                                  double* __restrict__ part_rr) {
+__device__ __forceinline__ void gather(const Geom& g, const double* __restrict__ v, int c,
+                                       const int (&xc)[3], double (&u)[1 + 2 * D][D + 1]) {
+  constexpr int R = D + 1;
+  const int nc = g.ncell;
+#pragma unroll
+  for (int k = 0; k < R; ++k) u[0][k] = v[(size_t)k * nc + c];
+#pragma unroll
+  for (int f = 0; f < 2 * D; ++f) {
+    const int n = face_neighbour(g, xc, f);
+#pragma unroll
+    for (int k = 0; k < R; ++k) u[1 + f][k] = (n >= 0) ? v[(size_t)k * nc + n] : 0.0;
+  }
+}
+
+// w = omega * Dinv_c r_c  (+ e on coefficient 0)
+template <int D>
+__device__ __forceinline__ void jacobi_cell(const Geom& g, const double* __restrict__ Dinv,
+                                            const double* __restrict__ r, double omega, int c,
+                                            double e0, double (&w)[D + 1]) {
+  constexpr int R = D + 1;
+  const int nc = g.ncell;
+  double rv[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) rv[k] = r[(size_t)k * nc + c];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], t);
+    w[i] = omega * t;
+  }
+  w[0] += e0;
+}
+
+// Level 1 stencil: the (0,0) entries of the self and face blocks.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_mg_extract(Geom g, const double* __restrict__ K,
+                                                     double* __restrict__ diag,
+                                                     double* __restrict__ off) {
+  constexpr int R = D + 1;
+  const int nc = g.ncell;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+    diag[c] = K[c];
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) off[(size_t)f * nc + c] = K[(size_t)((1 + f) * R * R) * nc + c];
+  }
+}
+
+// Level 0 down: z0 = omega0 D^-1 r, level-1 right-hand side = coefficient 0 of
+// r - A z0.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_mg0_down(Geom g, const double* __restrict__ K,
+                                                   const double* __restrict__ Dinv,
+                                                   const double* __restrict__ r, double omega0,
+                                                   double* __restrict__ b1) {
+  constexpr int R = D + 1;
+  const int nc = g.ncell;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+    int xc[3];
+    cell_coords(g, c, xc);
+    double u[1 + 2 * D][R];
+    jacobi_cell<D>(g, Dinv, r, omega0, c, 0.0, u[0]);
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) {
+      const int n = face_neighbour(g, xc, f);
+      if (n >= 0) {
+        jacobi_cell<D>(g, Dinv, r, omega0, n, 0.0, u[1 + f]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) u[1 + f][k] = 0.0;
+      }
+    }
+    double y[R];
+    stencil_rows<D, 0, 1>(g, K, u, c, y);
+    b1[c] = r[c] - y[0];
+  }
+}
+
+// Level 0 up: z = z0 + alpha0 e1 (on coefficient 0), then z += omega0 D^-1 (r - A z);
+// partials of r . z.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_mg0_up(Geom g, const double* __restrict__ K,
+                                                 const double* __restrict__ Dinv,
+                                                 const double* __restrict__ r,
+                                                 const double* __restrict__ e1, double omega0,
+                                                 double* __restrict__ z,
+                                                 double* __restrict__ part_rz) {
   constexpr int R = D + 1;
   __shared__ double red[4];
   const int nc = g.ncell;
-  double rz = 0.0, rr = 0.0;
+  double rz = 0.0;
   for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
-    double rv[R];
+    int xc[3];
+    cell_coords(g, c, xc);
+    double u[1 + 2 * D][R];
+    jacobi_cell<D>(g, Dinv, r, omega0, c, kMgAlpha0 * e1[c], u[0]);
 #pragma unroll
-    for (int k = 0; k < R; ++k) rv[k] = b[(size_t)k * nc + c];
+    for (int f = 0; f < 2 * D; ++f) {
+      const int n = face_neighbour(g, xc, f);
+      if (n >= 0) {
+        jacobi_cell<D>(g, Dinv, r, omega0, n, kMgAlpha0 * e1[n], u[1 + f]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) u[1 + f][k] = 0.0;
+      }
+    }
+    double y[R], res[R];
+    stencil_rows<D, 0, R>(g, K, u, c, y);
+#pragma unroll
+    for (int k = 0; k < R; ++k) res[k] = r[(size_t)k * nc + c] - y[k];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       double t = 0.0;
 #pragma unroll
-      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], t);
-      x[(size_t)i * nc + c] = 0.0;
-      r[(size_t)i * nc + c] = rv[i];
-      z[(size_t)i * nc + c] = t;
-      rz = fma(rv[i], t, rz);
-      rr = fma(rv[i], rv[i], rr);
+      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], res[j], t);
+      const double zi = fma(omega0, t, u[0][i]);
+      z[(size_t)i * nc + c] = zi;
+      rz = fma(r[(size_t)i * nc + c], zi, rz);
     }
   }
-  const double a = block_sum(rz, red);
-  const double bb = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = a;
-    part_rr[blockIdx.x] = bb;
+  const double t = block_sum(rz, red);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
+}
+
+// One P0 level: cells m[0] x m[1] x m[2], x fastest.
+struct MgGrid {
+  int m[3], n;
+};
+
+__device__ __forceinline__ int mg_neighbour(const MgGrid& L, const int (&x)[3], int f) {
+  const int a = f >> 1;
+  int y[3] = {x[0], x[1], x[2]};
+  y[a] += (f & 1) ? 1 : -1;
+  if (y[a] < 0 || y[a] >= L.m[a]) return -1;
+  return y[0] + L.m[0] * (y[1] + L.m[1] * y[2]);
+}
+
+__device__ __forceinline__ void mg_coords(const MgGrid& L, int c, int (&x)[3]) {
+  x[0] = c % L.m[0];
+  x[1] = (c / L.m[0]) % L.m[1];
+  x[2] = c / (L.m[0] * L.m[1]);
+}
+
+__device__ __forceinline__ int mg_parent(const MgGrid& C, const int (&x)[3]) {
+  return (x[0] >> 1) + C.m[0] * ((x[1] >> 1) + C.m[1] * (x[2] >> 1));
+}
+
+// Level l down: e = omega b / d on every cell of a coarse cell's aggregate,
+// coarse right-hand side = sum over the aggregate of b - A e.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_mgl_down(MgGrid L, MgGrid C,
+                                                   const double* __restrict__ diag,
+                                                   const double* __restrict__ off,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ bc) {
+  for (int q = blockIdx.x * kBlk + threadIdx.x; q < C.n; q += gridDim.x * kBlk) {
+    int X[3];
+    mg_coords(C, q, X);
+    double sum = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < (1 << D); ++ch) {
+      const int x[3] = {2 * X[0] + (ch & 1), 2 * X[1] + ((ch >> 1) & 1),
+                        D == 3 ? 2 * X[2] + ((ch >> 2) & 1) : 0};
+      if (x[0] >= L.m[0] || x[1] >= L.m[1] || x[2] >= L.m[2]) continue;
+      const int c = x[0] + L.m[0] * (x[1] + L.m[1] * x[2]);
+      const double bcv = b[c];
+      double res = bcv - kMgOmega * bcv;
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const int n = mg_neighbour(L, x, f);
+        if (n >= 0) res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n]);
+      }
+      sum += res;
+    }
+    bc[q] = sum;
   }
+}
+
+// Level l up: e = omega b / d + alpha P e_coarse, then e += omega (b - A e) / d.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_mgl_up(MgGrid L, MgGrid C,
+                                                 const double* __restrict__ diag,
+                                                 const double* __restrict__ off,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ ec,
+                                                 double* __restrict__ e) {
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < L.n; c += gridDim.x * kBlk) {
+    int x[3];
+    mg_coords(L, c, x);
+    const double dc = diag[c];
+    const double ev = kMgOmega * b[c] / dc + kMgAlpha * ec[mg_parent(C, x)];
+    double res = b[c] - dc * ev;
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) {
+      const int n = mg_neighbour(L, x, f);
+      if (n < 0) continue;
+      int y[3];
+      mg_coords(L, n, y);
+      res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n] + kMgAlpha * ec[mg_parent(C, y)]);
+    }
+    e[c] = ev + kMgOmega * res / dc;
+  }
+}
+
+// Coarsest level: e = A^-1 b with the dense symmetric inverse (column reads).
+__global__ __launch_bounds__(kBlk) void k_mg_coarse(int n, const double* __restrict__ inv,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ e) {
+  const int i = blockIdx.x * kBlk + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s = fma(inv[(size_t)j * n + i], b[j], s);
+  e[i] = s;
+}
+
+// Power iteration for the largest eigenvalue of D^-1 A: w = D^-1 A (v * scale);
+// partials of |w|^2.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_power(Geom g, const double* __restrict__ K,
+                                                const double* __restrict__ Dinv,
+                                                const double* __restrict__ v, double scale,
+                                                double* __restrict__ w,
+                                                double* __restrict__ part) {
+  constexpr int R = D + 1;
+  __shared__ double red[4];
+  const int nc = g.ncell;
+  double acc = 0.0;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+    int xc[3];
+    cell_coords(g, c, xc);
+    double u[1 + 2 * D][R];
+    gather<D>(g, v, c, xc, u);
+    double y[R];
+    stencil_rows<D, 0, R>(g, K, u, c, y);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], y[j], t);
+      t *= scale;
+      w[(size_t)i * nc + c] = t;
+      acc = fma(t, t, acc);
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlk) void k_power_start(long long n, double* __restrict__ v) {
+  const long long i = blockIdx.x * (long long)kBlk + threadIdx.x;
+  if (i >= n) return;
+  // a fixed, non-special start vector: values in [0.5, 1.5)
+  unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  v[i] = 0.5 + (double)(h >> 11) * 0x1.0p-53;
+}
+
+// x = 0, r = b; partials of r . r.
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_cg_init(Geom g, const double* __restrict__ b,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ part_rr) {
+  constexpr int R = D + 1;
+  __shared__ double red[4];
+  const int nc = g.ncell;
+  double rr = 0.0;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double v = b[(size_t)k * nc + c];
+      x[(size_t)k * nc + c] = 0.0;
+      r[(size_t)k * nc + c] = v;
+      rr = fma(v, v, rr);
+    }
+  }
+  const double t = block_sum(rr, red);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
 }
 
 // beta = (r.z)_new / (r.z)_old (0 on the first iteration); p = z + beta p,
@@ -261,12 +520,16 @@ __global__ __launch_bounds__(kBlk) void k_cg_direction(Geom g, const double* __r
   }
   double dot = 0.0;
   for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += nb * kBlk) {
+    int xc[3];
+    cell_coords(g, c, xc);
+    double u[1 + 2 * D][R];
+    gather<D>(g, z, c, xc, u);
     double w[R];
-    stencil_apply<D>(g, K, z, c, w);
+    stencil_rows<D, 0, R>(g, K, u, c, w);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const size_t i = (size_t)k * nc + c;
-      const double pk = FIRST ? z[i] : fma(beta, p[i], z[i]);
+      const double pk = FIRST ? u[0][k] : fma(beta, p[i], u[0][k]);
       const double ak = FIRST ? w[k] : fma(beta, Ap[i], w[k]);
       p[i] = pk;
       Ap[i] = ak;
@@ -277,17 +540,15 @@ __global__ __launch_bounds__(kBlk) void k_cg_direction(Geom g, const double* __r
   if (threadIdx.x == 0) part_pap[blockIdx.x] = t;
 }
 
-// alpha = (r.z) / (p.Ap); x += alpha p, r -= alpha Ap, z = D^-1 r; partials
-// of the new r.z and r.r.  A non-positive or non-finite curvature sets fail.
+// alpha = (r.z) / (p.Ap); x += alpha p, r -= alpha Ap; partials of r.r.  A
+// non-positive or non-finite curvature or r.z sets fail.
 template <int D>
-__global__ __launch_bounds__(kBlk) void k_cg_update(Geom g, const double* __restrict__ Dinv,
-                                                    double* __restrict__ x, double* __restrict__ r,
-                                                    double* __restrict__ z,
+__global__ __launch_bounds__(kBlk) void k_cg_update(Geom g, double* __restrict__ x,
+                                                    double* __restrict__ r,
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ Ap,
                                                     const double* __restrict__ rz_cur,
                                                     const double* __restrict__ part_pap,
-                                                    double* __restrict__ rz_next,
                                                     double* __restrict__ part_rr,
                                                     int* __restrict__ fail) {
   constexpr int R = D + 1;
@@ -295,35 +556,22 @@ __global__ __launch_bounds__(kBlk) void k_cg_update(Geom g, const double* __rest
   const int nc = g.ncell, nb = gridDim.x;
   const double rz = sum_partials(rz_cur, nb, red);
   const double pap = sum_partials(part_pap, nb, red);
-  const bool ok = pap > 0.0 && isfinite(pap);
+  const bool ok = pap > 0.0 && isfinite(pap) && rz >= 0.0;
   const double al = ok ? rz / pap : 0.0;
   if (!ok && blockIdx.x == 0 && threadIdx.x == 0) *fail = 1;
-  double rzn = 0.0, rr = 0.0;
+  double rr = 0.0;
   for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += nb * kBlk) {
-    double rv[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const size_t i = (size_t)k * nc + c;
       x[i] = fma(al, p[i], x[i]);
-      rv[k] = fma(-al, Ap[i], r[i]);
-      r[i] = rv[k];
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      double t = 0.0;
-#pragma unroll
-      for (int j = 0; j < R; ++j) t = fma(Dinv[(size_t)(i * R + j) * nc + c], rv[j], t);
-      z[(size_t)i * nc + c] = t;
-      rzn = fma(rv[i], t, rzn);
-      rr = fma(rv[i], rv[i], rr);
+      const double rv = fma(-al, Ap[i], r[i]);
+      r[i] = rv;
+      rr = fma(rv, rv, rr);
     }
   }
-  const double a = block_sum(rzn, red);
-  const double bb = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    rz_next[blockIdx.x] = a;
-    part_rr[blockIdx.x] = bb;
-  }
+  const double t = block_sum(rr, red);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
 }
 
 // ---- time of flight -----------------------------------------------------------
@@ -464,7 +712,14 @@ __global__ __launch_bounds__(kBlk) void k_tof_sweep(Geom g, const double* __rest
 // ---- host drivers --------------------------------------------------------------
 struct DevBuf {
   double* p = nullptr;
-  bool alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(double)) == hipSuccess; }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  bool alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(double)) == hipSuccess;
+  }
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
@@ -478,48 +733,212 @@ static double host_sum(const std::vector<double>& v) {
   return s;
 }
 
+// Fine pressure solver of one problem: work arrays and the mobility-free
+// coarse hierarchy, reused over solves with different mobilities.
+struct FineSolver {
+  Geom g{};
+  int nb = 0, nbc = 0;
+  DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, fl, mg, cinv;
+  std::vector<MgGrid> grids;           // P0 levels 1 .. L
+  std::vector<double*> diag, off, b, e;
+  bool have_mg = false;
+};
+
+// Dense inverse of the SPD matrix A (n x n, row-major, in place) by Cholesky.
+static bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / d;
+    }
+  }
+  std::vector<double> y(n), x(n);
+  for (int col = 0; col < n; ++col) {
+    for (int i = 0; i < n; ++i) {
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * y[k];
+      y[i] = v / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * x[k];
+      x[i] = v / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) A[(size_t)i * n + col] = x[i];
+  }
+  return true;
+}
+
+// Coarse hierarchy from the level-1 stencil (the (0,0) entries of K).
 template <int D>
-static int fine_solve_t(const Geom& g, double* mom, const double* field, int kind, double rtol,
+static int build_hierarchy(FineSolver& S) {
+  const Geom& g = S.g;
+  S.grids.clear();
+  MgGrid L1{{g.n[0], g.n[1], g.n[2]}, g.ncell};
+  S.grids.push_back(L1);
+  while (S.grids.back().n > kMgCoarse && S.grids.size() < 24) {
+    MgGrid C = S.grids.back();
+    for (int a = 0; a < D; ++a) C.m[a] = (C.m[a] + 1) / 2;
+    C.n = C.m[0] * C.m[1] * C.m[2];
+    S.grids.push_back(C);
+  }
+  const int nl = (int)S.grids.size();
+  size_t total = 0;
+  for (auto& G : S.grids) total += (size_t)(3 + 2 * D) * G.n;
+  if (!S.mg.alloc(total)) return LRBMS_E_OOM;
+  S.diag.assign(nl, nullptr);
+  S.off.assign(nl, nullptr);
+  S.b.assign(nl, nullptr);
+  S.e.assign(nl, nullptr);
+  size_t o = 0;
+  for (int l = 0; l < nl; ++l) {
+    const size_t n = S.grids[l].n;
+    S.diag[l] = S.mg.p + o;
+    S.off[l] = S.diag[l] + n;
+    S.b[l] = S.off[l] + 2 * D * n;
+    S.e[l] = S.b[l] + n;
+    o += (size_t)(3 + 2 * D) * n;
+  }
+  hipLaunchKernelGGL(k_mg_extract<D>, dim3(std::min(blocks_for(g.ncell), 4096)), dim3(kBlk), 0, 0,
+                     g, S.K.p, S.diag[0], S.off[0]);
+  std::vector<double> hd(g.ncell), ho((size_t)2 * D * g.ncell);
+  if (hipMemcpy(hd.data(), S.diag[0], hd.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(ho.data(), S.off[0], ho.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return LRBMS_E_HIP;
+  for (int l = 0; l + 1 < nl; ++l) {
+    const MgGrid& F = S.grids[l];
+    const MgGrid& C = S.grids[l + 1];
+    std::vector<double> cd(C.n, 0.0), co((size_t)2 * D * C.n, 0.0);
+    for (int c = 0; c < F.n; ++c) {
+      const int x[3] = {c % F.m[0], (c / F.m[0]) % F.m[1], c / (F.m[0] * F.m[1])};
+      const int P = (x[0] >> 1) + C.m[0] * ((x[1] >> 1) + C.m[1] * (x[2] >> 1));
+      cd[P] += hd[c];
+      for (int f = 0; f < 2 * D; ++f) {
+        const int a = f >> 1;
+        int y[3] = {x[0], x[1], x[2]};
+        y[a] += (f & 1) ? 1 : -1;
+        if (y[a] < 0 || y[a] >= F.m[a]) continue;
+        const int Q = (y[0] >> 1) + C.m[0] * ((y[1] >> 1) + C.m[1] * (y[2] >> 1));
+        const double v = ho[(size_t)f * F.n + c];
+        if (Q == P) cd[P] += v;
+        else co[(size_t)f * C.n + P] += v;
+      }
+    }
+    if (hipMemcpy(S.diag[l + 1], cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S.off[l + 1], co.data(), co.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return LRBMS_E_HIP;
+    hd.swap(cd);
+    ho.swap(co);
+  }
+  // dense inverse of the coarsest level
+  const MgGrid& Cg = S.grids.back();
+  const int n = Cg.n;
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    const int x[3] = {c % Cg.m[0], (c / Cg.m[0]) % Cg.m[1], c / (Cg.m[0] * Cg.m[1])};
+    A[(size_t)c * n + c] = hd[c];
+    for (int f = 0; f < 2 * D; ++f) {
+      const int a = f >> 1;
+      int y[3] = {x[0], x[1], x[2]};
+      y[a] += (f & 1) ? 1 : -1;
+      if (y[a] < 0 || y[a] >= Cg.m[a]) continue;
+      A[(size_t)c * n + y[0] + Cg.m[0] * (y[1] + Cg.m[1] * y[2])] = ho[(size_t)f * n + c];
+    }
+  }
+  if (!spd_inverse(A, n)) return LRBMS_E_NOT_SPD;
+  if (!S.cinv.alloc((size_t)n * n)) return LRBMS_E_OOM;
+  if (hipMemcpy(S.cinv.p, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return LRBMS_E_HIP;
+  S.have_mg = true;
+  return LRBMS_OK;
+}
+
+// z = B r (one V-cycle); partials of r . z.
+template <int D>
+static void vcycle(FineSolver& S, double omega0, const double* r, double* z, double* part_rz) {
+  const Geom& g = S.g;
+  const int nl = (int)S.grids.size();
+  hipLaunchKernelGGL(k_mg0_down<D>, dim3(std::min(blocks_for(g.ncell), 8192)), dim3(kBlk), 0, 0,
+                     g, S.K.p, S.Dinv.p, r, omega0, S.b[0]);
+  for (int l = 0; l + 1 < nl; ++l)
+    hipLaunchKernelGGL(k_mgl_down<D>, dim3(std::min(blocks_for(S.grids[l + 1].n), 8192)),
+                       dim3(kBlk), 0, 0, S.grids[l], S.grids[l + 1], S.diag[l], S.off[l], S.b[l],
+                       S.b[l + 1]);
+  hipLaunchKernelGGL(k_mg_coarse, dim3(blocks_for(S.grids.back().n)), dim3(kBlk), 0, 0,
+                     S.grids.back().n, S.cinv.p, S.b[nl - 1], S.e[nl - 1]);
+  for (int l = nl - 2; l >= 0; --l)
+    hipLaunchKernelGGL(k_mgl_up<D>, dim3(std::min(blocks_for(S.grids[l].n), 8192)), dim3(kBlk), 0,
+                       0, S.grids[l], S.grids[l + 1], S.diag[l], S.off[l], S.b[l], S.e[l + 1],
+                       S.e[l]);
+  hipLaunchKernelGGL(k_mg0_up<D>, dim3(S.nbc), dim3(kBlk), 0, 0, g, S.K.p, S.Dinv.p, r, S.e[0],
+                     omega0, z, part_rz);
+}
+
+template <int D>
+static int fine_solve_t(FineSolver& S, double* mom, const double* field, int kind, double rtol,
                         int maxit, double* d_p, int* d_status, int* iters, double* relres) {
   constexpr int R = D + 1;
-  const int nc = g.ncell;
+  const Geom& g = S.g;
+  const int nc = g.ncell, nb = S.nb, nbc = S.nbc;
   const size_t n = (size_t)R * nc;
-  const int nb = blocks_for(nc);
-  const int nbc = std::min(nb, kCgMaxBlocks);
   hipStream_t st = 0;
-  DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, fl;
-  if (!K.alloc((size_t)(1 + 2 * D) * R * R * nc) || !Dinv.alloc((size_t)R * R * nc) ||
-      !l.alloc(n) || !r.alloc(n) || !z.alloc(n) || !pv.alloc(n) || !Ap.alloc(n) ||
-      !prz.alloc(2 * (size_t)nbc) || !prr.alloc(nbc) || !ppap.alloc(nbc) || !fl.alloc(1))
-    return LRBMS_E_OOM;
-  int* d_fail = reinterpret_cast<int*>(fl.p);
+  int* d_fail = reinterpret_cast<int*>(S.fl.p);
   if (hipMemset(d_fail, 0, sizeof(int)) != hipSuccess) return LRBMS_E_HIP;
   if (launch_moments(g, field, kind, nullptr, 0, 0, mom, st) != hipSuccess) return LRBMS_E_HIP;
   hipLaunchKernelGGL(k_fine_stencil<D>, dim3(blocks_for((long long)nc * R)), dim3(kBlk), 0, st, g,
-                     mom, K.p);
-  hipLaunchKernelGGL(k_fine_rhs<D>, dim3(nb), dim3(kBlk), 0, st, g, mom, l.p);
-  hipLaunchKernelGGL(k_fine_jacobi<D>, dim3(nb), dim3(kBlk), 0, st, g, K.p, Dinv.p, d_status);
-  hipLaunchKernelGGL(k_cg_init<D>, dim3(nbc), dim3(kBlk), 0, st, g, l.p, Dinv.p, d_p, r.p, z.p,
-                     prz.p, prr.p);
-  hipLaunchKernelGGL((k_cg_direction<D, true>), dim3(nbc), dim3(kBlk), 0, st, g, K.p, z.p, pv.p,
-                     Ap.p, prz.p, prz.p, ppap.p);
+                     mom, S.K.p);
+  hipLaunchKernelGGL(k_fine_rhs<D>, dim3(nb), dim3(kBlk), 0, st, g, mom, S.l.p);
+  hipLaunchKernelGGL(k_fine_jacobi<D>, dim3(nb), dim3(kBlk), 0, st, g, S.K.p, S.Dinv.p, d_status);
   if (hipGetLastError() != hipSuccess) return LRBMS_E_HIP;
+  int rc;
+  if (!S.have_mg && (rc = build_hierarchy<D>(S))) return rc;
+  // damping of the level-0 smoother from a power estimate of lambda_max(D^-1 A)
   std::vector<double> h(nbc);
-  if (hipMemcpy(h.data(), prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+  double* v = S.z.p;
+  double* w = S.Ap.p;
+  hipLaunchKernelGGL(k_power_start, dim3(blocks_for((long long)n)), dim3(kBlk), 0, st,
+                     (long long)n, v);
+  double scale = 1.0, lam = 0.0;
+  for (int k = 0; k < 12; ++k) {
+    hipLaunchKernelGGL(k_power<D>, dim3(nbc), dim3(kBlk), 0, st, g, S.K.p, S.Dinv.p, v, scale, w,
+                       S.prr.p);
+    if (hipMemcpy(h.data(), S.prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return LRBMS_E_HIP;
+    const double nrm = std::sqrt(host_sum(h));
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return LRBMS_E_NONFINITE;
+    if (k > 0) lam = nrm;   // |D^-1 A v| for a unit v
+    scale = 1.0 / nrm;
+    std::swap(v, w);
+  }
+  const double omega0 = kMgOmega0 / lam;
+  // conjugate gradients
+  hipLaunchKernelGGL(k_cg_init<D>, dim3(nbc), dim3(kBlk), 0, st, g, S.l.p, d_p, S.r.p, S.prr.p);
+  if (hipMemcpy(h.data(), S.prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return LRBMS_E_HIP;
   const double bb = host_sum(h);
   double rr = bb;
   bool conv = !(rr > rtol * rtol * bb);   // zero right-hand side
   int it = 0;
+  if (!conv) {
+    vcycle<D>(S, omega0, S.r.p, S.z.p, S.prz.p);
+    hipLaunchKernelGGL((k_cg_direction<D, true>), dim3(nbc), dim3(kBlk), 0, st, g, S.K.p, S.z.p,
+                       S.pv.p, S.Ap.p, S.prz.p, S.prz.p, S.ppap.p);
+  }
   for (; it < maxit && !conv; ++it) {
-    double* cur = prz.p + (size_t)(it & 1) * nbc;
-    double* nxt = prz.p + (size_t)((it + 1) & 1) * nbc;
-    hipLaunchKernelGGL(k_cg_update<D>, dim3(nbc), dim3(kBlk), 0, st, g, Dinv.p, d_p, r.p, z.p,
-                       pv.p, Ap.p, cur, ppap.p, nxt, prr.p, d_fail);
-    const bool check = (it + 1) % 20 == 0 || it + 1 == maxit;
-    if (check) {
+    double* cur = S.prz.p + (size_t)(it & 1) * nbc;
+    double* nxt = S.prz.p + (size_t)((it + 1) & 1) * nbc;
+    hipLaunchKernelGGL(k_cg_update<D>, dim3(nbc), dim3(kBlk), 0, st, g, d_p, S.r.p, S.pv.p,
+                       S.Ap.p, cur, S.ppap.p, S.prr.p, d_fail);
+    if ((it + 1) % 5 == 0 || it + 1 == maxit) {
       int f = 0;
-      if (hipMemcpy(h.data(), prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+      if (hipMemcpy(h.data(), S.prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(&f, d_fail, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return LRBMS_E_HIP;
       if (f) return LRBMS_E_NOT_SPD;
@@ -531,8 +950,9 @@ static int fine_solve_t(const Geom& g, double* mom, const double* field, int kin
         break;
       }
     }
-    hipLaunchKernelGGL((k_cg_direction<D, false>), dim3(nbc), dim3(kBlk), 0, st, g, K.p, z.p,
-                       pv.p, Ap.p, nxt, cur, ppap.p);
+    vcycle<D>(S, omega0, S.r.p, S.z.p, nxt);
+    hipLaunchKernelGGL((k_cg_direction<D, false>), dim3(nbc), dim3(kBlk), 0, st, g, S.K.p, S.z.p,
+                       S.pv.p, S.Ap.p, nxt, cur, S.ppap.p);
   }
   if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) return LRBMS_E_HIP;
   if (iters) *iters = it;
@@ -540,10 +960,28 @@ static int fine_solve_t(const Geom& g, double* mom, const double* field, int kin
   return conv ? LRBMS_OK : LRBMS_E_STATE;
 }
 
-int fine_solve(const Geom& g, double* mom, const double* field, int kind, double rtol, int maxit,
-               double* d_p, int* d_status, int* iters, double* relres) {
-  return g.dim == 2 ? fine_solve_t<2>(g, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres)
-                    : fine_solve_t<3>(g, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres);
+FineSolver* fine_solver_create(const Geom& g) {
+  std::unique_ptr<FineSolver> S(new FineSolver());
+  S->g = g;
+  const int D = g.dim, R = D + 1, nc = g.ncell;
+  const size_t n = (size_t)R * nc;
+  S->nb = blocks_for(nc);
+  S->nbc = std::min(S->nb, kCgMaxBlocks);
+  if (!S->K.alloc((size_t)(1 + 2 * D) * R * R * nc) || !S->Dinv.alloc((size_t)R * R * nc) ||
+      !S->l.alloc(n) || !S->r.alloc(n) || !S->z.alloc(n) || !S->pv.alloc(n) || !S->Ap.alloc(n) ||
+      !S->prz.alloc(2 * (size_t)S->nbc) || !S->prr.alloc(S->nbc) || !S->ppap.alloc(S->nbc) ||
+      !S->fl.alloc(1))
+    return nullptr;
+  return S.release();
+}
+
+void fine_solver_destroy(FineSolver* S) { delete S; }
+
+int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
+                      int maxit, double* d_p, int* d_status, int* iters, double* relres) {
+  return S->g.dim == 2
+             ? fine_solve_t<2>(*S, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres)
+             : fine_solve_t<3>(*S, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres);
 }
 
 template <int D>
