@@ -21,6 +21,9 @@ Passes, in order:
   kernels      K steps with the library's per-kernel event timing switched on:
                per kernel kind the mean launch time and the algorithmic
                flops and bytes, hence the roofline of the dominant kernel;
+  context      the fine reference (Alg. 1 on the GPU, --fine-steps steps) and
+               one run of the GPU offline stage (--offline), reported beside
+               the metric;
   cpu_baseline the FP64 CPU oracle's online step on a bounded sample of the
                same workload (skipped with --no-cpu-baseline).
 """
@@ -104,6 +107,10 @@ def main():
     ap.add_argument("--mode", default="direct", choices=["direct"])
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fine-steps", type=int, default=10,
+                    help="steps of the fine reference (Alg. 1) timed for context; 0 skips")
+    ap.add_argument("--offline", type=int, default=1,
+                    help="1: time the GPU offline stage once for context")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (scale of the HBM counters)")
     args = ap.parse_args()
@@ -228,6 +235,43 @@ def main():
     roof["kernel"] = dom
     roof["avg_launch_us"] = kd["avg_launch_us"]
     roof["algorithmic_per_launch"] = {"bytes": kd["bytes_per_launch"], "flops": kd["flops_per_launch"]}
+    # ---- context: the fine reference (Alg. 1) and the offline stage on the GPU
+    extras = {}
+    if args.fine_steps > 0:
+        from paper_1405_2810_amd.lrbms import Fine
+        fine = Fine(p)
+        sf_a, sf_b = s0.clone(), torch.zeros_like(s0)
+        ph = torch.zeros_like(s0)
+        its = []
+        fine.step(sf_a, ph, flux, sf_b, flags)          # first solve: hierarchy set-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.fine_steps):
+            it, _ = fine.step(sf_a, ph, flux, sf_b, flags, warm=True)
+            its.append(it)
+            sf_a, sf_b = sf_b, sf_a
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t0) / args.fine_steps * 1e3
+        fine.close()
+        extras["fine_reference"] = {
+            "what": "Alg. 1 on the same GPU: fine SWIP pressure by multigrid-preconditioned CG "
+                    "(rtol 1e-13, warm start), fluxes, transport, limiter",
+            "ms_per_step": fms, "cg_iterations_mean": float(np.mean(its)),
+            "steps": args.fine_steps, "online_speedup": fms / ms}
+        log(f"[bench] fine reference: {fms:.2f} ms/step, {np.mean(its):.0f} CG iterations; "
+            f"online step is {fms / ms:.1f}x faster")
+    if args.offline:
+        from synth import training_params
+        from paper_1405_2810_amd.lrbms import Model
+        params = training_params(p.M, p.n_train, np.random.default_rng(p.seed))
+        T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        om, rep = Model.build_offline(p, params, ne_cap=p.ne_cap, horizon=T, pcg_rtol=1e-12)
+        osec = time.perf_counter() - t0
+        extras["offline_stage"] = {"seconds": osec, "N": om.info["N"], **rep}
+        om.close()
+        log(f"[bench] offline stage (Alg. 2 without greedy) on the GPU: {osec:.2f} s, {rep}")
     # ---- CPU oracle baseline ----------------------------------------------
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
@@ -263,6 +307,7 @@ def main():
                         "GBs": round(v["GBs"], 2), "TFLOPs": round(v["TFLOPs"], 4)}
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -119,6 +119,8 @@ typedef struct lrbms_offline_opts {
   int32_t tof_maxit;        /* sweep limit (> 0)                                    */
   int32_t keep_profiles;    /* 1: keep the linearly independent profiles (AFFINE,
                                DIRECT_FIT); 0: a model without profiles             */
+  const double* d_s0;       /* device [r*ncell] saturation whose flow defines the time
+                               of flight (re-basing from a later state); NULL: s = 0 */
 } lrbms_offline_opts;
 
 /* What the offline stage did (filled when the caller passes a non-NULL pointer). */
@@ -163,9 +165,13 @@ int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
  *  iterations, relres: host outputs (nullable): CG iterations and the final
  *           relative residual |l - A p| / |l|, from the recursion
  * Synchronous (default stream); allocates its work arrays per call.
+ * The preconditioner is one symmetric multigrid V-cycle: damped cell-block
+ * Jacobi on P1, then the cell-wise constants, whose Galerkin operator is the
+ * mobility-free penalty part, coarsened by aggregation down to a dense solve.
  * Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP, LRBMS_E_NOT_SPD (a singular
- * cell block or a non-positive curvature), LRBMS_E_NONFINITE, LRBMS_E_STATE
- * when maxit iterations end above rtol (d_p then holds the last iterate).    */
+ * cell block, a non-positive curvature or an indefinite preconditioner),
+ * LRBMS_E_NONFINITE, LRBMS_E_STATE when maxit iterations end above rtol
+ * (d_p then holds the last iterate).                                         */
 enum { LRBMS_FIELD_SATURATION = 0, LRBMS_FIELD_MOBILITY = 1 };
 int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_t kind,
                         double rtol, int32_t maxit, double* d_p, int32_t* iterations,
@@ -186,8 +192,27 @@ int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_
 int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double tol,
                          int32_t maxit, double* d_tau, int32_t* sweeps);
 
+/* Fine reference: the high-dimensional IMPES scheme of Alg. 1 on the device
+ * (the accuracy reference that the LRBMS online step replaces).  A handle owns
+ * the problem on the device and the fine solver's work arrays and coarse
+ * hierarchy.  One lrbms_fine_step is one time step: p_h from lambda(d_sat)
+ * (lrbms_fine_pressure's solver; warm != 0 starts CG from the contents of
+ * d_ph, e.g. the previous step's pressure), the face fluxes of Def.
+ * velocityDG, the saturation step of Def. saturationDG and the limiter as in
+ * lrbms_transport_step.
+ *  d_sat (in), d_ph (in/out), d_flux, d_sat_out, d_flags (nullable): device
+ *  arrays as in the online calls; d_sat_out must not alias d_sat.
+ *  iterations, relres: host outputs (nullable).
+ * Synchronous (default stream).  Errors as lrbms_fine_pressure.               */
+typedef struct lrbms_fine lrbms_fine;
+int lrbms_fine_create(const lrbms_problem* prob, lrbms_fine** out);
+int lrbms_fine_step(lrbms_fine* f, const double* d_sat, double rtol, int32_t maxit, int32_t warm,
+                    double* d_ph, double* d_flux, double* d_sat_out, uint8_t* d_flags,
+                    int32_t* iterations, double* relres);
+void lrbms_fine_destroy(lrbms_fine* f);
+
 /* Offline stage on the device (Alg. 2 steps 1-2 without the error-driven
- * selection): initial pressure at s = 0 by lrbms_fine_pressure, its face
+ * selection): initial pressure at s0 (default 0) by lrbms_fine_pressure, its face
  * fluxes (Def. velocityDG), the time of flight, the M profiles of Alg. 2
  * step 1c (Lambda^1 = lambda(0), Lambda^M = lambda(1), Lambda^q = lambda(0)
  * where the cell mean of tau exceeds (q-1) T/(M-2), else lambda(1)), one

@@ -568,8 +568,10 @@ struct FineSolverHandle {
 };
 
 static int fine_solve_checked(Model& M, FineSolver* S, const double* d_field, int kind,
-                              double rtol, int maxit, double* d_p, int* iters, double* relres) {
-  int rc = fine_solver_solve(S, M.d_mom, d_field, kind, rtol, maxit, d_p, M.d_status, iters, relres);
+                              double rtol, int maxit, double* d_p, int* iters, double* relres,
+                              bool warm = false) {
+  int rc = fine_solver_solve(S, M.d_mom, d_field, kind, rtol, maxit, warm, d_p, M.d_status, iters,
+                             relres);
   const int st = take_status(M);
   if (st < 0 && (rc == LRBMS_OK || rc == LRBMS_E_STATE)) rc = st;
   switch (rc) {
@@ -691,12 +693,12 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
   if (!(fs.s = fine_solver_create(g))) return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
   int it = 0;
   double rr = 0.0;
-  rc = fine_solve_checked(tmp, fs.s, tmp.d_scratch_sat, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit,
-                          tmp.d_scratch_ph, &it, &rr);
+  const double* s0 = o->d_s0 ? o->d_s0 : tmp.d_scratch_sat;   // zeros unless given
+  rc = fine_solve_checked(tmp, fs.s, s0, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit, tmp.d_scratch_ph,
+                          &it, &rr);
   note(it, rr);
   if (rc) return rc;
-  if (!hip_ok(launch_flux(g, tmp.d_scratch_ph, tmp.d_scratch_sat, flux.p, 0), "initial flux"))
-    return LRBMS_E_HIP;
+  if (!hip_ok(launch_flux(g, tmp.d_scratch_ph, s0, flux.p, 0), "initial flux")) return LRBMS_E_HIP;
   if ((rc = tof_checked(tmp, flux.p, o->tof_tol, o->tof_maxit, tau.p, &R.tof_sweeps))) return rc;
   std::vector<double> h_tau(L);
   if (!hip_ok(hipMemcpy(h_tau.data(), tau.p, L * sizeof(double), hipMemcpyDeviceToHost), "tau"))
@@ -740,6 +742,32 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
   return model_create_impl(p, sizes.data(), basis.data(), R.n_profiles_kept,
                            kept.empty() ? nullptr : kept.data(), out);
 }
+
+// Transport step (Def. saturationDG) and the limiter (eq. limiterMain) on a
+// model's geometry; the limiter reads the unlimited state from scratch.
+static int transport_impl(Model& M, const double* d_sat, const double* d_flux, double* d_sat_out,
+                          uint8_t* d_flags, hipStream_t st) {
+  const Geom& g = M.g;
+  if (g.limiter) {
+    if (!hip_ok(launch_transport(g, d_sat, d_flux, M.d_scratch_sat, st), "transport") ||
+        !hip_ok(launch_limiter(g, M.d_scratch_sat, d_flux, d_sat_out, d_flags, st), "limiter"))
+      return LRBMS_E_HIP;
+  } else {
+    if (!hip_ok(launch_transport(g, d_sat, d_flux, d_sat_out, st), "transport")) return LRBMS_E_HIP;
+    if (d_flags) {
+      hipLaunchKernelGGL(k_fill_u8, dim3((g.ncell + 255) / 256), dim3(256), 0, st, d_flags,
+                         g.ncell, (uint8_t)0);
+      if (!hip_ok(hipGetLastError(), "fill flags")) return LRBMS_E_HIP;
+    }
+  }
+  return LRBMS_OK;
+}
+
+// Fine reference (Alg. 1): the problem on the device and a fine solver.
+struct FineModel {
+  Model M;
+  FineSolverHandle S;
+};
 
 }  // namespace lrbms
 
@@ -902,23 +930,58 @@ int lrbms_transport_step(lrbms_model* m, const double* d_sat, const double* d_fl
   if (d_sat_out == d_sat) return (set_error("d_sat_out must not alias d_sat"), LRBMS_E_ARG);
   Model* M = M_(m);
   TimerScope timing(&M->timer);
-  hipStream_t st = (hipStream_t)stream;
-  const Geom& g = M->g;
-  if (g.limiter) {
-    if (!hip_ok(launch_transport(g, d_sat, d_flux, M->d_scratch_sat, st), "transport") ||
-        !hip_ok(launch_limiter(g, M->d_scratch_sat, d_flux, d_sat_out, d_flags, st), "limiter"))
-      return LRBMS_E_HIP;
-  } else {
-    if (!hip_ok(launch_transport(g, d_sat, d_flux, d_sat_out, st), "transport")) return LRBMS_E_HIP;
-    if (d_flags) {
-      hipLaunchKernelGGL(k_fill_u8, dim3((g.ncell + 255) / 256), dim3(256), 0, st, d_flags,
-                         g.ncell, (uint8_t)0);
-      if (!hip_ok(hipGetLastError(), "fill flags")) return LRBMS_E_HIP;
-    }
-  }
-  M->last_stream = st;
-  return LRBMS_OK;
+  const int rc = transport_impl(*M, d_sat, d_flux, d_sat_out, d_flags, (hipStream_t)stream);
+  if (rc == LRBMS_OK) M->last_stream = (hipStream_t)stream;
+  return rc;
 }
+
+int lrbms_fine_create(const lrbms_problem* prob, lrbms_fine** out) {
+  try {
+    if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
+    *out = nullptr;
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    std::unique_ptr<FineModel> F(new FineModel());
+    setup_layout(F->M, prob, nullptr);
+    if ((rc = upload_problem(F->M, prob))) return rc;
+    if (!(F->S.s = fine_solver_create(F->M.g)))
+      return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
+    *out = reinterpret_cast<lrbms_fine*>(F.release());
+    return LRBMS_OK;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_fine_step(lrbms_fine* f, const double* d_sat, double rtol, int32_t maxit, int32_t warm,
+                    double* d_ph, double* d_flux, double* d_sat_out, uint8_t* d_flags,
+                    int32_t* iterations, double* relres) {
+  try {
+    if (!f || !d_sat || !d_ph || !d_flux || !d_sat_out)
+      return (set_error("NULL argument"), LRBMS_E_ARG);
+    if (d_sat_out == d_sat) return (set_error("d_sat_out must not alias d_sat"), LRBMS_E_ARG);
+    if (!(rtol > 0.0) || maxit < 1) return (set_error("rtol must be > 0 and maxit >= 1"), LRBMS_E_ARG);
+    FineModel* F = reinterpret_cast<FineModel*>(f);
+    int it = 0;
+    double rr = 0.0;
+    int rc = fine_solve_checked(F->M, F->S.s, d_sat, GAMMA_SAT, rtol, maxit, d_ph, &it, &rr,
+                                warm != 0);
+    if (iterations) *iterations = it;
+    if (relres) *relres = rr;
+    if (rc) return rc;
+    if (!hip_ok(launch_flux(F->M.g, d_ph, d_sat, d_flux, 0), "flux")) return LRBMS_E_HIP;
+    if ((rc = transport_impl(F->M, d_sat, d_flux, d_sat_out, d_flags, 0))) return rc;
+    if (!hip_ok(hipStreamSynchronize(0), "fine step")) return LRBMS_E_HIP;
+    return LRBMS_OK;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+void lrbms_fine_destroy(lrbms_fine* f) { delete reinterpret_cast<FineModel*>(f); }
+
 
 int lrbms_copy_reduced_system(lrbms_model* m, double* blocks, double* fN) {
   if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);

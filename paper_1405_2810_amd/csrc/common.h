@@ -144,13 +144,14 @@ hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* fl
 // Offline solvers (synchronous, default stream).  FineSolver: the fine SWIP
 // pressure by multigrid-preconditioned CG, its work arrays and coarse
 // hierarchy kept over solves of one problem (mom: moment scratch of the grid,
-// d_status: device status word).  tof_solve: the time of flight by
+// d_status: device status word; warm: start from the contents of d_p).  tof_solve: the time of flight by
 // block-Jacobi sweeps.  Return an LRBMS_* code.
 struct FineSolver;
 FineSolver* fine_solver_create(const Geom& g);
 void fine_solver_destroy(FineSolver* S);
 int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
-                      int maxit, double* d_p, int* d_status, int* iters, double* relres);
+                      int maxit, bool warm, double* d_p, int* d_status, int* iters,
+                      double* relres);
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps);
 // Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and

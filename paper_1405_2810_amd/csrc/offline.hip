@@ -477,26 +477,42 @@ __global__ __launch_bounds__(kBlk) void k_power_start(long long n, double* __res
   v[i] = 0.5 + (double)(h >> 11) * 0x1.0p-53;
 }
 
-// x = 0, r = b; partials of r . r.
-template <int D>
-__global__ __launch_bounds__(kBlk) void k_cg_init(Geom g, const double* __restrict__ b,
+// r = b - A x (WARM: x as given) or x = 0, r = b; partials of r . r and b . b.
+template <int D, bool WARM>
+__global__ __launch_bounds__(kBlk) void k_cg_init(Geom g, const double* __restrict__ K,
+                                                  const double* __restrict__ b,
                                                   double* __restrict__ x, double* __restrict__ r,
-                                                  double* __restrict__ part_rr) {
+                                                  double* __restrict__ part_rr,
+                                                  double* __restrict__ part_bb) {
   constexpr int R = D + 1;
   __shared__ double red[4];
   const int nc = g.ncell;
-  double rr = 0.0;
+  double rr = 0.0, bb = 0.0;
   for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+    double ax[R];
+    if (WARM) {
+      int xc[3];
+      cell_coords(g, c, xc);
+      double u[1 + 2 * D][R];
+      gather<D>(g, x, c, xc, u);
+      stencil_rows<D, 0, R>(g, K, u, c, ax);
+    }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const double v = b[(size_t)k * nc + c];
-      x[(size_t)k * nc + c] = 0.0;
-      r[(size_t)k * nc + c] = v;
-      rr = fma(v, v, rr);
+      const double rv = WARM ? v - ax[k] : v;
+      if (!WARM) x[(size_t)k * nc + c] = 0.0;
+      r[(size_t)k * nc + c] = rv;
+      rr = fma(rv, rv, rr);
+      bb = fma(v, v, bb);
     }
   }
   const double t = block_sum(rr, red);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+  const double t2 = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = t;
+    part_bb[blockIdx.x] = t2;
+  }
 }
 
 // beta = (r.z)_new / (r.z)_old (0 on the first iteration); p = z + beta p,
@@ -883,7 +899,8 @@ static void vcycle(FineSolver& S, double omega0, const double* r, double* z, dou
 
 template <int D>
 static int fine_solve_t(FineSolver& S, double* mom, const double* field, int kind, double rtol,
-                        int maxit, double* d_p, int* d_status, int* iters, double* relres) {
+                        int maxit, bool warm, double* d_p, int* d_status, int* iters,
+                        double* relres) {
   constexpr int R = D + 1;
   const Geom& g = S.g;
   const int nc = g.ncell, nb = S.nb, nbc = S.nbc;
@@ -919,12 +936,20 @@ static int fine_solve_t(FineSolver& S, double* mom, const double* field, int kin
   }
   const double omega0 = kMgOmega0 / lam;
   // conjugate gradients
-  hipLaunchKernelGGL(k_cg_init<D>, dim3(nbc), dim3(kBlk), 0, st, g, S.l.p, d_p, S.r.p, S.prr.p);
+  if (warm)
+    hipLaunchKernelGGL((k_cg_init<D, true>), dim3(nbc), dim3(kBlk), 0, st, g, S.K.p, S.l.p, d_p,
+                       S.r.p, S.prr.p, S.ppap.p);
+  else
+    hipLaunchKernelGGL((k_cg_init<D, false>), dim3(nbc), dim3(kBlk), 0, st, g, S.K.p, S.l.p, d_p,
+                       S.r.p, S.prr.p, S.ppap.p);
   if (hipMemcpy(h.data(), S.prr.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
     return LRBMS_E_HIP;
+  double rr = host_sum(h);
+  if (hipMemcpy(h.data(), S.ppap.p, nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return LRBMS_E_HIP;
   const double bb = host_sum(h);
-  double rr = bb;
-  bool conv = !(rr > rtol * rtol * bb);   // zero right-hand side
+  if (!std::isfinite(rr)) return LRBMS_E_NONFINITE;
+  bool conv = !(rr > rtol * rtol * bb);   // zero right-hand side or a converged start
   int it = 0;
   if (!conv) {
     vcycle<D>(S, omega0, S.r.p, S.z.p, S.prz.p);
@@ -978,10 +1003,12 @@ FineSolver* fine_solver_create(const Geom& g) {
 void fine_solver_destroy(FineSolver* S) { delete S; }
 
 int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
-                      int maxit, double* d_p, int* d_status, int* iters, double* relres) {
-  return S->g.dim == 2
-             ? fine_solve_t<2>(*S, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres)
-             : fine_solve_t<3>(*S, mom, field, kind, rtol, maxit, d_p, d_status, iters, relres);
+                      int maxit, bool warm, double* d_p, int* d_status, int* iters,
+                      double* relres) {
+  return S->g.dim == 2 ? fine_solve_t<2>(*S, mom, field, kind, rtol, maxit, warm, d_p, d_status,
+                                         iters, relres)
+                       : fine_solve_t<3>(*S, mom, field, kind, rtol, maxit, warm, d_p, d_status,
+                                         iters, relres);
 }
 
 template <int D>

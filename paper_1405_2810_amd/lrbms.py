@@ -58,7 +58,7 @@ class OfflineOpts_C(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_train", C.c_int32), ("ne_cap", C.c_int32),
                 ("unit_functions", C.c_int32), ("horizon", C.c_double), ("pcg_rtol", C.c_double),
                 ("pcg_maxit", C.c_int32), ("tof_tol", C.c_double), ("tof_maxit", C.c_int32),
-                ("keep_profiles", C.c_int32)]
+                ("keep_profiles", C.c_int32), ("d_s0", C.c_void_p)]
 
 
 class OfflineReport_C(C.Structure):
@@ -103,6 +103,11 @@ def lib():
                                           C.POINTER(dbl)]
         L.lrbms_time_of_flight.argtypes = [vp, vp, dbl, i32, vp, C.POINTER(i32)]
         L.lrbms_model_export_profiles.argtypes = [vp, vp]
+        L.lrbms_fine_create.argtypes = [vp, C.POINTER(vp)]
+        L.lrbms_fine_step.argtypes = [vp, vp, dbl, i32, i32, vp, vp, vp, vp, C.POINTER(i32),
+                                      C.POINTER(dbl)]
+        L.lrbms_fine_destroy.argtypes = [vp]
+        L.lrbms_fine_destroy.restype = None
         L.lrbms_model_destroy.argtypes = [vp]
         L.lrbms_model_destroy.restype = None
         _lib = L
@@ -213,17 +218,19 @@ class Model:
 
     @classmethod
     def build_offline(cls, prob, mu, ne_cap: int, horizon: float, unit_functions=True,
-                      keep_profiles=True, pcg_rtol=1e-13, pcg_maxit=200000, tof_tol=1e-14,
-                      tof_maxit=100000):
+                      keep_profiles=True, pcg_rtol=1e-13, pcg_maxit=20000, tof_tol=1e-14,
+                      tof_maxit=100000, s0=None):
         """Offline stage on the device (lrbms_build_offline_bases); mu is the
-        (n_train, M) array of training parameters.  Returns (model, report)."""
+        (n_train, M) array of training parameters, s0 an optional device
+        saturation whose flow defines the time of flight.  Returns (model,
+        report)."""
         pc = ProblemC(prob)
         mu = np.ascontiguousarray(np.atleast_2d(mu), dtype=np.float64)
         o = OfflineOpts_C(M=mu.shape[1], n_train=mu.shape[0], ne_cap=int(ne_cap),
                           unit_functions=int(bool(unit_functions)), horizon=float(horizon),
                           pcg_rtol=float(pcg_rtol), pcg_maxit=int(pcg_maxit),
                           tof_tol=float(tof_tol), tof_maxit=int(tof_maxit),
-                          keep_profiles=int(bool(keep_profiles)))
+                          keep_profiles=int(bool(keep_profiles)), d_s0=_ptr(s0) or None)
         rep = OfflineReport_C()
         h = C.c_void_p()
         _check(lib().lrbms_build_offline_bases(pc.ref(), C.byref(o), _ptr(mu), C.byref(h),
@@ -370,7 +377,7 @@ class Model:
         return self._sizes, self._offs
 
 
-def fine_pressure(prob, field, p_out, kind=FIELD_SATURATION, rtol=1e-13, maxit=200000):
+def fine_pressure(prob, field, p_out, kind=FIELD_SATURATION, rtol=1e-13, maxit=20000):
     """Fine SWIP pressure (lrbms_fine_pressure) into the device buffer p_out;
     returns (iterations, relative residual)."""
     pc = ProblemC(prob)
@@ -388,6 +395,34 @@ def time_of_flight(prob, flux, tau_out, tol=0.0, maxit=100000):
     _check(lib().lrbms_time_of_flight(pc.ref(), _ptr(flux), float(tol), int(maxit), _ptr(tau_out),
                                       C.byref(sw)))
     return sw.value
+
+
+class Fine:
+    """Fine reference of Alg. 1 on the device (lrbms_fine handle)."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self._h = C.c_void_p()
+        _check(lib().lrbms_fine_create(ProblemC(prob).ref(), C.byref(self._h)))
+
+    def step(self, sat, ph, flux, sat_out, flags=None, rtol=1e-13, maxit=20000, warm=False):
+        """One time step; returns (CG iterations, relative residual)."""
+        it, rr = C.c_int32(0), C.c_double(0.0)
+        _check(lib().lrbms_fine_step(self._h, _ptr(sat), float(rtol), int(maxit), int(bool(warm)),
+                                     _ptr(ph), _ptr(flux), _ptr(sat_out), _ptr(flags),
+                                     C.byref(it), C.byref(rr)))
+        return it.value, rr.value
+
+    def close(self):
+        if self._h:
+            lib().lrbms_fine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:

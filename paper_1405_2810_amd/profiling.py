@@ -62,20 +62,31 @@ def counters(path: str, counter: str):
     return vals
 
 
+_ASM = ("assemble.hip", "swip.h", "common.h")
+_SOLVER = ("solver.hip", "solver.h", "common.h")
+_TRANSPORT = ("transport.hip", "common.h")
+_OFFLINE = ("offline.hip", "swip.h", "common.h")
 KERNEL_SOURCE = {
-    "k_moments": "assemble.hip", "k_lsq": "assemble.hip", "k_lsq_partial": "assemble.hip", "k_lsq_final": "assemble.hip",
-    "k_affine_sum": "assemble.hip", "k_asm_box": "assemble.hip",
-    "k_reduce_box": "assemble.hip", "k_asm_iface": "assemble.hip",
-    "k_front_asm": "solver.hip", "k_front_factor0": "solver.hip", "k_front_step": "solver.hip",
-    "k_front_backward": "solver.hip", "k_reconstruct": "transport.hip", "k_flux": "transport.hip",
-    "k_transport": "transport.hip", "k_limiter": "transport.hip",
+    "k_moments": _ASM, "k_lsq": _ASM, "k_lsq_partial": _ASM, "k_lsq_final": _ASM,
+    "k_affine_sum": _ASM, "k_asm_box": _ASM, "k_reduce_box": _ASM, "k_asm_iface": _ASM,
+    "k_front_asm": _SOLVER, "k_front_factor0": _SOLVER, "k_front_step": _SOLVER,
+    "k_front_backward": _SOLVER,
+    "k_reconstruct": _TRANSPORT, "k_flux": _TRANSPORT, "k_transport": _TRANSPORT,
+    "k_limiter": _TRANSPORT,
+    **{k: _OFFLINE for k in ("k_fine_stencil", "k_fine_rhs", "k_fine_jacobi", "k_mg_extract",
+                             "k_mg0_down", "k_mg0_up", "k_mgl_down", "k_mgl_up", "k_mg_coarse",
+                             "k_power", "k_power_start", "k_cg_init", "k_cg_direction",
+                             "k_cg_update", "k_tof_setup", "k_tof_sweep")},
 }
 
 
 def source_sha(kernel: str) -> str:
-    path = os.path.join(ROOT, "paper_1405_2810_amd", "csrc", KERNEL_SOURCE[kernel])
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of the source files a kernel is built from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCE[kernel]:
+        with open(os.path.join(ROOT, "paper_1405_2810_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main(argv):

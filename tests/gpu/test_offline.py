@@ -161,14 +161,9 @@ def _processed(g, snaps, cells, cap):
     return len(snaps)
 
 
-@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
-def test_build_offline_bases(L, name):
-    p = make_problem(name)
-    g = Grid(p)
-    params = training_params(p.M, p.n_train, np.random.default_rng(p.seed))
-    ref = build_offline(g, p, params)
-    T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
-    m, rep = L.Model.build_offline(p, params, ne_cap=p.ne_cap, horizon=T, pcg_rtol=RTOL)
+def check_offline(name, p, g, params, ref, m, rep, T):
+    """GPU offline model (m, rep) against the oracle's build_offline result
+    ref: profiles, kept profiles, local bases."""
     log(f"{name}: report {rep}")
     assert rep["n_solves"] == 1 + len(params)
     assert rep["pcg_relres_max"] <= RTOL
@@ -214,3 +209,14 @@ def test_build_offline_bases(L, name):
             worst = max(worst, res / np.linalg.norm(sn))
             assert res <= bound, (E, res, bound)
     log(f"{name}: largest |(I-P_E) s_E| / |s| = {worst:.2e} (eps {eps:.1e})")
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
+def test_build_offline_bases(L, name):
+    p = make_problem(name)
+    g = Grid(p)
+    params = training_params(p.M, p.n_train, np.random.default_rng(p.seed))
+    ref = build_offline(g, p, params)
+    T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
+    m, rep = L.Model.build_offline(p, params, ne_cap=p.ne_cap, horizon=T, pcg_rtol=RTOL)
+    check_offline(name, p, g, params, ref, m, rep, T)
