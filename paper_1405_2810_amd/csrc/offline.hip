@@ -365,38 +365,68 @@ __device__ __forceinline__ int mg_parent(const MgGrid& C, const int (&x)[3]) {
   return (x[0] >> 1) + C.m[0] * ((x[1] >> 1) + C.m[1] * (x[2] >> 1));
 }
 
-// Level l down: e = omega b / d on every cell of a coarse cell's aggregate,
-// coarse right-hand side = sum over the aggregate of b - A e.
+// Level l down for coarse cell q: e = omega b / d on every cell of its
+// aggregate, coarse right-hand side = sum over the aggregate of b - A e.
+// (b may live in LDS or in global memory.)
+template <int D>
+__device__ __forceinline__ double mg_down_value(const MgGrid& L, const MgGrid& C,
+                                                const double* __restrict__ diag,
+                                                const double* __restrict__ off,
+                                                const double* b, int q) {
+  int X[3];
+  mg_coords(C, q, X);
+  double sum = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < (1 << D); ++ch) {
+    const int x[3] = {2 * X[0] + (ch & 1), 2 * X[1] + ((ch >> 1) & 1),
+                      D == 3 ? 2 * X[2] + ((ch >> 2) & 1) : 0};
+    if (x[0] >= L.m[0] || x[1] >= L.m[1] || x[2] >= L.m[2]) continue;
+    const int c = x[0] + L.m[0] * (x[1] + L.m[1] * x[2]);
+    const double bcv = b[c];
+    double res = bcv - kMgOmega * bcv;
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) {
+      const int n = mg_neighbour(L, x, f);
+      if (n >= 0) res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n]);
+    }
+    sum += res;
+  }
+  return sum;
+}
+
+// Level l up for cell c: e = omega b / d + alpha P e_coarse, then
+// e += omega (b - A e) / d.
+template <int D>
+__device__ __forceinline__ double mg_up_value(const MgGrid& L, const MgGrid& C,
+                                              const double* __restrict__ diag,
+                                              const double* __restrict__ off, const double* b,
+                                              const double* ec, int c) {
+  int x[3];
+  mg_coords(L, c, x);
+  const double dc = diag[c];
+  const double ev = kMgOmega * b[c] / dc + kMgAlpha * ec[mg_parent(C, x)];
+  double res = b[c] - dc * ev;
+#pragma unroll
+  for (int f = 0; f < 2 * D; ++f) {
+    const int n = mg_neighbour(L, x, f);
+    if (n < 0) continue;
+    int y[3];
+    mg_coords(L, n, y);
+    res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n] + kMgAlpha * ec[mg_parent(C, y)]);
+  }
+  return ev + kMgOmega * res / dc;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlk) void k_mgl_down(MgGrid L, MgGrid C,
                                                    const double* __restrict__ diag,
                                                    const double* __restrict__ off,
                                                    const double* __restrict__ b,
                                                    double* __restrict__ bc) {
-  for (int q = blockIdx.x * kBlk + threadIdx.x; q < C.n; q += gridDim.x * kBlk) {
-    int X[3];
-    mg_coords(C, q, X);
-    double sum = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < (1 << D); ++ch) {
-      const int x[3] = {2 * X[0] + (ch & 1), 2 * X[1] + ((ch >> 1) & 1),
-                        D == 3 ? 2 * X[2] + ((ch >> 2) & 1) : 0};
-      if (x[0] >= L.m[0] || x[1] >= L.m[1] || x[2] >= L.m[2]) continue;
-      const int c = x[0] + L.m[0] * (x[1] + L.m[1] * x[2]);
-      const double bcv = b[c];
-      double res = bcv - kMgOmega * bcv;
-#pragma unroll
-      for (int f = 0; f < 2 * D; ++f) {
-        const int n = mg_neighbour(L, x, f);
-        if (n >= 0) res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n]);
-      }
-      sum += res;
-    }
-    bc[q] = sum;
-  }
+  for (int q = blockIdx.x * kBlk + threadIdx.x; q < C.n; q += gridDim.x * kBlk)
+    bc[q] = mg_down_value<D>(L, C, diag, off, b, q);
 }
 
-// Level l up: e = omega b / d + alpha P e_coarse, then e += omega (b - A e) / d.
 template <int D>
 __global__ __launch_bounds__(kBlk) void k_mgl_up(MgGrid L, MgGrid C,
                                                  const double* __restrict__ diag,
@@ -404,33 +434,73 @@ __global__ __launch_bounds__(kBlk) void k_mgl_up(MgGrid L, MgGrid C,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ ec,
                                                  double* __restrict__ e) {
-  for (int c = blockIdx.x * kBlk + threadIdx.x; c < L.n; c += gridDim.x * kBlk) {
-    int x[3];
-    mg_coords(L, c, x);
-    const double dc = diag[c];
-    const double ev = kMgOmega * b[c] / dc + kMgAlpha * ec[mg_parent(C, x)];
-    double res = b[c] - dc * ev;
-#pragma unroll
-    for (int f = 0; f < 2 * D; ++f) {
-      const int n = mg_neighbour(L, x, f);
-      if (n < 0) continue;
-      int y[3];
-      mg_coords(L, n, y);
-      res -= off[(size_t)f * L.n + c] * (kMgOmega * b[n] / diag[n] + kMgAlpha * ec[mg_parent(C, y)]);
-    }
-    e[c] = ev + kMgOmega * res / dc;
-  }
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < L.n; c += gridDim.x * kBlk)
+    e[c] = mg_up_value<D>(L, C, diag, off, b, ec, c);
 }
 
-// Coarsest level: e = A^-1 b with the dense symmetric inverse (column reads).
-__global__ __launch_bounds__(kBlk) void k_mg_coarse(int n, const double* __restrict__ inv,
-                                                    const double* __restrict__ b,
-                                                    double* __restrict__ e) {
-  const int i = blockIdx.x * kBlk + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = 0; j < n; ++j) s = fma(inv[(size_t)j * n + i], b[j], s);
-  e[i] = s;
+// The small levels of the V-cycle in one workgroup: from level t (at most
+// kTailCells cells) down to the coarsest, the dense coarse solve, and back up
+// to level t, with every level's b and e in LDS (barriers between the levels
+// instead of launches).
+constexpr int kTailCells = 4096;
+constexpr int kTailLevels = 8;
+constexpr int kTailThreads = 1024;
+struct TailDesc {
+  int nt;                               // levels t .. t+nt-1 (the last is the coarsest)
+  MgGrid grid[kTailLevels];
+  const double* diag[kTailLevels];
+  const double* off[kTailLevels];
+  int lds[kTailLevels];                 // offset of the level's b (its e follows)
+};
+
+template <int D>
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(TailDesc T,
+                                                          const double* __restrict__ inv,
+                                                          const double* __restrict__ bt,
+                                                          double* __restrict__ et) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x;
+  const int n0 = T.grid[0].n;
+  for (int c = tid; c < n0; c += kTailThreads) sm[T.lds[0] + c] = bt[c];
+  __syncthreads();
+  for (int k = 0; k + 1 < T.nt; ++k) {
+    const double* b = sm + T.lds[k];
+    double* bc = sm + T.lds[k + 1];
+    for (int q = tid; q < T.grid[k + 1].n; q += kTailThreads)
+      bc[q] = mg_down_value<D>(T.grid[k], T.grid[k + 1], T.diag[k], T.off[k], b, q);
+    __syncthreads();
+  }
+  {
+    // coarsest: e = A^-1 b.  Thread (row i, column quarter q) sums a quarter
+    // of row i (inv holds A^-1 transposed, so the reads are coalesced over i);
+    // the quarters meet in LDS in a fixed order.
+    const int k = T.nt - 1, n = T.grid[k].n;
+    const double* b = sm + T.lds[k];
+    double* e = sm + T.lds[k] + n;
+    double* part = sm + T.lds[k] + 2 * n;   // 4 n doubles past the last level
+    const int nq = (n + 3) / 4;
+    for (int w = tid; w < 4 * n; w += kTailThreads) {
+      const int i = w % n, q = w / n;
+      const int j0 = q * nq, j1 = min(n, j0 + nq);
+      double s = 0.0;
+      for (int j = j0; j < j1; ++j) s = fma(inv[(size_t)j * n + i], b[j], s);
+      part[q * n + i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kTailThreads)
+      e[i] = (part[i] + part[n + i]) + (part[2 * n + i] + part[3 * n + i]);
+    __syncthreads();
+  }
+  for (int k = T.nt - 2; k >= 0; --k) {
+    const int n = T.grid[k].n;
+    const double* b = sm + T.lds[k];
+    const double* ec = sm + T.lds[k + 1] + T.grid[k + 1].n;
+    double* e = sm + T.lds[k] + n;
+    for (int c = tid; c < n; c += kTailThreads)
+      e[c] = mg_up_value<D>(T.grid[k], T.grid[k + 1], T.diag[k], T.off[k], b, ec, c);
+    __syncthreads();
+  }
+  for (int c = tid; c < n0; c += kTailThreads) et[c] = sm[T.lds[0] + n0 + c];
 }
 
 // Power iteration for the largest eigenvalue of D^-1 A: w = D^-1 A (v * scale);
@@ -757,6 +827,9 @@ struct FineSolver {
   DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, fl, mg, cinv;
   std::vector<MgGrid> grids;           // P0 levels 1 .. L
   std::vector<double*> diag, off, b, e;
+  int tail_start = 0;                  // first level of the single-workgroup tail
+  TailDesc tail{};
+  size_t tail_lds = 0;
   bool have_mg = false;
 };
 
@@ -869,8 +942,32 @@ static int build_hierarchy(FineSolver& S) {
     }
   }
   if (!spd_inverse(A, n)) return LRBMS_E_NOT_SPD;
+  // the tail: levels from the first with at most kTailCells cells
+  int t = 0;
+  while (S.grids[t].n > kTailCells) ++t;
+  t = std::max(t, nl - kTailLevels);
+  S.tail_start = t;
+  S.tail = TailDesc{};
+  S.tail.nt = nl - t;
+  size_t lds = 0;
+  for (int k = 0; k < S.tail.nt; ++k) {
+    S.tail.grid[k] = S.grids[t + k];
+    S.tail.diag[k] = S.diag[t + k];
+    S.tail.off[k] = S.off[t + k];
+    S.tail.lds[k] = (int)lds;
+    lds += 2 * (size_t)S.grids[t + k].n;
+  }
+  lds += 4 * (size_t)S.grids[nl - 1].n;   // partial sums of the coarse solve
+  S.tail_lds = lds * sizeof(double);
+  if (S.tail_lds > 160 * 1024) return LRBMS_E_ARG;
+  if (hipFuncSetAttribute((const void*)k_mg_tail<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)S.tail_lds) != hipSuccess)
+    return LRBMS_E_HIP;
+  std::vector<double> At((size_t)n * n);   // transposed: At[j n + i] = (A^-1)_ij
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) At[(size_t)j * n + i] = A[(size_t)i * n + j];
   if (!S.cinv.alloc((size_t)n * n)) return LRBMS_E_OOM;
-  if (hipMemcpy(S.cinv.p, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpy(S.cinv.p, At.data(), At.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return LRBMS_E_HIP;
   S.have_mg = true;
   return LRBMS_OK;
@@ -880,16 +977,16 @@ static int build_hierarchy(FineSolver& S) {
 template <int D>
 static void vcycle(FineSolver& S, double omega0, const double* r, double* z, double* part_rz) {
   const Geom& g = S.g;
-  const int nl = (int)S.grids.size();
   hipLaunchKernelGGL(k_mg0_down<D>, dim3(std::min(blocks_for(g.ncell), 8192)), dim3(kBlk), 0, 0,
                      g, S.K.p, S.Dinv.p, r, omega0, S.b[0]);
-  for (int l = 0; l + 1 < nl; ++l)
+  const int t = S.tail_start;
+  for (int l = 0; l < t; ++l)
     hipLaunchKernelGGL(k_mgl_down<D>, dim3(std::min(blocks_for(S.grids[l + 1].n), 8192)),
                        dim3(kBlk), 0, 0, S.grids[l], S.grids[l + 1], S.diag[l], S.off[l], S.b[l],
                        S.b[l + 1]);
-  hipLaunchKernelGGL(k_mg_coarse, dim3(blocks_for(S.grids.back().n)), dim3(kBlk), 0, 0,
-                     S.grids.back().n, S.cinv.p, S.b[nl - 1], S.e[nl - 1]);
-  for (int l = nl - 2; l >= 0; --l)
+  hipLaunchKernelGGL(k_mg_tail<D>, dim3(1), dim3(kTailThreads), S.tail_lds, 0, S.tail, S.cinv.p,
+                     S.b[t], S.e[t]);
+  for (int l = t - 1; l >= 0; --l)
     hipLaunchKernelGGL(k_mgl_up<D>, dim3(std::min(blocks_for(S.grids[l].n), 8192)), dim3(kBlk), 0,
                        0, S.grids[l], S.grids[l + 1], S.diag[l], S.off[l], S.b[l], S.e[l + 1],
                        S.e[l]);
