@@ -395,9 +395,10 @@ __device__ __forceinline__ double rcp_nr(double d) {
 // Columns c0 .. c0+15 of the tile, rows c0 .. 63, by wave 0: lane = row,
 // right-looking on unnormalized columns.  At pivot k the raw column k (final
 // since pivot k-1) is broadcast through LDS while the reciprocal of the pivot
-// is formed, and the Schur update uses a(i,k) / d_k, so the serial chain per
-// pivot is the reciprocal and one multiply-add; 1/sqrt(d_k), for the scaling
-// of the stored factor, is computed beside it.  The LDS requests of one wave
+// is formed, and the Schur update uses a(i,k) / d_k; the next column's
+// multiplier a(k+1, k) comes by readlane, so the serial chain per pivot is the
+// reciprocal and one multiply-add; 1/sqrt(d_k), for the scaling of the stored
+// factor, is computed beside it.  The LDS requests of one wave
 // complete in issue order, so the broadcast needs no wait beyond the use of
 // the loaded values.  Non-positive or non-finite pivots set the status word
 // and are replaced by 1 so that the results stay finite.  With inv, the
@@ -412,18 +413,22 @@ __device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool 
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    double* cb = A.cb[k & 1];
-    cb[lane] = a[k];
-    __builtin_amdgcn_wave_barrier();
+    // the next pivot column needs only a(k+1, k), taken by readlane; the
+    // later columns get theirs through LDS, off the serial chain
     double dk = readlane_f64(a[k], k);
+    const double ak1 = (k + 1 < 16) ? readlane_f64(a[k], k + 1) : 0.0;
+    double* cb = A.cb[k & 1];
+    if (k + 2 < 16) cb[lane] = a[k];
+    __builtin_amdgcn_wave_barrier();
     const bool ok = (dk > 0.0) && (dk < 1.0e300);
     bad = bad || !ok;
     dk = ok ? dk : 1.0;
     ds[k] = dk;
     ys[k] = rsqrt_nr(dk);
     const double mk = a[k] * rcp_nr(dk);
+    if (k + 1 < 16) a[k + 1] = fma(-mk, ak1, a[k + 1]);
 #pragma unroll
-    for (int t = k + 1; t < 16; ++t) a[t] = fma(-mk, cb[t], a[t]);
+    for (int t = k + 2; t < 16; ++t) a[t] = fma(-mk, cb[t], a[t]);
     __builtin_amdgcn_wave_barrier();
   }
   if (bad && lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
