@@ -407,7 +407,24 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
   if (!hip_ok(assemble_prepare(g, M.subs, M.max_ne, M.asm_layout, b), "assembly layout"))
     return LRBMS_E_OOM;
   // solver
-  if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, M.leaf_max, M.plan)) {
+  // leaf size of the nested dissection: the one whose launch sequence is
+  // shortest.  Every level costs an assembly, a first-tile factorization and
+  // a backward launch, every further panel a step launch, each of roughly the
+  // same latency (about 64 us per level and 28.5 us per step on gfx950 at
+  // these sizes); leaves above 8 boxes lengthen the leaf fronts' steps.
+  double best = 1e300;
+  for (int leaf : {2, 4, 8}) {
+    SolverPlan P;
+    if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, leaf, P)) continue;
+    double cost = 0.0;
+    for (int h = 0; h < P.nlevels; ++h) cost += 64.0 + 28.5 * (double)P.step_items[h].size();
+    if (cost < best) {
+      best = cost;
+      M.leaf_max = leaf;
+      M.plan = std::move(P);
+    }
+  }
+  if (best == 1e300) {
     set_error("solver symbolic analysis failed");
     return LRBMS_E_ARG;
   }

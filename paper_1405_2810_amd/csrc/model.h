@@ -35,7 +35,7 @@ struct Model {
   int* d_status = nullptr;
   AsmLayout asm_layout;
   // reduced solver
-  int leaf_max = 2;
+  int leaf_max = 2;             // leaf size of the nested dissection (chosen per model)
   SolverPlan plan;
   SolverDev sdev;
   bool assembled = false;
