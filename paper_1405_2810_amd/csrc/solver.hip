@@ -407,9 +407,15 @@ __device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool 
   const int lane = threadIdx.x & 63;
   const int row = c0 + lane;
   const bool act = row < kNB;
+  const int rr = act ? row : kNB - 1;
   double a[16], ys[16], ds[16];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) a[t] = (act && c0 + t <= row) ? D[row][c0 + t] : 0.0;
+  for (int t = 0; t < 16; ++t) a[t] = D[rr][c0 + t];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const long long keep = (act && c0 + t <= row) ? -1ll : 0ll;
+    a[t] = __longlong_as_double(__double_as_longlong(a[t]) & keep);
+  }
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -436,11 +442,10 @@ __device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool 
 #pragma unroll
   for (int k = 0; k < 16; ++k)
     a[k] = (lane > k) ? a[k] * ys[k] : ((lane == k) ? ds[k] * ys[k] : 0.0);
-  if (lane < 16) {
+  double yl = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (lane == k) A.dinv[c0 + k] = ys[k];
-  }
+  for (int k = 0; k < 16; ++k) yl = (lane == k) ? ys[k] : yl;
+  if (lane < 16) A.dinv[c0 + lane] = yl;
   if (act) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) D[row][c0 + t] = (c0 + t <= row) ? a[t] : 0.0;
