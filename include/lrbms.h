@@ -192,6 +192,29 @@ int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_
 int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double tol,
                          int32_t maxit, double* d_tau, int32_t* sweeps);
 
+/* Greedy basis construction (Alg. 2 step 2, the error-driven extension) on the
+ * device, with the true error measure: the energy norm |p_H(mu) - p_h(mu)| of
+ * b_h(., .; sum_q mubar_q Lambda^q).  Steps 1a-1c as lrbms_build_offline_bases
+ * (options M, n_train, horizon, solver tolerances, d_s0, keep_profiles; ne_cap
+ * and unit_functions are not used).  Then the fine snapshots of all n_train
+ * training parameters are computed as one batch and kept on the device; each
+ * iteration solves, for every training parameter, the reduced system of the
+ * current local bases (affine terms with theta = mu), measures the error,
+ * picks the worst parameter (first of equal maxima) and extends every local
+ * basis by Gram-Schmidt with its snapshot.  Starts from empty local bases;
+ * stops when the largest error is <= tol, the total size reaches n_max, no
+ * basis grows, or after 63 extensions.
+ *  mu:      host [n_train][M];  mu_bar: host [M] or NULL (1/M each)
+ *  chosen:  host [max_iter] (nullable): the parameter added in each extension
+ *  errors:  host [max_iter] (nullable): the largest error of each evaluation
+ *  n_iter:  host (nullable): number of evaluations (extensions + 1 at most)
+ * Synchronous.  Errors: as lrbms_build_offline_bases; LRBMS_E_ARG when a box
+ * ends with no basis function.                                                 */
+int lrbms_build_greedy_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
+                             const double* mu, int32_t n_max, double tol, const double* mu_bar,
+                             lrbms_model** out, int32_t* chosen, double* errors,
+                             int32_t max_iter, int32_t* n_iter, lrbms_offline_report* report);
+
 /* Fine reference: the high-dimensional IMPES scheme of Alg. 1 on the device
  * (the accuracy reference that the LRBMS online step replaces).  A handle owns
  * the problem on the device and the fine solver's work arrays and coarse

@@ -387,7 +387,7 @@ static void set_unit_figures(Model& M) {
   M.unit_bytes[KK_LIMITER] = 8.0 * (2.0 * r * n + nf) + n;
 }
 
-int model_finish(Model& M, const double* basis, int nprof, const double* profiles) {
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq) {
   Geom& g = M.g;
   long long& b = M.dev_bytes;
   if (!dev_copy(&M.d_subs, M.subs.data(), M.subs.size(), b)) return LRBMS_E_OOM;
@@ -444,10 +444,11 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
         for (size_t k = 0; k < L; ++k) s += profiles[i * L + k] * profiles[j * L + k];
         G[i * nprof + j] = s;
       }
-    if (!small_cholesky(G, nprof)) {
+    if (lsq && !small_cholesky(G, nprof)) {
       set_error("profile Gram matrix is not positive definite (profiles must be independent)");
       return LRBMS_E_ARG;
     }
+    M.lsq_ok = lsq;
     if (!dev_copy(&M.d_prof, profiles, (size_t)nprof * L, b) ||
         !dev_copy(&M.d_gchol, G.data(), G.size(), b) || !dev_zero(&M.d_theta, (size_t)nprof, b))
       return LRBMS_E_OOM;
@@ -495,7 +496,7 @@ int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double
       return (set_error("local basis sizes must be in 1..63"), LRBMS_E_ARG);
   setup_layout(*M, p, sizes);
   if ((rc = upload_problem(*M, p))) return rc;
-  if ((rc = model_finish(*M, basis, nprof, profiles))) return rc;
+  if ((rc = model_finish(*M, basis, nprof, profiles, true))) return rc;
   *out = reinterpret_cast<lrbms_model*>(M.release());
   return LRBMS_OK;
 }
@@ -562,6 +563,8 @@ static void local_gram_schmidt(const Model& M, int nsnap, const double* snaps, i
 struct DevArray {
   double* p = nullptr;
   bool alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
     return hip_ok(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(double)), "hipMalloc");
   }
   ~DevArray() {
@@ -676,67 +679,107 @@ static std::vector<int> independent_profiles(const std::vector<double>& prof, in
   return keep;
 }
 
+// State of the offline stage: the problem on the device, the fine solver, the
+// profiles and the solver figures.
+struct OfflineCtx {
+  Model tmp;
+  FineSolverHandle fs;
+  DevArray field;
+  std::vector<double> prof;   // [M][r*ncell]
+  lrbms_offline_report R{};
+  size_t L = 0;
+  void note(int it, double rr) {
+    R.n_solves += 1;
+    R.pcg_iters_max = std::max(R.pcg_iters_max, it);
+    R.pcg_iters_total += it;
+    R.pcg_relres_max = std::max(R.pcg_relres_max, rr);
+  }
+};
+
+static int check_offline_opts(const lrbms_offline_opts* o, const double* mu, bool need_cap) {
+  if (!o || !mu) return (set_error("options or training parameters missing"), LRBMS_E_ARG);
+  if (o->M < 3 || o->M > kMaxProfiles) return (set_error("M must be in 3..64"), LRBMS_E_ARG);
+  if (o->n_train < 1) return (set_error("n_train must be >= 1"), LRBMS_E_ARG);
+  if (need_cap && (o->ne_cap < 1 || o->ne_cap > 63))
+    return (set_error("ne_cap must be in 1..63"), LRBMS_E_ARG);
+  if (!(o->horizon > 0.0)) return (set_error("horizon must be > 0"), LRBMS_E_ARG);
+  if (!(o->pcg_rtol > 0.0) || o->pcg_maxit < 1 || !(o->tof_tol >= 0.0) || o->tof_maxit < 1)
+    return (set_error("invalid solver tolerances or iteration limits"), LRBMS_E_ARG);
+  for (long long i = 0; i < (long long)o->n_train * o->M; ++i)
+    if (!std::isfinite(mu[i])) return (set_error("training parameters must be finite"), LRBMS_E_ARG);
+  return LRBMS_OK;
+}
+
+// Alg. 2 step 1: pressure and velocity at s0, time of flight, profiles.
+static int offline_profiles(const lrbms_problem* p, const lrbms_offline_opts* o, OfflineCtx& C) {
+  int rc;
+  setup_layout(C.tmp, p, nullptr);
+  if ((rc = upload_problem(C.tmp, p))) return rc;
+  const Geom& g = C.tmp.g;
+  C.L = (size_t)g.r * g.ncell;
+  DevArray flux, tau;
+  if (!flux.alloc(g.nface) || !tau.alloc(C.L) || !C.field.alloc(C.L)) return LRBMS_E_OOM;
+  if (!(C.fs.s = fine_solver_create(g)))
+    return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
+  int it = 0;
+  double rr = 0.0;
+  const double* s0 = o->d_s0 ? o->d_s0 : C.tmp.d_scratch_sat;   // zeros unless given
+  rc = fine_solve_checked(C.tmp, C.fs.s, s0, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit,
+                          C.tmp.d_scratch_ph, &it, &rr);
+  C.note(it, rr);
+  if (rc) return rc;
+  if (!hip_ok(launch_flux(g, C.tmp.d_scratch_ph, s0, flux.p, 0), "initial flux")) return LRBMS_E_HIP;
+  if ((rc = tof_checked(C.tmp, flux.p, o->tof_tol, o->tof_maxit, tau.p, &C.R.tof_sweeps))) return rc;
+  std::vector<double> h_tau(C.L);
+  if (!hip_ok(hipMemcpy(h_tau.data(), tau.p, C.L * sizeof(double), hipMemcpyDeviceToHost), "tau"))
+    return LRBMS_E_HIP;
+  mobility_profiles(g, p, h_tau, o->M, o->horizon, C.prof);
+  return LRBMS_OK;
+}
+
+// The field sum_q w_q Lambda^q, uploaded into C.field.
+static int combine_profiles(OfflineCtx& C, int nq, const double* w) {
+  std::vector<double> gam(C.L, 0.0);
+  for (int q = 0; q < nq; ++q) {
+    const double* f = C.prof.data() + (size_t)q * C.L;
+    for (size_t k = 0; k < C.L; ++k) gam[k] += w[q] * f[k];
+  }
+  return hip_ok(hipMemcpy(C.field.p, gam.data(), C.L * sizeof(double), hipMemcpyHostToDevice),
+                "gamma")
+             ? LRBMS_OK
+             : LRBMS_E_HIP;
+}
+
+static std::vector<double> kept_profiles(const OfflineCtx& C, int nq, bool keep) {
+  std::vector<double> kept;
+  if (keep)
+    for (int q : independent_profiles(C.prof, nq, C.L))
+      kept.insert(kept.end(), C.prof.begin() + (size_t)q * C.L,
+                  C.prof.begin() + (size_t)(q + 1) * C.L);
+  return kept;
+}
+
 static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* o,
                               const double* mu, lrbms_model** out, lrbms_offline_report* rep) {
   if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
   *out = nullptr;
   int rc = check_problem(p);
   if (rc) return rc;
-  if (!o || !mu) return (set_error("options or training parameters missing"), LRBMS_E_ARG);
-  if (o->M < 3 || o->M > kMaxProfiles) return (set_error("M must be in 3..64"), LRBMS_E_ARG);
-  if (o->n_train < 1) return (set_error("n_train must be >= 1"), LRBMS_E_ARG);
-  if (o->ne_cap < 1 || o->ne_cap > 63) return (set_error("ne_cap must be in 1..63"), LRBMS_E_ARG);
-  if (!(o->horizon > 0.0)) return (set_error("horizon must be > 0"), LRBMS_E_ARG);
-  if (!(o->pcg_rtol > 0.0) || o->pcg_maxit < 1 || !(o->tof_tol >= 0.0) || o->tof_maxit < 1)
-    return (set_error("invalid solver tolerances or iteration limits"), LRBMS_E_ARG);
-  for (long long i = 0; i < (long long)o->n_train * o->M; ++i)
-    if (!std::isfinite(mu[i])) return (set_error("training parameters must be finite"), LRBMS_E_ARG);
-  lrbms_offline_report R{};
-  Model tmp;
-  setup_layout(tmp, p, nullptr);
-  if ((rc = upload_problem(tmp, p))) return rc;
-  const Geom& g = tmp.g;
-  const size_t L = (size_t)g.r * g.ncell;
-  auto note = [&](int it, double rr) {
-    R.n_solves += 1;
-    R.pcg_iters_max = std::max(R.pcg_iters_max, it);
-    R.pcg_iters_total += it;
-    R.pcg_relres_max = std::max(R.pcg_relres_max, rr);
-  };
-  // Alg. 2 step 1a-1b: pressure and velocity at s = 0, time of flight
-  DevArray flux, tau, field, snap;
-  if (!flux.alloc(g.nface) || !tau.alloc(L) || !field.alloc(L) || !snap.alloc(L)) return LRBMS_E_OOM;
-  FineSolverHandle fs;
-  if (!(fs.s = fine_solver_create(g))) return (set_error("fine solver allocation failed"), LRBMS_E_OOM);
-  int it = 0;
-  double rr = 0.0;
-  const double* s0 = o->d_s0 ? o->d_s0 : tmp.d_scratch_sat;   // zeros unless given
-  rc = fine_solve_checked(tmp, fs.s, s0, GAMMA_SAT, o->pcg_rtol, o->pcg_maxit, tmp.d_scratch_ph,
-                          &it, &rr);
-  note(it, rr);
-  if (rc) return rc;
-  if (!hip_ok(launch_flux(g, tmp.d_scratch_ph, s0, flux.p, 0), "initial flux")) return LRBMS_E_HIP;
-  if ((rc = tof_checked(tmp, flux.p, o->tof_tol, o->tof_maxit, tau.p, &R.tof_sweeps))) return rc;
-  std::vector<double> h_tau(L);
-  if (!hip_ok(hipMemcpy(h_tau.data(), tau.p, L * sizeof(double), hipMemcpyDeviceToHost), "tau"))
-    return LRBMS_E_HIP;
-  // Alg. 2 step 1c: profiles
-  std::vector<double> prof;
-  mobility_profiles(g, p, h_tau, o->M, o->horizon, prof);
+  if ((rc = check_offline_opts(o, mu, true))) return rc;
+  OfflineCtx C;
+  if ((rc = offline_profiles(p, o, C))) return rc;
+  const size_t L = C.L;
   // snapshots at gamma = sum_q mu_q Lambda^q
-  std::vector<double> snaps((size_t)o->n_train * L), gam(L);
+  DevArray snap;
+  if (!snap.alloc(L)) return LRBMS_E_OOM;
+  std::vector<double> snaps((size_t)o->n_train * L);
   for (int i = 0; i < o->n_train; ++i) {
-    std::fill(gam.begin(), gam.end(), 0.0);
-    for (int q = 0; q < o->M; ++q) {
-      const double m = mu[(size_t)i * o->M + q];
-      const double* f = prof.data() + (size_t)q * L;
-      for (size_t k = 0; k < L; ++k) gam[k] += m * f[k];
-    }
-    if (!hip_ok(hipMemcpy(field.p, gam.data(), L * sizeof(double), hipMemcpyHostToDevice), "gamma"))
-      return LRBMS_E_HIP;
-    rc = fine_solve_checked(tmp, fs.s, field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit, snap.p,
-                            &it, &rr);
-    note(it, rr);
+    if ((rc = combine_profiles(C, o->M, mu + (size_t)i * o->M))) return rc;
+    int it = 0;
+    double rr = 0.0;
+    rc = fine_solve_checked(C.tmp, C.fs.s, C.field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit,
+                            snap.p, &it, &rr);
+    C.note(it, rr);
     if (rc) return rc;
     if (!hip_ok(hipMemcpy(snaps.data() + (size_t)i * L, snap.p, L * sizeof(double),
                           hipMemcpyDeviceToHost),
@@ -746,17 +789,175 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
   // Alg. 2 step 2e: local bases
   std::vector<int> sizes;
   std::vector<double> basis;
-  local_gram_schmidt(tmp, o->n_train, snaps.data(), o->ne_cap, o->unit_functions != 0, sizes, basis);
-  for (int s : sizes)
-    if (s < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
-  std::vector<double> kept;
-  if (o->keep_profiles) {
-    for (int q : independent_profiles(prof, o->M, L))
-      kept.insert(kept.end(), prof.begin() + (size_t)q * L, prof.begin() + (size_t)(q + 1) * L);
+  local_gram_schmidt(C.tmp, o->n_train, snaps.data(), o->ne_cap, o->unit_functions != 0, sizes,
+                     basis);
+  for (int sz : sizes)
+    if (sz < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
+  const std::vector<double> kept = kept_profiles(C, o->M, o->keep_profiles != 0);
+  C.R.n_profiles_kept = (int)(kept.size() / L);
+  if (rep) *rep = C.R;
+  return model_create_impl(p, sizes.data(), basis.data(), C.R.n_profiles_kept,
+                           kept.empty() ? nullptr : kept.data(), out);
+}
+
+// Gram-Schmidt extension of one local basis (L2(E), two passes, rejection of
+// remaining norms <= 1e-8 of the original).
+static bool gs_extend(std::vector<std::vector<double>>& B, std::vector<double> v) {
+  double nv = 0.0;
+  for (double x : v) nv += x * x;
+  nv = std::sqrt(nv);
+  if (nv == 0.0) return false;
+  for (int pass = 0; pass < 2; ++pass)
+    for (auto& b : B) {
+      double d = 0.0;
+      for (size_t i = 0; i < v.size(); ++i) d += b[i] * v[i];
+      for (size_t i = 0; i < v.size(); ++i) v[i] -= d * b[i];
+    }
+  double nw = 0.0;
+  for (double x : v) nw += x * x;
+  nw = std::sqrt(nw);
+  if (nw <= 1e-8 * nv) return false;
+  for (auto& x : v) x /= nw;
+  B.push_back(std::move(v));
+  return true;
+}
+
+// Alg. 2 step 2 (the greedy basis extension) with the true energy-norm error
+// of Sec. 6: the fine snapshots of the whole training set are computed first
+// (one batch of fine solves), then every iteration solves the reduced system
+// of every training parameter on the device (affine terms with theta = mu),
+// measures |p_H - p_h| in the energy norm of b_h(., .; sum_q mubar_q Lambda^q),
+// and extends every local basis with the worst parameter's snapshot.
+static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o,
+                             const double* mu, int n_max, double tol, const double* mu_bar,
+                             lrbms_model** out, int32_t* chosen, double* errors, int max_iter,
+                             int32_t* n_iter, lrbms_offline_report* rep) {
+  if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
+  *out = nullptr;
+  int rc = check_problem(p);
+  if (rc) return rc;
+  if ((rc = check_offline_opts(o, mu, false))) return rc;
+  if (n_max < 1 || !(tol >= 0.0)) return (set_error("n_max must be >= 1 and tol >= 0"), LRBMS_E_ARG);
+  if ((chosen || errors) && max_iter < 1) return (set_error("max_iter must be >= 1"), LRBMS_E_ARG);
+  OfflineCtx C;
+  if ((rc = offline_profiles(p, o, C))) return rc;
+  const size_t L = C.L;
+  const int nt = o->n_train, nq = o->M;
+  // every training snapshot, resident on the device
+  DevArray snaps, ph, pN;
+  if (!snaps.alloc((size_t)nt * L) || !ph.alloc(L)) return LRBMS_E_OOM;
+  for (int i = 0; i < nt; ++i) {
+    if ((rc = combine_profiles(C, nq, mu + (size_t)i * nq))) return rc;
+    int it = 0;
+    double rr = 0.0;
+    rc = fine_solve_checked(C.tmp, C.fs.s, C.field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit,
+                            snaps.p + (size_t)i * L, &it, &rr);
+    C.note(it, rr);
+    if (rc) return rc;
   }
-  R.n_profiles_kept = (int)(kept.size() / L);
-  if (rep) *rep = R;
-  return model_create_impl(p, sizes.data(), basis.data(), R.n_profiles_kept,
+  // the energy norm of the error measure
+  std::vector<double> wbar(nq, 1.0 / nq);
+  if (mu_bar)
+    for (int q = 0; q < nq; ++q) wbar[q] = mu_bar[q];
+  if ((rc = combine_profiles(C, nq, wbar.data()))) return rc;
+  if ((rc = fine_energy_setup(C.fs.s, C.tmp.d_mom, C.field.p))) return rc;
+  // local bases, empty at the start
+  const Model& T = C.tmp;
+  std::vector<std::vector<int>> cells(T.n_sub);
+  for (int sb = 0; sb < T.n_sub; ++sb) {
+    const Sub& S = T.subs[sb];
+    const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+    for (int l = 0; l < S.nE; ++l) {
+      const int x = S.lo[0] + l % bx, y = S.lo[1] + (l / bx) % by, z = S.lo[2] + l / (bx * by);
+      cells[sb].push_back(x + T.g.n[0] * (y + T.g.n[1] * z));
+    }
+  }
+  std::vector<std::vector<std::vector<double>>> B(T.n_sub);
+  std::vector<double> err(nt), h_snap(L);
+  int iters = 0;
+  const int r = T.g.r, nc = T.g.ncell;
+  auto flat_basis = [&](std::vector<int>& sizes, std::vector<double>& basis) {
+    sizes.assign(T.n_sub, 0);
+    basis.clear();
+    for (int sb = 0; sb < T.n_sub; ++sb) {
+      sizes[sb] = (int)B[sb].size();
+      for (auto& v : B[sb]) basis.insert(basis.end(), v.begin(), v.end());
+    }
+  };
+  while (true) {
+    int total = 0;
+    for (auto& b : B) total += (int)b.size();
+    if (total == 0) {
+      for (int i = 0; i < nt; ++i)
+        if ((rc = fine_energy_diff(C.fs.s, snaps.p + (size_t)i * L, nullptr, &err[i]))) return rc;
+    } else {
+      // the reduced model of the current bases with every profile (theta = mu)
+      std::vector<int> sizes;
+      std::vector<double> basis;
+      flat_basis(sizes, basis);
+      for (int sz : sizes)
+        if (sz < 1 || sz > 63)
+          return (set_error("greedy: a local basis is empty or above 63 functions"), LRBMS_E_ARG);
+      std::unique_ptr<Model> RM(new Model());
+      setup_layout(*RM, p, sizes.data());
+      if ((rc = upload_problem(*RM, p))) return rc;
+      if ((rc = model_finish(*RM, basis.data(), nq, C.prof.data(), false))) return rc;
+      if (!pN.alloc(RM->N)) return LRBMS_E_OOM;
+      for (int i = 0; i < nt; ++i) {
+        if (!hip_ok(hipMemcpy(RM->d_theta, mu + (size_t)i * nq, nq * sizeof(double),
+                              hipMemcpyHostToDevice),
+                    "theta") ||
+            !hip_ok(launch_affine_sum(RM->d_c, RM->d_bq, RM->nblk, RM->d_theta, nq, RM->d_blocks, 0),
+                    "affine sum") ||
+            !hip_ok(launch_affine_sum(RM->d_e, RM->d_dq, RM->N, RM->d_theta, nq, RM->d_fN, 0),
+                    "affine sum") ||
+            !hip_ok(solver_factor_solve(RM->plan, RM->sdev, RM->d_blocks, RM->d_fN, pN.p,
+                                        RM->d_status, 0),
+                    "reduced solve") ||
+            !hip_ok(launch_reconstruct(RM->g, RM->d_subs, RM->n_sub, RM->d_tiles, RM->n_tiles,
+                                       RM->d_phi, pN.p, ph.p, 0),
+                    "reconstruct"))
+          return LRBMS_E_HIP;
+        if ((rc = fine_energy_diff(C.fs.s, ph.p, snaps.p + (size_t)i * L, &err[i]))) return rc;
+      }
+      int st = 0;
+      if (!hip_ok(hipMemcpy(&st, RM->d_status, sizeof(int), hipMemcpyDeviceToHost), "status"))
+        return LRBMS_E_HIP;
+      if (st) return (set_error("greedy: reduced matrix not positive definite"), st);
+    }
+    int k = 0;
+    for (int i = 0; i < nt; ++i) {
+      err[i] = std::sqrt(std::max(err[i], 0.0));
+      if (err[i] > err[k]) k = i;
+    }
+    if (errors && iters < max_iter) errors[iters] = err[k];
+    ++iters;
+    if (err[k] <= tol || total >= n_max || iters > 63) break;
+    if (chosen && iters - 1 < max_iter) chosen[iters - 1] = k;
+    if (!hip_ok(hipMemcpy(h_snap.data(), snaps.p + (size_t)k * L, L * sizeof(double),
+                          hipMemcpyDeviceToHost),
+                "snapshot"))
+      return LRBMS_E_HIP;
+    bool grew = false;
+    for (int sb = 0; sb < T.n_sub; ++sb) {
+      const int nE = (int)cells[sb].size();
+      std::vector<double> v((size_t)r * nE);
+      for (int kk = 0; kk < r; ++kk)
+        for (int l = 0; l < nE; ++l) v[(size_t)kk * nE + l] = h_snap[(size_t)kk * nc + cells[sb][l]];
+      grew = gs_extend(B[sb], std::move(v)) || grew;
+    }
+    if (!grew) break;
+  }
+  if (n_iter) *n_iter = iters;
+  std::vector<int> sizes;
+  std::vector<double> basis;
+  flat_basis(sizes, basis);
+  for (int sz : sizes)
+    if (sz < 1) return (set_error("greedy: a box received an empty local basis"), LRBMS_E_ARG);
+  const std::vector<double> kept = kept_profiles(C, nq, o->keep_profiles != 0);
+  C.R.n_profiles_kept = (int)(kept.size() / L);
+  if (rep) *rep = C.R;
+  return model_create_impl(p, sizes.data(), basis.data(), C.R.n_profiles_kept,
                            kept.empty() ? nullptr : kept.data(), out);
 }
 
@@ -879,6 +1080,8 @@ int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, voi
     return (set_error("unknown assembly mode"), LRBMS_E_ARG);
   if (mode != LRBMS_DIRECT && M->nprof == 0)
     return (set_error("this mode needs mobility profiles"), LRBMS_E_STATE);
+  if (mode != LRBMS_DIRECT && !M->lsq_ok)
+    return (set_error("this model's profiles admit no least-squares fit"), LRBMS_E_STATE);
   const int all = PART_GAMMA | PART_PEN | PART_RHS_CONST | PART_RHS_GAMMA;
   if (mode == LRBMS_DIRECT) {
     if (!hip_ok(launch_moments(g, d_sat, GAMMA_SAT, nullptr, 0, 0, M->d_mom, st), "moments"))
@@ -1142,6 +1345,19 @@ int lrbms_build_offline_bases(const lrbms_problem* prob, const lrbms_offline_opt
                               const double* mu, lrbms_model** out, lrbms_offline_report* report) {
   try {
     return build_offline_impl(prob, opts, mu, out, report);
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return LRBMS_E_OOM;
+  }
+}
+
+int lrbms_build_greedy_bases(const lrbms_problem* prob, const lrbms_offline_opts* opts,
+                             const double* mu, int32_t n_max, double tol, const double* mu_bar,
+                             lrbms_model** out, int32_t* chosen, double* errors,
+                             int32_t max_iter, int32_t* n_iter, lrbms_offline_report* report) {
+  try {
+    return build_greedy_impl(prob, opts, mu, n_max, tol, mu_bar, out, chosen, errors, max_iter,
+                             n_iter, report);
   } catch (const std::exception& e) {
     set_error(e.what());
     return LRBMS_E_OOM;

@@ -152,6 +152,10 @@ void fine_solver_destroy(FineSolver* S);
 int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
                       int maxit, bool warm, double* d_p, int* d_status, int* iters,
                       double* relres);
+// Energy norm |a - b|^2 (b may be NULL) under b_h(., .; field), the field
+// given once by fine_energy_setup (the greedy error measure).
+int fine_energy_setup(FineSolver* S, double* mom, const double* field);
+int fine_energy_diff(FineSolver* S, const double* a, const double* b, double* out);
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps);
 // Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and

@@ -25,6 +25,7 @@ struct Model {
   double* d_fN = nullptr;
   // affine decomposition (Sec. 4.4)
   int nprof = 0, lsq_blocks = 0;
+  bool lsq_ok = false;          // the profile Gram matrix is factored (least-squares fit)
   double *d_prof = nullptr, *d_gchol = nullptr, *d_theta = nullptr, *d_partial = nullptr;
   double *d_c = nullptr, *d_bq = nullptr, *d_e = nullptr, *d_dq = nullptr;
   // fine-grid scratch
@@ -47,7 +48,9 @@ struct Model {
   ~Model();
 };
 
-int model_finish(Model& M, const double* basis, int nprof, const double* profiles);
+// lsq: the profiles are independent and the model fits theta from s (AFFINE,
+// DIRECT_FIT); without it the affine terms serve a caller-given theta only.
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq);
 int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double* basis, int nprof,
                       const double* profiles, lrbms_model** out);
 

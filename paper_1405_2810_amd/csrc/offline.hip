@@ -660,6 +660,37 @@ __global__ __launch_bounds__(kBlk) void k_cg_update(Geom g, double* __restrict__
   if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
 }
 
+// ---- energy norm of the greedy error measure ---------------------------------
+// partials of e . (A e) for the operator held in K
+template <int D>
+__global__ __launch_bounds__(kBlk) void k_energy(Geom g, const double* __restrict__ K,
+                                                 const double* __restrict__ e,
+                                                 double* __restrict__ part) {
+  constexpr int R = D + 1;
+  __shared__ double red[4];
+  const int nc = g.ncell;
+  double acc = 0.0;
+  for (int c = blockIdx.x * kBlk + threadIdx.x; c < nc; c += gridDim.x * kBlk) {
+    int xc[3];
+    cell_coords(g, c, xc);
+    double u[1 + 2 * D][R];
+    gather<D>(g, e, c, xc, u);
+    double y[R];
+    stencil_rows<D, 0, R>(g, K, u, c, y);
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc = fma(u[0][k], y[k], acc);
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlk) void k_diff(long long n, const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               double* __restrict__ out) {
+  const long long i = blockIdx.x * (long long)kBlk + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
 // ---- time of flight -----------------------------------------------------------
 // Per cell: Minv (r x r, the inverse of the cell block: volume term with the
 // RT0 velocity of the face fluxes and the own trace on outflow faces), C (one
@@ -825,6 +856,8 @@ struct FineSolver {
   Geom g{};
   int nb = 0, nbc = 0;
   DevBuf K, Dinv, l, r, z, pv, Ap, prz, prr, ppap, fl, mg, cinv;
+  DevBuf Kbar, ework;                  // operator of the energy norm, difference vector
+  bool have_bar = false;
   std::vector<MgGrid> grids;           // P0 levels 1 .. L
   std::vector<double*> diag, off, b, e;
   int tail_start = 0;                  // first level of the single-workgroup tail
@@ -1098,6 +1131,48 @@ FineSolver* fine_solver_create(const Geom& g) {
 }
 
 void fine_solver_destroy(FineSolver* S) { delete S; }
+
+// The operator b_h(., .; gamma) of a mobility field, kept for energy norms.
+template <int D>
+static int energy_setup_t(FineSolver& S, double* mom, const double* field) {
+  constexpr int R = D + 1;
+  const Geom& g = S.g;
+  const int nc = g.ncell;
+  if (!S.Kbar.alloc((size_t)(1 + 2 * D) * R * R * nc) || !S.ework.alloc((size_t)R * nc))
+    return LRBMS_E_OOM;
+  if (launch_moments(g, field, GAMMA_FIELD, nullptr, 0, 0, mom, 0) != hipSuccess) return LRBMS_E_HIP;
+  hipLaunchKernelGGL(k_fine_stencil<D>, dim3(blocks_for((long long)nc * R)), dim3(kBlk), 0, 0, g,
+                     mom, S.Kbar.p);
+  if (hipGetLastError() != hipSuccess) return LRBMS_E_HIP;
+  S.have_bar = true;
+  return LRBMS_OK;
+}
+
+int fine_energy_setup(FineSolver* S, double* mom, const double* field) {
+  return S->g.dim == 2 ? energy_setup_t<2>(*S, mom, field) : energy_setup_t<3>(*S, mom, field);
+}
+
+// |a - b|^2 in the energy norm of the kept operator (a, b device fields).
+int fine_energy_diff(FineSolver* S, const double* a, const double* b, double* out) {
+  if (!S->have_bar) return LRBMS_E_STATE;
+  const Geom& g = S->g;
+  const long long n = (long long)g.r * g.ncell;
+  double* e = S->ework.p;
+  if (b) {
+    hipLaunchKernelGGL(k_diff, dim3(blocks_for(n)), dim3(kBlk), 0, 0, n, a, b, e);
+  } else if (hipMemcpy(e, a, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess) {
+    return LRBMS_E_HIP;
+  }
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_energy<2>, dim3(S->nbc), dim3(kBlk), 0, 0, g, S->Kbar.p, e, S->prr.p);
+  else
+    hipLaunchKernelGGL(k_energy<3>, dim3(S->nbc), dim3(kBlk), 0, 0, g, S->Kbar.p, e, S->prr.p);
+  std::vector<double> h(S->nbc);
+  if (hipMemcpy(h.data(), S->prr.p, S->nbc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return LRBMS_E_HIP;
+  *out = host_sum(h);
+  return std::isfinite(*out) ? LRBMS_OK : LRBMS_E_NONFINITE;
+}
 
 int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
                       int maxit, bool warm, double* d_p, int* d_status, int* iters,

@@ -103,6 +103,8 @@ def lib():
                                           C.POINTER(dbl)]
         L.lrbms_time_of_flight.argtypes = [vp, vp, dbl, i32, vp, C.POINTER(i32)]
         L.lrbms_model_export_profiles.argtypes = [vp, vp]
+        L.lrbms_build_greedy_bases.argtypes = [vp, vp, vp, i32, dbl, vp, C.POINTER(vp), vp, vp,
+                                               i32, C.POINTER(i32), vp]
         L.lrbms_fine_create.argtypes = [vp, C.POINTER(vp)]
         L.lrbms_fine_step.argtypes = [vp, vp, dbl, i32, i32, vp, vp, vp, vp, C.POINTER(i32),
                                       C.POINTER(dbl)]
@@ -238,6 +240,35 @@ class Model:
         m = cls(h, prob)
         m._sizes = None
         return m, {f: getattr(rep, f) for f, _ in OfflineReport_C._fields_}
+
+    @classmethod
+    def build_greedy(cls, prob, mu, n_max: int, tol: float, horizon: float, mu_bar=None,
+                     keep_profiles=True, pcg_rtol=1e-13, pcg_maxit=20000, tof_tol=1e-14,
+                     tof_maxit=100000, s0=None):
+        """Greedy basis construction on the device (lrbms_build_greedy_bases).
+        Returns (model, chosen indices, error history, report)."""
+        pc = ProblemC(prob)
+        mu = np.ascontiguousarray(np.atleast_2d(mu), dtype=np.float64)
+        o = OfflineOpts_C(M=mu.shape[1], n_train=mu.shape[0], ne_cap=1, unit_functions=0,
+                          horizon=float(horizon), pcg_rtol=float(pcg_rtol),
+                          pcg_maxit=int(pcg_maxit), tof_tol=float(tof_tol),
+                          tof_maxit=int(tof_maxit), keep_profiles=int(bool(keep_profiles)),
+                          d_s0=_ptr(s0) or None)
+        mb = None if mu_bar is None else np.ascontiguousarray(mu_bar, dtype=np.float64)
+        cap = 64
+        chosen = np.full(cap, -1, dtype=np.int32)
+        errs = np.zeros(cap)
+        n = C.c_int32(0)
+        rep = OfflineReport_C()
+        h = C.c_void_p()
+        _check(lib().lrbms_build_greedy_bases(pc.ref(), C.byref(o), _ptr(mu), int(n_max),
+                                              float(tol), _ptr(mb), C.byref(h), _ptr(chosen),
+                                              _ptr(errs), cap, C.byref(n), C.byref(rep)))
+        m = cls(h, prob)
+        m._sizes = None
+        k = n.value
+        return (m, [int(c) for c in chosen[:k] if c >= 0], errs[:k].tolist(),
+                {f: getattr(rep, f) for f, _ in OfflineReport_C._fields_})
 
     def export_profiles(self) -> np.ndarray:
         out = np.empty((self.info["n_profiles"], self.info["r"] * self.info["ncell"]))
