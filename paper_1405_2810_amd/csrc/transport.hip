@@ -156,97 +156,117 @@ __device__ __forceinline__ void load_cell(const Geom& g, const double* s, int c,
   for (int k = 0; k < 4; ++k) co[k] = k < g.r ? s[(long long)k * g.ncell + c] : 0.0;
 }
 
+// One thread per cell, templated on the dimension; every load of the cell and
+// its face neighbours (states, permeabilities, fluxes, boundary data) is
+// issued before the arithmetic, so their latencies overlap.
+template <int D>
 __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restrict__ sat,
                                                    const double* __restrict__ flux,
                                                    double* __restrict__ out) {
+  constexpr int R = D + 1, NF = 2 * D;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.ncell) return;
-  const int d = g.dim, r = g.r, nc = g.ncell;
+  const int nc = g.ncell;
   int x[3];
   cell_coords(g, e, x);
-  double se[4];
-  load_cell(g, sat, e, se);
-  double R[4] = {0.0, 0.0, 0.0, 0.0};
-  R[0] += g.q2[e] * g.vol * g.isv;
+  // ---- loads
+  double se[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) se[k] = sat[(long long)k * nc + e];
+  const double q2 = g.q2[e], ke = g.perm[e], phi = g.poro[e];
+  double F[NF], kn[NF], bsv[NF], sn[NF][4];
+  int8_t bsd[NF];
+  bool inter[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int a = f >> 1, dir = f & 1;
+    int xf[3] = {x[0], x[1], x[2]};
+    xf[a] += dir;
+    const int fid = face_index(g, a, xf);
+    int xn[3] = {x[0], x[1], x[2]};
+    xn[a] += dir ? 1 : -1;
+    inter[f] = xn[a] >= 0 && xn[a] < g.n[a];
+    const int en = inter[f] ? cell_index(g, xn) : e;   // boundary: a valid cell, unused
+    F[f] = flux[fid];
+    kn[f] = g.perm[en];
+    bsd[f] = g.bc_sat[fid];
+    bsv[f] = g.bc_sval[fid];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sn[f][k] = k < R ? sat[(long long)k * nc + en] : 0.0;
+  }
+  // ---- arithmetic
+  double Rr[4] = {0.0, 0.0, 0.0, 0.0};
+  Rr[0] += q2 * g.vol * g.isv;
   const double gp = 1.0 / kSqrt3;
   // volume term int_e u f_w(s) . grad v
   {
-    double Flo[3], Fhi[3];
-    for (int a = 0; a < d; ++a) {
-      int xf[3] = {x[0], x[1], x[2]};
-      Flo[a] = flux[face_index(g, a, xf)];
-      xf[a] += 1;
-      Fhi[a] = flux[face_index(g, a, xf)];
-    }
-    const int nq = 1 << d;
+    constexpr int nq = 1 << D;
     double acc[3] = {0, 0, 0};
+#pragma unroll
     for (int p = 0; p < nq; ++p) {
       double xi[3], sq[3];
-      for (int a = 0; a < d; ++a) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
         xi[a] = ((p >> a) & 1) ? gp : -gp;
         sq[a] = kSqrt3 * xi[a];
       }
-      const double fw = frac_flow(g, p1_value(se, d, sq, g.isv));
-      for (int a = 0; a < d; ++a) {
+      const double fw = frac_flow(g, p1_value(se, D, sq, g.isv));
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
         const double t = 0.5 * (1.0 + xi[a]);
-        const double ua = ((1.0 - t) * Flo[a] + t * Fhi[a]) / g.area[a];
+        const double ua = ((1.0 - t) * F[2 * a] + t * F[2 * a + 1]) / g.area[a];
         acc[a] += ua * fw * (g.vol / nq);
       }
     }
-    for (int a = 0; a < d; ++a) R[a + 1] += (kSqrt3 * 2.0 / g.h[a] * g.isv) * acc[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) Rr[a + 1] += (kSqrt3 * 2.0 / g.h[a] * g.isv) * acc[a];
   }
   // face terms
-  for (int a = 0; a < d; ++a) {
-    int tax[2], nt = 0;
-    for (int b = 0; b < d; ++b)
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int tax[2] = {0, 0}, nt = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b)
       if (b != a) tax[nt++] = b;
-    const int nq = 1 << nt;
+    constexpr int nq = 1 << (D - 1);
     const double wq = g.area[a] / nq;
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-      int xf[3] = {x[0], x[1], x[2]};
-      xf[a] += dir;
-      const int fid = face_index(g, a, xf);
-      const double F = flux[fid];
+      const int f = 2 * a + dir;
+      const double Ff = F[f];
       const double al = dir ? 1.0 : -1.0;   // position of the face in this cell
-      int xn[3] = {x[0], x[1], x[2]};
-      xn[a] += dir ? 1 : -1;
-      const bool interior = xn[a] >= 0 && xn[a] < g.n[a];
-      double sn[4] = {0, 0, 0, 0};
-      double ke = g.perm[e], kn = 0.0;
-      if (interior) {
-        const int en = cell_index(g, xn);
-        load_cell(g, sat, en, sn);
-        kn = g.perm[en];
-      }
-      const bool sd = !interior && g.bc_sat[fid] == 1;
-      const double sval = interior ? 0.0 : g.bc_sval[fid];
+      const bool interior = inter[f];
+      const bool sd = !interior && bsd[f] == 1;
+      const double sval = interior ? 0.0 : bsv[f];
       double sig;
       if (interior) {
-        const double klo = dir ? ke : kn, khi = dir ? kn : ke;
+        const double klo = dir ? ke : kn[f], khi = dir ? kn[f] : ke;
         sig = g.sat_pen * (g.pen * 2.0 * klo * khi / (klo + khi)) / g.hf[a];
       } else {
         sig = g.sat_pen * (g.pen * ke) / g.hf[a];
       }
       double acc[4] = {0, 0, 0, 0};
+#pragma unroll
       for (int p = 0; p < nq; ++p) {
         double sqe[3] = {0, 0, 0}, sqn[3] = {0, 0, 0};
         double xt[2] = {0, 0};
         sqe[a] = kSqrt3 * al;
         sqn[a] = -kSqrt3 * al;
-        for (int ti = 0; ti < nt; ++ti) {
+#pragma unroll
+        for (int ti = 0; ti < D - 1; ++ti) {
           xt[ti] = ((p >> ti) & 1) ? gp : -gp;
           sqe[tax[ti]] = kSqrt3 * xt[ti];
           sqn[tax[ti]] = kSqrt3 * xt[ti];
         }
-        const double ve = p1_value(se, d, sqe, g.isv);
+        const double ve = p1_value(se, D, sqe, g.isv);
         double tot;
         if (interior) {
-          const double vn = p1_value(sn, d, sqn, g.isv);
+          const double vn = p1_value(sn[f], D, sqn, g.isv);
           const double vlo = dir ? ve : vn, vhi = dir ? vn : ve;
-          const double up = (F >= 0.0) ? vlo : vhi;
-          tot = (F / g.area[a]) * frac_flow(g, up) + sig * (vlo - vhi);
+          const double up = (Ff >= 0.0) ? vlo : vhi;
+          tot = (Ff / g.area[a]) * frac_flow(g, up) + sig * (vlo - vhi);
         } else {
-          const double fout = al * F;
+          const double fout = al * Ff;
           const double chi = sd ? sval : ve;
           tot = (fout / g.area[a]) * frac_flow(g, chi) + (sd ? sig * (ve - sval) : 0.0);
         }
@@ -254,23 +274,29 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
         const double tw = tot * wq * g.isv;
         acc[0] += tw;
         acc[a + 1] += tw * kSqrt3 * al;
-        for (int ti = 0; ti < nt; ++ti) acc[tax[ti] + 1] += tw * kSqrt3 * xt[ti];
+#pragma unroll
+        for (int ti = 0; ti < D - 1; ++ti) acc[tax[ti] + 1] += tw * kSqrt3 * xt[ti];
       }
       // [v] = +v on the low-side cell (face on its +a side), -v on the high-side cell;
       // a boundary face has [v] = v
       const double jv = interior ? al : 1.0;
-      for (int k = 0; k < r; ++k) R[k] -= jv * acc[k];
+#pragma unroll
+      for (int k = 0; k < R; ++k) Rr[k] -= jv * acc[k];
     }
   }
-  const double phi = g.poro[e];
-  for (int k = 0; k < r; ++k) out[(long long)k * nc + e] = se[k] + g.dt * R[k] / phi;
+#pragma unroll
+  for (int k = 0; k < R; ++k) out[(long long)k * nc + e] = se[k] + g.dt * Rr[k] / phi;
 }
 
 hipError_t launch_transport(const Geom& g, const double* sat, const double* flux, double* sat_bar,
                             hipStream_t st) {
   ktimer_begin(KK_TRANSPORT, st);
-  hipLaunchKernelGGL(k_transport, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat, flux,
-                     sat_bar);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_transport<2>, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat, flux,
+                       sat_bar);
+  else
+    hipLaunchKernelGGL(k_transport<3>, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat, flux,
+                       sat_bar);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
