@@ -73,41 +73,60 @@ __device__ __forceinline__ void face_coords(const Geom& g, int fid, int& a, int 
   x[2] = l / (e0 * e1);
 }
 
-// int_f lambda(s) over a face of cell c at xi_a = xia (2-point Gauss).
-__device__ __forceinline__ double face_mobility_int(const Geom& g, const double* sat, int c, int a,
-                                                    double xia) {
-  const int d = g.dim, nc = g.ncell;
-  double co[4] = {0, 0, 0, 0};
-  for (int k = 0; k < g.r; ++k) co[k] = sat[(long long)k * nc + c];
-  int tax[2], nt = 0;
-  for (int b = 0; b < d; ++b)
+// Integral of the total mobility lambda(s) over the face of axis a at local
+// coordinate xi_a of a cell with coefficients co (2-point Gauss in the
+// tangential directions).
+template <int D>
+__device__ __forceinline__ double face_mobility_co(const Geom& g, const double (&co)[4], int a,
+                                                   double xia) {
+  int tax[2] = {0, 0}, nt = 0;
+#pragma unroll
+  for (int b = 0; b < D; ++b)
     if (b != a) tax[nt++] = b;
   const double gp = 1.0 / kSqrt3;
   double sum = 0.0;
-  for (int p = 0; p < (1 << nt); ++p) {
+#pragma unroll
+  for (int p = 0; p < (1 << (D - 1)); ++p) {
     double sq[3] = {0, 0, 0};
     sq[a] = kSqrt3 * xia;
-    for (int ti = 0; ti < nt; ++ti) sq[tax[ti]] = kSqrt3 * (((p >> ti) & 1) ? gp : -gp);
-    sum += total_mobility(g, p1_value(co, d, sq, g.isv));
+#pragma unroll
+    for (int ti = 0; ti < D - 1; ++ti) sq[tax[ti]] = kSqrt3 * (((p >> ti) & 1) ? gp : -gp);
+    sum += total_mobility(g, p1_value(co, D, sq, g.isv));
   }
-  return sum * g.area[a] / (1 << nt);
+  return sum * g.area[a] / (1 << (D - 1));
 }
 
+// One thread per face, templated on the dimension; the loads of both cells
+// and of the face data are issued before the arithmetic.
+template <int D>
 __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__ ph,
                                               const double* __restrict__ sat,
                                               double* __restrict__ flux) {
+  constexpr int R = D + 1;
   const int fid = blockIdx.x * blockDim.x + threadIdx.x;
   if (fid >= g.nface) return;
   int a, x[3];
   face_coords(g, fid, a, x);
   const int nc = g.ncell;
-  const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
   int xl[3] = {x[0], x[1], x[2]};
   xl[a] -= 1;
   const bool has_lo = x[a] >= 1, has_hi = x[a] < g.n[a];
+  // cells on both sides (a boundary face uses its one cell twice)
+  const int c0 = has_lo ? cell_index(g, xl) : cell_index(g, x);
+  const int c1 = has_hi ? cell_index(g, x) : c0;
+  double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    s0[k] = sat[(long long)k * nc + c0];
+    s1[k] = sat[(long long)k * nc + c1];
+  }
+  const double k0 = g.perm[c0], k1 = g.perm[c1];
+  const double p00 = ph[c0], p0a = ph[(long long)(a + 1) * nc + c0];
+  const double p10 = ph[c1], p1a = ph[(long long)(a + 1) * nc + c1];
+  const int bt = g.bc_type[fid];
+  const double val = g.bc_val[fid];
+  const double gf = kSqrt3 * 2.0 / g.h[a] * g.isv;
   if (has_lo && has_hi) {
-    const int c0 = cell_index(g, xl), c1 = cell_index(g, x);
-    const double k0 = g.perm[c0], k1 = g.perm[c1];
     double w0, w1;
     if (g.weights == 0) {
       w0 = k1 / (k0 + k1);
@@ -116,26 +135,21 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
       w0 = k0 / (k0 + k1);
       w1 = k1 / (k0 + k1);
     }
-    const double g0 = face_mobility_int(g, sat, c0, a, 1.0);
-    const double g1 = face_mobility_int(g, sat, c1, a, -1.0);
-    const double p00 = ph[c0], p0a = ph[(long long)(a + 1) * nc + c0];
-    const double p10 = ph[c1], p1a = ph[(long long)(a + 1) * nc + c1];
+    const double g0 = face_mobility_co<D>(g, s0, a, 1.0);
+    const double g1 = face_mobility_co<D>(g, s1, a, -1.0);
     const double jump = g.area[a] * g.isv * ((p00 + kSqrt3 * p0a) - (p10 - kSqrt3 * p1a));
     const double sig = g.pen * 2.0 * k0 * k1 / (k0 + k1) / g.hf[a];
     flux[fid] = -(w0 * k0 * g0 * (gf * p0a) + w1 * k1 * g1 * (gf * p1a)) + sig * jump;
     return;
   }
   const double al = has_lo ? 1.0 : -1.0;           // outward normal sign
-  const int c = has_lo ? cell_index(g, xl) : cell_index(g, x);
-  const int bt = g.bc_type[fid];
-  const double val = g.bc_val[fid];
   double out = 0.0;
   if (bt == LRBMS_BC_NEUMANN) {
     out = val * g.area[a];
   } else if (bt == LRBMS_BC_DIRICHLET) {
-    const double kc = g.perm[c];
-    const double gm = face_mobility_int(g, sat, c, a, al);
-    const double p0 = ph[c], pa = ph[(long long)(a + 1) * nc + c];
+    const double kc = k0;
+    const double gm = face_mobility_co<D>(g, s0, a, al);
+    const double p0 = p00, pa = p0a;
     const double sig = g.pen * kc / g.hf[a];
     const double trace = g.area[a] * g.isv * (p0 + kSqrt3 * al * pa);
     out = -kc * gm * (al * gf * pa) + sig * (trace - val * g.area[a]);
@@ -146,15 +160,15 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
 hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, double* flux,
                        hipStream_t st) {
   ktimer_begin(KK_FLUX, st);
-  hipLaunchKernelGGL(k_flux, dim3((g.nface + 255) / 256), dim3(256), 0, st, g, ph, sat, flux);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_flux<2>, dim3((g.nface + 255) / 256), dim3(256), 0, st, g, ph, sat, flux);
+  else
+    hipLaunchKernelGGL(k_flux<3>, dim3((g.nface + 255) / 256), dim3(256), 0, st, g, ph, sat, flux);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void load_cell(const Geom& g, const double* s, int c, double* co) {
-  for (int k = 0; k < 4; ++k) co[k] = k < g.r ? s[(long long)k * g.ncell + c] : 0.0;
-}
 
 // One thread per cell, templated on the dimension; every load of the cell and
 // its face neighbours (states, permeabilities, fluxes, boundary data) is
@@ -309,63 +323,90 @@ __device__ __forceinline__ double gradient_scale(double gi, double di) {
   return 1.0;
 }
 
+// One thread per cell, templated on the dimension; the loads of the cell and
+// its face neighbours are issued before the arithmetic.
+template <int D>
 __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restrict__ sb,
                                                  const double* __restrict__ flux,
                                                  double* __restrict__ out,
                                                  uint8_t* __restrict__ flags) {
+  constexpr int R = D + 1, NF = 2 * D;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= g.ncell) return;
-  const int d = g.dim, r = g.r, nc = g.ncell;
+  const int nc = g.ncell;
   int x[3];
   cell_coords(g, e, x);
-  double se[4];
-  load_cell(g, sb, e, se);
+  // ---- loads
+  double se[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) se[k] = sb[(long long)k * nc + e];
+  double F[NF], bsv[NF], sn[NF][4];
+  int8_t bsd[NF];
+  bool inter[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int a = f >> 1, dir = f & 1;
+    int xf[3] = {x[0], x[1], x[2]};
+    xf[a] += dir;
+    const int fid = face_index(g, a, xf);
+    int xn[3] = {x[0], x[1], x[2]};
+    xn[a] += dir ? 1 : -1;
+    inter[f] = xn[a] >= 0 && xn[a] < g.n[a];
+    const int en = inter[f] ? cell_index(g, xn) : e;   // boundary: a valid cell, unused
+    F[f] = flux[fid];
+    bsd[f] = g.bc_sat[fid];
+    bsv[f] = g.bc_sval[fid];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sn[f][k] = (k < R && inter[f]) ? sb[(long long)k * nc + en] : 0.0;
+  }
+  // ---- arithmetic
   const double mean = se[0] * g.isv;
   bool outside = false;
-  for (int p = 0; p < (1 << d); ++p) {
+#pragma unroll
+  for (int p = 0; p < (1 << D); ++p) {
     double sq[3];
-    for (int a = 0; a < d; ++a) sq[a] = ((p >> a) & 1) ? kSqrt3 : -kSqrt3;
-    const double v = p1_value(se, d, sq, g.isv);
+#pragma unroll
+    for (int a = 0; a < D; ++a) sq[a] = ((p >> a) & 1) ? kSqrt3 : -kSqrt3;
+    const double v = p1_value(se, D, sq, g.isv);
     if (v < 0.0 || v > 1.0) outside = true;
   }
   const double gp = 1.0 / kSqrt3;
   double S = 0.0, mmin = 1.0;
-  for (int a = 0; a < d; ++a) {
-    int tax[2], nt = 0;
-    for (int b = 0; b < d; ++b)
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int tax[2] = {0, 0}, nt = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b)
       if (b != a) tax[nt++] = b;
-    const double wq = g.area[a] / (1 << nt);
+    constexpr int nq = 1 << (D - 1);
+    const double wq = g.area[a] / nq;
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-      int xf[3] = {x[0], x[1], x[2]};
-      xf[a] += dir;
-      const int fid = face_index(g, a, xf);
-      const double F = flux[fid];
+      const int f = 2 * a + dir;
       const double al = dir ? 1.0 : -1.0;
-      int xn[3] = {x[0], x[1], x[2]};
-      xn[a] += dir ? 1 : -1;
-      const bool interior = xn[a] >= 0 && xn[a] < g.n[a];
-      double sn[4] = {0, 0, 0, 0};
-      if (interior) load_cell(g, sb, cell_index(g, xn), sn);
-      const bool inflow = (al * F) < 0.0;
-      const bool sd = !interior && g.bc_sat[fid] == 1;
+      const bool interior = inter[f];
+      const bool inflow = (al * F[f]) < 0.0;
+      const bool sd = !interior && bsd[f] == 1;
       if (inflow && (interior || sd)) {
         double J = 0.0;
-        for (int p = 0; p < (1 << nt); ++p) {
+#pragma unroll
+        for (int p = 0; p < nq; ++p) {
           double sqe[3] = {0, 0, 0}, sqn[3] = {0, 0, 0};
           sqe[a] = kSqrt3 * al;
           sqn[a] = -kSqrt3 * al;
-          for (int ti = 0; ti < nt; ++ti) {
+#pragma unroll
+          for (int ti = 0; ti < D - 1; ++ti) {
             const double xt = ((p >> ti) & 1) ? gp : -gp;
             sqe[tax[ti]] = kSqrt3 * xt;
             sqn[tax[ti]] = kSqrt3 * xt;
           }
-          const double ve = p1_value(se, d, sqe, g.isv);
+          const double ve = p1_value(se, D, sqe, g.isv);
           double jmp;
           if (interior) {
-            const double vn = p1_value(sn, d, sqn, g.isv);
+            const double vn = p1_value(sn[f], D, sqn, g.isv);
             jmp = dir ? (ve - vn) : (vn - ve);   // low side minus high side
           } else {
-            jmp = ve - g.bc_sval[fid];
+            jmp = ve - bsv[f];
           }
           J += jmp * wq;
         }
@@ -374,23 +415,28 @@ __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restric
       if (interior) {
         const double ga = kSqrt3 * 2.0 / g.h[a] * g.isv * se[a + 1];
         const double gi = ga * (al * g.h[a]);
-        const double di = sn[0] * g.isv - mean;
+        const double di = sn[f][0] * g.isv - mean;
         mmin = fmin(mmin, gradient_scale(gi, di));
       }
     }
   }
-  S = S / (0.08 * d * sqrt(g.he) * g.vol);
+  S = S / (0.08 * D * sqrt(g.he) * g.vol);
   const bool flag = (S > 1.0) || outside;
   out[e] = se[0];
-  for (int k = 1; k < r; ++k) out[(long long)k * nc + e] = flag ? se[k] * mmin : se[k];
+#pragma unroll
+  for (int k = 1; k < R; ++k) out[(long long)k * nc + e] = flag ? se[k] * mmin : se[k];
   if (flags) flags[e] = flag ? 1 : 0;
 }
 
 hipError_t launch_limiter(const Geom& g, const double* sat_bar, const double* flux,
                           double* sat_out, uint8_t* flags, hipStream_t st) {
   ktimer_begin(KK_LIMITER, st);
-  hipLaunchKernelGGL(k_limiter, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat_bar, flux,
-                     sat_out, flags);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_limiter<2>, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat_bar,
+                       flux, sat_out, flags);
+  else
+    hipLaunchKernelGGL(k_limiter<3>, dim3((g.ncell + 255) / 256), dim3(256), 0, st, g, sat_bar,
+                       flux, sat_out, flags);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
