@@ -29,15 +29,18 @@ namespace lrbms {
 // a1: mobility moments per cell.  gamma is lambda(s_h) (kind GAMMA_SAT), a P1
 // field (GAMMA_FIELD) or sum_q theta_q Lambda^q (GAMMA_COMBO); integrals by the
 // 2-point Gauss rules, which are exact for the quadratic mobility of a P1 state.
-__global__ __launch_bounds__(256) void k_moments(Geom g, const double* __restrict__ src, int kind,
+template <int D, int KIND>
+__global__ __launch_bounds__(256) void k_moments(Geom g, const double* __restrict__ src,
                                                  const double* __restrict__ theta, int nprof,
                                                  long long pstride, double* __restrict__ mom) {
+  constexpr int R = D + 1;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
-  const int d = g.dim, nc = g.ncell;
-  double co[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < g.r; ++k) {
-    if (kind == GAMMA_COMBO) {
+  const int nc = g.ncell;
+  double co[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (KIND == GAMMA_COMBO) {
       double v = 0.0;
       for (int q = 0; q < nprof; ++q) v += theta[q] * src[q * pstride + (long long)k * nc + c];
       co[k] = v;
@@ -46,50 +49,75 @@ __global__ __launch_bounds__(256) void k_moments(Geom g, const double* __restric
     }
   }
   // value of gamma at local point xi (sq holds sqrt(3) xi_a)
-  auto gam = [&](const double sq[3]) {
+  auto gam = [&](const double (&sq)[3]) {
     double v = co[0];
-    for (int a = 0; a < d; ++a) v += sq[a] * co[a + 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v += sq[a] * co[a + 1];
     v *= g.isv;
-    return kind == GAMMA_SAT ? total_mobility(g, v) : v;
+    return KIND == GAMMA_SAT ? total_mobility(g, v) : v;
   };
   const double gp = 1.0 / kSqrt3;
-  double sq[3];
+  double sq[3] = {0.0, 0.0, 0.0};
   double sum = 0.0;
-  const int nq = 1 << d;
+  constexpr int nq = 1 << D;
+#pragma unroll
   for (int p = 0; p < nq; ++p) {
-    for (int a = 0; a < d; ++a) sq[a] = kSqrt3 * (((p >> a) & 1) ? gp : -gp);
+#pragma unroll
+    for (int a = 0; a < D; ++a) sq[a] = kSqrt3 * (((p >> a) & 1) ? gp : -gp);
     sum += gam(sq);
   }
-  mom[c] = sum * g.vol / nq;
-  for (int a = 0; a < d; ++a) {
-    int tax[2], nt = 0;
-    for (int b = 0; b < d; ++b)
+  double out[1 + 2 * D * D];
+  out[0] = sum * g.vol / nq;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int tax[2] = {0, 0}, nt = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b)
       if (b != a) tax[nt++] = b;
-    const double w = g.area[a] / (1 << nt);
+    const double w = g.area[a] / (1 << (D - 1));
+#pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
       double m0 = 0.0, mt[2] = {0.0, 0.0};
-      for (int p = 0; p < (1 << nt); ++p) {
+#pragma unroll
+      for (int p = 0; p < (1 << (D - 1)); ++p) {
         double xi[3] = {0.0, 0.0, 0.0};
         xi[a] = dir ? 1.0 : -1.0;
-        for (int ti = 0; ti < nt; ++ti) xi[tax[ti]] = ((p >> ti) & 1) ? gp : -gp;
-        for (int b = 0; b < d; ++b) sq[b] = kSqrt3 * xi[b];
+#pragma unroll
+        for (int ti = 0; ti < D - 1; ++ti) xi[tax[ti]] = ((p >> ti) & 1) ? gp : -gp;
+#pragma unroll
+        for (int b = 0; b < D; ++b) sq[b] = kSqrt3 * xi[b];
         const double v = gam(sq);
         m0 += v;
-        for (int ti = 0; ti < nt; ++ti) mt[ti] += v * xi[tax[ti]];
+#pragma unroll
+        for (int ti = 0; ti < D - 1; ++ti) mt[ti] += v * xi[tax[ti]];
       }
-      const int s = mom_slot(d, a, dir);
-      mom[(long long)s * nc + c] = m0 * w;
-      for (int ti = 0; ti < nt; ++ti) mom[(long long)(s + 1 + ti) * nc + c] = mt[ti] * w;
+      const int s0 = mom_slot(D, a, dir);
+      out[s0] = m0 * w;
+#pragma unroll
+      for (int ti = 0; ti < D - 1; ++ti) out[s0 + 1 + ti] = mt[ti] * w;
     }
   }
+#pragma unroll
+  for (int k = 0; k < 1 + 2 * D * D; ++k) mom[(long long)k * nc + c] = out[k];
 }
 
 hipError_t launch_moments(const Geom& g, const double* src, int kind, const double* theta,
                           int nprof, long long prof_stride, double* mom, hipStream_t st) {
   const int nb = (g.ncell + 255) / 256;
   ktimer_begin(KK_MOMENTS, st);
-  hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, st, g, src, kind, theta, nprof,
-                     prof_stride, mom);
+#define LRBMS_MOMENTS(D, K)                                                                  \
+  hipLaunchKernelGGL((k_moments<D, K>), dim3(nb), dim3(256), 0, st, g, src, theta, nprof,      \
+                     prof_stride, mom)
+  if (g.dim == 2) {
+    if (kind == GAMMA_SAT) LRBMS_MOMENTS(2, GAMMA_SAT);
+    else if (kind == GAMMA_FIELD) LRBMS_MOMENTS(2, GAMMA_FIELD);
+    else LRBMS_MOMENTS(2, GAMMA_COMBO);
+  } else {
+    if (kind == GAMMA_SAT) LRBMS_MOMENTS(3, GAMMA_SAT);
+    else if (kind == GAMMA_FIELD) LRBMS_MOMENTS(3, GAMMA_FIELD);
+    else LRBMS_MOMENTS(3, GAMMA_COMBO);
+  }
+#undef LRBMS_MOMENTS
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }

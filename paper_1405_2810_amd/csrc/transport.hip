@@ -27,11 +27,16 @@ __device__ __forceinline__ double p1_value(const double* co, int d, const double
 
 // ---------------------------------------------------------------------------
 // p_h on the cells of one tile (box, first cell): coalesced over cells.
+// Eight basis functions per pass: their 8 r coefficients and p_N entries are
+// loaded before the multiply-adds (indices past N_E are clamped and their
+// weight set to zero).
+template <int D>
 __global__ __launch_bounds__(256) void k_reconstruct(Geom g, const Sub* __restrict__ subs,
                                                      const int* __restrict__ tiles,
                                                      const double* __restrict__ phi,
                                                      const double* __restrict__ pN,
                                                      double* __restrict__ ph) {
+  constexpr int R = D + 1, U = 8;
   const int sub = tiles[2 * blockIdx.x], c0 = tiles[2 * blockIdx.x + 1];
   const Sub S = subs[sub];
   const int l = c0 + threadIdx.x;
@@ -39,15 +44,29 @@ __global__ __launch_bounds__(256) void k_reconstruct(Geom g, const Sub* __restri
   const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
   const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
   const int e = cell_index(g, x);
-  const int r = g.r;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
   const double* base = phi + S.phi_off + l;
-  const long long cs = (long long)r * S.nE;
-  for (int i = 0; i < S.NE; ++i) {
-    const double p = pN[S.pn_off + i];
-    for (int k = 0; k < r; ++k) acc[k] += base[i * cs + (long long)k * S.nE] * p;
+  const long long cs = (long long)R * S.nE;
+  for (int i0 = 0; i0 < S.NE; i0 += U) {
+    double v[U][R], pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(i0 + u, S.NE - 1);
+      pv[u] = pN[S.pn_off + i];
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[u][k] = base[i * cs + (long long)k * S.nE];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double p = (i0 + u < S.NE) ? pv[u] : 0.0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] += v[u][k] * p;
+    }
   }
-  for (int k = 0; k < r; ++k) ph[(long long)k * g.ncell + e] = acc[k];
+#pragma unroll
+  for (int k = 0; k < R; ++k) ph[(long long)k * g.ncell + e] = acc[k];
 }
 
 hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const int* d_tiles,
@@ -55,8 +74,12 @@ hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const
                               hipStream_t st) {
   (void)n_sub;
   ktimer_begin(KK_RECONSTRUCT, st);
-  hipLaunchKernelGGL(k_reconstruct, dim3(n_tiles), dim3(256), 0, st, g, d_subs, d_tiles, phi, pN,
-                     ph);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_reconstruct<2>, dim3(n_tiles), dim3(256), 0, st, g, d_subs, d_tiles, phi,
+                       pN, ph);
+  else
+    hipLaunchKernelGGL(k_reconstruct<3>, dim3(n_tiles), dim3(256), 0, st, g, d_subs, d_tiles, phi,
+                       pN, ph);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
