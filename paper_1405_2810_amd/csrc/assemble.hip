@@ -134,7 +134,10 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 template <int D> struct AsmShape {
   static constexpr int R = D + 1;
   static constexpr int NF = 1 + 2 * D;          // self block + one per face
-  static constexpr int CH = D == 2 ? 64 : 32;   // cells per chunk
+  static constexpr int CH = 64;                 // cells per chunk
+  // LDS doubles per cell of stencil blocks: odd, so that the 16 cells one
+  // wave reads at a time fall in different banks
+  static constexpr int KS = (NF * R * R) | 1;
   static constexpr int PC = 16;                 // cells per staged piece
   static constexpr int PR = PC * R;             // rows per staged piece
 };
@@ -142,7 +145,7 @@ template <int D> struct AsmShape {
 template <int D, int NEP>
 __host__ __device__ constexpr size_t box_lds_doubles() {
   using S = AsmShape<D>;
-  return (size_t)S::CH * S::NF * S::R * S::R + 2 * (size_t)S::PR * (NEP + 1);
+  return (size_t)S::CH * S::KS + 2 * (size_t)S::PR * (NEP + 1);
 }
 
 template <int D, int NEP>
@@ -170,8 +173,8 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   constexpr int R = SH::R, NF = SH::NF, PC = SH::PC, PR = SH::PR, LDP = NEP + 1;
   constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 3) / 4;
   extern __shared__ double lds[];
-  double* Kst = lds;                                   // [CH][NF][R][R]
-  double* PhiS = Kst + (size_t)SH::CH * NF * R * R;    // [PR][LDP]
+  double* Kst = lds;                                   // [CH][KS >= NF R R]
+  double* PhiS = Kst + (size_t)SH::CH * SH::KS;        // [PR][LDP]
   double* YS = PhiS + (size_t)PR * LDP;                // [PR][LDP]
   const int sub = chunks[2 * blockIdx.x], c0 = chunks[2 * blockIdx.x + 1];
   const Sub S = subs[sub];
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
       const int e = cell_index(g, x);
       double self[R], nbr[2 * D][R];
       cell_stencil<D>(g, S, e, x, mom, parts, kp, self, nbr);
-      double* K = Kst + (size_t)lc * NF * R * R;
+      double* K = Kst + (size_t)lc * SH::KS;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         K[k * R + kp] = self[k];
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
         const int l = c0 + lc;
         if (col < NE) {
           if (want_mat) {
-            const double* K = Kst + (size_t)lc * NF * R * R;
+            const double* K = Kst + (size_t)lc * SH::KS;
 #pragma unroll
             for (int k = 0; k < R; ++k)
 #pragma unroll
