@@ -72,6 +72,129 @@ def build_model(p, n_snap, cap, seed):
     return Model.from_snapshots(p, snaps, ne_cap=cap, unit_functions=True), snaps
 
 
+def build_ensemble(n: int, seed: int = 500):
+    """n simulations, alternately 2D 256x256 and 3D 64x64x32 on seeded uneven
+    coarse partitions, each with its own permeability seed and seeded local
+    basis sizes in 5..60 per box (the first N_E functions of a Gram-Schmidt
+    basis of 61 seeded plane-wave fields plus 1_E, shared per grid)."""
+    from synth import CONFIGS, make_problem, wave_fields, ensemble_caps
+    from paper_1405_2810_amd.lrbms import Model
+    snaps, out = {}, []
+    for i in range(n):
+        name = "ens2d" if i % 2 == 0 else "ens3d"
+        p = make_problem(name, seed=CONFIGS[name]["seed"] + i)
+        if name not in snaps:
+            snaps[name] = wave_fields(p, 61, np.random.default_rng(seed + len(snaps)))
+        full = Model.from_snapshots(p, snaps[name], ne_cap=60, unit_functions=True)
+        m = full.truncated(ensemble_caps(p, np.random.default_rng(seed + 1000 + i)))
+        full.close()
+        out.append((p, m))
+    return out
+
+
+def _states(members, seed):
+    import torch
+    from synth import random_saturation
+    return [torch.as_tensor(random_saturation(p, np.random.default_rng(seed + i), lo=0.0, hi=0.6),
+                            dtype=torch.float64, device="cuda") for i, (p, _) in enumerate(members)]
+
+
+def bench_batch(members, steps: int, warmup: int):
+    """One ensemble step = one online step (DIRECT) of every member.  Three
+    ways: the plain per-simulation path (members one after another on one
+    stream), the batch with direct launches on per-member branches, and the
+    batch captured into one graph (one launch per ensemble step)."""
+    import torch
+    from paper_1405_2810_amd.lrbms import Batch, DIRECT
+    st = torch.cuda.current_stream()
+    models = [m for _, m in members]
+    sats = _states(members, 900)
+    bufs = [(torch.zeros(m.info["N"], dtype=torch.float64, device="cuda"),
+             torch.zeros(m.info["nface"], dtype=torch.float64, device="cuda"),
+             torch.zeros_like(s)) for m, s in zip(models, sats)]
+
+    def plain():
+        for m, s, (pN, fl, nx) in zip(models, sats, bufs):
+            m.assemble(s, DIRECT, st)
+            m.solve(pN, st)
+            m.reconstruct_flux(pN, s, fl, None, st)
+            m.transport_step(s, fl, nx, None, st)
+            s.copy_(nx)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        ev[0].record(st)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(st)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps * 1e3
+        lat = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        return {"ms_per_ensemble_step": wall, "solves_per_s": len(models) * 1e3 / wall,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+
+    res = {"plain": timed(plain)}
+    for key, graph in (("batched_streams", False), ("batched_graph", True)):
+        B = Batch(models, mode=DIRECT, graph=graph)
+        res[key] = timed(lambda: B.step(sats, None, st))
+        B.close()
+    for m in models:
+        if m.status() != 0:
+            raise RuntimeError("device status error in the batched pass")
+    for k in ("batched_streams", "batched_graph"):
+        res[k]["vs_plain"] = res[k]["solves_per_s"] / res["plain"]["solves_per_s"]
+    return res
+
+
+def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77):
+    """Poisson arrivals of online-step requests, each for a uniformly drawn
+    member, at each rate; the server admits every member (the budget is the
+    sum of their footprints) and dispatches onto `slots` slot streams;
+    slots=1 is the plain path (one request on the device at a time).
+    Per rate: achieved solves/s (requests over the time from the first
+    submit to the last completion) and p50/p99 latency (submit to completion
+    seen by poll)."""
+    from paper_1405_2810_amd.lrbms import Server, DIRECT
+    models = [m for _, m in members]
+    sats = _states(members, 700)
+    foot = sum(m.info["device_bytes"] + 8 * (m.info["N"] + m.info["nface"] +
+                                             m.info["r"] * m.info["ncell"]) for m in models)
+    out = {}
+    for rate in rates:
+        rng = np.random.default_rng(seed)
+        arrive = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        who = rng.integers(0, len(models), n_req)
+        S = Server(hbm_budget=foot, max_slots=slots, mode=DIRECT)
+        ids = [S.attach(m, s) for m, s in zip(models, sats)]
+        lat = []
+        t0 = time.perf_counter()
+        k = 0
+        while len(lat) < n_req:
+            now = time.perf_counter() - t0
+            while k < n_req and arrive[k] <= now:
+                S.submit(ids[who[k]], k)
+                k += 1
+            for _, ms, rc in S.poll(1024):
+                if rc != 0:
+                    raise RuntimeError(f"request failed with status {rc}")
+                lat.append(ms)
+        span = time.perf_counter() - t0
+        S.close()
+        lat = np.array(lat)
+        out[f"{rate:g}"] = {"solves_per_s": n_req / span, "p50_ms": float(np.percentile(lat, 50)),
+                            "p99_ms": float(np.percentile(lat, 99))}
+        log(f"[bench] serve slots={slots} rate {rate:g}/s: {n_req / span:.0f} solves/s, "
+            f"p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms")
+    for m in models:
+        if m.status() != 0:
+            raise RuntimeError("device status error in the serving pass")
+    return out
+
+
 def cpu_baseline(p, snaps, s0, n_steps: int, mode: str):
     """The FP64 CPU oracle's online step (same problem, bases built by the
     oracle from the same snapshots) timed over n_steps from s0."""
@@ -111,6 +234,11 @@ def main():
                     help="steps of the fine reference (Alg. 1) timed for context; 0 skips")
     ap.add_argument("--offline", type=int, default=1,
                     help="1: time the GPU offline stage once for context")
+    ap.add_argument("--ensemble", type=int, default=64,
+                    help="members of the batched ensemble and serving passes; 0 skips both")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (scale of the HBM counters)")
     args = ap.parse_args()
@@ -272,6 +400,33 @@ def main():
         extras["offline_stage"] = {"seconds": osec, "N": om.info["N"], **rep}
         om.close()
         log(f"[bench] offline stage (Alg. 2 without greedy) on the GPU: {osec:.2f} s, {rep}")
+    if args.ensemble > 0:
+        log(f"[bench] ensemble: building {args.ensemble} members")
+        t0 = time.time()
+        members = build_ensemble(args.ensemble)
+        sz = [m.info["N"] for _, m in members]
+        log(f"[bench] ensemble ready in {time.time() - t0:.1f}s: N {min(sz)}..{max(sz)}, "
+            f"device MB {sum(m.info['device_bytes'] for _, m in members) / 1e6:.0f}")
+        bat = bench_batch(members, args.ensemble_steps, 3)
+        for k, v in bat.items():
+            log(f"[bench] ensemble {k}: {v['ms_per_ensemble_step']:.2f} ms per ensemble step, "
+                f"{v['solves_per_s']:.0f} solves/s, p99 {v['p99_ms']:.2f} ms")
+        rates = [1e3, 3e3, 1e4, 3e4, 5e4]
+        serve = {"slots": args.serve_slots,
+                 "continuous": bench_serve(members, rates, args.serve_requests, args.serve_slots),
+                 "plain_one_slot": bench_serve(members, rates, args.serve_requests, 1)}
+        extras["ensemble"] = {
+            "what": f"{args.ensemble} simulations, alternately 2D 256x256 and 3D 64x64x32 on "
+                    "seeded uneven coarse partitions, seeded N_E in 5..60 per box, DIRECT online "
+                    "step per member",
+            "members": args.ensemble, "N_range": [min(sz), max(sz)], **bat}
+        extras["serving"] = {
+            "what": "Poisson arrivals of single online-step requests for uniformly drawn members "
+                    f"of the same ensemble, {args.serve_requests} requests per rate; continuous "
+                    f"batching over {args.serve_slots} slot streams against the plain path "
+                    "(one slot)", **serve}
+        for _, m in members:
+            m.close()
     # ---- CPU oracle baseline ----------------------------------------------
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:

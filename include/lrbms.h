@@ -326,6 +326,94 @@ typedef struct lrbms_kernel_stat {
 int lrbms_profile_enable(lrbms_model* m, int32_t enable);
 int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int32_t* n_out);
 
+/* ---- many simulations on one device ------------------------------------------
+ * Both patterns run, for each simulation, exactly the four online calls above
+ * (one time step of Alg. 3 step 5: assembly in the given mode, reduced solve,
+ * flux reconstruction, transport + limiter) and copy the new state over the
+ * simulation's state buffer, so each simulation's result equals that of the
+ * plain per-simulation path, bit for bit.  A model may belong to one batch or
+ * server at a time and must not be stepped elsewhere meanwhile; destroy the
+ * batch or server (or detach) before destroying its models.  Not thread-safe:
+ * one host thread drives a batch or server.  Kernel timing
+ * (lrbms_profile_enable) must be off for its models (LRBMS_E_STATE otherwise). */
+
+typedef struct lrbms_batch lrbms_batch;
+#define LRBMS_BATCH_GRAPH 1  /* capture the whole batched step into one HIP graph */
+
+/* Batched ensemble: n models (distinct) advanced together.  The batch owns,
+ * per simulation, p_N [N], the face fluxes [nface] and the next state
+ * [r*ncell] (device).  mode: LRBMS_DIRECT / _FIT / AFFINE, available for
+ * every model (LRBMS_E_ARG otherwise).  flags: 0 or LRBMS_BATCH_GRAPH.
+ * Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP.                              */
+int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int32_t flags,
+                       lrbms_batch** out);
+
+/* One time step of every simulation of the batch, asynchronous on `stream`:
+ * d_sat[i] (device, [r*ncell] of model i) is advanced in place; d_flags
+ * (nullable; else an array of n nullable device pointers, [ncell] each)
+ * receives the limiter flags.  Every simulation runs on a branch of its own
+ * (up to 64 branches, then round robin), forked from and joined back into
+ * `stream`.  With LRBMS_BATCH_GRAPH the branches are captured once into a
+ * HIP graph (recaptured when the state or flag pointers change) and every
+ * step is one graph launch; otherwise the branches are launched directly.
+ * Errors: LRBMS_E_ARG, LRBMS_E_STATE, LRBMS_E_HIP.                             */
+int lrbms_batch_step(lrbms_batch* b, double* const* d_sat, uint8_t* const* d_flags, void* stream);
+
+/* Device pointers of simulation i's p_N and face fluxes of the last step.  */
+int lrbms_batch_buffers(lrbms_batch* b, int32_t i, double** d_pN, double** d_flux);
+void lrbms_batch_destroy(lrbms_batch* b);
+
+/* Serving loop with continuous batching.  Simulations are attached with
+ * their state buffer and admitted, in attach order, while the sum of the
+ * admitted simulations' footprints (the model's device bytes plus the step
+ * buffers the server allocates on admission: p_N, fluxes, next state) stays
+ * within hbm_budget bytes.  A request is one time step of one simulation.
+ * Requests are dispatched in submit order onto up to max_slots (1..64) slot
+ * streams, at most one request per simulation in flight (its steps are
+ * sequential); requests of simulations not yet admitted, or whose previous
+ * step still runs, wait while later ones go ahead.  The server makes
+ * progress (retires finished requests, admits, dispatches) inside attach,
+ * submit, poll, detach and drain; a serving loop calls poll regularly.
+ * Latency of a request = host time from its submit to the poll or drain
+ * that first sees it finished.                                                */
+typedef struct lrbms_server lrbms_server;
+typedef struct lrbms_server_info_t {
+  int64_t resident_bytes, budget_bytes;
+  int32_t n_pending, n_in_flight, n_admitted, n_waiting;
+} lrbms_server_info_t;
+
+/* Errors: LRBMS_E_ARG (budget <= 0, max_slots outside 1..64, unknown mode),
+ * LRBMS_E_HIP.                                                                 */
+int lrbms_server_create(int64_t hbm_budget, int32_t max_slots, int32_t mode, lrbms_server** out);
+
+/* Attach model m with its state d_sat (device, [r*ncell], advanced in place by
+ * every request; the device is synchronized first, so work that wrote it on
+ * any stream is complete); *sim_id receives the simulation's id.  LRBMS_E_ADMIT when
+ * the footprint alone exceeds the budget, LRBMS_E_ARG when m is attached
+ * already or lacks the server's mode.  A simulation that does not fit yet
+ * waits for others to be detached.                                            */
+int lrbms_server_attach(lrbms_server* s, lrbms_model* m, double* d_sat, int32_t* sim_id);
+
+/* Queue one time step of simulation sim_id under the caller's request id.  */
+int lrbms_server_submit(lrbms_server* s, int32_t sim_id, uint64_t req_id);
+
+/* Copy up to cap finished requests (oldest first): ids, latency in ms
+ * (nullable) and status (nullable; 0 or a negative LRBMS_E_* of a launch).
+ * Device-detected errors are read with lrbms_model_status.                    */
+int lrbms_server_poll(lrbms_server* s, uint64_t* req_ids, double* latency_ms, int32_t* status,
+                      int32_t cap, int32_t* n_done);
+
+/* Progress until no request is queued or in flight.  LRBMS_E_ADMIT when the
+ * remaining requests belong to simulations that cannot be admitted until
+ * others are detached.                                                        */
+int lrbms_server_drain(lrbms_server* s);
+
+/* Detach a simulation (waits for its request in flight; LRBMS_E_STATE while it
+ * has queued requests), free its step buffers and admit waiting ones.       */
+int lrbms_server_detach(lrbms_server* s, int32_t sim_id);
+int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info);
+void lrbms_server_destroy(lrbms_server* s);
+
 /* Synchronize and return the device status word (0 or a negative LRBMS_E_*). */
 int lrbms_model_status(lrbms_model* m);
 

@@ -1,0 +1,494 @@
+// Many simulations on one device: the batched ensemble step (all simulations
+// advanced by one graph launch) and the serving loop (online steps of many
+// simulations admitted by memory footprint, dispatched onto slot streams as
+// slots free up, their work overlapping on the device).
+//
+// Both run, per simulation, exactly the calls of one online step (Alg. 3
+// step 5): mobility + reduced assembly, the reduced solve, p_h and the face
+// fluxes, the saturation step with the limiter; a simulation's result is the
+// one the plain per-simulation path gives, bit for bit, because the same
+// kernels run on the same data in the same order.
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "model.h"
+
+namespace lrbms {
+
+namespace {
+
+// Buffers of one simulation's step that the batch or the server owns: p_N,
+// the face fluxes and the next state (copied back over the caller's state).
+struct StepBufs {
+  double* pN = nullptr;
+  double* flux = nullptr;
+  double* next = nullptr;
+  long long bytes = 0;
+  bool alloc(const Model& M) {
+    release();
+    const size_t n[3] = {(size_t)std::max(M.N, 1), (size_t)std::max(M.g.nface, 1),
+                         (size_t)M.g.r * M.g.ncell};
+    double** p[3] = {&pN, &flux, &next};
+    for (int k = 0; k < 3; ++k) {
+      if (!hip_ok(hipMalloc(p[k], n[k] * sizeof(double)), "hipMalloc")) {
+        release();
+        return false;
+      }
+      bytes += (long long)(n[k] * sizeof(double));
+    }
+    return true;
+  }
+  void release() {
+    for (double* q : {pN, flux, next})
+      if (q) (void)hipFree(q);
+    pN = flux = next = nullptr;
+    bytes = 0;
+  }
+};
+
+Model* model_of(lrbms_model* m) { return reinterpret_cast<Model*>(m); }
+
+bool mode_ok(const Model& M, int mode) {
+  if (mode == LRBMS_DIRECT) return true;
+  if (mode != LRBMS_DIRECT_FIT && mode != LRBMS_AFFINE) return false;
+  return M.nprof > 0 && M.lsq_ok;
+}
+
+// One online step of one simulation on stream st; the state d_sat is
+// advanced in place (through b.next).
+int sim_step(lrbms_model* m, int mode, double* d_sat, uint8_t* d_flags, const StepBufs& b,
+             hipStream_t st) {
+  int rc;
+  if ((rc = lrbms_online_assemble(m, d_sat, mode, st)) != LRBMS_OK) return rc;
+  if ((rc = lrbms_online_solve(m, b.pN, st)) != LRBMS_OK) return rc;
+  if ((rc = lrbms_reconstruct_flux(m, b.pN, d_sat, b.flux, nullptr, st)) != LRBMS_OK) return rc;
+  if ((rc = lrbms_transport_step(m, d_sat, b.flux, b.next, d_flags, st)) != LRBMS_OK) return rc;
+  const Model& M = *model_of(m);
+  const size_t bytes = (size_t)M.g.r * M.g.ncell * sizeof(double);
+  if (!hip_ok(hipMemcpyAsync(d_sat, b.next, bytes, hipMemcpyDeviceToDevice, st), "state copy"))
+    return LRBMS_E_HIP;
+  return LRBMS_OK;
+}
+
+}  // namespace
+
+// ---- batched ensemble ------------------------------------------------------------
+
+struct Batch {
+  std::vector<lrbms_model*> models;
+  std::vector<StepBufs> bufs;
+  int mode = LRBMS_DIRECT;
+  bool use_graph = true;
+  std::vector<hipStream_t> branch;       // one per simulation, up to kBranches
+  hipStream_t origin = nullptr;          // capture origin
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double*> cap_sat;          // state pointers the graph was captured with
+  std::vector<uint8_t*> cap_flags;
+  static constexpr int kBranches = 64;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    cap_sat.clear();
+    cap_flags.clear();
+  }
+  ~Batch() {
+    for (hipStream_t s : branch) (void)hipStreamSynchronize(s);
+    if (origin) (void)hipStreamSynchronize(origin);
+    drop_graph();
+    for (lrbms_model* m : models) model_of(m)->last_stream = nullptr;
+    for (auto& b : bufs) b.release();
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipStream_t s : branch) (void)hipStreamDestroy(s);
+    if (origin) (void)hipStreamDestroy(origin);
+  }
+
+  // Fork from `from`, one step of every simulation on its branch, join back.
+  int enqueue(hipStream_t from, double* const* d_sat, uint8_t* const* d_flags) {
+    if (!hip_ok(hipEventRecord(fork, from), "fork")) return LRBMS_E_HIP;
+    const int nb = (int)branch.size();
+    for (int b = 0; b < nb; ++b)
+      if (!hip_ok(hipStreamWaitEvent(branch[b], fork, 0), "fork")) return LRBMS_E_HIP;
+    for (size_t i = 0; i < models.size(); ++i) {
+      const int rc = sim_step(models[i], mode, d_sat[i], d_flags ? d_flags[i] : nullptr, bufs[i],
+                              branch[i % nb]);
+      if (rc != LRBMS_OK) return rc;
+    }
+    for (int b = 0; b < nb; ++b)
+      if (!hip_ok(hipEventRecord(join[b], branch[b]), "join") ||
+          !hip_ok(hipStreamWaitEvent(from, join[b], 0), "join"))
+        return LRBMS_E_HIP;
+    return LRBMS_OK;
+  }
+
+  int capture(double* const* d_sat, uint8_t* const* d_flags) {
+    drop_graph();
+    if (!hip_ok(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal), "begin capture"))
+      return LRBMS_E_HIP;
+    const int rc = enqueue(origin, d_sat, d_flags);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(origin, &g);
+    if (rc != LRBMS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (!hip_ok(e, "end capture")) return LRBMS_E_HIP;
+    graph = g;
+    if (!hip_ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate")) {
+      drop_graph();
+      return LRBMS_E_HIP;
+    }
+    const size_t n = models.size();
+    cap_sat.assign(d_sat, d_sat + n);
+    if (d_flags) cap_flags.assign(d_flags, d_flags + n);
+    return LRBMS_OK;
+  }
+
+  bool same_pointers(double* const* d_sat, uint8_t* const* d_flags) const {
+    const size_t n = models.size();
+    if (!exec || cap_sat.size() != n) return false;
+    if (!std::equal(cap_sat.begin(), cap_sat.end(), d_sat)) return false;
+    if (!d_flags) return cap_flags.empty();
+    return cap_flags.size() == n && std::equal(cap_flags.begin(), cap_flags.end(), d_flags);
+  }
+};
+
+// ---- serving loop ---------------------------------------------------------------
+
+struct Server {
+  using Clock = std::chrono::steady_clock;
+  struct Sim {
+    lrbms_model* m = nullptr;
+    double* sat = nullptr;
+    long long footprint = 0;   // model bytes + step buffers
+    bool attached = false, admitted = false, busy = false;
+    StepBufs bufs;
+  };
+  struct Req {
+    int sim;
+    uint64_t id;
+    Clock::time_point t0;
+  };
+  struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    int sim = -1;
+    Req req{};
+    int rc = LRBMS_OK;
+  };
+  struct Done {
+    uint64_t id;
+    double ms;
+    int rc;
+  };
+  long long budget = 0, resident = 0;
+  int mode = LRBMS_DIRECT;
+  std::vector<Slot> slots;
+  std::vector<Sim> sims;
+  std::deque<int> waiting;     // attached, not yet admitted, in attach order
+  std::deque<Req> pending;     // submitted, not yet dispatched, in submit order
+  std::deque<Done> done;       // completed, not yet polled
+
+  ~Server() {
+    for (auto& s : slots) {
+      if (s.st) (void)hipStreamSynchronize(s.st);
+    }
+    for (auto& s : sims) {
+      if (s.m) model_of(s.m)->last_stream = nullptr;
+      s.bufs.release();
+    }
+    for (auto& s : slots) {
+      if (s.done) (void)hipEventDestroy(s.done);
+      if (s.st) (void)hipStreamDestroy(s.st);
+    }
+  }
+
+  // Admit waiting simulations, in attach order, while they fit the budget.
+  int admit() {
+    while (!waiting.empty()) {
+      Sim& S = sims[waiting.front()];
+      if (resident + S.footprint > budget) break;
+      if (!S.bufs.alloc(*model_of(S.m))) return LRBMS_E_OOM;
+      S.admitted = true;
+      resident += S.footprint;
+      waiting.pop_front();
+    }
+    return LRBMS_OK;
+  }
+
+  // Retire finished requests; then admit; then dispatch pending requests in
+  // submit order onto free slots (one request per simulation in flight).
+  int progress() {
+    for (auto& s : slots) {
+      if (s.sim < 0) continue;
+      const hipError_t e = hipEventQuery(s.done);
+      if (e == hipErrorNotReady) continue;
+      const double ms =
+          std::chrono::duration<double, std::milli>(Clock::now() - s.req.t0).count();
+      done.push_back(Done{s.req.id, ms, e == hipSuccess ? s.rc : LRBMS_E_HIP});
+      sims[s.sim].busy = false;
+      s.sim = -1;
+    }
+    int rc = admit();
+    if (rc != LRBMS_OK) return rc;
+    size_t free_slots = 0;
+    for (auto& s : slots) free_slots += s.sim < 0;
+    for (auto it = pending.begin(); it != pending.end() && free_slots > 0;) {
+      Sim& S = sims[it->sim];
+      if (!S.admitted || S.busy) {
+        ++it;
+        continue;
+      }
+      Slot* slot = nullptr;
+      for (auto& s : slots)
+        if (s.sim < 0) {
+          slot = &s;
+          break;
+        }
+      slot->sim = it->sim;
+      slot->req = *it;
+      slot->rc = sim_step(S.m, mode, S.sat, nullptr, S.bufs, slot->st);
+      if (!hip_ok(hipEventRecord(slot->done, slot->st), "request event")) slot->rc = LRBMS_E_HIP;
+      model_of(S.m)->last_stream = slot->st;
+      S.busy = true;
+      --free_slots;
+      it = pending.erase(it);
+    }
+    return LRBMS_OK;
+  }
+
+  bool idle() const {
+    for (auto& s : slots)
+      if (s.sim >= 0) return false;
+    return true;
+  }
+};
+
+}  // namespace lrbms
+
+using namespace lrbms;
+
+extern "C" {
+
+int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int32_t flags,
+                       lrbms_batch** out) {
+  try {
+    if (!out || !models || n < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
+    *out = nullptr;
+    if (flags & ~LRBMS_BATCH_GRAPH) return (set_error("unknown batch flags"), LRBMS_E_ARG);
+    for (int i = 0; i < n; ++i) {
+      if (!models[i]) return (set_error("NULL model"), LRBMS_E_ARG);
+      for (int j = 0; j < i; ++j)
+        if (models[j] == models[i])
+          return (set_error("a model appears twice in the batch"), LRBMS_E_ARG);
+      if (!mode_ok(*model_of(models[i]), mode))
+        return (set_error("assembly mode not available for every model"), LRBMS_E_ARG);
+    }
+    auto B = std::make_unique<Batch>();
+    B->models.assign(models, models + n);
+    B->mode = mode;
+    B->use_graph = (flags & LRBMS_BATCH_GRAPH) != 0;
+    B->bufs.resize(n);
+    for (int i = 0; i < n; ++i)
+      if (!B->bufs[i].alloc(*model_of(models[i]))) return LRBMS_E_OOM;
+    const int nb = std::min(n, Batch::kBranches);
+    B->branch.assign(nb, nullptr);
+    B->join.assign(nb, nullptr);
+    for (int b = 0; b < nb; ++b)
+      if (!hip_ok(hipStreamCreateWithFlags(&B->branch[b], hipStreamNonBlocking), "stream") ||
+          !hip_ok(hipEventCreateWithFlags(&B->join[b], hipEventDisableTiming), "event"))
+        return LRBMS_E_HIP;
+    if (!hip_ok(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking), "stream") ||
+        !hip_ok(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming), "event"))
+      return LRBMS_E_HIP;
+    *out = reinterpret_cast<lrbms_batch*>(B.release());
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
+int lrbms_batch_step(lrbms_batch* b, double* const* d_sat, uint8_t* const* d_flags, void* stream) {
+  if (!b || !d_sat) return (set_error("NULL argument"), LRBMS_E_ARG);
+  Batch* B = reinterpret_cast<Batch*>(b);
+  const size_t n = B->models.size();
+  for (size_t i = 0; i < n; ++i) {
+    if (!d_sat[i]) return (set_error("NULL state"), LRBMS_E_ARG);
+    if (model_of(B->models[i])->timer.on)
+      return (set_error("kernel timing is on for a model of the batch"), LRBMS_E_STATE);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (B->use_graph) {
+    if (!B->same_pointers(d_sat, d_flags) && (rc = B->capture(d_sat, d_flags)) != LRBMS_OK)
+      return rc;
+    if (!hip_ok(hipGraphLaunch(B->exec, st), "graph launch")) return LRBMS_E_HIP;
+  } else if ((rc = B->enqueue(st, d_sat, d_flags)) != LRBMS_OK) {
+    return rc;
+  }
+  for (lrbms_model* m : B->models) model_of(m)->last_stream = st;
+  return LRBMS_OK;
+}
+
+int lrbms_batch_buffers(lrbms_batch* b, int32_t i, double** d_pN, double** d_flux) {
+  if (!b) return (set_error("NULL batch"), LRBMS_E_ARG);
+  Batch* B = reinterpret_cast<Batch*>(b);
+  if (i < 0 || i >= (int)B->models.size()) return (set_error("index out of range"), LRBMS_E_ARG);
+  if (d_pN) *d_pN = B->bufs[i].pN;
+  if (d_flux) *d_flux = B->bufs[i].flux;
+  return LRBMS_OK;
+}
+
+void lrbms_batch_destroy(lrbms_batch* b) { delete reinterpret_cast<Batch*>(b); }
+
+int lrbms_server_create(int64_t hbm_budget, int32_t max_slots, int32_t mode, lrbms_server** out) {
+  try {
+    if (!out || hbm_budget <= 0 || max_slots < 1 || max_slots > 64)
+      return (set_error("invalid argument"), LRBMS_E_ARG);
+    *out = nullptr;
+    if (mode != LRBMS_DIRECT && mode != LRBMS_DIRECT_FIT && mode != LRBMS_AFFINE)
+      return (set_error("unknown assembly mode"), LRBMS_E_ARG);
+    auto S = std::make_unique<Server>();
+    S->budget = hbm_budget;
+    S->mode = mode;
+    S->slots.resize(max_slots);
+    for (auto& s : S->slots)
+      if (!hip_ok(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking), "stream") ||
+          !hip_ok(hipEventCreateWithFlags(&s.done, hipEventDisableTiming), "event"))
+        return LRBMS_E_HIP;
+    *out = reinterpret_cast<lrbms_server*>(S.release());
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
+int lrbms_server_attach(lrbms_server* s, lrbms_model* m, double* d_sat, int32_t* sim_id) {
+  try {
+    if (!s || !m || !d_sat || !sim_id) return (set_error("NULL argument"), LRBMS_E_ARG);
+    Server* S = reinterpret_cast<Server*>(s);
+    const Model& M = *model_of(m);
+    for (auto& x : S->sims)
+      if (x.attached && x.m == m) return (set_error("model already attached"), LRBMS_E_ARG);
+    if (!mode_ok(M, S->mode)) return (set_error("assembly mode not available"), LRBMS_E_ARG);
+    if (M.timer.on) return (set_error("kernel timing is on for this model"), LRBMS_E_STATE);
+    Server::Sim x;
+    x.m = m;
+    x.sat = d_sat;
+    x.footprint = M.dev_bytes + (long long)sizeof(double) *
+                                    ((long long)std::max(M.N, 1) + std::max(M.g.nface, 1) +
+                                     (long long)M.g.r * M.g.ncell);
+    if (x.footprint > S->budget)
+      return (set_error("simulation footprint exceeds the memory budget"), LRBMS_E_ADMIT);
+    // the slot streams do not wait for the caller's streams: whatever wrote
+    // the state must be finished
+    if (!hip_ok(hipDeviceSynchronize(), "synchronize")) return LRBMS_E_HIP;
+    x.attached = true;
+    S->sims.push_back(x);
+    *sim_id = (int32_t)S->sims.size() - 1;
+    S->waiting.push_back(*sim_id);
+    return S->progress();
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
+int lrbms_server_submit(lrbms_server* s, int32_t sim_id, uint64_t req_id) {
+  try {
+    if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+    Server* S = reinterpret_cast<Server*>(s);
+    if (sim_id < 0 || sim_id >= (int)S->sims.size() || !S->sims[sim_id].attached)
+      return (set_error("unknown simulation"), LRBMS_E_ARG);
+    S->pending.push_back(Server::Req{sim_id, req_id, Server::Clock::now()});
+    return S->progress();
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
+int lrbms_server_poll(lrbms_server* s, uint64_t* req_ids, double* latency_ms, int32_t* status,
+                      int32_t cap, int32_t* n_done) {
+  if (!s || !n_done || cap < 0 || (cap > 0 && !req_ids)) return (set_error("invalid argument"), LRBMS_E_ARG);
+  Server* S = reinterpret_cast<Server*>(s);
+  const int rc = S->progress();
+  int k = 0;
+  while (k < cap && !S->done.empty()) {
+    const auto& d = S->done.front();
+    req_ids[k] = d.id;
+    if (latency_ms) latency_ms[k] = d.ms;
+    if (status) status[k] = d.rc;
+    S->done.pop_front();
+    ++k;
+  }
+  *n_done = k;
+  return rc;
+}
+
+int lrbms_server_drain(lrbms_server* s) {
+  if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+  Server* S = reinterpret_cast<Server*>(s);
+  for (;;) {
+    int rc = S->progress();
+    if (rc != LRBMS_OK) return rc;
+    if (S->idle()) {
+      if (S->pending.empty()) return LRBMS_OK;
+      // nothing in flight and nothing dispatchable: the rest waits for memory
+      return (set_error("pending requests wait for memory no detach will free"), LRBMS_E_ADMIT);
+    }
+    for (auto& x : S->slots)
+      if (x.sim >= 0) {
+        (void)hipEventSynchronize(x.done);
+        break;
+      }
+  }
+}
+
+int lrbms_server_detach(lrbms_server* s, int32_t sim_id) {
+  if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+  Server* S = reinterpret_cast<Server*>(s);
+  if (sim_id < 0 || sim_id >= (int)S->sims.size() || !S->sims[sim_id].attached)
+    return (set_error("unknown simulation"), LRBMS_E_ARG);
+  Server::Sim& x = S->sims[sim_id];
+  for (const auto& r : S->pending)
+    if (r.sim == sim_id) return (set_error("simulation has pending requests"), LRBMS_E_STATE);
+  for (auto& sl : S->slots)
+    if (sl.sim == sim_id) (void)hipEventSynchronize(sl.done);
+  int rc = S->progress();
+  if (x.admitted) S->resident -= x.footprint;
+  x.bufs.release();
+  S->waiting.erase(std::remove(S->waiting.begin(), S->waiting.end(), sim_id), S->waiting.end());
+  model_of(x.m)->last_stream = nullptr;
+  x = Server::Sim{};
+  if (rc == LRBMS_OK) rc = S->progress();
+  return rc;
+}
+
+int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info) {
+  if (!s || !info) return (set_error("NULL argument"), LRBMS_E_ARG);
+  const Server* S = reinterpret_cast<const Server*>(s);
+  info->resident_bytes = S->resident;
+  info->budget_bytes = S->budget;
+  info->n_pending = (int32_t)S->pending.size();
+  int busy = 0, adm = 0, wait = (int)S->waiting.size();
+  for (auto& sl : S->slots) busy += sl.sim >= 0;
+  for (auto& x : S->sims) adm += x.attached && x.admitted;
+  info->n_in_flight = busy;
+  info->n_admitted = adm;
+  info->n_waiting = wait;
+  return LRBMS_OK;
+}
+
+void lrbms_server_destroy(lrbms_server* s) { delete reinterpret_cast<Server*>(s); }
+
+}  // extern "C"

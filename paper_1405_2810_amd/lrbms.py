@@ -112,6 +112,20 @@ def lib():
         L.lrbms_fine_destroy.restype = None
         L.lrbms_model_destroy.argtypes = [vp]
         L.lrbms_model_destroy.restype = None
+        L.lrbms_batch_create.argtypes = [vp, i32, i32, i32, C.POINTER(vp)]
+        L.lrbms_batch_step.argtypes = [vp, vp, vp, vp]
+        L.lrbms_batch_buffers.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp)]
+        L.lrbms_batch_destroy.argtypes = [vp]
+        L.lrbms_batch_destroy.restype = None
+        L.lrbms_server_create.argtypes = [C.c_int64, i32, i32, C.POINTER(vp)]
+        L.lrbms_server_attach.argtypes = [vp, vp, vp, C.POINTER(i32)]
+        L.lrbms_server_submit.argtypes = [vp, i32, C.c_uint64]
+        L.lrbms_server_poll.argtypes = [vp, vp, vp, vp, i32, C.POINTER(i32)]
+        L.lrbms_server_drain.argtypes = [vp]
+        L.lrbms_server_detach.argtypes = [vp, i32]
+        L.lrbms_server_info.argtypes = [vp, vp]
+        L.lrbms_server_destroy.argtypes = [vp]
+        L.lrbms_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -319,15 +333,34 @@ class Model:
         _check(lib().lrbms_model_interfaces(self._h, _ptr(ax), _ptr(lo), _ptr(hi)))
         return ax, lo, hi
 
-    def export_basis(self):
-        """(sizes, basis) as given to lrbms_model_create."""
+    def box_cells(self) -> list:
+        """Cells per coarse box, boxes in lexicographic order (x fastest)."""
         cuts = [np.asarray(c) for c in self.prob.cuts]
-        ncells = []
+        out = []
         for ez in range(len(cuts[2]) - 1 if self.prob.dim == 3 else 1):
             for ey in range(len(cuts[1]) - 1):
                 for ex in range(len(cuts[0]) - 1):
                     nz = (cuts[2][ez + 1] - cuts[2][ez]) if self.prob.dim == 3 else 1
-                    ncells.append((cuts[0][ex + 1] - cuts[0][ex]) * (cuts[1][ey + 1] - cuts[1][ey]) * nz)
+                    out.append(int((cuts[0][ex + 1] - cuts[0][ex]) *
+                                   (cuts[1][ey + 1] - cuts[1][ey]) * nz))
+        return out
+
+    def truncated(self, caps):
+        """A new model with the first min(caps[E], N_E) basis functions of
+        every box E (orthonormal subsets of the orthonormal local bases)."""
+        sizes, flat = self.export_basis()
+        r = self.info["r"]
+        keep, parts, off = [], [], 0
+        for NE, nE, cap in zip(sizes, self.box_cells(), caps):
+            k = int(min(NE, cap))
+            parts.append(flat[off:off + k * r * nE])
+            keep.append(k)
+            off += int(NE) * r * nE
+        return Model.create(self.prob, keep, np.concatenate(parts))
+
+    def export_basis(self):
+        """(sizes, basis) as given to lrbms_model_create."""
+        ncells = self.box_cells()
         sizes = np.empty(self.info["n_sub"], dtype=np.int32)
         basis = np.empty(sum(63 * self.info["r"] * n for n in ncells))   # at most 63 per box
         _check(lib().lrbms_model_export_basis(self._h, _ptr(sizes), _ptr(basis)))
@@ -490,3 +523,103 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
         levels.append(dict(fronts=lf, asm=asm, steps=steps))
     return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,
                 front_doubles=fd, vec_doubles=vd, inv_doubles=idd, lpan_doubles=lpd, flops=flops)
+
+
+BATCH_GRAPH = 1
+
+
+class ServerInfo_C(C.Structure):
+    _fields_ = [("resident_bytes", C.c_int64), ("budget_bytes", C.c_int64),
+                ("n_pending", C.c_int32), ("n_in_flight", C.c_int32),
+                ("n_admitted", C.c_int32), ("n_waiting", C.c_int32)]
+
+
+class Batch:
+    """Batched ensemble (lrbms_batch_*): one time step of every model per
+    ``step``; states are device tensors advanced in place.  Close it before
+    closing its models."""
+
+    def __init__(self, models: Sequence["Model"], mode=DIRECT, graph: bool = True):
+        self.models = list(models)
+        arr = (C.c_void_p * len(self.models))(*[m._h for m in self.models])
+        h = C.c_void_p()
+        _check(lib().lrbms_batch_create(arr, len(self.models), mode,
+                                        BATCH_GRAPH if graph else 0, C.byref(h)))
+        self._h = h
+
+    def step(self, sats, flags=None, stream=None):
+        n = len(self.models)
+        if len(sats) != n or (flags is not None and len(flags) != n):
+            raise ValueError("one state (and flag buffer) per model")
+        sp = (C.c_void_p * n)(*[_ptr(x) for x in sats])
+        fp = None if flags is None else (C.c_void_p * n)(*[_ptr(x) for x in flags])
+        _check(lib().lrbms_batch_step(self._h, sp, fp, _stream(stream)))
+
+    def buffers(self, i: int):
+        """Device addresses of simulation i's p_N and face fluxes."""
+        a, b = C.c_void_p(), C.c_void_p()
+        _check(lib().lrbms_batch_buffers(self._h, i, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lrbms_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (lrbms_server_*): simulations attached with their state,
+    admitted by memory footprint; requests (one time step each) dispatched
+    onto slot streams as slots free up.  Close it before closing its models."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT):
+        h = C.c_void_p()
+        _check(lib().lrbms_server_create(int(hbm_budget), max_slots, mode, C.byref(h)))
+        self._h = h
+
+    def attach(self, model: "Model", sat) -> int:
+        sid = C.c_int32()
+        _check(lib().lrbms_server_attach(self._h, model._h, _ptr(sat), C.byref(sid)))
+        return sid.value
+
+    def detach(self, sim: int):
+        _check(lib().lrbms_server_detach(self._h, sim))
+
+    def submit(self, sim: int, req_id: int):
+        _check(lib().lrbms_server_submit(self._h, sim, req_id))
+
+    def poll(self, cap: int = 256):
+        """Finished requests: list of (req_id, latency_ms, status)."""
+        ids = np.zeros(cap, np.uint64)
+        lat = np.zeros(cap, np.float64)
+        st = np.zeros(cap, np.int32)
+        n = C.c_int32()
+        _check(lib().lrbms_server_poll(self._h, ids.ctypes.data, lat.ctypes.data, st.ctypes.data,
+                                       cap, C.byref(n)))
+        k = n.value
+        return list(zip(ids[:k].tolist(), lat[:k].tolist(), st[:k].tolist()))
+
+    def drain(self):
+        _check(lib().lrbms_server_drain(self._h))
+
+    def info(self) -> dict:
+        i = ServerInfo_C()
+        _check(lib().lrbms_server_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in ServerInfo_C._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lrbms_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,7 +6,9 @@ It holds none of the method's arithmetic: no discretization, no mobility, no
 solve.  Both the CPU oracle and the GPU path consume what it produces.
 """
 from .problems import (Problem, CONFIGS, make_problem, gaussian_field,
-                       face_counts, random_saturation, training_params, smooth_fields)
+                       face_counts, random_saturation, training_params, smooth_fields,
+                       wave_fields, ensemble_caps)
 
 __all__ = ["Problem", "CONFIGS", "make_problem", "gaussian_field", "face_counts",
-           "random_saturation", "training_params", "smooth_fields"]
+           "random_saturation", "training_params", "smooth_fields", "wave_fields",
+           "ensemble_caps"]

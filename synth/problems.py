@@ -193,6 +193,34 @@ def smooth_fields(prob: Problem, count: int, rng, corr: float = 0.3) -> list:
     return out
 
 
+def wave_fields(prob: Problem, count: int, rng) -> list:
+    """Seeded plane-wave P1 fields (SoA, orthonormal cell basis): cell means
+    sin(k . x + phase) at the cell centres with seeded wave vectors of up to
+    four periods across the domain, small random slopes.  Cheap stand-ins
+    for snapshots when only timing matters."""
+    d = prob.dim
+    vol = float(np.prod(prob.h[:d]))
+    axes = [(np.arange(prob.n[a]) + 0.5) / prob.n[a] for a in range(d)]
+    X = np.meshgrid(*axes[::-1], indexing="ij")[::-1]   # x fastest in ravel order
+    out = []
+    for _ in range(count):
+        k = rng.uniform(-4.0, 4.0, d) * 2.0 * math.pi
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        g = np.sin(sum(k[a] * X[a] for a in range(d)) + ph).ravel()
+        f = np.zeros((d + 1) * prob.ncell)
+        f[:prob.ncell] = g * math.sqrt(vol)
+        f[prob.ncell:] = 0.05 * rng.standard_normal(d * prob.ncell) * math.sqrt(vol)
+        out.append(f)
+    return out
+
+
+def ensemble_caps(prob: Problem, rng, lo: int = 5, hi: int = 60) -> np.ndarray:
+    """Seeded local basis size per coarse box (lexicographic box order),
+    uniform in [lo, hi]."""
+    n_sub = int(np.prod([len(c) - 1 for c in prob.cuts[:prob.dim]]))
+    return rng.integers(lo, hi + 1, n_sub).astype(np.int32)
+
+
 def training_params(M: int, n_train: int, rng) -> np.ndarray:
     """Training parameters mu in the simplex (sum 1, entries >= 1e-4): first
     the M unit vectors (the profiles themselves), then seeded Dirichlet
@@ -224,6 +252,15 @@ CONFIGS: Dict[str, dict] = {
                  corr=0.1, sigma=3.0, ratio=10.0, steps=100, M=16, n_train=41,
                  ne_cap=40, wells="five3d", Q=1.0e-2, dt=1.0e4, seed=33, t_end=2.0e9,
                  channels=True),
+    # ensemble members: 2D 256x256 and 3D 64x64x32 on seeded uneven coarse
+    # partitions (boxes of 16..48 cells per side in 2D, 8..24 x 8..24 x 4..12
+    # in 3D), local basis sizes drawn per box by ensemble_caps
+    "ens2d": dict(dim=2, n=(256, 256, 1), L=(1.0, 1.0, 1.0), nc=(8, 8, 1), corr=0.05,
+                  sigma=2.0, ratio=5.0, steps=200, M=16, n_train=26, ne_cap=60,
+                  wells="quarter5", Q=1.2e-6, dt=0.2, seed=101, uneven=True, t_end=8.0e4),
+    "ens3d": dict(dim=3, n=(64, 64, 32), L=(640.0, 640.0, 64.0), nc=(4, 4, 4), corr=0.1,
+                  sigma=3.0, ratio=10.0, steps=100, M=16, n_train=26, ne_cap=60,
+                  wells="five3d", Q=4.0e-3, dt=1.0e4, seed=201, uneven=True, t_end=2.0e9),
     # small cases for tests
     "tiny2d": dict(dim=2, n=(8, 8, 1), L=(1.0, 1.0, 1.0), nc=(2, 2, 1), corr=0.2,
                    sigma=1.0, ratio=10.0, steps=5, M=4, n_train=6, ne_cap=6,

@@ -80,3 +80,25 @@ def test_fine_solver_arguments_checked_before_device_work(L):
     with pytest.raises(L.LrbmsError) as ei:
         L.time_of_flight(p, None, buf)
     assert ei.value.code == -1
+
+
+def test_batch_and_server_arguments_checked_before_device_work(L):
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.lrbms_batch_create(None, 0, 0, 0, C.byref(h)) == -1
+    models = (C.c_void_p * 1)(None)
+    assert lib.lrbms_batch_create(models, 1, 0, 0, C.byref(h)) == -1
+    assert lib.lrbms_batch_step(None, None, None, None) == -1
+    assert lib.lrbms_batch_buffers(None, 0, None, None) == -1
+    for budget, slots, mode in ((0, 4, 0), (1 << 30, 0, 0), (1 << 30, 65, 0), (1 << 30, 4, 9)):
+        assert lib.lrbms_server_create(budget, slots, mode, C.byref(h)) == -1
+    sid = C.c_int32()
+    assert lib.lrbms_server_attach(None, None, None, C.byref(sid)) == -1
+    assert lib.lrbms_server_submit(None, 0, 1) == -1
+    n = C.c_int32()
+    assert lib.lrbms_server_poll(None, None, None, None, 0, C.byref(n)) == -1
+    assert lib.lrbms_server_drain(None) == -1
+    assert lib.lrbms_server_detach(None, 0) == -1
+    assert lib.lrbms_server_info(None, None) == -1
+    lib.lrbms_batch_destroy(None)
+    lib.lrbms_server_destroy(None)
