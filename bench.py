@@ -100,10 +100,11 @@ def _states(members, seed):
 
 
 def bench_batch(members, steps: int, warmup: int):
-    """One ensemble step = one online step (DIRECT) of every member.  Three
-    ways: the plain per-simulation path (members one after another on one
-    stream), the batch with direct launches on per-member branches, and the
-    batch captured into one graph (one launch per ensemble step)."""
+    """One ensemble step = one online step (DIRECT) of every member.  The
+    plain per-simulation path (members one after another on one stream)
+    against the batch: members on branches of their own with direct launches
+    or captured into one graph (one launch per ensemble step), each with the
+    members' own reduced solves or with one fused solve for all members."""
     import torch
     from paper_1405_2810_amd.lrbms import Batch, DIRECT
     st = torch.cuda.current_stream()
@@ -138,14 +139,18 @@ def bench_batch(members, steps: int, warmup: int):
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
 
     res = {"plain": timed(plain)}
-    for key, graph in (("batched_streams", False), ("batched_graph", True)):
-        B = Batch(models, mode=DIRECT, graph=graph)
+    for key, graph, fused in (("batched_streams", False, False), ("batched_graph", True, False),
+                              ("fused_solve_streams", False, True),
+                              ("fused_solve_graph", True, True)):
+        B = Batch(models, mode=DIRECT, graph=graph, fused=fused)
         res[key] = timed(lambda: B.step(sats, None, st))
+        if B.status() != 0:
+            raise RuntimeError(f"device status error in the {key} pass")
         B.close()
     for m in models:
         if m.status() != 0:
             raise RuntimeError("device status error in the batched pass")
-    for k in ("batched_streams", "batched_graph"):
+    for k in res:
         res[k]["vs_plain"] = res[k]["solves_per_s"] / res["plain"]["solves_per_s"]
     return res
 

@@ -306,6 +306,16 @@ int lrbms_copy_theta(lrbms_model* m, double* theta);
 int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,
                              int32_t leaf_max, int64_t* buf, int64_t cap, int64_t* needed);
 
+/* The same for the combined plan of a fused batch of n problems (member k
+ * with basis sizes basis_sizes[k] and leaf size leaf_max[k]): fronts, nodes
+ * and work lists of all members, level by level, with their offsets into
+ * shared storage (A_N blocks, f_N and p_N of the members one after another,
+ * in member order).  Host only; LRBMS_E_ARG also when an offset of the plan
+ * would fall outside its storage.                                              */
+int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
+                                   const int32_t* const* basis_sizes, const int32_t* leaf_max,
+                                   int32_t n, int64_t* buf, int64_t cap, int64_t* needed);
+
 /* Kernel timing, for roofline measurement (off by default).
  * lrbms_profile_enable synchronizes the model's last stream, clears the
  * counters and switches timing on (enable != 0) or off.  While on, every
@@ -338,12 +348,18 @@ int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int3
  * (lrbms_profile_enable) must be off for its models (LRBMS_E_STATE otherwise). */
 
 typedef struct lrbms_batch lrbms_batch;
-#define LRBMS_BATCH_GRAPH 1  /* capture the whole batched step into one HIP graph */
+#define LRBMS_BATCH_GRAPH 1        /* capture the whole batched step into one HIP graph */
+#define LRBMS_BATCH_FUSED_SOLVE 2  /* one reduced solve for all members (shared launches) */
 
 /* Batched ensemble: n models (distinct) advanced together.  The batch owns,
  * per simulation, p_N [N], the face fluxes [nface] and the next state
  * [r*ncell] (device).  mode: LRBMS_DIRECT / _FIT / AFFINE, available for
- * every model (LRBMS_E_ARG otherwise).  flags: 0 or LRBMS_BATCH_GRAPH.
+ * every model (LRBMS_E_ARG otherwise).  flags: LRBMS_BATCH_GRAPH and/or
+ * LRBMS_BATCH_FUSED_SOLVE.  Fused: the members' reduced systems are solved
+ * together: one multifrontal plan holds the fronts of every member (level by
+ * level), so each launch of the solver processes the fronts of all members
+ * at that point of their schedules; the members' A_N and f_N live in storage
+ * of the batch while it exists (a model belongs to at most one fused batch).
  * Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP.                              */
 int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int32_t flags,
                        lrbms_batch** out);
@@ -358,6 +374,10 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
  * step is one graph launch; otherwise the branches are launched directly.
  * Errors: LRBMS_E_ARG, LRBMS_E_STATE, LRBMS_E_HIP.                             */
 int lrbms_batch_step(lrbms_batch* b, double* const* d_sat, uint8_t* const* d_flags, void* stream);
+
+/* Synchronize the device; the first non-zero status of the fused solve or of
+ * the members (as lrbms_model_status), else 0.                                */
+int lrbms_batch_status(lrbms_batch* b);
 
 /* Device pointers of simulation i's p_N and face fluxes of the last step.  */
 int lrbms_batch_buffers(lrbms_batch* b, int32_t i, double** d_pN, double** d_flux);

@@ -1279,59 +1279,98 @@ void lrbms_model_destroy(lrbms_model* m) {
   delete M;
 }
 
+}  // extern "C"
+
+namespace lrbms {
+// The plan flattened into int64 records (layout parsed by the Python binding).
+static std::vector<int64_t> flatten_plan(const SolverPlan& plan) {
+  std::vector<int64_t> o;
+  const int H = plan.nlevels;
+  o.push_back((int64_t)plan.fronts.size());
+  o.push_back(H);
+  o.push_back((int64_t)plan.nodes.size());
+  o.push_back((int64_t)plan.children.size());
+  o.push_back(plan.lpan_doubles);
+  o.push_back(plan.front_doubles);
+  o.push_back(plan.vec_doubles);
+  o.push_back(plan.inv_doubles);
+  o.push_back((int64_t)(plan.flops));
+  for (auto& f : plan.fronts) {
+    int64_t v[12] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
+                     f.nchild, f.n_s_nodes, f.npanels, f.loff};
+    o.insert(o.end(), v, v + 12);
+  }
+  for (auto& n : plan.nodes) {
+    int64_t v[4] = {n.pos, n.pn_off, n.size, n.ppos};
+    o.insert(o.end(), v, v + 4);
+  }
+  for (int c : plan.children) o.push_back(c);
+  for (int h = 0; h < H; ++h) {
+    o.push_back((int64_t)plan.level_fronts[h].size());
+    for (int f : plan.level_fronts[h]) o.push_back(f);
+    o.push_back((int64_t)plan.asm_items[h].size());
+    for (auto& it : plan.asm_items[h]) {
+      int64_t v[7] = {it.front, it.dr, it.dc, it.nr, it.nc, it.diag, it.nsrc};
+      o.insert(o.end(), v, v + 7);
+      for (int q = 0; q < 3; ++q) {
+        int64_t w[4] = {it.src[q].so, it.src[q].rs, it.src[q].cs, it.src[q].kind};
+        o.insert(o.end(), w, w + 4);
+      }
+    }
+    o.push_back((int64_t)plan.step_items[h].size());
+    for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
+      o.push_back((int64_t)plan.step_items[h][p].size());
+      for (auto& it : plan.step_items[h][p]) {
+        int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
+        o.insert(o.end(), v, v + 4);
+      }
+    }
+  }
+  return o;
+}
+}  // namespace lrbms
+
+extern "C" {
+
 int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,
                              int32_t leaf_max, int64_t* buf, int64_t cap, int64_t* needed) {
+  return lrbms_solver_plan_export_batch(&prob, &basis_sizes, &leaf_max, 1, buf, cap, needed);
+}
+
+int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
+                                   const int32_t* const* basis_sizes, const int32_t* leaf_max,
+                                   int32_t n, int64_t* buf, int64_t cap, int64_t* needed) {
   try {
-    int rc = check_problem(prob);
-    if (rc) return rc;
-    if (!basis_sizes || !needed || leaf_max < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
-    Model tmp;
-    setup_layout(tmp, prob, basis_sizes);
-    SolverPlan plan;
-    if (!build_solver_plan(tmp.g.dim, tmp.nc, tmp.subs, tmp.ifaces, leaf_max, plan))
-      return (set_error("solver symbolic analysis failed"), LRBMS_E_ARG);
-    std::vector<int64_t> o;
-    const int H = plan.nlevels;
-    o.push_back((int64_t)plan.fronts.size());
-    o.push_back(H);
-    o.push_back((int64_t)plan.nodes.size());
-    o.push_back((int64_t)plan.children.size());
-    o.push_back(plan.lpan_doubles);
-    o.push_back(plan.front_doubles);
-    o.push_back(plan.vec_doubles);
-    o.push_back(plan.inv_doubles);
-    o.push_back((int64_t)(plan.flops));
-    for (auto& f : plan.fronts) {
-      int64_t v[12] = {f.off, f.voff, f.inv_off, f.m, f.u, f.node_off, f.n_nodes, f.child_off,
-                       f.nchild, f.n_s_nodes, f.npanels, f.loff};
-      o.insert(o.end(), v, v + 12);
+    if (!probs || !basis_sizes || !leaf_max || !needed || n < 1)
+      return (set_error("invalid argument"), LRBMS_E_ARG);
+    std::vector<SolverPlan> plans(n);
+    std::vector<const SolverPlan*> ptrs;
+    std::vector<long long> blk_base, pn_base;
+    long long nblk = 0, nN = 0;
+    for (int k = 0; k < n; ++k) {
+      int rc = check_problem(probs[k]);
+      if (rc) return rc;
+      if (!basis_sizes[k] || leaf_max[k] < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
+      Model tmp;
+      setup_layout(tmp, probs[k], basis_sizes[k]);
+      if (!build_solver_plan(tmp.g.dim, tmp.nc, tmp.subs, tmp.ifaces, leaf_max[k], plans[k]))
+        return (set_error("solver symbolic analysis failed"), LRBMS_E_ARG);
+      ptrs.push_back(&plans[k]);
+      blk_base.push_back(nblk);
+      pn_base.push_back(nN);
+      nblk += tmp.nblk;
+      nN += tmp.N;
     }
-    for (auto& n : plan.nodes) {
-      int64_t v[4] = {n.pos, n.pn_off, n.size, n.ppos};
-      o.insert(o.end(), v, v + 4);
+    SolverPlan combined;
+    const SolverPlan* plan = &plans[0];
+    if (n > 1) {
+      if (!combine_plans(ptrs, blk_base, pn_base, combined))
+        return (set_error("plans cannot be combined"), LRBMS_E_ARG);
+      plan = &combined;
     }
-    for (int c : plan.children) o.push_back(c);
-    for (int h = 0; h < H; ++h) {
-      o.push_back((int64_t)plan.level_fronts[h].size());
-      for (int f : plan.level_fronts[h]) o.push_back(f);
-      o.push_back((int64_t)plan.asm_items[h].size());
-      for (auto& it : plan.asm_items[h]) {
-        int64_t v[7] = {it.front, it.dr, it.dc, it.nr, it.nc, it.diag, it.nsrc};
-        o.insert(o.end(), v, v + 7);
-        for (int q = 0; q < 3; ++q) {
-          int64_t w[4] = {it.src[q].so, it.src[q].rs, it.src[q].cs, it.src[q].kind};
-          o.insert(o.end(), w, w + 4);
-        }
-      }
-      o.push_back((int64_t)plan.step_items[h].size());
-      for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
-        o.push_back((int64_t)plan.step_items[h][p].size());
-        for (auto& it : plan.step_items[h][p]) {
-          int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
-          o.insert(o.end(), v, v + 4);
-        }
-      }
-    }
+    if (!plan_in_bounds(*plan, nblk, nN))
+      return (set_error("solver plan out of bounds"), LRBMS_E_ARG);
+    const std::vector<int64_t> o = flatten_plan(*plan);
     *needed = (int64_t)o.size();
     if (buf && cap >= (int64_t)o.size()) std::copy(o.begin(), o.end(), buf);
     return LRBMS_OK;

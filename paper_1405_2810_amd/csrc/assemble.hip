@@ -238,41 +238,50 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
         for (int k = 0; k < R; ++k) po[u][f][k] = in ? cp[(long long)k * nE + ln] : 0.0;
       }
     }
+    // Y = K Phi for all items of this thread (one cell, IT columns: 256 is a
+    // multiple of PC), each stencil value read from LDS once; columns beyond
+    // N_E have zero Phi and so zero Y
+    const int lp = tid % PC, lc = p0 + lp;
+    double Y[IT][R];
+#pragma unroll
+    for (int u = 0; u < IT; ++u)
+#pragma unroll
+      for (int k = 0; k < R; ++k) Y[u][k] = 0.0;
+    if (lc < cc && want_mat) {
+      const double* K = Kst + (size_t)lc * SH::KS;
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int kp = 0; kp < R; ++kp) {
+          const double kv = K[k * R + kp];
+#pragma unroll
+          for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, ps[u][kp], Y[u][k]);
+        }
+#pragma unroll
+      for (int f = 0; f < NB; ++f)
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+          for (int kp = 0; kp < R; ++kp) {
+            const double kv = K[((1 + f) * R + k) * R + kp];
+#pragma unroll
+            for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, po[u][f][kp], Y[u][k]);
+          }
+    }
 #pragma unroll
     for (int u = 0; u < IT; ++u) {
-      const int it = tid + 256 * u;
-      const int lp = it % PC, col = it / PC;
-      const int lc = p0 + lp;
-      double Y[R];
+      const int col = (tid + 256 * u) / PC;
+      if (lc < cc && col == NE && want_rhs) {
+        int x[3];
+        box_xyz(c0 + lc, x);
 #pragma unroll
-      for (int k = 0; k < R; ++k) Y[k] = 0.0;
-      if (lc < cc) {
-        const int l = c0 + lc;
-        if (col < NE) {
-          if (want_mat) {
-            const double* K = Kst + (size_t)lc * SH::KS;
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-#pragma unroll
-              for (int kp = 0; kp < R; ++kp) Y[k] = fma(K[k * R + kp], ps[u][kp], Y[k]);
-#pragma unroll
-            for (int f = 0; f < NB; ++f)
-#pragma unroll
-              for (int k = 0; k < R; ++k)
-#pragma unroll
-                for (int kp = 0; kp < R; ++kp)
-                  Y[k] = fma(K[((1 + f) * R + k) * R + kp], po[u][f][kp], Y[k]);
-          }
-        } else if (col == NE && want_rhs) {
-          int x[3];
-          box_xyz(l, x);
-          cell_rhs<D>(g, cell_index(g, x), x, mom, parts, Y);
-        }
+        for (int k = 0; k < R; ++k) Y[u][k] = 0.0;
+        cell_rhs<D>(g, cell_index(g, x), x, mom, parts, Y[u]);
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         PhiS[(size_t)(lp * R + k) * LDP + col] = ps[u][k];
-        YS[(size_t)(lp * R + k) * LDP + col] = Y[k];
+        YS[(size_t)(lp * R + k) * LDP + col] = Y[u][k];
       }
     }
     __syncthreads();
@@ -303,6 +312,8 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
 }
 
 // Sum the chunk partials of every box in chunk order; write A[E][E] and f_E.
+// Workgroup (box, y) takes entries 256 y .. 256 y + 255 of the box's
+// NE x (NE + 1) values; eight chunks' loads are issued before their sums.
 template <int NEP>
 __global__ __launch_bounds__(256) void k_reduce_box(const Sub* __restrict__ subs,
                                                     const int* __restrict__ first_chunk,
@@ -310,18 +321,28 @@ __global__ __launch_bounds__(256) void k_reduce_box(const Sub* __restrict__ subs
                                                     int has_mat, int has_rhs,
                                                     double* __restrict__ blocks,
                                                     double* __restrict__ fN) {
+  constexpr int U = 8;
   const Sub S = subs[blockIdx.x];
   const int q0 = first_chunk[blockIdx.x], q1 = first_chunk[blockIdx.x + 1];
   const int NE = S.NE, ncol = NE + 1;
-  for (int idx = threadIdx.x; idx < NE * ncol; idx += blockDim.x) {
-    const int i = idx / ncol, j = idx % ncol;
-    double v = 0.0;
-    for (int c = q0; c < q1; ++c) v += partial[(size_t)c * NEP * NEP + (size_t)i * NEP + j];
-    if (j < NE) {
-      if (has_mat) blocks[S.blk_off + (long long)i * NE + j] = v;
-    } else if (has_rhs) {
-      fN[S.pn_off + i] = v;
-    }
+  const int idx = blockIdx.y * 256 + threadIdx.x;
+  if (idx >= NE * ncol) return;
+  const int i = idx / ncol, j = idx % ncol;
+  const double* src = partial + (size_t)i * NEP + j;
+  double v = 0.0;
+  int c = q0;
+  for (; c + U <= q1; c += U) {
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = src[(size_t)(c + u) * NEP * NEP];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v += t[u];
+  }
+  for (; c < q1; ++c) v += src[(size_t)c * NEP * NEP];
+  if (j < NE) {
+    if (has_mat) blocks[S.blk_off + (long long)i * NE + j] = v;
+  } else if (has_rhs) {
+    fN[S.pn_off + i] = v;
   }
 }
 
@@ -348,41 +369,50 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
   d4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int IT = PC * NEP / 256;   // columns per thread and piece, all on one fine face
+  const int lq = tid % PC;
   for (int q0 = 0; q0 < I.nf; q0 += PC) {
-    for (int it = tid; it < PC * NEP; it += 256) {
-      const int lq = it % PC, col = it / PC;
-      const int fq = q0 + lq;
-      double Y[R], pl[R];
+    // the fine face of this thread: cells on both sides, moments, permeabilities
+    const int fq = q0 + lq;
+    const bool live = fq < I.nf;
+    int x0[3] = {0, 0, 0}, x1[3];
+    x0[A] = SL.hi[A] - 1;
+    x0[T0] = SL.lo[T0] + (live ? fq : 0) % ext0;
+    if (D == 3) x0[T1] = SL.lo[T1] + (live ? fq : 0) / ext0;
+    for (int b = 0; b < 3; ++b) x1[b] = x0[b];
+    x1[A] = SH2.lo[A];
+    const int l0 = (x0[0] - SL.lo[0]) + extL[0] * ((x0[1] - SL.lo[1]) + extL[1] * (x0[2] - SL.lo[2]));
+    const int l1 = (x1[0] - SH2.lo[0]) + extH[0] * ((x1[1] - SH2.lo[1]) + extH[1] * (x1[2] - SH2.lo[2]));
+    const int e0 = cell_index(g, x0), e1 = cell_index(g, x1);
+    double ms[D], mo[D];
+    face_moments<D>(g, mom, e0, A, 1, ms);
+    face_moments<D>(g, mom, e1, A, 0, mo);
+    const double k0 = g.perm[e0], k1 = g.perm[e1];
+    // Phi values of every column of this thread, loaded before any arithmetic
+    double po[IT][R], pl[IT][R];
 #pragma unroll
-      for (int k = 0; k < R; ++k) Y[k] = pl[k] = 0.0;
-      if (fq < I.nf) {
-        int x0[3] = {0, 0, 0}, x1[3];
-        x0[A] = SL.hi[A] - 1;
-        x0[T0] = SL.lo[T0] + fq % ext0;
-        if (D == 3) x0[T1] = SL.lo[T1] + fq / ext0;
-        for (int b = 0; b < 3; ++b) x1[b] = x0[b];
-        x1[A] = SH2.lo[A];
-        const int l0 = (x0[0] - SL.lo[0]) + extL[0] * ((x0[1] - SL.lo[1]) + extL[1] * (x0[2] - SL.lo[2]));
-        const int l1 = (x1[0] - SH2.lo[0]) + extH[0] * ((x1[1] - SH2.lo[1]) + extH[1] * (x1[2] - SH2.lo[2]));
-        if (col < NH) {
-          const int e0 = cell_index(g, x0), e1 = cell_index(g, x1);
-          const double* cp = phi + SH2.phi_off + (long long)col * R * SH2.nE;
-          double po[R], ms[D], mo[D];
-#pragma unroll
-          for (int k = 0; k < R; ++k) po[k] = cp[(long long)k * SH2.nE + l1];
-          face_moments<D>(g, mom, e0, A, 1, ms);
-          face_moments<D>(g, mom, e1, A, 0, mo);
-          face_terms<D, A>(g, 1.0, true, g.perm[e0], g.perm[e1], ms, mo, zero, po, gam, pen, Y);
-        }
-        if (col < NL) {
-          const double* cp = phi + SL.phi_off + (long long)col * R * SL.nE;
-#pragma unroll
-          for (int k = 0; k < R; ++k) pl[k] = cp[(long long)k * SL.nE + l0];
-        }
-      }
+    for (int u = 0; u < IT; ++u) {
+      const int col = (tid + 256 * u) / PC;
+      const bool hi_ok = live && col < NH, lo_ok = live && col < NL;
+      const double* ch = phi + SH2.phi_off + (long long)(hi_ok ? col : 0) * R * SH2.nE;
+      const double* cl = phi + SL.phi_off + (long long)(lo_ok ? col : 0) * R * SL.nE;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        PhiS[(size_t)(lq * R + k) * LDP + col] = pl[k];
+        po[u][k] = hi_ok ? ch[(long long)k * SH2.nE + l1] : 0.0;
+        pl[u][k] = lo_ok ? cl[(long long)k * SL.nE + l0] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int col = (tid + 256 * u) / PC;
+      double Y[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) Y[k] = 0.0;
+      if (live && col < NH)
+        face_terms<D, A>(g, 1.0, true, k0, k1, ms, mo, zero, po[u], gam, pen, Y);
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        PhiS[(size_t)(lq * R + k) * LDP + col] = pl[u][k];
         YS[(size_t)(lq * R + k) * LDP + col] = Y[k];
       }
     }
@@ -451,7 +481,9 @@ static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub
                        g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
     ktimer_end(-1.0, -1.0, st);
     ktimer_begin(KK_ASM_REDUCE, st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce_box<NEP>), dim3(n_sub), dim3(256), 0, st, d_subs,
+    // NE (NE + 1) < NEP^2 values per box (NE < NEP), NEP a multiple of 16
+    constexpr int kSplit = NEP * NEP / 256;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce_box<NEP>), dim3(n_sub, kSplit), dim3(256), 0, st, d_subs,
                        L.first_chunk, L.partial, has_mat ? 1 : 0, has_rhs ? 1 : 0, blocks, fN);
     ktimer_end(-1.0, -1.0, st);
     hipError_t e = hipGetLastError();

@@ -40,6 +40,7 @@ struct Model {
   SolverPlan plan;
   SolverDev sdev;
   bool assembled = false;
+  void* owner = nullptr;        // fused batch whose shared storage holds d_blocks / d_fN
   hipStream_t last_stream = nullptr;
   long long dev_bytes = 0;
   // kernel timing and the fixed per-launch algorithmic figures per kernel kind

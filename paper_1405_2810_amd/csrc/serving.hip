@@ -17,6 +17,7 @@
 
 #include "common.h"
 #include "model.h"
+#include "solver.h"
 
 namespace lrbms {
 
@@ -28,13 +29,17 @@ struct StepBufs {
   double* pN = nullptr;
   double* flux = nullptr;
   double* next = nullptr;
+  bool own_pN = true;
   long long bytes = 0;
-  bool alloc(const Model& M) {
+  // pN_ext: p_N lives in storage the caller owns (the fused batch's p_N)
+  bool alloc(const Model& M, double* pN_ext = nullptr) {
     release();
     const size_t n[3] = {(size_t)std::max(M.N, 1), (size_t)std::max(M.g.nface, 1),
                          (size_t)M.g.r * M.g.ncell};
     double** p[3] = {&pN, &flux, &next};
-    for (int k = 0; k < 3; ++k) {
+    own_pN = pN_ext == nullptr;
+    if (!own_pN) pN = pN_ext;
+    for (int k = own_pN ? 0 : 1; k < 3; ++k) {
       if (!hip_ok(hipMalloc(p[k], n[k] * sizeof(double)), "hipMalloc")) {
         release();
         return false;
@@ -44,9 +49,11 @@ struct StepBufs {
     return true;
   }
   void release() {
-    for (double* q : {pN, flux, next})
+    if (pN && own_pN) (void)hipFree(pN);
+    for (double* q : {flux, next})
       if (q) (void)hipFree(q);
     pN = flux = next = nullptr;
+    own_pN = true;
     bytes = 0;
   }
 };
@@ -59,13 +66,11 @@ bool mode_ok(const Model& M, int mode) {
   return M.nprof > 0 && M.lsq_ok;
 }
 
-// One online step of one simulation on stream st; the state d_sat is
-// advanced in place (through b.next).
-int sim_step(lrbms_model* m, int mode, double* d_sat, uint8_t* d_flags, const StepBufs& b,
-             hipStream_t st) {
+// The part of one online step after the reduced solve: p_h, the fluxes, the
+// saturation step with the limiter, and the new state copied over d_sat.
+int sim_after_solve(lrbms_model* m, double* d_sat, uint8_t* d_flags, const StepBufs& b,
+                    hipStream_t st) {
   int rc;
-  if ((rc = lrbms_online_assemble(m, d_sat, mode, st)) != LRBMS_OK) return rc;
-  if ((rc = lrbms_online_solve(m, b.pN, st)) != LRBMS_OK) return rc;
   if ((rc = lrbms_reconstruct_flux(m, b.pN, d_sat, b.flux, nullptr, st)) != LRBMS_OK) return rc;
   if ((rc = lrbms_transport_step(m, d_sat, b.flux, b.next, d_flags, st)) != LRBMS_OK) return rc;
   const Model& M = *model_of(m);
@@ -73,6 +78,16 @@ int sim_step(lrbms_model* m, int mode, double* d_sat, uint8_t* d_flags, const St
   if (!hip_ok(hipMemcpyAsync(d_sat, b.next, bytes, hipMemcpyDeviceToDevice, st), "state copy"))
     return LRBMS_E_HIP;
   return LRBMS_OK;
+}
+
+// One online step of one simulation on stream st; the state d_sat is
+// advanced in place (through b.next).
+int sim_step(lrbms_model* m, int mode, double* d_sat, uint8_t* d_flags, const StepBufs& b,
+             hipStream_t st) {
+  int rc;
+  if ((rc = lrbms_online_assemble(m, d_sat, mode, st)) != LRBMS_OK) return rc;
+  if ((rc = lrbms_online_solve(m, b.pN, st)) != LRBMS_OK) return rc;
+  return sim_after_solve(m, d_sat, d_flags, b, st);
 }
 
 }  // namespace
@@ -93,6 +108,17 @@ struct Batch {
   std::vector<double*> cap_sat;          // state pointers the graph was captured with
   std::vector<uint8_t*> cap_flags;
   static constexpr int kBranches = 64;
+  // fused reduced solve: one plan for all members, shared storage for A_N,
+  // f_N and p_N (the members' block pointers point into it while the batch
+  // lives), one status word
+  bool fused = false;
+  SolverPlan cplan;
+  SolverDev cdev;
+  double *cblocks = nullptr, *cfN = nullptr, *cpN = nullptr;
+  int* cstatus = nullptr;
+  std::vector<double*> own_blocks, own_fN;
+  hipEvent_t fork2 = nullptr;
+  std::vector<hipEvent_t> join2;
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -103,32 +129,103 @@ struct Batch {
     cap_flags.clear();
   }
   ~Batch() {
-    for (hipStream_t s : branch) (void)hipStreamSynchronize(s);
-    if (origin) (void)hipStreamSynchronize(origin);
+    (void)hipDeviceSynchronize();
     drop_graph();
-    for (lrbms_model* m : models) model_of(m)->last_stream = nullptr;
+    for (size_t i = 0; i < models.size(); ++i) {
+      Model* M = model_of(models[i]);
+      M->last_stream = nullptr;
+      if (i < own_blocks.size()) {
+        M->d_blocks = own_blocks[i];
+        M->d_fN = own_fN[i];
+        M->owner = nullptr;
+      }
+    }
     for (auto& b : bufs) b.release();
+    solver_free(cdev);
+    for (void* q : {(void*)cblocks, (void*)cfN, (void*)cpN, (void*)cstatus})
+      if (q) (void)hipFree(q);
     for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join2) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
+    if (fork2) (void)hipEventDestroy(fork2);
     for (hipStream_t s : branch) (void)hipStreamDestroy(s);
     if (origin) (void)hipStreamDestroy(origin);
   }
 
+  int fork_from(hipStream_t from, hipEvent_t ev) {
+    if (!hip_ok(hipEventRecord(ev, from), "fork")) return LRBMS_E_HIP;
+    for (hipStream_t b : branch)
+      if (!hip_ok(hipStreamWaitEvent(b, ev, 0), "fork")) return LRBMS_E_HIP;
+    return LRBMS_OK;
+  }
+  int join_into(hipStream_t from, std::vector<hipEvent_t>& evs) {
+    for (size_t b = 0; b < branch.size(); ++b)
+      if (!hip_ok(hipEventRecord(evs[b], branch[b]), "join") ||
+          !hip_ok(hipStreamWaitEvent(from, evs[b], 0), "join"))
+        return LRBMS_E_HIP;
+    return LRBMS_OK;
+  }
+
   // Fork from `from`, one step of every simulation on its branch, join back.
+  // Fused: the members' assemblies on their branches, the combined reduced
+  // solve on `from`, then the members' flux and transport on their branches.
   int enqueue(hipStream_t from, double* const* d_sat, uint8_t* const* d_flags) {
-    if (!hip_ok(hipEventRecord(fork, from), "fork")) return LRBMS_E_HIP;
     const int nb = (int)branch.size();
-    for (int b = 0; b < nb; ++b)
-      if (!hip_ok(hipStreamWaitEvent(branch[b], fork, 0), "fork")) return LRBMS_E_HIP;
+    int rc;
+    if ((rc = fork_from(from, fork)) != LRBMS_OK) return rc;
     for (size_t i = 0; i < models.size(); ++i) {
-      const int rc = sim_step(models[i], mode, d_sat[i], d_flags ? d_flags[i] : nullptr, bufs[i],
-                              branch[i % nb]);
+      uint8_t* fl = d_flags ? d_flags[i] : nullptr;
+      rc = fused ? lrbms_online_assemble(models[i], d_sat[i], mode, branch[i % nb])
+                 : sim_step(models[i], mode, d_sat[i], fl, bufs[i], branch[i % nb]);
       if (rc != LRBMS_OK) return rc;
     }
-    for (int b = 0; b < nb; ++b)
-      if (!hip_ok(hipEventRecord(join[b], branch[b]), "join") ||
-          !hip_ok(hipStreamWaitEvent(from, join[b], 0), "join"))
-        return LRBMS_E_HIP;
+    if ((rc = join_into(from, join)) != LRBMS_OK || !fused) return rc;
+    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, from),
+                "fused reduced solve"))
+      return LRBMS_E_HIP;
+    if ((rc = fork_from(from, fork2)) != LRBMS_OK) return rc;
+    for (size_t i = 0; i < models.size(); ++i) {
+      rc = sim_after_solve(models[i], d_sat[i], d_flags ? d_flags[i] : nullptr, bufs[i],
+                           branch[i % nb]);
+      if (rc != LRBMS_OK) return rc;
+    }
+    return join_into(from, join2);
+  }
+
+  // Shared storage and the combined plan of the fused solve.
+  int setup_fused() {
+    const size_t n = models.size();
+    std::vector<const SolverPlan*> plans;
+    std::vector<long long> blk_base, pn_base;
+    long long nblk = 0, nN = 0;
+    for (lrbms_model* m : models) {
+      const Model& M = *model_of(m);
+      plans.push_back(&M.plan);
+      blk_base.push_back(nblk);
+      pn_base.push_back(nN);
+      nblk += M.nblk;
+      nN += M.N;
+    }
+    if (!combine_plans(plans, blk_base, pn_base, cplan) || !plan_in_bounds(cplan, nblk, nN))
+      return (set_error("fused solve: plans cannot be combined"), LRBMS_E_ARG);
+    if (!solver_upload(cplan, cdev)) return (set_error("fused solve: upload failed"), LRBMS_E_OOM);
+    auto zalloc = [](void** p, size_t bytes) {
+      return hip_ok(hipMalloc(p, std::max<size_t>(bytes, 8)), "hipMalloc") &&
+             hip_ok(hipMemset(*p, 0, std::max<size_t>(bytes, 8)), "hipMemset");
+    };
+    if (!zalloc((void**)&cblocks, sizeof(double) * nblk) ||
+        !zalloc((void**)&cfN, sizeof(double) * nN) || !zalloc((void**)&cpN, sizeof(double) * nN) ||
+        !zalloc((void**)&cstatus, sizeof(int)))
+      return LRBMS_E_OOM;
+    for (size_t i = 0; i < n; ++i) {
+      Model* M = model_of(models[i]);
+      own_blocks.push_back(M->d_blocks);
+      own_fN.push_back(M->d_fN);
+      M->d_blocks = cblocks + blk_base[i];
+      M->d_fN = cfN + pn_base[i];
+      M->owner = this;
+      if (!bufs[i].alloc(*M, cpN + pn_base[i])) return LRBMS_E_OOM;
+    }
     return LRBMS_OK;
   }
 
@@ -286,9 +383,12 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
   try {
     if (!out || !models || n < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
     *out = nullptr;
-    if (flags & ~LRBMS_BATCH_GRAPH) return (set_error("unknown batch flags"), LRBMS_E_ARG);
+    if (flags & ~(LRBMS_BATCH_GRAPH | LRBMS_BATCH_FUSED_SOLVE))
+      return (set_error("unknown batch flags"), LRBMS_E_ARG);
     for (int i = 0; i < n; ++i) {
       if (!models[i]) return (set_error("NULL model"), LRBMS_E_ARG);
+      if (model_of(models[i])->owner)
+        return (set_error("a model belongs to a fused batch already"), LRBMS_E_ARG);
       for (int j = 0; j < i; ++j)
         if (models[j] == models[i])
           return (set_error("a model appears twice in the batch"), LRBMS_E_ARG);
@@ -299,18 +399,27 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
     B->models.assign(models, models + n);
     B->mode = mode;
     B->use_graph = (flags & LRBMS_BATCH_GRAPH) != 0;
+    B->fused = (flags & LRBMS_BATCH_FUSED_SOLVE) != 0;
     B->bufs.resize(n);
-    for (int i = 0; i < n; ++i)
-      if (!B->bufs[i].alloc(*model_of(models[i]))) return LRBMS_E_OOM;
+    int rc;
+    if (B->fused) {
+      if ((rc = B->setup_fused()) != LRBMS_OK) return rc;
+    } else {
+      for (int i = 0; i < n; ++i)
+        if (!B->bufs[i].alloc(*model_of(models[i]))) return LRBMS_E_OOM;
+    }
     const int nb = std::min(n, Batch::kBranches);
     B->branch.assign(nb, nullptr);
     B->join.assign(nb, nullptr);
+    B->join2.assign(nb, nullptr);
     for (int b = 0; b < nb; ++b)
       if (!hip_ok(hipStreamCreateWithFlags(&B->branch[b], hipStreamNonBlocking), "stream") ||
-          !hip_ok(hipEventCreateWithFlags(&B->join[b], hipEventDisableTiming), "event"))
+          !hip_ok(hipEventCreateWithFlags(&B->join[b], hipEventDisableTiming), "event") ||
+          !hip_ok(hipEventCreateWithFlags(&B->join2[b], hipEventDisableTiming), "event"))
         return LRBMS_E_HIP;
     if (!hip_ok(hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking), "stream") ||
-        !hip_ok(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming), "event"))
+        !hip_ok(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming), "event") ||
+        !hip_ok(hipEventCreateWithFlags(&B->fork2, hipEventDisableTiming), "event"))
       return LRBMS_E_HIP;
     *out = reinterpret_cast<lrbms_batch*>(B.release());
     return LRBMS_OK;
@@ -348,6 +457,23 @@ int lrbms_batch_buffers(lrbms_batch* b, int32_t i, double** d_pN, double** d_flu
   if (d_pN) *d_pN = B->bufs[i].pN;
   if (d_flux) *d_flux = B->bufs[i].flux;
   return LRBMS_OK;
+}
+
+int lrbms_batch_status(lrbms_batch* b) {
+  if (!b) return (set_error("NULL batch"), LRBMS_E_ARG);
+  Batch* B = reinterpret_cast<Batch*>(b);
+  if (!hip_ok(hipDeviceSynchronize(), "synchronize")) return LRBMS_E_HIP;
+  int st = 0;
+  if (B->cstatus) {
+    if (!hip_ok(hipMemcpy(&st, B->cstatus, sizeof(int), hipMemcpyDeviceToHost), "status"))
+      return LRBMS_E_HIP;
+    if (st && !hip_ok(hipMemset(B->cstatus, 0, sizeof(int)), "status")) return LRBMS_E_HIP;
+  }
+  for (lrbms_model* m : B->models) {
+    const int ms = lrbms_model_status(m);
+    if (!st) st = ms;
+  }
+  return st;
 }
 
 void lrbms_batch_destroy(lrbms_batch* b) { delete reinterpret_cast<Batch*>(b); }

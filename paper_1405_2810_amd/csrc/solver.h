@@ -88,6 +88,24 @@ struct SolverPlan {
 bool build_solver_plan(int dim, const int nc[3], const std::vector<Sub>& subs,
                        const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan);
 
+// One plan for several independent systems solved together: the fronts, node
+// references and work lists of member k are appended level by level (levels
+// counted by height, so every member keeps its own order: assembly, first
+// tile, panel steps of a level before the next level; the backward sweep
+// from each member's root down), with all offsets shifted into shared
+// storage: front storage, L panels, inverses and vectors by the sizes of
+// the members before it, blocks of A_N by blk_base[k], f_N and p_N by
+// pn_base[k].  Every front is computed by the same items as in its own
+// plan, so each member's result is unchanged bit for bit.
+bool combine_plans(const std::vector<const SolverPlan*>& plans,
+                   const std::vector<long long>& blk_base, const std::vector<long long>& pn_base,
+                   SolverPlan& out);
+
+// Host check that every access the numeric kernels derive from the plan
+// stays inside its storage: fronts, L panels, inverses, vectors, node and
+// child lists, and sources in A_N (nblk doubles), f_N and p_N (nN doubles).
+bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN);
+
 // Device copy of a plan plus workspaces.
 struct SolverDev {
   FrontD* fronts = nullptr;

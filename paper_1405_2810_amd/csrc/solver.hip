@@ -897,6 +897,159 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
   }
 }
 
+bool combine_plans(const std::vector<const SolverPlan*>& plans,
+                   const std::vector<long long>& blk_base, const std::vector<long long>& pn_base,
+                   SolverPlan& out) {
+  if (plans.empty() || blk_base.size() != plans.size() || pn_base.size() != plans.size())
+    return false;
+  for (long long b : pn_base)
+    if (b < 0 || b >= (1LL << 30)) return false;   // p_N offsets are int
+  out = SolverPlan{};
+  int H = 0;
+  for (const SolverPlan* P : plans) H = std::max(H, P->nlevels);
+  out.nlevels = H;
+  out.level_fronts.assign(H, {});
+  out.asm_items.assign(H, {});
+  out.step_items.assign(H, {});
+  out.asm_flops.assign(H, 0.0);
+  out.asm_bytes.assign(H, 0.0);
+  out.f0_flops.assign(H, 0.0);
+  out.f0_bytes.assign(H, 0.0);
+  out.bw_flops.assign(H, 0.0);
+  out.bw_bytes.assign(H, 0.0);
+  out.step_flops.assign(H, {});
+  out.step_bytes.assign(H, {});
+  for (int h = 0; h < H; ++h) {
+    size_t np = 0;
+    for (const SolverPlan* P : plans)
+      if (h < P->nlevels) np = std::max(np, P->step_items[h].size());
+    out.step_items[h].assign(np, {});
+    out.step_flops[h].assign(np, 0.0);
+    out.step_bytes[h].assign(np, 0.0);
+  }
+  for (size_t k = 0; k < plans.size(); ++k) {
+    const SolverPlan& P = *plans[k];
+    const int fbase = (int)out.fronts.size();
+    const int nbase = (int)out.nodes.size();
+    const int cbase = (int)out.children.size();
+    const long long front0 = out.front_doubles;
+    for (FrontD f : P.fronts) {
+      f.off += out.front_doubles;
+      f.loff += out.lpan_doubles;
+      f.voff += out.vec_doubles;
+      f.inv_off += out.inv_doubles;
+      f.node_off += nbase;
+      f.child_off += cbase;
+      out.fronts.push_back(f);
+    }
+    for (NodeRef r : P.nodes) {
+      r.pn_off += (int)pn_base[k];
+      out.nodes.push_back(r);
+    }
+    for (int c : P.children) out.children.push_back(c + fbase);
+    out.front_doubles += P.front_doubles;
+    out.lpan_doubles += P.lpan_doubles;
+    out.vec_doubles += P.vec_doubles;
+    out.inv_doubles += P.inv_doubles;
+    out.flops += P.flops;
+    for (int h = 0; h < P.nlevels; ++h) {
+      for (int f : P.level_fronts[h]) out.level_fronts[h].push_back(f + fbase);
+      for (AsmItem it : P.asm_items[h]) {
+        it.front += fbase;
+        for (int q = 0; q < it.nsrc; ++q) {
+          AsmSrc& S = it.src[q];
+          S.so += S.kind == 0 ? blk_base[k] : (S.kind == 1 ? front0 : pn_base[k]);
+        }
+        out.asm_items[h].push_back(it);
+      }
+      for (size_t b = 0; b < P.step_items[h].size(); ++b) {
+        for (StepItem it : P.step_items[h][b]) {
+          it.front += fbase;
+          out.step_items[h][b].push_back(it);
+        }
+        out.step_flops[h][b] += P.step_flops[h][b];
+        out.step_bytes[h][b] += P.step_bytes[h][b];
+      }
+      out.asm_flops[h] += P.asm_flops[h];
+      out.asm_bytes[h] += P.asm_bytes[h];
+      out.f0_flops[h] += P.f0_flops[h];
+      out.f0_bytes[h] += P.f0_bytes[h];
+      out.bw_flops[h] += P.bw_flops[h];
+      out.bw_bytes[h] += P.bw_bytes[h];
+    }
+  }
+  return true;
+}
+
+bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
+  const long long nf = (long long)plan.fronts.size();
+  for (const FrontD& f : plan.fronts) {
+    const long long ld = (long long)f.m + f.u;
+    if (f.m < 1 || f.u < 0 || ld + 1 > kMaxLd) return false;
+    if (f.npanels != (f.m + kNB - 1) / kNB) return false;
+    if (f.off < 0 || f.off + (ld + 1) * ld > plan.front_doubles) return false;
+    if (f.voff < 0 || f.voff + ld > plan.vec_doubles) return false;
+    if (f.inv_off < 0 || f.inv_off + (long long)f.npanels * kNB * kNB > plan.inv_doubles)
+      return false;
+    const int last = f.npanels - 1;
+    const long long cs = std::min(kNB * (last + 1), f.m);
+    if (f.loff < 0 || lpanel_base(f, last) + (ld + 1 - cs) * kNB > plan.lpan_doubles) return false;
+    if (f.node_off < 0 || f.n_s_nodes > f.n_nodes ||
+        (long long)f.node_off + f.n_nodes > (long long)plan.nodes.size())
+      return false;
+    if (f.child_off < 0 || (long long)f.child_off + f.nchild > (long long)plan.children.size())
+      return false;
+    for (int n = 0; n < f.n_nodes; ++n) {
+      const NodeRef& r = plan.nodes[f.node_off + n];
+      if (r.pos < 0 || r.size < 0 || r.pos + r.size > ld) return false;
+      if (r.pn_off < 0 || (long long)r.pn_off + r.size > nN) return false;
+    }
+  }
+  for (int c : plan.children)
+    if (c < 0 || c >= nf) return false;
+  auto span_ok = [](long long so, int nr, int nc, int rs, int cs, long long size) {
+    const long long lo = so + std::min(0LL, (long long)(nr - 1) * rs) +
+                         std::min(0LL, (long long)(nc - 1) * cs);
+    const long long hi = so + std::max(0LL, (long long)(nr - 1) * rs) +
+                         std::max(0LL, (long long)(nc - 1) * cs);
+    return lo >= 0 && hi < size;
+  };
+  if ((int)plan.level_fronts.size() != plan.nlevels || (int)plan.asm_items.size() != plan.nlevels ||
+      (int)plan.step_items.size() != plan.nlevels)
+    return false;
+  for (int h = 0; h < plan.nlevels; ++h) {
+    for (int f : plan.level_fronts[h])
+      if (f < 0 || f >= nf) return false;
+    for (const AsmItem& it : plan.asm_items[h]) {
+      if (it.front < 0 || it.front >= nf || it.nsrc < 0 || it.nsrc > 3) return false;
+      const FrontD& f = plan.fronts[it.front];
+      const int ld = f.m + f.u;
+      if (it.nr < 1 || it.nc < 1 || it.dr < 0 || it.dc < 0 || it.dr + it.nr > ld + 1 ||
+          it.dc + it.nc > ld)
+        return false;
+      for (int q = 0; q < it.nsrc; ++q) {
+        const AsmSrc& S = it.src[q];
+        const long long size = S.kind == 0 ? nblk : (S.kind == 1 ? plan.front_doubles : nN);
+        if (S.kind < 0 || S.kind > 2 || !span_ok(S.so, it.nr, it.nc, S.rs, S.cs, size))
+          return false;
+      }
+    }
+    for (const auto& items : plan.step_items[h])
+      for (const StepItem& it : items) {
+        if (it.front < 0 || it.front >= nf) return false;
+        const FrontD& f = plan.fronts[it.front];
+        if (it.panel < 0 || it.panel >= f.npanels || it.ti < 0 || it.tj < -1 ||
+            (it.tj >= 0 && it.tj > it.ti))
+          return false;
+        const int ld = f.m + f.u;
+        const int cs = it.panel * kNB + std::min(kNB, f.m - it.panel * kNB);
+        if (cs + it.ti * kNB > ld) return false;
+        if (it.tj >= 0 && cs + it.tj * kNB >= ld) return false;
+      }
+  }
+  return true;
+}
+
 // ============================ upload / launch ================================
 template <typename T>
 static bool upload(const std::vector<T>& v, T** out, long long& bytes) {

@@ -115,6 +115,7 @@ def lib():
         L.lrbms_batch_create.argtypes = [vp, i32, i32, i32, C.POINTER(vp)]
         L.lrbms_batch_step.argtypes = [vp, vp, vp, vp]
         L.lrbms_batch_buffers.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp)]
+        L.lrbms_batch_status.argtypes = [vp]
         L.lrbms_batch_destroy.argtypes = [vp]
         L.lrbms_batch_destroy.restype = None
         L.lrbms_server_create.argtypes = [C.c_int64, i32, i32, C.POINTER(vp)]
@@ -502,6 +503,29 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
     buf = np.zeros(int(need[0]), dtype=np.int64)
     _check(L.lrbms_solver_plan_export(pc.ref(), _ptr(sz), int(leaf_max), _ptr(buf), buf.size,
                                       _ptr(need)))
+    return _parse_plan(buf)
+
+
+def solver_plan_batch(probs, sizes, leaf_max) -> dict:
+    """Host-only export of the combined plan of a fused batch
+    (lrbms_solver_plan_export_batch), parsed like solver_plan."""
+    L = lib()
+    L.lrbms_solver_plan_export_batch.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                                 C.c_void_p, C.c_int64, C.c_void_p]
+    n = len(probs)
+    pcs = [ProblemC(p) for p in probs]
+    szs = [np.ascontiguousarray(s, dtype=np.int32) for s in sizes]
+    pp = (C.c_void_p * n)(*[C.addressof(pc.struct) for pc in pcs])
+    sp = (C.c_void_p * n)(*[_ptr(s) for s in szs])
+    lv = np.ascontiguousarray(leaf_max, dtype=np.int32)
+    need = np.zeros(1, dtype=np.int64)
+    _check(L.lrbms_solver_plan_export_batch(pp, sp, _ptr(lv), n, None, 0, _ptr(need)))
+    buf = np.zeros(int(need[0]), dtype=np.int64)
+    _check(L.lrbms_solver_plan_export_batch(pp, sp, _ptr(lv), n, _ptr(buf), buf.size, _ptr(need)))
+    return _parse_plan(buf)
+
+
+def _parse_plan(buf) -> dict:
     it = iter(buf.tolist())
     nxt = lambda k: [next(it) for _ in range(k)]
     nf, H, nn, nch, lpd, fd, vd, idd, flops = nxt(9)
@@ -526,6 +550,7 @@ def solver_plan(prob, sizes, leaf_max: int = 2) -> dict:
 
 
 BATCH_GRAPH = 1
+BATCH_FUSED_SOLVE = 2
 
 
 class ServerInfo_C(C.Structure):
@@ -539,13 +564,18 @@ class Batch:
     ``step``; states are device tensors advanced in place.  Close it before
     closing its models."""
 
-    def __init__(self, models: Sequence["Model"], mode=DIRECT, graph: bool = True):
+    def __init__(self, models: Sequence["Model"], mode=DIRECT, graph: bool = True,
+                 fused: bool = False):
         self.models = list(models)
         arr = (C.c_void_p * len(self.models))(*[m._h for m in self.models])
         h = C.c_void_p()
-        _check(lib().lrbms_batch_create(arr, len(self.models), mode,
-                                        BATCH_GRAPH if graph else 0, C.byref(h)))
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_FUSED_SOLVE if fused else 0)
+        _check(lib().lrbms_batch_create(arr, len(self.models), mode, flags, C.byref(h)))
         self._h = h
+
+    def status(self) -> int:
+        """Synchronize; first non-zero device status of the batch, else 0."""
+        return lib().lrbms_batch_status(self._h)
 
     def step(self, sats, flags=None, stream=None):
         n = len(self.models)

@@ -64,12 +64,12 @@ class Plain:
         self.sat.copy_(self.nxt)
 
 
-def _check_batch(L, probs, models, mode, graph, steps=4):
+def _check_batch(L, probs, models, mode, graph, steps=4, fused=False):
     import torch
     sats = [_state(p, 40 + i) for i, p in enumerate(probs)]
     flags = [torch.full((m.info["ncell"],), 7, dtype=torch.uint8, device="cuda") for m in models]
     ref = [Plain(m, s, mode) for m, s in zip(models, sats)]
-    B = L.Batch(models, mode=mode, graph=graph)
+    B = L.Batch(models, mode=mode, graph=graph, fused=fused)
     try:
         for k in range(steps):
             if k == 2:
@@ -84,29 +84,53 @@ def _check_batch(L, probs, models, mode, graph, steps=4):
                 assert torch.equal(flags[i], r.flags), (i, k)
                 pN_addr, _ = B.buffers(i)
                 assert pN_addr
-            log(f"[batch] mode={mode} graph={graph} step {k}: {len(models)} simulations equal")
-        for m in models:
-            assert m.status() == 0
+            log(f"[batch] mode={mode} graph={graph} fused={fused} step {k}: "
+                f"{len(models)} simulations equal")
+        assert B.status() == 0
     finally:
         B.close()
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_direct_equals_plain(L, graph):
+@pytest.mark.parametrize("graph,fused", [(True, False), (False, False), (True, True),
+                                         (False, True)])
+def test_batch_direct_equals_plain(L, graph, fused):
+    """Fused: one reduced solve for all members; the plain path runs each
+    member's own solver on the same assembled systems, so p_N and every
+    state must still agree bit for bit."""
     built = [_model(L, n, i) for i, n in enumerate(NAMES)]
     probs, models = [b[0] for b in built], [b[1] for b in built]
     try:
-        _check_batch(L, probs, models, L.DIRECT, graph)
+        _check_batch(L, probs, models, L.DIRECT, graph, fused=fused)
     finally:
         for m in models:
             m.close()
 
 
-def test_batch_affine_equals_plain(L):
+@pytest.mark.parametrize("fused", [False, True])
+def test_batch_affine_equals_plain(L, fused):
     built = [_offline_model(L, n) for n in ["tiny2d", "small2d"]]
     probs, models = [b[0] for b in built], [b[1] for b in built]
     try:
-        _check_batch(L, probs, models, L.AFFINE, True, steps=3)
+        _check_batch(L, probs, models, L.AFFINE, True, steps=3, fused=fused)
+    finally:
+        for m in models:
+            m.close()
+
+
+def test_fused_batch_of_many_grids(L):
+    """Ten members of five grids (2D and 3D, even and uneven partitions,
+    basis sizes 6..40) in one fused solve."""
+    names = NAMES + ["cfg1", "small2d", "small3d", "tiny2d", "cfg1", "small3d"]
+    built = [_model(L, n, 10 + i) for i, n in enumerate(names)]
+    probs, models = [b[0] for b in built], [b[1] for b in built]
+    try:
+        _check_batch(L, probs, models, L.DIRECT, True, steps=3, fused=True)
+        # a model of a fused batch cannot join another one meanwhile
+        B = L.Batch(models[:2], fused=True)
+        with pytest.raises(L.LrbmsError) as ei:
+            L.Batch(models[1:3], fused=True)
+        assert ei.value.code == -1
+        B.close()
     finally:
         for m in models:
             m.close()
