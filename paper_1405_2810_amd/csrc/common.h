@@ -49,6 +49,11 @@ struct Iface {
 // ---- device helpers ---------------------------------------------------------
 __device__ __forceinline__ double clip01(double s) { return fmin(fmax(s, 0.0), 1.0); }
 
+// General Corey power, kept out of line: inlined at every mobility evaluation
+// it would multiply the code of the kernels many times over (instruction
+// cache misses) for a path that the quadratic exponents never take.
+__device__ __noinline__ double corey_power(double s, double e) { return pow(s, e); }
+
 __device__ __forceinline__ void mobilities(const Geom& g, double s, double& lw, double& lo) {
   const double sc = clip01(s);
   double krw, kro;
@@ -56,9 +61,9 @@ __device__ __forceinline__ void mobilities(const Geom& g, double s, double& lw, 
     krw = sc;
     kro = 1.0 - sc;
   } else {
-    krw = (g.cw == 2.0) ? sc * sc : pow(sc, g.cw);
+    krw = (g.cw == 2.0) ? sc * sc : corey_power(sc, g.cw);
     const double so = 1.0 - sc;
-    kro = (g.co == 2.0) ? so * so : pow(so, g.co);
+    kro = (g.co == 2.0) ? so * so : corey_power(so, g.co);
   }
   lw = krw / g.visc_w;
   lo = kro / g.visc_o;
