@@ -23,8 +23,8 @@ const char* kernel_kind_name(int kind) {
   static const char* const names[KK_COUNT] = {
       "k_moments",        "k_lsq",          "k_affine_sum",     "k_asm_box",
       "k_reduce_box",     "k_asm_iface",    "k_front_asm",      "k_front_factor0",
-      "k_front_step",     "k_front_backward", "k_reconstruct",  "k_flux",
-      "k_transport",      "k_limiter"};
+      "k_front_step",     "k_front_backward", "k_front_update", "k_reconstruct",
+      "k_flux",           "k_transport",      "k_limiter"};
   return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 
@@ -1317,13 +1317,15 @@ static std::vector<int64_t> flatten_plan(const SolverPlan& plan) {
         o.insert(o.end(), w, w + 4);
       }
     }
+    // a split step lists its rows-only items, then its update items
     o.push_back((int64_t)plan.step_items[h].size());
     for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
-      o.push_back((int64_t)plan.step_items[h][p].size());
-      for (auto& it : plan.step_items[h][p]) {
-        int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
-        o.insert(o.end(), v, v + 4);
-      }
+      o.push_back((int64_t)(plan.step_items[h][p].size() + plan.upd_items[h][p].size()));
+      for (const auto* list : {&plan.step_items[h][p], &plan.upd_items[h][p]})
+        for (auto& it : *list) {
+          int64_t v[4] = {it.front, it.panel, it.ti, it.tj};
+          o.insert(o.end(), v, v + 4);
+        }
     }
   }
   return o;

@@ -22,6 +22,7 @@ enum KernelKind {
   KK_FRONT_FACTOR0,
   KK_FRONT_STEP,
   KK_FRONT_BACKWARD,
+  KK_FRONT_UPDATE,
   KK_RECONSTRUCT,
   KK_FLUX,
   KK_TRANSPORT,

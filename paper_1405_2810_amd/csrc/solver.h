@@ -77,12 +77,22 @@ struct SolverPlan {
   std::vector<std::vector<int>> level_fronts;  // front ids per level (height)
   std::vector<std::vector<AsmItem>> asm_items;
   std::vector<std::vector<std::vector<StepItem>>> step_items;  // [level][panel]
+  // Steps with many tiles are split in two launches: step_items then holds
+  // one rows-only item (tj = -1) per tile row, and upd_items the trailing
+  // updates, which read both L tiles from the L store instead of forming them
+  std::vector<std::vector<std::vector<StepItem>>> upd_items;   // [level][panel]
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0, lpan_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
   std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]
   std::vector<std::vector<double>> step_flops, step_bytes;                           // [level][panel]
+  std::vector<std::vector<double>> upd_flops, upd_bytes;                             // [level][panel]
 };
+
+// Smallest number of tiles of one panel step that is split in two launches
+// (environment variable LRBMS_STEP_SPLIT_MIN, default 1024).
+int step_split_min();
+void split_steps(SolverPlan& plan, int split_min);
 
 // Build the plan for the box grid with box sizes subs[].NE and interfaces.
 bool build_solver_plan(int dim, const int nc[3], const std::vector<Sub>& subs,
@@ -113,6 +123,7 @@ struct SolverDev {
   int* children = nullptr;
   std::vector<AsmItem*> asm_items;
   std::vector<std::vector<StepItem*>> step_items;
+  std::vector<std::vector<StepItem*>> upd_items;
   std::vector<int*> level_fronts;
   double* F = nullptr;
   double* L = nullptr;

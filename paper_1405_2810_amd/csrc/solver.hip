@@ -1,5 +1,7 @@
 // Multifrontal block Cholesky of the reduced SPD system (eq. reducedSystem)
 // with nested-dissection ordering of the coarse boxes.  See solver.h.
+#include <cstdlib>
+
 #include "solver.h"
 
 #include "ktimer.h"
@@ -300,6 +302,9 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
       }
     }
   }
+  plan.upd_items.assign(H, {});
+  for (int h = 0; h < H; ++h) plan.upd_items[h].assign(plan.step_items[h].size(), {});
+  split_steps(plan, step_split_min());
   // algorithmic figures per launch: Cholesky arithmetic of the work each
   // launch does, and the front entries it must read and write (8 B each)
   plan.asm_flops.assign(H, 0.0);
@@ -310,6 +315,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.bw_bytes.assign(H, 0.0);
   plan.step_flops.assign(H, {});
   plan.step_bytes.assign(H, {});
+  plan.upd_flops.assign(H, {});
+  plan.upd_bytes.assign(H, {});
   for (int h = 0; h < H; ++h) {
     for (const AsmItem& it : plan.asm_items[h]) {
       const double e = (double)it.nr * it.nc;
@@ -318,6 +325,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     }
     plan.step_flops[h].assign(plan.step_items[h].size(), 0.0);
     plan.step_bytes[h].assign(plan.step_items[h].size(), 0.0);
+    plan.upd_flops[h].assign(plan.step_items[h].size(), 0.0);
+    plan.upd_bytes[h].assign(plan.step_items[h].size(), 0.0);
     for (int p : plan.level_fronts[h]) {
       const FrontD& d = plan.fronts[p];
       const double ld = d.m + d.u;
@@ -328,10 +337,18 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
         const double nb = std::min(kNB, d.m - b * kNB);
         const double cs = b * kNB + nb, t = ld - cs;
         const double nb1 = (b + 1 < d.npanels) ? std::min(kNB, d.m - (int)cs) : 0.0;
-        plan.step_flops[h][b] += (t + 1) * nb * nb + t * (t + 1) * nb + 2.0 * t * nb +
-                                 2.0 * nb1 * nb1 * nb1 / 3.0;
-        plan.step_bytes[h][b] += 8.0 * (2.0 * (t + 1) * nb + t * (t + 1) + 2.0 * t + nb * nb +
-                                        nb1 * nb1);
+        // L rows, then trailing update and the next diagonal tile; a split
+        // step counts them in its two launches
+        const double fl = (t + 1) * nb * nb, by = 8.0 * (2.0 * (t + 1) * nb + nb * nb);
+        const double fu = t * (t + 1) * nb + 2.0 * t * nb + 2.0 * nb1 * nb1 * nb1 / 3.0;
+        const double bu = 8.0 * (t * (t + 1) + 2.0 * t + nb1 * nb1);
+        const bool split = !plan.upd_items[h][b].empty();
+        plan.step_flops[h][b] += split ? fl : fl + fu;
+        plan.step_bytes[h][b] += split ? by : by + bu;
+        if (split) {
+          plan.upd_flops[h][b] += fu;
+          plan.upd_bytes[h][b] += bu;
+        }
       }
       const double m = d.m, u = d.u;
       plan.bw_flops[h] += 2.0 * m * u + m * m;
@@ -897,6 +914,31 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
   }
 }
 
+// Split every step of at least split_min items that still holds trailing
+// updates: each tile row keeps one rows-only item (its item with tj <= 0
+// becomes tj = -1), the items with tj >= 0 move to the update launch.
+void split_steps(SolverPlan& plan, int split_min) {
+  for (int h = 0; h < plan.nlevels; ++h)
+    for (size_t b = 0; b < plan.step_items[h].size(); ++b) {
+      std::vector<StepItem>& items = plan.step_items[h][b];
+      size_t n_upd = 0;
+      for (const StepItem& it : items) n_upd += it.tj >= 0;
+      if (n_upd == 0 || (long long)items.size() < split_min) continue;
+      std::vector<StepItem> rows;
+      std::vector<StepItem>& upd = plan.upd_items[h][b];
+      for (const StepItem& it : items) {
+        if (it.tj <= 0) rows.push_back(StepItem{it.front, it.panel, it.ti, -1});
+        if (it.tj >= 0) upd.push_back(it);
+      }
+      items.swap(rows);
+    }
+}
+
+int step_split_min() {
+  const char* e = std::getenv("LRBMS_STEP_SPLIT_MIN");
+  return e && *e ? std::atoi(e) : 1024;
+}
+
 bool combine_plans(const std::vector<const SolverPlan*>& plans,
                    const std::vector<long long>& blk_base, const std::vector<long long>& pn_base,
                    SolverPlan& out) {
@@ -919,6 +961,9 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   out.bw_bytes.assign(H, 0.0);
   out.step_flops.assign(H, {});
   out.step_bytes.assign(H, {});
+  out.upd_items.assign(H, {});
+  out.upd_flops.assign(H, {});
+  out.upd_bytes.assign(H, {});
   for (int h = 0; h < H; ++h) {
     size_t np = 0;
     for (const SolverPlan* P : plans)
@@ -926,6 +971,9 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
     out.step_items[h].assign(np, {});
     out.step_flops[h].assign(np, 0.0);
     out.step_bytes[h].assign(np, 0.0);
+    out.upd_items[h].assign(np, {});
+    out.upd_flops[h].assign(np, 0.0);
+    out.upd_bytes[h].assign(np, 0.0);
   }
   for (size_t k = 0; k < plans.size(); ++k) {
     const SolverPlan& P = *plans[k];
@@ -967,8 +1015,14 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
           it.front += fbase;
           out.step_items[h][b].push_back(it);
         }
+        for (StepItem it : P.upd_items[h][b]) {
+          it.front += fbase;
+          out.upd_items[h][b].push_back(it);
+        }
         out.step_flops[h][b] += P.step_flops[h][b];
         out.step_bytes[h][b] += P.step_bytes[h][b];
+        out.upd_flops[h][b] += P.upd_flops[h][b];
+        out.upd_bytes[h][b] += P.upd_bytes[h][b];
       }
       out.asm_flops[h] += P.asm_flops[h];
       out.asm_bytes[h] += P.asm_bytes[h];
@@ -978,6 +1032,9 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
       out.bw_bytes[h] += P.bw_bytes[h];
     }
   }
+  // the members' steps side by side can be large enough to split (the
+  // per-launch figures then stay those of the members' own launches)
+  split_steps(out, step_split_min());
   return true;
 }
 
@@ -1015,7 +1072,7 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
     return lo >= 0 && hi < size;
   };
   if ((int)plan.level_fronts.size() != plan.nlevels || (int)plan.asm_items.size() != plan.nlevels ||
-      (int)plan.step_items.size() != plan.nlevels)
+      (int)plan.step_items.size() != plan.nlevels || (int)plan.upd_items.size() != plan.nlevels)
     return false;
   for (int h = 0; h < plan.nlevels; ++h) {
     for (int f : plan.level_fronts[h])
@@ -1034,8 +1091,15 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
           return false;
       }
     }
-    for (const auto& items : plan.step_items[h])
-      for (const StepItem& it : items) {
+    if (plan.upd_items[h].size() != plan.step_items[h].size()) return false;
+    for (const auto& items : plan.upd_items[h])
+      for (const StepItem& it : items)
+        if (it.tj < 0) return false;
+    std::vector<const std::vector<StepItem>*> lists;
+    for (const auto& items : plan.step_items[h]) lists.push_back(&items);
+    for (const auto& items : plan.upd_items[h]) lists.push_back(&items);
+    for (const auto* lp : lists)
+      for (const StepItem& it : *lp) {
         if (it.front < 0 || it.front >= nf) return false;
         const FrontD& f = plan.fronts[it.front];
         if (it.panel < 0 || it.panel >= f.npanels || it.ti < 0 || it.tj < -1 ||
@@ -1048,6 +1112,79 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
       }
   }
   return true;
+}
+
+// Trailing update of one tile (ti, tj >= 0) of a split panel step: both L
+// tiles come from the L store written by the rows-only launch of the same
+// step (the values the fused step forms itself), then F(ti,tj) -= L(ti)
+// L(tj)^T; the workgroup of tile (0, 0) factors the next diagonal tile.
+__global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict__ items,
+                                                      const FrontD* __restrict__ fronts,
+                                                      double* __restrict__ F,
+                                                      const double* __restrict__ Lb,
+                                                      double* __restrict__ Inv, int* status) {
+  __shared__ Tile S0[kNB];
+  __shared__ Tile S1[kNB];
+  __shared__ Tile S2[kNB];
+  __shared__ TileAux aux;
+  const StepItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const long long ld = f.m + f.u, lda = ld + 1;
+  double* Fp = F + f.off;
+  const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
+  const int R0 = cs + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
+  const int C0 = cs + it.tj * kNB, ncl = (int)min((long long)kNB, ld - C0);
+  const bool diag = it.tj == it.ti;
+  const double* Lp = Lb + lpanel_base(f, it.panel);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  // loads: the F tile (kept in registers) and both L tiles (row-major rows of
+  // the L store, kNB doubles each), all issued before the first LDS store
+  double fold[16], la[16], lb[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    const int i = idx & 63, k = idx >> 6;
+    fold[p] = (i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
+    const int li = idx >> 6, lk = idx & 63;
+    la[p] = (li < nr && lk < nb) ? Lp[(long long)(R0 - cs + li) * kNB + lk] : 0.0;
+    lb[p] = (!diag && li < ncl && lk < nb) ? Lp[(long long)(C0 - cs + li) * kNB + lk] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    S1[idx >> 6][idx & 63] = la[p];
+    S0[idx >> 6][idx & 63] = lb[p];
+  }
+  __syncthreads();
+  const Tile* Bt = diag ? S1 : S0;
+  // U = L(ti) L(tj)^T: wave w forms row block w
+  d4 u[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) u[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nc = (nb + 3) >> 2;
+  for (int c = 0; c < nc; ++c) {
+    const double a = S1[16 * w + r][4 * c + q];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) u[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], u[cb]);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = u[cb][v];
+  __syncthreads();
+  const bool ahead = it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels;
+  const int nb1 = ahead ? min(kNB, f.m - cs) : 0;
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p;
+    const int i = idx & 63, k = idx >> 6;
+    const double nv = fold[p] - S2[i][k];
+    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = nv;
+    if (ahead) S0[i][k] = (i < nb1 && k < nb1) ? nv : (i == k ? 1.0 : 0.0);
+  }
+  if (!ahead) return;
+  __syncthreads();
+  tile_factor_inv(S0, S1, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
+                  status);
 }
 
 // ============================ upload / launch ================================
@@ -1069,13 +1206,17 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
   dev.asm_items.assign(H, nullptr);
   dev.level_fronts.assign(H, nullptr);
   dev.step_items.assign(H, {});
+  dev.upd_items.assign(H, {});
   for (int h = 0; h < H; ++h) {
     if (!upload(plan.asm_items[h], &dev.asm_items[h], b) ||
         !upload(plan.level_fronts[h], &dev.level_fronts[h], b))
       return false;
     dev.step_items[h].assign(plan.step_items[h].size(), nullptr);
+    dev.upd_items[h].assign(plan.step_items[h].size(), nullptr);
     for (size_t p = 0; p < plan.step_items[h].size(); ++p)
-      if (!upload(plan.step_items[h][p], &dev.step_items[h][p], b)) return false;
+      if (!upload(plan.step_items[h][p], &dev.step_items[h][p], b) ||
+          !upload(plan.upd_items[h][p], &dev.upd_items[h][p], b))
+        return false;
   }
   int maxld = 1;
   for (auto& f : plan.fronts) maxld = std::max(maxld, f.m + f.u);
@@ -1101,6 +1242,8 @@ void solver_free(SolverDev& dev) {
   for (auto p : dev.asm_items) f(p);
   for (auto p : dev.level_fronts) f(p);
   for (auto& v : dev.step_items)
+    for (auto p : v) f(p);
+  for (auto& v : dev.upd_items)
     for (auto p : v) f(p);
   f(dev.F);
   f(dev.L);
@@ -1131,6 +1274,13 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
         hipLaunchKernelGGL(k_front_step, dim3(ni), dim3(256), 0, st, dev.step_items[h][p],
                            dev.fronts, dev.F, dev.L, dev.Inv, status);
         ktimer_end(plan.step_flops[h][p], plan.step_bytes[h][p], st);
+      }
+      const int nu = (int)plan.upd_items[h][p].size();
+      if (nu) {
+        ktimer_begin(KK_FRONT_UPDATE, st);
+        hipLaunchKernelGGL(k_front_update, dim3(nu), dim3(256), 0, st, dev.upd_items[h][p],
+                           dev.fronts, dev.F, dev.L, dev.Inv, status);
+        ktimer_end(plan.upd_flops[h][p], plan.upd_bytes[h][p], st);
       }
     }
   }
