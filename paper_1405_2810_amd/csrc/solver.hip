@@ -1123,10 +1123,12 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
                                                       double* __restrict__ F,
                                                       const double* __restrict__ Lb,
                                                       double* __restrict__ Inv, int* status) {
+  // two tiles: L(ti) and L(tj); the product is staged in the first once
+  // both are consumed, and the look-ahead factorization works in both
   __shared__ Tile S0[kNB];
   __shared__ Tile S1[kNB];
-  __shared__ Tile S2[kNB];
   __shared__ TileAux aux;
+  Tile* S2 = S1;
   const StepItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
   const long long ld = f.m + f.u, lda = ld + 1;
@@ -1167,6 +1169,7 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) u[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], u[cb]);
   }
+  __syncthreads();   // every wave is done with both L tiles
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
