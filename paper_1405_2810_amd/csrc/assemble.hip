@@ -142,10 +142,21 @@ template <int D> struct AsmShape {
   static constexpr int PR = PC * R;             // rows per staged piece
 };
 
+// 3D boxes with up to 47 basis functions: the apply phase loads one axis of
+// neighbours at a time and chunks hold 32 cells, so that a workgroup needs
+// at most 244 registers per lane and 79 KB of LDS (two workgroups per CU);
+// elsewhere all loads of a thread are issued first and chunks hold 64 cells.
+template <int D, int NEP> struct BoxPlan {
+  static constexpr bool kPhased = D == 3 && NEP <= 48;
+  static constexpr int CH = kPhased ? 32 : AsmShape<D>::CH;
+};
+
+int box_chunk_cells(int dim, int nep) { return (dim == 3 && nep <= 48) ? 32 : 64; }
+
 template <int D, int NEP>
 __host__ __device__ constexpr size_t box_lds_doubles() {
   using S = AsmShape<D>;
-  return (size_t)S::CH * S::KS + 2 * (size_t)S::PR * (NEP + 1);
+  return (size_t)BoxPlan<D, NEP>::CH * S::KS + 2 * (size_t)S::PR * (NEP + 1);
 }
 
 template <int D, int NEP>
@@ -173,13 +184,14 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   constexpr int R = SH::R, NF = SH::NF, PC = SH::PC, PR = SH::PR, LDP = NEP + 1;
   constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 3) / 4;
   extern __shared__ double lds[];
+  constexpr int CH = BoxPlan<D, NEP>::CH;
   double* Kst = lds;                                   // [CH][KS >= NF R R]
-  double* PhiS = Kst + (size_t)SH::CH * SH::KS;        // [PR][LDP]
+  double* PhiS = Kst + (size_t)CH * SH::KS;            // [PR][LDP]
   double* YS = PhiS + (size_t)PR * LDP;                // [PR][LDP]
   const int sub = chunks[2 * blockIdx.x], c0 = chunks[2 * blockIdx.x + 1];
   const Sub S = subs[sub];
   const int NE = S.NE, nE = S.nE;
-  const int cc = min(SH::CH, nE - c0);
+  const int cc = min(CH, nE - c0);
   const int ext[3] = {S.hi[0] - S.lo[0], S.hi[1] - S.lo[1], S.hi[2] - S.lo[2]};
   const int tid = threadIdx.x;
   const bool want_mat = parts & (PART_GAMMA | PART_PEN);
@@ -215,58 +227,120 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   constexpr int IT = PC * NEP / 256;             // (cell, column) items per thread and piece
   constexpr int NB = 2 * D;
   for (int p0 = 0; p0 < cc; p0 += PC) {
-    // apply: the Phi values of all items of this thread are loaded first
-    double ps[IT][R], po[IT][NB][R];
-#pragma unroll
-    for (int u = 0; u < IT; ++u) {
-      const int it = tid + 256 * u;
-      const int lp = it % PC, col = it / PC;
-      const int lc = p0 + lp, l = c0 + lc;
-      const bool live = lc < cc && col < NE;
-      const double* cp = phi + S.phi_off + (long long)col * R * nE;
+    const int lp = tid % PC, lc = p0 + lp;
+    double ps[IT][R], Y[IT][R];
+    if constexpr (BoxPlan<D, NEP>::kPhased) {
+      // apply, one axis at a time: self values, then the two neighbours along
+      // each axis (the loads of a phase issued together; the phases kept
+      // apart so that one phase's registers serve the next)
+      const int l = c0 + lc;
       const int bl[3] = {l % ext[0], (l / ext[0]) % ext[1], l / (ext[0] * ext[1])};
       const int bst[3] = {1, ext[0], ext[0] * ext[1]};
 #pragma unroll
-      for (int k = 0; k < R; ++k) ps[u][k] = live ? cp[(long long)k * nE + l] : 0.0;
+      for (int u = 0; u < IT; ++u) {
+        const int col = (tid + 256 * u) / PC;
+        const bool live = lc < cc && col < NE;
+        const double* cp = phi + S.phi_off + (long long)col * R * nE;
 #pragma unroll
-      for (int f = 0; f < NB; ++f) {
-        const int a = f >> 1, dir = f & 1;
-        const int ba = bl[a] + (dir ? 1 : -1);
-        const bool in = live && want_mat && ba >= 0 && ba < ext[a];
-        const int ln = l + (dir ? bst[a] : -bst[a]);
-#pragma unroll
-        for (int k = 0; k < R; ++k) po[u][f][k] = in ? cp[(long long)k * nE + ln] : 0.0;
-      }
-    }
-    // Y = K Phi for all items of this thread (one cell, IT columns: 256 is a
-    // multiple of PC), each stencil value read from LDS once; columns beyond
-    // N_E have zero Phi and so zero Y
-    const int lp = tid % PC, lc = p0 + lp;
-    double Y[IT][R];
-#pragma unroll
-    for (int u = 0; u < IT; ++u)
-#pragma unroll
-      for (int k = 0; k < R; ++k) Y[u][k] = 0.0;
-    if (lc < cc && want_mat) {
-      const double* K = Kst + (size_t)lc * SH::KS;
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-#pragma unroll
-        for (int kp = 0; kp < R; ++kp) {
-          const double kv = K[k * R + kp];
-#pragma unroll
-          for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, ps[u][kp], Y[u][k]);
+        for (int k = 0; k < R; ++k) {
+          ps[u][k] = live ? cp[(long long)k * nE + l] : 0.0;
+          Y[u][k] = 0.0;
         }
-#pragma unroll
-      for (int f = 0; f < NB; ++f)
+      }
+      const double* K = Kst + (size_t)(lc < cc ? lc : 0) * SH::KS;
+      if (lc < cc && want_mat) {
 #pragma unroll
         for (int k = 0; k < R; ++k)
 #pragma unroll
           for (int kp = 0; kp < R; ++kp) {
-            const double kv = K[((1 + f) * R + k) * R + kp];
+            const double kv = K[k * R + kp];
 #pragma unroll
-            for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, po[u][f][kp], Y[u][k]);
+            for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, ps[u][kp], Y[u][k]);
           }
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        asm volatile("" ::: "memory");   // keep the next phase's loads here
+        double po[IT][2][R];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+          const int col = (tid + 256 * u) / PC;
+          const bool live = lc < cc && col < NE;
+          const double* cp = phi + S.phi_off + (long long)col * R * nE;
+#pragma unroll
+          for (int dir = 0; dir < 2; ++dir) {
+            const int ba = bl[a] + (dir ? 1 : -1);
+            const bool in = live && want_mat && ba >= 0 && ba < ext[a];
+            const int ln = l + (dir ? bst[a] : -bst[a]);
+#pragma unroll
+            for (int k = 0; k < R; ++k) po[u][dir][k] = in ? cp[(long long)k * nE + ln] : 0.0;
+          }
+        }
+        if (lc < cc && want_mat) {
+#pragma unroll
+          for (int dir = 0; dir < 2; ++dir)
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+#pragma unroll
+              for (int kp = 0; kp < R; ++kp) {
+                const double kv = K[((1 + 2 * a + dir) * R + k) * R + kp];
+#pragma unroll
+                for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, po[u][dir][kp], Y[u][k]);
+              }
+        }
+      }
+    } else {
+      // apply: the Phi values of all items of this thread are loaded first
+      double po[IT][NB][R];
+#pragma unroll
+      for (int u = 0; u < IT; ++u) {
+        const int it = tid + 256 * u;
+        const int col = it / PC;
+        const int l = c0 + lc;
+        const bool live = lc < cc && col < NE;
+        const double* cp = phi + S.phi_off + (long long)col * R * nE;
+        const int bl[3] = {l % ext[0], (l / ext[0]) % ext[1], l / (ext[0] * ext[1])};
+        const int bst[3] = {1, ext[0], ext[0] * ext[1]};
+#pragma unroll
+        for (int k = 0; k < R; ++k) ps[u][k] = live ? cp[(long long)k * nE + l] : 0.0;
+#pragma unroll
+        for (int f = 0; f < NB; ++f) {
+          const int a = f >> 1, dir = f & 1;
+          const int ba = bl[a] + (dir ? 1 : -1);
+          const bool in = live && want_mat && ba >= 0 && ba < ext[a];
+          const int ln = l + (dir ? bst[a] : -bst[a]);
+#pragma unroll
+          for (int k = 0; k < R; ++k) po[u][f][k] = in ? cp[(long long)k * nE + ln] : 0.0;
+        }
+      }
+      // Y = K Phi for all items of this thread (one cell, IT columns: 256 is a
+      // multiple of PC), each stencil value read from LDS once; columns beyond
+      // N_E have zero Phi and so zero Y
+#pragma unroll
+      for (int u = 0; u < IT; ++u)
+#pragma unroll
+        for (int k = 0; k < R; ++k) Y[u][k] = 0.0;
+      if (lc < cc && want_mat) {
+        const double* K = Kst + (size_t)lc * SH::KS;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+          for (int kp = 0; kp < R; ++kp) {
+            const double kv = K[k * R + kp];
+#pragma unroll
+            for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, ps[u][kp], Y[u][k]);
+          }
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+#pragma unroll
+          for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int kp = 0; kp < R; ++kp) {
+              const double kv = K[((1 + f) * R + k) * R + kp];
+#pragma unroll
+              for (int u = 0; u < IT; ++u) Y[u][k] = fma(kv, po[u][f][kp], Y[u][k]);
+            }
+      }
     }
 #pragma unroll
     for (int u = 0; u < IT; ++u) {
@@ -525,7 +599,7 @@ hipError_t assemble_prepare(const Geom& g, const std::vector<Sub>& subs, int max
                             AsmLayout& L, long long& bytes) {
   if (max_ne + 1 > 64) return hipErrorInvalidValue;
   std::vector<int> chunks, first(1, 0);
-  const int ch = g.dim == 2 ? AsmShape<2>::CH : AsmShape<3>::CH;
+  const int ch = box_chunk_cells(g.dim, assemble_cols(max_ne));
   for (size_t s = 0; s < subs.size(); ++s) {
     for (int c0 = 0; c0 < subs[s].nE; c0 += ch) {
       chunks.push_back((int)s);
