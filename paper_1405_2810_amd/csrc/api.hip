@@ -182,6 +182,7 @@ Model::~Model() {
   f(d_bc_type);
   f(d_bc_sat);
   f(d_phi);
+  f(d_tr);
   f(d_mom);
   f(d_blocks);
   f(d_fN);
@@ -279,6 +280,7 @@ static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) 
   M.N = pn;
   M.phi_len = phi_off;
   M.ifaces.clear();
+  long long tr = 0;
   for (int a = 0; a < p->dim; ++a)
     for (int ez = 0; ez < M.nc[2]; ++ez)
       for (int ey = 0; ey < M.nc[1]; ++ey)
@@ -297,9 +299,12 @@ static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) 
             if (b != a) I.nf *= M.subs[lo].hi[b] - M.subs[lo].lo[b];
           I.blk_off = blk;
           blk += (long long)M.subs[lo].NE * M.subs[hi].NE;
+          I.tr_off = tr;
+          tr += (long long)(M.subs[lo].NE + M.subs[hi].NE) * (p->dim + 1) * I.nf;
           M.ifaces.push_back(I);
         }
   M.n_iface = (int)M.ifaces.size();
+  M.tr_len = tr;
   M.nblk = blk;
   M.max_ne = 0;
   for (auto& s : M.subs) M.max_ne = std::max(M.max_ne, s.NE);
@@ -393,6 +398,10 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
   if (!dev_copy(&M.d_subs, M.subs.data(), M.subs.size(), b)) return LRBMS_E_OOM;
   if (!dev_copy(&M.d_ifaces, M.ifaces.data(), M.ifaces.size(), b)) return LRBMS_E_OOM;
   if (!dev_copy(&M.d_phi, basis, (size_t)M.phi_len, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_tr, (size_t)M.tr_len, b)) return LRBMS_E_OOM;
+  if (!hip_ok(launch_face_traces(g, M.d_subs, M.d_ifaces, M.n_iface, M.d_phi, M.d_tr, 0), "face traces") ||
+      !hip_ok(hipStreamSynchronize(0), "face traces"))
+    return LRBMS_E_HIP;
   if (!dev_zero(&M.d_blocks, (size_t)M.nblk, b) || !dev_zero(&M.d_fN, (size_t)M.N, b))
     return LRBMS_E_OOM;
   // reconstruction tiles (box, first cell)
@@ -459,7 +468,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
       return LRBMS_E_OOM;
     hipStream_t st = 0;
     // c: penalty part (gamma-free), e: gamma-free right-hand side
-    if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+    if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi, M.d_tr,
                                 M.d_mom, PART_PEN | PART_RHS_CONST, M.d_c, M.d_e, st),
                 "assemble c, e"))
       return LRBMS_E_HIP;
@@ -468,7 +477,7 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
                                  st),
                   "profile moments"))
         return LRBMS_E_HIP;
-      if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi,
+      if (!hip_ok(launch_assemble(M.asm_layout, g, M.d_subs, M.n_sub, M.max_ne, M.d_ifaces, M.n_iface, M.d_phi, M.d_tr,
                                   M.d_mom, PART_GAMMA | PART_RHS_GAMMA, M.d_bq + (size_t)q * M.nblk,
                                   M.d_dq + (size_t)q * M.N, st),
                   "assemble b_q, d_q"))
@@ -1106,7 +1115,7 @@ int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, voi
       return LRBMS_E_HIP;
   } else {
     if (!hip_ok(launch_assemble(M->asm_layout, g, M->d_subs, M->n_sub, M->max_ne, M->d_ifaces, M->n_iface,
-                                M->d_phi, M->d_mom, all, M->d_blocks, M->d_fN, st),
+                                M->d_phi, M->d_tr, M->d_mom, all, M->d_blocks, M->d_fN, st),
                 "assemble"))
       return LRBMS_E_HIP;
   }

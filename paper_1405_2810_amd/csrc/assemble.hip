@@ -423,10 +423,11 @@ __global__ __launch_bounds__(256) void k_reduce_box(const Sub* __restrict__ subs
 // Coupling block A[lo][hi] of one coarse interface, one workgroup per
 // interface: for 16 fine faces at a time, Y(row, j) = the face terms of the
 // lo-side test dofs against basis function j of the hi box, staged in LDS with
-// the lo-side Phi rows, then contracted on FP64 MFMA.
+// the lo-side Phi rows, then contracted on FP64 MFMA.  The Phi values on both
+// sides come from the interface's face traces (k_face_traces).
 template <int D, int A, int NEP>
 __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const Sub& SH2,
-                                           const Iface& I, const double* __restrict__ phi,
+                                           const Iface& I, const double* __restrict__ tr,
                                            const double* __restrict__ mom, int parts,
                                            double* __restrict__ blocks, double* PhiS, double* YS) {
   using SHP = AsmShape<D>;
@@ -436,8 +437,6 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
   const int NL = SL.NE, NH = SH2.NE;
   const bool gam = parts & PART_GAMMA, pen = parts & PART_PEN;
   const int ext0 = SL.hi[T0] - SL.lo[T0];
-  const int extL[3] = {SL.hi[0] - SL.lo[0], SL.hi[1] - SL.lo[1], SL.hi[2] - SL.lo[2]};
-  const int extH[3] = {SH2.hi[0] - SH2.lo[0], SH2.hi[1] - SH2.lo[1], SH2.hi[2] - SH2.lo[2]};
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
   const double zero[R] = {};
   d4 acc[TPW];
@@ -455,25 +454,24 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
     if (D == 3) x0[T1] = SL.lo[T1] + (live ? fq : 0) / ext0;
     for (int b = 0; b < 3; ++b) x1[b] = x0[b];
     x1[A] = SH2.lo[A];
-    const int l0 = (x0[0] - SL.lo[0]) + extL[0] * ((x0[1] - SL.lo[1]) + extL[1] * (x0[2] - SL.lo[2]));
-    const int l1 = (x1[0] - SH2.lo[0]) + extH[0] * ((x1[1] - SH2.lo[1]) + extH[1] * (x1[2] - SH2.lo[2]));
     const int e0 = cell_index(g, x0), e1 = cell_index(g, x1);
     double ms[D], mo[D];
     face_moments<D>(g, mom, e0, A, 1, ms);
     face_moments<D>(g, mom, e1, A, 0, mo);
     const double k0 = g.perm[e0], k1 = g.perm[e1];
-    // Phi values of every column of this thread, loaded before any arithmetic
+    // face traces of every column of this thread (contiguous over the fine
+    // faces), loaded before any arithmetic
     double po[IT][R], pl[IT][R];
+    const double* tl = tr + I.tr_off;
+    const double* th = tl + (long long)NL * R * I.nf;
 #pragma unroll
     for (int u = 0; u < IT; ++u) {
       const int col = (tid + 256 * u) / PC;
       const bool hi_ok = live && col < NH, lo_ok = live && col < NL;
-      const double* ch = phi + SH2.phi_off + (long long)(hi_ok ? col : 0) * R * SH2.nE;
-      const double* cl = phi + SL.phi_off + (long long)(lo_ok ? col : 0) * R * SL.nE;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        po[u][k] = hi_ok ? ch[(long long)k * SH2.nE + l1] : 0.0;
-        pl[u][k] = lo_ok ? cl[(long long)k * SL.nE + l0] : 0.0;
+        po[u][k] = hi_ok ? th[((long long)col * R + k) * I.nf + fq] : 0.0;
+        pl[u][k] = lo_ok ? tl[((long long)col * R + k) * I.nf + fq] : 0.0;
       }
     }
 #pragma unroll
@@ -521,7 +519,7 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
 template <int D, int NEP>
 __global__ __launch_bounds__(256) void k_asm_iface(Geom g, const Sub* __restrict__ subs,
                                                    const Iface* __restrict__ ifs,
-                                                   const double* __restrict__ phi,
+                                                   const double* __restrict__ tr,
                                                    const double* __restrict__ mom, int parts,
                                                    double* __restrict__ blocks) {
   extern __shared__ double lds[];
@@ -530,11 +528,48 @@ __global__ __launch_bounds__(256) void k_asm_iface(Geom g, const Sub* __restrict
   const Iface I = ifs[blockIdx.x];
   const Sub SL = subs[I.lo], SH2 = subs[I.hi];
   if (I.axis == 0)
-    iface_body<D, 0, NEP>(g, SL, SH2, I, phi, mom, parts, blocks, PhiS, YS);
+    iface_body<D, 0, NEP>(g, SL, SH2, I, tr, mom, parts, blocks, PhiS, YS);
   else if (I.axis == 1)
-    iface_body<D, 1, NEP>(g, SL, SH2, I, phi, mom, parts, blocks, PhiS, YS);
+    iface_body<D, 1, NEP>(g, SL, SH2, I, tr, mom, parts, blocks, PhiS, YS);
   else if constexpr (D == 3)
-    iface_body<D, 2, NEP>(g, SL, SH2, I, phi, mom, parts, blocks, PhiS, YS);
+    iface_body<D, 2, NEP>(g, SL, SH2, I, tr, mom, parts, blocks, PhiS, YS);
+}
+
+// Face traces of the local bases, one workgroup per coarse interface: for
+// fine face q of the interface (q = t0 + ext0 t1 over the tangential axes of
+// the low box), the r coefficients of every basis function of the low box at
+// its cell on the face and of the high box at its cell across it, stored
+// (function, coefficient, q) with q fastest, so that the interface assembly
+// reads them contiguously.  Set-up work, once per model.
+__global__ __launch_bounds__(256) void k_face_traces(Geom g, const Sub* __restrict__ subs,
+                                                     const Iface* __restrict__ ifs,
+                                                     const double* __restrict__ phi,
+                                                     double* __restrict__ tr) {
+  const Iface I = ifs[blockIdx.x];
+  const Sub SL = subs[I.lo], SH = subs[I.hi];
+  const int A = I.axis, T0 = (A == 0) ? 1 : 0, T1 = (A == 2) ? 1 : 2, r = g.r;
+  const int ext0 = SL.hi[T0] - SL.lo[T0];
+  const long long nlo = (long long)SL.NE * r * I.nf, n = nlo + (long long)SH.NE * r * I.nf;
+  for (long long idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const bool lo = idx < nlo;
+    const long long j = lo ? idx : idx - nlo;
+    const int q = (int)(j % I.nf), k = (int)((j / I.nf) % r), col = (int)(j / ((long long)I.nf * r));
+    const Sub& S = lo ? SL : SH;
+    int x[3] = {0, 0, 0};
+    x[A] = lo ? SL.hi[A] - 1 : SH.lo[A];
+    x[T0] = SL.lo[T0] + q % ext0;
+    if (g.dim == 3) x[T1] = SL.lo[T1] + q / ext0;
+    const int ex0 = S.hi[0] - S.lo[0], ex1 = S.hi[1] - S.lo[1];
+    const int l = (x[0] - S.lo[0]) + ex0 * ((x[1] - S.lo[1]) + ex1 * (x[2] - S.lo[2]));
+    tr[I.tr_off + idx] = phi[S.phi_off + ((long long)col * r + k) * S.nE + l];
+  }
+}
+
+hipError_t launch_face_traces(const Geom& g, const Sub* d_subs, const Iface* d_ifaces, int n_iface,
+                              const double* phi, double* tr, hipStream_t st) {
+  if (n_iface == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_traces, dim3(n_iface), dim3(256), 0, st, g, d_subs, d_ifaces, phi, tr);
+  return hipGetLastError();
 }
 
 int assemble_cols(int max_ne) { return ((max_ne + 1 + 15) / 16) * 16; }
@@ -542,8 +577,8 @@ int assemble_cols(int max_ne) { return ((max_ne + 1 + 15) / 16) * 16; }
 template <int D, int NEP>
 static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub* d_subs,
                                     int n_sub, const Iface* d_ifaces, int n_iface,
-                                    const double* phi, const double* mom, int parts,
-                                    double* blocks, double* fN, hipStream_t st) {
+                                    const double* phi, const double* tr, const double* mom,
+                                    int parts, double* blocks, double* fN, hipStream_t st) {
   const bool has_mat = (parts & (PART_GAMMA | PART_PEN)) && blocks;
   const bool has_rhs = (parts & (PART_RHS_CONST | PART_RHS_GAMMA)) && fN;
   const int pdiag = (has_mat ? (PART_GAMMA | PART_PEN) & parts : 0) |
@@ -567,7 +602,7 @@ static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub
     const size_t lds = sizeof(double) * iface_lds_doubles<D, NEP>();
     ktimer_begin(KK_ASM_IFACE, st);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_asm_iface<D, NEP>), dim3(n_iface), dim3(256), lds, st, g,
-                       d_subs, d_ifaces, phi, mom, parts, blocks);
+                       d_subs, d_ifaces, tr, mom, parts, blocks);
     ktimer_end(-1.0, -1.0, st);
     return hipGetLastError();
   }
@@ -634,33 +669,33 @@ void assemble_free(AsmLayout& L) {
 template <int D>
 static hipError_t launch_assemble_d(const AsmLayout& L, const Geom& g, const Sub* d_subs,
                                     int n_sub, int max_ne, const Iface* d_ifaces, int n_iface,
-                                    const double* phi, const double* mom, int parts,
-                                    double* blocks, double* fN, hipStream_t st) {
+                                    const double* phi, const double* tr, const double* mom,
+                                    int parts, double* blocks, double* fN, hipStream_t st) {
   switch (assemble_cols(max_ne)) {
     case 16:
-      return launch_assemble_t<D, 16>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts,
+      return launch_assemble_t<D, 16>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, tr, mom, parts,
                                       blocks, fN, st);
     case 32:
-      return launch_assemble_t<D, 32>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts,
+      return launch_assemble_t<D, 32>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, tr, mom, parts,
                                       blocks, fN, st);
     case 48:
-      return launch_assemble_t<D, 48>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts,
+      return launch_assemble_t<D, 48>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, tr, mom, parts,
                                       blocks, fN, st);
     default:
-      return launch_assemble_t<D, 64>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, mom, parts,
+      return launch_assemble_t<D, 64>(L, g, d_subs, n_sub, d_ifaces, n_iface, phi, tr, mom, parts,
                                       blocks, fN, st);
   }
 }
 
 hipError_t launch_assemble(const AsmLayout& L, const Geom& g, const Sub* d_subs, int n_sub,
                            int max_ne, const Iface* d_ifaces, int n_iface, const double* phi,
-                           const double* mom, int parts, double* blocks, double* fN,
-                           hipStream_t st) {
+                           const double* tr, const double* mom, int parts, double* blocks,
+                           double* fN, hipStream_t st) {
   if (g.dim == 2)
-    return launch_assemble_d<2>(L, g, d_subs, n_sub, max_ne, d_ifaces, n_iface, phi, mom, parts,
-                                blocks, fN, st);
-  return launch_assemble_d<3>(L, g, d_subs, n_sub, max_ne, d_ifaces, n_iface, phi, mom, parts,
-                              blocks, fN, st);
+    return launch_assemble_d<2>(L, g, d_subs, n_sub, max_ne, d_ifaces, n_iface, phi, tr, mom,
+                                parts, blocks, fN, st);
+  return launch_assemble_d<3>(L, g, d_subs, n_sub, max_ne, d_ifaces, n_iface, phi, tr, mom,
+                              parts, blocks, fN, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -44,6 +44,7 @@ struct Sub {
 struct Iface {
   int axis, lo, hi, nf;
   long long blk_off; // offset of A[lo][hi] (N_lo x N_hi, row-major)
+  long long tr_off;  // offset of its face traces: lo side (N_lo, r, nf), then hi side (N_hi, r, nf)
 };
 
 // ---- device helpers ---------------------------------------------------------
@@ -130,8 +131,11 @@ hipError_t assemble_prepare(const Geom& g, const std::vector<Sub>& subs, int max
 void assemble_free(AsmLayout& L);
 hipError_t launch_assemble(const AsmLayout& L, const Geom& g, const Sub* d_subs, int n_sub,
                            int max_ne, const Iface* d_ifaces, int n_iface, const double* phi,
-                           const double* mom, int parts, double* blocks, double* fN,
-                           hipStream_t st);
+                           const double* tr, const double* mom, int parts, double* blocks,
+                           double* fN, hipStream_t st);
+// Face traces of the local bases per coarse interface (Iface::tr_off layout).
+hipError_t launch_face_traces(const Geom& g, const Sub* d_subs, const Iface* d_ifaces, int n_iface,
+                              const double* phi, double* tr, hipStream_t st);
 hipError_t launch_affine_sum(const double* base, const double* terms, long long n,
                              const double* theta, int nq, double* out, hipStream_t st);
 hipError_t launch_lsq(const Geom& g, const double* sat, const double* prof, int nprof,

@@ -20,6 +20,8 @@ struct Model {
   double *d_bc_val = nullptr, *d_bc_sval = nullptr;
   int8_t *d_bc_type = nullptr, *d_bc_sat = nullptr;
   double* d_phi = nullptr;      // local bases, per box (N_E, r, n_E)
+  double* d_tr = nullptr;       // face traces of the bases, per interface (Iface::tr_off)
+  long long tr_len = 0;
   double* d_mom = nullptr;      // mobility moments, n_moments(dim) x ncell
   double* d_blocks = nullptr;   // A_N in block storage
   double* d_fN = nullptr;
