@@ -343,7 +343,8 @@ int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int3
  * simulation's state buffer, so each simulation's result equals that of the
  * plain per-simulation path, bit for bit.  A model may belong to one batch or
  * server at a time and must not be stepped elsewhere meanwhile; destroy the
- * batch or server (or detach) before destroying its models.  Not thread-safe:
+ * batch or server (or detach) before destroying its models (a member of a
+ * fused batch or of a server refuses to be destroyed until then).  Not thread-safe:
  * one host thread drives a batch or server.  Kernel timing
  * (lrbms_profile_enable) must be off for its models (LRBMS_E_STATE otherwise). */
 
@@ -438,6 +439,9 @@ void lrbms_server_destroy(lrbms_server* s);
 int lrbms_model_status(lrbms_model* m);
 
 const char* lrbms_last_error(void);
+/* Frees the model.  A model that belongs to a fused batch or is attached to a
+ * server is not destroyed (lrbms_last_error says why): destroy the batch or
+ * the server, or detach it, first.                                             */
 void lrbms_model_destroy(lrbms_model* m);
 
 #ifdef __cplusplus

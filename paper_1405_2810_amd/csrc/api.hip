@@ -1284,6 +1284,10 @@ int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int3
 void lrbms_model_destroy(lrbms_model* m) {
   if (!m) return;
   Model* M = M_(m);
+  if (M->owner) {
+    set_error("model_destroy: the model belongs to a fused batch or a server; destroy that first");
+    return;
+  }
   (void)hipStreamSynchronize(M->last_stream);
   delete M;
 }

@@ -42,7 +42,9 @@ struct Model {
   SolverPlan plan;
   SolverDev sdev;
   bool assembled = false;
-  void* owner = nullptr;        // fused batch whose shared storage holds d_blocks / d_fN
+  // fused batch (whose storage holds d_blocks / d_fN) or server the model is
+  // attached to; the model cannot be destroyed while it is set
+  void* owner = nullptr;
   hipStream_t last_stream = nullptr;
   long long dev_bytes = 0;
   // kernel timing and the fixed per-launch algorithmic figures per kernel kind

@@ -131,14 +131,15 @@ struct Batch {
   ~Batch() {
     (void)hipDeviceSynchronize();
     drop_graph();
+    // members of a fused batch get their own block storage back
     for (size_t i = 0; i < models.size(); ++i) {
       Model* M = model_of(models[i]);
-      M->last_stream = nullptr;
+      if (M->owner != this) continue;
       if (i < own_blocks.size()) {
         M->d_blocks = own_blocks[i];
         M->d_fN = own_fN[i];
-        M->owner = nullptr;
       }
+      M->owner = nullptr;
     }
     for (auto& b : bufs) b.release();
     solver_free(cdev);
@@ -223,7 +224,6 @@ struct Batch {
       own_fN.push_back(M->d_fN);
       M->d_blocks = cblocks + blk_base[i];
       M->d_fN = cfN + pn_base[i];
-      M->owner = this;
       if (!bufs[i].alloc(*M, cpN + pn_base[i])) return LRBMS_E_OOM;
     }
     return LRBMS_OK;
@@ -302,7 +302,10 @@ struct Server {
       if (s.st) (void)hipStreamSynchronize(s.st);
     }
     for (auto& s : sims) {
-      if (s.m) model_of(s.m)->last_stream = nullptr;
+      if (s.m) {
+        model_of(s.m)->last_stream = nullptr;
+        model_of(s.m)->owner = nullptr;
+      }
       s.bufs.release();
     }
     for (auto& s : slots) {
@@ -388,7 +391,7 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
     for (int i = 0; i < n; ++i) {
       if (!models[i]) return (set_error("NULL model"), LRBMS_E_ARG);
       if (model_of(models[i])->owner)
-        return (set_error("a model belongs to a fused batch already"), LRBMS_E_ARG);
+        return (set_error("a model belongs to a fused batch or a server already"), LRBMS_E_ARG);
       for (int j = 0; j < i; ++j)
         if (models[j] == models[i])
           return (set_error("a model appears twice in the batch"), LRBMS_E_ARG);
@@ -397,6 +400,7 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
     }
     auto B = std::make_unique<Batch>();
     B->models.assign(models, models + n);
+    for (int i = 0; i < n; ++i) model_of(models[i])->owner = B.get();
     B->mode = mode;
     B->use_graph = (flags & LRBMS_BATCH_GRAPH) != 0;
     B->fused = (flags & LRBMS_BATCH_FUSED_SOLVE) != 0;
@@ -505,8 +509,7 @@ int lrbms_server_attach(lrbms_server* s, lrbms_model* m, double* d_sat, int32_t*
     if (!s || !m || !d_sat || !sim_id) return (set_error("NULL argument"), LRBMS_E_ARG);
     Server* S = reinterpret_cast<Server*>(s);
     const Model& M = *model_of(m);
-    for (auto& x : S->sims)
-      if (x.attached && x.m == m) return (set_error("model already attached"), LRBMS_E_ARG);
+    if (M.owner) return (set_error("model belongs to a fused batch or a server already"), LRBMS_E_ARG);
     if (!mode_ok(M, S->mode)) return (set_error("assembly mode not available"), LRBMS_E_ARG);
     if (M.timer.on) return (set_error("kernel timing is on for this model"), LRBMS_E_STATE);
     Server::Sim x;
@@ -522,6 +525,7 @@ int lrbms_server_attach(lrbms_server* s, lrbms_model* m, double* d_sat, int32_t*
     if (!hip_ok(hipDeviceSynchronize(), "synchronize")) return LRBMS_E_HIP;
     x.attached = true;
     S->sims.push_back(x);
+    model_of(m)->owner = S;
     *sim_id = (int32_t)S->sims.size() - 1;
     S->waiting.push_back(*sim_id);
     return S->progress();
@@ -595,6 +599,7 @@ int lrbms_server_detach(lrbms_server* s, int32_t sim_id) {
   x.bufs.release();
   S->waiting.erase(std::remove(S->waiting.begin(), S->waiting.end(), sim_id), S->waiting.end());
   model_of(x.m)->last_stream = nullptr;
+  model_of(x.m)->owner = nullptr;
   x = Server::Sim{};
   if (rc == LRBMS_OK) rc = S->progress();
   return rc;

@@ -151,6 +151,10 @@ def test_batch_arguments(L):
             B.step([_state(p, 1)])
         assert ei.value.code == -2
         m.profile_enable(False)
+        # a member of a batch is not destroyed before the batch
+        L.lib().lrbms_model_destroy(m._h)
+        assert b"destroy that first" in L.lib().lrbms_last_error()
+        assert L.lib().lrbms_model_status(m._h) == 0   # still alive
         B.close()
     finally:
         m.close()
@@ -241,9 +245,14 @@ def test_server_admission_by_footprint(L):
         assert torch.equal(sats[2], alone[2].sat)
         done = S.poll()
         assert sorted(d[0] for d in done) == sorted(10 * i + k for i in ids for k in range(2))
+        # a footprint above the whole budget (the model detached above)
         with pytest.raises(L.LrbmsError) as ei:
-            L.Server(hbm_budget=fp[0] - 1).attach(models[0], sats[0])
+            L.Server(hbm_budget=fp[1] - 1).attach(models[1], sats[1])
         assert ei.value.code == -7
+        # a model attached to this server belongs to it: no second owner
+        with pytest.raises(L.LrbmsError) as ei:
+            L.Batch([models[0]])
+        assert ei.value.code == -1
     finally:
         S.close()
         for m in models:
