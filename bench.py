@@ -244,6 +244,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: pick the reduced solver's shapes by timing them (untimed set-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (scale of the HBM counters)")
     args = ap.parse_args()
@@ -278,6 +280,11 @@ def main():
     st = torch.cuda.current_stream()
     s0_host = random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6)
     s0 = torch.as_tensor(s0_host, dtype=torch.float64, device=dev)
+    tune = gm.autotune(s0, reps=10) if args.autotune else None
+    if tune:
+        log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']}: "
+            f"{tune['us_per_solve']:.1f} us per solve (was {tune['us_before']:.1f}, "
+            f"{tune['n_candidates']} shapes)")
     s_a = s0.clone()
     s_b = torch.zeros_like(s_a)
     pN = torch.zeros(info["N"], dtype=torch.float64, device=dev)
@@ -456,7 +463,8 @@ def main():
                                f"{'x'.join(str(v) for v in p.n[:p.dim])} fine cells, "
                                f"{'x'.join(str(v) for v in nc)} coarse boxes, N_E<={p.ne_cap}, "
                                f"online step a1-a7 ({args.mode}), plain per-simulation path",
-                   "mode": args.mode, "N": info["N"], "fine_cells": info["ncell"]},
+                   "mode": args.mode, "N": info["N"], "fine_cells": info["ncell"],
+                   "solver_shapes": tune},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "per_call_ms": {"assemble": float(parts[:, 0].mean()), "solve": float(parts[:, 1].mean()),
                         "flux": float(parts[:, 2].mean()), "transport": float(parts[:, 3].mean())},

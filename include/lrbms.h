@@ -316,6 +316,25 @@ int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
                                    const int32_t* const* basis_sizes, const int32_t* leaf_max,
                                    int32_t n, int64_t* buf, int64_t cap, int64_t* needed);
 
+/* Autotuner of the reduced solver's shapes: the leaf size of the nested
+ * dissection (1, 2, 4, 8 or 16 boxes) and the smallest panel step that is
+ * split in two launches (256 or 1024 tiles, or never).  Assembles the
+ * reduced system of d_sat (device, [r*ncell]; DIRECT), then for every
+ * candidate builds the solver plan, times reps solves (after two untimed
+ * ones) with HIP events on the default stream, and keeps the fastest plan in
+ * the model.  The report (nullable) gives the chosen shapes, its time per
+ * solve, the time of the plan the model had before, and the number of
+ * candidates timed.  Synchronous; allocates; results of later solves differ
+ * from before only by rounding (another elimination order).
+ * LRBMS_E_STATE while the model belongs to a batch or server.                 */
+typedef struct lrbms_tune_report {
+  int32_t leaf_max, split_min;   /* split_min: 0 = never split */
+  int32_t n_candidates, pad;
+  double us_per_solve, us_before;
+} lrbms_tune_report;
+int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
+                         lrbms_tune_report* report);
+
 /* Kernel timing, for roofline measurement (off by default).
  * lrbms_profile_enable synchronizes the model's last stream, clears the
  * counters and switches timing on (enable != 0) or off.  While on, every

@@ -1281,6 +1281,89 @@ int lrbms_profile_read(lrbms_model* m, lrbms_kernel_stat* out, int32_t cap, int3
   return LRBMS_OK;
 }
 
+int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
+                         lrbms_tune_report* report) {
+  try {
+    if (!m || !d_sat || reps < 1) return (set_error("invalid argument"), LRBMS_E_ARG);
+    Model* M = M_(m);
+    if (M->owner) return (set_error("model belongs to a batch or server"), LRBMS_E_STATE);
+    if (M->timer.on) return (set_error("kernel timing is on"), LRBMS_E_STATE);
+    int rc = lrbms_online_assemble(m, d_sat, LRBMS_DIRECT, nullptr);
+    if (rc != LRBMS_OK) return rc;
+    DevArray pN;
+    if (!pN.alloc((size_t)std::max(M->N, 1))) return LRBMS_E_OOM;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!hip_ok(hipEventCreate(&e0), "event") || !hip_ok(hipEventCreate(&e1), "event"))
+      return LRBMS_E_HIP;
+    auto time_plan = [&](const SolverPlan& P, const SolverDev& D, double& us) {
+      for (int i = 0; i < 2; ++i)
+        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0), "solve"))
+          return false;
+      if (!hip_ok(hipEventRecord(e0, 0), "event")) return false;
+      for (int i = 0; i < reps; ++i)
+        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0), "solve"))
+          return false;
+      float ms = 0.0f;
+      if (!hip_ok(hipEventRecord(e1, 0), "event") || !hip_ok(hipEventSynchronize(e1), "event") ||
+          !hip_ok(hipEventElapsedTime(&ms, e0, e1), "event"))
+        return false;
+      us = 1e3 * ms / reps;
+      return true;
+    };
+    lrbms_tune_report rep{};
+    bool ok = time_plan(M->plan, M->sdev, rep.us_before);
+    double best = 1e300;
+    int best_leaf = M->leaf_max, best_split = M->split_min;
+    SolverPlan best_plan;
+    for (int leaf : {1, 2, 4, 8, 16}) {
+      for (int split : {256, 1024, 1 << 30}) {
+        if (!ok) break;
+        SolverPlan P;
+        if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf, P, split)) continue;
+        SolverDev D;
+        if (!solver_upload(P, D)) {
+          solver_free(D);
+          continue;   // this shape does not fit: skip it
+        }
+        double us = 0.0;
+        ok = time_plan(P, D, us);
+        solver_free(D);
+        ++rep.n_candidates;
+        if (ok && us < best) {
+          best = us;
+          best_leaf = leaf;
+          best_split = split;
+          best_plan = std::move(P);
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return LRBMS_E_HIP;
+    if (rep.n_candidates > 0 && best < rep.us_before) {
+      SolverDev D;
+      if (!solver_upload(best_plan, D)) {
+        solver_free(D);
+        return (set_error("solver allocation failed"), LRBMS_E_OOM);
+      }
+      M->dev_bytes += D.bytes - M->sdev.bytes;
+      solver_free(M->sdev);
+      M->sdev = D;
+      M->plan = std::move(best_plan);
+      M->leaf_max = best_leaf;
+      M->split_min = best_split;
+    }
+    rep.leaf_max = M->leaf_max;
+    rep.split_min = M->split_min >= (1 << 30) ? 0 : (M->split_min < 0 ? step_split_min() : M->split_min);
+    rep.us_per_solve = std::min(best, rep.us_before);
+    if (report) *report = rep;
+    M->last_stream = nullptr;
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
 void lrbms_model_destroy(lrbms_model* m) {
   if (!m) return;
   Model* M = M_(m);

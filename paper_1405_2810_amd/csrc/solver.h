@@ -94,9 +94,12 @@ struct SolverPlan {
 int step_split_min();
 void split_steps(SolverPlan& plan, int split_min);
 
-// Build the plan for the box grid with box sizes subs[].NE and interfaces.
+// Build the plan for the box grid with box sizes subs[].NE and interfaces;
+// panel steps of at least split_min tiles are split (split_min < 0: the
+// default of step_split_min()).
 bool build_solver_plan(int dim, const int nc[3], const std::vector<Sub>& subs,
-                       const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan);
+                       const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan,
+                       int split_min = -1);
 
 // One plan for several independent systems solved together: the fronts, node
 // references and work lists of member k are appended level by level (levels

@@ -72,7 +72,8 @@ int nd_build(const int nc[3], const Region& R, int leaf_max, std::vector<FrontH>
 }  // namespace
 
 bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs,
-                       const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan) {
+                       const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan,
+                       int split_min) {
   int nc[3] = {nc_in[0], nc_in[1], dim == 3 ? nc_in[2] : 1};
   const int nsub = nc[0] * nc[1] * nc[2];
   if ((int)subs.size() != nsub) return false;
@@ -304,7 +305,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   }
   plan.upd_items.assign(H, {});
   for (int h = 0; h < H; ++h) plan.upd_items[h].assign(plan.step_items[h].size(), {});
-  split_steps(plan, step_split_min());
+  split_steps(plan, split_min < 0 ? step_split_min() : split_min);
   // algorithmic figures per launch: Cholesky arithmetic of the work each
   // launch does, and the front entries it must read and write (8 B each)
   plan.asm_flops.assign(H, 0.0);

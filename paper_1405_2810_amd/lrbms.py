@@ -54,6 +54,11 @@ class ModelInfo_C(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class TuneReport_C(C.Structure):
+    _fields_ = [("leaf_max", C.c_int32), ("split_min", C.c_int32), ("n_candidates", C.c_int32),
+                ("pad", C.c_int32), ("us_per_solve", C.c_double), ("us_before", C.c_double)]
+
+
 class OfflineOpts_C(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_train", C.c_int32), ("ne_cap", C.c_int32),
                 ("unit_functions", C.c_int32), ("horizon", C.c_double), ("pcg_rtol", C.c_double),
@@ -112,6 +117,7 @@ def lib():
         L.lrbms_fine_destroy.restype = None
         L.lrbms_model_destroy.argtypes = [vp]
         L.lrbms_model_destroy.restype = None
+        L.lrbms_model_autotune.argtypes = [vp, vp, i32, vp]
         L.lrbms_batch_create.argtypes = [vp, i32, i32, i32, C.POINTER(vp)]
         L.lrbms_batch_step.argtypes = [vp, vp, vp, vp]
         L.lrbms_batch_buffers.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp)]
@@ -367,6 +373,13 @@ class Model:
         _check(lib().lrbms_model_export_basis(self._h, _ptr(sizes), _ptr(basis)))
         total = sum(int(k) * self.info["r"] * n for k, n in zip(sizes, ncells))
         return sizes, basis[:total].copy()
+
+    def autotune(self, sat, reps: int = 10) -> dict:
+        """Time every solver shape on the reduced system of `sat` and keep
+        the fastest (lrbms_model_autotune)."""
+        rep = TuneReport_C()
+        _check(lib().lrbms_model_autotune(self._h, _ptr(sat), int(reps), C.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in TuneReport_C._fields_ if k != "pad"}
 
     def profile_enable(self, on: bool = True):
         """Switch the per-kernel event timing of the online calls on or off

@@ -102,3 +102,4 @@ def test_batch_and_server_arguments_checked_before_device_work(L):
     assert lib.lrbms_server_info(None, None) == -1
     lib.lrbms_batch_destroy(None)
     lib.lrbms_server_destroy(None)
+    assert lib.lrbms_model_autotune(None, None, 1, None) == -1
