@@ -23,8 +23,8 @@ const char* kernel_kind_name(int kind) {
   static const char* const names[KK_COUNT] = {
       "k_moments",        "k_lsq",          "k_affine_sum",     "k_asm_box",
       "k_reduce_box",     "k_asm_iface",    "k_front_asm",      "k_front_factor0",
-      "k_front_step",     "k_front_backward", "k_front_update", "k_reconstruct",
-      "k_flux",           "k_transport",      "k_limiter"};
+      "k_front_step",     "k_front_backward", "k_front_update", "k_front_bw_gemv",
+      "k_reconstruct",    "k_flux",           "k_transport",    "k_limiter"};
   return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 

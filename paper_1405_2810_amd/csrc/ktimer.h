@@ -23,6 +23,7 @@ enum KernelKind {
   KK_FRONT_STEP,
   KK_FRONT_BACKWARD,
   KK_FRONT_UPDATE,
+  KK_FRONT_BW_GEMV,
   KK_RECONSTRUCT,
   KK_FLUX,
   KK_TRANSPORT,

@@ -45,7 +45,18 @@ struct FrontD {
   int node_off, n_nodes;   // nodes of S then U: (pos in front, p_N offset, size, pos in parent)
   int child_off, nchild;   // children (front ids) in extend-add order
   int n_s_nodes, npanels;
+  // large fronts: the backward product L_US^T x_U split over nzc workgroups
+  // of 64 U rows each, partial vectors (m each) at zoff; U row r takes x_U
+  // from p_N[urow_pn[urow_off + r]]
+  int nzc = 0, urow_off = 0;
+  long long zoff = 0;
 };
+
+// One workgroup of the split backward product: 64 U rows of one front.
+struct BwItem { int front, chunk; };
+// Smallest m u (front entries of L_US) whose backward product is split
+// (environment variable LRBMS_BW_SPLIT_MIN, default 2^18).
+long long bw_split_min();
 
 struct NodeRef { int pos, pn_off, size, ppos; };
 
@@ -81,6 +92,9 @@ struct SolverPlan {
   // one rows-only item (tj = -1) per tile row, and upd_items the trailing
   // updates, which read both L tiles from the L store instead of forming them
   std::vector<std::vector<std::vector<StepItem>>> upd_items;   // [level][panel]
+  std::vector<std::vector<BwItem>> bw_items;                    // [level]
+  std::vector<int> urow_pn;
+  long long bw_part_doubles = 0;   // partial vectors of the split products (one level at a time)
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0, lpan_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
@@ -93,6 +107,9 @@ struct SolverPlan {
 // (environment variable LRBMS_STEP_SPLIT_MIN, default 1024).
 int step_split_min();
 void split_steps(SolverPlan& plan, int split_min);
+// Work items and partial storage of the split backward products, from the
+// fronts' nzc (level by level, fronts in level order).
+void assign_backward_split(SolverPlan& plan);
 
 // Build the plan for the box grid with box sizes subs[].NE and interfaces;
 // panel steps of at least split_min tiles are split (split_min < 0: the
@@ -127,6 +144,9 @@ struct SolverDev {
   std::vector<AsmItem*> asm_items;
   std::vector<std::vector<StepItem*>> step_items;
   std::vector<std::vector<StepItem*>> upd_items;
+  std::vector<BwItem*> bw_items;
+  int* urow_pn = nullptr;
+  double* part = nullptr;
   std::vector<int*> level_fronts;
   double* F = nullptr;
   double* L = nullptr;

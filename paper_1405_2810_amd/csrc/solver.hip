@@ -176,6 +176,24 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     for (int v : f.U)
       if (!add_ref(v, true)) return false;
   }
+  // large fronts: the backward product over their U rows is split, and every
+  // U row's place in p_N recorded
+  plan.urow_pn.clear();
+  const long long bw_min = bw_split_min();
+  for (FrontD& d : plan.fronts) {
+    d.nzc = 0;
+    d.urow_off = (int)plan.urow_pn.size();
+    if (d.u == 0 || (long long)d.m * d.u < bw_min) continue;
+    d.nzc = (d.u + 63) / 64;
+    std::vector<int> urow(d.u, -1);
+    for (int n = d.n_s_nodes; n < d.n_nodes; ++n) {
+      const NodeRef& r = plan.nodes[d.node_off + n];
+      for (int i = 0; i < r.size; ++i) urow[r.pos + i - d.m] = r.pn_off + i;
+    }
+    for (int v : urow)
+      if (v < 0) return false;
+    plan.urow_pn.insert(plan.urow_pn.end(), urow.begin(), urow.end());
+  }
   plan.front_doubles = foff;
   plan.vec_doubles = voff;
   plan.inv_doubles = ioff;
@@ -306,6 +324,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.upd_items.assign(H, {});
   for (int h = 0; h < H; ++h) plan.upd_items[h].assign(plan.step_items[h].size(), {});
   split_steps(plan, split_min < 0 ? step_split_min() : split_min);
+  assign_backward_split(plan);
   // algorithmic figures per launch: Cholesky arithmetic of the work each
   // launch does, and the front entries it must read and write (8 B each)
   plan.asm_flops.assign(H, 0.0);
@@ -786,11 +805,43 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 // z_{<b} -= L_{b,<b}^T x_b.  L is read row-wise from the panel-major store,
 // lane = column within a panel, so every load is one coalesced row; the loads
 // of a panel's update are issued before x_b is formed.
+// Split backward product of a large front: for 64 U rows (one work item),
+// the partial vector part[c][j] = sum over those rows r, in order, of
+// L_US(r, j) x_U(r), for every column j of S.
+__global__ __launch_bounds__(256) void k_front_bw_gemv(const BwItem* __restrict__ items,
+                                                       const FrontD* __restrict__ fronts,
+                                                       const double* __restrict__ Lpan,
+                                                       const int* __restrict__ urow_pn,
+                                                       const double* __restrict__ pN,
+                                                       double* __restrict__ part) {
+  __shared__ double xr[kNB];
+  const BwItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const int m = f.m, r0 = kNB * it.chunk, nr = min(kNB, f.u - r0), tid = threadIdx.x;
+  if (tid < kNB) xr[tid] = tid < nr ? pN[urow_pn[f.urow_off + r0 + tid]] : 0.0;
+  __syncthreads();
+  double* out = part + f.zoff + (long long)it.chunk * m;
+  for (int j = tid; j < m; j += blockDim.x) {
+    const int b = j >> 6, k = j & 63, cs = min(kNB * (b + 1), m);
+    const double* Lr = Lpan + lpanel_base(f, b) + (long long)(m - cs + r0) * kNB + k;
+    double s = 0.0;
+    for (int g = 0; g < nr; g += 16) {
+      double a[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[t] = (g + t < nr) ? Lr[(long long)(g + t) * kNB] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) s = fma(a[t], xr[g + t], s);
+    }
+    out[j] = s;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
                                                         const double* __restrict__ Lpan,
                                                         const double* __restrict__ Inv,
+                                                        const double* __restrict__ part,
                                                         double* __restrict__ pN) {
   extern __shared__ double w[];   // m + u values
   __shared__ double red[4][4][kNB];
@@ -809,8 +860,18 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
     for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = pN[nr.pn_off + i];
   }
   __syncthreads();
-  // z_S = y_S - L_US^T x_U: four panels at a time, rows of U split over the waves
-  for (int p0 = 0; p0 < np && u > 0; p0 += 4) {
+  // z_S = y_S - L_US^T x_U; a large front's products come in partial
+  // vectors (k_front_bw_gemv), summed here in chunk order
+  if (f.nzc > 0) {
+    for (int j = tid; j < m; j += blockDim.x) {
+      double acc = 0.0;
+      for (int c = 0; c < f.nzc; ++c) acc += part[f.zoff + (long long)c * m + j];
+      w[j] -= acc;
+    }
+    __syncthreads();
+  }
+  // otherwise: four panels at a time, rows of U split over the waves
+  for (int p0 = 0; p0 < np && u > 0 && f.nzc == 0; p0 += 4) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r0 = g; r0 < u; r0 += 64) {
       double a[4][16];
@@ -935,6 +996,27 @@ void split_steps(SolverPlan& plan, int split_min) {
     }
 }
 
+void assign_backward_split(SolverPlan& plan) {
+  plan.bw_items.assign(plan.nlevels, {});
+  plan.bw_part_doubles = 0;
+  for (int h = 0; h < plan.nlevels; ++h) {
+    long long off = 0;
+    for (int fi : plan.level_fronts[h]) {
+      FrontD& d = plan.fronts[fi];
+      if (d.nzc == 0) continue;
+      d.zoff = off;
+      off += (long long)d.nzc * d.m;
+      for (int c = 0; c < d.nzc; ++c) plan.bw_items[h].push_back(BwItem{fi, c});
+    }
+    plan.bw_part_doubles = std::max(plan.bw_part_doubles, off);
+  }
+}
+
+long long bw_split_min() {
+  const char* e = std::getenv("LRBMS_BW_SPLIT_MIN");
+  return e && *e ? std::atoll(e) : (1LL << 18);
+}
+
 int step_split_min() {
   const char* e = std::getenv("LRBMS_STEP_SPLIT_MIN");
   return e && *e ? std::atoi(e) : 1024;
@@ -982,7 +1064,10 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
     const int nbase = (int)out.nodes.size();
     const int cbase = (int)out.children.size();
     const long long front0 = out.front_doubles;
+    const int ubase = (int)out.urow_pn.size();
+    for (int v : P.urow_pn) out.urow_pn.push_back(v + (int)pn_base[k]);
     for (FrontD f : P.fronts) {
+      f.urow_off += ubase;
       f.off += out.front_doubles;
       f.loff += out.lpan_doubles;
       f.voff += out.vec_doubles;
@@ -1036,6 +1121,7 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   // the members' steps side by side can be large enough to split (the
   // per-launch figures then stay those of the members' own launches)
   split_steps(out, step_split_min());
+  assign_backward_split(out);
   return true;
 }
 
@@ -1061,6 +1147,16 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
       const NodeRef& r = plan.nodes[f.node_off + n];
       if (r.pos < 0 || r.size < 0 || r.pos + r.size > ld) return false;
       if (r.pn_off < 0 || (long long)r.pn_off + r.size > nN) return false;
+    }
+    if (f.nzc != 0) {
+      if (f.nzc != (f.u + 63) / 64 || f.urow_off < 0 ||
+          (long long)f.urow_off + f.u > (long long)plan.urow_pn.size() || f.zoff < 0 ||
+          f.zoff + (long long)f.nzc * f.m > plan.bw_part_doubles)
+        return false;
+      for (int rr = 0; rr < f.u; ++rr) {
+        const int v = plan.urow_pn[f.urow_off + rr];
+        if (v < 0 || v >= nN) return false;
+      }
     }
   }
   for (int c : plan.children)
@@ -1093,6 +1189,10 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
       }
     }
     if (plan.upd_items[h].size() != plan.step_items[h].size()) return false;
+    if ((int)plan.bw_items.size() != plan.nlevels) return false;
+    for (const BwItem& it : plan.bw_items[h])
+      if (it.front < 0 || it.front >= nf || it.chunk < 0 || it.chunk >= plan.fronts[it.front].nzc)
+        return false;
     for (const auto& items : plan.upd_items[h])
       for (const StepItem& it : items)
         if (it.tj < 0) return false;
@@ -1222,6 +1322,10 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
           !upload(plan.upd_items[h][p], &dev.upd_items[h][p], b))
         return false;
   }
+  dev.bw_items.assign(H, nullptr);
+  for (int h = 0; h < H; ++h)
+    if (!upload(plan.bw_items[h], &dev.bw_items[h], b)) return false;
+  if (!upload(plan.urow_pn, &dev.urow_pn, b)) return false;
   int maxld = 1;
   for (auto& f : plan.fronts) maxld = std::max(maxld, f.m + f.u);
   if (hipFuncSetAttribute((const void*)k_front_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1233,7 +1337,8 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
     return hipMemset(*p, 0, std::max<long long>(n, 1) * sizeof(double)) == hipSuccess;
   };
   return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.lpan_doubles) &&
-         alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles);
+         alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles) &&
+         alloc(&dev.part, plan.bw_part_doubles);
 }
 
 void solver_free(SolverDev& dev) {
@@ -1249,6 +1354,9 @@ void solver_free(SolverDev& dev) {
     for (auto p : v) f(p);
   for (auto& v : dev.upd_items)
     for (auto p : v) f(p);
+  for (auto p : dev.bw_items) f(p);
+  f(dev.urow_pn);
+  f(dev.part);
   f(dev.F);
   f(dev.L);
   f(dev.V);
@@ -1293,9 +1401,16 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
     int maxld = 0;
     for (int f : plan.level_fronts[h])
       maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
+    const int nbw = (int)plan.bw_items[h].size();
+    if (nbw) {
+      ktimer_begin(KK_FRONT_BW_GEMV, st);
+      hipLaunchKernelGGL(k_front_bw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
+                         dev.fronts, dev.L, dev.urow_pn, pN, dev.part);
+      ktimer_end(0.0, 0.0, st);
+    }
     ktimer_begin(KK_FRONT_BACKWARD, st);
     hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
-                       dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, pN);
+                       dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, dev.part, pN);
     ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
   }
   return hipGetLastError();

@@ -1,8 +1,13 @@
-"""Split panel steps of the reduced solver (rows-only launch, then the
-trailing updates reading both L tiles from the L store) against the fused
-steps: the same arithmetic on the same values, so p_N must agree bit for
-bit.  Splitting is forced for every step by LRBMS_STEP_SPLIT_MIN=1 when the
-model is created (large workloads split only their largest steps)."""
+"""Split launches of the reduced solver, forced on small problems through
+the environment when the model is created (large workloads split only their
+largest fronts):
+* panel steps split into a rows-only launch and the trailing updates (which
+  read both L tiles from the L store) against the fused steps: the same
+  arithmetic on the same values, so p_N must agree bit for bit
+  (LRBMS_STEP_SPLIT_MIN=1);
+* the backward product L_US^T x_U split over workgroups of 64 U rows
+  (LRBMS_BW_SPLIT_MIN=1): other summation order, so p_N is checked against
+  the oracle's reduced solve."""
 import os
 
 import numpy as np
@@ -15,16 +20,21 @@ from .helpers import log
 pytestmark = pytest.mark.gpu
 
 
-def _model(L, p, snaps, split_min):
-    old = os.environ.get("LRBMS_STEP_SPLIT_MIN")
-    os.environ["LRBMS_STEP_SPLIT_MIN"] = str(split_min)
+def _with_env(var, value, make):
+    old = os.environ.get(var)
+    os.environ[var] = str(value)
     try:
-        return L.Model.from_snapshots(p, snaps, ne_cap=p.ne_cap, unit_functions=True)
+        return make()
     finally:
         if old is None:
-            del os.environ["LRBMS_STEP_SPLIT_MIN"]
+            del os.environ[var]
         else:
-            os.environ["LRBMS_STEP_SPLIT_MIN"] = old
+            os.environ[var] = old
+
+
+def _model(L, p, snaps, split_min):
+    return _with_env("LRBMS_STEP_SPLIT_MIN", split_min,
+                     lambda: L.Model.from_snapshots(p, snaps, ne_cap=p.ne_cap, unit_functions=True))
 
 
 @pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1", "cfg2"])
@@ -53,3 +63,26 @@ def test_split_steps_equal_fused(name):
     finally:
         fused.close()
         split.close()
+
+
+@pytest.mark.parametrize("name", ["small2d", "small3d", "cfg1"])
+def test_split_backward_product(name):
+    import torch
+    from paper_1405_2810_amd import lrbms as L
+    from oracle.online import reduced_system, solve_reduced, DIRECT
+    from .helpers import TOL_PN, rel_l2, oracle_case, gpu_model, dev, host
+    p, g, om, _ = oracle_case(name)
+    gm = _with_env("LRBMS_BW_SPLIT_MIN", 1, lambda: gpu_model(p, om))
+    try:
+        for seed in (3, 4):
+            s = random_saturation(p, np.random.default_rng(seed))
+            pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
+            gm.assemble(dev(s), L.DIRECT)
+            gm.solve(pN)
+            assert gm.status() == 0
+            A, f = reduced_system(om, s, DIRECT)
+            err = rel_l2(host(pN), solve_reduced(A, f))
+            log(f"[split] {name} backward product split, seed {seed}: p_N err {err:.2e}")
+            assert err <= TOL_PN
+    finally:
+        gm.close()
