@@ -261,7 +261,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for {args.gpus}): the online step of one "
-              "simulation runs on one device and this build has no multi-GPU path", file=sys.stderr)
+              "simulation runs on one device and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from synth import make_problem, random_saturation
