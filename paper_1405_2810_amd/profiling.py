@@ -3,6 +3,8 @@
   python -m paper_1405_2810_amd.profiling stats  <kernel_stats.csv> <title> <command> <out.txt>
   python -m paper_1405_2810_amd.profiling traffic <workload> <fetch_dir> <write_dir>
          <calib_fetch_dir> <calib_write_dir> <steps> <out.json> <out.txt> <command...>
+  python -m paper_1405_2810_amd.profiling mfma <pmc_dir> <kernel_stats.csv> <title> <out.txt>
+         <command...>
 
 `stats` turns a `--kernel-trace --stats` kernel_stats.csv into a short text
 table.  `traffic` reads four `--pmc` counter-collection CSVs (FETCH_SIZE and
@@ -10,6 +12,10 @@ WRITE_SIZE, each for the benchmark and for a plain device copy of known size),
 scales each counter by what it reads for the copy (bytes per KiB counted), and
 records per kernel the HBM bytes per launch with the sha256 of the kernel's
 source file, so that a figure taken before a change of the kernel is not used.
+`mfma` reads one `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64` run: per kernel the FP64
+matrix-core flops per launch (MOPS x 512), their rate over the kernel's mean
+launch time from a `--kernel-trace --stats` run of the same passes, and that
+rate against the FP64 matrix peak.
 """
 from __future__ import annotations
 
@@ -142,6 +148,36 @@ def main(argv):
         with open(out_json, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
         with open(out_txt, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
+    if argv[0] == "mfma":
+        pmc_dir, stats_csv, title, out = argv[1:5]
+        command = " ".join(argv[5:])
+        peak = 78.6e12        # FP64 matrix peak of the GPU, FLOP/s
+        mops = counters(pmc_dir, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+        avg_ns = {}
+        for name, calls, total, avg, pct in stats_table(stats_csv):
+            k = short_name(name)
+            if k in KERNEL_SOURCE and calls:
+                avg_ns[k] = avg
+        lines = [f"# {title}", f"# command: {command}",
+                 "# FP64 matrix flops = SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 per launch; rate over the "
+                 "mean launch time of the kernel-stats run; peak 78.6 TFLOP/s",
+                 f"{'kernel':20s} {'launches':>8s} {'MFLOP/launch':>13s} {'avg_us':>9s} "
+                 f"{'TFLOP/s':>8s} {'of peak':>8s}"]
+        for k in sorted(mops):
+            if k not in KERNEL_SOURCE:
+                continue
+            v = mops[k]
+            fl = sum(v) * 512.0 / len(v)
+            if fl == 0.0:
+                continue
+            t = avg_ns.get(k, 0.0) * 1e-9
+            rate = fl / t if t > 0 else 0.0
+            lines.append(f"{k:20s} {len(v):8d} {fl / 1e6:13.2f} {t * 1e6:9.2f} "
+                         f"{rate / 1e12:8.3f} {100 * rate / peak:7.2f}%")
+        with open(out, "w") as f:
             f.write("\n".join(lines) + "\n")
         print("\n".join(lines))
         return
