@@ -420,26 +420,28 @@ struct TileAux {
   double dinv[kNB];   // 1 / L(k, k)
 };
 
-// 1/d: the hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rcp_nr(double d) {
-  double y = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-d, y, 1.0);
-  return fma(y, e, y);
-}
-
 // Columns c0 .. c0+15 of the tile, rows c0 .. 63, by wave 0: lane = row,
-// right-looking on unnormalized columns.  At pivot k the raw column k (final
-// since pivot k-1) is broadcast through LDS while the reciprocal of the pivot
-// is formed, and the Schur update uses a(i,k) / d_k; the next column's
-// multiplier a(k+1, k) comes by readlane, so the serial chain per pivot is the
-// reciprocal and one multiply-add; 1/sqrt(d_k), for the scaling of the stored
-// factor, is computed beside it.  The LDS requests of one wave
-// complete in issue order, so the broadcast needs no wait beyond the use of
-// the loaded values.  Non-positive or non-finite pivots set the status word
-// and are replaced by 1 so that the results stay finite.  With inv, the
-// inverse of the diagonal block is also formed from the registers.
+// right-looking on unnormalized columns: pivot k subtracts a(i,k) a(j,k) / d_k
+// from every later column j.  The wave issues one FP64 instruction every few
+// cycles and a dependent one waits tens of cycles, so the loop keeps both the
+// instruction count per pivot and the chain from d_k to d_{k+1} short:
+//  * the pivot test runs on the scalar unit (integer compare of the high word:
+//    a normal positive double below 1e300); a failed pivot sets the status
+//    word and is replaced by 1 so that the results stay finite;
+//  * 1/d_k = y0 (1 + e + e^2), e = 1 - d_k y0, from the hardware estimate y0
+//    (good to ~5e-8, so e^3 is below double rounding): three operations where
+//    two Newton steps take four;
+//  * column k+1 is updated at once with its multiplier a(k+1,k) taken by
+//    readlane; for the later columns the raw column k is broadcast through LDS
+//    and their update is applied one pivot later, when the loads have landed
+//    and the instructions fill the waits of the next pivot's chain (the
+//    scheduling barrier keeps the compiler from sinking the loads to their
+//    use); the LDS requests of one wave complete in issue order, so the
+//    broadcast needs no other wait;
+//  * 1/sqrt(d_k), for the scaling of the stored factor, is formed once per
+//    lane after the loop.
+// With inv, the inverse of the diagonal block is also formed from the
+// registers.
 __device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool inv, int* status) {
   const int lane = threadIdx.x & 63;
   const int row = c0 + lane;
@@ -454,34 +456,49 @@ __device__ __noinline__ void panel16(Tile* D, Tile* X, TileAux& A, int c0, bool 
     a[t] = __longlong_as_double(__double_as_longlong(a[t]) & keep);
   }
   bool bad = false;
+  double mp = 0.0, cp[16];   // multipliers and broadcast column of the previous pivot
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    // the next pivot column needs only a(k+1, k), taken by readlane; the
-    // later columns get theirs through LDS, off the serial chain
     double dk = readlane_f64(a[k], k);
     const double ak1 = (k + 1 < 16) ? readlane_f64(a[k], k + 1) : 0.0;
-    double* cb = A.cb[k & 1];
-    if (k + 2 < 16) cb[lane] = a[k];
-    __builtin_amdgcn_wave_barrier();
-    const bool ok = (dk > 0.0) && (dk < 1.0e300);
+    double cn[16];
+    if (k + 2 < 16) {
+      double* cb = A.cb[k & 1];
+      cb[lane] = a[k];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int t = k + 2; t < 16; ++t) cn[t] = cb[t];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (k >= 1) {
+#pragma unroll
+      for (int t = k + 1; t < 16; ++t) a[t] = fma(-mp, cp[t], a[t]);
+    }
+#pragma unroll
+    for (int t = k + 2; t < 16; ++t) cp[t] = cn[t];
+    const int hi = __double2hiint(dk);
+    const bool ok = (hi >= 0x00100000) && (hi < 0x7E37E43C);
     bad = bad || !ok;
     dk = ok ? dk : 1.0;
     ds[k] = dk;
-    ys[k] = rsqrt_nr(dk);
-    const double mk = a[k] * rcp_nr(dk);
-    if (k + 1 < 16) a[k + 1] = fma(-mk, ak1, a[k + 1]);
-#pragma unroll
-    for (int t = k + 2; t < 16; ++t) a[t] = fma(-mk, cb[t], a[t]);
+    const double y0 = __builtin_amdgcn_rcp(dk);
+    const double e = fma(-dk, y0, 1.0);
+    const double g = fma(e, e, e);
+    mp = a[k] * fma(y0, g, y0);
+    if (k + 1 < 16) a[k + 1] = fma(-mp, ak1, a[k + 1]);
     __builtin_amdgcn_wave_barrier();
   }
   if (bad && lane == 0) atomicMin(status, (int)LRBMS_E_NOT_SPD);
+  double dl = 1.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) dl = (lane == k) ? ds[k] : dl;
+  const double yl = rsqrt_nr(dl);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) ys[k] = readlane_f64(yl, k);
   // scale: L(i,k) = a(i,k) / sqrt(d_k) below the diagonal, sqrt(d_k) on it
 #pragma unroll
   for (int k = 0; k < 16; ++k)
     a[k] = (lane > k) ? a[k] * ys[k] : ((lane == k) ? ds[k] * ys[k] : 0.0);
-  double yl = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) yl = (lane == k) ? ys[k] : yl;
   if (lane < 16) A.dinv[c0 + lane] = yl;
   if (act) {
 #pragma unroll
