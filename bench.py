@@ -282,7 +282,8 @@ def main():
     s0 = torch.as_tensor(s0_host, dtype=torch.float64, device=dev)
     tune = gm.autotune(s0, reps=10) if args.autotune else None
     if tune:
-        log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']}: "
+        log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']} "
+            f"backward split {tune['bw_split_min']}: "
             f"{tune['us_per_solve']:.1f} us per solve (was {tune['us_before']:.1f}, "
             f"{tune['n_candidates']} shapes)")
     s_a = s0.clone()

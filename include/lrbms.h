@@ -318,18 +318,20 @@ int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
 
 /* Autotuner of the reduced solver's shapes: the leaf size of the nested
  * dissection (1, 2, 4, 8 or 16 boxes) and the smallest panel step that is
- * split in two launches (256 or 1024 tiles, or never).  Assembles the
- * reduced system of d_sat (device, [r*ncell]; DIRECT), then for every
- * candidate builds the solver plan, times reps solves (after two untimed
- * ones) with HIP events on the default stream, and keeps the fastest plan in
- * the model.  The report (nullable) gives the chosen shapes, its time per
- * solve, the time of the plan the model had before, and the number of
+ * split in two launches (256 or 1024 tiles, or never); then, on the fastest
+ * of those, the smallest front (m u entries of L_US: 2^12, 2^14, 2^16, 2^18
+ * or never) whose backward product is split over many workgroups.
+ * Assembles the reduced system of d_sat (device, [r*ncell]; DIRECT), then for
+ * every candidate builds the solver plan, times reps solves (after two
+ * untimed ones) with HIP events on the default stream, and keeps the fastest
+ * plan in the model.  The report (nullable) gives the chosen shapes, its time
+ * per solve, the time of the plan the model had before, and the number of
  * candidates timed.  Synchronous; allocates; results of later solves differ
  * from before only by rounding (another elimination order).
  * LRBMS_E_STATE while the model belongs to a batch or server.                 */
 typedef struct lrbms_tune_report {
   int32_t leaf_max, split_min;   /* split_min: 0 = never split */
-  int32_t n_candidates, pad;
+  int32_t n_candidates, bw_split_min;   /* bw_split_min: 0 = never split */
   double us_per_solve, us_before;
 } lrbms_tune_report;
 int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,

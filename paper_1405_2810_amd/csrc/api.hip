@@ -1314,29 +1314,36 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
     bool ok = time_plan(M->plan, M->sdev, rep.us_before);
     double best = 1e300;
     int best_leaf = M->leaf_max, best_split = M->split_min;
+    long long best_bw = M->bw_min;
     SolverPlan best_plan;
-    for (int leaf : {1, 2, 4, 8, 16}) {
-      for (int split : {256, 1024, 1 << 30}) {
-        if (!ok) break;
-        SolverPlan P;
-        if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf, P, split)) continue;
-        SolverDev D;
-        if (!solver_upload(P, D)) {
-          solver_free(D);
-          continue;   // this shape does not fit: skip it
-        }
-        double us = 0.0;
-        ok = time_plan(P, D, us);
+    auto candidate = [&](int leaf, int split, long long bw) {
+      SolverPlan P;
+      if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf, P, split, bw)) return;
+      SolverDev D;
+      if (!solver_upload(P, D)) {
         solver_free(D);
-        ++rep.n_candidates;
-        if (ok && us < best) {
-          best = us;
-          best_leaf = leaf;
-          best_split = split;
-          best_plan = std::move(P);
-        }
+        return;   // this shape does not fit: skip it
       }
-    }
+      double us = 0.0;
+      ok = time_plan(P, D, us);
+      solver_free(D);
+      ++rep.n_candidates;
+      if (ok && us < best) {
+        best = us;
+        best_leaf = leaf;
+        best_split = split;
+        best_bw = bw;
+        best_plan = std::move(P);
+      }
+    };
+    // leaf size and step split first, then the backward split on that shape
+    for (int leaf : {1, 2, 4, 8, 16})
+      for (int split : {256, 1024, 1 << 30})
+        if (ok) candidate(leaf, split, M->bw_min);
+    const int leaf1 = best_leaf, split1 = best_split;
+    const long long bw0 = M->bw_min < 0 ? bw_split_min() : M->bw_min;
+    for (long long bw : {1LL << 12, 1LL << 14, 1LL << 16, 1LL << 18, 1LL << 62})
+      if (ok && bw != bw0) candidate(leaf1, split1, bw);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!ok) return LRBMS_E_HIP;
@@ -1352,9 +1359,14 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
       M->plan = std::move(best_plan);
       M->leaf_max = best_leaf;
       M->split_min = best_split;
+      M->bw_min = best_bw;
     }
     rep.leaf_max = M->leaf_max;
     rep.split_min = M->split_min >= (1 << 30) ? 0 : (M->split_min < 0 ? step_split_min() : M->split_min);
+    {
+      const long long bw = M->bw_min < 0 ? bw_split_min() : M->bw_min;
+      rep.bw_split_min = bw > INT32_MAX ? 0 : (int32_t)bw;
+    }
     rep.us_per_solve = std::min(best, rep.us_before);
     if (report) *report = rep;
     M->last_stream = nullptr;

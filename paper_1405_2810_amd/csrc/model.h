@@ -40,6 +40,7 @@ struct Model {
   // reduced solver
   int leaf_max = 2;             // leaf size of the nested dissection (chosen per model)
   int split_min = -1;           // smallest panel step that is split (-1: the default)
+  long long bw_min = -1;        // smallest m u whose backward product is split (-1: the default)
   SolverPlan plan;
   SolverDev sdev;
   bool assembled = false;

@@ -99,6 +99,7 @@ struct SolverPlan {
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
   std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]
+  std::vector<double> bwg_flops, bwg_bytes;   // split backward products [level]
   std::vector<std::vector<double>> step_flops, step_bytes;                           // [level][panel]
   std::vector<std::vector<double>> upd_flops, upd_bytes;                             // [level][panel]
 };
@@ -113,10 +114,11 @@ void assign_backward_split(SolverPlan& plan);
 
 // Build the plan for the box grid with box sizes subs[].NE and interfaces;
 // panel steps of at least split_min tiles are split (split_min < 0: the
-// default of step_split_min()).
+// default of step_split_min()), and the backward product of every front with
+// m u >= bw_min (bw_min < 0: the default of bw_split_min()).
 bool build_solver_plan(int dim, const int nc[3], const std::vector<Sub>& subs,
                        const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan,
-                       int split_min = -1);
+                       int split_min = -1, long long bw_min = -1);
 
 // One plan for several independent systems solved together: the fronts, node
 // references and work lists of member k are appended level by level (levels

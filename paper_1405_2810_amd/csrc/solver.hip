@@ -73,7 +73,7 @@ int nd_build(const int nc[3], const Region& R, int leaf_max, std::vector<FrontH>
 
 bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs,
                        const std::vector<Iface>& ifaces, int leaf_max, SolverPlan& plan,
-                       int split_min) {
+                       int split_min, long long bw_min_in) {
   int nc[3] = {nc_in[0], nc_in[1], dim == 3 ? nc_in[2] : 1};
   const int nsub = nc[0] * nc[1] * nc[2];
   if ((int)subs.size() != nsub) return false;
@@ -179,7 +179,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   // large fronts: the backward product over their U rows is split, and every
   // U row's place in p_N recorded
   plan.urow_pn.clear();
-  const long long bw_min = bw_split_min();
+  const long long bw_min = bw_min_in < 0 ? bw_split_min() : bw_min_in;
   for (FrontD& d : plan.fronts) {
     d.nzc = 0;
     d.urow_off = (int)plan.urow_pn.size();
@@ -333,6 +333,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.f0_bytes.assign(H, 0.0);
   plan.bw_flops.assign(H, 0.0);
   plan.bw_bytes.assign(H, 0.0);
+  plan.bwg_flops.assign(H, 0.0);
+  plan.bwg_bytes.assign(H, 0.0);
   plan.step_flops.assign(H, {});
   plan.step_bytes.assign(H, {});
   plan.upd_flops.assign(H, {});
@@ -370,9 +372,19 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
           plan.upd_bytes[h][b] += bu;
         }
       }
-      const double m = d.m, u = d.u;
-      plan.bw_flops[h] += 2.0 * m * u + m * m;
-      plan.bw_bytes[h] += 8.0 * (m * u + m * (m + 1) / 2 + 2.0 * m + u);
+      // backward: the product L_US^T x_U (in its own launch for a split
+      // front, which writes nzc partial vectors that the backward sums), then
+      // the triangular solve with L_SS
+      const double m = d.m, u = d.u, pz = (double)d.nzc * d.m;
+      if (d.nzc > 0) {
+        plan.bwg_flops[h] += 2.0 * m * u;
+        plan.bwg_bytes[h] += 8.0 * (m * u + u + pz);
+        plan.bw_flops[h] += pz + m * m;
+        plan.bw_bytes[h] += 8.0 * (pz + m * (m + 1) / 2 + 2.0 * m + u);
+      } else {
+        plan.bw_flops[h] += 2.0 * m * u + m * m;
+        plan.bw_bytes[h] += 8.0 * (m * u + m * (m + 1) / 2 + 2.0 * m + u);
+      }
     }
   }
   return true;
@@ -1059,6 +1071,8 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   out.f0_bytes.assign(H, 0.0);
   out.bw_flops.assign(H, 0.0);
   out.bw_bytes.assign(H, 0.0);
+  out.bwg_flops.assign(H, 0.0);
+  out.bwg_bytes.assign(H, 0.0);
   out.step_flops.assign(H, {});
   out.step_bytes.assign(H, {});
   out.upd_items.assign(H, {});
@@ -1133,6 +1147,8 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
       out.f0_bytes[h] += P.f0_bytes[h];
       out.bw_flops[h] += P.bw_flops[h];
       out.bw_bytes[h] += P.bw_bytes[h];
+      out.bwg_flops[h] += P.bwg_flops[h];
+      out.bwg_bytes[h] += P.bwg_bytes[h];
     }
   }
   // the members' steps side by side can be large enough to split (the
@@ -1423,7 +1439,7 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
       ktimer_begin(KK_FRONT_BW_GEMV, st);
       hipLaunchKernelGGL(k_front_bw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
                          dev.fronts, dev.L, dev.urow_pn, pN, dev.part);
-      ktimer_end(0.0, 0.0, st);
+      ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
     }
     ktimer_begin(KK_FRONT_BACKWARD, st);
     hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,

@@ -56,7 +56,8 @@ class ModelInfo_C(C.Structure):
 
 class TuneReport_C(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("split_min", C.c_int32), ("n_candidates", C.c_int32),
-                ("pad", C.c_int32), ("us_per_solve", C.c_double), ("us_before", C.c_double)]
+                ("bw_split_min", C.c_int32), ("us_per_solve", C.c_double),
+                ("us_before", C.c_double)]
 
 
 class OfflineOpts_C(C.Structure):
@@ -379,7 +380,7 @@ class Model:
         the fastest (lrbms_model_autotune)."""
         rep = TuneReport_C()
         _check(lib().lrbms_model_autotune(self._h, _ptr(sat), int(reps), C.byref(rep)))
-        return {k: getattr(rep, k) for k, _ in TuneReport_C._fields_ if k != "pad"}
+        return {k: getattr(rep, k) for k, _ in TuneReport_C._fields_}
 
     def profile_enable(self, on: bool = True):
         """Switch the per-kernel event timing of the online calls on or off

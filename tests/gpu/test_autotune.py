@@ -26,6 +26,7 @@ def test_autotune_keeps_parity(name):
         assert rep["n_candidates"] >= 5
         assert rep["leaf_max"] in (1, 2, 4, 8, 16)
         assert rep["split_min"] in (0, 256, 1024)
+        assert rep["bw_split_min"] in (0, 1 << 12, 1 << 14, 1 << 16, 1 << 18)
         assert 0.0 < rep["us_per_solve"] <= rep["us_before"] * (1 + 1e-12)
         for seed in (8, 9):
             s = random_saturation(p, np.random.default_rng(seed))
