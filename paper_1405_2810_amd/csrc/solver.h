@@ -55,7 +55,7 @@ struct FrontD {
 // One workgroup of the split backward product: 64 U rows of one front.
 struct BwItem { int front, chunk; };
 // Smallest m u (front entries of L_US) whose backward product is split
-// (environment variable LRBMS_BW_SPLIT_MIN, default 2^18).
+// (environment variable LRBMS_BW_SPLIT_MIN, default 2^14).
 long long bw_split_min();
 
 struct NodeRef { int pos, pn_off, size, ppos; };

@@ -1043,7 +1043,7 @@ void assign_backward_split(SolverPlan& plan) {
 
 long long bw_split_min() {
   const char* e = std::getenv("LRBMS_BW_SPLIT_MIN");
-  return e && *e ? std::atoll(e) : (1LL << 18);
+  return e && *e ? std::atoll(e) : (1LL << 14);
 }
 
 int step_split_min() {
