@@ -433,25 +433,29 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
 }
 
 int lrbms_batch_step(lrbms_batch* b, double* const* d_sat, uint8_t* const* d_flags, void* stream) {
-  if (!b || !d_sat) return (set_error("NULL argument"), LRBMS_E_ARG);
-  Batch* B = reinterpret_cast<Batch*>(b);
-  const size_t n = B->models.size();
-  for (size_t i = 0; i < n; ++i) {
-    if (!d_sat[i]) return (set_error("NULL state"), LRBMS_E_ARG);
-    if (model_of(B->models[i])->timer.on)
-      return (set_error("kernel timing is on for a model of the batch"), LRBMS_E_STATE);
-  }
-  hipStream_t st = (hipStream_t)stream;
-  int rc;
-  if (B->use_graph) {
-    if (!B->same_pointers(d_sat, d_flags) && (rc = B->capture(d_sat, d_flags)) != LRBMS_OK)
+  try {
+    if (!b || !d_sat) return (set_error("NULL argument"), LRBMS_E_ARG);
+    Batch* B = reinterpret_cast<Batch*>(b);
+    const size_t n = B->models.size();
+    for (size_t i = 0; i < n; ++i) {
+      if (!d_sat[i]) return (set_error("NULL state"), LRBMS_E_ARG);
+      if (model_of(B->models[i])->timer.on)
+        return (set_error("kernel timing is on for a model of the batch"), LRBMS_E_STATE);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if (B->use_graph) {
+      if (!B->same_pointers(d_sat, d_flags) && (rc = B->capture(d_sat, d_flags)) != LRBMS_OK)
+        return rc;
+      if (!hip_ok(hipGraphLaunch(B->exec, st), "graph launch")) return LRBMS_E_HIP;
+    } else if ((rc = B->enqueue(st, d_sat, d_flags)) != LRBMS_OK) {
       return rc;
-    if (!hip_ok(hipGraphLaunch(B->exec, st), "graph launch")) return LRBMS_E_HIP;
-  } else if ((rc = B->enqueue(st, d_sat, d_flags)) != LRBMS_OK) {
-    return rc;
+    }
+    for (lrbms_model* m : B->models) model_of(m)->last_stream = st;
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
   }
-  for (lrbms_model* m : B->models) model_of(m)->last_stream = st;
-  return LRBMS_OK;
 }
 
 int lrbms_batch_buffers(lrbms_batch* b, int32_t i, double** d_pN, double** d_flux) {
@@ -549,60 +553,74 @@ int lrbms_server_submit(lrbms_server* s, int32_t sim_id, uint64_t req_id) {
 
 int lrbms_server_poll(lrbms_server* s, uint64_t* req_ids, double* latency_ms, int32_t* status,
                       int32_t cap, int32_t* n_done) {
-  if (!s || !n_done || cap < 0 || (cap > 0 && !req_ids)) return (set_error("invalid argument"), LRBMS_E_ARG);
-  Server* S = reinterpret_cast<Server*>(s);
-  const int rc = S->progress();
-  int k = 0;
-  while (k < cap && !S->done.empty()) {
-    const auto& d = S->done.front();
-    req_ids[k] = d.id;
-    if (latency_ms) latency_ms[k] = d.ms;
-    if (status) status[k] = d.rc;
-    S->done.pop_front();
-    ++k;
+  try {
+    if (!s || !n_done || cap < 0 || (cap > 0 && !req_ids))
+      return (set_error("invalid argument"), LRBMS_E_ARG);
+    *n_done = 0;
+    Server* S = reinterpret_cast<Server*>(s);
+    const int rc = S->progress();
+    int k = 0;
+    while (k < cap && !S->done.empty()) {
+      const auto& d = S->done.front();
+      req_ids[k] = d.id;
+      if (latency_ms) latency_ms[k] = d.ms;
+      if (status) status[k] = d.rc;
+      S->done.pop_front();
+      ++k;
+    }
+    *n_done = k;
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
   }
-  *n_done = k;
-  return rc;
 }
 
 int lrbms_server_drain(lrbms_server* s) {
-  if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
-  Server* S = reinterpret_cast<Server*>(s);
-  for (;;) {
-    int rc = S->progress();
-    if (rc != LRBMS_OK) return rc;
-    if (S->idle()) {
-      if (S->pending.empty()) return LRBMS_OK;
-      // nothing in flight and nothing dispatchable: the rest waits for memory
-      return (set_error("pending requests wait for memory no detach will free"), LRBMS_E_ADMIT);
-    }
-    for (auto& x : S->slots)
-      if (x.sim >= 0) {
-        (void)hipEventSynchronize(x.done);
-        break;
+  try {
+    if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+    Server* S = reinterpret_cast<Server*>(s);
+    for (;;) {
+      int rc = S->progress();
+      if (rc != LRBMS_OK) return rc;
+      if (S->idle()) {
+        if (S->pending.empty()) return LRBMS_OK;
+        // nothing in flight and nothing dispatchable: the rest waits for memory
+        return (set_error("pending requests wait for memory no detach will free"), LRBMS_E_ADMIT);
       }
+      for (auto& x : S->slots)
+        if (x.sim >= 0) {
+          (void)hipEventSynchronize(x.done);
+          break;
+        }
+    }
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
   }
 }
 
 int lrbms_server_detach(lrbms_server* s, int32_t sim_id) {
-  if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
-  Server* S = reinterpret_cast<Server*>(s);
-  if (sim_id < 0 || sim_id >= (int)S->sims.size() || !S->sims[sim_id].attached)
-    return (set_error("unknown simulation"), LRBMS_E_ARG);
-  Server::Sim& x = S->sims[sim_id];
-  for (const auto& r : S->pending)
-    if (r.sim == sim_id) return (set_error("simulation has pending requests"), LRBMS_E_STATE);
-  for (auto& sl : S->slots)
-    if (sl.sim == sim_id) (void)hipEventSynchronize(sl.done);
-  int rc = S->progress();
-  if (x.admitted) S->resident -= x.footprint;
-  x.bufs.release();
-  S->waiting.erase(std::remove(S->waiting.begin(), S->waiting.end(), sim_id), S->waiting.end());
-  model_of(x.m)->last_stream = nullptr;
-  model_of(x.m)->owner = nullptr;
-  x = Server::Sim{};
-  if (rc == LRBMS_OK) rc = S->progress();
-  return rc;
+  try {
+    if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+    Server* S = reinterpret_cast<Server*>(s);
+    if (sim_id < 0 || sim_id >= (int)S->sims.size() || !S->sims[sim_id].attached)
+      return (set_error("unknown simulation"), LRBMS_E_ARG);
+    Server::Sim& x = S->sims[sim_id];
+    for (const auto& r : S->pending)
+      if (r.sim == sim_id) return (set_error("simulation has pending requests"), LRBMS_E_STATE);
+    for (auto& sl : S->slots)
+      if (sl.sim == sim_id) (void)hipEventSynchronize(sl.done);
+    int rc = S->progress();
+    if (x.admitted) S->resident -= x.footprint;
+    x.bufs.release();
+    S->waiting.erase(std::remove(S->waiting.begin(), S->waiting.end(), sim_id), S->waiting.end());
+    model_of(x.m)->last_stream = nullptr;
+    model_of(x.m)->owner = nullptr;
+    x = Server::Sim{};
+    if (rc == LRBMS_OK) rc = S->progress();
+    return rc;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
 }
 
 int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info) {
