@@ -299,8 +299,10 @@ int lrbms_copy_theta(lrbms_model* m, double* theta);
 
 /* Host-only inspection of the reduced solver's symbolic analysis (no device
  * work): the nested-dissection assembly tree, fronts, index maps and the
- * per-level work lists that the numeric kernels execute, flattened into
- * int64 records (layout documented in the Python binding).  With buf == NULL
+ * per-level work lists that the numeric kernels execute, including the split
+ * backward products (environment variable LRBMS_BW_SPLIT_MIN, as for a
+ * model), flattened into int64 records (layout documented in the Python
+ * binding).  With buf == NULL
  * or cap too small only *needed is set.  leaf_max: largest region (in boxes)
  * that becomes a leaf front.                                                   */
 int lrbms_solver_plan_export(const lrbms_problem* prob, const int32_t* basis_sizes,

@@ -1436,6 +1436,22 @@ static std::vector<int64_t> flatten_plan(const SolverPlan& plan) {
         }
     }
   }
+  // split backward products: partial storage, the p_N place of every split
+  // front's U rows, each front's split data, the work items of every level
+  o.push_back(plan.bw_part_doubles);
+  o.push_back((int64_t)plan.urow_pn.size());
+  for (int v : plan.urow_pn) o.push_back(v);
+  for (auto& f : plan.fronts) {
+    int64_t v[3] = {f.nzc, f.urow_off, f.zoff};
+    o.insert(o.end(), v, v + 3);
+  }
+  for (int h = 0; h < H; ++h) {
+    o.push_back((int64_t)plan.bw_items[h].size());
+    for (auto& it : plan.bw_items[h]) {
+      int64_t v[2] = {it.front, it.chunk};
+      o.insert(o.end(), v, v + 2);
+    }
+  }
   return o;
 }
 }  // namespace lrbms

@@ -540,6 +540,15 @@ def solver_plan_batch(probs, sizes, leaf_max) -> dict:
 
 
 def _parse_plan(buf) -> dict:
+    """Layout of the int64 plan record: a header (fronts, levels, nodes,
+    children, L-store / front / vector / inverse doubles, flops); 12 values
+    per front (off, voff, inv_off, m, u, node_off, n_nodes, child_off, nchild,
+    n_s_nodes, npanels, loff); 4 per node reference (pos, pn_off, size, ppos);
+    the children; per level its fronts, its extend-add items (7 values and
+    three sources of 4) and its panel steps (items of 4: front, panel, ti, tj;
+    a split step lists its rows-only items, then its update items); then the
+    split backward products: partial-vector doubles, the U-row map, 3 values
+    per front (nzc, urow_off, zoff) and per level its (front, chunk) items."""
     it = iter(buf.tolist())
     nxt = lambda k: [next(it) for _ in range(k)]
     nf, H, nn, nch, lpd, fd, vd, idd, flops = nxt(9)
@@ -559,8 +568,20 @@ def _parse_plan(buf) -> dict:
         for _ in range(next(it)):
             steps.append([dict(zip(["front", "panel", "ti", "tj"], nxt(4))) for _ in range(next(it))])
         levels.append(dict(fronts=lf, asm=asm, steps=steps))
+    # split backward products: partial storage, U-row map, per-front split
+    # data (nzc chunks of 64 U rows, their first map entry, partial offset),
+    # per-level work items (front, chunk)
+    part = next(it)
+    urow = nxt(next(it))
+    for f in fronts:
+        f["nzc"], f["urow_off"], f["zoff"] = nxt(3)
+    for lev in levels:
+        lev["bw"] = [tuple(nxt(2)) for _ in range(next(it))]
+    if next(it, None) is not None:
+        raise ValueError("plan record longer than its layout")
     return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,
-                front_doubles=fd, vec_doubles=vd, inv_doubles=idd, lpan_doubles=lpd, flops=flops)
+                front_doubles=fd, vec_doubles=vd, inv_doubles=idd, lpan_doubles=lpd, flops=flops,
+                urow_pn=urow, bw_part_doubles=part)
 
 
 BATCH_GRAPH = 1

@@ -60,7 +60,9 @@ def emulate(plan, blocks, fN):
     """The numeric phase as the device kernels execute it: fronts column-major
     with a right-hand-side row at the bottom, fused panel steps with the L rows
     in a separate panel-major store, look-ahead tile factorization, backward
-    sweep reading L row-wise."""
+    sweep reading L row-wise; a split front's product L_US^T x_U is formed
+    first in partial vectors, one per 64 U rows read through the plan's U-row
+    map, and the backward subtracts their sum in chunk order."""
     F = np.zeros(plan["front_doubles"])
     Lb = np.zeros(plan["lpan_doubles"])
     V = np.zeros(plan["vec_doubles"])
@@ -120,7 +122,21 @@ def emulate(plan, blocks, fN):
                 if it["ti"] == 0 and it["tj"] == 0 and p + 1 < f["npanels"]:
                     _factor_tile(Fp, f["m"], p + 1, Inv, f)
     pN = np.zeros_like(fN)
+    part = np.full(max(plan["bw_part_doubles"], 1), np.nan)
+    urow = np.asarray(plan["urow_pn"], dtype=np.int64)
     for lev in reversed(plan["levels"]):
+        for fi, c in lev["bw"]:
+            f = fr[fi]
+            m = f["m"]
+            r0 = NB * c
+            nr = min(NB, f["u"] - r0)
+            xr = pN[urow[f["urow_off"] + r0:f["urow_off"] + r0 + nr]]
+            assert f["zoff"] + (c + 1) * m <= plan["bw_part_doubles"]
+            out = part[f["zoff"] + c * m:f["zoff"] + (c + 1) * m]
+            for b in range(f["npanels"]):
+                rows, cs_b = lpanel(f, b)
+                nbb = min(NB, m - b * NB)
+                out[b * NB:b * NB + nbb] = rows[m - cs_b + r0:m - cs_b + r0 + nr, :nbb].T @ xr
         for fi in lev["fronts"]:
             f = fr[fi]
             ld, m = f["m"] + f["u"], f["m"]
@@ -131,7 +147,12 @@ def emulate(plan, blocks, fN):
                 w[b * NB:b * NB + nbb] = rows[ld - cs_b, :nbb]
             for n in nodes[f["node_off"] + f["n_s_nodes"]:f["node_off"] + f["n_nodes"]]:
                 w[n["pos"]:n["pos"] + n["size"]] = pN[n["pn_off"]:n["pn_off"] + n["size"]]
-            for b in range(f["npanels"]):
+            if f["nzc"] > 0:
+                acc = np.zeros(m)
+                for c in range(f["nzc"]):
+                    acc += part[f["zoff"] + c * m:f["zoff"] + (c + 1) * m]
+                w[:m] -= acc
+            for b in range(f["npanels"] if f["nzc"] == 0 else 0):
                 rows, cs_b = lpanel(f, b)
                 nbb = min(NB, m - b * NB)
                 w[b * NB:b * NB + nbb] -= rows[m - cs_b:ld - cs_b, :nbb].T @ w[m:]
@@ -202,3 +223,52 @@ def test_combined_plan_export_arguments():
     p = make_problem("tiny2d")
     with pytest.raises(LrbmsError):
         solver_plan_batch([p], [np.full(4, 3)], [0])
+
+
+@pytest.mark.parametrize("combined", [False, True])
+def test_split_backward_maps(monkeypatch, combined):
+    """Every front with U rows split (LRBMS_BW_SPLIT_MIN=1): each split
+    front has one chunk per 64 U rows and one work item per chunk, its U-row
+    map sends every U row to the p_N place its node reference gives, the
+    partial vectors of a level fit their storage, and the emulated solve with
+    the split products is exact (single plans and the combined plan of a
+    fused batch, whose maps are shifted into shared storage)."""
+    from paper_1405_2810_amd.lrbms import solver_plan, solver_plan_batch
+    monkeypatch.setenv("LRBMS_BW_SPLIT_MIN", "1")
+    specs = [("tiny2d", 6, 2), ("small3d", 8, 4), ("cfg1", 12, 1), ("small2d", 70, 2)]
+    rng = np.random.default_rng(23)
+    probs, sizes, leaves, systems = [], [], [], []
+    for name, ne, leaf in specs:
+        p = make_problem(name)
+        nsub = int(np.prod([len(c) - 1 for c in p.cuts]))
+        sz = rng.integers(max(1, ne // 2), ne + 1, nsub)
+        probs.append(p)
+        sizes.append(sz)
+        leaves.append(leaf)
+        systems.append(_random_system(p, sz, rng))
+    plans = ([solver_plan_batch(probs, sizes, leaves)] if combined else
+             [solver_plan(p, sz, lf) for p, sz, lf in zip(probs, sizes, leaves)])
+    groups = [systems] if combined else [[s] for s in systems]
+    for plan, group in zip(plans, groups):
+        n_split = 0
+        for fi, f in enumerate(plan["fronts"]):
+            assert f["nzc"] == ((f["u"] + 63) // 64 if f["u"] > 0 else 0)
+            n_split += f["nzc"] > 0
+            u_nodes = plan["nodes"][f["node_off"] + f["n_s_nodes"]:f["node_off"] + f["n_nodes"]]
+            for n in u_nodes:
+                for i in range(n["size"]):
+                    assert plan["urow_pn"][f["urow_off"] + n["pos"] + i - f["m"]] == n["pn_off"] + i
+        assert n_split > 0
+        for lev in plan["levels"]:
+            want = sorted((fi, c) for fi in lev["fronts"] for c in range(plan["fronts"][fi]["nzc"]))
+            assert sorted(lev["bw"]) == want
+        blocks = np.concatenate([b for _, b, _ in group])
+        fN = np.concatenate([f for _, _, f in group])
+        x = emulate(plan, blocks, fN)
+        off = 0
+        for (A, _, f) in group:
+            ref = np.linalg.solve(A, f)
+            got = x[off:off + len(f)]
+            assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+            off += len(f)
+        assert off == len(x)
