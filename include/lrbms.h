@@ -138,7 +138,12 @@ typedef struct lrbms_offline_report {
  *  basis:       host, concatenated per-box arrays (N_E, r, n_E) as documented
  *  n_profiles/profiles: host [n_profiles][r*ncell] total-mobility profiles for
  *               AFFINE / DIRECT_FIT (linearly independent; n_profiles may be 0)
- * The model precomputes the affine terms when profiles are given.
+ * The model precomputes the affine terms when profiles are given.  The
+ * reduced solver's plan of a new model takes the leaf size with the shortest
+ * launch sequence (2, 4 or 8 boxes), splits panel steps of at least
+ * LRBMS_STEP_SPLIT_MIN tiles (environment, default 1024) and the backward
+ * product of fronts with m u >= LRBMS_BW_SPLIT_MIN (default 2^14);
+ * lrbms_model_autotune replaces these shapes by measured ones.
  * Errors: LRBMS_E_ARG for inconsistent sizes, LRBMS_E_OOM, LRBMS_E_HIP.       */
 int lrbms_model_create(const lrbms_problem* prob, const int32_t* basis_sizes,
                        const double* basis, int32_t n_profiles, const double* profiles,
