@@ -161,3 +161,69 @@ def test_tof_uniform_flow_exact():
     assert np.allclose(cell_means(g, tau), 0.2 * g.centers[:, 0] / u, rtol=1e-10)
     slope = tau[nc:2 * nc] * math.sqrt(3) / math.sqrt(g.vol)          # half-cell increment
     assert np.allclose(slope, 0.2 * g.h[0] / (2 * u), rtol=1e-10)
+
+
+def _strip_state(g, means, drops):
+    """P1 state on a strip of cells along x: cell means and the change of s
+    across each cell in x (orthonormal basis: mean coefficient mean sqrt|e|,
+    x coefficient (change / 2) sqrt|e| / sqrt(3), vertex values mean +- change / 2)."""
+    nc = g.ncell
+    s = np.zeros(g.r * nc)
+    s[:nc] = np.asarray(means) * math.sqrt(g.vol)
+    s[nc:2 * nc] = np.asarray(drops) / 2 * math.sqrt(g.vol) / math.sqrt(3)
+    return s
+
+
+def test_limiter_gradient_scales_by_hand():
+    """Five cells in a row with no flow (no shock detector contribution), so
+    a cell is flagged exactly when a vertex value leaves [0, 1].  The gradient
+    scales follow the case table of the limiter (Sec. 3.5): with
+    g_i = grad s . (b_i - b) and d_i the difference of the cell means,
+      cell 0: mean -0.2, flat         -> flagged, nothing to scale
+      cell 1: mean 0.03, change 0.08  -> |g| < |d| on both sides: m = 1
+      cell 2: mean 0.5,  change 1.2   -> left  g = -1.2, d = -0.47: m = 0.47/1.2
+                                         right g =  1.2, d =  0.1:  m = 0.1/1.2
+      cell 3: mean 0.6,  flat         -> inside [0, 1]: not flagged
+      cell 4: mean 0.9,  change -0.4  -> left  g = 0.4, d = -0.3: g d < 0, m = 0
+    and the limited slope is min_i m_i times the slope; the means stay."""
+    p, g = _bl_problem(5)
+    means = [-0.2, 0.03, 0.5, 0.6, 0.9]
+    drops = [0.0, 0.08, 1.2, 0.0, -0.4]
+    s = _strip_state(g, means, drops)
+    out, flags = limit(g, p, s, np.zeros(g.nface))
+    nc = g.ncell
+    assert flags.tolist() == [1, 1, 1, 0, 1]
+    assert np.array_equal(out[:nc], s[:nc])
+    want = np.array([0.0, 0.08, 1.2 * (0.1 / 1.2), 0.0, 0.0])
+    got = out[nc:2 * nc] * 2 / math.sqrt(g.vol) * math.sqrt(3)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-15)
+    assert np.array_equal(out[2 * nc:], s[2 * nc:])
+
+
+def test_shock_detector_by_hand():
+    """Piecewise-constant means under a flow in +x: the upstream interface
+    of cell i > 0 is its left face, of cell 0 the inflow boundary with s_D = 1,
+    so S(e) = |jump| |f| / (0.08 d sqrt(h_e) |e|) with h_e = diam(e) (Sec. 3.5
+    shock detector; reading: absolute value of the face integral).  All
+    values lie in [0, 1], so the limiter flags exactly the cells with S > 1
+    (cell 4's small jump gives S < 1)."""
+    p, g = _bl_problem(5)
+    means = [0.9, 0.7, 0.7, 0.2, 0.21]
+    s = _strip_state(g, means, [0.0] * 5)
+    F = np.zeros(g.nface)
+    F[g.faces[0]["gid"]] = 1e-5 * g.faces[0]["area"]
+    S = shock_detector(g, p, s, F)
+    hx, hy = 1.0 / 5, 1.0 / 5
+    diam, vol, face = math.hypot(hx, hy), hx * hy, hy
+    up = [1.0] + means[:-1]
+    want = [abs(u - m) * face / (0.08 * 2 * math.sqrt(diam) * vol) for u, m in zip(up, means)]
+    assert np.allclose(S, want, rtol=1e-12, atol=1e-14)
+    assert [w > 1 for w in want] == [True, True, False, True, False]
+    _, flags = limit(g, p, s, F)
+    assert flags.tolist() == [1, 1, 0, 1, 0]
+    # the same state under the reverse flow: the upstream faces are the right ones
+    S_rev = shock_detector(g, p, s, -F)
+    down = means[1:] + [None]
+    want_rev = [abs(dn - m) * face / (0.08 * 2 * math.sqrt(diam) * vol) if dn is not None else 0.0
+                for dn, m in zip(down, means)]
+    assert np.allclose(S_rev, want_rev, rtol=1e-12, atol=1e-14)
