@@ -644,6 +644,7 @@ class Server:
     onto slot streams as slots free up.  Close it before closing its models."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT):
+        self._carry = []
         h = C.c_void_p()
         _check(lib().lrbms_server_create(int(hbm_budget), max_slots, mode, C.byref(h)))
         self._h = h
@@ -660,15 +661,23 @@ class Server:
         _check(lib().lrbms_server_submit(self._h, sim, req_id))
 
     def poll(self, cap: int = 256):
-        """Finished requests: list of (req_id, latency_ms, status)."""
+        """Finished requests, at most cap taken from the server per call: list
+        of (req_id, latency_ms, status).  When the server reports an error
+        after handing records over (its progress step failed), the records
+        are kept and returned by the next call, and the error is raised."""
         ids = np.zeros(cap, np.uint64)
         lat = np.zeros(cap, np.float64)
         st = np.zeros(cap, np.int32)
         n = C.c_int32()
-        _check(lib().lrbms_server_poll(self._h, ids.ctypes.data, lat.ctypes.data, st.ctypes.data,
-                                       cap, C.byref(n)))
+        rc = lib().lrbms_server_poll(self._h, ids.ctypes.data, lat.ctypes.data, st.ctypes.data,
+                                     cap, C.byref(n))
         k = n.value
-        return list(zip(ids[:k].tolist(), lat[:k].tolist(), st[:k].tolist()))
+        got = self._carry + list(zip(ids[:k].tolist(), lat[:k].tolist(), st[:k].tolist()))
+        self._carry = []
+        if rc < 0:
+            self._carry = got
+            _check(rc)
+        return got
 
     def drain(self):
         _check(lib().lrbms_server_drain(self._h))
