@@ -205,6 +205,8 @@ class ProblemC:
 class Model:
     """An LRBMS model resident on the device (opaque lrbms_model handle)."""
 
+    _owner = None   # the open Batch or Server holding the model, if any
+
     def __init__(self, handle, prob):
         self._h = handle
         self.prob = prob
@@ -298,7 +300,12 @@ class Model:
         return out
 
     def close(self):
+        """Destroy the model.  The library keeps a model that an open batch or
+        server holds (it cannot be destroyed before them): close that first."""
         if self._h:
+            if self._owner is not None and getattr(self._owner, "_h", None):
+                raise LrbmsError(-2, "the model belongs to an open batch or server; "
+                                     "close that first")
             lib().lrbms_model_destroy(self._h)
             self._h = None
 
@@ -607,6 +614,8 @@ class Batch:
         flags = (BATCH_GRAPH if graph else 0) | (BATCH_FUSED_SOLVE if fused else 0)
         _check(lib().lrbms_batch_create(arr, len(self.models), mode, flags, C.byref(h)))
         self._h = h
+        for m in self.models:
+            m._owner = self
 
     def status(self) -> int:
         """Synchronize; first non-zero device status of the batch, else 0."""
@@ -630,6 +639,9 @@ class Batch:
         if getattr(self, "_h", None):
             lib().lrbms_batch_destroy(self._h)
             self._h = None
+            for m in self.models:
+                if m._owner is self:
+                    m._owner = None
 
     def __del__(self):
         try:
@@ -645,6 +657,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT):
         self._carry = []
+        self._sims = {}
         h = C.c_void_p()
         _check(lib().lrbms_server_create(int(hbm_budget), max_slots, mode, C.byref(h)))
         self._h = h
@@ -652,10 +665,15 @@ class Server:
     def attach(self, model: "Model", sat) -> int:
         sid = C.c_int32()
         _check(lib().lrbms_server_attach(self._h, model._h, _ptr(sat), C.byref(sid)))
+        self._sims[sid.value] = model
+        model._owner = self
         return sid.value
 
     def detach(self, sim: int):
         _check(lib().lrbms_server_detach(self._h, sim))
+        m = self._sims.pop(sim, None)
+        if m is not None and m._owner is self:
+            m._owner = None
 
     def submit(self, sim: int, req_id: int):
         _check(lib().lrbms_server_submit(self._h, sim, req_id))
@@ -691,6 +709,10 @@ class Server:
         if getattr(self, "_h", None):
             lib().lrbms_server_destroy(self._h)
             self._h = None
+            for m in self._sims.values():
+                if m._owner is self:
+                    m._owner = None
+            self._sims.clear()
 
     def __del__(self):
         try:
