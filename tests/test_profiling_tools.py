@@ -1,6 +1,6 @@
 """The rocprofv3 summary tools behind profiles/: the HBM traffic record
-(counters scaled by what they read for a plain copy of known size) and the
-FP64 matrix-core summary, on small synthetic counter files."""
+(counters scaled by what they read for a plain copy of known size), the
+FP64 matrix-core summary and the kernel-stats table, on small synthetic files."""
 import csv
 import json
 import os
@@ -55,3 +55,27 @@ def test_mfma_summary(tmp_path):
     # 1e6 x 512 flops per launch over 51.2 us = 10 TFLOP/s, 12.7 % of 78.6
     assert line[1] == "4" and float(line[2]) == 512.0 and float(line[4]) == 10.0
     assert line[5] == "12.72%"
+
+
+def test_kernel_stats_table(tmp_path):
+    """The kernel-stats summary: the title and command lines, then one row
+    per kernel with short names, sorted by total time, in ms and us."""
+    stats = tmp_path / "s"
+    os.makedirs(stats)
+    with open(stats / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs",
+                                          "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": "void lrbms::k_flux<2>(lrbms::Geom)", "Calls": 10,
+                    "TotalDurationNs": 50000, "AverageNs": 5000, "Percentage": 20})
+        w.writerow({"Name": "void lrbms::k_front_step(lrbms::StepItem const*)", "Calls": 8,
+                    "TotalDurationNs": 200000, "AverageNs": 25000, "Percentage": 80})
+    out = tmp_path / "stats.txt"
+    profiling.main(["stats", str(stats / "run_kernel_stats.csv"), "title line", "the command",
+                    str(out)])
+    lines = open(out).read().splitlines()
+    assert lines[0] == "# title line" and lines[1] == "# command: the command"
+    rows = [l.split() for l in lines[3:]]
+    assert [r[0] for r in rows] == ["k_front_step", "k_flux"]
+    assert rows[0][1:] == ["8", "0.200", "25.00", "80.00"]
+    assert rows[1][1:] == ["10", "0.050", "5.00", "20.00"]
