@@ -227,3 +227,58 @@ def test_shock_detector_by_hand():
     want_rev = [abs(dn - m) * face / (0.08 * 2 * math.sqrt(diam) * vol) if dn is not None else 0.0
                 for dn, m in zip(down, means)]
     assert np.allclose(S_rev, want_rev, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("name,n,L,axis", [("tiny2d", (4, 6, 1), (1.0, 1.2, 1.0), 1),
+                                           ("small3d", (3, 4, 5), (1.0, 1.0, 2.0), 2)])
+def test_tof_uniform_flow_along_y_and_z_exact(name, n, L, axis):
+    """Uniform flow v along y (2D) or z (3D), entering through the whole
+    lower boundary: tau = phi x_axis / v lies in V_h, so the upwind DG time of
+    flight reproduces it exactly, with no slope in the other directions (the
+    x-only pin cannot see a mistake in the indexing of the other axes)."""
+    p = make_problem(name, n=n, L=L, nc=(1, 1, 1))
+    p.poro[:] = 0.2
+    g = Grid(p)
+    v = 2e-6
+    F = np.zeros(g.nface)
+    F[g.faces[axis]["gid"]] = v * g.faces[axis]["area"]
+    tau = time_of_flight(g, p, F)
+    nc = g.ncell
+    assert np.allclose(cell_means(g, tau), 0.2 * g.centers[:, axis] / v, rtol=1e-12)
+    slope = tau[(axis + 1) * nc:(axis + 2) * nc] * math.sqrt(3) / math.sqrt(g.vol)
+    assert np.allclose(slope, 0.2 * g.h[axis] / (2 * v), rtol=1e-12)
+    for a in range(g.dim):
+        if a != axis:
+            assert np.abs(tau[(a + 1) * nc:(a + 2) * nc]).max() <= 1e-12 * np.abs(tau).max()
+
+
+def _tof_error_growing_flow(ny):
+    """Flow along y with v(y) = v0 (1 + y) on the unit height (face fluxes
+    v(y_f) |f|; the RT0 field is then exactly v).  The weak form of the time
+    of flight is the conservative d(v tau)/dy = phi, so tau = phi y / (v0 (1 + y));
+    returns the relative L2 error of the P1 solution at the cell quadrature
+    points."""
+    p = make_problem("tiny2d", n=(3, ny, 1), L=(0.6, 1.0, 1.0), nc=(1, 1, 1))
+    p.poro[:] = 0.2
+    g = Grid(p)
+    v0 = 2e-6
+    f = g.faces[1]
+    yf = np.where(f["hi"] >= 0, g.centers[np.maximum(f["hi"], 0), 1] - g.h[1] / 2,
+                  g.centers[np.maximum(f["lo"], 0), 1] + g.h[1] / 2)
+    F = np.zeros(g.nface)
+    F[f["gid"]] = v0 * (1 + yf) * f["area"]
+    tau = time_of_flight(g, p, F)
+    pts, w = g.cell_qpts()
+    vals = g.eval_field(tau, np.arange(g.ncell), pts)
+    y = g.centers[:, 1][:, None] + pts[None, :, 1] * g.h[1] / 2
+    exact = 0.2 * y / (v0 * (1 + y))
+    return math.sqrt(((vals - exact) ** 2 @ w).sum() / (g.ncell * w.sum())) / (0.2 / v0)
+
+
+def test_tof_growing_flow_second_order():
+    """Non-uniform velocity (a source term in the flow): the P1 upwind DG
+    time of flight converges at second order to the closed form."""
+    e = [_tof_error_growing_flow(n) for n in (8, 16, 32)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(orders) >= 1.8, (e, orders)
+    assert e[-1] < 1e-4
