@@ -282,3 +282,36 @@ def test_tof_growing_flow_second_order():
     orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
     assert min(orders) >= 1.8, (e, orders)
     assert e[-1] < 1e-4
+
+
+def test_saturation_penalty_by_hand():
+    """No flow and no source: a piecewise-constant state changes only through
+    the jump penalty of Def. saturationDG, - sum_f sigma_f / h_f int_f [s]* [v],
+    on interior faces and on the saturation Dirichlet face (s_D = 1 on the
+    left).  With sigma_f = scale (c_f / max eta) 2 k1 k2 / (k1 + k2) inside and
+    scale (c_f / max eta) k on the boundary face (eq. penaltyParam; reading:
+    h_f = face diameter), each cell mean moves by
+    dt / (phi |e|) * sum over its faces of -sigma_f / h_f |f| (s_e - s_other)."""
+    p, g = _bl_problem(3)
+    p.q2[:] = 0.0
+    p.poro[:] = 0.2
+    p.perm[:] = [1e-13, 3e-13, 2e-13]
+    p.sat_penalty_scale = 1.5
+    means = [0.3, 0.8, 0.5]
+    s = _strip_state(g, means, [0.0] * 3)
+    c = 1.5 * p.penalty_c / max(p.visc_w, p.visc_o)
+    k = [1e-13, 3e-13, 2e-13]
+    h = 1.0 / 3                               # cell size, face length and face diameter
+    area, vol = h, h * h
+    sig01 = c * 2 * k[0] * k[1] / (k[0] + k[1])
+    sig12 = c * 2 * k[1] * k[2] / (k[1] + k[2])
+    sigb = c * k[0]
+    dt = 0.05 * 0.2 * vol * h / (sig12 * area)     # moves of a few per cent
+    flux = [-(sigb * (means[0] - 1.0) + sig01 * (means[0] - means[1])),
+            -(sig01 * (means[1] - means[0]) + sig12 * (means[1] - means[2])),
+            -(sig12 * (means[2] - means[1]))]
+    want = [m + dt / (0.2 * vol) * f * area / h for m, f in zip(means, flux)]
+    out = euler_step(g, p, s, np.zeros(g.nface), dt=dt)
+    got = out[:g.ncell] / math.sqrt(vol)
+    assert np.allclose(got - means, np.array(want) - means, rtol=1e-10, atol=0)
+    assert abs(got[0] - means[0]) > 1e-3         # the moves are not negligible
