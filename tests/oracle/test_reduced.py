@@ -191,3 +191,46 @@ def test_pca_energy_criterion():
     Q = np.stack([m.ravel() for m in modes], 1)
     resid = X - Q @ (Q.T @ X)
     assert (resid ** 2).sum() <= 1e-8 * (X ** 2).sum()
+
+
+def test_direct_fit_equals_affine_with_dirichlet_pressure(affine_model):
+    """The same identity for the right-hand side when the Dirichlet pressure
+    is not zero, so that the lambda-dependent terms d_q of f_N do not vanish
+    (with p_D = 0 they are zero and their sign or scale is not seen)."""
+    p, g, off, m = affine_model
+    p2 = p.copy()
+    p2.bc_val[p2.bc_type == 2] = 2.0e5
+    m2 = Model(p2, off["basis"].phis, m.profiles)
+    assert max(np.abs(d).max() for d in m2.terms["d"]) > 0.0
+    s = random_saturation(p2, np.random.default_rng(6))
+    A1, f1 = reduced_system(m2, s, AFFINE)
+    A2, f2 = reduced_system(m2, s, DIRECT_FIT)
+    assert abs(A1 - A2).max() <= 1e-12 * abs(A2).max()
+    assert np.abs(f1 - f2).max() <= 1e-12 * np.abs(f2).max()
+
+
+def test_projected_mobility_closed_form():
+    """L2 projection of lambda(s) onto P1 for s = a + b xi on each cell of a
+    strip (xi in [-1, 1] along x) with quadratic Corey laws: lambda = alpha +
+    beta xi + gamma xi^2 with alpha = a^2/eta_w + (1-a)^2/eta_o,
+    beta = 2ab/eta_w - 2b(1-a)/eta_o, gamma = b^2 (1/eta_w + 1/eta_o); the mean
+    coefficient is sqrt|e| (alpha + gamma/3), the x coefficient
+    sqrt|e| beta / sqrt(3), the y coefficient 0 (eq. leastSquaresFit's
+    right-hand side; the 2-point Gauss rule is exact for these cubics)."""
+    p = make_problem("tiny2d", n=(4, 1, 1), L=(1.0, 0.25, 1.0), nc=(1, 1, 1))
+    p.relperm, p.corey_w, p.corey_o = 1, 2.0, 2.0
+    g = Grid(p)
+    a = np.array([0.2, 0.45, 0.7, 0.5])
+    b = np.array([0.1, -0.15, 0.2, 0.0])
+    nc, sv = g.ncell, math.sqrt(g.vol)
+    s = np.zeros(g.r * nc)
+    s[:nc] = a * sv
+    s[nc:2 * nc] = b * sv / math.sqrt(3)          # s = a + b xi
+    ew, eo = p.visc_w, p.visc_o
+    alpha = a ** 2 / ew + (1 - a) ** 2 / eo
+    beta = 2 * a * b / ew - 2 * b * (1 - a) / eo
+    gamma = b ** 2 * (1 / ew + 1 / eo)
+    got = projected_mobility(g, p, s)
+    assert np.allclose(got[:nc], sv * (alpha + gamma / 3), rtol=1e-13)
+    assert np.allclose(got[nc:2 * nc], sv * beta / math.sqrt(3), rtol=1e-12, atol=1e-18)
+    assert np.abs(got[2 * nc:]).max() <= 1e-12 * np.abs(got).max()
