@@ -234,3 +234,40 @@ def test_projected_mobility_closed_form():
     assert np.allclose(got[:nc], sv * (alpha + gamma / 3), rtol=1e-13)
     assert np.allclose(got[nc:2 * nc], sv * beta / math.sqrt(3), rtol=1e-12, atol=1e-18)
     assert np.abs(got[2 * nc:]).max() <= 1e-12 * np.abs(got).max()
+
+
+def test_gram_schmidt_keeps_orthonormality_on_nearly_dependent_vectors():
+    """The local bases must be orthonormal in L2(E): extending a basis one
+    vector at a time with nearly dependent snapshots (monomials on close
+    nodes, condition number ~1e11) keeps |Q^T Q - I| at rounding level (one
+    classical Gram-Schmidt pass would not)."""
+    from oracle.offline import gs_extend
+    x = np.linspace(1.0, 1.1, 40)
+    basis = []
+    kept = 0
+    for j in range(8):
+        kept += gs_extend(basis, x ** j)
+    Q = np.stack(basis, axis=1)
+    assert kept == len(basis) >= 6
+    assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() <= 1e-13
+
+
+def test_mobility_profile_thresholds_by_hand():
+    """Alg. 2 step 1c: Lambda^1 = lambda(0), Lambda^M = lambda(1) and, for
+    1 < q < M, lambda(0) where the cell-mean time of flight exceeds
+    (q-1) T/(M-2), else lambda(1).  M = 5, T = 3: thresholds 1, 2, 3 for
+    q = 2, 3, 4, against cell means 0.5, 1.5, 2.5, 3.5."""
+    from oracle.fem import mobilities
+    p = make_problem("tiny2d", n=(4, 1, 1), L=(1.0, 0.25, 1.0), nc=(1, 1, 1))
+    g = Grid(p)
+    tau = np.zeros(g.r * g.ncell)
+    tau[:g.ncell] = np.array([0.5, 1.5, 2.5, 3.5]) * math.sqrt(g.vol)
+    prof = mobility_profiles(g, p, tau, 5, 3.0)
+    l0 = mobilities(np.array([0.0]), p)[2][0]
+    l1 = mobilities(np.array([1.0]), p)[2][0]
+    want = [[l0] * 4, [l1, l0, l0, l0], [l1, l1, l0, l0], [l1, l1, l1, l0], [l1] * 4]
+    got = [q[:g.ncell] / math.sqrt(g.vol) for q in prof]
+    assert len(got) == 5
+    for w, q in zip(want, got):
+        assert np.allclose(q, w, rtol=1e-14)
+    assert all(np.abs(q[g.ncell:]).max() == 0.0 for q in prof)
