@@ -271,3 +271,34 @@ def test_mobility_profile_thresholds_by_hand():
     for w, q in zip(want, got):
         assert np.allclose(q, w, rtol=1e-14)
     assert all(np.abs(q[g.ncell:]).max() == 0.0 for q in prof)
+
+
+def test_greedy_energy_norm_of_a_constant_by_hand():
+    """The greedy's error measure is the energy norm of b_h(., .; lambda-bar):
+    for a constant error e = c the gradient and every interior jump vanish,
+    so only the Dirichlet faces' penalty is left,
+    |e|^2 = c^2 sum over Dirichlet faces of sigma_f |f| / h_f with
+    sigma_f = (c_f / max eta) kappa of the boundary cell (eq. penaltyParam,
+    reading: h_f = face diameter)."""
+    from oracle.offline import energy_error
+    from oracle.pressure import assemble
+    p = make_problem("small2d")
+    g = Grid(p)
+    rng = np.random.default_rng(3)
+    prof = [np.concatenate([rng.uniform(0.5, 2.0, g.ncell) * math.sqrt(g.vol),
+                            np.zeros((g.r - 1) * g.ncell)]) for _ in range(2)]
+    A_bar = assemble(g, p, Mobility(g, p, field=training_mobility(prof, np.array([0.5, 0.5]))))
+    c = 3.0
+    e = np.zeros(g.r * g.ncell)
+    e[:g.ncell] = c * math.sqrt(g.vol)
+    want = 0.0
+    cf = p.penalty_c / max(p.visc_w, p.visc_o)
+    for a in range(g.dim):
+        f = g.faces[a]
+        dirichlet = p.bc_type[f["gid"]] == 2
+        cell = np.where(f["lo"] >= 0, f["lo"], f["hi"])[dirichlet]
+        hf = f["hf"] if np.isscalar(f["hf"]) else f["hf"][dirichlet]
+        want += np.sum(cf * np.asarray(p.perm)[cell] * f["area"] / hf)
+    assert want > 0.0
+    got = energy_error(g, p, A_bar, e, np.zeros_like(e))
+    assert abs(got - c * math.sqrt(want)) <= 1e-12 * c * math.sqrt(want)
