@@ -315,3 +315,46 @@ def test_saturation_penalty_by_hand():
     got = out[:g.ncell] / math.sqrt(vol)
     assert np.allclose(got - means, np.array(want) - means, rtol=1e-10, atol=0)
     assert abs(got[0] - means[0]) > 1e-3         # the moves are not negligible
+
+
+def _dg1d_tof(v_faces, h, phi):
+    """Textbook 1D P1 upwind DG for d(v tau)/dy = phi, v > 0 linear in each
+    cell (face values v_faces), tau = 0 at the inflow: per cell tau = t0 + t1 xi
+    (xi in [-1, 1]); testing with 1 and xi gives
+      v_R (t0 + t1) - v_L T = phi h
+      -(2 a t0 + 2/3 b t1) + v_R (t0 + t1) + v_L T = 0,
+    a = (v_L + v_R)/2, b = (v_R - v_L)/2, T the upwind trace from below."""
+    T, out = 0.0, []
+    for vL, vR in zip(v_faces[:-1], v_faces[1:]):
+        a, b = 0.5 * (vL + vR), 0.5 * (vR - vL)
+        M = np.array([[vR, vR], [vR - 2 * a, vR - 2.0 / 3.0 * b]])
+        t0, t1 = np.linalg.solve(M, [phi * h + vL * T, -vL * T])
+        out.append((t0, t1))
+        T = t0 + t1
+    return np.array(out)
+
+
+def test_tof_growing_flow_equals_1d_dg():
+    """The same growing flow as above on a strip that is uniform in x: the
+    oracle's DG time of flight equals, cell by cell, an independent 1D P1
+    upwind DG solution (a change of the discrete scheme, even one of higher
+    order such as the velocity interpolated along the wrong axis, shows here)."""
+    ny, nx = 7, 3
+    p = make_problem("tiny2d", n=(nx, ny, 1), L=(0.6, 1.0, 1.0), nc=(1, 1, 1))
+    p.poro[:] = 0.2
+    g = Grid(p)
+    v0, h = 2e-6, 1.0 / ny
+    f = g.faces[1]
+    yf = np.where(f["hi"] >= 0, g.centers[np.maximum(f["hi"], 0), 1] - h / 2,
+                  g.centers[np.maximum(f["lo"], 0), 1] + h / 2)
+    F = np.zeros(g.nface)
+    F[f["gid"]] = v0 * (1 + yf) * f["area"]
+    tau = time_of_flight(g, p, F)
+    ref = _dg1d_tof(v0 * (1 + np.arange(ny + 1) * h), h, 0.2)
+    nc = g.ncell
+    row = np.rint(g.centers[:, 1] / h - 0.5).astype(int)
+    means = cell_means(g, tau)
+    half = tau[2 * nc:3 * nc] * math.sqrt(3) / math.sqrt(g.vol)   # half-cell change in y
+    assert np.allclose(means, ref[row, 0], rtol=1e-12)
+    assert np.allclose(half, ref[row, 1], rtol=1e-10)
+    assert np.abs(tau[nc:2 * nc]).max() <= 1e-12 * np.abs(tau).max()
