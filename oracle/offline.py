@@ -280,18 +280,38 @@ def greedy(grid, prob, profiles, params, n_max, tol, mu_bar=None):
     return [np.stack(b) if b else np.zeros((0, grid.r, len(c))) for b, c in zip(local, cells)], chosen, hist
 
 
+def galerkin(B, A):
+    """Phi^T A Phi: the reduced matrix of a fine operator A for the basis
+    matrix B (columns = basis functions), accumulated in extended precision
+    (x87 long double) and rounded once.  The reduced matrices of strongly
+    heterogeneous problems are ill conditioned (2-norm condition ~1e9 at
+    256 x 256, sigma_logk = 2) and their entries are sums with heavy
+    cancellation (the penalty term pairs values on both sides of every fine
+    face), so the rounding of a plain double evaluation moves the reduced
+    solution by ~1e-10 on its own; rounded once, the entries carry only the
+    rounding of the fine operator."""
+    Bl = B.astype(np.longdouble)
+    return (Bl.T @ (A.astype(np.longdouble) @ Bl)).tocsr().astype(np.float64)
+
+
+def project(B, l):
+    """Phi^T l, accumulated in extended precision and rounded once."""
+    return np.asarray(B.T.astype(np.longdouble) @ np.asarray(l, dtype=np.longdouble),
+                      dtype=np.float64)
+
+
 def affine_terms(grid, prob, basis: Basis, profiles):
     """Sec. 4.4: c = Phi^T P Phi (penalty), b_q = Phi^T K(Lambda^q) Phi (volume
     and consistency terms), e = Phi^T l (gamma-free part), d_q = Phi^T l
     (gamma part with gamma = Lambda^q).  Sparse N x N matrices."""
     B = basis.matrix()
     P = assemble(grid, prob, None, vol=False, cons=False, pen=True)
-    c = (B.T @ (P @ B)).tocsr()
-    e = B.T @ rhs(grid, prob, None, part="const")
+    c = galerkin(B, P)
+    e = project(B, rhs(grid, prob, None, part="const"))
     bq, dq = [], []
     for prof in profiles:
         gam = Mobility(grid, prob, field=prof)
         K = assemble(grid, prob, gam, vol=True, cons=True, pen=False)
-        bq.append((B.T @ (K @ B)).tocsr())
-        dq.append(B.T @ rhs(grid, prob, gam, part="gamma"))
+        bq.append(galerkin(B, K))
+        dq.append(project(B, rhs(grid, prob, gam, part="gamma")))
     return dict(c=c, e=e, b=bq, d=dq)
