@@ -24,8 +24,12 @@
  *    (coefficient-major); boxes are concatenated in box order.
  *  - p_N: box blocks in box order, each of length N_E.
  *  - Return codes: 0 success, negative errors (LRBMS_E_*), positive warnings.
- *    Errors found on the device set the model's status word; the next call
- *    or lrbms_model_status returns them.  No C++ exception crosses the ABI.
+ *    Errors found on the device (a non-positive pivot, a non-finite residual,
+ *    flux or saturation) and the CFL warning of a transport step set the
+ *    model's status words; lrbms_model_status returns them, and so does
+ *    every online call while checks are on (lrbms_model_set_checks).  The
+ *    online calls are asynchronous otherwise.  No C++ exception crosses the
+ *    ABI.
  *    lrbms_last_error() gives a thread-local message for the last error.
  *  - Every call taking a `stream` (a hipStream_t, 0 = null stream) enqueues
  *    work asynchronously on it and does not synchronize unless stated.
@@ -272,9 +276,19 @@ int lrbms_model_export_profiles(const lrbms_model* m, double* profiles);
 int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, void* stream);
 
 /* a) Factor A_N (multifrontal block Cholesky, nested-dissection order over the
- *    coarse boxes) and solve; d_pN (device, [N]) receives p_N.
- *    LRBMS_E_STATE if no assembly preceded.                                    */
+ *    coarse boxes) and solve A_N p_N = f_N (eq. reducedSystem); d_pN (device,
+ *    [N]) receives p_N.  Then the model's refinement steps (default 1): the
+ *    residual f_N - A_N p_N in double-double arithmetic, a forward and a
+ *    backward substitution of it with the stored factor, p_N += correction.
+ *    LRBMS_E_STATE if no assembly preceded (synchronous).  Device-detected:
+ *    a non-positive pivot sets LRBMS_E_NOT_SPD, a non-finite residual
+ *    LRBMS_E_NONFINITE in the status word (lrbms_model_status).              */
 int lrbms_online_solve(lrbms_model* m, double* d_pN, void* stream);
+
+/* Iterative refinement steps of every later reduced solve of the model
+ * (0..4; 1 at creation).  LRBMS_E_ARG outside 0..4; LRBMS_E_STATE while a
+ * batch or server holds the model (the members of a batch must agree).    */
+int lrbms_model_set_refinement(lrbms_model* m, int32_t steps);
 
 /* b)+c) p_h = Phi p_N and the face fluxes of Def. velocityDG with lambda(d_sat):
  *    d_flux (device, [nface]) along +axis; on Neumann faces the flux is v_N |f|.
@@ -463,8 +477,20 @@ int lrbms_server_detach(lrbms_server* s, int32_t sim_id);
 int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info);
 void lrbms_server_destroy(lrbms_server* s);
 
-/* Synchronize and return the device status word (0 or a negative LRBMS_E_*). */
+/* Synchronize with the model's last stream and return its device status:
+ * the first error (LRBMS_E_NOT_SPD: non-positive pivot; LRBMS_E_NONFINITE:
+ * NaN/Inf in the reduced residual, a face flux or the new saturation), else
+ * LRBMS_W_CFL if a transport step's CFL number, dt max|f_w'| times a cell's
+ * outflow over phi |e| (Def. saturationDG, explicit Euler), exceeded 1/2,
+ * else 0.  The words keep their value (reading does not clear them).       */
 int lrbms_model_status(lrbms_model* m);
+
+/* on != 0: every online call (assemble, solve, reconstruct_flux,
+ * transport_step) synchronizes its stream and returns lrbms_model_status
+ * (for callers that want errors and the CFL warning at the call that
+ * caused them); 0 (the default): the calls stay asynchronous.  LRBMS_E_ARG
+ * for a NULL model.                                                         */
+int lrbms_model_set_checks(lrbms_model* m, int32_t on);
 
 const char* lrbms_last_error(void);
 /* Frees the model.  A model that belongs to a fused batch or is attached to a

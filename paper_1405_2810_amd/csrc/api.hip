@@ -24,7 +24,8 @@ const char* kernel_kind_name(int kind) {
       "k_moments",        "k_lsq",          "k_affine_sum",     "k_asm_box",
       "k_reduce_box",     "k_asm_iface",    "k_front_asm",      "k_front_factor0",
       "k_front_step",     "k_front_backward", "k_front_update", "k_front_bw_gemv",
-      "k_reconstruct",    "k_flux",           "k_transport",    "k_limiter"};
+      "k_reconstruct",    "k_flux",           "k_transport",    "k_limiter",
+      "k_residual",       "k_front_forward",  "k_front_fw_gemv"};
   return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 
@@ -243,6 +244,8 @@ static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) 
   g.nface = off;
   g.visc_w = p->visc_w;
   g.visc_o = p->visc_o;
+  g.ivw = 1.0 / p->visc_w;
+  g.ivo = 1.0 / p->visc_o;
   g.relperm = p->relperm;
   g.cw = p->corey_w;
   g.co = p->corey_o;
@@ -251,6 +254,30 @@ static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) 
   g.sat_pen = p->sat_penalty_scale;
   g.limiter = p->limiter;
   g.dt = p->dt;
+  {
+    // largest slope of the fractional flow, sampled on [0, 1] (central
+    // differences of the mobilities of the problem's law)
+    auto fw = [&](double s) {
+      s = std::min(1.0, std::max(0.0, s));
+      double krw, kro;
+      if (p->relperm == 0) {
+        krw = s;
+        kro = 1.0 - s;
+      } else {
+        krw = std::pow(s, p->corey_w);
+        kro = std::pow(1.0 - s, p->corey_o);
+      }
+      const double lw = krw / p->visc_w, lo = kro / p->visc_o;
+      return lw / (lw + lo);
+    };
+    const int n = 4096;
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double a = (double)i / n, b = (double)(i + 1) / n;
+      mx = std::max(mx, std::fabs(fw(b) - fw(a)) * n);
+    }
+    g.cfl_coef = g.dt * mx;
+  }
   // boxes
   M.subs.clear();
   long long phi_off = 0, blk = 0;
@@ -331,7 +358,8 @@ static int upload_problem(Model& M, const lrbms_problem* p) {
   if (!dev_zero(&M.d_mom, (size_t)n_moments(g.dim) * nc, b)) return LRBMS_E_OOM;
   if (!dev_zero(&M.d_scratch_sat, (size_t)g.r * nc, b)) return LRBMS_E_OOM;
   if (!dev_zero(&M.d_scratch_ph, (size_t)g.r * nc, b)) return LRBMS_E_OOM;
-  if (!dev_zero(&M.d_status, 1, b)) return LRBMS_E_OOM;
+  if (!dev_zero(&M.d_status, 2, b)) return LRBMS_E_OOM;
+  g.status = M.d_status;
   return LRBMS_OK;
 }
 
@@ -424,7 +452,9 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
   double best = 1e300;
   for (int leaf : {2, 4, 8}) {
     SolverPlan P;
-    if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, leaf, P)) continue;
+    if (!build_solver_plan(g.dim, M.nc, M.subs, M.ifaces, leaf, P) ||
+        !plan_in_bounds(P, M.nblk, M.N))
+      continue;
     double cost = 0.0;
     for (int h = 0; h < P.nlevels; ++h) cost += 64.0 + 28.5 * (double)P.step_items[h].size();
     if (cost < best) {
@@ -580,6 +610,31 @@ struct DevArray {
     if (p) (void)hipFree(p);
   }
 };
+
+// The model's device status words (the caller has synchronized): the first
+// error, else the warning, else 0; with a message for either.
+static int read_status(Model& M) {
+  int s[2] = {0, 0};
+  if (!hip_ok(hipMemcpy(s, M.d_status, sizeof(s), hipMemcpyDeviceToHost), "status"))
+    return LRBMS_E_HIP;
+  if (s[0] == LRBMS_E_NOT_SPD)
+    set_error("device reported a non-positive pivot in the reduced Cholesky");
+  else if (s[0] == LRBMS_E_NONFINITE)
+    set_error("device reported a non-finite value (reduced residual, flux or saturation)");
+  else if (s[0])
+    set_error("device reported an error");
+  else if (s[1] == LRBMS_W_CFL)
+    set_error("warning: a transport step exceeded the CFL bound of its fluxes");
+  return s[0] ? s[0] : s[1];
+}
+
+// With checks on, an online call waits for its own work and returns what
+// the device reported.
+static int checked(Model& M, hipStream_t st) {
+  if (!M.checks) return LRBMS_OK;
+  if (!hip_ok(hipStreamSynchronize(st), "synchronize")) return LRBMS_E_HIP;
+  return read_status(M);
+}
 
 // Read and clear the device status word of a scratch model.
 static int take_status(Model& M) {
@@ -921,7 +976,7 @@ static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o
             !hip_ok(launch_affine_sum(RM->d_e, RM->d_dq, RM->N, RM->d_theta, nq, RM->d_fN, 0),
                     "affine sum") ||
             !hip_ok(solver_factor_solve(RM->plan, RM->sdev, RM->d_blocks, RM->d_fN, pN.p,
-                                        RM->d_status, 0),
+                                        RM->d_status, 0, RM->refine),
                     "reduced solve") ||
             !hip_ok(launch_reconstruct(RM->g, RM->d_subs, RM->n_sub, RM->d_tiles, RM->n_tiles,
                                        RM->d_phi, pN.p, ph.p, 0),
@@ -1121,7 +1176,7 @@ int lrbms_online_assemble(lrbms_model* m, const double* d_sat, int32_t mode, voi
   }
   M->assembled = true;
   M->last_stream = st;
-  return LRBMS_OK;
+  return checked(*M, st);
 }
 
 int lrbms_online_solve(lrbms_model* m, double* d_pN, void* stream) {
@@ -1130,10 +1185,21 @@ int lrbms_online_solve(lrbms_model* m, double* d_pN, void* stream) {
   TimerScope timing(&M->timer);
   if (!M->assembled) return (set_error("online_solve called before online_assemble"), LRBMS_E_STATE);
   hipStream_t st = (hipStream_t)stream;
-  if (!hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, d_pN, M->d_status, st),
+  if (!hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, d_pN, M->d_status, st,
+                                  M->refine),
               "reduced solve"))
     return LRBMS_E_HIP;
   M->last_stream = st;
+  return checked(*M, st);
+}
+
+int lrbms_model_set_refinement(lrbms_model* m, int32_t steps) {
+  if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+  if (steps < 0 || steps > kMaxRefine)
+    return (set_error("refinement steps must be in 0..4"), LRBMS_E_ARG);
+  Model* M = M_(m);
+  if (M->owner) return (set_error("model belongs to a batch or server"), LRBMS_E_STATE);
+  M->refine = steps;
   return LRBMS_OK;
 }
 
@@ -1150,7 +1216,7 @@ int lrbms_reconstruct_flux(lrbms_model* m, const double* d_pN, const double* d_s
       !hip_ok(launch_flux(M->g, ph, d_sat, d_flux, st), "flux"))
     return LRBMS_E_HIP;
   M->last_stream = st;
-  return LRBMS_OK;
+  return checked(*M, st);
 }
 
 int lrbms_transport_step(lrbms_model* m, const double* d_sat, const double* d_flux,
@@ -1160,8 +1226,9 @@ int lrbms_transport_step(lrbms_model* m, const double* d_sat, const double* d_fl
   Model* M = M_(m);
   TimerScope timing(&M->timer);
   const int rc = transport_impl(*M, d_sat, d_flux, d_sat_out, d_flags, (hipStream_t)stream);
-  if (rc == LRBMS_OK) M->last_stream = (hipStream_t)stream;
-  return rc;
+  if (rc != LRBMS_OK) return rc;
+  M->last_stream = (hipStream_t)stream;
+  return checked(*M, (hipStream_t)stream);
 }
 
 int lrbms_fine_create(const lrbms_problem* prob, lrbms_fine** out) {
@@ -1240,11 +1307,13 @@ int lrbms_model_status(lrbms_model* m) {
   if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
   Model* M = M_(m);
   if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
-  int s = 0;
-  if (!hip_ok(hipMemcpy(&s, M->d_status, sizeof(int), hipMemcpyDeviceToHost), "status"))
-    return LRBMS_E_HIP;
-  if (s) set_error("device reported an error (non-positive pivot in the reduced Cholesky)");
-  return s;
+  return read_status(*M);
+}
+
+int lrbms_model_set_checks(lrbms_model* m, int32_t on) {
+  if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+  M_(m)->checks = on != 0;
+  return LRBMS_OK;
 }
 
 int lrbms_profile_enable(lrbms_model* m, int32_t enable) {
@@ -1297,11 +1366,13 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
       return LRBMS_E_HIP;
     auto time_plan = [&](const SolverPlan& P, const SolverDev& D, double& us) {
       for (int i = 0; i < 2; ++i)
-        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0), "solve"))
+        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0, M->refine),
+                    "solve"))
           return false;
       if (!hip_ok(hipEventRecord(e0, 0), "event")) return false;
       for (int i = 0; i < reps; ++i)
-        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0), "solve"))
+        if (!hip_ok(solver_factor_solve(P, D, M->d_blocks, M->d_fN, pN.p, M->d_status, 0, M->refine),
+                    "solve"))
           return false;
       float ms = 0.0f;
       if (!hip_ok(hipEventRecord(e1, 0), "event") || !hip_ok(hipEventSynchronize(e1), "event") ||
@@ -1318,7 +1389,9 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
     SolverPlan best_plan;
     auto candidate = [&](int leaf, int split, long long bw) {
       SolverPlan P;
-      if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf, P, split, bw)) return;
+      if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf, P, split, bw) ||
+          !plan_in_bounds(P, M->nblk, M->N))
+        return;
       SolverDev D;
       if (!solver_upload(P, D)) {
         solver_free(D);

@@ -21,15 +21,25 @@ struct Geom {
   int nfa[3], foff[3], nface;
   double h[3], vol, isv, area[3], hf[3], he;
   double visc_w, visc_o, cw, co;
+  double ivw, ivo;   // 1 / visc_w, 1 / visc_o
   int relperm;
   double pen;        // penalty_c / max(visc_w, visc_o)
   int weights;
   double sat_pen;    // sat_penalty_scale
   int limiter;
   double dt;
+  // dt max |f_w'| over [0, 1]: the transport step's CFL number of a cell is
+  // cfl_coef times its outflow over phi |e|
+  double cfl_coef;
   const double *perm, *poro, *q1, *q2, *bc_val, *bc_sval;
   const int8_t *bc_type, *bc_sat;
+  // device status words: [0] the first error (atomicMin of LRBMS_E_* codes),
+  // [1] a warning (LRBMS_W_CFL)
+  int* status;
 };
+
+// CFL number above which a transport step raises LRBMS_W_CFL.
+constexpr double kCflWarn = 0.5;
 
 // One coarse box E.
 struct Sub {
@@ -66,8 +76,8 @@ __device__ __forceinline__ void mobilities(const Geom& g, double s, double& lw, 
     const double so = 1.0 - sc;
     kro = (g.co == 2.0) ? so * so : corey_power(so, g.co);
   }
-  lw = krw / g.visc_w;
-  lo = kro / g.visc_o;
+  lw = krw * g.ivw;
+  lo = kro * g.ivo;
 }
 
 __device__ __forceinline__ double total_mobility(const Geom& g, double s) {
@@ -76,10 +86,21 @@ __device__ __forceinline__ double total_mobility(const Geom& g, double s) {
   return lw + lo;
 }
 
+// 1/d for a positive normal d: the hardware estimate y0 (relative error
+// e = 1 - d y0 below 1e-7) refined to y0 (1 + e + e^2), whose error e^3 is
+// below the rounding of a double.
+__device__ __forceinline__ double rcp_refined(double d) {
+  const double y0 = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, y0, 1.0);
+  return fma(fma(e, e, e), y0, y0);
+}
+
+// Fractional flow f_w = lambda_w / (lambda_w + lambda_o); the total mobility
+// is positive on [0, 1] (k_rw + k_ro > 0 for every law here).
 __device__ __forceinline__ double frac_flow(const Geom& g, double s) {
   double lw, lo;
   mobilities(g, s, lw, lo);
-  return lw / (lw + lo);
+  return lw * rcp_refined(lw + lo);
 }
 
 __device__ __forceinline__ void cell_coords(const Geom& g, int c, int x[3]) {

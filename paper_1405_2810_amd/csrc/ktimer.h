@@ -28,6 +28,9 @@ enum KernelKind {
   KK_FLUX,
   KK_TRANSPORT,
   KK_LIMITER,
+  KK_RESIDUAL,
+  KK_FRONT_FORWARD,
+  KK_FRONT_FW_GEMV,
   KK_COUNT
 };
 

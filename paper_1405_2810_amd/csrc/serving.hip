@@ -116,6 +116,7 @@ struct Batch {
   SolverDev cdev;
   double *cblocks = nullptr, *cfN = nullptr, *cpN = nullptr;
   int* cstatus = nullptr;
+  int refine = 0;   // refinement steps of the fused solve (those of every member)
   std::vector<double*> own_blocks, own_fN;
   hipEvent_t fork2 = nullptr;
   std::vector<hipEvent_t> join2;
@@ -181,7 +182,7 @@ struct Batch {
       if (rc != LRBMS_OK) return rc;
     }
     if ((rc = join_into(from, join)) != LRBMS_OK || !fused) return rc;
-    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, from),
+    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, from, refine),
                 "fused reduced solve"))
       return LRBMS_E_HIP;
     if ((rc = fork_from(from, fork2)) != LRBMS_OK) return rc;
@@ -397,6 +398,8 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
           return (set_error("a model appears twice in the batch"), LRBMS_E_ARG);
       if (!mode_ok(*model_of(models[i]), mode))
         return (set_error("assembly mode not available for every model"), LRBMS_E_ARG);
+      if (model_of(models[i])->refine != model_of(models[0])->refine)
+        return (set_error("the members' refinement steps differ"), LRBMS_E_ARG);
     }
     auto B = std::make_unique<Batch>();
     B->models.assign(models, models + n);
@@ -404,6 +407,7 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
     B->mode = mode;
     B->use_graph = (flags & LRBMS_BATCH_GRAPH) != 0;
     B->fused = (flags & LRBMS_BATCH_FUSED_SOLVE) != 0;
+    B->refine = model_of(models[0])->refine;
     B->bufs.resize(n);
     int rc;
     if (B->fused) {

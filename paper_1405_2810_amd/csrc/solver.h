@@ -60,6 +60,14 @@ long long bw_split_min();
 
 struct NodeRef { int pos, pn_off, size, ppos; };
 
+// Row block of one box in A_N, for the residual of the iterative refinement:
+// the diagonal block (lower triangle used, as the factorization does) and
+// neighbour blocks nb0 .. nb1-1 of the residual plan.
+struct ResBox { long long blk_off; int pn_off, ne, nb0, nb1, pad; };
+// One coupling block of a box's rows: A(i, j) = blocks[blk_off + i rs + j cs]
+// for the neighbour's ne unknowns at p_N[pn_off ..].
+struct ResNb { long long blk_off; int pn_off, ne, rs, cs; };
+
 // The L rows below the diagonal tile of panel b of a front (rows cs_b .. ld,
 // cs_b = min(kNB (b + 1), m), the last one the forward-substituted right-hand
 // side) are stored row by row, kNB doubles per row: row r of panel b starts
@@ -94,12 +102,18 @@ struct SolverPlan {
   std::vector<std::vector<std::vector<StepItem>>> upd_items;   // [level][panel]
   std::vector<std::vector<BwItem>> bw_items;                    // [level]
   std::vector<int> urow_pn;
+  // residual plan (boxes in p_N order) and the number of reduced unknowns
+  std::vector<ResBox> rboxes;
+  std::vector<ResNb> rnbs;
+  long long nN = 0;
   long long bw_part_doubles = 0;   // partial vectors of the split products (one level at a time)
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0, lpan_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
   std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]
   std::vector<double> bwg_flops, bwg_bytes;   // split backward products [level]
+  std::vector<double> fw_flops, fw_bytes;     // forward substitution with a new right-hand side [level]
+  double res_flops = 0.0, res_bytes = 0.0;    // residual of the refinement
   std::vector<std::vector<double>> step_flops, step_bytes;                           // [level][panel]
   std::vector<std::vector<double>> upd_flops, upd_bytes;                             // [level][panel]
 };
@@ -148,7 +162,11 @@ struct SolverDev {
   std::vector<std::vector<StepItem*>> upd_items;
   std::vector<BwItem*> bw_items;
   int* urow_pn = nullptr;
+  ResBox* rboxes = nullptr;
+  ResNb* rnbs = nullptr;
   double* part = nullptr;
+  double* res = nullptr;   // residual of the refinement (nN)
+  double* cor = nullptr;   // its correction (nN)
   std::vector<int*> level_fronts;
   double* F = nullptr;
   double* L = nullptr;
@@ -159,8 +177,14 @@ struct SolverDev {
 
 bool solver_upload(const SolverPlan& plan, SolverDev& dev);
 void solver_free(SolverDev& dev);
+// Factor A_N (blocks, f_N) and solve for p_N, then `refine` steps of
+// iterative refinement: the residual f_N - A_N p_N accumulated in
+// double-double arithmetic (compensated products and sums), a forward and a
+// backward substitution of it with the stored factor, and p_N += correction.
+// A non-finite residual sets the status word to LRBMS_E_NONFINITE.
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN,
-                               int* status, hipStream_t st);
+                               int* status, hipStream_t st, int refine = 0);
+constexpr int kMaxRefine = 4;
 
 }  // namespace lrbms

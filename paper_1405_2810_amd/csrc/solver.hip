@@ -198,6 +198,43 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.vec_doubles = voff;
   plan.inv_doubles = ioff;
   plan.lpan_doubles = loff;
+  // residual plan: every box's row of blocks, its interfaces in index order
+  plan.rboxes.clear();
+  plan.rnbs.clear();
+  plan.nN = 0;
+  plan.res_flops = plan.res_bytes = 0.0;
+  for (int v = 0; v < (int)subs.size(); ++v) {
+    ResBox rb{};
+    rb.blk_off = subs[v].blk_off;
+    rb.pn_off = subs[v].pn_off;
+    rb.ne = subs[v].NE;
+    rb.nb0 = (int)plan.rnbs.size();
+    double cols = rb.ne;
+    for (const Iface& I : ifaces) {
+      ResNb nb{};
+      nb.blk_off = I.blk_off;
+      if (I.lo == v) {          // A[v][hi], stored N_v x N_hi row-major
+        nb.pn_off = subs[I.hi].pn_off;
+        nb.ne = subs[I.hi].NE;
+        nb.rs = subs[I.hi].NE;
+        nb.cs = 1;
+      } else if (I.hi == v) {   // A[v][lo] = A[lo][v]^T
+        nb.pn_off = subs[I.lo].pn_off;
+        nb.ne = subs[I.lo].NE;
+        nb.rs = 1;
+        nb.cs = subs[v].NE;
+      } else {
+        continue;
+      }
+      cols += nb.ne;
+      plan.rnbs.push_back(nb);
+    }
+    rb.nb1 = (int)plan.rnbs.size();
+    plan.rboxes.push_back(rb);
+    plan.nN = std::max(plan.nN, (long long)rb.pn_off + rb.ne);
+    plan.res_flops += 2.0 * rb.ne * cols;
+    plan.res_bytes += 8.0 * (rb.ne * cols + 2.0 * rb.ne + cols);
+  }
   // levels by height
   int H = 0;
   for (auto& f : F) H = std::max(H, f.height + 1);
@@ -335,6 +372,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.bw_bytes.assign(H, 0.0);
   plan.bwg_flops.assign(H, 0.0);
   plan.bwg_bytes.assign(H, 0.0);
+  plan.fw_flops.assign(H, 0.0);
+  plan.fw_bytes.assign(H, 0.0);
   plan.step_flops.assign(H, {});
   plan.step_bytes.assign(H, {});
   plan.upd_flops.assign(H, {});
@@ -371,6 +410,13 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
           plan.upd_flops[h][b] += fu;
           plan.upd_bytes[h][b] += bu;
         }
+      }
+      // forward substitution of a new right-hand side (refinement): the
+      // same entries of L as the backward, read once
+      {
+        const double m = d.m, u = d.u;
+        plan.fw_flops[h] += 2.0 * m * u + m * m;
+        plan.fw_bytes[h] += 8.0 * (m * u + m * (m + 1) / 2 + 2.0 * (m + u));
       }
       // backward: the product L_US^T x_U (in its own launch for a split
       // front, which writes nzc partial vectors that the backward sums), then
@@ -865,13 +911,19 @@ __global__ __launch_bounds__(256) void k_front_bw_gemv(const BwItem* __restrict_
   }
 }
 
+// ysrc = nullptr: y_S is the forward-substituted right-hand side row of the
+// factorization; otherwise y_S = ysrc[voff ..] (k_front_forward of a new
+// right-hand side).  padd != nullptr: x_S is also added to padd (the
+// refinement's correction of p_N).
 __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
                                                         const double* __restrict__ Lpan,
                                                         const double* __restrict__ Inv,
                                                         const double* __restrict__ part,
-                                                        double* __restrict__ pN) {
+                                                        const double* __restrict__ ysrc,
+                                                        double* __restrict__ pN,
+                                                        double* __restrict__ padd) {
   extern __shared__ double w[];   // m + u values
   __shared__ double red[4][4][kNB];
   __shared__ double xb[kNB];
@@ -882,7 +934,8 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
   // y_S from the right-hand-side rows, x_U from the parent
   for (int i = tid; i < m; i += blockDim.x) {
     const int b = i >> 6;
-    w[i] = Lpan[lpanel_base(f, b) + (long long)(ld - csof(b)) * kNB + (i - kNB * b)];
+    w[i] = ysrc ? ysrc[f.voff + i]
+                : Lpan[lpanel_base(f, b) + (long long)(ld - csof(b)) * kNB + (i - kNB * b)];
   }
   for (int n = f.n_s_nodes; n < f.n_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
@@ -1001,8 +1054,239 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
   }
   for (int n = 0; n < f.n_s_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
-    for (int i = tid; i < nr.size; i += blockDim.x) pN[nr.pn_off + i] = w[nr.pos + i];
+    for (int i = tid; i < nr.size; i += blockDim.x) {
+      const double x = w[nr.pos + i];
+      pN[nr.pn_off + i] = x;
+      if (padd) padd[nr.pn_off + i] += x;
+    }
   }
+}
+
+// ---- iterative refinement -------------------------------------------------------
+// Error-free transformations (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005): a + b = s + e and a b = p + e exactly in floating point.
+// hipcc contracts a * b + c into fma by default, which would break these
+// transformations (the rounding of a b is what they capture): contraction is
+// switched off inside them.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double z = s - a;
+  e = (a - (s - z)) + (b - z);
+}
+
+// acc (s, c): s + c ~ s_exact; adds -a x with the product and sum errors kept.
+__device__ __forceinline__ void dot2_sub(double a, double x, double& s, double& c) {
+#pragma clang fp contract(off)
+  const double p = a * x;
+  const double pe = fma(a, x, -p);   // a x = p + pe
+  double t, e;
+  two_sum(s, -p, t, e);
+  s = t;
+  c += e - pe;
+}
+
+// r = f_N - A_N p_N for one box per workgroup, lane = row of the box (64
+// rows at a time), the columns of its row of blocks dealt to the four waves;
+// every product and sum is compensated (Dot2), the waves' pairs are joined
+// the same way, so r is accurate to about one rounding of its own size.  The
+// diagonal block is read through its lower triangle, the part the
+// factorization uses.
+__global__ __launch_bounds__(256) void k_residual(const ResBox* __restrict__ boxes,
+                                                  const ResNb* __restrict__ nbs,
+                                                  const double* __restrict__ blocks,
+                                                  const double* __restrict__ fN,
+                                                  const double* __restrict__ pN,
+                                                  double* __restrict__ res, int* status) {
+  __shared__ double xs[2][4][kNB];
+  const ResBox B = boxes[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ne = B.ne;
+  const double* D = blocks + B.blk_off;
+  for (int i0 = 0; i0 < ne; i0 += kNB) {
+    const int i = i0 + lane;
+    const bool row = i < ne;
+    double s = (wv == 0 && row) ? fN[B.pn_off + i] : 0.0, c = 0.0;
+    for (int j = wv; j < ne; j += 4) {
+      const double a = row ? (j <= i ? D[(long long)i * ne + j] : D[(long long)j * ne + i]) : 0.0;
+      dot2_sub(a, pN[B.pn_off + j], s, c);
+    }
+    for (int q = B.nb0; q < B.nb1; ++q) {
+      const ResNb nb = nbs[q];
+      const double* A = blocks + nb.blk_off + (long long)i * nb.rs;
+      for (int j = wv; j < nb.ne; j += 4) {
+        const double a = row ? A[(long long)j * nb.cs] : 0.0;
+        dot2_sub(a, pN[nb.pn_off + j], s, c);
+      }
+    }
+    xs[0][wv][lane] = s;
+    xs[1][wv][lane] = c;
+    __syncthreads();
+    if (wv == 0 && row) {
+      double t = xs[0][0][lane], cc = xs[1][0][lane];
+      for (int k = 1; k < 4; ++k) {
+        double u, e;
+        two_sum(t, xs[0][k][lane], u, e);
+        t = u;
+        cc += e + xs[1][k][lane];
+      }
+      const double r = t + cc;
+      res[B.pn_off + i] = r;
+      if (!isfinite(r)) atomicMin(status, (int)LRBMS_E_NONFINITE);
+    }
+    __syncthreads();
+  }
+}
+
+// w[R0 + i] -= sum_k T[i][k] y[k] for the rows i < nr of a 64 x 64 tile staged
+// in LDS (zero beyond its columns), y = w[c0 ..]: four partial sums per row,
+// one per wave, joined in a fixed order.
+__device__ __forceinline__ void tile_rows_sub(Tile* T, double* w, int c0, int nb, int R0, int nr,
+                                              double (*red)[kNB]) {
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int k = 16 * g + t;
+    s = fma(T[lane][k], k < nb ? w[c0 + k] : 0.0, s);
+  }
+  red[g][lane] = s;
+  __syncthreads();
+  if (threadIdx.x < nr)
+    w[R0 + threadIdx.x] -= (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                           (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  __syncthreads();
+}
+
+// Forward substitution L y = r of a new right-hand side, one workgroup per
+// front, from the leaves up (one launch per level): w = (r_S, 0_U) plus the
+// children's update vectors at their places in the front; then panel by
+// panel y_b = L_bb^{-1} w_b with the stored tile inverse and
+// w_{>b} -= L_{>b,b} y_b (a split front leaves its U rows to
+// k_front_fw_gemv).  The front's vector store receives (y_S, w_U): y_S for
+// the backward substitution, w_U for the parent.
+__global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ list,
+                                                       const FrontD* __restrict__ fronts,
+                                                       const NodeRef* __restrict__ nodes,
+                                                       const int* __restrict__ children,
+                                                       const double* __restrict__ Lpan,
+                                                       const double* __restrict__ Inv,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ V) {
+  extern __shared__ double w[];   // m + u values
+  __shared__ Tile T[kNB];
+  __shared__ double red[4][kNB];
+  const FrontD f = fronts[list[blockIdx.x]];
+  const int m = f.m, ld = m + f.u, np = f.npanels, tid = threadIdx.x;
+  for (int i = tid; i < ld; i += blockDim.x) w[i] = 0.0;
+  __syncthreads();
+  for (int n = 0; n < f.n_s_nodes; ++n) {
+    const NodeRef nr = nodes[f.node_off + n];
+    for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = r[nr.pn_off + i];
+  }
+  __syncthreads();
+  // children in their fixed order; the places of one child's U nodes are distinct
+  for (int c = 0; c < f.nchild; ++c) {
+    const FrontD fc = fronts[children[f.child_off + c]];
+    for (int n = fc.n_s_nodes; n < fc.n_nodes; ++n) {
+      const NodeRef nr = nodes[fc.node_off + n];
+      for (int i = tid; i < nr.size; i += blockDim.x) w[nr.ppos + i] += V[fc.voff + nr.pos + i];
+    }
+    __syncthreads();
+  }
+  const int rows_end = f.nzc > 0 ? m : ld;
+  for (int b = 0; b < np; ++b) {
+    const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
+    const double* Ip = Inv + f.inv_off + (long long)b * kNB * kNB;
+    {
+      double v[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
+        v[p] = (i < nb && k <= i) ? Ip[idx] : 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p;
+        T[idx >> 6][idx & 63] = v[p];
+      }
+    }
+    __syncthreads();
+    // y_b = Linv w_b: the same partial sums, written instead of subtracted
+    {
+      const int lane = tid & 63, g = tid >> 6;
+      double sacc = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int k = 16 * g + t;
+        sacc = fma(T[lane][k], k < nb ? w[c0 + k] : 0.0, sacc);
+      }
+      red[g][lane] = sacc;
+      __syncthreads();
+      if (tid < nb) w[c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      __syncthreads();
+    }
+    const double* Lb = Lpan + lpanel_base(f, b);
+    for (int R0 = cs; R0 < rows_end; R0 += kNB) {
+      const int nr = min(kNB, rows_end - R0);
+      double v[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
+        v[p] = (i < nr && k < nb) ? Lb[(long long)(R0 - cs + i) * kNB + k] : 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p;
+        T[idx >> 6][idx & 63] = v[p];
+      }
+      __syncthreads();
+      tile_rows_sub(T, w, c0, nb, R0, nr, red);
+    }
+  }
+  for (int i = tid; i < ld; i += blockDim.x) V[f.voff + i] = w[i];
+}
+
+// U rows of a split front's forward substitution: for 64 U rows (one work
+// item) V[voff + m + r] -= sum_j L_US(r, j) y_S(j), y_S = V[voff ..], the
+// columns panel by panel (tiles staged in LDS).
+__global__ __launch_bounds__(256) void k_front_fw_gemv(const BwItem* __restrict__ items,
+                                                       const FrontD* __restrict__ fronts,
+                                                       const double* __restrict__ Lpan,
+                                                       double* __restrict__ V) {
+  __shared__ Tile T[kNB];
+  __shared__ double red[4][kNB];
+  const BwItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const int m = f.m, r0 = kNB * it.chunk, nr = min(kNB, f.u - r0), tid = threadIdx.x;
+  const int lane = tid & 63, g = tid >> 6;
+  const double* y = V + f.voff;
+  double sacc = 0.0;
+  for (int b = 0; b < f.npanels; ++b) {
+    const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
+    const double* Lb = Lpan + lpanel_base(f, b) + (long long)(m - cs + r0) * kNB;
+    double v[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
+      v[p] = (i < nr && k < nb) ? Lb[(long long)i * kNB + k] : 0.0;
+    }
+    __syncthreads();   // the previous panel's reads of T are done
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p;
+      T[idx >> 6][idx & 63] = v[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int k = 16 * g + t;
+      sacc = fma(T[lane][k], k < nb ? y[c0 + k] : 0.0, sacc);
+    }
+  }
+  red[g][lane] = sacc;
+  __syncthreads();
+  if (tid < nr)
+    V[f.voff + m + r0 + tid] -= (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // Split every step of at least split_min items that still holds trailing
@@ -1073,6 +1357,8 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   out.bw_bytes.assign(H, 0.0);
   out.bwg_flops.assign(H, 0.0);
   out.bwg_bytes.assign(H, 0.0);
+  out.fw_flops.assign(H, 0.0);
+  out.fw_bytes.assign(H, 0.0);
   out.step_flops.assign(H, {});
   out.step_bytes.assign(H, {});
   out.upd_items.assign(H, {});
@@ -1112,6 +1398,22 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
       out.nodes.push_back(r);
     }
     for (int c : P.children) out.children.push_back(c + fbase);
+    const int rbase = (int)out.rnbs.size();
+    for (ResBox rb : P.rboxes) {
+      rb.blk_off += blk_base[k];
+      rb.pn_off += (int)pn_base[k];
+      rb.nb0 += rbase;
+      rb.nb1 += rbase;
+      out.rboxes.push_back(rb);
+    }
+    for (ResNb nb : P.rnbs) {
+      nb.blk_off += blk_base[k];
+      nb.pn_off += (int)pn_base[k];
+      out.rnbs.push_back(nb);
+    }
+    out.nN = std::max(out.nN, P.nN + pn_base[k]);
+    out.res_flops += P.res_flops;
+    out.res_bytes += P.res_bytes;
     out.front_doubles += P.front_doubles;
     out.lpan_doubles += P.lpan_doubles;
     out.vec_doubles += P.vec_doubles;
@@ -1149,6 +1451,8 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
       out.bw_bytes[h] += P.bw_bytes[h];
       out.bwg_flops[h] += P.bwg_flops[h];
       out.bwg_bytes[h] += P.bwg_bytes[h];
+      out.fw_flops[h] += P.fw_flops[h];
+      out.fw_bytes[h] += P.fw_bytes[h];
     }
   }
   // the members' steps side by side can be large enough to split (the
@@ -1194,6 +1498,20 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
   }
   for (int c : plan.children)
     if (c < 0 || c >= nf) return false;
+  if (plan.nN > nN) return false;
+  for (const ResBox& rb : plan.rboxes) {
+    if (rb.ne < 1 || rb.pn_off < 0 || (long long)rb.pn_off + rb.ne > plan.nN ||
+        rb.blk_off < 0 || rb.blk_off + (long long)rb.ne * rb.ne > nblk || rb.nb0 < 0 ||
+        rb.nb1 < rb.nb0 || rb.nb1 > (int)plan.rnbs.size())
+      return false;
+    for (int q = rb.nb0; q < rb.nb1; ++q) {
+      const ResNb& nb = plan.rnbs[q];
+      if (nb.ne < 1 || nb.pn_off < 0 || (long long)nb.pn_off + nb.ne > plan.nN ||
+          nb.blk_off < 0 || nb.rs < 1 || nb.cs < 1 ||
+          nb.blk_off + (long long)(rb.ne - 1) * nb.rs + (long long)(nb.ne - 1) * nb.cs >= nblk)
+        return false;
+    }
+  }
   auto span_ok = [](long long so, int nr, int nc, int rs, int cs, long long size) {
     const long long lo = so + std::min(0LL, (long long)(nr - 1) * rs) +
                          std::min(0LL, (long long)(nc - 1) * cs);
@@ -1358,10 +1676,14 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
   dev.bw_items.assign(H, nullptr);
   for (int h = 0; h < H; ++h)
     if (!upload(plan.bw_items[h], &dev.bw_items[h], b)) return false;
-  if (!upload(plan.urow_pn, &dev.urow_pn, b)) return false;
+  if (!upload(plan.urow_pn, &dev.urow_pn, b) || !upload(plan.rboxes, &dev.rboxes, b) ||
+      !upload(plan.rnbs, &dev.rnbs, b))
+    return false;
   int maxld = 1;
   for (auto& f : plan.fronts) maxld = std::max(maxld, f.m + f.u);
   if (hipFuncSetAttribute((const void*)k_front_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(double) * maxld)) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_front_forward, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(sizeof(double) * maxld)) != hipSuccess)
     return false;
   auto alloc = [&](double** p, long long n) {
@@ -1371,7 +1693,8 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
   };
   return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.lpan_doubles) &&
          alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles) &&
-         alloc(&dev.part, plan.bw_part_doubles);
+         alloc(&dev.part, plan.bw_part_doubles) && alloc(&dev.res, plan.nN) &&
+         alloc(&dev.cor, plan.nN);
 }
 
 void solver_free(SolverDev& dev) {
@@ -1389,6 +1712,10 @@ void solver_free(SolverDev& dev) {
     for (auto p : v) f(p);
   for (auto p : dev.bw_items) f(p);
   f(dev.urow_pn);
+  f(dev.rboxes);
+  f(dev.rnbs);
+  f(dev.res);
+  f(dev.cor);
   f(dev.part);
   f(dev.F);
   f(dev.L);
@@ -1397,9 +1724,35 @@ void solver_free(SolverDev& dev) {
   dev = SolverDev{};
 }
 
+// Backward substitution from the root down: x = L^{-T} y with y the
+// factorization's right-hand-side rows (ysrc = nullptr) or a forward
+// substitution's vectors; x into pN, and added to padd when given.
+static void backward_sweep(const SolverPlan& plan, const SolverDev& dev, const double* ysrc,
+                           double* pN, double* padd, hipStream_t st) {
+  const int H = plan.nlevels;
+  for (int h = H - 1; h >= 0; --h) {
+    const int n = (int)plan.level_fronts[h].size();
+    int maxld = 0;
+    for (int f : plan.level_fronts[h])
+      maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
+    const int nbw = (int)plan.bw_items[h].size();
+    if (nbw) {
+      ktimer_begin(KK_FRONT_BW_GEMV, st);
+      hipLaunchKernelGGL(k_front_bw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
+                         dev.fronts, dev.L, dev.urow_pn, pN, dev.part);
+      ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
+    }
+    ktimer_begin(KK_FRONT_BACKWARD, st);
+    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
+                       dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, dev.part, ysrc,
+                       pN, padd);
+    ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
+  }
+}
+
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN, int* status,
-                               hipStream_t st) {
+                               hipStream_t st, int refine) {
   const int H = plan.nlevels;
   for (int h = 0; h < H; ++h) {
     const int na = (int)plan.asm_items[h].size();
@@ -1429,22 +1782,32 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
       }
     }
   }
-  for (int h = H - 1; h >= 0; --h) {
-    const int n = (int)plan.level_fronts[h].size();
-    int maxld = 0;
-    for (int f : plan.level_fronts[h])
-      maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
-    const int nbw = (int)plan.bw_items[h].size();
-    if (nbw) {
-      ktimer_begin(KK_FRONT_BW_GEMV, st);
-      hipLaunchKernelGGL(k_front_bw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
-                         dev.fronts, dev.L, dev.urow_pn, pN, dev.part);
-      ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
+  backward_sweep(plan, dev, nullptr, pN, nullptr, st);
+  const int nbox = (int)plan.rboxes.size();
+  for (int it = 0; it < std::min(refine, kMaxRefine) && nbox > 0; ++it) {
+    ktimer_begin(KK_RESIDUAL, st);
+    hipLaunchKernelGGL(k_residual, dim3(nbox), dim3(256), 0, st, dev.rboxes, dev.rnbs, blocks, fN,
+                       pN, dev.res, status);
+    ktimer_end(plan.res_flops, plan.res_bytes, st);
+    for (int h = 0; h < H; ++h) {
+      const int n = (int)plan.level_fronts[h].size();
+      int maxld = 0;
+      for (int f : plan.level_fronts[h])
+        maxld = std::max(maxld, plan.fronts[f].m + plan.fronts[f].u);
+      ktimer_begin(KK_FRONT_FORWARD, st);
+      hipLaunchKernelGGL(k_front_forward, dim3(n), dim3(256), sizeof(double) * maxld, st,
+                         dev.level_fronts[h], dev.fronts, dev.nodes, dev.children, dev.L, dev.Inv,
+                         dev.res, dev.V);
+      ktimer_end(plan.fw_flops[h], plan.fw_bytes[h], st);
+      const int nbw = (int)plan.bw_items[h].size();
+      if (nbw) {
+        ktimer_begin(KK_FRONT_FW_GEMV, st);
+        hipLaunchKernelGGL(k_front_fw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
+                           dev.fronts, dev.L, dev.V);
+        ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
+      }
     }
-    ktimer_begin(KK_FRONT_BACKWARD, st);
-    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
-                       dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, dev.part, pN);
-    ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
+    backward_sweep(plan, dev, dev.V, dev.cor, pN, st);
   }
   return hipGetLastError();
 }

@@ -97,6 +97,8 @@ def lib():
         L.lrbms_model_interfaces.argtypes = [vp, vp, vp, vp]
         L.lrbms_online_assemble.argtypes = [vp, vp, i32, vp]
         L.lrbms_online_solve.argtypes = [vp, vp, vp]
+        L.lrbms_model_set_refinement.argtypes = [vp, i32]
+        L.lrbms_model_set_checks.argtypes = [vp, i32]
         L.lrbms_reconstruct_flux.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lrbms_transport_step.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lrbms_copy_reduced_system.argtypes = [vp, vp, vp]
@@ -157,6 +159,28 @@ def _ptr(a) -> int:
     if isinstance(a, np.ndarray):
         return a.ctypes.data
     return a.data_ptr()
+
+
+def _dev(t, dtype: str, n: int, name: str, optional: bool = False) -> int:
+    """Device address of a caller buffer handed to device kernels: a
+    contiguous torch tensor on the GPU of the expected dtype ("float64" or
+    "uint8") with at least n elements; anything else raises LrbmsError(-1)
+    (E_ARG) before any device work."""
+    if t is None:
+        if optional:
+            return 0
+        raise LrbmsError(-1, f"{name}: a device tensor is required")
+    import torch
+    want = {"float64": torch.float64, "uint8": torch.uint8}[dtype]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise LrbmsError(-1, f"{name}: expected a torch tensor on the GPU")
+    if t.dtype != want:
+        raise LrbmsError(-1, f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise LrbmsError(-1, f"{name}: tensor must be contiguous")
+    if t.numel() < n:
+        raise LrbmsError(-1, f"{name}: {t.numel()} elements, {n} needed")
+    return t.data_ptr()
 
 
 def _stream(stream) -> int:
@@ -316,19 +340,37 @@ class Model:
             pass
 
     # ---- online step --------------------------------------------------
+    def _nsat(self):
+        return self.info["r"] * self.info["ncell"]
+
     def assemble(self, sat, mode=DIRECT, stream=None):
-        _check(lib().lrbms_online_assemble(self._h, _ptr(sat), int(mode), _stream(stream)))
+        return _check(lib().lrbms_online_assemble(
+            self._h, _dev(sat, "float64", self._nsat(), "sat"), int(mode), _stream(stream)))
 
     def solve(self, pN, stream=None):
-        _check(lib().lrbms_online_solve(self._h, _ptr(pN), _stream(stream)))
+        return _check(lib().lrbms_online_solve(self._h, _dev(pN, "float64", self.info["N"], "pN"),
+                                               _stream(stream)))
+
+    def set_refinement(self, steps: int):
+        _check(lib().lrbms_model_set_refinement(self._h, int(steps)))
+
+    def set_checks(self, on: bool):
+        _check(lib().lrbms_model_set_checks(self._h, int(bool(on))))
 
     def reconstruct_flux(self, pN, sat, flux, ph=None, stream=None):
-        _check(lib().lrbms_reconstruct_flux(self._h, _ptr(pN), _ptr(sat), _ptr(flux), _ptr(ph),
-                                            _stream(stream)))
+        n = self._nsat()
+        return _check(lib().lrbms_reconstruct_flux(
+            self._h, _dev(pN, "float64", self.info["N"], "pN"), _dev(sat, "float64", n, "sat"),
+            _dev(flux, "float64", self.info["nface"], "flux"),
+            _dev(ph, "float64", n, "ph", optional=True), _stream(stream)))
 
     def transport_step(self, sat, flux, sat_out, flags=None, stream=None):
-        _check(lib().lrbms_transport_step(self._h, _ptr(sat), _ptr(flux), _ptr(sat_out),
-                                          _ptr(flags), _stream(stream)))
+        n = self._nsat()
+        return _check(lib().lrbms_transport_step(
+            self._h, _dev(sat, "float64", n, "sat"),
+            _dev(flux, "float64", self.info["nface"], "flux"),
+            _dev(sat_out, "float64", n, "sat_out"),
+            _dev(flags, "uint8", self.info["ncell"], "flags", optional=True), _stream(stream)))
 
     # ---- inspection ---------------------------------------------------
     def reduced_system(self):
@@ -429,9 +471,10 @@ class Model:
             pos += nl * nh
         return A
 
-    def sparse_reduced_matrix(self, blocks: Optional[np.ndarray] = None):
+    def sparse_reduced_matrix(self, blocks: Optional[np.ndarray] = None, lower: bool = False):
         """The block storage as a scipy.sparse CSR matrix (host), both
-        triangles of the coupling blocks."""
+        triangles of the coupling blocks; lower: each diagonal block taken
+        from its lower triangle (the symmetric matrix the solver factors)."""
         import scipy.sparse as sp
         if blocks is None:
             blocks, _ = self.reduced_system()
@@ -441,7 +484,11 @@ class Model:
         for E, ne in enumerate(sizes):
             i, j = np.meshgrid(np.arange(ne), np.arange(ne), indexing="ij")
             rows.append(offs[E] + i.ravel()); cols.append(offs[E] + j.ravel())
-            vals.append(blocks[pos:pos + ne * ne])
+            blk = blocks[pos:pos + ne * ne]
+            if lower:
+                b2 = blk.reshape(ne, ne)
+                blk = (np.tril(b2) + np.tril(b2, -1).T).ravel()
+            vals.append(blk)
             pos += ne * ne
         ax, lo, hi = self.interfaces()
         for t in range(len(ax)):
@@ -658,19 +705,25 @@ class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT):
         self._carry = []
         self._sims = {}
+        self._states = {}
         h = C.c_void_p()
         _check(lib().lrbms_server_create(int(hbm_budget), max_slots, mode, C.byref(h)))
         self._h = h
 
     def attach(self, model: "Model", sat) -> int:
+        """Attach a simulation with its state tensor; the server advances it
+        in place and keeps a reference to it until detach or close."""
         sid = C.c_int32()
-        _check(lib().lrbms_server_attach(self._h, model._h, _ptr(sat), C.byref(sid)))
+        ptr = _dev(sat, "float64", model.info["r"] * model.info["ncell"], "sat")
+        _check(lib().lrbms_server_attach(self._h, model._h, ptr, C.byref(sid)))
         self._sims[sid.value] = model
+        self._states[sid.value] = sat
         model._owner = self
         return sid.value
 
     def detach(self, sim: int):
         _check(lib().lrbms_server_detach(self._h, sim))
+        self._states.pop(sim, None)
         m = self._sims.pop(sim, None)
         if m is not None and m._owner is self:
             m._owner = None
@@ -713,6 +766,7 @@ class Server:
                 if m._owner is self:
                     m._owner = None
             self._sims.clear()
+            self._states.clear()
 
     def __del__(self):
         try:

@@ -252,6 +252,23 @@ CONFIGS: Dict[str, dict] = {
                  corr=0.1, sigma=3.0, ratio=10.0, steps=100, M=16, n_train=41,
                  ne_cap=40, wells="five3d", Q=1.0e-2, dt=1.0e4, seed=33, t_end=2.0e9,
                  channels=True),
+    # the 3D workload's coarse grid (6x22x5 boxes, N_E = 40, sigma_logk = 3 with
+    # channels) on a fine grid half as fine per axis (30x110x40 cells), small
+    # enough for the oracle's element-by-element parity
+    "cfg3s": dict(dim=3, n=(30, 110, 40), L=(600.0, 2200.0, 170.0), nc=(6, 22, 5),
+                  corr=0.1, sigma=3.0, ratio=10.0, steps=100, M=16, n_train=41,
+                  ne_cap=40, wells="five3d", Q=1.0e-2, dt=1.0e4, seed=33, t_end=2.0e9,
+                  channels=True),
+    # shaped like the paper's 2D benchmark (Sec. 6): [0,300] x [0,60] m, 400 x 160
+    # cells, linear relative permeabilities, the printed viscosities, water
+    # entering on the left (p = 10, s = 1), outward flux 3e-4 on the right,
+    # no flow on top and bottom, no sources, T = 3e5 s in 6000 steps; its
+    # permeability and porosity fields are not given, so a seeded log-normal
+    # field (kappa_g = 1e-10 m^2) and porosity 0.2 stand in; 8 x 2 boxes
+    "paper": dict(dim=2, n=(400, 160, 1), L=(300.0, 60.0, 1.0), nc=(8, 2, 1), corr=0.1 * 300.0,
+                  sigma=1.0, steps=6000, M=8, n_train=8, ne_cap=25, wells="paper", Q=0.0,
+                  dt=50.0, seed=44, t_end=3.0e5, kg=1.0e-10, visc_w=0.00130581, visc_o=0.008,
+                  relperm=0, p_left=10.0, v_right=3.0e-4),
     # ensemble members: 2D 256x256 and 3D 64x64x32 on seeded uneven coarse
     # partitions (boxes of 16..48 cells per side in 2D, 8..24 x 8..24 x 4..12
     # in 3D), local basis sizes drawn per box by ensemble_caps
@@ -300,7 +317,7 @@ def make_problem(name: str, seed: Optional[int] = None, **overrides) -> Problem:
     nx, ny, nz = n
     h = [L[a] / n[a] for a in range(3)]
     vol = h[0] * h[1] * (h[2] if dim == 3 else 1.0)
-    kg = 1e-13
+    kg = cfg.get("kg", 1e-13)
     if dim == 2:
         g = gaussian_field((ny, nx), (h[1], h[0]), cfg["corr"], rng)
         g = g.reshape(1, ny, nx)
@@ -383,17 +400,18 @@ def make_problem(name: str, seed: Optional[int] = None, **overrides) -> Problem:
         cuts = [even_cuts(n[a], cfg["nc"][a]) if a < dim else np.array([0, 1], dtype=np.int32)
                 for a in range(3)]
 
-    ratio = cfg["ratio"]
-    visc_w = 1e-3
-    visc_o = ratio * visc_w
+    visc_w = cfg.get("visc_w", 1e-3)
+    visc_o = cfg.get("visc_o", cfg.get("ratio", 1.0) * visc_w)
     c0 = 4.0 if dim == 2 else 30.0
     penalty_c = c0 * max(visc_w, visc_o) / min(visc_w, visc_o)
     return Problem(dim=dim, n=n, L=L if dim == 3 else (L[0], L[1], 1.0), cuts=cuts,
                    perm=perm, poro=poro, visc_w=visc_w, visc_o=visc_o,
-                   relperm=RELPERM_COREY, corey_w=2.0, corey_o=2.0,
+                   relperm=cfg.get("relperm", RELPERM_COREY), corey_w=cfg.get("corey_w", 2.0),
+                   corey_o=cfg.get("corey_o", 2.0),
                    bc_type=bc_type, bc_val=bc_val, bc_sat=bc_sat, bc_sval=bc_sval,
-                   q1=q1, q2=q2, penalty_c=penalty_c, weights=WEIGHTS_SWIP,
-                   sat_penalty_scale=1.0, limiter=1, dt=cfg["dt"], n_steps=cfg["steps"],
+                   q1=q1, q2=q2, penalty_c=penalty_c, weights=cfg.get("weights", WEIGHTS_SWIP),
+                   sat_penalty_scale=1.0, limiter=cfg.get("limiter", 1), dt=cfg["dt"],
+                   n_steps=cfg["steps"],
                    M=cfg["M"], n_train=cfg["n_train"], ne_cap=cfg["ne_cap"],
                    basis_method=cfg.get("basis_method", "gs"),
                    pca_eps=cfg.get("pca_eps", 1e-4), unit_functions=True,

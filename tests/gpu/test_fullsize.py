@@ -1,22 +1,28 @@
 """Full-size workloads in the benchmark's launch configuration.
 
-2D 256 x 256 cells, 16 x 16 boxes, N_E = 25 (the benchmark workload): every
-call of the online step against the oracle element by element, the oracle
-being fast enough at this size (identical basis inputs on both sides).  The
-reduced matrix of this workload has a 2-norm condition number near 3e9, so
-rounding-level differences in its entries (a different summation order in
-the assembly) move the exact reduced solution by about 1e-10; the p_N bound
-is therefore max(1e-10, 4 x the oracle's own sensitivity), the latter
-measured by re-solving with the matrix perturbed by two ulps per entry.
+2D 256 x 256 cells, 16 x 16 boxes, N_E = 25: every call of the online step
+against the oracle element by element (identical basis inputs on both
+sides), p_N at the 1e-10 bound, and the GPU's reduced solve against the
+oracle's solve of the GPU's own A_N, f_N at 1e-12 (the solver alone).  The
+reduced matrix of this workload has a condition number near 3e9 (logged), so
+the oracle forms its A_N in extended precision and rounds once; the GPU
+refines its solution with a double-double residual.
 
-3D 60 x 220 x 85 cells, 6 x 22 x 5 boxes, N_E = 40: the oracle's reduced
-solve at N = 26,400 is too slow for a test, so the GPU step is checked by
-properties that hold at any size: symmetric diagonal blocks, the residual of
-the reduced solve, exact coarse conservation with 1_E in every local basis
-(the Galerkin equation for the test function 1_E), the reconstruction
-p_h = Phi p_N on sampled boxes, and the discrete mass balance of the
-saturation step."""
+The 3D workload's coarse grid (6 x 22 x 5 boxes, N_E = 40, sigma_logk = 3
+with channels, N = 26,400) on a 30 x 110 x 40 fine grid: the same solver
+plan as the 60 x 220 x 85 workload (the 660-box tree, split panel steps and
+backward products), compared element by element with the oracle: A_N, f_N,
+p_N, fluxes, saturation and limiter flags, with the plan of model creation,
+the autotuned plan and every panel step forced to split.
+
+3D 60 x 220 x 85 cells, 6 x 22 x 5 boxes, N_E = 40 (the benchmark
+workload): the reduced solve against the oracle's solve of the GPU's own
+system, and properties that hold at any size: symmetric diagonal blocks,
+the reconstruction p_h = Phi p_N on sampled boxes, exact coarse
+conservation with 1_E in every local basis, and the discrete mass balance
+of the saturation step."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -24,28 +30,14 @@ import pytest
 from synth import make_problem, random_saturation, smooth_fields
 from oracle.fem import Grid
 from oracle.offline import local_bases
-from oracle.online import Model as OModel, reduced_system, solve_reduced, online_step, DIRECT
+from oracle.online import (Model as OModel, reduced_system, solve_reduced, online_step, DIRECT,
+                           condition_estimate)
 
 from .helpers import TOL_BLOCK, TOL_PN, TOL_SAT, TOL_FLUX, log, rel_l2, gpu_model, dev, host
 
 pytestmark = pytest.mark.gpu
 
-
-def _sensitivity(A_o, f_o, x_o, seed=0):
-    """Relative change of the oracle's reduced solution when every entry of
-    A_N is perturbed by up to two ulps (symmetrically)."""
-    A = A_o.toarray()
-    rng = np.random.default_rng(seed)
-    E = np.triu(rng.uniform(-2.0, 2.0, A.shape) * np.spacing(np.abs(A)))
-    E = E + np.triu(E, 1).T
-    import scipy.sparse as sp
-    x_p = solve_reduced(sp.csr_matrix(A + E), f_o)
-    return rel_l2(x_p, x_o)
-
-
-def _pn_bound(A_o, f_o, x_o):
-    sens = _sensitivity(A_o, f_o, x_o)
-    return max(TOL_PN, 4.0 * sens), sens
+TOL_SOLVE = 1e-12   # GPU reduced solve vs the oracle's solve of the same system
 
 
 @pytest.fixture(scope="module")
@@ -62,27 +54,35 @@ def cfg2():
     gm.close()
 
 
-def test_cfg2_reduced_system_and_solve(cfg2):
+def _check_system_and_solve(tag, om, gm, s):
     import torch
-    p, g, om, gm = cfg2
-    s = random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6)
     gm.assemble(dev(s), DIRECT)
     A_o, f_o = reduced_system(om, s, DIRECT)
     blocks, f_g = gm.reduced_system()
     A_g = gm.sparse_reduced_matrix(blocks)
     err = abs(A_g - A_o).max() / abs(A_o).max()
-    log(f"[fullsize] cfg2: A err {err:.2e} f err {rel_l2(f_g, f_o):.2e}")
-    assert err <= TOL_BLOCK
-    assert rel_l2(f_g, f_o) <= TOL_BLOCK
+    e_f = rel_l2(f_g, f_o)
     pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
     gm.solve(pN)
     assert gm.status() == 0
+    x_g = host(pN)
     x_o = solve_reduced(A_o, f_o)
-    e_p = rel_l2(host(pN), x_o)
-    bound, sens = _pn_bound(A_o, f_o, x_o)
-    log(f"[fullsize] cfg2: pN err {e_p:.2e} (oracle sensitivity to 2-ulp entries {sens:.2e}, "
-        f"bound {bound:.2e})")
-    assert e_p <= bound
+    e_p = rel_l2(x_g, x_o)
+    e_s = rel_l2(x_g, solve_reduced(gm.sparse_reduced_matrix(blocks, lower=True), f_g))
+    log(f"[fullsize] {tag}: A err {err:.2e} f err {e_f:.2e} pN err {e_p:.2e} "
+        f"(solver alone {e_s:.2e}; 1-norm condition ~{condition_estimate(A_o):.1e})")
+    assert err <= TOL_BLOCK
+    assert e_f <= TOL_BLOCK
+    assert e_s <= TOL_SOLVE
+    assert e_p <= TOL_PN
+    return pN
+
+
+def test_cfg2_reduced_system_and_solve(cfg2):
+    p, g, om, gm = cfg2
+    for seed in (1, 3):
+        s = random_saturation(p, np.random.default_rng(seed), lo=0.0, hi=0.6)
+        _check_system_and_solve(f"cfg2 seed {seed}", om, gm, s)
 
 
 def test_cfg2_flux_and_transport(cfg2):
@@ -115,21 +115,104 @@ def test_cfg2_free_run(cfg2):
     pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
     flux = torch.zeros(g.nface, dtype=torch.float64, device="cuda")
     for n in range(5):
-        A_o, f_o = reduced_system(om, s_o, DIRECT)
         o = online_step(om, s_o, DIRECT)
         s_o = o["s"]
         gm.assemble(s_a, DIRECT)
         gm.solve(pN)
         e_p = rel_l2(host(pN), o["pN"])
-        bound = TOL_PN if e_p <= TOL_PN else _pn_bound(A_o, f_o, o["pN"])[0]
         gm.reconstruct_flux(pN, s_a, flux)
         gm.transport_step(s_a, flux, s_b)
         s_a, s_b = s_b, s_a
-        log(f"[fullsize] cfg2 step {n}: pN err {e_p:.2e} (bound {bound:.2e}) "
-            f"sat err {rel_l2(host(s_a), s_o):.2e}")
-        assert e_p <= bound
+        log(f"[fullsize] cfg2 step {n}: pN err {e_p:.2e} sat err {rel_l2(host(s_a), s_o):.2e}")
+        assert e_p <= TOL_PN
     assert gm.status() == 0
     assert rel_l2(host(s_a), s_o) <= TOL_SAT
+
+
+def _with_env(var, value, make):
+    old = os.environ.get(var)
+    os.environ[var] = str(value)
+    try:
+        return make()
+    finally:
+        if old is None:
+            del os.environ[var]
+        else:
+            os.environ[var] = old
+
+
+@pytest.fixture(scope="module")
+def cfg3s():
+    p = make_problem("cfg3s")
+    g = Grid(p)
+    log("[fullsize] cfg3s: oracle bases from seeded smooth snapshots")
+    snaps = smooth_fields(p, p.ne_cap + 4, np.random.default_rng(p.seed + 1))
+    phis = local_bases(g, p, snaps, method="gs", cap=p.ne_cap, unit=True)
+    om = OModel(p, phis, None)
+    log("[fullsize] cfg3s: oracle model ready")
+    yield p, g, om
+
+
+@pytest.mark.parametrize("plan", ["created", "autotuned", "all-split"])
+def test_cfg3s_reduced_system_and_solve(cfg3s, plan):
+    p, g, om = cfg3s
+    s = random_saturation(p, np.random.default_rng(11), lo=0.0, hi=0.6)
+    if plan == "all-split":
+        gm = _with_env("LRBMS_STEP_SPLIT_MIN", 1, lambda: gpu_model(p, om))
+    else:
+        gm = gpu_model(p, om)
+    if plan == "autotuned":
+        rep = gm.autotune(dev(s), reps=2)
+        log(f"[fullsize] cfg3s: autotuned {rep}")
+    log(f"[fullsize] cfg3s ({plan}): N={gm.info['N']}")
+    try:
+        _check_system_and_solve(f"cfg3s {plan}", om, gm, s)
+    finally:
+        gm.close()
+
+
+def test_cfg3s_flux_transport_and_free_run(cfg3s):
+    import torch
+    p, g, om = cfg3s
+    gm = gpu_model(p, om)
+    try:
+        s = random_saturation(p, np.random.default_rng(12), lo=0.0, hi=0.6)
+        out = online_step(om, s, DIRECT)
+        flux = torch.zeros(g.nface, dtype=torch.float64, device="cuda")
+        ph = torch.zeros(g.r * g.ncell, dtype=torch.float64, device="cuda")
+        gm.reconstruct_flux(dev(out["pN"]), dev(s), flux, ph)
+        e_h = rel_l2(host(ph), out["ph"])
+        ef = rel_l2(host(flux), out["F"])
+        s_out = torch.zeros_like(ph)
+        flags = torch.zeros(g.ncell, dtype=torch.uint8, device="cuda")
+        gm.transport_step(dev(s), dev(out["F"]), s_out, flags)
+        es = rel_l2(host(s_out), out["s"])
+        log(f"[fullsize] cfg3s: ph err {e_h:.2e} flux err {ef:.2e} sat err {es:.2e} "
+            f"flags {int(host(flags).sum())}")
+        assert e_h <= TOL_PN
+        assert ef <= TOL_FLUX
+        assert es <= TOL_SAT
+        assert np.array_equal(host(flags), out["flags"])
+        # two free steps from s0 = 0
+        s_o = np.zeros(g.r * g.ncell)
+        s_a = torch.zeros(g.r * g.ncell, dtype=torch.float64, device="cuda")
+        s_b = torch.zeros_like(s_a)
+        pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
+        for n in range(2):
+            o = online_step(om, s_o, DIRECT)
+            s_o = o["s"]
+            gm.assemble(s_a, DIRECT)
+            gm.solve(pN)
+            e_p = rel_l2(host(pN), o["pN"])
+            gm.reconstruct_flux(pN, s_a, flux)
+            gm.transport_step(s_a, flux, s_b)
+            s_a, s_b = s_b, s_a
+            log(f"[fullsize] cfg3s step {n}: pN err {e_p:.2e} sat err {rel_l2(host(s_a), s_o):.2e}")
+            assert e_p <= TOL_PN
+        assert gm.status() == 0
+        assert rel_l2(host(s_a), s_o) <= TOL_SAT
+    finally:
+        gm.close()
 
 
 def _box_bases(p, ne, rng):
@@ -185,10 +268,13 @@ def test_cfg3_fullsize_properties():
     gm.solve(pN)
     assert gm.status() == 0
     x = host(pN)
-    A = gm.sparse_reduced_matrix(blocks)
+    A = gm.sparse_reduced_matrix(blocks, lower=True)
     res = np.abs(A @ x - fN).max() / (abs(A).sum(axis=1).max() * np.abs(x).max())
-    log(f"[fullsize] cfg3: reduced residual {res:.2e}")
+    e_s = rel_l2(x, solve_reduced(A, fN))
+    log(f"[fullsize] cfg3: reduced residual {res:.2e}, solver against the oracle's solve of "
+        f"the same system {e_s:.2e}")
     assert res <= 1e-13
+    assert e_s <= TOL_SOLVE
     flux = torch.zeros(gm.info["nface"], dtype=torch.float64, device="cuda")
     ph = torch.zeros(r * ncell, dtype=torch.float64, device="cuda")
     gm.reconstruct_flux(pN, dev(s), flux, ph)
@@ -243,7 +329,9 @@ def test_cfg3_fullsize_properties():
     s_out = torch.zeros_like(ph)
     flags = torch.zeros(ncell, dtype=torch.uint8, device="cuda")
     gm.transport_step(dev(s0), flux, s_out, flags)
-    assert gm.status() == 0
+    # no error; the CFL warning is expected: the random local bases make
+    # rough pressures and fluxes far above the workload's time-step bound
+    assert gm.status() in (0, 1)
     so = host(s_out)
     assert np.all(np.isfinite(so))
     F = host(flux)

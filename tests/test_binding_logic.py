@@ -76,6 +76,22 @@ class _FakeOwnerLib:
         return b""
 
 
+class _FakeCudaTensor:
+    """Stands in for a GPU tensor (is_cuda) of a given dtype, layout and size."""
+
+    def __init__(self, dtype, n, contiguous=True):
+        self.dtype, self._n, self._c, self.is_cuda = dtype, n, contiguous, True
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 4096
+
+
 def _fake_model(L, h):
     m = object.__new__(L.Model)
     m._h = h
@@ -95,15 +111,57 @@ def test_model_of_an_open_batch_or_server_is_not_closed(monkeypatch):
     a.close()
     assert fake.destroyed == ["batch", 7] and a._h is None
     S = object.__new__(lrbms.Server)
-    S._carry, S._sims, S._h = [], {}, 99
-    sid = S.attach(b, None)
+    S._carry, S._sims, S._states, S._h = [], {}, {}, 99
+    state = _FakeCudaTensor(np.float64, 48)
+    monkeypatch.setattr(lrbms, "_dev", lambda t, dtype, n, name, optional=False: 4096)
+    b.info = dict(r=3, ncell=16)
+    sid = S.attach(b, state)
+    assert S._states[sid] is state
     with pytest.raises(lrbms.LrbmsError):
         b.close()
     S.detach(sid)
     b.close()
     assert fake.destroyed == ["batch", 7, 8]
     c = _fake_model(lrbms, 9)
-    S.attach(c, None)
+    c.info = dict(r=3, ncell=16)
+    S.attach(c, state)
     S.close()
     c.close()
     assert fake.destroyed == ["batch", 7, 8, "server", 9]
+
+
+def test_device_buffers_are_checked_before_the_library(monkeypatch):
+    """The online calls accept only contiguous GPU tensors of the expected
+    dtype and size: a host array, a CPU tensor, a wrong dtype, a strided
+    view or a short tensor raises E_ARG before anything reaches the
+    library."""
+    import torch
+    from paper_1405_2810_amd import lrbms
+
+    class _NoLib:
+        def __getattr__(self, name):
+            def call(*a):
+                raise AssertionError(f"{name} reached the library")
+            return call
+
+    monkeypatch.setattr(lrbms, "lib", lambda: _NoLib())
+    m = object.__new__(lrbms.Model)
+    m._h = None
+    m.info = dict(r=3, ncell=16, N=8, nface=40)
+    for bad in (np.zeros(48), torch.zeros(48, dtype=torch.float64), None):
+        with pytest.raises(lrbms.LrbmsError) as ei:
+            m.assemble(bad)
+        assert ei.value.code == -1
+    with pytest.raises(lrbms.LrbmsError):
+        m.solve(torch.zeros(8, dtype=torch.float32))
+    assert lrbms._dev(None, "float64", 4, "ph", optional=True) == 0
+
+    _FakeCuda = _FakeCudaTensor
+    monkeypatch.setattr(torch, "Tensor", _FakeCuda)
+    assert lrbms._dev(_FakeCuda(torch.float64, 48), "float64", 48, "sat") == 4096
+    for bad in (_FakeCuda(torch.float32, 48), _FakeCuda(torch.float64, 47),
+                _FakeCuda(torch.float64, 48, contiguous=False)):
+        with pytest.raises(lrbms.LrbmsError) as ei:
+            lrbms._dev(bad, "float64", 48, "sat")
+        assert ei.value.code == -1
+    assert lrbms._dev(_FakeCuda(torch.uint8, 16), "uint8", 16, "flags") == 4096

@@ -56,7 +56,7 @@ def _factor_tile(Fp, m, panel, Inv, f):
     Inv[o:o + NB * NB] = pad.ravel()
 
 
-def emulate(plan, blocks, fN):
+def emulate(plan, blocks, fN, refine=False):
     """The numeric phase as the device kernels execute it: fronts column-major
     with a right-hand-side row at the bottom, fused panel steps with the L rows
     in a separate panel-major store, look-ahead tile factorization, backward
@@ -121,7 +121,66 @@ def emulate(plan, blocks, fN):
                 Fp[R0:R0 + nr, C0:C0 + ncl] -= A @ Bt[:ncl].T
                 if it["ti"] == 0 and it["tj"] == 0 and p + 1 < f["npanels"]:
                     _factor_tile(Fp, f["m"], p + 1, Inv, f)
-    pN = np.zeros_like(fN)
+    def rhs_rows(f):
+        ld, m = f["m"] + f["u"], f["m"]
+        y = np.zeros(m)
+        for b in range(f["npanels"]):
+            rows, cs_b = lpanel(f, b)
+            nbb = min(NB, m - b * NB)
+            y[b * NB:b * NB + nbb] = rows[ld - cs_b, :nbb]
+        return y
+
+    pN = _backward(plan, lpanel, Inv, rhs_rows, np.zeros_like(fN))
+    if refine:
+        return pN, (lpanel, Inv)
+    return pN
+
+
+def _forward(plan, lpanel, Inv, r):
+    """Forward substitution L y = r of a new right-hand side as
+    k_front_forward and k_front_fw_gemv run it: per front (leaves first)
+    w = (r_S, 0) plus the children's update vectors at their parent places,
+    panel by panel y_b = Linv_b w_b and w_{>b} -= L_{>b,b} y_b (a split
+    front's U rows afterwards, chunk by chunk); the front's vector store
+    receives (y_S, w_U)."""
+    fr, nodes = plan["fronts"], plan["nodes"]
+    V = np.full(plan["vec_doubles"], np.nan)
+    for lev in plan["levels"]:
+        for fi in lev["fronts"]:
+            f = fr[fi]
+            ld, m = f["m"] + f["u"], f["m"]
+            w = np.zeros(ld)
+            for n in nodes[f["node_off"]:f["node_off"] + f["n_s_nodes"]]:
+                w[n["pos"]:n["pos"] + n["size"]] = r[n["pn_off"]:n["pn_off"] + n["size"]]
+            for c in plan["children"][f["child_off"]:f["child_off"] + f["nchild"]]:
+                fc = fr[c]
+                for n in nodes[fc["node_off"] + fc["n_s_nodes"]:fc["node_off"] + fc["n_nodes"]]:
+                    w[n["ppos"]:n["ppos"] + n["size"]] += V[fc["voff"] + n["pos"]:fc["voff"] + n["pos"] + n["size"]]
+            rows_end = m if f["nzc"] > 0 else ld
+            for b in range(f["npanels"]):
+                c0, nb = b * NB, min(NB, m - b * NB)
+                Li = Inv[f["inv_off"] + b * NB * NB:f["inv_off"] + (b + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
+                w[c0:c0 + nb] = np.tril(Li) @ w[c0:c0 + nb]
+                rows, cs_b = lpanel(f, b)
+                w[c0 + nb:rows_end] -= rows[0:rows_end - cs_b, :nb] @ w[c0:c0 + nb]
+            V[f["voff"]:f["voff"] + ld] = w
+        for fi, c in lev["bw"]:
+            f = fr[fi]
+            m, r0 = f["m"], NB * c
+            nr = min(NB, f["u"] - r0)
+            y = V[f["voff"]:f["voff"] + m]
+            acc = np.zeros(nr)
+            for b in range(f["npanels"]):
+                rows, cs_b = lpanel(f, b)
+                nbb = min(NB, m - b * NB)
+                acc += rows[m - cs_b + r0:m - cs_b + r0 + nr, :nbb] @ y[b * NB:b * NB + nbb]
+            V[f["voff"] + m + r0:f["voff"] + m + r0 + nr] -= acc
+    return V
+
+
+def _backward(plan, lpanel, Inv, y_of, pN):
+    """Backward sweep L^T x = y from the root down; y_S of a front from y_of."""
+    fr, nodes = plan["fronts"], plan["nodes"]
     part = np.full(max(plan["bw_part_doubles"], 1), np.nan)
     urow = np.asarray(plan["urow_pn"], dtype=np.int64)
     for lev in reversed(plan["levels"]):
@@ -141,10 +200,7 @@ def emulate(plan, blocks, fN):
             f = fr[fi]
             ld, m = f["m"] + f["u"], f["m"]
             w = np.zeros(ld)
-            for b in range(f["npanels"]):
-                rows, cs_b = lpanel(f, b)
-                nbb = min(NB, m - b * NB)
-                w[b * NB:b * NB + nbb] = rows[ld - cs_b, :nbb]
+            w[:m] = y_of(f)
             for n in nodes[f["node_off"] + f["n_s_nodes"]:f["node_off"] + f["n_nodes"]]:
                 w[n["pos"]:n["pos"] + n["size"]] = pN[n["pn_off"]:n["pn_off"] + n["size"]]
             if f["nzc"] > 0:
@@ -272,3 +328,42 @@ def test_split_backward_maps(monkeypatch, combined):
             assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
             off += len(f)
         assert off == len(x)
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_refinement_sweeps_solve_new_rhs(monkeypatch, split):
+    """The refinement's substitutions with the stored factor (forward sweep
+    with the children's update vectors, split U-row products, backward sweep
+    from the front vectors) solve a new right-hand side exactly as a dense
+    solver does, for single plans and the combined plan of a fused batch."""
+    from paper_1405_2810_amd.lrbms import solver_plan, solver_plan_batch
+    if split:
+        monkeypatch.setenv("LRBMS_BW_SPLIT_MIN", "1")
+    specs = [("tiny2d", 6, 2), ("small3d", 8, 4), ("cfg1", 12, 1), ("small2d", 70, 2)]
+    rng = np.random.default_rng(29)
+    probs, sizes, leaves, systems = [], [], [], []
+    for name, ne, leaf in specs:
+        p = make_problem(name)
+        nsub = int(np.prod([len(c) - 1 for c in p.cuts]))
+        sz = rng.integers(max(1, ne // 2), ne + 1, nsub)
+        probs.append(p)
+        sizes.append(sz)
+        leaves.append(leaf)
+        systems.append(_random_system(p, sz, rng))
+    plans = [solver_plan(p, sz, lf) for p, sz, lf in zip(probs, sizes, leaves)]
+    plans.append(solver_plan_batch(probs, sizes, leaves))
+    groups = [[s] for s in systems] + [systems]
+    for plan, group in zip(plans, groups):
+        blocks = np.concatenate([b for _, b, _ in group])
+        fN = np.concatenate([f for _, _, f in group])
+        _, (lpanel, Inv) = emulate(plan, blocks, fN, refine=True)
+        r = rng.standard_normal(len(fN))
+        V = _forward(plan, lpanel, Inv, r)
+        d = _backward(plan, lpanel, Inv, lambda f: V[f["voff"]:f["voff"] + f["m"]],
+                      np.full(len(fN), np.nan))
+        off = 0
+        for (A, _, _) in group:
+            n = A.shape[0]
+            ref = np.linalg.solve(A, r[off:off + n])
+            assert np.linalg.norm(d[off:off + n] - ref) <= 1e-10 * np.linalg.norm(ref)
+            off += n
