@@ -5,12 +5,16 @@ mobility + reduced assembly, reduced solve, pressure/flux reconstruction,
 saturation step + limiter, all through the C ABI of liblrbms.so, inputs
 resident in HBM.  Prints one JSON line on stdout (progress goes to stderr).
 
-Default workload: 2D 256x256 fine cells on the unit square, 16x16 coarse
-boxes of 16x16 cells, log-normal permeability (correlation length 0.05,
-sigma_logk 2), Corey exponents 2, viscosity ratio 5, local bases of size 25
-(1_E plus Gram-Schmidt of seeded smooth snapshot fields), FP64, the plain
+Default workload: 3D 60x220x85 fine cells (1.12 M) on 600x2200x170 m,
+6x22x5 coarse boxes of 10x10x17 cells, layered log-normal permeability
+(sigma_logk 3) with seeded high-permeability channels, Corey exponents 2,
+viscosity ratio 10, five-spot wells, local bases of size 40 (1_E plus
+Gram-Schmidt of seeded smooth snapshot fields), N = 26,400, FP64, the plain
 per-simulation path (sequential launches on one stream, no graph, no
-batching).
+batching).  The autotuner (untimed set-up) picks the reduced solver's shapes
+and keeps one refinement step in every reduced solve unless the unrefined
+solve's own error, measured on the device, is below 1e-13.  The 2D 256x256
+workload (16x16 boxes, N_E = 25) is timed after it for context.
 
 Passes, in order:
   warm-up      W untimed steps;
@@ -24,8 +28,11 @@ Passes, in order:
   context      the fine reference (Alg. 1 on the GPU, --fine-steps steps) and
                one run of the GPU offline stage (--offline), reported beside
                the metric;
-  cpu_baseline the FP64 CPU oracle's online step on a bounded sample of the
-               same workload (skipped with --no-cpu-baseline).
+  extra        the plain path on the --extra-config workload;
+  cpu_baseline the GPU's reduced solve against the oracle's solve of the same
+               system, then the FP64 CPU oracle's online step on a bounded
+               sample of the same workload at all cores and at one thread
+               (skipped with --no-cpu-baseline).
 """
 from __future__ import annotations
 
@@ -200,30 +207,112 @@ def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77):
     return out
 
 
-def cpu_baseline(p, snaps, s0, n_steps: int, mode: str):
-    """The FP64 CPU oracle's online step (same problem, bases built by the
-    oracle from the same snapshots) timed over n_steps from s0."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(p, snaps, s0, n_steps: int, threads: int):
+    """Seconds per online step of the oracle (DIRECT, a1-a7; bases built by
+    the oracle from the same snapshots, untimed) over n_steps from s0, with
+    the BLAS/OpenMP pools limited to `threads`."""
+    from threadpoolctl import threadpool_limits
     from oracle.fem import Grid
     from oracle.offline import local_bases
     from oracle.online import Model as OModel, online_step, DIRECT as O_DIRECT
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover - threadpoolctl is optional
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     g = Grid(p)
     phis = local_bases(g, p, snaps, method="gs", cap=p.ne_cap, unit=True)
     om = OModel(p, phis, None)
     s = np.asarray(s0, dtype=np.float64).copy()
-    online_step(om, s, O_DIRECT)          # first call: caches, imports
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        s = online_step(om, s, O_DIRECT)["s"]
-    dt = time.perf_counter() - t0
-    return {"value": n_steps / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_steps} consecutive online steps (DIRECT, a1-a7) of the same workload "
-                      f"from the same initial saturation, after one untimed step; "
-                      f"{dt:.1f} s of CPU time; BLAS threads = {threads}"}
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            s = online_step(om, s, O_DIRECT)["s"]
+        return (time.perf_counter() - t0) / n_steps
+
+
+def cpu_baseline(name: str, p, snaps, s0, n_steps: int):
+    """The FP64 CPU oracle's online step timed on the host, at all cores and
+    at one thread.  The 3D 60x220x85 workload takes minutes per oracle step,
+    so its sample is the same recipe on a slab of 2 of its 22 box rows
+    (60x20x85 cells, 6x2x5 boxes of 10x10x17 cells, N_E = 40, the five-spot
+    wells of the slab), one step, scaled by the ratio of boxes (660 / 60)."""
+    from synth import make_problem, random_saturation, smooth_fields
+    ncores = os.cpu_count() or 1
+    scale, what = 1.0, f"{n_steps} consecutive online steps of the same workload from the same state"
+    if name == "cfg3":
+        p = make_problem("cfg3", n=(60, 20, 85), L=(600.0, 200.0, 170.0), nc=(6, 2, 5))
+        snaps = smooth_fields(p, p.ne_cap + 4, np.random.default_rng(p.seed + 1))
+        s0 = random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6)
+        n_steps, scale = 1, 660.0 / 60.0
+        what = ("one online step of a 2-of-22-box-row slab of the workload (60x20x85 cells, "
+                "6x2x5 boxes, N_E = 40, same recipe), scaled by 660/60 boxes")
+    t_all = _oracle_steps(p, snaps, s0, n_steps, ncores) * scale
+    t_one = _oracle_steps(p, snaps, s0, n_steps, 1) * scale
+    return {"value": 1.0 / t_all, "unit": "solves/s", "cores": int(ncores), "kind": "oracle",
+            "one_thread": {"value": 1.0 / t_one, "unit": "solves/s", "cores": 1},
+            "cpu_model": cpu_model(),
+            "sample": f"{what} (DIRECT, a1-a7, FP64 NumPy/SciPy oracle; bases built untimed); "
+                      f"{t_all:.1f} s per full-workload step at {ncores} threads, {t_one:.1f} s at "
+                      f"1 thread; CPU: {cpu_model()}"}
+
+
+def solver_parity(gm, sat, mode):
+    """Relative L2 distance of the GPU's p_N (after its refinement) from the
+    oracle's solve of the same reduced system (the GPU's own A_N, f_N)."""
+    import torch
+    from oracle.online import solve_reduced
+    gm.assemble(sat, mode)
+    pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
+    gm.solve(pN)
+    blocks, f = gm.reduced_system()
+    x = solve_reduced(gm.sparse_reduced_matrix(blocks, lower=True), f)
+    got = pN.cpu().numpy()
+    return float(np.linalg.norm(got - x) / np.linalg.norm(x))
+
+
+def measure_plain(name: str, steps: int, warmup: int, autotune: int):
+    """The plain per-simulation path on another workload: ms per online step."""
+    import torch
+    from synth import make_problem, random_saturation
+    from paper_1405_2810_amd.lrbms import DIRECT
+    p = make_problem(name)
+    gm, _ = build_model(p, n_snap=p.ne_cap + 4, cap=p.ne_cap, seed=p.seed + 1)
+    st = torch.cuda.current_stream()
+    s_a = torch.as_tensor(random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6),
+                          dtype=torch.float64, device="cuda")
+    tune = gm.autotune(s_a, reps=10) if autotune else None
+    s_b = torch.zeros_like(s_a)
+    pN = torch.zeros(gm.info["N"], dtype=torch.float64, device="cuda")
+    flux = torch.zeros(gm.info["nface"], dtype=torch.float64, device="cuda")
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        gm.assemble(s_a, DIRECT, st)
+        gm.solve(pN, st)
+        gm.reconstruct_flux(pN, s_a, flux, None, st)
+        gm.transport_step(s_a, flux, s_b, None, st)
+        s_a, s_b = s_b, s_a
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    status = gm.status()
+    info = gm.info
+    gm.close()
+    if status < 0:
+        raise RuntimeError(f"device status error on {name}")
+    nc = [len(c) - 1 for c in p.cuts[:p.dim]]
+    log(f"[bench] {name}: {ms:.3f} ms/step ({1e3 / ms:.0f} solves/s)")
+    return {"workload": f"{name}: {p.dim}D {'x'.join(str(v) for v in p.n[:p.dim])} fine cells, "
+                        f"{'x'.join(str(v) for v in nc)} coarse boxes, N_E<={p.ne_cap}, plain path",
+            "N": info["N"], "ms_per_step": ms, "solves_per_s": 1e3 / ms, "solver_shapes": tune,
+            "cfl_warning": status == 1}
 
 
 def main():
@@ -231,14 +320,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--config", default="cfg3")
+    ap.add_argument("--extra-config", default="cfg2",
+                    help="a second workload timed on the plain path for context ('' skips)")
     ap.add_argument("--mode", default="direct", choices=["direct"])
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fine-steps", type=int, default=10,
+    ap.add_argument("--fine-steps", type=int, default=3,
                     help="steps of the fine reference (Alg. 1) timed for context; 0 skips")
-    ap.add_argument("--offline", type=int, default=1,
-                    help="1: time the GPU offline stage once for context")
+    ap.add_argument("--offline", type=int, default=-1,
+                    help="1: time the GPU offline stage once for context (-1: only for 2D "
+                         "workloads; the 3D one takes about a minute)")
     ap.add_argument("--ensemble", type=int, default=64,
                     help="members of the batched ensemble and serving passes; 0 skips both")
     ap.add_argument("--ensemble-steps", type=int, default=20)
@@ -246,6 +338,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick the reduced solver's shapes by timing them (untimed set-up)")
+    ap.add_argument("--refine", type=int, default=-1,
+                    help=">= 0: refinement steps of the reduced solve, set after the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 256 MiB (scale of the HBM counters)")
     args = ap.parse_args()
@@ -268,6 +362,8 @@ def main():
     from paper_1405_2810_amd.lrbms import DIRECT, AFFINE
 
     p = make_problem(args.config)
+    if args.offline < 0:
+        args.offline = 1 if p.dim == 2 else 0
     r = p.dim + 1
     log(f"[bench] config {args.config}: building model")
     t0 = time.time()
@@ -283,9 +379,14 @@ def main():
     tune = gm.autotune(s0, reps=10) if args.autotune else None
     if tune:
         log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']} "
-            f"backward split {tune['bw_split_min']}: "
+            f"backward split {tune['bw_split_min']}, unrefined error "
+            f"{tune['unrefined_error']:.1e} -> refinement steps {tune['refine']}: "
             f"{tune['us_per_solve']:.1f} us per solve (was {tune['us_before']:.1f}, "
             f"{tune['n_candidates']} shapes)")
+    refine_steps = tune["refine"] if tune else 1
+    if args.refine >= 0:
+        gm.set_refinement(args.refine)
+        refine_steps = args.refine
     s_a = s0.clone()
     s_b = torch.zeros_like(s_a)
     pN = torch.zeros(info["N"], dtype=torch.float64, device=dev)
@@ -327,6 +428,7 @@ def main():
     status = gm.status()
     if status < 0:
         raise RuntimeError("device status error in the timed region")
+    cfl_warning = status == 1
     log(f"[bench] timed: {ms:.3f} ms/step")
     # ---- latency pass ------------------------------------------------------
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
@@ -441,12 +543,24 @@ def main():
                     "(one slot)", **serve}
         for _, m in members:
             m.close()
-    # ---- CPU oracle baseline ----------------------------------------------
-    cpu = None
+    if args.extra_config:
+        extras[args.extra_config] = measure_plain(args.extra_config, args.steps, args.warmup,
+                                                  args.autotune)
+    # ---- CPU oracle baseline, and the GPU solve against the oracle's ------
+    cpu, parity = None, None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
-        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
-        cpu = cpu_baseline(p, snaps, s0_host, args.cpu_steps, args.mode)
-        log(f"[bench] cpu baseline: {cpu['value']:.3f} solves/s on {cpu['cores']} threads")
+        log("[bench] solver parity: the oracle's solve of the GPU's own reduced system")
+        parity = {"pN_rel_l2_vs_oracle_solve_of_same_system": solver_parity(gm, s0, mode),
+                  "refinement_steps": refine_steps,
+                  "unrefined_error_measured": tune["unrefined_error"] if tune else None,
+                  "note": "A_N/f_N parity with the oracle's own assembly and the end-to-end "
+                          "p_N bound (1e-10) are tested on the 256x256 workload and on the 3D "
+                          "workload's coarse grid at 30x110x40 (tests/gpu/test_fullsize.py)"}
+        log(f"[bench] solver parity {parity['pN_rel_l2_vs_oracle_solve_of_same_system']:.2e}")
+        log(f"[bench] cpu baseline: oracle ({args.config})")
+        cpu = cpu_baseline(args.config, p, snaps, s0_host, args.cpu_steps)
+        log(f"[bench] cpu baseline: {cpu['value']:.4f} solves/s on {cpu['cores']} threads, "
+            f"{cpu['one_thread']['value']:.4f} on 1 ({cpu['cpu_model']})")
     nc = [len(c) - 1 for c in p.cuts[:p.dim]]
     out = {
         "metric": "online pressure solves/s + p50/p99 latency vs plain GPU path at rel err<=1e-10",
@@ -472,6 +586,8 @@ def main():
                         "flux": float(parts[:, 2].mean()), "transport": float(parts[:, 3].mean())},
         "pressure_solves_per_s": 1e3 / float((parts[:, 0] + parts[:, 1]).mean()),
         "roofline": roof,
+        "parity": parity,
+        "cfl_warning": cfl_warning,
         "kernels": {k: {"avg_launch_us": round(v["avg_launch_us"], 3),
                         "launches_per_step": v["launches_per_step"],
                         "GBs": round(v["GBs"], 2), "TFLOPs": round(v["TFLOPs"], 4)}

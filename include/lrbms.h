@@ -345,15 +345,26 @@ int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
  * Assembles the reduced system of d_sat (device, [r*ncell]; DIRECT), then for
  * every candidate builds the solver plan, times reps solves (after two
  * untimed ones) with HIP events on the default stream, and keeps the fastest
- * plan in the model.  The report (nullable) gives the chosen shapes, its time
- * per solve, the time of the plan the model had before, and the number of
- * candidates timed.  Synchronous; allocates; results of later solves differ
- * from before only by rounding (another elimination order).
+ * plan in the model.  Then it measures the error of the unrefined reduced
+ * solve on that system (the relative size of one refinement step's
+ * correction) and sets the model's refinement steps to 0 when it is below
+ * 1e-13, else keeps them (at least 1).  The report (nullable) gives the
+ * chosen shapes, its time per solve, the time of the plan the model had
+ * before, the number of candidates timed, the measured unrefined error and
+ * the refinement steps kept.  Synchronous; allocates; results of later
+ * solves differ from before only by rounding (another elimination order, or
+ * no refinement step).
  * LRBMS_E_STATE while the model belongs to a batch or server.                 */
 typedef struct lrbms_tune_report {
   int32_t leaf_max, split_min;   /* split_min: 0 = never split */
   int32_t n_candidates, bw_split_min;   /* bw_split_min: 0 = never split */
   double us_per_solve, us_before;
+  /* error of the unrefined solve, measured as |p_1 - p_0| / |p_1| for the
+   * solutions without (p_0) and with one refinement step (p_1) on the tuning
+   * state; the model keeps its refinement steps unless this is below 1e-13
+   * (three orders under the 1e-10 parity bound), then it solves unrefined  */
+  double unrefined_error;
+  int32_t refine, pad;
 } lrbms_tune_report;
 int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
                          lrbms_tune_report* report);

@@ -25,7 +25,7 @@ const char* kernel_kind_name(int kind) {
       "k_reduce_box",     "k_asm_iface",    "k_front_asm",      "k_front_factor0",
       "k_front_step",     "k_front_backward", "k_front_update", "k_front_bw_gemv",
       "k_reconstruct",    "k_flux",           "k_transport",    "k_limiter",
-      "k_residual",       "k_front_forward",  "k_front_fw_gemv"};
+      "k_residual",       "k_front_forward",  "k_front_fw_gemv",  "k_front_schur"};
   return (kind >= 0 && kind < KK_COUNT) ? names[kind] : "?";
 }
 
@@ -203,16 +203,16 @@ Model::~Model() {
   assemble_free(asm_layout);
 }
 
-// Fill geometry, boxes and interfaces (host side only).
-static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) {
-  Geom& g = M.g;
+// Geometry and physics constants of a checked problem (host side only, no
+// allocation); nc receives the coarse box counts.
+static void fill_geom(Geom& g, int nc[3], const lrbms_problem* p) {
   std::memset(&g, 0, sizeof(g));
   g.dim = p->dim;
   g.r = p->dim + 1;
   for (int a = 0; a < 3; ++a) {
     g.n[a] = a < p->dim ? p->n[a] : 1;
     g.h[a] = a < p->dim ? p->len[a] / p->n[a] : 1.0;
-    M.nc[a] = a < p->dim ? p->nc[a] : 1;
+    nc[a] = a < p->dim ? p->nc[a] : 1;
   }
   g.ncell = g.n[0] * g.n[1] * g.n[2];
   g.vol = 1.0;
@@ -278,6 +278,12 @@ static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) 
     }
     g.cfl_coef = g.dt * mx;
   }
+}
+
+// Fill geometry, boxes and interfaces (host side only).
+static int setup_layout(Model& M, const lrbms_problem* p, const int32_t* sizes) {
+  Geom& g = M.g;
+  fill_geom(g, M.nc, p);
   // boxes
   M.subs.clear();
   long long phi_off = 0, blk = 0;
@@ -1441,6 +1447,31 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
       rep.bw_split_min = bw > INT32_MAX ? 0 : (int32_t)bw;
     }
     rep.us_per_solve = std::min(best, rep.us_before);
+    // the unrefined solve's own error: one refinement step's correction
+    {
+      DevArray p0;
+      if (!p0.alloc((size_t)std::max(M->N, 1))) return LRBMS_E_OOM;
+      const int keep = std::max(M->refine, 1);
+      if (!hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, p0.p, M->d_status, 0, 0),
+                  "solve") ||
+          !hip_ok(solver_factor_solve(M->plan, M->sdev, M->d_blocks, M->d_fN, pN.p, M->d_status, 0, 1),
+                  "solve"))
+        return LRBMS_E_HIP;
+      std::vector<double> a(M->N), c(M->N);
+      if (!hip_ok(hipMemcpy(a.data(), p0.p, a.size() * sizeof(double), hipMemcpyDeviceToHost),
+                  "copy") ||
+          !hip_ok(hipMemcpy(c.data(), pN.p, c.size() * sizeof(double), hipMemcpyDeviceToHost),
+                  "copy"))
+        return LRBMS_E_HIP;
+      double dn = 0.0, cn = 0.0;
+      for (int i = 0; i < M->N; ++i) {
+        dn += (c[i] - a[i]) * (c[i] - a[i]);
+        cn += c[i] * c[i];
+      }
+      rep.unrefined_error = cn > 0.0 ? std::sqrt(dn / cn) : 0.0;
+      M->refine = (std::isfinite(rep.unrefined_error) && rep.unrefined_error < 1e-13) ? 0 : keep;
+      rep.refine = M->refine;
+    }
     if (report) *report = rep;
     M->last_stream = nullptr;
     return LRBMS_OK;
@@ -1523,6 +1554,14 @@ static std::vector<int64_t> flatten_plan(const SolverPlan& plan) {
     for (auto& it : plan.bw_items[h]) {
       int64_t v[2] = {it.front, it.chunk};
       o.insert(o.end(), v, v + 2);
+    }
+  }
+  // deferred Schur complements: per level its (front, ti, tj) tiles
+  for (int h = 0; h < H; ++h) {
+    o.push_back((int64_t)plan.schur_items[h].size());
+    for (auto& it : plan.schur_items[h]) {
+      int64_t v[3] = {it.front, it.ti, it.tj};
+      o.insert(o.end(), v, v + 3);
     }
   }
   return o;

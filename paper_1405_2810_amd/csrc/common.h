@@ -188,6 +188,13 @@ int fine_energy_setup(FineSolver* S, double* mom, const double* field);
 int fine_energy_diff(FineSolver* S, const double* a, const double* b, double* out);
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps);
+// The time of flight on caller-given work memory (no allocation):
+// tof_scratch_doubles(g) doubles carved by tof_carve.
+struct TofBufs { double *Minv, *C, *b, *other, *pc, *ps, *red; };
+size_t tof_scratch_doubles(const Geom& g);
+void tof_carve(const Geom& g, double* base, TofBufs& B);
+int tof_solve_bufs(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
+                   int* d_status, int* sweeps, const TofBufs& B);
 // Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and
 // the number of workgroups of the least-squares projection.
 int assemble_cols(int max_ne);

@@ -31,6 +31,7 @@ enum KernelKind {
   KK_RESIDUAL,
   KK_FRONT_FORWARD,
   KK_FRONT_FW_GEMV,
+  KK_FRONT_SCHUR,
   KK_COUNT
 };
 

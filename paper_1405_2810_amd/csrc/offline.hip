@@ -1183,41 +1183,80 @@ int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind,
                                          iters, relres);
 }
 
+// Largest entries of two partial arrays (one workgroup): out[0] = max a,
+// out[1] = max b; a NaN anywhere gives NaN.
+__global__ __launch_bounds__(kBlk) void k_max_pair(const double* __restrict__ a,
+                                                   const double* __restrict__ b, int n,
+                                                   double* __restrict__ out) {
+  __shared__ double ra[kBlk], rb[kBlk];
+  double ma = 0.0, mb = 0.0;
+  bool nan = false;
+  for (int i = threadIdx.x; i < n; i += kBlk) {
+    const double x = a[i], y = b[i];
+    nan = nan || x != x || y != y;
+    ma = fmax(ma, x);
+    mb = fmax(mb, y);
+  }
+  ra[threadIdx.x] = nan ? NAN : ma;
+  rb[threadIdx.x] = mb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double xa = 0.0, xb = 0.0;
+    bool bad = false;
+    for (int i = 0; i < kBlk; ++i) {
+      bad = bad || ra[i] != ra[i];
+      xa = fmax(xa, ra[i]);
+      xb = fmax(xb, rb[i]);
+    }
+    out[0] = bad ? NAN : xa;
+    out[1] = xb;
+  }
+}
+
+size_t tof_scratch_doubles(const Geom& g) {
+  const size_t R = g.dim + 1, nc = g.ncell, nb = (nc + kBlk - 1) / kBlk;
+  return R * R * nc + 2 * g.dim * R * R * nc + 2 * R * nc + 2 * nb + 2;
+}
+
+void tof_carve(const Geom& g, double* base, TofBufs& B) {
+  const size_t R = g.dim + 1, nc = g.ncell, nb = (nc + kBlk - 1) / kBlk;
+  B.Minv = base;
+  B.C = B.Minv + R * R * nc;
+  B.b = B.C + 2 * g.dim * R * R * nc;
+  B.other = B.b + R * nc;
+  B.pc = B.other + R * nc;
+  B.ps = B.pc + nb;
+  B.red = B.ps + nb;
+}
+
+// The sweeps on given work buffers (no allocation): set-up of the cell
+// blocks, then block-Jacobi sweeps; every 16 sweeps the largest change and
+// the largest coefficient come back to the host (two doubles).
 template <int D>
 static int tof_solve_t(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
-                       int* d_status, int* sweeps) {
+                       int* d_status, int* sweeps, const TofBufs& B) {
   constexpr int R = D + 1;
   const int nc = g.ncell;
   const size_t n = (size_t)R * nc;
   const int nb = blocks_for(nc);
   hipStream_t st = 0;
-  DevBuf Minv, C, b, other, pc, ps;
-  if (!Minv.alloc((size_t)R * R * nc) || !C.alloc((size_t)2 * D * R * R * nc) || !b.alloc(n) ||
-      !other.alloc(n) || !pc.alloc(nb) || !ps.alloc(nb))
-    return LRBMS_E_OOM;
-  hipLaunchKernelGGL(k_tof_setup<D>, dim3(nb), dim3(kBlk), 0, st, g, d_flux, Minv.p, C.p, b.p,
+  hipLaunchKernelGGL(k_tof_setup<D>, dim3(nb), dim3(kBlk), 0, st, g, d_flux, B.Minv, B.C, B.b,
                      d_status);
   if (hipMemsetAsync(d_tau, 0, n * sizeof(double), st) != hipSuccess) return LRBMS_E_HIP;
   double* cur = d_tau;
-  double* nxt = other.p;
-  std::vector<double> hc(nb), hs(nb);
+  double* nxt = B.other;
   int it = 0;
   bool done = false;
   for (; it < maxit && !done; ++it) {
-    hipLaunchKernelGGL(k_tof_sweep<D>, dim3(nb), dim3(kBlk), 0, st, g, Minv.p, C.p, b.p, cur, nxt,
-                       pc.p, ps.p);
+    hipLaunchKernelGGL(k_tof_sweep<D>, dim3(nb), dim3(kBlk), 0, st, g, B.Minv, B.C, B.b, cur, nxt,
+                       B.pc, B.ps);
     std::swap(cur, nxt);
     if ((it + 1) % 16 == 0 || it + 1 == maxit) {
-      if (hipMemcpy(hc.data(), pc.p, nb * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(hs.data(), ps.p, nb * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        return LRBMS_E_HIP;
-      double mc = 0.0, ms = 0.0;
-      for (int i = 0; i < nb; ++i) {
-        mc = std::max(mc, hc[i]);
-        ms = std::max(ms, hs[i]);
-      }
-      if (!std::isfinite(mc) || !std::isfinite(ms)) return LRBMS_E_NONFINITE;
-      done = mc <= tol * ms;
+      hipLaunchKernelGGL(k_max_pair, dim3(1), dim3(kBlk), 0, st, B.pc, B.ps, nb, B.red);
+      double h[2];
+      if (hipMemcpy(h, B.red, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return LRBMS_E_HIP;
+      if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return LRBMS_E_NONFINITE;
+      done = h[0] <= tol * h[1];
     }
   }
   if (cur != d_tau &&
@@ -1228,10 +1267,19 @@ static int tof_solve_t(const Geom& g, const double* d_flux, double tol, int maxi
   return done ? LRBMS_OK : LRBMS_E_STATE;
 }
 
+int tof_solve_bufs(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
+                   int* d_status, int* sweeps, const TofBufs& B) {
+  return g.dim == 2 ? tof_solve_t<2>(g, d_flux, tol, maxit, d_tau, d_status, sweeps, B)
+                    : tof_solve_t<3>(g, d_flux, tol, maxit, d_tau, d_status, sweeps, B);
+}
+
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps) {
-  return g.dim == 2 ? tof_solve_t<2>(g, d_flux, tol, maxit, d_tau, d_status, sweeps)
-                    : tof_solve_t<3>(g, d_flux, tol, maxit, d_tau, d_status, sweeps);
+  DevBuf work;
+  if (!work.alloc(tof_scratch_doubles(g))) return LRBMS_E_OOM;
+  TofBufs B;
+  tof_carve(g, work.p, B);
+  return tof_solve_bufs(g, d_flux, tol, maxit, d_tau, d_status, sweeps, B);
 }
 
 }  // namespace lrbms

@@ -19,8 +19,12 @@
 //             diagonal tile;
 //   step      one launch per panel: every tile workgroup forms its rows of L
 //             (F Linv^T, kept in a separate buffer), and applies the trailing
-//             update F(ti,tj) -= L(ti) L(tj)^T; the workgroup of the next
-//             diagonal tile factors it (look-ahead);
+//             update F(ti,tj) -= L(ti) L(tj)^T to the columns of S; the
+//             workgroup of the next diagonal tile factors it (look-ahead);
+//   schur     after the last panel, the U x U block and the right-hand-side
+//             row's U part in one product with all m columns of L_US
+//             (one 64 x 64 output tile per workgroup, FP64 MFMA), instead of
+//             one rank-64 update per panel;
 //   backward  one workgroup per front, from the root down, with the stored
 //             tile inverses.
 // Diagonal tiles are factored by a 16-wide blocked Cholesky: the 16 x 16
@@ -85,7 +89,14 @@ __host__ __device__ inline long long lpanel_base(const FrontD& f, int b) {
 struct AsmSrc { long long so; int rs, cs, kind, pad; };
 struct AsmItem { int front, dr, dc, nr, nc, diag, nsrc, pad; AsmSrc src[3]; };
 // One tile of the fused panel step; tj = -1: rows only (no trailing columns).
+// The trailing columns of a step are the front's S columns only: the U x U
+// block and the right-hand-side row's U part are updated once, after the
+// last panel, by the deferred Schur complement (SchurItem).
 struct StepItem { int front, panel, ti, tj; };
+// One 64 x 64 output tile of a front's deferred Schur complement: rows
+// m + 64 ti .. (U rows and the right-hand-side row), columns m + 64 tj ..
+// (U columns), tj <= ti.
+struct SchurItem { int front, ti, tj, pad; };
 
 struct SolverPlan {
   std::vector<FrontD> fronts;
@@ -101,6 +112,7 @@ struct SolverPlan {
   // updates, which read both L tiles from the L store instead of forming them
   std::vector<std::vector<std::vector<StepItem>>> upd_items;   // [level][panel]
   std::vector<std::vector<BwItem>> bw_items;                    // [level]
+  std::vector<std::vector<SchurItem>> schur_items;              // [level]
   std::vector<int> urow_pn;
   // residual plan (boxes in p_N order) and the number of reduced unknowns
   std::vector<ResBox> rboxes;
@@ -113,6 +125,7 @@ struct SolverPlan {
   std::vector<double> asm_flops, asm_bytes, f0_flops, f0_bytes, bw_flops, bw_bytes;  // [level]
   std::vector<double> bwg_flops, bwg_bytes;   // split backward products [level]
   std::vector<double> fw_flops, fw_bytes;     // forward substitution with a new right-hand side [level]
+  std::vector<double> schur_flops, schur_bytes;   // deferred Schur complements [level]
   double res_flops = 0.0, res_bytes = 0.0;    // residual of the refinement
   std::vector<std::vector<double>> step_flops, step_bytes;                           // [level][panel]
   std::vector<std::vector<double>> upd_flops, upd_bytes;                             // [level][panel]
@@ -161,6 +174,7 @@ struct SolverDev {
   std::vector<std::vector<StepItem*>> step_items;
   std::vector<std::vector<StepItem*>> upd_items;
   std::vector<BwItem*> bw_items;
+  std::vector<SchurItem*> schur_items;
   int* urow_pn = nullptr;
   ResBox* rboxes = nullptr;
   ResNb* rnbs = nullptr;

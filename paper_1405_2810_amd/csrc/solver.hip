@@ -346,7 +346,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
       for (int b = 0; b < d.npanels; ++b) {
         const int cs = b * kNB + std::min(kNB, d.m - b * kNB);
         const int nrt = (ld + 1 - cs + kNB - 1) / kNB;
-        const int nct = (ld - cs + kNB - 1) / kNB;
+        const int nct = (d.m - cs + kNB - 1) / kNB;   // trailing S columns only
         for (int ti = 0; ti < nrt; ++ti) {
           if (nct == 0) {
             plan.step_items[h][b].push_back(StepItem{p, b, ti, -1});
@@ -360,6 +360,17 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   }
   plan.upd_items.assign(H, {});
   for (int h = 0; h < H; ++h) plan.upd_items[h].assign(plan.step_items[h].size(), {});
+  // deferred Schur complements: the lower tiles of (U + rhs row) x U
+  plan.schur_items.assign(H, {});
+  for (int h = 0; h < H; ++h)
+    for (int p : plan.level_fronts[h]) {
+      const FrontD& d = plan.fronts[p];
+      if (d.u == 0) continue;
+      const int nrt = (d.u + 1 + kNB - 1) / kNB, nct = (d.u + kNB - 1) / kNB;
+      for (int ti = 0; ti < nrt; ++ti)
+        for (int tj = 0; tj <= std::min(ti, nct - 1); ++tj)
+          plan.schur_items[h].push_back(SchurItem{p, ti, tj, 0});
+    }
   split_steps(plan, split_min < 0 ? step_split_min() : split_min);
   assign_backward_split(plan);
   // algorithmic figures per launch: Cholesky arithmetic of the work each
@@ -374,6 +385,8 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
   plan.bwg_bytes.assign(H, 0.0);
   plan.fw_flops.assign(H, 0.0);
   plan.fw_bytes.assign(H, 0.0);
+  plan.schur_flops.assign(H, 0.0);
+  plan.schur_bytes.assign(H, 0.0);
   plan.step_flops.assign(H, {});
   plan.step_bytes.assign(H, {});
   plan.upd_flops.assign(H, {});
@@ -396,13 +409,15 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
       plan.f0_bytes[h] += 8.0 * (nb0 * (nb0 + 1) / 2 + nb0 * nb0);
       for (int b = 0; b < d.npanels; ++b) {
         const double nb = std::min(kNB, d.m - b * kNB);
-        const double cs = b * kNB + nb, t = ld - cs;
+        const double cs = b * kNB + nb, t = ld - cs, sc = d.m - cs;
         const double nb1 = (b + 1 < d.npanels) ? std::min(kNB, d.m - (int)cs) : 0.0;
-        // L rows, then trailing update and the next diagonal tile; a split
-        // step counts them in its two launches
+        // L rows, then the trailing update of the S columns (the lower
+        // trapezoid of t + 1 rows by sc columns) and the next diagonal tile;
+        // a split step counts them in its two launches
         const double fl = (t + 1) * nb * nb, by = 8.0 * (2.0 * (t + 1) * nb + nb * nb);
-        const double fu = t * (t + 1) * nb + 2.0 * t * nb + 2.0 * nb1 * nb1 * nb1 / 3.0;
-        const double bu = 8.0 * (t * (t + 1) + 2.0 * t + nb1 * nb1);
+        const double ent = sc * (t + 1) - sc * (sc - 1) / 2.0;
+        const double fu = 2.0 * nb * ent + 2.0 * nb1 * nb1 * nb1 / 3.0;
+        const double bu = 8.0 * (2.0 * ent + nb1 * nb1);
         const bool split = !plan.upd_items[h][b].empty();
         plan.step_flops[h][b] += split ? fl : fl + fu;
         plan.step_bytes[h][b] += split ? by : by + bu;
@@ -410,6 +425,13 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
           plan.upd_flops[h][b] += fu;
           plan.upd_bytes[h][b] += bu;
         }
+      }
+      // deferred Schur complement: the lower part of (U + rhs row) x U read
+      // and written once, L_US and the rhs row's S part read once
+      if (d.u > 0) {
+        const double m = d.m, u = d.u, ent = u * (u + 3) / 2.0;
+        plan.schur_flops[h] += 2.0 * m * ent;
+        plan.schur_bytes[h] += 8.0 * (2.0 * ent + (u + 1) * m);
       }
       // forward substitution of a new right-hand side (refinement): the
       // same entries of L as the backward, read once
@@ -784,7 +806,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
   const bool upd = it.tj >= 0;
   const int C0 = cs + (upd ? it.tj : 0) * kNB;
-  const int ncl = upd ? (int)min((long long)kNB, ld - C0) : 0;
+  const int ncl = upd ? min(kNB, f.m - C0) : 0;   // S columns only
   // loads: L_panel^{-1} (row-major), the panel columns of tile row ti, and the
   // F tile (ti, tj) this workgroup updates (kept in registers)
   // (all loads are issued before the first LDS store, so their latencies overlap)
@@ -1137,24 +1159,15 @@ __global__ __launch_bounds__(256) void k_residual(const ResBox* __restrict__ box
   }
 }
 
-// w[R0 + i] -= sum_k T[i][k] y[k] for the rows i < nr of a 64 x 64 tile staged
-// in LDS (zero beyond its columns), y = w[c0 ..]: four partial sums per row,
-// one per wave, joined in a fixed order.
-__device__ __forceinline__ void tile_rows_sub(Tile* T, double* w, int c0, int nb, int R0, int nr,
-                                              double (*red)[kNB]) {
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int k = 16 * g + t;
-    s = fma(T[lane][k], k < nb ? w[c0 + k] : 0.0, s);
-  }
-  red[g][lane] = s;
-  __syncthreads();
-  if (threadIdx.x < nr)
-    w[R0 + threadIdx.x] -= (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                           (red[2][threadIdx.x] + red[3][threadIdx.x]);
-  __syncthreads();
+// Row-block products of the substitutions, four lanes per row: lane l of wave
+// g takes row 16 g + l / 4 of a 64-row block and the 16 columns 16 (l % 4) ..
+// of a 64-column panel (contiguous in the panel-major L store, so the four
+// lanes of a row read 128 contiguous bytes each); the four partial sums of a
+// row are joined by two lane exchanges.
+__device__ __forceinline__ double quad_sum(double s) {
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  return s;
 }
 
 // Forward substitution L y = r of a new right-hand side, one workgroup per
@@ -1173,10 +1186,9 @@ __global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ l
                                                        const double* __restrict__ r,
                                                        double* __restrict__ V) {
   extern __shared__ double w[];   // m + u values
-  __shared__ Tile T[kNB];
-  __shared__ double red[4][kNB];
   const FrontD f = fronts[list[blockIdx.x]];
   const int m = f.m, ld = m + f.u, np = f.npanels, tid = threadIdx.x;
+  const int lane = tid & 63, g = tid >> 6, rr = 16 * g + (lane >> 2), seg = 16 * (lane & 3);
   for (int i = tid; i < ld; i += blockDim.x) w[i] = 0.0;
   __syncthreads();
   for (int n = 0; n < f.n_s_nodes; ++n) {
@@ -1196,97 +1208,71 @@ __global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ l
   const int rows_end = f.nzc > 0 ? m : ld;
   for (int b = 0; b < np; ++b) {
     const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
-    const double* Ip = Inv + f.inv_off + (long long)b * kNB * kNB;
+    // y_b = Linv w_b (row rr of the tile inverse, masked to its lower part)
     {
-      double v[16];
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
-        v[p] = (i < nb && k <= i) ? Ip[idx] : 0.0;
-      }
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const int idx = tid + 256 * p;
-        T[idx >> 6][idx & 63] = v[p];
-      }
-    }
-    __syncthreads();
-    // y_b = Linv w_b: the same partial sums, written instead of subtracted
-    {
-      const int lane = tid & 63, g = tid >> 6;
+      const double* Ir = Inv + f.inv_off + (long long)b * kNB * kNB + (long long)rr * kNB + seg;
       double sacc = 0.0;
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
-        const int k = 16 * g + t;
-        sacc = fma(T[lane][k], k < nb ? w[c0 + k] : 0.0, sacc);
+        const int k = seg + t;
+        const bool on = rr < nb && k <= rr;
+        sacc = fma(on ? Ir[t] : 0.0, on ? w[c0 + k] : 0.0, sacc);
       }
-      red[g][lane] = sacc;
-      __syncthreads();
-      if (tid < nb) w[c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+      sacc = quad_sum(sacc);
+      __syncthreads();   // every lane has read w_b
+      if ((lane & 3) == 0 && rr < nb) w[c0 + rr] = sacc;
       __syncthreads();
     }
-    const double* Lb = Lpan + lpanel_base(f, b);
-    for (int R0 = cs; R0 < rows_end; R0 += kNB) {
-      const int nr = min(kNB, rows_end - R0);
-      double v[16];
+    // w_R -= L(R, panel b) y_b for the rows after the panel
+    const double* Lb = Lpan + lpanel_base(f, b) + seg;
+    double y[16];
 #pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
-        v[p] = (i < nr && k < nb) ? Lb[(long long)(R0 - cs + i) * kNB + k] : 0.0;
-      }
+    for (int t = 0; t < 16; ++t) y[t] = (seg + t < nb) ? w[c0 + seg + t] : 0.0;
+#pragma unroll 2
+    for (int R0 = cs; R0 < rows_end; R0 += kNB) {   // uniform over the workgroup
+      const int R = R0 + rr;
+      const bool on = R < rows_end;
+      const double* Lr = Lb + (long long)(on ? R - cs : 0) * kNB;
+      double sacc = 0.0;
 #pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        const int idx = tid + 256 * p;
-        T[idx >> 6][idx & 63] = v[p];
-      }
-      __syncthreads();
-      tile_rows_sub(T, w, c0, nb, R0, nr, red);
+      for (int t = 0; t < 16; ++t) sacc = fma(on ? Lr[t] : 0.0, y[t], sacc);
+      sacc = quad_sum(sacc);
+      if ((lane & 3) == 0 && on) w[R] -= sacc;
     }
+    __syncthreads();
   }
   for (int i = tid; i < ld; i += blockDim.x) V[f.voff + i] = w[i];
 }
 
 // U rows of a split front's forward substitution: for 64 U rows (one work
 // item) V[voff + m + r] -= sum_j L_US(r, j) y_S(j), y_S = V[voff ..], the
-// columns panel by panel (tiles staged in LDS).
+// panels one after another, four lanes per row.
 __global__ __launch_bounds__(256) void k_front_fw_gemv(const BwItem* __restrict__ items,
                                                        const FrontD* __restrict__ fronts,
                                                        const double* __restrict__ Lpan,
                                                        double* __restrict__ V) {
-  __shared__ Tile T[kNB];
-  __shared__ double red[4][kNB];
   const BwItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
   const int m = f.m, r0 = kNB * it.chunk, nr = min(kNB, f.u - r0), tid = threadIdx.x;
-  const int lane = tid & 63, g = tid >> 6;
+  const int lane = tid & 63, g = tid >> 6, rr = 16 * g + (lane >> 2), seg = 16 * (lane & 3);
+  const bool on = rr < nr;
   const double* y = V + f.voff;
   double sacc = 0.0;
   for (int b = 0; b < f.npanels; ++b) {
     const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
-    const double* Lb = Lpan + lpanel_base(f, b) + (long long)(m - cs + r0) * kNB;
-    double v[16];
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
-      v[p] = (i < nr && k < nb) ? Lb[(long long)i * kNB + k] : 0.0;
-    }
-    __syncthreads();   // the previous panel's reads of T are done
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int idx = tid + 256 * p;
-      T[idx >> 6][idx & 63] = v[p];
-    }
-    __syncthreads();
+    const double* Lr = Lpan + lpanel_base(f, b) + (long long)(m - cs + r0 + (on ? rr : 0)) * kNB + seg;
+    double a[16], yv[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      const int k = 16 * g + t;
-      sacc = fma(T[lane][k], k < nb ? y[c0 + k] : 0.0, sacc);
+      const bool k_on = seg + t < nb;
+      a[t] = (on && k_on) ? Lr[t] : 0.0;
+      yv[t] = k_on ? y[c0 + seg + t] : 0.0;
     }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sacc = fma(a[t], yv[t], sacc);
   }
-  red[g][lane] = sacc;
-  __syncthreads();
-  if (tid < nr)
-    V[f.voff + m + r0 + tid] -= (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  sacc = quad_sum(sacc);
+  if ((lane & 3) == 0 && on) V[f.voff + m + r0 + rr] -= sacc;
 }
 
 // Split every step of at least split_min items that still holds trailing
@@ -1359,6 +1345,9 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   out.bwg_bytes.assign(H, 0.0);
   out.fw_flops.assign(H, 0.0);
   out.fw_bytes.assign(H, 0.0);
+  out.schur_flops.assign(H, 0.0);
+  out.schur_bytes.assign(H, 0.0);
+  out.schur_items.assign(H, {});
   out.step_flops.assign(H, {});
   out.step_bytes.assign(H, {});
   out.upd_items.assign(H, {});
@@ -1453,6 +1442,12 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
       out.bwg_bytes[h] += P.bwg_bytes[h];
       out.fw_flops[h] += P.fw_flops[h];
       out.fw_bytes[h] += P.fw_bytes[h];
+      out.schur_flops[h] += P.schur_flops[h];
+      out.schur_bytes[h] += P.schur_bytes[h];
+      for (SchurItem it : P.schur_items[h]) {
+        it.front += fbase;
+        out.schur_items[h].push_back(it);
+      }
     }
   }
   // the members' steps side by side can be large enough to split (the
@@ -1541,6 +1536,14 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
     }
     if (plan.upd_items[h].size() != plan.step_items[h].size()) return false;
     if ((int)plan.bw_items.size() != plan.nlevels) return false;
+    if ((int)plan.schur_items.size() != plan.nlevels) return false;
+    for (const SchurItem& it : plan.schur_items[h]) {
+      if (it.front < 0 || it.front >= nf) return false;
+      const FrontD& f = plan.fronts[it.front];
+      if (f.u < 1 || it.ti < 0 || it.tj < 0 || it.tj > it.ti || kNB * it.ti > f.u ||
+          kNB * it.tj >= f.u)
+        return false;
+    }
     for (const BwItem& it : plan.bw_items[h])
       if (it.front < 0 || it.front >= nf || it.chunk < 0 || it.chunk >= plan.fronts[it.front].nzc)
         return false;
@@ -1587,7 +1590,7 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
   double* Fp = F + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
   const int R0 = cs + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
-  const int C0 = cs + it.tj * kNB, ncl = (int)min((long long)kNB, ld - C0);
+  const int C0 = cs + it.tj * kNB, ncl = min(kNB, f.m - C0);   // S columns only
   const bool diag = it.tj == it.ti;
   const double* Lp = Lb + lpanel_base(f, it.panel);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
@@ -1642,6 +1645,79 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
                   status);
 }
 
+// Deferred Schur complement of one front, one 64 x 64 output tile per
+// workgroup: F(R, C) -= sum_k L(R, k) L(C, k) over the m columns of S, rows R
+// of U and the right-hand-side row, columns C of U, the product accumulated
+// on FP64 MFMA over the front's panels (L tiles from the panel-major store,
+// the next panel's loads in flight during the current panel's products),
+// then one read-modify-write of the tile.
+__global__ __launch_bounds__(256) void k_front_schur(const SchurItem* __restrict__ items,
+                                                     const FrontD* __restrict__ fronts,
+                                                     double* __restrict__ F,
+                                                     const double* __restrict__ Lb) {
+  __shared__ Tile SA[kNB];
+  __shared__ Tile SB[kNB];
+  const SchurItem it = items[blockIdx.x];
+  const FrontD f = fronts[it.front];
+  const long long ld = f.m + f.u, lda = ld + 1;
+  double* Fp = F + f.off;
+  const int m = f.m;
+  const int R0 = m + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
+  const int C0 = m + it.tj * kNB, ncl = (int)min((long long)kNB, ld - C0);
+  const bool diag = it.ti == it.tj;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  double la[16], lb[16];
+  auto load = [&](int b) {
+    const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
+    const double* Lp = Lb + lpanel_base(f, b);
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p, li = idx >> 6, lk = idx & 63;
+      la[p] = (li < nr && lk < nb) ? Lp[(long long)(R0 - cs + li) * kNB + lk] : 0.0;
+      lb[p] = (!diag && li < ncl && lk < nb) ? Lp[(long long)(C0 - cs + li) * kNB + lk] : 0.0;
+    }
+  };
+  d4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int b = 0; b < f.npanels; ++b) {
+    if (b > 0) __syncthreads();   // every wave is done with the previous tiles
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p;
+      SA[idx >> 6][idx & 63] = la[p];
+      SB[idx >> 6][idx & 63] = lb[p];
+    }
+    __syncthreads();
+    if (b + 1 < f.npanels) load(b + 1);
+    const Tile* Bt = diag ? SA : SB;
+    const int nc = (min(kNB, m - b * kNB) + 3) >> 2;
+    for (int c = 0; c < nc; ++c) {
+      const double a = SA[16 * w + r][4 * c + q];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], acc[cb]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) SA[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
+  __syncthreads();
+  double fold[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
+    fold[p] = (i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
+    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = fold[p] - SA[i][k];
+  }
+}
+
 // ============================ upload / launch ================================
 template <typename T>
 static bool upload(const std::vector<T>& v, T** out, long long& bytes) {
@@ -1674,8 +1750,11 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
         return false;
   }
   dev.bw_items.assign(H, nullptr);
+  dev.schur_items.assign(H, nullptr);
   for (int h = 0; h < H; ++h)
-    if (!upload(plan.bw_items[h], &dev.bw_items[h], b)) return false;
+    if (!upload(plan.bw_items[h], &dev.bw_items[h], b) ||
+        !upload(plan.schur_items[h], &dev.schur_items[h], b))
+      return false;
   if (!upload(plan.urow_pn, &dev.urow_pn, b) || !upload(plan.rboxes, &dev.rboxes, b) ||
       !upload(plan.rnbs, &dev.rnbs, b))
     return false;
@@ -1711,6 +1790,7 @@ void solver_free(SolverDev& dev) {
   for (auto& v : dev.upd_items)
     for (auto p : v) f(p);
   for (auto p : dev.bw_items) f(p);
+  for (auto p : dev.schur_items) f(p);
   f(dev.urow_pn);
   f(dev.rboxes);
   f(dev.rnbs);
@@ -1780,6 +1860,13 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                            dev.fronts, dev.F, dev.L, dev.Inv, status);
         ktimer_end(plan.upd_flops[h][p], plan.upd_bytes[h][p], st);
       }
+    }
+    const int ns = (int)plan.schur_items[h].size();
+    if (ns) {
+      ktimer_begin(KK_FRONT_SCHUR, st);
+      hipLaunchKernelGGL(k_front_schur, dim3(ns), dim3(256), 0, st, dev.schur_items[h], dev.fronts,
+                         dev.F, dev.L);
+      ktimer_end(plan.schur_flops[h], plan.schur_bytes[h], st);
     }
   }
   backward_sweep(plan, dev, nullptr, pN, nullptr, st);

@@ -57,7 +57,8 @@ class ModelInfo_C(C.Structure):
 class TuneReport_C(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("split_min", C.c_int32), ("n_candidates", C.c_int32),
                 ("bw_split_min", C.c_int32), ("us_per_solve", C.c_double),
-                ("us_before", C.c_double)]
+                ("us_before", C.c_double), ("unrefined_error", C.c_double),
+                ("refine", C.c_int32), ("pad", C.c_int32)]
 
 
 class OfflineOpts_C(C.Structure):
@@ -525,8 +526,11 @@ def time_of_flight(prob, flux, tau_out, tol=0.0, maxit=100000):
     returns the number of sweeps."""
     pc = ProblemC(prob)
     sw = C.c_int32(0)
-    _check(lib().lrbms_time_of_flight(pc.ref(), _ptr(flux), float(tol), int(maxit), _ptr(tau_out),
-                                      C.byref(sw)))
+    r, nface = int(prob.dim) + 1, len(prob.bc_type)
+    ncell = int(np.prod(prob.n[:prob.dim]))
+    fn = lib().lrbms_time_of_flight
+    _check(fn(pc.ref(), _dev(flux, "float64", nface, "flux"), float(tol), int(maxit),
+              _dev(tau_out, "float64", r * ncell, "tau"), C.byref(sw)))
     return sw.value
 
 
@@ -602,7 +606,9 @@ def _parse_plan(buf) -> dict:
     three sources of 4) and its panel steps (items of 4: front, panel, ti, tj;
     a split step lists its rows-only items, then its update items); then the
     split backward products: partial-vector doubles, the U-row map, 3 values
-    per front (nzc, urow_off, zoff) and per level its (front, chunk) items."""
+    per front (nzc, urow_off, zoff) and per level its (front, chunk) items;
+    then per level the (front, ti, tj) tiles of the deferred Schur
+    complements."""
     it = iter(buf.tolist())
     nxt = lambda k: [next(it) for _ in range(k)]
     nf, H, nn, nch, lpd, fd, vd, idd, flops = nxt(9)
@@ -631,6 +637,9 @@ def _parse_plan(buf) -> dict:
         f["nzc"], f["urow_off"], f["zoff"] = nxt(3)
     for lev in levels:
         lev["bw"] = [tuple(nxt(2)) for _ in range(next(it))]
+    # deferred Schur complements: per level (front, ti, tj) output tiles
+    for lev in levels:
+        lev["schur"] = [tuple(nxt(3)) for _ in range(next(it))]
     if next(it, None) is not None:
         raise ValueError("plan record longer than its layout")
     return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,

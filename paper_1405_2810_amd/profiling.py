@@ -78,6 +78,7 @@ KERNEL_SOURCE = {
     "k_front_asm": _SOLVER, "k_front_factor0": _SOLVER, "k_front_step": _SOLVER,
     "k_front_backward": _SOLVER, "k_front_update": _SOLVER, "k_front_bw_gemv": _SOLVER,
     "k_residual": _SOLVER, "k_front_forward": _SOLVER, "k_front_fw_gemv": _SOLVER,
+    "k_front_schur": _SOLVER,
     "k_reconstruct": _TRANSPORT, "k_flux": _TRANSPORT, "k_transport": _TRANSPORT,
     "k_limiter": _TRANSPORT,
     **{k: _OFFLINE for k in ("k_fine_stencil", "k_fine_rhs", "k_fine_jacobi", "k_mg_extract",

@@ -60,7 +60,10 @@ def emulate(plan, blocks, fN, refine=False):
     """The numeric phase as the device kernels execute it: fronts column-major
     with a right-hand-side row at the bottom, fused panel steps with the L rows
     in a separate panel-major store, look-ahead tile factorization, backward
-    sweep reading L row-wise; a split front's product L_US^T x_U is formed
+    sweep reading L row-wise; the trailing updates of a panel step touch the
+    S columns only, and each front's U x U block and the right-hand-side row's
+    U part are updated once after its last panel (deferred Schur complement);
+    a split front's product L_US^T x_U is formed
     first in partial vectors, one per 64 U rows read through the plan's U-row
     map, and the backward subtracts their sum in chunk order."""
     F = np.zeros(plan["front_doubles"])
@@ -116,11 +119,26 @@ def emulate(plan, blocks, fN, refine=False):
                 if it["tj"] < 0:
                     continue
                 C0 = cs + it["tj"] * NB
-                ncl = min(NB, ld - C0)
+                ncl = min(NB, f["m"] - C0)      # S columns only
                 Bt = A if it["tj"] == it["ti"] else Fp[C0:C0 + ncl, c0:cs] @ Li.T
                 Fp[R0:R0 + nr, C0:C0 + ncl] -= A @ Bt[:ncl].T
                 if it["ti"] == 0 and it["tj"] == 0 and p + 1 < f["npanels"]:
                     _factor_tile(Fp, f["m"], p + 1, Inv, f)
+        # deferred Schur complement: (U + rhs row) x U minus L_US L_US^T over
+        # all m columns, tile by tile, the panels in order
+        for fi, ti, tj in lev["schur"]:
+            f = fr[fi]
+            Fp = view(F, f)
+            ld, m = f["m"] + f["u"], f["m"]
+            R0, C0 = m + ti * NB, m + tj * NB
+            nr, ncl = min(NB, ld + 1 - R0), min(NB, ld - C0)
+            acc = np.zeros((nr, ncl))
+            for b in range(f["npanels"]):
+                rows, cs_b = lpanel(f, b)
+                nbb = min(NB, m - b * NB)
+                acc += rows[R0 - cs_b:R0 - cs_b + nr, :nbb] @ rows[C0 - cs_b:C0 - cs_b + ncl, :nbb].T
+            Fp[R0:R0 + nr, C0:C0 + ncl] -= acc
+
     def rhs_rows(f):
         ld, m = f["m"] + f["u"], f["m"]
         y = np.zeros(m)
