@@ -201,6 +201,21 @@ int lrbms_fine_pressure(const lrbms_problem* prob, const double* d_field, int32_
 int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double tol,
                          int32_t maxit, double* d_tau, int32_t* sweeps);
 
+/* lrbms_time_of_flight for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation, arguments, results and errors, but every
+ * work buffer (the cell and face blocks, the sweep vector, the partial
+ * maxima, the porosity and the status word) lives in one fixed scratch
+ * array of 128 MiB per device inside the library, held until the process
+ * ends; no hipMalloc, hipFree or allocating library call is made.  The
+ * problem must fit that array: (1 + ncell + r^2 ncell + 2 dim r^2 ncell +
+ * 2 r ncell + 2 ceil(ncell/256) + 2) doubles (up to about 320,000 cells in
+ * 2D and 138,000 in 3D); LRBMS_E_ARG otherwise.  Calls on one device share the array: calls
+ * that overlap in time on the same device race and must be serialized by the
+ * caller; every call clears what it needs at its start.                     */
+int lrbms_time_of_flight_noalloc(const lrbms_problem* prob, const double* d_flux, double tol,
+                                 int32_t maxit, double* d_tau, int32_t* sweeps);
+
 /* Greedy basis construction (Alg. 2 step 2, the error-driven extension) on the
  * device, with the true error measure: the energy norm |p_H(mu) - p_h(mu)| of
  * b_h(., .; sum_q mubar_q Lambda^q).  Steps 1a-1c as lrbms_build_offline_bases

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -1059,6 +1060,32 @@ struct FineModel {
 
 }  // namespace lrbms
 
+namespace lrbms {
+
+// Fixed work memory of the entry points that allocate nothing (128 MiB per
+// device, held until the process ends).  Host code never uses the array's
+// name as an address: scratch_ptr() looks its device address up once per
+// device (hipGetSymbolAddress, with that device current) and keeps it.
+constexpr size_t kScratchDoubles = (128ull << 20) / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+static double* scratch_ptr() {
+  int dev = 0;
+  if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return nullptr;
+  if (dev < 0 || dev >= 64) return (set_error("device index out of range"), nullptr);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (!hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress")) return nullptr;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace lrbms
+
 using namespace lrbms;
 
 static Model* M_(lrbms_model* m) { return reinterpret_cast<Model*>(m); }
@@ -1689,6 +1716,49 @@ int lrbms_time_of_flight(const lrbms_problem* prob, const double* d_flux, double
     set_error(e.what());
     return LRBMS_E_OOM;
   }
+}
+
+int lrbms_time_of_flight_noalloc(const lrbms_problem* prob, const double* d_flux, double tol,
+                                 int32_t maxit, double* d_tau, int32_t* sweeps) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!d_flux || !d_tau) return (set_error("NULL device pointer"), LRBMS_E_ARG);
+  if (!(tol >= 0.0) || maxit < 1) return (set_error("tol must be >= 0 and maxit >= 1"), LRBMS_E_ARG);
+  Geom g;
+  int nc[3];
+  fill_geom(g, nc, prob);
+  // scratch layout: status (2 ints in one double slot), porosity, TOF work
+  const size_t need = 1 + (size_t)g.ncell + tof_scratch_doubles(g);
+  if (need > kScratchDoubles)
+    return (set_error("time_of_flight_noalloc: the problem needs more than the fixed scratch "
+                      "(128 MiB)"),
+            LRBMS_E_ARG);
+  double* base = scratch_ptr();
+  if (!base) return LRBMS_E_HIP;
+  int* status = reinterpret_cast<int*>(base);
+  double* poro = base + 1;
+  if (!hip_ok(hipMemsetAsync(status, 0, 2 * sizeof(int), 0), "clear status") ||
+      !hip_ok(hipMemcpy(poro, prob->poro, (size_t)g.ncell * sizeof(double), hipMemcpyHostToDevice),
+              "copy porosity"))
+    return LRBMS_E_HIP;
+  g.poro = poro;
+  g.status = status;
+  TofBufs B;
+  tof_carve(g, poro + g.ncell, B);
+  int sw = 0;
+  rc = tof_solve_bufs(g, d_flux, tol, maxit, d_tau, status, &sw, B);
+  if (sweeps) *sweeps = sw;
+  int st[2] = {0, 0};
+  if (!hip_ok(hipMemcpy(st, status, sizeof(st), hipMemcpyDeviceToHost), "status")) return LRBMS_E_HIP;
+  if (st[0] < 0 && (rc == LRBMS_OK || rc == LRBMS_E_STATE)) rc = st[0];
+  switch (rc) {
+    case LRBMS_OK: break;
+    case LRBMS_E_STATE: set_error("time of flight: sweeps did not converge within maxit"); break;
+    case LRBMS_E_NOT_SPD: set_error("time of flight: singular cell block (a cell without flux)"); break;
+    case LRBMS_E_NONFINITE: set_error("time of flight: non-finite values"); break;
+    default: set_error("time of flight: HIP error"); break;
+  }
+  return rc;
 }
 
 int lrbms_model_export_profiles(const lrbms_model* m, double* profiles) {

@@ -111,6 +111,7 @@ def lib():
         L.lrbms_fine_pressure.argtypes = [vp, vp, i32, dbl, i32, vp, C.POINTER(i32),
                                           C.POINTER(dbl)]
         L.lrbms_time_of_flight.argtypes = [vp, vp, dbl, i32, vp, C.POINTER(i32)]
+        L.lrbms_time_of_flight_noalloc.argtypes = [vp, vp, dbl, i32, vp, C.POINTER(i32)]
         L.lrbms_model_export_profiles.argtypes = [vp, vp]
         L.lrbms_build_greedy_bases.argtypes = [vp, vp, vp, i32, dbl, vp, C.POINTER(vp), vp, vp,
                                                i32, C.POINTER(i32), vp]
@@ -521,14 +522,15 @@ def fine_pressure(prob, field, p_out, kind=FIELD_SATURATION, rtol=1e-13, maxit=2
     return it.value, rr.value
 
 
-def time_of_flight(prob, flux, tau_out, tol=0.0, maxit=100000):
-    """Time of flight (lrbms_time_of_flight) into the device buffer tau_out;
-    returns the number of sweeps."""
+def time_of_flight(prob, flux, tau_out, tol=0.0, maxit=100000, noalloc=False):
+    """Time of flight (lrbms_time_of_flight, or lrbms_time_of_flight_noalloc
+    with its fixed work memory) into the device buffer tau_out; returns the
+    number of sweeps."""
     pc = ProblemC(prob)
     sw = C.c_int32(0)
     r, nface = int(prob.dim) + 1, len(prob.bc_type)
     ncell = int(np.prod(prob.n[:prob.dim]))
-    fn = lib().lrbms_time_of_flight
+    fn = lib().lrbms_time_of_flight_noalloc if noalloc else lib().lrbms_time_of_flight
     _check(fn(pc.ref(), _dev(flux, "float64", nface, "flux"), float(tol), int(maxit),
               _dev(tau_out, "float64", r * ncell, "tau"), C.byref(sw)))
     return sw.value
