@@ -501,6 +501,18 @@ int lrbms_server_drain(lrbms_server* s);
  * has queued requests), free its step buffers and admit waiting ones.       */
 int lrbms_server_detach(lrbms_server* s, int32_t sim_id);
 int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info);
+/* Fused dispatch (call before the first attach; on != 0): the pending
+ * requests of distinct admitted simulations, up to max_slots, form a wave:
+ * their assemblies run on the slot streams, then ONE reduced solve by the
+ * combined multifrontal plan of every admitted simulation runs with the
+ * wave's members active and the others masked off (their workgroups return
+ * at once), then their fluxes and transport run on the slot streams.  One
+ * wave is on the device at a time; requests arriving meanwhile join the
+ * next one (continuous batching).  The combined plan and storage (A_N, f_N,
+ * p_N of every member) are rebuilt whenever the admitted set changes.  Each
+ * simulation's result is the one its plain path gives, bit for bit.
+ * LRBMS_E_STATE after the first attach.                                      */
+int lrbms_server_set_fused(lrbms_server* s, int32_t on);
 void lrbms_server_destroy(lrbms_server* s);
 
 /* Synchronize with the model's last stream and return its device status:

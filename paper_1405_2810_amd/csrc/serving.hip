@@ -66,6 +66,18 @@ bool mode_ok(const Model& M, int mode) {
   return M.nprof > 0 && M.lsq_ok;
 }
 
+// Members of a wave: mask[i] = 1 for the listed members of a combined plan, 0
+// for the others.
+struct MaskArgs {
+  int count, total;
+  int ids[64];
+};
+__global__ void k_set_mask(int* __restrict__ mask, MaskArgs a) {
+  for (int i = threadIdx.x; i < a.total; i += blockDim.x) mask[i] = 0;
+  __syncthreads();
+  if ((int)threadIdx.x < a.count) mask[a.ids[threadIdx.x]] = 1;
+}
+
 // The part of one online step after the reduced solve: p_h, the fluxes, the
 // saturation step with the limiter, and the new state copied over d_sat.
 int sim_after_solve(lrbms_model* m, double* d_sat, uint8_t* d_flags, const StepBufs& b,
@@ -298,10 +310,192 @@ struct Server {
   std::deque<Req> pending;     // submitted, not yet dispatched, in submit order
   std::deque<Done> done;       // completed, not yet polled
 
+  // Fused dispatch: the pending requests of distinct admitted simulations
+  // (up to one per slot) form a wave: their assemblies on the slot streams,
+  // then one reduced solve by the combined plan of all admitted simulations
+  // with the wave's members active and the others masked off, then their
+  // fluxes and transport on the slot streams.  One wave is on the device at
+  // a time (the split backward products share partial storage per level);
+  // requests that arrive meanwhile join the next wave.  The combined plan
+  // and its storage are rebuilt whenever the admitted set changes.
+  bool fused = false;
+  bool cdirty = true;
+  SolverPlan cplan;
+  SolverDev cdev;
+  double *cblocks = nullptr, *cfN = nullptr, *cpN = nullptr;
+  int* cstatus = nullptr;
+  int* cmask = nullptr;                 // device, one flag per member of the combined plan
+  std::vector<int> cmembers;            // member index -> simulation
+  std::vector<int> cmember_of;          // simulation -> member index (-1: not a member)
+  std::vector<double*> own_blocks, own_fN;
+  int refine = 0;
+  hipStream_t wst = nullptr;
+  hipEvent_t wfork = nullptr, wfork2 = nullptr, wdone = nullptr;
+  std::vector<hipEvent_t> wjoin, wjoin2;
+  std::vector<Req> wave;                // the wave on the device
+
+  // Give the members back their own block storage and drop the combined plan.
+  void drop_combined() {
+    for (size_t k = 0; k < cmembers.size(); ++k) {
+      Sim& S = sims[cmembers[k]];
+      if (!S.m) continue;
+      Model* M = model_of(S.m);
+      M->d_blocks = own_blocks[k];
+      M->d_fN = own_fN[k];
+      S.bufs.release();
+    }
+    own_blocks.clear();
+    own_fN.clear();
+    cmembers.clear();
+    cmember_of.assign(sims.size(), -1);
+    solver_free(cdev);
+    cplan = SolverPlan{};
+    for (void* q : {(void*)cblocks, (void*)cfN, (void*)cpN, (void*)cstatus, (void*)cmask})
+      if (q) (void)hipFree(q);
+    cblocks = cfN = cpN = nullptr;
+    cstatus = cmask = nullptr;
+    cdirty = true;
+  }
+
+  // Combined plan and storage of every admitted simulation (no wave on the
+  // device); each member's A_N, f_N and p_N live in the combined storage.
+  int build_combined() {
+    drop_combined();
+    std::vector<const SolverPlan*> plans;
+    std::vector<long long> blk_base, pn_base;
+    long long nblk = 0, nN = 0;
+    for (size_t i = 0; i < sims.size(); ++i) {
+      if (!sims[i].attached || !sims[i].admitted) continue;
+      const Model& M = *model_of(sims[i].m);
+      cmember_of[i] = (int)cmembers.size();
+      cmembers.push_back((int)i);
+      plans.push_back(&M.plan);
+      blk_base.push_back(nblk);
+      pn_base.push_back(nN);
+      nblk += M.nblk;
+      nN += M.N;
+    }
+    cdirty = false;
+    if (cmembers.empty()) return LRBMS_OK;
+    refine = model_of(sims[cmembers[0]].m)->refine;
+    for (int id : cmembers)
+      if (model_of(sims[id].m)->refine != refine)
+        return (set_error("fused serving: the simulations' refinement steps differ"), LRBMS_E_ARG);
+    if (!combine_plans(plans, blk_base, pn_base, cplan) || !plan_in_bounds(cplan, nblk, nN))
+      return (set_error("fused serving: plans cannot be combined"), LRBMS_E_ARG);
+    if (!solver_upload(cplan, cdev)) return (set_error("fused serving: upload failed"), LRBMS_E_OOM);
+    auto zalloc = [](void** q, size_t bytes) {
+      return hip_ok(hipMalloc(q, std::max<size_t>(bytes, 8)), "hipMalloc") &&
+             hip_ok(hipMemset(*q, 0, std::max<size_t>(bytes, 8)), "hipMemset");
+    };
+    if (!zalloc((void**)&cblocks, sizeof(double) * nblk) ||
+        !zalloc((void**)&cfN, sizeof(double) * nN) || !zalloc((void**)&cpN, sizeof(double) * nN) ||
+        !zalloc((void**)&cstatus, sizeof(int)) ||
+        !zalloc((void**)&cmask, sizeof(int) * cmembers.size()))
+      return LRBMS_E_OOM;
+    for (size_t k = 0; k < cmembers.size(); ++k) {
+      Sim& S = sims[cmembers[k]];
+      Model* M = model_of(S.m);
+      own_blocks.push_back(M->d_blocks);
+      own_fN.push_back(M->d_fN);
+      M->d_blocks = cblocks + blk_base[k];
+      M->d_fN = cfN + pn_base[k];
+      if (!S.bufs.alloc(*M, cpN + pn_base[k])) return LRBMS_E_OOM;
+    }
+    return LRBMS_OK;
+  }
+
+  int launch_wave(const std::vector<Req>& reqs) {
+    const int n = (int)reqs.size();
+    MaskArgs ma{};
+    ma.count = n;
+    ma.total = (int)cmembers.size();
+    for (int i = 0; i < n; ++i) ma.ids[i] = cmember_of[reqs[i].sim];
+    hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, wst, cmask, ma);
+    if (!hip_ok(hipGetLastError(), "mask") || !hip_ok(hipEventRecord(wfork, wst), "event"))
+      return LRBMS_E_HIP;
+    const int ns = (int)slots.size();
+    int rc;
+    for (int i = 0; i < n; ++i) {
+      hipStream_t b = slots[i % ns].st;
+      Sim& S = sims[reqs[i].sim];
+      if (!hip_ok(hipStreamWaitEvent(b, wfork, 0), "wait")) return LRBMS_E_HIP;
+      if ((rc = lrbms_online_assemble(S.m, S.sat, mode, b)) != LRBMS_OK) return rc;
+      if (!hip_ok(hipEventRecord(wjoin[i], b), "event")) return LRBMS_E_HIP;
+    }
+    for (int i = 0; i < n; ++i)
+      if (!hip_ok(hipStreamWaitEvent(wst, wjoin[i], 0), "wait")) return LRBMS_E_HIP;
+    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, wst, refine, cmask),
+                "fused reduced solve") ||
+        !hip_ok(hipEventRecord(wfork2, wst), "event"))
+      return LRBMS_E_HIP;
+    for (int i = 0; i < n; ++i) {
+      hipStream_t b = slots[i % ns].st;
+      Sim& S = sims[reqs[i].sim];
+      if (!hip_ok(hipStreamWaitEvent(b, wfork2, 0), "wait")) return LRBMS_E_HIP;
+      if ((rc = sim_after_solve(S.m, S.sat, nullptr, S.bufs, b)) != LRBMS_OK) return rc;
+      if (!hip_ok(hipEventRecord(wjoin2[i], b), "event")) return LRBMS_E_HIP;
+      model_of(S.m)->last_stream = wst;
+      S.busy = true;
+    }
+    for (int i = 0; i < n; ++i)
+      if (!hip_ok(hipStreamWaitEvent(wst, wjoin2[i], 0), "wait")) return LRBMS_E_HIP;
+    if (!hip_ok(hipEventRecord(wdone, wst), "event")) return LRBMS_E_HIP;
+    wave = reqs;
+    return LRBMS_OK;
+  }
+
+  // Fused dispatch: retire the wave on the device, admit, rebuild the
+  // combined plan if the admitted set changed, and launch the next wave.
+  // Retire the wave on the device if it has finished; true when none is left.
+  bool retire_wave() {
+    if (!wave.empty()) {
+      const hipError_t e = hipEventQuery(wdone);
+      if (e == hipErrorNotReady) return false;
+      int st = 0;
+      if (e == hipSuccess &&
+          !hip_ok(hipMemcpy(&st, cstatus, sizeof(int), hipMemcpyDeviceToHost), "status"))
+        st = LRBMS_E_HIP;
+      const auto now = Clock::now();
+      for (const Req& r : wave) {
+        const double ms = std::chrono::duration<double, std::milli>(now - r.t0).count();
+        done.push_back(Done{r.id, ms, e == hipSuccess ? st : LRBMS_E_HIP});
+        sims[r.sim].busy = false;
+      }
+      wave.clear();
+    }
+    return true;
+  }
+
+  int progress_fused() {
+    if (!retire_wave()) return LRBMS_OK;
+    const size_t before = waiting.size();
+    int rc = admit();
+    if (rc != LRBMS_OK) return rc;
+    if (waiting.size() != before) cdirty = true;
+    if (cdirty && (rc = build_combined()) != LRBMS_OK) return rc;
+    std::vector<Req> reqs;
+    std::vector<char> taken(sims.size(), 0);
+    for (auto it = pending.begin(); it != pending.end() && reqs.size() < slots.size();) {
+      Sim& S = sims[it->sim];
+      if (!S.admitted || S.busy || taken[it->sim]) {
+        ++it;
+        continue;
+      }
+      taken[it->sim] = 1;
+      reqs.push_back(*it);
+      it = pending.erase(it);
+    }
+    if (reqs.empty()) return LRBMS_OK;
+    return launch_wave(reqs);
+  }
+
   ~Server() {
     for (auto& s : slots) {
       if (s.st) (void)hipStreamSynchronize(s.st);
     }
+    if (wst) (void)hipStreamSynchronize(wst);
+    if (fused) drop_combined();
     for (auto& s : sims) {
       if (s.m) {
         model_of(s.m)->last_stream = nullptr;
@@ -313,6 +507,11 @@ struct Server {
       if (s.done) (void)hipEventDestroy(s.done);
       if (s.st) (void)hipStreamDestroy(s.st);
     }
+    for (hipEvent_t e : wjoin) (void)hipEventDestroy(e);
+    for (hipEvent_t e : wjoin2) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {wfork, wfork2, wdone})
+      if (e) (void)hipEventDestroy(e);
+    if (wst) (void)hipStreamDestroy(wst);
   }
 
   // Admit waiting simulations, in attach order, while they fit the budget.
@@ -320,7 +519,7 @@ struct Server {
     while (!waiting.empty()) {
       Sim& S = sims[waiting.front()];
       if (resident + S.footprint > budget) break;
-      if (!S.bufs.alloc(*model_of(S.m))) return LRBMS_E_OOM;
+      if (!fused && !S.bufs.alloc(*model_of(S.m))) return LRBMS_E_OOM;
       S.admitted = true;
       resident += S.footprint;
       waiting.pop_front();
@@ -331,6 +530,7 @@ struct Server {
   // Retire finished requests; then admit; then dispatch pending requests in
   // submit order onto free slots (one request per simulation in flight).
   int progress() {
+    if (fused) return progress_fused();
     for (auto& s : slots) {
       if (s.sim < 0) continue;
       const hipError_t e = hipEventQuery(s.done);
@@ -370,6 +570,7 @@ struct Server {
   }
 
   bool idle() const {
+    if (!wave.empty()) return false;
     for (auto& s : slots)
       if (s.sim >= 0) return false;
     return true;
@@ -591,6 +792,7 @@ int lrbms_server_drain(lrbms_server* s) {
         // nothing in flight and nothing dispatchable: the rest waits for memory
         return (set_error("pending requests wait for memory no detach will free"), LRBMS_E_ADMIT);
       }
+      if (!S->wave.empty()) (void)hipEventSynchronize(S->wdone);
       for (auto& x : S->slots)
         if (x.sim >= 0) {
           (void)hipEventSynchronize(x.done);
@@ -613,7 +815,16 @@ int lrbms_server_detach(lrbms_server* s, int32_t sim_id) {
       if (r.sim == sim_id) return (set_error("simulation has pending requests"), LRBMS_E_STATE);
     for (auto& sl : S->slots)
       if (sl.sim == sim_id) (void)hipEventSynchronize(sl.done);
-    int rc = S->progress();
+    int rc = LRBMS_OK;
+    if (S->fused) {
+      // the wave on the device ends; the members get their own storage back
+      // and the combined plan is rebuilt without this simulation
+      if (!S->wave.empty()) (void)hipEventSynchronize(S->wdone);
+      S->retire_wave();
+      S->drop_combined();
+    } else {
+      rc = S->progress();
+    }
     if (x.admitted) S->resident -= x.footprint;
     x.bufs.release();
     S->waiting.erase(std::remove(S->waiting.begin(), S->waiting.end(), sim_id), S->waiting.end());
@@ -635,11 +846,37 @@ int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info) {
   info->n_pending = (int32_t)S->pending.size();
   int busy = 0, adm = 0, wait = (int)S->waiting.size();
   for (auto& sl : S->slots) busy += sl.sim >= 0;
+  busy += (int)S->wave.size();
   for (auto& x : S->sims) adm += x.attached && x.admitted;
   info->n_in_flight = busy;
   info->n_admitted = adm;
   info->n_waiting = wait;
   return LRBMS_OK;
+}
+
+int lrbms_server_set_fused(lrbms_server* s, int32_t on) {
+  try {
+    if (!s) return (set_error("NULL server"), LRBMS_E_ARG);
+    Server* S = reinterpret_cast<Server*>(s);
+    if (!S->sims.empty()) return (set_error("set_fused before the first attach"), LRBMS_E_STATE);
+    S->fused = on != 0;
+    if (S->fused && !S->wst) {
+      if (!hip_ok(hipStreamCreateWithFlags(&S->wst, hipStreamNonBlocking), "stream") ||
+          !hip_ok(hipEventCreateWithFlags(&S->wfork, hipEventDisableTiming), "event") ||
+          !hip_ok(hipEventCreateWithFlags(&S->wfork2, hipEventDisableTiming), "event") ||
+          !hip_ok(hipEventCreateWithFlags(&S->wdone, hipEventDisableTiming), "event"))
+        return LRBMS_E_HIP;
+      S->wjoin.assign(S->slots.size(), nullptr);
+      S->wjoin2.assign(S->slots.size(), nullptr);
+      for (size_t i = 0; i < S->slots.size(); ++i)
+        if (!hip_ok(hipEventCreateWithFlags(&S->wjoin[i], hipEventDisableTiming), "event") ||
+            !hip_ok(hipEventCreateWithFlags(&S->wjoin2[i], hipEventDisableTiming), "event"))
+          return LRBMS_E_HIP;
+    }
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
 }
 
 void lrbms_server_destroy(lrbms_server* s) { delete reinterpret_cast<Server*>(s); }

@@ -54,6 +54,8 @@ struct FrontD {
   // from p_N[urow_pn[urow_off + r]]
   int nzc = 0, urow_off = 0;
   long long zoff = 0;
+  int member = 0;     // member of a combined plan (0 in a single plan)
+  int pad = 0;
 };
 
 // One workgroup of the split backward product: 64 U rows of one front.
@@ -67,7 +69,7 @@ struct NodeRef { int pos, pn_off, size, ppos; };
 // Row block of one box in A_N, for the residual of the iterative refinement:
 // the diagonal block (lower triangle used, as the factorization does) and
 // neighbour blocks nb0 .. nb1-1 of the residual plan.
-struct ResBox { long long blk_off; int pn_off, ne, nb0, nb1, pad; };
+struct ResBox { long long blk_off; int pn_off, ne, nb0, nb1, member; };
 // One coupling block of a box's rows: A(i, j) = blocks[blk_off + i rs + j cs]
 // for the neighbour's ne unknowns at p_N[pn_off ..].
 struct ResNb { long long blk_off; int pn_off, ne, rs, cs; };
@@ -196,9 +198,12 @@ void solver_free(SolverDev& dev);
 // double-double arithmetic (compensated products and sums), a forward and a
 // backward substitution of it with the stored factor, and p_N += correction.
 // A non-finite residual sets the status word to LRBMS_E_NONFINITE.
+// active (device, nullable): per member of a combined plan 1 to solve, 0 to
+// skip (every workgroup of a skipped member's fronts returns at once).
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN,
-                               int* status, hipStream_t st, int refine = 0);
+                               int* status, hipStream_t st, int refine = 0,
+                               const int* active = nullptr);
 constexpr int kMaxRefine = 4;
 
 }  // namespace lrbms

@@ -348,7 +348,9 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
         const int nrt = (ld + 1 - cs + kNB - 1) / kNB;
         const int nct = (d.m - cs + kNB - 1) / kNB;   // trailing S columns only
         for (int ti = 0; ti < nrt; ++ti) {
-          if (nct == 0) {
+          // a tile of U rows only: its panel columns take the earlier
+          // panels' products left-looking, in its rows-only item
+          if (nct == 0 || cs + kNB * ti >= d.m) {
             plan.step_items[h][b].push_back(StepItem{p, b, ti, -1});
             continue;
           }
@@ -411,11 +413,18 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
         const double nb = std::min(kNB, d.m - b * kNB);
         const double cs = b * kNB + nb, t = ld - cs, sc = d.m - cs;
         const double nb1 = (b + 1 < d.npanels) ? std::min(kNB, d.m - (int)cs) : 0.0;
-        // L rows, then the trailing update of the S columns (the lower
-        // trapezoid of t + 1 rows by sc columns) and the next diagonal tile;
-        // a split step counts them in its two launches
-        const double fl = (t + 1) * nb * nb, by = 8.0 * (2.0 * (t + 1) * nb + nb * nb);
-        const double ent = sc * (t + 1) - sc * (sc - 1) / 2.0;
+        // first row of the tiles of U rows only (left-looking), and the rows
+        // of the tiles updated right-looking (from cs)
+        const double ru0 = cs + kNB * std::ceil(sc / kNB), ts = ru0 - cs;
+        const double nu = std::max(0.0, ld + 1 - std::max(ru0, (double)kNB * d.npanels));
+        const double c0 = (double)b * kNB;
+        // L rows (with the left-looking products of the U-row tiles), then
+        // the trailing update of the S columns of the other tiles (the lower
+        // trapezoid of ts rows by sc columns) and the next diagonal tile; a
+        // split step counts them in its two launches
+        const double fl = (t + 1) * nb * nb + 2.0 * nu * nb * c0;
+        const double by = 8.0 * (2.0 * (t + 1) * nb + nb * nb + (nu + nb) * c0);
+        const double ent = std::max(0.0, sc * ts - sc * (sc - 1) / 2.0);
         const double fu = 2.0 * nb * ent + 2.0 * nb1 * nb1 * nb1 / 3.0;
         const double bu = 8.0 * (2.0 * ent + nb1 * nb1);
         const bool split = !plan.upd_items[h][b].empty();
@@ -708,9 +717,11 @@ __global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ i
                                                    const FrontD* __restrict__ fronts,
                                                    const double* __restrict__ blocks,
                                                    const double* __restrict__ fN,
-                                                   double* __restrict__ F) {
+                                                   double* __restrict__ F,
+                                                   const int* __restrict__ active) {
   const AsmItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const long long lda = f.m + f.u + 1;
   double* Fp = F + f.off;
   const int n = it.nr * it.nc;
@@ -744,11 +755,13 @@ __global__ __launch_bounds__(256) void k_front_asm(const AsmItem* __restrict__ i
 __global__ __launch_bounds__(256) void k_front_factor0(const int* __restrict__ list,
                                                        const FrontD* __restrict__ fronts,
                                                        const double* __restrict__ F,
-                                                       double* __restrict__ Inv, int* status) {
+                                                       double* __restrict__ Inv, int* status,
+                                                       const int* __restrict__ active) {
   __shared__ Tile D[kNB];
   __shared__ Tile X[kNB];
   __shared__ TileAux aux;
   const FrontD f = fronts[list[blockIdx.x]];
+  if (active && !active[f.member]) return;
   const long long lda = f.m + f.u + 1;
   const double* Fp = F + f.off;
   const int nb = min(kNB, f.m);
@@ -791,13 +804,15 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
                                                     const FrontD* __restrict__ fronts,
                                                     double* __restrict__ F,
                                                     double* __restrict__ Lb,
-                                                    double* __restrict__ Inv, int* status) {
+                                                    double* __restrict__ Inv, int* status,
+                                                    const int* __restrict__ active) {
   __shared__ Tile S0[kNB];
   __shared__ Tile S1[kNB];
   __shared__ Tile S2[kNB];
   __shared__ TileAux aux;
   const StepItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
@@ -807,6 +822,53 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   const bool upd = it.tj >= 0;
   const int C0 = cs + (upd ? it.tj : 0) * kNB;
   const int ncl = upd ? min(kNB, f.m - C0) : 0;   // S columns only
+  // a tile of U rows only: the panel columns of its rows from 64 npanels on
+  // have had no update yet (the rows between m and there were updated
+  // right-looking, in the tile that straddles m before the last panel); the
+  // earlier panels' products sum_c L(R, c) L(P, c)^T are formed here on FP64
+  // MFMA (L from the store, panel by panel), staged in S1 and subtracted
+  // from those rows
+  const bool left = !upd && R0 >= f.m && it.panel > 0;
+  const int mU = f.npanels * kNB;
+  if (left) {
+    d4 c2[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) c2[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double la[16], lp[16];
+    auto load = [&](int cp) {
+      const double* Lc = Lb + lpanel_base(f, cp);
+      const int csc = kNB * (cp + 1);   // panels before the last are full
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p, i = idx >> 6, k = idx & 63;
+        la[p] = (i < nr) ? Lc[(long long)(R0 - csc + i) * kNB + k] : 0.0;
+        lp[p] = (i < nb) ? Lc[(long long)(c0 - csc + i) * kNB + k] : 0.0;
+      }
+    };
+    load(0);
+    for (int cp = 0; cp < it.panel; ++cp) {
+      if (cp > 0) __syncthreads();   // the previous panel's products are done
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int idx = tid + 256 * p;
+        S1[idx >> 6][idx & 63] = la[p];
+        S2[idx >> 6][idx & 63] = lp[p];
+      }
+      __syncthreads();
+      if (cp + 1 < it.panel) load(cp + 1);   // in flight during the products
+      for (int c = 0; c < kNB / 4; ++c) {
+        const double a = S1[16 * w + r][4 * c + q];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) c2[cb] = mfma16(a, S2[16 * cb + r][4 * c + q], c2[cb]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
+    __syncthreads();
+  }
   // loads: L_panel^{-1} (row-major), the panel columns of tile row ti, and the
   // F tile (ti, tj) this workgroup updates (kept in registers)
   // (all loads are issued before the first LDS store, so their latencies overlap)
@@ -823,7 +885,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   for (int p = 0; p < 16; ++p) {
     const int idx = tid + 256 * p;
     S0[idx >> 6][idx & 63] = li[p];
-    S2[idx & 63][idx >> 6] = bv[p];
+    S2[idx & 63][idx >> 6] = (left && R0 + (idx & 63) >= mU) ? bv[p] - S1[idx & 63][idx >> 6] : bv[p];
   }
   __syncthreads();
   d4 acc[4];
@@ -910,10 +972,12 @@ __global__ __launch_bounds__(256) void k_front_bw_gemv(const BwItem* __restrict_
                                                        const double* __restrict__ Lpan,
                                                        const int* __restrict__ urow_pn,
                                                        const double* __restrict__ pN,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part,
+                                                       const int* __restrict__ active) {
   __shared__ double xr[kNB];
   const BwItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const int m = f.m, r0 = kNB * it.chunk, nr = min(kNB, f.u - r0), tid = threadIdx.x;
   if (tid < kNB) xr[tid] = tid < nr ? pN[urow_pn[f.urow_off + r0 + tid]] : 0.0;
   __syncthreads();
@@ -945,11 +1009,13 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
                                                         const double* __restrict__ part,
                                                         const double* __restrict__ ysrc,
                                                         double* __restrict__ pN,
-                                                        double* __restrict__ padd) {
+                                                        double* __restrict__ padd,
+                                                        const int* __restrict__ active) {
   extern __shared__ double w[];   // m + u values
   __shared__ double red[4][4][kNB];
   __shared__ double xb[kNB];
   const FrontD f = fronts[list[blockIdx.x]];
+  if (active && !active[f.member]) return;
   const int m = f.m, u = f.u, ld = m + u, np = f.npanels, tid = threadIdx.x;
   const int k = tid & 63, g = tid >> 6;
   auto csof = [&](int b) { return min(kNB * (b + 1), m); };
@@ -1119,9 +1185,11 @@ __global__ __launch_bounds__(256) void k_residual(const ResBox* __restrict__ box
                                                   const double* __restrict__ blocks,
                                                   const double* __restrict__ fN,
                                                   const double* __restrict__ pN,
-                                                  double* __restrict__ res, int* status) {
+                                                  double* __restrict__ res, int* status,
+                                                  const int* __restrict__ active) {
   __shared__ double xs[2][4][kNB];
   const ResBox B = boxes[blockIdx.x];
+  if (active && !active[B.member]) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, ne = B.ne;
   const double* D = blocks + B.blk_off;
   for (int i0 = 0; i0 < ne; i0 += kNB) {
@@ -1184,9 +1252,11 @@ __global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ l
                                                        const double* __restrict__ Lpan,
                                                        const double* __restrict__ Inv,
                                                        const double* __restrict__ r,
-                                                       double* __restrict__ V) {
+                                                       double* __restrict__ V,
+                                                       const int* __restrict__ active) {
   extern __shared__ double w[];   // m + u values
   const FrontD f = fronts[list[blockIdx.x]];
+  if (active && !active[f.member]) return;
   const int m = f.m, ld = m + f.u, np = f.npanels, tid = threadIdx.x;
   const int lane = tid & 63, g = tid >> 6, rr = 16 * g + (lane >> 2), seg = 16 * (lane & 3);
   for (int i = tid; i < ld; i += blockDim.x) w[i] = 0.0;
@@ -1250,9 +1320,11 @@ __global__ __launch_bounds__(256) void k_front_forward(const int* __restrict__ l
 __global__ __launch_bounds__(256) void k_front_fw_gemv(const BwItem* __restrict__ items,
                                                        const FrontD* __restrict__ fronts,
                                                        const double* __restrict__ Lpan,
-                                                       double* __restrict__ V) {
+                                                       double* __restrict__ V,
+                                                       const int* __restrict__ active) {
   const BwItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const int m = f.m, r0 = kNB * it.chunk, nr = min(kNB, f.u - r0), tid = threadIdx.x;
   const int lane = tid & 63, g = tid >> 6, rr = 16 * g + (lane >> 2), seg = 16 * (lane & 3);
   const bool on = rr < nr;
@@ -1373,6 +1445,7 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
     const int ubase = (int)out.urow_pn.size();
     for (int v : P.urow_pn) out.urow_pn.push_back(v + (int)pn_base[k]);
     for (FrontD f : P.fronts) {
+      f.member = (int)k;
       f.urow_off += ubase;
       f.off += out.front_doubles;
       f.loff += out.lpan_doubles;
@@ -1389,6 +1462,7 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
     for (int c : P.children) out.children.push_back(c + fbase);
     const int rbase = (int)out.rnbs.size();
     for (ResBox rb : P.rboxes) {
+      rb.member = (int)k;
       rb.blk_off += blk_base[k];
       rb.pn_off += (int)pn_base[k];
       rb.nb0 += rbase;
@@ -1577,7 +1651,8 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
                                                       const FrontD* __restrict__ fronts,
                                                       double* __restrict__ F,
                                                       const double* __restrict__ Lb,
-                                                      double* __restrict__ Inv, int* status) {
+                                                      double* __restrict__ Inv, int* status,
+                                                      const int* __restrict__ active) {
   // two tiles: L(ti) and L(tj); the product is staged in the first once
   // both are consumed, and the look-ahead factorization works in both
   __shared__ Tile S0[kNB];
@@ -1586,6 +1661,7 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
   Tile* S2 = S1;
   const StepItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
@@ -1654,11 +1730,13 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
 __global__ __launch_bounds__(256) void k_front_schur(const SchurItem* __restrict__ items,
                                                      const FrontD* __restrict__ fronts,
                                                      double* __restrict__ F,
-                                                     const double* __restrict__ Lb) {
+                                                     const double* __restrict__ Lb,
+                                                     const int* __restrict__ active) {
   __shared__ Tile SA[kNB];
   __shared__ Tile SB[kNB];
   const SchurItem it = items[blockIdx.x];
   const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   const int m = f.m;
@@ -1808,7 +1886,7 @@ void solver_free(SolverDev& dev) {
 // factorization's right-hand-side rows (ysrc = nullptr) or a forward
 // substitution's vectors; x into pN, and added to padd when given.
 static void backward_sweep(const SolverPlan& plan, const SolverDev& dev, const double* ysrc,
-                           double* pN, double* padd, hipStream_t st) {
+                           double* pN, double* padd, hipStream_t st, const int* active) {
   const int H = plan.nlevels;
   for (int h = H - 1; h >= 0; --h) {
     const int n = (int)plan.level_fronts[h].size();
@@ -1819,45 +1897,45 @@ static void backward_sweep(const SolverPlan& plan, const SolverDev& dev, const d
     if (nbw) {
       ktimer_begin(KK_FRONT_BW_GEMV, st);
       hipLaunchKernelGGL(k_front_bw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
-                         dev.fronts, dev.L, dev.urow_pn, pN, dev.part);
+                         dev.fronts, dev.L, dev.urow_pn, pN, dev.part, active);
       ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
     }
     ktimer_begin(KK_FRONT_BACKWARD, st);
     hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
                        dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, dev.part, ysrc,
-                       pN, padd);
+                       pN, padd, active);
     ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
   }
 }
 
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN, int* status,
-                               hipStream_t st, int refine) {
+                               hipStream_t st, int refine, const int* active) {
   const int H = plan.nlevels;
   for (int h = 0; h < H; ++h) {
     const int na = (int)plan.asm_items[h].size();
     const int nf = (int)plan.level_fronts[h].size();
     ktimer_begin(KK_FRONT_ASM, st);
     hipLaunchKernelGGL(k_front_asm, dim3(na), dim3(256), 0, st, dev.asm_items[h], dev.fronts,
-                       blocks, fN, dev.F);
+                       blocks, fN, dev.F, active);
     ktimer_end(plan.asm_flops[h], plan.asm_bytes[h], st);
     ktimer_begin(KK_FRONT_FACTOR0, st);
     hipLaunchKernelGGL(k_front_factor0, dim3(nf), dim3(256), 0, st, dev.level_fronts[h],
-                       dev.fronts, dev.F, dev.Inv, status);
+                       dev.fronts, dev.F, dev.Inv, status, active);
     ktimer_end(plan.f0_flops[h], plan.f0_bytes[h], st);
     for (size_t p = 0; p < plan.step_items[h].size(); ++p) {
       const int ni = (int)plan.step_items[h][p].size();
       if (ni) {
         ktimer_begin(KK_FRONT_STEP, st);
         hipLaunchKernelGGL(k_front_step, dim3(ni), dim3(256), 0, st, dev.step_items[h][p],
-                           dev.fronts, dev.F, dev.L, dev.Inv, status);
+                           dev.fronts, dev.F, dev.L, dev.Inv, status, active);
         ktimer_end(plan.step_flops[h][p], plan.step_bytes[h][p], st);
       }
       const int nu = (int)plan.upd_items[h][p].size();
       if (nu) {
         ktimer_begin(KK_FRONT_UPDATE, st);
         hipLaunchKernelGGL(k_front_update, dim3(nu), dim3(256), 0, st, dev.upd_items[h][p],
-                           dev.fronts, dev.F, dev.L, dev.Inv, status);
+                           dev.fronts, dev.F, dev.L, dev.Inv, status, active);
         ktimer_end(plan.upd_flops[h][p], plan.upd_bytes[h][p], st);
       }
     }
@@ -1865,16 +1943,16 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
     if (ns) {
       ktimer_begin(KK_FRONT_SCHUR, st);
       hipLaunchKernelGGL(k_front_schur, dim3(ns), dim3(256), 0, st, dev.schur_items[h], dev.fronts,
-                         dev.F, dev.L);
+                         dev.F, dev.L, active);
       ktimer_end(plan.schur_flops[h], plan.schur_bytes[h], st);
     }
   }
-  backward_sweep(plan, dev, nullptr, pN, nullptr, st);
+  backward_sweep(plan, dev, nullptr, pN, nullptr, st, active);
   const int nbox = (int)plan.rboxes.size();
   for (int it = 0; it < std::min(refine, kMaxRefine) && nbox > 0; ++it) {
     ktimer_begin(KK_RESIDUAL, st);
     hipLaunchKernelGGL(k_residual, dim3(nbox), dim3(256), 0, st, dev.rboxes, dev.rnbs, blocks, fN,
-                       pN, dev.res, status);
+                       pN, dev.res, status, active);
     ktimer_end(plan.res_flops, plan.res_bytes, st);
     for (int h = 0; h < H; ++h) {
       const int n = (int)plan.level_fronts[h].size();
@@ -1884,17 +1962,17 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
       ktimer_begin(KK_FRONT_FORWARD, st);
       hipLaunchKernelGGL(k_front_forward, dim3(n), dim3(256), sizeof(double) * maxld, st,
                          dev.level_fronts[h], dev.fronts, dev.nodes, dev.children, dev.L, dev.Inv,
-                         dev.res, dev.V);
+                         dev.res, dev.V, active);
       ktimer_end(plan.fw_flops[h], plan.fw_bytes[h], st);
       const int nbw = (int)plan.bw_items[h].size();
       if (nbw) {
         ktimer_begin(KK_FRONT_FW_GEMV, st);
         hipLaunchKernelGGL(k_front_fw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
-                           dev.fronts, dev.L, dev.V);
+                           dev.fronts, dev.L, dev.V, active);
         ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
       }
     }
-    backward_sweep(plan, dev, dev.V, dev.cor, pN, st);
+    backward_sweep(plan, dev, dev.V, dev.cor, pN, st, active);
   }
   return hipGetLastError();
 }

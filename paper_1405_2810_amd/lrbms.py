@@ -136,6 +136,7 @@ def lib():
         L.lrbms_server_drain.argtypes = [vp]
         L.lrbms_server_detach.argtypes = [vp, i32]
         L.lrbms_server_info.argtypes = [vp, vp]
+        L.lrbms_server_set_fused.argtypes = [vp, i32]
         L.lrbms_server_destroy.argtypes = [vp]
         L.lrbms_server_destroy.restype = None
         _lib = L
@@ -713,13 +714,15 @@ class Server:
     admitted by memory footprint; requests (one time step each) dispatched
     onto slot streams as slots free up.  Close it before closing its models."""
 
-    def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT):
+    def __init__(self, hbm_budget: int, max_slots: int = 8, mode=DIRECT, fused: bool = False):
         self._carry = []
         self._sims = {}
         self._states = {}
         h = C.c_void_p()
         _check(lib().lrbms_server_create(int(hbm_budget), max_slots, mode, C.byref(h)))
         self._h = h
+        if fused:
+            _check(lib().lrbms_server_set_fused(self._h, 1))
 
     def attach(self, model: "Model", sat) -> int:
         """Attach a simulation with its state tensor; the server advances it

@@ -165,10 +165,12 @@ def _footprint(m):
     return i["device_bytes"] + 8 * (max(i["N"], 1) + max(i["nface"], 1) + i["r"] * i["ncell"])
 
 
-def test_server_mix_equals_alone(L):
+@pytest.mark.parametrize("fused", [False, True])
+def test_server_mix_equals_alone(L, fused):
     """Requests of four simulations of different grids, interleaved in a
-    seeded order over three slots: every simulation ends where its plain
-    path, run alone, ends."""
+    seeded order over three slots (fused: waves of up to three requests
+    whose reduced solves run as one combined-plan solve): every simulation
+    ends where its plain path, run alone, ends."""
     import torch
     built = [_model(L, n, i) for i, n in enumerate(NAMES)]
     probs, models = [b[0] for b in built], [b[1] for b in built]
@@ -181,7 +183,7 @@ def test_server_mix_equals_alone(L):
     torch.cuda.synchronize()
     order = np.repeat(np.arange(len(models)), steps)
     np.random.default_rng(5).shuffle(order)
-    S = L.Server(hbm_budget=sum(_footprint(m) for m in models), max_slots=3)
+    S = L.Server(hbm_budget=sum(_footprint(m) for m in models), max_slots=3, fused=fused)
     try:
         ids = [S.attach(m, s) for m, s in zip(models, sats)]
         info = S.info()
@@ -207,7 +209,8 @@ def test_server_mix_equals_alone(L):
             m.close()
 
 
-def test_server_admission_by_footprint(L):
+@pytest.mark.parametrize("fused", [False, True])
+def test_server_admission_by_footprint(L, fused):
     """A budget that holds two of three simulations: the third waits, its
     requests wait with it, and it is admitted (and served, with the same
     result as alone) once another simulation is detached."""
@@ -223,7 +226,7 @@ def test_server_admission_by_footprint(L):
         for _ in range(2):
             r.step()
     torch.cuda.synchronize()
-    S = L.Server(hbm_budget=budget, max_slots=4)
+    S = L.Server(hbm_budget=budget, max_slots=4, fused=fused)
     try:
         ids = [S.attach(m, s) for m, s in zip(models, sats)]
         info = S.info()

@@ -112,6 +112,15 @@ def emulate(plan, blocks, fN, refine=False):
                 Li = Inv[f["inv_off"] + p * NB * NB:f["inv_off"] + (p + 1) * NB * NB].reshape(NB, NB)[:nb, :nb]
                 R0 = cs + it["ti"] * NB
                 nr = min(NB, ld + 1 - R0)
+                if it["tj"] < 0 and R0 >= f["m"] and p > 0:
+                    # a tile of U rows: the earlier panels' products, left-looking,
+                    # for its rows from 64 npanels on (the rows before were in the
+                    # tile straddling m, updated right-looking)
+                    lo = max(R0, NB * f["npanels"])
+                    for cp in range(p):
+                        rows_c, cs_c = lpanel(f, cp)
+                        Fp[lo:R0 + nr, c0:cs] -= (rows_c[lo - cs_c:R0 - cs_c + nr, :]
+                                                  @ rows_c[c0 - cs_c:c0 - cs_c + (cs - c0), :].T)
                 A = Fp[R0:R0 + nr, c0:cs] @ Li.T
                 if it["tj"] <= 0:
                     rows, cs_b = lpanel(f, p)
