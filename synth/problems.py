@@ -262,12 +262,15 @@ CONFIGS: Dict[str, dict] = {
     # shaped like the paper's 2D benchmark (Sec. 6): [0,300] x [0,60] m, 400 x 160
     # cells, linear relative permeabilities, the printed viscosities, water
     # entering on the left (p = 10, s = 1), outward flux 3e-4 on the right,
-    # no flow on top and bottom, no sources, T = 3e5 s in 6000 steps; its
-    # permeability and porosity fields are not given, so a seeded log-normal
-    # field (kappa_g = 1e-10 m^2) and porosity 0.2 stand in; 8 x 2 boxes
+    # no flow on top and bottom, no sources, T = 3e5 s; its permeability and
+    # porosity fields are not given, so a seeded log-normal field
+    # (kappa_g = 1e-10 m^2) and porosity 0.2 stand in; 8 x 2 boxes.  The
+    # printed step (50 s, 6000 steps) gives this stand-in a CFL number of
+    # 1.3 (its flow concentrates in the high-permeability streaks), so the
+    # step is 15 s (CFL about 0.4, 20000 steps)
     "paper": dict(dim=2, n=(400, 160, 1), L=(300.0, 60.0, 1.0), nc=(8, 2, 1), corr=0.1 * 300.0,
                   sigma=1.0, steps=6000, M=8, n_train=8, ne_cap=25, wells="paper", Q=0.0,
-                  dt=50.0, seed=44, t_end=3.0e5, kg=1.0e-10, visc_w=0.00130581, visc_o=0.008,
+                  dt=15.0, seed=44, t_end=3.0e5, kg=1.0e-10, visc_w=0.00130581, visc_o=0.008,
                   relperm=0, p_left=10.0, v_right=3.0e-4),
     # ensemble members: 2D 256x256 and 3D 64x64x32 on seeded uneven coarse
     # partitions (boxes of 16..48 cells per side in 2D, 8..24 x 8..24 x 4..12

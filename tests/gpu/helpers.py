@@ -29,6 +29,29 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def cfl_number(p, F):
+    """CFL number of an explicit Euler transport step with face fluxes F:
+    dt max|f_w'| (slopes over 4096 equal saturation intervals) times a
+    cell's outflow over phi |e|, maximised over cells."""
+    from synth.problems import face_counts
+    s = np.linspace(0.0, 1.0, 4097)
+    kw, ko = (s, 1.0 - s) if p.relperm == 0 else (s ** p.corey_w, (1.0 - s) ** p.corey_o)
+    fw = (kw / p.visc_w) / (kw / p.visc_w + ko / p.visc_o)
+    fmax = np.max(np.abs(np.diff(fw)) * 4096)
+    nx, ny, nz = p.n
+    fx, fy, _ = face_counts(p.dim, p.n)
+    F = np.asarray(F)
+    Fx = F[:fx].reshape(nz, ny, nx + 1)
+    Fy = F[fx:fx + fy].reshape(nz, ny + 1, nx)
+    out = (np.maximum(0, Fx[:, :, 1:]) + np.maximum(0, -Fx[:, :, :-1]) +
+           np.maximum(0, Fy[:, 1:, :]) + np.maximum(0, -Fy[:, :-1, :]))
+    if p.dim == 3:
+        Fz = F[fx + fy:].reshape(nz + 1, ny, nx)
+        out = out + np.maximum(0, Fz[1:]) + np.maximum(0, -Fz[:-1])
+    vol = float(np.prod(p.h[:p.dim]))
+    return float((p.dt * fmax * out.ravel() / (np.asarray(p.poro) * vol)).max())
+
+
 def oracle_case(name, with_profiles=True, **kw):
     """Problem, oracle model (bases from the oracle's offline stage), the
     flat basis and the kept profiles."""
