@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick the reduced solver's shapes by timing them (untimed set-up)")
+    ap.add_argument("--shapes", default="",
+                    help="leaf,split,bw: install these solver shapes instead of autotuning "
+                         "(0 = never split), e.g. to profile the plan a timed run chose")
     ap.add_argument("--refine", type=int, default=-1,
                     help=">= 0: refinement steps of the reduced solve, set after the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -376,7 +379,14 @@ def main():
     st = torch.cuda.current_stream()
     s0_host = random_saturation(p, np.random.default_rng(1), lo=0.0, hi=0.6)
     s0 = torch.as_tensor(s0_host, dtype=torch.float64, device=dev)
-    tune = gm.autotune(s0, reps=10) if args.autotune else None
+    tune = gm.autotune(s0, reps=10) if args.autotune and not args.shapes else None
+    if args.shapes:
+        leaf, split, bw = (int(v) for v in args.shapes.split(","))
+        gm.set_solver_shapes(leaf, split, bw)
+        log(f"[bench] solver shapes set: leaf {leaf} split {split} backward split {bw}")
+        shapes = dict(leaf_max=leaf, split_min=split, bw_split_min=bw, source="--shapes")
+    else:
+        shapes = tune
     if tune:
         log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']} "
             f"backward split {tune['bw_split_min']}, unrefined error "
@@ -580,7 +590,7 @@ def main():
                                f"{'x'.join(str(v) for v in nc)} coarse boxes, N_E<={p.ne_cap}, "
                                f"online step a1-a7 ({args.mode}), plain per-simulation path",
                    "mode": args.mode, "N": info["N"], "fine_cells": info["ncell"],
-                   "solver_shapes": tune},
+                   "solver_shapes": shapes},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "per_call_ms": {"assemble": float(parts[:, 0].mean()), "solve": float(parts[:, 1].mean()),
                         "flux": float(parts[:, 2].mean()), "transport": float(parts[:, 3].mean())},

@@ -384,6 +384,16 @@ typedef struct lrbms_tune_report {
 int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
                          lrbms_tune_report* report);
 
+/* Installs the reduced solver's plan for given shapes (the fields of a tune
+ * report: leaf_max 1..64 boxes, split_min 0 = never split else >= 1 tile,
+ * bw_split_min 0 = never split else >= 1 entry), as the autotuner would
+ * after choosing them: for reusing a tuned configuration without timing
+ * it again.  Synchronous; allocates.  LRBMS_E_ARG for shapes out of range
+ * or a plan that does not fit its storage, LRBMS_E_STATE while the model
+ * belongs to a batch or server, LRBMS_E_OOM.                                 */
+int lrbms_model_set_solver_shapes(lrbms_model* m, int32_t leaf_max, int32_t split_min,
+                                  int32_t bw_split_min);
+
 /* Kernel timing, for roofline measurement (off by default).
  * lrbms_profile_enable synchronizes the model's last stream, clears the
  * counters and switches timing on (enable != 0) or off.  While on, every

@@ -1236,6 +1236,39 @@ int lrbms_model_set_refinement(lrbms_model* m, int32_t steps) {
   return LRBMS_OK;
 }
 
+int lrbms_model_set_solver_shapes(lrbms_model* m, int32_t leaf_max, int32_t split_min,
+                                  int32_t bw_split_min) {
+  try {
+    if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+    if (leaf_max < 1 || leaf_max > 64 || split_min < 0 || bw_split_min < 0)
+      return (set_error("solver shapes out of range"), LRBMS_E_ARG);
+    Model* M = M_(m);
+    if (M->owner) return (set_error("model belongs to a batch or server"), LRBMS_E_STATE);
+    const int split = split_min == 0 ? (1 << 30) : split_min;
+    const long long bw = bw_split_min == 0 ? (1LL << 62) : (long long)bw_split_min;
+    SolverPlan P;
+    if (!build_solver_plan(M->g.dim, M->nc, M->subs, M->ifaces, leaf_max, P, split, bw) ||
+        !plan_in_bounds(P, M->nblk, M->N))
+      return (set_error("solver plan of these shapes does not fit"), LRBMS_E_ARG);
+    if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+    SolverDev D;
+    if (!solver_upload(P, D)) {
+      solver_free(D);
+      return (set_error("solver allocation failed"), LRBMS_E_OOM);
+    }
+    M->dev_bytes += D.bytes - M->sdev.bytes;
+    solver_free(M->sdev);
+    M->sdev = D;
+    M->plan = std::move(P);
+    M->leaf_max = leaf_max;
+    M->split_min = split;
+    M->bw_min = bw;
+    return LRBMS_OK;
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
 int lrbms_reconstruct_flux(lrbms_model* m, const double* d_pN, const double* d_sat,
                            double* d_flux, double* d_ph, void* stream) {
   if (!m || !d_pN || !d_sat || !d_flux) return (set_error("NULL argument"), LRBMS_E_ARG);

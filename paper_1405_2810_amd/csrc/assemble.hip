@@ -188,7 +188,9 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   double* Kst = lds;                                   // [CH][KS >= NF R R]
   double* PhiS = Kst + (size_t)CH * SH::KS;            // [PR][LDP]
   double* YS = PhiS + (size_t)PR * LDP;                // [PR][LDP]
-  const int sub = chunks[2 * blockIdx.x], c0 = chunks[2 * blockIdx.x + 1];
+  // consecutive chunks of a box share the Phi rows of their neighbour cells
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int sub = chunks[2 * item], c0 = chunks[2 * item + 1];
   const Sub S = subs[sub];
   const int NE = S.NE, nE = S.nE;
   const int cc = min(CH, nE - c0);
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
     }
     __syncthreads();
   }
-  double* out = partial + (size_t)blockIdx.x * NEP * NEP;
+  double* out = partial + (size_t)item * NEP * NEP;
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int tile = w + 4 * t;

@@ -58,6 +58,16 @@ struct Iface {
 };
 
 // ---- device helpers ---------------------------------------------------------
+
+// Workgroup b of a launch of n goes to XCD b mod 8 (the dispatcher hands
+// them to the eight XCDs in turn, each XCD with an L2 of its own).  The work
+// item a workgroup takes is renumbered so that every XCD works through one
+// contiguous range of items: neighbouring items, which read the same input
+// lines, then meet in the same L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int per = n >> 3, rem = n & 7, x = b & 7, i = b >> 3;
+  return x * per + min(x, rem) + i;
+}
 __device__ __forceinline__ double clip01(double s) { return fmin(fmax(s, 0.0), 1.0); }
 
 // General Corey power, kept out of line: inlined at every mobility evaluation

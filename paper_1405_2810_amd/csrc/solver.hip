@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   __shared__ Tile S1[kNB];
   __shared__ Tile S2[kNB];
   __shared__ TileAux aux;
-  const StepItem it = items[blockIdx.x];
+  const StepItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const FrontD f = fronts[it.front];
   if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
@@ -1659,7 +1659,7 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
   __shared__ Tile S1[kNB];
   __shared__ TileAux aux;
   Tile* S2 = S1;
-  const StepItem it = items[blockIdx.x];
+  const StepItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const FrontD f = fronts[it.front];
   if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
@@ -1734,7 +1734,7 @@ __global__ __launch_bounds__(256) void k_front_schur(const SchurItem* __restrict
                                                      const int* __restrict__ active) {
   __shared__ Tile SA[kNB];
   __shared__ Tile SB[kNB];
-  const SchurItem it = items[blockIdx.x];
+  const SchurItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const FrontD f = fronts[it.front];
   if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;

@@ -99,6 +99,7 @@ def lib():
         L.lrbms_online_assemble.argtypes = [vp, vp, i32, vp]
         L.lrbms_online_solve.argtypes = [vp, vp, vp]
         L.lrbms_model_set_refinement.argtypes = [vp, i32]
+        L.lrbms_model_set_solver_shapes.argtypes = [vp, i32, i32, i32]
         L.lrbms_model_set_checks.argtypes = [vp, i32]
         L.lrbms_reconstruct_flux.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lrbms_transport_step.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -426,6 +427,12 @@ class Model:
         _check(lib().lrbms_model_export_basis(self._h, _ptr(sizes), _ptr(basis)))
         total = sum(int(k) * self.info["r"] * n for k, n in zip(sizes, ncells))
         return sizes, basis[:total].copy()
+
+    def set_solver_shapes(self, leaf_max: int, split_min: int, bw_split_min: int):
+        """Install the solver plan of given shapes (as a tune report gives
+        them; 0 = never split) without timing (lrbms_model_set_solver_shapes)."""
+        _check(lib().lrbms_model_set_solver_shapes(self._h, int(leaf_max), int(split_min),
+                                                   int(bw_split_min)))
 
     def autotune(self, sat, reps: int = 10) -> dict:
         """Time every solver shape on the reduced system of `sat` and keep
