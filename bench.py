@@ -99,6 +99,31 @@ def build_ensemble(n: int, seed: int = 500):
     return out
 
 
+def build_serving_mix(n64: int, n256: int, big=None, seed: int = 600):
+    """The serving mix: n64 simulations on the 64x64 grid (4x4 boxes, N_E <= 10)
+    and n256 on the 256x256 grid (16x16 boxes, N_E <= 25), each with its own
+    permeability seed; the local bases of a grid are one Gram-Schmidt basis of
+    seeded smooth snapshot fields of that grid (shared by its simulations);
+    big: an existing (problem, model) pair appended to the mix."""
+    from synth import CONFIGS, make_problem, smooth_fields
+    from paper_1405_2810_amd.lrbms import Model
+    out = []
+    for name, n in (("cfg1", n64), ("cfg2", n256)):
+        if n <= 0:
+            continue
+        p0 = make_problem(name)
+        snaps = smooth_fields(p0, p0.ne_cap + 4, np.random.default_rng(seed))
+        base = Model.from_snapshots(p0, snaps, ne_cap=p0.ne_cap, unit_functions=True)
+        sizes, flat = base.export_basis()
+        base.close()
+        for i in range(n):
+            p = make_problem(name, seed=CONFIGS[name]["seed"] + 1 + i)
+            out.append((p, Model.create(p, sizes, flat)))
+    if big is not None:
+        out.append(big)
+    return out
+
+
 def _states(members, seed):
     import torch
     from synth import random_saturation
@@ -162,14 +187,17 @@ def bench_batch(members, steps: int, warmup: int):
     return res
 
 
-def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77):
+def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77, fused: bool = False,
+                label: str = ""):
     """Poisson arrivals of online-step requests, each for a uniformly drawn
-    member, at each rate; the server admits every member (the budget is the
+    member, at each rate (rate 0: every request submitted at once, which
+    measures the capacity); the server admits every member (the budget is the
     sum of their footprints) and dispatches onto `slots` slot streams;
-    slots=1 is the plain path (one request on the device at a time).
-    Per rate: achieved solves/s (requests over the time from the first
-    submit to the last completion) and p50/p99 latency (submit to completion
-    seen by poll)."""
+    slots=1 is the plain path (one request on the device at a time); fused:
+    waves of up to `slots` requests whose reduced solves run as one
+    combined-plan solve.  Per rate: achieved solves/s (requests over the time
+    from the first submit to the last completion) and p50/p99 latency
+    (submit to completion seen by poll)."""
     from paper_1405_2810_amd.lrbms import Server, DIRECT
     models = [m for _, m in members]
     sats = _states(members, 700)
@@ -178,9 +206,10 @@ def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77):
     out = {}
     for rate in rates:
         rng = np.random.default_rng(seed)
-        arrive = np.cumsum(rng.exponential(1.0 / rate, n_req))
+        arrive = (np.zeros(n_req) if rate <= 0 else
+                  np.cumsum(rng.exponential(1.0 / rate, n_req)))
         who = rng.integers(0, len(models), n_req)
-        S = Server(hbm_budget=foot, max_slots=slots, mode=DIRECT)
+        S = Server(hbm_budget=foot, max_slots=slots, mode=DIRECT, fused=fused)
         ids = [S.attach(m, s) for m, s in zip(models, sats)]
         lat = []
         t0 = time.perf_counter()
@@ -197,9 +226,11 @@ def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77):
         span = time.perf_counter() - t0
         S.close()
         lat = np.array(lat)
-        out[f"{rate:g}"] = {"solves_per_s": n_req / span, "p50_ms": float(np.percentile(lat, 50)),
-                            "p99_ms": float(np.percentile(lat, 99))}
-        log(f"[bench] serve slots={slots} rate {rate:g}/s: {n_req / span:.0f} solves/s, "
+        key = "burst" if rate <= 0 else f"{rate:g}"
+        out[key] = {"solves_per_s": n_req / span, "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99))}
+        log(f"[bench] serve {label} slots={slots}{' fused' if fused else ''} "
+            f"{'burst' if rate <= 0 else f'rate {rate:g}/s'}: {n_req / span:.0f} solves/s, "
             f"p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms")
     for m in models:
         if m.status() < 0:
@@ -332,9 +363,14 @@ def main():
                     help="1: time the GPU offline stage once for context (-1: only for 2D "
                          "workloads; the 3D one takes about a minute)")
     ap.add_argument("--ensemble", type=int, default=64,
-                    help="members of the batched ensemble and serving passes; 0 skips both")
+                    help="members of the batched ensemble pass; 0 skips it")
     ap.add_argument("--ensemble-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=1500,
+                    help="requests per rate of the serving pass; 0 skips it")
+    ap.add_argument("--serve-64", type=int, default=128,
+                    help="simulations on the 64x64 grid in the serving mix")
+    ap.add_argument("--serve-256", type=int, default=96,
+                    help="simulations on the 256x256 grid in the serving mix")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick the reduced solver's shapes by timing them (untimed set-up)")
@@ -537,22 +573,52 @@ def main():
         for k, v in bat.items():
             log(f"[bench] ensemble {k}: {v['ms_per_ensemble_step']:.2f} ms per ensemble step, "
                 f"{v['solves_per_s']:.0f} solves/s, p99 {v['p99_ms']:.2f} ms")
-        rates = [1e3, 3e3, 1e4, 3e4, 5e4]
-        serve = {"slots": args.serve_slots,
-                 "continuous": bench_serve(members, rates, args.serve_requests, args.serve_slots),
-                 "plain_one_slot": bench_serve(members, rates, args.serve_requests, 1)}
+        # the same members served (fused waves of up to 64 requests) against the
+        # fused batch step
+        if args.serve_requests > 0:
+            bat["served_fused_waves"] = bench_serve(members, [0, 5e4], args.serve_requests, 64,
+                                                    fused=True, label="ensemble")
         extras["ensemble"] = {
             "what": f"{args.ensemble} simulations, alternately 2D 256x256 and 3D 64x64x32 on "
                     "seeded uneven coarse partitions, seeded N_E in 5..60 per box, DIRECT online "
-                    "step per member",
+                    "step per member; served_fused_waves: the same members behind the server "
+                    "(Poisson arrivals, uniformly drawn members, 'burst' = all at once)",
             "members": args.ensemble, "N_range": [min(sz), max(sz)], **bat}
-        extras["serving"] = {
-            "what": "Poisson arrivals of single online-step requests for uniformly drawn members "
-                    f"of the same ensemble, {args.serve_requests} requests per rate; continuous "
-                    f"batching over {args.serve_slots} slot streams against the plain path "
-                    "(one slot)", **serve}
         for _, m in members:
             m.close()
+    if args.serve_requests > 0:
+        log(f"[bench] serving mix: building {args.serve_64} x 64x64 and {args.serve_256} x "
+            f"256x256 simulations, plus the {args.config} model")
+        t0 = time.time()
+        mix = build_serving_mix(args.serve_64, args.serve_256, big=(p, gm))
+        log(f"[bench] serving mix ready in {time.time() - t0:.1f}s: {len(mix)} simulations, "
+            f"device MB {sum(m.info['device_bytes'] for _, m in mix) / 1e6:.0f}")
+        rates = [0, 1e3, 1e4, 5e4]
+        nreq = args.serve_requests
+        serve = {"continuous": bench_serve(mix, rates, nreq, args.serve_slots, label="mix"),
+                 "fused_waves": bench_serve(mix, rates, nreq, 64, fused=True, label="mix"),
+                 "plain_one_slot": bench_serve(mix, rates, nreq, 1, label="mix")}
+        caps = {k: max(r["solves_per_s"] for r in v.values()) for k, v in serve.items()}
+        best = max(caps, key=caps.get)
+        cap = caps[best]
+        below = 0.8 * cap
+        serve[best][f"{below:.0f} (0.8 capacity)"] = bench_serve(
+            mix, [below], nreq, 64 if best == "fused_waves" else
+            (1 if best == "plain_one_slot" else args.serve_slots),
+            fused=best == "fused_waves", label="mix")[f"{below:g}"]
+        extras["serving"] = {
+            "what": f"{len(mix)} concurrent simulations: {args.serve_64} on 64x64 (4x4 boxes, "
+                    f"N_E <= 10), {args.serve_256} on 256x256 (16x16 boxes, N_E <= 25), each with "
+                    f"its own permeability seed, and the {args.config} model; Poisson arrivals "
+                    f"of single online-step requests for uniformly drawn simulations, {nreq} "
+                    "requests per rate ('burst': all at once, the capacity); continuous: "
+                    f"{args.serve_slots} slot streams; fused_waves: waves of up to 64 requests "
+                    "with one combined-plan reduced solve; plain_one_slot: one request on the "
+                    "device at a time (the plain per-simulation path)",
+            "simulations": len(mix), "capacity_solves_per_s": caps, "best": best, **serve}
+        for q, m in mix:
+            if m is not gm:
+                m.close()
     if args.extra_config:
         extras[args.extra_config] = measure_plain(args.extra_config, args.steps, args.warmup,
                                                   args.autotune)

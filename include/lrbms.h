@@ -439,6 +439,8 @@ typedef struct lrbms_batch lrbms_batch;
  * level), so each launch of the solver processes the fronts of all members
  * at that point of their schedules; the members' A_N and f_N live in storage
  * of the batch while it exists (a model belongs to at most one fused batch).
+ * Members may differ in refinement steps: each takes its own (a member is
+ * masked off the fused refinement steps beyond its count).
  * Errors: LRBMS_E_ARG, LRBMS_E_OOM, LRBMS_E_HIP.                              */
 int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int32_t flags,
                        lrbms_batch** out);
@@ -519,8 +521,10 @@ int lrbms_server_info(const lrbms_server* s, lrbms_server_info_t* info);
  * at once), then their fluxes and transport run on the slot streams.  One
  * wave is on the device at a time; requests arriving meanwhile join the
  * next one (continuous batching).  The combined plan and storage (A_N, f_N,
- * p_N of every member) are rebuilt whenever the admitted set changes.  Each
- * simulation's result is the one its plain path gives, bit for bit.
+ * p_N of every member) are rebuilt whenever the admitted set changes.  A
+ * wave takes the largest refinement steps of its members, each member only
+ * its own.  Each simulation's result is the one its plain path gives, bit
+ * for bit.
  * LRBMS_E_STATE after the first attach.                                      */
 int lrbms_server_set_fused(lrbms_server* s, int32_t on);
 void lrbms_server_destroy(lrbms_server* s);

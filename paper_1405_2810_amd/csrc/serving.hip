@@ -67,15 +67,22 @@ bool mode_ok(const Model& M, int mode) {
 }
 
 // Members of a wave: mask[i] = 1 for the listed members of a combined plan, 0
-// for the others.
+// for the others; then kMaxRefine refinement masks of `total` flags each:
+// mask[(1 + k) total + i] = 1 for the listed members that take refinement
+// step k (refs[j] > k).
 struct MaskArgs {
   int count, total;
   int ids[64];
+  int refs[64];
 };
 __global__ void k_set_mask(int* __restrict__ mask, MaskArgs a) {
-  for (int i = threadIdx.x; i < a.total; i += blockDim.x) mask[i] = 0;
+  for (int i = threadIdx.x; i < (1 + kMaxRefine) * a.total; i += blockDim.x) mask[i] = 0;
   __syncthreads();
-  if ((int)threadIdx.x < a.count) mask[a.ids[threadIdx.x]] = 1;
+  if ((int)threadIdx.x < a.count) {
+    const int id = a.ids[threadIdx.x], ref = a.refs[threadIdx.x];
+    mask[id] = 1;
+    for (int k = 0; k < kMaxRefine; ++k) mask[(1 + k) * a.total + id] = ref > k ? 1 : 0;
+  }
 }
 
 // The part of one online step after the reduced solve: p_h, the fluxes, the
@@ -128,7 +135,8 @@ struct Batch {
   SolverDev cdev;
   double *cblocks = nullptr, *cfN = nullptr, *cpN = nullptr;
   int* cstatus = nullptr;
-  int refine = 0;   // refinement steps of the fused solve (those of every member)
+  int refine = 0;          // refinement steps of the fused solve: the members' largest
+  int* cref = nullptr;     // device, kMaxRefine x n: members taking step k (nullptr: all)
   std::vector<double*> own_blocks, own_fN;
   hipEvent_t fork2 = nullptr;
   std::vector<hipEvent_t> join2;
@@ -156,7 +164,7 @@ struct Batch {
     }
     for (auto& b : bufs) b.release();
     solver_free(cdev);
-    for (void* q : {(void*)cblocks, (void*)cfN, (void*)cpN, (void*)cstatus})
+    for (void* q : {(void*)cblocks, (void*)cfN, (void*)cpN, (void*)cstatus, (void*)cref})
       if (q) (void)hipFree(q);
     for (hipEvent_t e : join) (void)hipEventDestroy(e);
     for (hipEvent_t e : join2) (void)hipEventDestroy(e);
@@ -194,7 +202,8 @@ struct Batch {
       if (rc != LRBMS_OK) return rc;
     }
     if ((rc = join_into(from, join)) != LRBMS_OK || !fused) return rc;
-    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, from, refine),
+    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, from, refine,
+                                    nullptr, cref, (int)models.size()),
                 "fused reduced solve"))
       return LRBMS_E_HIP;
     if ((rc = fork_from(from, fork2)) != LRBMS_OK) return rc;
@@ -231,6 +240,23 @@ struct Batch {
         !zalloc((void**)&cfN, sizeof(double) * nN) || !zalloc((void**)&cpN, sizeof(double) * nN) ||
         !zalloc((void**)&cstatus, sizeof(int)))
       return LRBMS_E_OOM;
+    // members with fewer refinement steps than the largest are masked off
+    // the later steps
+    refine = 0;
+    bool same = true;
+    for (size_t i = 0; i < n; ++i) {
+      refine = std::max(refine, model_of(models[i])->refine);
+      same = same && model_of(models[i])->refine == model_of(models[0])->refine;
+    }
+    if (!same) {
+      std::vector<int> h((size_t)kMaxRefine * n);
+      for (int k = 0; k < kMaxRefine; ++k)
+        for (size_t i = 0; i < n; ++i) h[k * n + i] = model_of(models[i])->refine > k ? 1 : 0;
+      if (!zalloc((void**)&cref, sizeof(int) * h.size()) ||
+          !hip_ok(hipMemcpy(cref, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice),
+                  "refine masks"))
+        return LRBMS_E_OOM;
+    }
     for (size_t i = 0; i < n; ++i) {
       Model* M = model_of(models[i]);
       own_blocks.push_back(M->d_blocks);
@@ -328,7 +354,6 @@ struct Server {
   std::vector<int> cmembers;            // member index -> simulation
   std::vector<int> cmember_of;          // simulation -> member index (-1: not a member)
   std::vector<double*> own_blocks, own_fN;
-  int refine = 0;
   hipStream_t wst = nullptr;
   hipEvent_t wfork = nullptr, wfork2 = nullptr, wdone = nullptr;
   std::vector<hipEvent_t> wjoin, wjoin2;
@@ -377,10 +402,6 @@ struct Server {
     }
     cdirty = false;
     if (cmembers.empty()) return LRBMS_OK;
-    refine = model_of(sims[cmembers[0]].m)->refine;
-    for (int id : cmembers)
-      if (model_of(sims[id].m)->refine != refine)
-        return (set_error("fused serving: the simulations' refinement steps differ"), LRBMS_E_ARG);
     if (!combine_plans(plans, blk_base, pn_base, cplan) || !plan_in_bounds(cplan, nblk, nN))
       return (set_error("fused serving: plans cannot be combined"), LRBMS_E_ARG);
     if (!solver_upload(cplan, cdev)) return (set_error("fused serving: upload failed"), LRBMS_E_OOM);
@@ -391,7 +412,7 @@ struct Server {
     if (!zalloc((void**)&cblocks, sizeof(double) * nblk) ||
         !zalloc((void**)&cfN, sizeof(double) * nN) || !zalloc((void**)&cpN, sizeof(double) * nN) ||
         !zalloc((void**)&cstatus, sizeof(int)) ||
-        !zalloc((void**)&cmask, sizeof(int) * cmembers.size()))
+        !zalloc((void**)&cmask, sizeof(int) * (1 + kMaxRefine) * cmembers.size()))
       return LRBMS_E_OOM;
     for (size_t k = 0; k < cmembers.size(); ++k) {
       Sim& S = sims[cmembers[k]];
@@ -410,7 +431,12 @@ struct Server {
     MaskArgs ma{};
     ma.count = n;
     ma.total = (int)cmembers.size();
-    for (int i = 0; i < n; ++i) ma.ids[i] = cmember_of[reqs[i].sim];
+    int refine = 0;   // the wave's members' largest refinement steps
+    for (int i = 0; i < n; ++i) {
+      ma.ids[i] = cmember_of[reqs[i].sim];
+      ma.refs[i] = model_of(sims[reqs[i].sim].m)->refine;
+      refine = std::max(refine, ma.refs[i]);
+    }
     hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, wst, cmask, ma);
     if (!hip_ok(hipGetLastError(), "mask") || !hip_ok(hipEventRecord(wfork, wst), "event"))
       return LRBMS_E_HIP;
@@ -425,7 +451,8 @@ struct Server {
     }
     for (int i = 0; i < n; ++i)
       if (!hip_ok(hipStreamWaitEvent(wst, wjoin[i], 0), "wait")) return LRBMS_E_HIP;
-    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, wst, refine, cmask),
+    if (!hip_ok(solver_factor_solve(cplan, cdev, cblocks, cfN, cpN, cstatus, wst, refine, cmask,
+                                    cmask + cmembers.size(), (int)cmembers.size()),
                 "fused reduced solve") ||
         !hip_ok(hipEventRecord(wfork2, wst), "event"))
       return LRBMS_E_HIP;
@@ -599,8 +626,6 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
           return (set_error("a model appears twice in the batch"), LRBMS_E_ARG);
       if (!mode_ok(*model_of(models[i]), mode))
         return (set_error("assembly mode not available for every model"), LRBMS_E_ARG);
-      if (model_of(models[i])->refine != model_of(models[0])->refine)
-        return (set_error("the members' refinement steps differ"), LRBMS_E_ARG);
     }
     auto B = std::make_unique<Batch>();
     B->models.assign(models, models + n);
@@ -608,7 +633,6 @@ int lrbms_batch_create(lrbms_model* const* models, int32_t n, int32_t mode, int3
     B->mode = mode;
     B->use_graph = (flags & LRBMS_BATCH_GRAPH) != 0;
     B->fused = (flags & LRBMS_BATCH_FUSED_SOLVE) != 0;
-    B->refine = model_of(models[0])->refine;
     B->bufs.resize(n);
     int rc;
     if (B->fused) {

@@ -200,10 +200,14 @@ void solver_free(SolverDev& dev);
 // A non-finite residual sets the status word to LRBMS_E_NONFINITE.
 // active (device, nullable): per member of a combined plan 1 to solve, 0 to
 // skip (every workgroup of a skipped member's fronts returns at once).
+// ref_masks (device, nullable): the members taking refinement step k, as
+// refine masks of mstride flags each (step k reads ref_masks + k mstride);
+// without it every step takes the members of `active`.
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN,
                                int* status, hipStream_t st, int refine = 0,
-                               const int* active = nullptr);
+                               const int* active = nullptr, const int* ref_masks = nullptr,
+                               int mstride = 0);
 constexpr int kMaxRefine = 4;
 
 }  // namespace lrbms

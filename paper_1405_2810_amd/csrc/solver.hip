@@ -1910,7 +1910,8 @@ static void backward_sweep(const SolverPlan& plan, const SolverDev& dev, const d
 
 hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
                                const double* blocks, const double* fN, double* pN, int* status,
-                               hipStream_t st, int refine, const int* active) {
+                               hipStream_t st, int refine, const int* active,
+                               const int* ref_masks, int mstride) {
   const int H = plan.nlevels;
   for (int h = 0; h < H; ++h) {
     const int na = (int)plan.asm_items[h].size();
@@ -1950,9 +1951,10 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
   backward_sweep(plan, dev, nullptr, pN, nullptr, st, active);
   const int nbox = (int)plan.rboxes.size();
   for (int it = 0; it < std::min(refine, kMaxRefine) && nbox > 0; ++it) {
+    const int* am = ref_masks ? ref_masks + (long long)it * mstride : active;
     ktimer_begin(KK_RESIDUAL, st);
     hipLaunchKernelGGL(k_residual, dim3(nbox), dim3(256), 0, st, dev.rboxes, dev.rnbs, blocks, fN,
-                       pN, dev.res, status, active);
+                       pN, dev.res, status, am);
     ktimer_end(plan.res_flops, plan.res_bytes, st);
     for (int h = 0; h < H; ++h) {
       const int n = (int)plan.level_fronts[h].size();
@@ -1962,17 +1964,17 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
       ktimer_begin(KK_FRONT_FORWARD, st);
       hipLaunchKernelGGL(k_front_forward, dim3(n), dim3(256), sizeof(double) * maxld, st,
                          dev.level_fronts[h], dev.fronts, dev.nodes, dev.children, dev.L, dev.Inv,
-                         dev.res, dev.V, active);
+                         dev.res, dev.V, am);
       ktimer_end(plan.fw_flops[h], plan.fw_bytes[h], st);
       const int nbw = (int)plan.bw_items[h].size();
       if (nbw) {
         ktimer_begin(KK_FRONT_FW_GEMV, st);
         hipLaunchKernelGGL(k_front_fw_gemv, dim3(nbw), dim3(256), 0, st, dev.bw_items[h],
-                           dev.fronts, dev.L, dev.V, active);
+                           dev.fronts, dev.L, dev.V, am);
         ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
       }
     }
-    backward_sweep(plan, dev, dev.V, dev.cor, pN, st, active);
+    backward_sweep(plan, dev, dev.V, dev.cor, pN, st, am);
   }
   return hipGetLastError();
 }

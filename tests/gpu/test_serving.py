@@ -119,10 +119,13 @@ def test_batch_affine_equals_plain(L, fused):
 
 def test_fused_batch_of_many_grids(L):
     """Ten members of five grids (2D and 3D, even and uneven partitions,
-    basis sizes 6..40) in one fused solve."""
+    basis sizes 6..40) in one fused solve, with 0, 1 or 2 refinement steps
+    (a member leaves the fused refinement after its own steps)."""
     names = NAMES + ["cfg1", "small2d", "small3d", "tiny2d", "cfg1", "small3d"]
     built = [_model(L, n, 10 + i) for i, n in enumerate(names)]
     probs, models = [b[0] for b in built], [b[1] for b in built]
+    for i, m in enumerate(models):
+        m.set_refinement(i % 3)
     try:
         _check_batch(L, probs, models, L.DIRECT, True, steps=3, fused=True)
         # a model of a fused batch cannot join another one meanwhile
@@ -167,13 +170,16 @@ def _footprint(m):
 
 @pytest.mark.parametrize("fused", [False, True])
 def test_server_mix_equals_alone(L, fused):
-    """Requests of four simulations of different grids, interleaved in a
-    seeded order over three slots (fused: waves of up to three requests
-    whose reduced solves run as one combined-plan solve): every simulation
-    ends where its plain path, run alone, ends."""
+    """Requests of four simulations of different grids (0, 1, 2 and 1
+    refinement steps), interleaved in a seeded order over three slots (fused:
+    waves of up to three requests whose reduced solves run as one
+    combined-plan solve): every simulation ends where its plain path, run
+    alone, ends."""
     import torch
     built = [_model(L, n, i) for i, n in enumerate(NAMES)]
     probs, models = [b[0] for b in built], [b[1] for b in built]
+    for m, k in zip(models, [0, 1, 2, 1]):
+        m.set_refinement(k)
     steps = 5
     sats = [_state(p, 60 + i) for i, p in enumerate(probs)]
     alone = [Plain(m, s, L.DIRECT) for m, s in zip(models, sats)]
