@@ -125,7 +125,22 @@ typedef struct lrbms_offline_opts {
                                DIRECT_FIT); 0: a model without profiles             */
   const double* d_s0;       /* device [r*ncell] saturation whose flow defines the time
                                of flight (re-basing from a later state); NULL: s = 0 */
+  int32_t basis_method;     /* LRBMS_BASIS_GS or LRBMS_BASIS_PCA (local bases below) */
+  double pca_eps;           /* PCA: discarded energy <= pca_eps^2 of the total (>= 0) */
 } lrbms_offline_opts;
+
+/* Local bases from snapshots, in every box on the device (one workgroup per
+ * box), 1_E first when unit functions are asked for, at most ne_cap functions:
+ *  LRBMS_BASIS_GS:  the restrictions of the snapshots in order, Gram-Schmidt
+ *                   in L2(E) (two passes, rejection of remaining norms
+ *                   <= 1e-8 of the original) (Alg. 2 step 2e);
+ *  LRBMS_BASIS_PCA: the method of snapshots (Alg. 2 step 3): the restrictions
+ *                   with their components along 1_E removed, the eigenpairs
+ *                   of their Gram matrix (Jacobi rotations), the fewest
+ *                   leading modes whose discarded eigenvalues sum to at most
+ *                   pca_eps^2 of the total, each added by the Gram-Schmidt
+ *                   step above; at most 64 snapshots.                         */
+enum { LRBMS_BASIS_GS = 0, LRBMS_BASIS_PCA = 1 };
 
 /* What the offline stage did (filled when the caller passes a non-NULL pointer). */
 typedef struct lrbms_offline_report {
@@ -154,19 +169,22 @@ int lrbms_model_create(const lrbms_problem* prob, const int32_t* basis_sizes,
                        lrbms_model** out);
 
 /* Create a model whose local bases come from global snapshots (host,
- * [n_snap][r*ncell]): in every box, 1_E first when unit_functions is set, then
- * the restrictions of the snapshots in order, Gram-Schmidt in L2(E) (two
- * passes, rejection of remaining norms <= 1e-8 of the original), at most
- * ne_cap functions (Alg. 2 step 2e).  Profiles as in lrbms_model_create.     */
+ * [n_snap][r*ncell], copied to the device once): local bases by
+ * basis_method (LRBMS_BASIS_GS or LRBMS_BASIS_PCA with pca_eps, as
+ * described above), 1_E first when unit_functions is set, at most ne_cap
+ * functions per box.  Profiles as in lrbms_model_create.  LRBMS_E_ARG also
+ * when a box ends with an empty local basis.                                 */
 int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
                                       const double* snapshots, int32_t ne_cap,
-                                      int32_t unit_functions, int32_t n_profiles,
+                                      int32_t unit_functions, int32_t basis_method,
+                                      double pca_eps, int32_t n_profiles,
                                       const double* profiles, lrbms_model** out);
 
 /* Fine pressure of Def. pressureDG (the SWIP discretisation on the fine grid,
  * b_h(p_h, v; gamma) = l_h(v; gamma)) solved on the device by conjugate
- * gradients with cell-block Jacobi preconditioning, x0 = 0.  Also the fine
- * reference of the online step and the snapshot solver of the offline stage.
+ * gradients preconditioned with one multigrid V-cycle (below), x0 = 0.  Also
+ * the fine reference of the online step and the snapshot solver of the
+ * offline stage.
  *  d_field: device [r*ncell]; with kind LRBMS_FIELD_SATURATION the mobility is
  *           lambda(s) of this saturation, with LRBMS_FIELD_MOBILITY it is the
  *           field itself (a P1 field, e.g. a training mobility of Alg. 2)
@@ -264,7 +282,7 @@ void lrbms_fine_destroy(lrbms_fine* f);
  * step 1c (Lambda^1 = lambda(0), Lambda^M = lambda(1), Lambda^q = lambda(0)
  * where the cell mean of tau exceeds (q-1) T/(M-2), else lambda(1)), one
  * fine snapshot per training mobility gamma = sum_q mu_q Lambda^q (in row
- * order), then local Gram-Schmidt as in lrbms_model_create_from_snapshots.
+ * order, kept on the device), then the local bases by opts->basis_method.
  * With keep_profiles the model keeps the profiles that are linearly
  * independent of the ones before them (in q order; Gram-Schmidt with a
  * relative threshold of 1e-12).

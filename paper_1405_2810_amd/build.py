@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblrbms.so")
-SOURCES = ["api.hip", "assemble.hip", "offline.hip", "serving.hip", "solver.hip", "transport.hip"]
+SOURCES = ["api.hip", "assemble.hip", "bases.hip", "offline.hip", "serving.hip", "solver.hip",
+           "transport.hip"]
 # Packed FP32 instructions are kept out of every kernel.
 HIP_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -427,12 +427,17 @@ static void set_unit_figures(Model& M) {
   M.unit_bytes[KK_LIMITER] = 8.0 * (2.0 * r * n + nf) + n;
 }
 
-int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq) {
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq,
+                 double* d_basis) {
   Geom& g = M.g;
   long long& b = M.dev_bytes;
+  if (d_basis) {
+    M.d_phi = d_basis;
+    b += M.phi_len * (long long)sizeof(double);
+  }
   if (!dev_copy(&M.d_subs, M.subs.data(), M.subs.size(), b)) return LRBMS_E_OOM;
   if (!dev_copy(&M.d_ifaces, M.ifaces.data(), M.ifaces.size(), b)) return LRBMS_E_OOM;
-  if (!dev_copy(&M.d_phi, basis, (size_t)M.phi_len, b)) return LRBMS_E_OOM;
+  if (!d_basis && !dev_copy(&M.d_phi, basis, (size_t)M.phi_len, b)) return LRBMS_E_OOM;
   if (!dev_zero(&M.d_tr, (size_t)M.tr_len, b)) return LRBMS_E_OOM;
   if (!hip_ok(launch_face_traces(g, M.d_subs, M.d_ifaces, M.n_iface, M.d_phi, M.d_tr, 0), "face traces") ||
       !hip_ok(hipStreamSynchronize(0), "face traces"))
@@ -547,62 +552,21 @@ int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double
   return LRBMS_OK;
 }
 
-// Local Gram-Schmidt (Alg. 2 step 2e) of global snapshots restricted to every
-// box: optional unit function 1_E first, two passes against the current
-// basis, rejection when the remaining L2(E) norm is <= 1e-8 of the original.
-static void local_gram_schmidt(const Model& M, int nsnap, const double* snaps, int cap, bool unit,
-                               std::vector<int>& sizes, std::vector<double>& basis) {
-  const Geom& g = M.g;
-  const int r = g.r;
-  const size_t L = (size_t)r * g.ncell;
-  sizes.assign(M.n_sub, 0);
-  basis.clear();
-  for (int s = 0; s < M.n_sub; ++s) {
-    const Sub& S = M.subs[s];
-    const int nE = S.nE;
-    std::vector<int> cells(nE);
-    const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
-    for (int l = 0; l < nE; ++l) {
-      const int x = S.lo[0] + l % bx, y = S.lo[1] + (l / bx) % by, z = S.lo[2] + l / (bx * by);
-      cells[l] = x + g.n[0] * (y + g.n[1] * z);
-    }
-    std::vector<std::vector<double>> B;
-    const size_t len = (size_t)r * nE;
-    if (unit) {
-      std::vector<double> v(len, 0.0);
-      double nrm = 0.0;
-      for (int l = 0; l < nE; ++l) {
-        v[l] = std::sqrt(g.vol);
-        nrm += v[l] * v[l];
-      }
-      nrm = std::sqrt(nrm);
-      for (auto& x : v) x /= nrm;
-      B.push_back(v);
-    }
-    for (int q = 0; q < nsnap && (int)B.size() < cap; ++q) {
-      std::vector<double> v(len);
-      for (int k = 0; k < r; ++k)
-        for (int l = 0; l < nE; ++l) v[k * nE + l] = snaps[q * L + (size_t)k * g.ncell + cells[l]];
-      double nv = 0.0;
-      for (double x : v) nv += x * x;
-      nv = std::sqrt(nv);
-      if (nv == 0.0) continue;
-      for (int pass = 0; pass < 2; ++pass)
-        for (auto& bb : B) {
-          double dot = 0.0;
-          for (size_t i = 0; i < len; ++i) dot += bb[i] * v[i];
-          for (size_t i = 0; i < len; ++i) v[i] -= dot * bb[i];
-        }
-      double nw = 0.0;
-      for (double x : v) nw += x * x;
-      nw = std::sqrt(nw);
-      if (nw <= 1e-8 * nv) continue;
-      for (auto& x : v) x /= nw;
-      B.push_back(v);
-    }
-    sizes[s] = (int)B.size();
-    for (auto& bb : B) basis.insert(basis.end(), bb.begin(), bb.end());
+// A model whose bases are the device array d_basis (model layout, sizes per
+// box), which the model takes over; freed here when the creation fails.
+static int model_create_dev(const lrbms_problem* p, const std::vector<int>& sizes,
+                            double* d_basis, int nprof, const double* profiles,
+                            lrbms_model** out) {
+  std::unique_ptr<Model> M(new Model());
+  setup_layout(*M, p, sizes.data());
+  int rc = upload_problem(*M, p);
+  if (rc) {
+    (void)hipFree(d_basis);
+    return rc;
   }
+  if ((rc = model_finish(*M, nullptr, nprof, profiles, true, d_basis))) return rc;
+  *out = reinterpret_cast<lrbms_model*>(M.release());
+  return LRBMS_OK;
 }
 
 // Device array owned by a host scope.
@@ -840,35 +804,31 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
   OfflineCtx C;
   if ((rc = offline_profiles(p, o, C))) return rc;
   const size_t L = C.L;
-  // snapshots at gamma = sum_q mu_q Lambda^q
-  DevArray snap;
-  if (!snap.alloc(L)) return LRBMS_E_OOM;
-  std::vector<double> snaps((size_t)o->n_train * L);
+  // snapshots at gamma = sum_q mu_q Lambda^q, kept on the device
+  DevArray snaps;
+  if (!snaps.alloc((size_t)o->n_train * L)) return LRBMS_E_OOM;
   for (int i = 0; i < o->n_train; ++i) {
     if ((rc = combine_profiles(C, o->M, mu + (size_t)i * o->M))) return rc;
     int it = 0;
     double rr = 0.0;
     rc = fine_solve_checked(C.tmp, C.fs.s, C.field.p, GAMMA_FIELD, o->pcg_rtol, o->pcg_maxit,
-                            snap.p, &it, &rr);
+                            snaps.p + (size_t)i * L, &it, &rr);
     C.note(it, rr);
     if (rc) return rc;
-    if (!hip_ok(hipMemcpy(snaps.data() + (size_t)i * L, snap.p, L * sizeof(double),
-                          hipMemcpyDeviceToHost),
-                "snapshot"))
-      return LRBMS_E_HIP;
   }
-  // Alg. 2 step 2e: local bases
+  // Alg. 2 step 2e: local bases on the device
   std::vector<int> sizes;
-  std::vector<double> basis;
-  local_gram_schmidt(C.tmp, o->n_train, snaps.data(), o->ne_cap, o->unit_functions != 0, sizes,
-                     basis);
-  for (int sz : sizes)
-    if (sz < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
+  double* d_basis = nullptr;
+  long long len = 0;
+  if ((rc = local_bases_device(C.tmp.g, C.tmp.subs, snaps.p, o->n_train, o->ne_cap,
+                               o->unit_functions != 0, o->basis_method, o->pca_eps, sizes,
+                               &d_basis, len)))
+    return rc;
   const std::vector<double> kept = kept_profiles(C, o->M, o->keep_profiles != 0);
   C.R.n_profiles_kept = (int)(kept.size() / L);
   if (rep) *rep = C.R;
-  return model_create_impl(p, sizes.data(), basis.data(), C.R.n_profiles_kept,
-                           kept.empty() ? nullptr : kept.data(), out);
+  return model_create_dev(p, sizes, d_basis, C.R.n_profiles_kept,
+                          kept.empty() ? nullptr : kept.data(), out);
 }
 
 // Gram-Schmidt extension of one local basis (L2(E), two passes, rejection of
@@ -1107,7 +1067,8 @@ int lrbms_model_create(const lrbms_problem* prob, const int32_t* basis_sizes, co
 
 int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
                                       const double* snapshots, int32_t ne_cap,
-                                      int32_t unit_functions, int32_t n_profiles,
+                                      int32_t unit_functions, int32_t basis_method,
+                                      double pca_eps, int32_t n_profiles,
                                       const double* profiles, lrbms_model** out) {
   try {
     if (!out) return (set_error("out is NULL"), LRBMS_E_ARG);
@@ -1116,14 +1077,25 @@ int lrbms_model_create_from_snapshots(const lrbms_problem* prob, int32_t n_snap,
     if (rc) return rc;
     if (n_snap < 0 || (n_snap > 0 && !snapshots) || ne_cap < 1 || ne_cap > 63)
       return (set_error("invalid snapshots or cap"), LRBMS_E_ARG);
+    if (n_profiles < 0 || n_profiles > kMaxProfiles || (n_profiles > 0 && !profiles))
+      return (set_error("invalid profiles"), LRBMS_E_ARG);
     Model tmp;
     setup_layout(tmp, prob, nullptr);
+    // the snapshots go to the device once; Alg. 2 step 2e runs there
+    const size_t L = (size_t)tmp.g.r * tmp.g.ncell;
+    DevArray snaps;
+    if (!snaps.alloc((size_t)n_snap * L)) return LRBMS_E_OOM;
+    if (n_snap > 0 && !hip_ok(hipMemcpy(snaps.p, snapshots, (size_t)n_snap * L * sizeof(double),
+                                        hipMemcpyHostToDevice),
+                              "snapshots"))
+      return LRBMS_E_HIP;
     std::vector<int> sizes;
-    std::vector<double> basis;
-    local_gram_schmidt(tmp, n_snap, snapshots, ne_cap, unit_functions != 0, sizes, basis);
-    for (int s : sizes)
-      if (s < 1) return (set_error("a box received an empty local basis"), LRBMS_E_ARG);
-    return model_create_impl(prob, sizes.data(), basis.data(), n_profiles, profiles, out);
+    double* d_basis = nullptr;
+    long long len = 0;
+    if ((rc = local_bases_device(tmp.g, tmp.subs, snaps.p, n_snap, ne_cap, unit_functions != 0,
+                                 basis_method, pca_eps, sizes, &d_basis, len)))
+      return rc;
+    return model_create_dev(prob, sizes, d_basis, n_profiles, profiles, out);
   } catch (const std::exception& e) {
     set_error(e.what());
     return LRBMS_E_OOM;

@@ -208,6 +208,15 @@ int tof_solve_bufs(const Geom& g, const double* d_flux, double tol, int maxit, d
 // Padded column count of the assembly tiles (N_E + 1 rounded up to 16) and
 // the number of workgroups of the least-squares projection.
 int assemble_cols(int max_ne);
+// Local bases of the device snapshots d_snaps ([nsnap][r*ncell]) in every
+// box of subs: Gram-Schmidt (LRBMS_BASIS_GS, Alg. 2 step 2e) or the method
+// of snapshots (LRBMS_BASIS_PCA with pca_eps, Alg. 2 step 3; at most 64
+// snapshots).  sizes receives N_E per box, *d_basis a new device array of
+// len doubles in the model's basis layout (the caller frees it).
+// Synchronous.
+int local_bases_device(const Geom& g, const std::vector<Sub>& subs, const double* d_snaps,
+                       int nsnap, int cap, bool unit, int method, double pca_eps,
+                       std::vector<int>& sizes, double** d_basis, long long& len);
 int lsq_blocks(int ncell);
 
 }  // namespace lrbms

@@ -59,7 +59,10 @@ struct Model {
 
 // lsq: the profiles are independent and the model fits theta from s (AFFINE,
 // DIRECT_FIT); without it the affine terms serve a caller-given theta only.
-int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq);
+// basis: host bases in the model layout, or d_basis: device bases the model
+// takes over (freed with the model, also when this fails).
+int model_finish(Model& M, const double* basis, int nprof, const double* profiles, bool lsq,
+                 double* d_basis = nullptr);
 int model_create_impl(const lrbms_problem* p, const int32_t* sizes, const double* basis, int nprof,
                       const double* profiles, lrbms_model** out);
 

@@ -65,7 +65,11 @@ class OfflineOpts_C(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_train", C.c_int32), ("ne_cap", C.c_int32),
                 ("unit_functions", C.c_int32), ("horizon", C.c_double), ("pcg_rtol", C.c_double),
                 ("pcg_maxit", C.c_int32), ("tof_tol", C.c_double), ("tof_maxit", C.c_int32),
-                ("keep_profiles", C.c_int32), ("d_s0", C.c_void_p)]
+                ("keep_profiles", C.c_int32), ("d_s0", C.c_void_p), ("basis_method", C.c_int32),
+                ("pca_eps", C.c_double)]
+
+
+BASIS_METHODS = {"gs": 0, "pca": 1}   # LRBMS_BASIS_GS, LRBMS_BASIS_PCA
 
 
 class OfflineReport_C(C.Structure):
@@ -92,7 +96,8 @@ def lib():
         vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
         L.lrbms_last_error.restype = C.c_char_p
         L.lrbms_model_create.argtypes = [vp, vp, vp, i32, vp, C.POINTER(vp)]
-        L.lrbms_model_create_from_snapshots.argtypes = [vp, i32, vp, i32, i32, i32, vp, C.POINTER(vp)]
+        L.lrbms_model_create_from_snapshots.argtypes = [vp, i32, vp, i32, i32, i32, C.c_double,
+                                                        i32, vp, C.POINTER(vp)]
         L.lrbms_model_get_info.argtypes = [vp, vp]
         L.lrbms_model_export_basis.argtypes = [vp, vp, vp]
         L.lrbms_model_interfaces.argtypes = [vp, vp, vp, vp]
@@ -259,7 +264,10 @@ class Model:
         return m
 
     @classmethod
-    def from_snapshots(cls, prob, snapshots, ne_cap: int, unit_functions=True, profiles=None):
+    def from_snapshots(cls, prob, snapshots, ne_cap: int, unit_functions=True, profiles=None,
+                       method: str = "gs", pca_eps: float = 1e-4):
+        """Local bases from host snapshots by Gram-Schmidt or PCA on the device
+        (lrbms_model_create_from_snapshots)."""
         pc = ProblemC(prob)
         sn = np.ascontiguousarray(np.stack(snapshots), dtype=np.float64)
         prof = None if profiles is None or len(profiles) == 0 else \
@@ -267,13 +275,14 @@ class Model:
         h = C.c_void_p()
         _check(lib().lrbms_model_create_from_snapshots(
             pc.ref(), sn.shape[0], _ptr(sn), int(ne_cap), int(bool(unit_functions)),
-            0 if prof is None else prof.shape[0], _ptr(prof), C.byref(h)))
+            BASIS_METHODS[method], float(pca_eps), 0 if prof is None else prof.shape[0],
+            _ptr(prof), C.byref(h)))
         return cls(h, prob)
 
     @classmethod
     def build_offline(cls, prob, mu, ne_cap: int, horizon: float, unit_functions=True,
                       keep_profiles=True, pcg_rtol=1e-13, pcg_maxit=20000, tof_tol=1e-14,
-                      tof_maxit=100000, s0=None):
+                      tof_maxit=100000, s0=None, method: str = "gs", pca_eps: float = 1e-4):
         """Offline stage on the device (lrbms_build_offline_bases); mu is the
         (n_train, M) array of training parameters, s0 an optional device
         saturation whose flow defines the time of flight.  Returns (model,
@@ -284,7 +293,8 @@ class Model:
                           unit_functions=int(bool(unit_functions)), horizon=float(horizon),
                           pcg_rtol=float(pcg_rtol), pcg_maxit=int(pcg_maxit),
                           tof_tol=float(tof_tol), tof_maxit=int(tof_maxit),
-                          keep_profiles=int(bool(keep_profiles)), d_s0=_ptr(s0) or None)
+                          keep_profiles=int(bool(keep_profiles)), d_s0=_ptr(s0) or None,
+                          basis_method=BASIS_METHODS[method], pca_eps=float(pca_eps))
         rep = OfflineReport_C()
         h = C.c_void_p()
         _check(lib().lrbms_build_offline_bases(pc.ref(), C.byref(o), _ptr(mu), C.byref(h),

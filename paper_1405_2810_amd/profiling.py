@@ -72,6 +72,7 @@ _ASM = ("assemble.hip", "swip.h", "common.h")
 _SOLVER = ("solver.hip", "solver.h", "common.h")
 _TRANSPORT = ("transport.hip", "common.h")
 _OFFLINE = ("offline.hip", "swip.h", "common.h")
+_BASES = ("bases.hip", "common.h")
 KERNEL_SOURCE = {
     "k_moments": _ASM, "k_lsq": _ASM, "k_lsq_partial": _ASM, "k_lsq_final": _ASM,
     "k_affine_sum": _ASM, "k_asm_box": _ASM, "k_reduce_box": _ASM, "k_asm_iface": _ASM,
@@ -85,6 +86,7 @@ KERNEL_SOURCE = {
                              "k_mg0_down", "k_mg0_up", "k_mgl_down", "k_mgl_up", "k_mg_coarse",
                              "k_power", "k_power_start", "k_cg_init", "k_cg_direction",
                              "k_cg_update", "k_tof_setup", "k_tof_sweep")},
+    **{k: _BASES for k in ("k_local_gs", "k_local_pca", "k_basis_compact")},
 }
 
 

@@ -220,3 +220,60 @@ def test_build_offline_bases(L, name):
     T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
     m, rep = L.Model.build_offline(p, params, ne_cap=p.ne_cap, horizon=T, pcg_rtol=RTOL)
     check_offline(name, p, g, params, ref, m, rep, T)
+
+
+def _box_bases(model, g, p):
+    sizes, flat = model.export_basis()
+    out, off = [], 0
+    for cells, NE in zip(subdomain_cells(g, p), sizes):
+        n = int(NE) * g.r * len(cells)
+        out.append(flat[off:off + n].reshape(int(NE), g.r * len(cells)))
+        off += n
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "small2d", "small3d", "cfg1"])
+def test_local_bases_gs_and_pca(L, name):
+    """Local bases of Alg. 2 steps 2e (Gram-Schmidt) and 3 (PCA, the method
+    of snapshots) on the device against the oracle's local_bases from the
+    same seeded snapshots: same sizes per box, orthonormal, 1_E first, the
+    same spans (projectors within 1e-7); for PCA also the energy criterion
+    itself: the snapshots' components off 1_E keep at most eps^2 of their
+    energy outside the span (pinned without the oracle)."""
+    from synth import smooth_fields
+    from oracle.offline import local_bases
+    p = make_problem(name)
+    g = Grid(p)
+    snaps = smooth_fields(p, 12, np.random.default_rng(17))
+    eps = 0.1   # truncates: 7..9 of the 12 modes per box are kept
+    for method in ("gs", "pca"):
+        cap = p.ne_cap if method == "gs" else 63
+        ref = local_bases(g, p, snaps, method=method, cap=cap, unit=True, eps=eps)
+        m = L.Model.from_snapshots(p, snaps, ne_cap=cap, unit_functions=True, method=method,
+                                   pca_eps=eps)
+        try:
+            got = _box_bases(m, g, p)
+            worst, energy = 0.0, 0.0
+            for cells, phi, phr in zip(subdomain_cells(g, p), got, ref):
+                phr = phr.reshape(phr.shape[0], -1)
+                assert phi.shape == phr.shape, (method, phi.shape, phr.shape)
+                assert np.abs(phi @ phi.T - np.eye(phi.shape[0])).max() <= 1e-12
+                unit = np.zeros(phi.shape[1])
+                unit[:len(cells)] = 1.0 / math.sqrt(len(cells))
+                assert np.abs(phi[0] - unit).max() <= 1e-15
+                worst = max(worst, np.abs(phi.T @ phi - phr.T @ phr).max())
+                if method == "pca":
+                    X = np.stack([np.concatenate([s[k * g.ncell + cells] for k in range(g.r)])
+                                  for s in snaps])
+                    X = X - np.outer(X @ unit, unit)
+                    rest = X - (X @ phi.T) @ phi
+                    tot = float((X * X).sum())
+                    energy = max(energy, float((rest * rest).sum()) / tot if tot > 0 else 0.0)
+            log(f"{name} {method}: sizes {[b.shape[0] for b in got][:8]}..., projector "
+                f"difference {worst:.2e}" + (f", kept energy loss {energy:.2e} <= eps^2 "
+                                             f"{eps * eps:.1e}" if method == "pca" else ""))
+            assert worst <= 1e-7
+            if method == "pca":
+                assert energy <= eps * eps * (1 + 1e-6) + 1e-14
+        finally:
+            m.close()
