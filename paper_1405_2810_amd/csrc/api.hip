@@ -831,34 +831,16 @@ static int build_offline_impl(const lrbms_problem* p, const lrbms_offline_opts* 
                           kept.empty() ? nullptr : kept.data(), out);
 }
 
-// Gram-Schmidt extension of one local basis (L2(E), two passes, rejection of
-// remaining norms <= 1e-8 of the original).
-static bool gs_extend(std::vector<std::vector<double>>& B, std::vector<double> v) {
-  double nv = 0.0;
-  for (double x : v) nv += x * x;
-  nv = std::sqrt(nv);
-  if (nv == 0.0) return false;
-  for (int pass = 0; pass < 2; ++pass)
-    for (auto& b : B) {
-      double d = 0.0;
-      for (size_t i = 0; i < v.size(); ++i) d += b[i] * v[i];
-      for (size_t i = 0; i < v.size(); ++i) v[i] -= d * b[i];
-    }
-  double nw = 0.0;
-  for (double x : v) nw += x * x;
-  nw = std::sqrt(nw);
-  if (nw <= 1e-8 * nv) return false;
-  for (auto& x : v) x /= nw;
-  B.push_back(std::move(v));
-  return true;
-}
-
 // Alg. 2 step 2 (the greedy basis extension) with the true energy-norm error
-// of Sec. 6: the fine snapshots of the whole training set are computed first
-// (one batch of fine solves), then every iteration solves the reduced system
-// of every training parameter on the device (affine terms with theta = mu),
-// measures |p_H - p_h| in the energy norm of b_h(., .; sum_q mubar_q Lambda^q),
-// and extends every local basis with the worst parameter's snapshot.
+// of Sec. 6.  The fine snapshots of the whole training set are computed
+// first and stay on the device, and so do the local bases, which grow there
+// (Gram-Schmidt of the worst parameter's snapshot in every box).  Every
+// iteration builds the reduced model of the current bases (affine terms),
+// solves the reduced systems of all training parameters (theta = mu) as one
+// fused solve per chunk of up to 64 parameters (the model's plan repeated,
+// members side by side), reconstructs their pressures and measures every
+// |p_H - p_h| in the energy norm of b_h(., .; sum_q mubar_q Lambda^q) with
+// one read-back per chunk.
 static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o,
                              const double* mu, int n_max, double tol, const double* mu_bar,
                              lrbms_model** out, int32_t* chosen, double* errors, int max_iter,
@@ -875,8 +857,11 @@ static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o
   const size_t L = C.L;
   const int nt = o->n_train, nq = o->M;
   // every training snapshot, resident on the device
-  DevArray snaps, ph, pN;
-  if (!snaps.alloc((size_t)nt * L) || !ph.alloc(L)) return LRBMS_E_OOM;
+  DevArray snaps, theta;
+  if (!snaps.alloc((size_t)nt * L) || !theta.alloc((size_t)nt * nq)) return LRBMS_E_OOM;
+  if (!hip_ok(hipMemcpy(theta.p, mu, (size_t)nt * nq * sizeof(double), hipMemcpyHostToDevice),
+              "training parameters"))
+    return LRBMS_E_HIP;
   for (int i = 0; i < nt; ++i) {
     if ((rc = combine_profiles(C, nq, mu + (size_t)i * nq))) return rc;
     int it = 0;
@@ -892,64 +877,90 @@ static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o
     for (int q = 0; q < nq; ++q) wbar[q] = mu_bar[q];
   if ((rc = combine_profiles(C, nq, wbar.data()))) return rc;
   if ((rc = fine_energy_setup(C.fs.s, C.tmp.d_mom, C.field.p))) return rc;
-  // local bases, empty at the start
+  // local bases, empty at the start, grown on the device
   const Model& T = C.tmp;
-  std::vector<std::vector<int>> cells(T.n_sub);
-  for (int sb = 0; sb < T.n_sub; ++sb) {
-    const Sub& S = T.subs[sb];
-    const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
-    for (int l = 0; l < S.nE; ++l) {
-      const int x = S.lo[0] + l % bx, y = S.lo[1] + (l / bx) % by, z = S.lo[2] + l / (bx * by);
-      cells[sb].push_back(x + T.g.n[0] * (y + T.g.n[1] * z));
-    }
-  }
-  std::vector<std::vector<std::vector<double>>> B(T.n_sub);
-  std::vector<double> err(nt), h_snap(L);
+  DeviceBases GB;
+  if ((rc = device_bases_init(T.g, T.subs, 63, GB))) return rc;
+  std::vector<double> err(nt);
   int iters = 0;
-  const int r = T.g.r, nc = T.g.ncell;
-  auto flat_basis = [&](std::vector<int>& sizes, std::vector<double>& basis) {
-    sizes.assign(T.n_sub, 0);
-    basis.clear();
-    for (int sb = 0; sb < T.n_sub; ++sb) {
-      sizes[sb] = (int)B[sb].size();
-      for (auto& v : B[sb]) basis.insert(basis.end(), v.begin(), v.end());
-    }
-  };
+  constexpr int kChunk = 64;
   while (true) {
     int total = 0;
-    for (auto& b : B) total += (int)b.size();
+    for (int sz : GB.sizes) total += sz;
     if (total == 0) {
-      for (int i = 0; i < nt; ++i)
-        if ((rc = fine_energy_diff(C.fs.s, snaps.p + (size_t)i * L, nullptr, &err[i]))) return rc;
+      if ((rc = fine_energy_diff_batch(C.fs.s, snaps.p, (long long)L, nullptr, 0, nt, err.data())))
+        return rc;
     } else {
-      // the reduced model of the current bases with every profile (theta = mu)
-      std::vector<int> sizes;
-      std::vector<double> basis;
-      flat_basis(sizes, basis);
-      for (int sz : sizes)
+      for (int sz : GB.sizes)
         if (sz < 1 || sz > 63)
           return (set_error("greedy: a local basis is empty or above 63 functions"), LRBMS_E_ARG);
+      // the reduced model of the current bases with every profile (theta = mu)
+      double* d_basis = nullptr;
+      long long len = 0;
+      if ((rc = device_bases_compact(T.g, T.subs, GB, &d_basis, len))) return rc;
       std::unique_ptr<Model> RM(new Model());
-      setup_layout(*RM, p, sizes.data());
-      if ((rc = upload_problem(*RM, p))) return rc;
-      if ((rc = model_finish(*RM, basis.data(), nq, C.prof.data(), false))) return rc;
-      if (!pN.alloc(RM->N)) return LRBMS_E_OOM;
-      for (int i = 0; i < nt; ++i) {
-        if (!hip_ok(hipMemcpy(RM->d_theta, mu + (size_t)i * nq, nq * sizeof(double),
-                              hipMemcpyHostToDevice),
-                    "theta") ||
-            !hip_ok(launch_affine_sum(RM->d_c, RM->d_bq, RM->nblk, RM->d_theta, nq, RM->d_blocks, 0),
-                    "affine sum") ||
-            !hip_ok(launch_affine_sum(RM->d_e, RM->d_dq, RM->N, RM->d_theta, nq, RM->d_fN, 0),
-                    "affine sum") ||
-            !hip_ok(solver_factor_solve(RM->plan, RM->sdev, RM->d_blocks, RM->d_fN, pN.p,
-                                        RM->d_status, 0, RM->refine),
-                    "reduced solve") ||
-            !hip_ok(launch_reconstruct(RM->g, RM->d_subs, RM->n_sub, RM->d_tiles, RM->n_tiles,
-                                       RM->d_phi, pN.p, ph.p, 0),
-                    "reconstruct"))
+      setup_layout(*RM, p, GB.sizes.data());
+      if ((rc = upload_problem(*RM, p))) {
+        (void)hipFree(d_basis);
+        return rc;
+      }
+      if ((rc = model_finish(*RM, nullptr, nq, C.prof.data(), false, d_basis))) return rc;
+      // the training parameters' reduced solves, up to kChunk side by side
+      const int cn = std::min(nt, kChunk);
+      std::vector<const SolverPlan*> plans(cn, &RM->plan);
+      std::vector<long long> blk_base(cn), pn_base(cn);
+      for (int i = 0; i < cn; ++i) {
+        blk_base[i] = (long long)i * RM->nblk;
+        pn_base[i] = (long long)i * RM->N;
+      }
+      SolverPlan CP;
+      if (!combine_plans(plans, blk_base, pn_base, CP) ||
+          !plan_in_bounds(CP, (long long)cn * RM->nblk, (long long)cn * RM->N))
+        return (set_error("greedy: reduced solves cannot be combined"), LRBMS_E_ARG);
+      SolverDev CD;
+      struct Free {
+        SolverDev& d;
+        ~Free() { solver_free(d); }
+      } free_cd{CD};
+      if (!solver_upload(CP, CD)) return (set_error("greedy: solver allocation failed"), LRBMS_E_OOM);
+      DevArray blocks, fN, pN, ph, mask;
+      if (!blocks.alloc((size_t)cn * RM->nblk) || !fN.alloc((size_t)cn * RM->N) ||
+          !pN.alloc((size_t)cn * RM->N) || !ph.alloc((size_t)cn * L) || !mask.alloc(cn))
+        return LRBMS_E_OOM;
+      for (int c0 = 0; c0 < nt; c0 += cn) {
+        const int cc = std::min(cn, nt - c0);
+        for (int i = 0; i < cc; ++i) {
+          const double* th = theta.p + (size_t)(c0 + i) * nq;
+          if (!hip_ok(launch_affine_sum(RM->d_c, RM->d_bq, RM->nblk, th, nq,
+                                        blocks.p + (size_t)i * RM->nblk, 0),
+                      "affine sum") ||
+              !hip_ok(launch_affine_sum(RM->d_e, RM->d_dq, RM->N, th, nq,
+                                        fN.p + (size_t)i * RM->N, 0),
+                      "affine sum"))
+            return LRBMS_E_HIP;
+        }
+        // a short last chunk masks the members it does not use
+        const int* active = nullptr;
+        if (cc < cn) {
+          std::vector<int> m(cn, 0);
+          for (int i = 0; i < cc; ++i) m[i] = 1;
+          if (!hip_ok(hipMemcpy(mask.p, m.data(), cn * sizeof(int), hipMemcpyHostToDevice), "mask"))
+            return LRBMS_E_HIP;
+          active = reinterpret_cast<const int*>(mask.p);
+        }
+        if (!hip_ok(solver_factor_solve(CP, CD, blocks.p, fN.p, pN.p, RM->d_status, 0,
+                                        RM->refine, active),
+                    "reduced solves"))
           return LRBMS_E_HIP;
-        if ((rc = fine_energy_diff(C.fs.s, ph.p, snaps.p + (size_t)i * L, &err[i]))) return rc;
+        for (int i = 0; i < cc; ++i)
+          if (!hip_ok(launch_reconstruct(RM->g, RM->d_subs, RM->n_sub, RM->d_tiles, RM->n_tiles,
+                                         RM->d_phi, pN.p + (size_t)i * RM->N,
+                                         ph.p + (size_t)i * L, 0),
+                      "reconstruct"))
+            return LRBMS_E_HIP;
+        if ((rc = fine_energy_diff_batch(C.fs.s, ph.p, (long long)L, snaps.p + (size_t)c0 * L,
+                                         (long long)L, cc, err.data() + c0)))
+          return rc;
       }
       int st = 0;
       if (!hip_ok(hipMemcpy(&st, RM->d_status, sizeof(int), hipMemcpyDeviceToHost), "status"))
@@ -965,31 +976,21 @@ static int build_greedy_impl(const lrbms_problem* p, const lrbms_offline_opts* o
     ++iters;
     if (err[k] <= tol || total >= n_max || iters > 63) break;
     if (chosen && iters - 1 < max_iter) chosen[iters - 1] = k;
-    if (!hip_ok(hipMemcpy(h_snap.data(), snaps.p + (size_t)k * L, L * sizeof(double),
-                          hipMemcpyDeviceToHost),
-                "snapshot"))
-      return LRBMS_E_HIP;
     bool grew = false;
-    for (int sb = 0; sb < T.n_sub; ++sb) {
-      const int nE = (int)cells[sb].size();
-      std::vector<double> v((size_t)r * nE);
-      for (int kk = 0; kk < r; ++kk)
-        for (int l = 0; l < nE; ++l) v[(size_t)kk * nE + l] = h_snap[(size_t)kk * nc + cells[sb][l]];
-      grew = gs_extend(B[sb], std::move(v)) || grew;
-    }
+    if ((rc = device_bases_extend(T.g, GB, snaps.p + (size_t)k * L, grew))) return rc;
     if (!grew) break;
   }
   if (n_iter) *n_iter = iters;
-  std::vector<int> sizes;
-  std::vector<double> basis;
-  flat_basis(sizes, basis);
-  for (int sz : sizes)
+  for (int sz : GB.sizes)
     if (sz < 1) return (set_error("greedy: a box received an empty local basis"), LRBMS_E_ARG);
+  double* d_basis = nullptr;
+  long long len = 0;
+  if ((rc = device_bases_compact(T.g, T.subs, GB, &d_basis, len))) return rc;
   const std::vector<double> kept = kept_profiles(C, nq, o->keep_profiles != 0);
   C.R.n_profiles_kept = (int)(kept.size() / L);
   if (rep) *rep = C.R;
-  return model_create_impl(p, sizes.data(), basis.data(), C.R.n_profiles_kept,
-                           kept.empty() ? nullptr : kept.data(), out);
+  return model_create_dev(p, GB.sizes, d_basis, C.R.n_profiles_kept,
+                          kept.empty() ? nullptr : kept.data(), out);
 }
 
 // Transport step (Def. saturationDG) and the limiter (eq. limiterMain) on a

@@ -321,6 +321,30 @@ __global__ __launch_bounds__(256) void k_basis_compact(const Sub* __restrict__ s
   for (long long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+// Box s: the restriction of one snapshot into the next free slot, kept by
+// the Gram-Schmidt step of k_local_gs (sizes[s] grows by one) unless it is
+// rejected or the box holds cap functions already.
+__global__ __launch_bounds__(kGsThreads) void k_extend_gs(Geom g, const Sub* __restrict__ subs,
+                                                         const long long* __restrict__ slot_off,
+                                                         const double* __restrict__ snap, int cap,
+                                                         double* __restrict__ slots,
+                                                         int* __restrict__ sizes) {
+  __shared__ double red[4];
+  const Sub S = subs[blockIdx.x];
+  const int nE = S.nE, nb = sizes[blockIdx.x];
+  if (nb >= cap) return;
+  const long long len = (long long)g.r * nE;
+  const int bx = S.hi[0] - S.lo[0], by = S.hi[1] - S.lo[1];
+  double* base = slots + slot_off[blockIdx.x];
+  double* v = base + (long long)nb * len;
+  for (long long i = threadIdx.x; i < len; i += kGsThreads) {
+    const int k = (int)(i / nE), l = (int)(i % nE);
+    const int x[3] = {S.lo[0] + l % bx, S.lo[1] + (l / bx) % by, S.lo[2] + l / (bx * by)};
+    v[i] = snap[(long long)k * g.ncell + cell_index(g, x)];
+  }
+  if (gs_extend_slot(base, len, nb, red) && threadIdx.x == 0) sizes[blockIdx.x] = nb + 1;
+}
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
@@ -399,6 +423,84 @@ int local_bases_device(const Geom& g, const std::vector<Sub>& subs, const double
   }
   *d_basis = out;
   return LRBMS_OK;
+}
+
+int device_bases_init(const Geom& g, const std::vector<Sub>& subs, int cap, DeviceBases& B) {
+  device_bases_free(B);
+  B.cap = cap;
+  B.n = (int)subs.size();
+  B.sizes.assign(B.n, 0);
+  B.slot_off.assign(B.n, 0);
+  long long total = 0;
+  for (int s = 0; s < B.n; ++s) {
+    B.slot_off[s] = total;
+    total += (long long)cap * g.r * subs[s].nE;
+  }
+  if (hipMalloc(&B.d_subs, std::max(B.n, 1) * sizeof(Sub)) != hipSuccess ||
+      hipMalloc(&B.d_slot_off, std::max(B.n, 1) * sizeof(long long)) != hipSuccess ||
+      hipMalloc(&B.d_sizes, std::max(B.n, 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(&B.d_slots, std::max<long long>(total, 1) * sizeof(double)) != hipSuccess)
+    return (set_error("local bases: device allocation failed"), LRBMS_E_OOM);
+  if (!hip_ok(hipMemcpy(B.d_subs, subs.data(), B.n * sizeof(Sub), hipMemcpyHostToDevice), "subs") ||
+      !hip_ok(hipMemcpy(B.d_slot_off, B.slot_off.data(), B.n * sizeof(long long),
+                        hipMemcpyHostToDevice),
+              "offsets") ||
+      !hip_ok(hipMemset(B.d_sizes, 0, std::max(B.n, 1) * sizeof(int)), "sizes"))
+    return LRBMS_E_HIP;
+  return LRBMS_OK;
+}
+
+int device_bases_extend(const Geom& g, DeviceBases& B, const double* d_snap, bool& grew) {
+  hipLaunchKernelGGL(k_extend_gs, dim3(B.n), dim3(kGsThreads), 0, 0, g, B.d_subs, B.d_slot_off,
+                     d_snap, B.cap, B.d_slots, B.d_sizes);
+  std::vector<int> now(B.n);
+  if (!hip_ok(hipGetLastError(), "basis extension") ||
+      !hip_ok(hipMemcpy(now.data(), B.d_sizes, B.n * sizeof(int), hipMemcpyDeviceToHost), "sizes"))
+    return LRBMS_E_HIP;
+  grew = false;
+  for (int s = 0; s < B.n; ++s) grew = grew || now[s] != B.sizes[s];
+  B.sizes = now;
+  return LRBMS_OK;
+}
+
+int device_bases_compact(const Geom& g, const std::vector<Sub>& subs, const DeviceBases& B,
+                         double** d_basis, long long& len) {
+  *d_basis = nullptr;
+  std::vector<long long> out_off(B.n);
+  len = 0;
+  for (int s = 0; s < B.n; ++s) {
+    out_off[s] = len;
+    len += (long long)B.sizes[s] * g.r * subs[s].nE;
+  }
+  DevBuf<long long> d_out_off;
+  double* out = nullptr;
+  if (!d_out_off.alloc(B.n) ||
+      hipMalloc(&out, std::max<long long>(len, 1) * sizeof(double)) != hipSuccess)
+    return (set_error("local bases: device allocation failed"), LRBMS_E_OOM);
+  if (!hip_ok(hipMemcpy(d_out_off.p, out_off.data(), B.n * sizeof(long long),
+                        hipMemcpyHostToDevice),
+              "offsets")) {
+    (void)hipFree(out);
+    return LRBMS_E_HIP;
+  }
+  hipLaunchKernelGGL(k_basis_compact, dim3(B.n), dim3(256), 0, 0, B.d_subs, g.r, B.d_slot_off,
+                     d_out_off.p, B.d_sizes, B.d_slots, out);
+  if (!hip_ok(hipGetLastError(), "basis layout") ||
+      !hip_ok(hipStreamSynchronize(0), "basis layout")) {
+    (void)hipFree(out);
+    return LRBMS_E_HIP;
+  }
+  *d_basis = out;
+  return LRBMS_OK;
+}
+
+void device_bases_free(DeviceBases& B) {
+  for (void* q : {(void*)B.d_subs, (void*)B.d_slot_off, (void*)B.d_sizes, (void*)B.d_slots})
+    if (q) (void)hipFree(q);
+  B.d_subs = nullptr;
+  B.d_slot_off = nullptr;
+  B.d_sizes = nullptr;
+  B.d_slots = nullptr;
 }
 
 }  // namespace lrbms

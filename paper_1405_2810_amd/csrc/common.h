@@ -196,6 +196,8 @@ int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind,
 // given once by fine_energy_setup (the greedy error measure).
 int fine_energy_setup(FineSolver* S, double* mom, const double* field);
 int fine_energy_diff(FineSolver* S, const double* a, const double* b, double* out);
+int fine_energy_diff_batch(FineSolver* S, const double* a, long long as, const double* b,
+                           long long bs, int n, double* out);
 int tof_solve(const Geom& g, const double* d_flux, double tol, int maxit, double* d_tau,
               int* d_status, int* sweeps);
 // The time of flight on caller-given work memory (no allocation):
@@ -217,6 +219,30 @@ int assemble_cols(int max_ne);
 int local_bases_device(const Geom& g, const std::vector<Sub>& subs, const double* d_snaps,
                        int nsnap, int cap, bool unit, int method, double pca_eps,
                        std::vector<int>& sizes, double** d_basis, long long& len);
+// Local bases grown one function at a time on the device (the greedy
+// extension of Alg. 2 step 2): room for cap functions per box.
+struct DeviceBases;
+void device_bases_free(DeviceBases& B);
+struct DeviceBases {
+  int cap = 0, n = 0;
+  std::vector<int> sizes;              // functions per box (host copy)
+  std::vector<long long> slot_off;     // first slot of each box
+  Sub* d_subs = nullptr;
+  long long* d_slot_off = nullptr;
+  int* d_sizes = nullptr;
+  double* d_slots = nullptr;
+  DeviceBases() = default;
+  DeviceBases(const DeviceBases&) = delete;
+  DeviceBases& operator=(const DeviceBases&) = delete;
+  ~DeviceBases() { device_bases_free(*this); }
+};
+int device_bases_init(const Geom& g, const std::vector<Sub>& subs, int cap, DeviceBases& B);
+// Gram-Schmidt of the restrictions of d_snap ([r*ncell]) into every box's
+// basis; grew: some box kept it.  Synchronous.
+int device_bases_extend(const Geom& g, DeviceBases& B, const double* d_snap, bool& grew);
+// The bases in the model layout: a new device array of len doubles.
+int device_bases_compact(const Geom& g, const std::vector<Sub>& subs, const DeviceBases& B,
+                         double** d_basis, long long& len);
 int lsq_blocks(int ncell);
 
 }  // namespace lrbms

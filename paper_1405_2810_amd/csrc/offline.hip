@@ -1174,6 +1174,47 @@ int fine_energy_diff(FineSolver* S, const double* a, const double* b, double* ou
   return std::isfinite(*out) ? LRBMS_OK : LRBMS_E_NONFINITE;
 }
 
+// |a_i - b_i|^2 (b nullable) for n pairs a_i = a + i as, b_i = b + i bs: the
+// kernels of fine_energy_diff per pair, the partial sums of all pairs read
+// back at once and summed on the host in the same order.
+int fine_energy_diff_batch(FineSolver* S, const double* a, long long as, const double* b,
+                           long long bs, int n, double* out) {
+  if (!S->have_bar) return LRBMS_E_STATE;
+  if (n <= 0) return LRBMS_OK;
+  const Geom& g = S->g;
+  const long long len = (long long)g.r * g.ncell;
+  double* e = S->ework.p;
+  double* parts = nullptr;
+  if (hipMalloc(&parts, (size_t)n * S->nbc * sizeof(double)) != hipSuccess) return LRBMS_E_OOM;
+  for (int i = 0; i < n; ++i) {
+    const double* ai = a + (long long)i * as;
+    if (b) {
+      hipLaunchKernelGGL(k_diff, dim3(blocks_for(len)), dim3(kBlk), 0, 0, len, ai,
+                         b + (long long)i * bs, e);
+    } else if (hipMemcpyAsync(e, ai, len * sizeof(double), hipMemcpyDeviceToDevice, 0) !=
+               hipSuccess) {
+      (void)hipFree(parts);
+      return LRBMS_E_HIP;
+    }
+    double* pr = parts + (size_t)i * S->nbc;
+    if (g.dim == 2)
+      hipLaunchKernelGGL(k_energy<2>, dim3(S->nbc), dim3(kBlk), 0, 0, g, S->Kbar.p, e, pr);
+    else
+      hipLaunchKernelGGL(k_energy<3>, dim3(S->nbc), dim3(kBlk), 0, 0, g, S->Kbar.p, e, pr);
+  }
+  std::vector<double> h((size_t)n * S->nbc);
+  const hipError_t err = hipMemcpy(h.data(), parts, h.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost);
+  (void)hipFree(parts);
+  if (err != hipSuccess) return LRBMS_E_HIP;
+  for (int i = 0; i < n; ++i) {
+    out[i] = host_sum(std::vector<double>(h.begin() + (size_t)i * S->nbc,
+                                          h.begin() + (size_t)(i + 1) * S->nbc));
+    if (!std::isfinite(out[i])) return LRBMS_E_NONFINITE;
+  }
+  return LRBMS_OK;
+}
+
 int fine_solver_solve(FineSolver* S, double* mom, const double* field, int kind, double rtol,
                       int maxit, bool warm, double* d_p, int* d_status, int* iters,
                       double* relres) {

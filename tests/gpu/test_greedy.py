@@ -23,9 +23,13 @@ def L():
     return lrbms
 
 
-@pytest.mark.parametrize("name,n_max", [("tiny2d", 12), ("small2d", 30), ("small3d", 24)])
-def test_greedy_matches_oracle(L, name, n_max):
-    p = make_problem(name)
+@pytest.mark.parametrize("name,n_max,n_train", [("tiny2d", 12, None), ("small2d", 30, None),
+                                                ("small3d", 24, None), ("small2d", 36, 300)])
+def test_greedy_matches_oracle(L, name, n_max, n_train):
+    """n_train = 300: the size of the paper's training set (Sec. 6); the GPU
+    solves the reduced systems in fused chunks of 64 parameters, the last
+    chunk (44) with the unused members masked off."""
+    p = make_problem(name) if n_train is None else make_problem(name, n_train=n_train)
     g = Grid(p)
     params = training_params(p.M, p.n_train, np.random.default_rng(p.seed))
     T = p.t_end if p.t_end > 0 else p.n_steps * p.dt
