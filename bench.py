@@ -79,11 +79,13 @@ def build_model(p, n_snap, cap, seed):
     return Model.from_snapshots(p, snaps, ne_cap=cap, unit_functions=True), snaps
 
 
-def build_ensemble(n: int, seed: int = 500):
+def build_ensemble(n: int, seed: int = 500, tune: bool = True):
     """n simulations, alternately 2D 256x256 and 3D 64x64x32 on seeded uneven
     coarse partitions, each with its own permeability seed and seeded local
     basis sizes in 5..60 per box (the first N_E functions of a Gram-Schmidt
-    basis of 61 seeded plane-wave fields plus 1_E, shared per grid)."""
+    basis of 61 seeded plane-wave fields plus 1_E, shared per grid); tune:
+    each member's assembly variant and solver shapes by the autotuner on a
+    seeded state of its own."""
     from synth import CONFIGS, make_problem, wave_fields, ensemble_caps
     from paper_1405_2810_amd.lrbms import Model
     snaps, out = {}, []
@@ -95,6 +97,13 @@ def build_ensemble(n: int, seed: int = 500):
         full = Model.from_snapshots(p, snaps[name], ne_cap=60, unit_functions=True)
         m = full.truncated(ensemble_caps(p, np.random.default_rng(seed + 1000 + i)))
         full.close()
+        if tune:
+            import torch
+            from synth import random_saturation
+            s = torch.as_tensor(random_saturation(p, np.random.default_rng(seed + 2000 + i),
+                                                  lo=0.0, hi=0.6),
+                                dtype=torch.float64, device="cuda")
+            m.tuned = m.autotune(s, reps=3)
         out.append((p, m))
     return out
 
@@ -375,8 +384,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: pick the reduced solver's shapes by timing them (untimed set-up)")
     ap.add_argument("--shapes", default="",
-                    help="leaf,split,bw: install these solver shapes instead of autotuning "
-                         "(0 = never split), e.g. to profile the plan a timed run chose")
+                    help="leaf,split,bw[,asm]: install these solver shapes (0 = never split) and "
+                         "box-assembly variant instead of autotuning, e.g. to profile the "
+                         "configuration a timed run chose")
     ap.add_argument("--refine", type=int, default=-1,
                     help=">= 0: refinement steps of the reduced solve, set after the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -417,13 +427,20 @@ def main():
     s0 = torch.as_tensor(s0_host, dtype=torch.float64, device=dev)
     tune = gm.autotune(s0, reps=10) if args.autotune and not args.shapes else None
     if args.shapes:
-        leaf, split, bw = (int(v) for v in args.shapes.split(","))
+        vals = [int(v) for v in args.shapes.split(",")]
+        leaf, split, bw = vals[:3]
+        asm = vals[3] if len(vals) > 3 else 0
         gm.set_solver_shapes(leaf, split, bw)
-        log(f"[bench] solver shapes set: leaf {leaf} split {split} backward split {bw}")
-        shapes = dict(leaf_max=leaf, split_min=split, bw_split_min=bw, source="--shapes")
+        gm.set_assembly_variant(asm)
+        log(f"[bench] shapes set: leaf {leaf} split {split} backward split {bw}, assembly "
+            f"variant {asm}")
+        shapes = dict(leaf_max=leaf, split_min=split, bw_split_min=bw, asm_variant=asm,
+                      source="--shapes")
     else:
         shapes = tune
     if tune:
+        log(f"[bench] assembly autotune: variant {tune['asm_variant']} "
+            f"({tune['asm_us'][0]:.1f} / {tune['asm_us'][1]:.1f} us per assembly)")
         log(f"[bench] solver autotune: leaf {tune['leaf_max']} split {tune['split_min']} "
             f"backward split {tune['bw_split_min']}, unrefined error "
             f"{tune['unrefined_error']:.1e} -> refinement steps {tune['refine']}: "
@@ -578,6 +595,18 @@ def main():
         if args.serve_requests > 0:
             bat["served_fused_waves"] = bench_serve(members, [0, 5e4], args.serve_requests, 64,
                                                     fused=True, label="ensemble")
+        tuned = [getattr(m, "tuned", None) for _, m in members]
+        tuned_summary = None
+        if all(t is not None for t in tuned):
+            from collections import Counter
+            tuned_summary = {
+                "asm_variant": dict(Counter(f"{'2D' if p.dim == 2 else '3D'} variant "
+                                            f"{t['asm_variant']}" for (p, _), t in
+                                            zip(members, tuned))),
+                "leaf_max": dict(Counter(str(t["leaf_max"]) for t in tuned)),
+                "refine": dict(Counter(str(t["refine"]) for t in tuned))}
+            log(f"[bench] ensemble tuned shapes: {tuned_summary}")
+        bat["tuned_shapes"] = tuned_summary
         extras["ensemble"] = {
             "what": f"{args.ensemble} simulations, alternately 2D 256x256 and 3D 64x64x32 on "
                     "seeded uneven coarse partitions, seeded N_E in 5..60 per box, DIRECT online "

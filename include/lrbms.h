@@ -370,7 +370,9 @@ int lrbms_solver_plan_export_batch(const lrbms_problem* const* probs,
                                    const int32_t* const* basis_sizes, const int32_t* leaf_max,
                                    int32_t n, int64_t* buf, int64_t cap, int64_t* needed);
 
-/* Autotuner of the reduced solver's shapes: the leaf size of the nested
+/* Autotuner of the box assembly and of the reduced solver's shapes.  First
+ * both box-assembly variants (lrbms_model_set_assembly_variant) are timed on
+ * reps DIRECT assemblies of d_sat and the faster is kept.  Then the solver: the leaf size of the nested
  * dissection (1, 2, 4, 8 or 16 boxes) and the smallest panel step that is
  * split in two launches (256 or 1024 tiles, or never); then, on the fastest
  * of those, the smallest front (m u entries of L_US: 2^12, 2^14, 2^16, 2^18
@@ -397,7 +399,9 @@ typedef struct lrbms_tune_report {
    * state; the model keeps its refinement steps unless this is below 1e-13
    * (three orders under the 1e-10 parity bound), then it solves unrefined  */
   double unrefined_error;
-  int32_t refine, pad;
+  int32_t refine;
+  int32_t asm_variant;   /* box assembly variant kept (lrbms_model_set_assembly_variant) */
+  double asm_us[2];      /* time of one DIRECT assembly with variant 0 and with 1      */
 } lrbms_tune_report;
 int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
                          lrbms_tune_report* report);
@@ -411,6 +415,16 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
  * belongs to a batch or server, LRBMS_E_OOM.                                 */
 int lrbms_model_set_solver_shapes(lrbms_model* m, int32_t leaf_max, int32_t split_min,
                                   int32_t bw_split_min);
+
+/* Box assembly variant of the model (Def. coarseScalePressure, the diagonal
+ * blocks Phi_E^T A_E Phi_E): 0 = four waves per workgroup, each thread
+ * forming K Phi for several columns of one cell (chunks of 32 cells in 3D
+ * up to 47 basis functions, else 64); 1 = six waves, one (cell, column) item
+ * per thread with all neighbour loads in flight at once (chunks of 30 cells
+ * in 3D, 64 in 2D).  Same arithmetic per entry; the chunk partials, and so
+ * the rounding of A_N, differ.  Synchronous.  LRBMS_E_ARG for another
+ * variant, LRBMS_E_STATE while the model belongs to a batch or server.       */
+int lrbms_model_set_assembly_variant(lrbms_model* m, int32_t variant);
 
 /* Kernel timing, for roofline measurement (off by default).
  * lrbms_profile_enable synchronizes the model's last stream, clears the

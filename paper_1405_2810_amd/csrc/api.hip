@@ -453,7 +453,8 @@ int model_finish(Model& M, const double* basis, int nprof, const double* profile
     }
   M.n_tiles = (int)tiles.size() / 2;
   if (!dev_copy(&M.d_tiles, tiles.data(), tiles.size(), b)) return LRBMS_E_OOM;
-  if (!hip_ok(assemble_prepare(g, M.subs, M.max_ne, M.asm_layout, b), "assembly layout"))
+  if (!hip_ok(assemble_prepare(g, M.subs, M.max_ne, M.asm_variant, M.asm_layout, b),
+              "assembly layout"))
     return LRBMS_E_OOM;
   // solver
   // leaf size of the nested dissection: the one whose launch sequence is
@@ -1209,6 +1210,34 @@ int lrbms_model_set_refinement(lrbms_model* m, int32_t steps) {
   return LRBMS_OK;
 }
 
+// Rebuild the box assembly's work layout for variant v (0 or 1).
+static int set_asm_variant(Model& M, int v) {
+  if (v == M.asm_variant && M.asm_layout.chunks) return LRBMS_OK;
+  const long long cols = assemble_cols(M.max_ne);
+  M.dev_bytes -= (long long)M.asm_layout.n_chunks * cols * cols * (long long)sizeof(double) +
+                 (2LL * M.asm_layout.n_chunks + M.n_sub + 1) * (long long)sizeof(int);
+  assemble_free(M.asm_layout);
+  M.asm_variant = v;
+  if (!hip_ok(assemble_prepare(M.g, M.subs, M.max_ne, v, M.asm_layout, M.dev_bytes),
+              "assembly layout"))
+    return LRBMS_E_OOM;
+  set_unit_figures(M);
+  return LRBMS_OK;
+}
+
+int lrbms_model_set_assembly_variant(lrbms_model* m, int32_t variant) {
+  try {
+    if (!m) return (set_error("NULL argument"), LRBMS_E_ARG);
+    if (variant < 0 || variant > 1) return (set_error("assembly variant must be 0 or 1"), LRBMS_E_ARG);
+    Model* M = M_(m);
+    if (M->owner) return (set_error("model belongs to a batch or server"), LRBMS_E_STATE);
+    if (!hip_ok(hipStreamSynchronize(M->last_stream), "synchronize")) return LRBMS_E_HIP;
+    return set_asm_variant(*M, variant);
+  } catch (const std::bad_alloc&) {
+    return (set_error("host allocation failed"), LRBMS_E_OOM);
+  }
+}
+
 int lrbms_model_set_solver_shapes(lrbms_model* m, int32_t leaf_max, int32_t split_min,
                                   int32_t bw_split_min) {
   try {
@@ -1401,6 +1430,14 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
     DevArray pN;
     if (!pN.alloc((size_t)std::max(M->N, 1))) return LRBMS_E_OOM;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Events {
+      hipEvent_t& a;
+      hipEvent_t& b;
+      ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } events{e0, e1};
     if (!hip_ok(hipEventCreate(&e0), "event") || !hip_ok(hipEventCreate(&e1), "event"))
       return LRBMS_E_HIP;
     auto time_plan = [&](const SolverPlan& P, const SolverDev& D, double& us) {
@@ -1421,6 +1458,26 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
       return true;
     };
     lrbms_tune_report rep{};
+    // the box assembly: both variants timed on this state, the faster kept
+    {
+      for (int v = 0; v < 2; ++v) {
+        if ((rc = set_asm_variant(*M, v)) != LRBMS_OK) return rc;
+        for (int i = 0; i < 2; ++i)
+          if ((rc = lrbms_online_assemble(m, d_sat, LRBMS_DIRECT, nullptr)) != LRBMS_OK) return rc;
+        float ms = 0.0f;
+        if (!hip_ok(hipEventRecord(e0, 0), "event")) return LRBMS_E_HIP;
+        for (int i = 0; i < reps; ++i)
+          if ((rc = lrbms_online_assemble(m, d_sat, LRBMS_DIRECT, nullptr)) != LRBMS_OK) return rc;
+        if (!hip_ok(hipEventRecord(e1, 0), "event") || !hip_ok(hipEventSynchronize(e1), "event") ||
+            !hip_ok(hipEventElapsedTime(&ms, e0, e1), "event"))
+          return LRBMS_E_HIP;
+        rep.asm_us[v] = 1e3 * ms / reps;
+      }
+      const int best = rep.asm_us[1] < rep.asm_us[0] ? 1 : 0;
+      if ((rc = set_asm_variant(*M, best)) != LRBMS_OK) return rc;
+      rep.asm_variant = best;
+      if ((rc = lrbms_online_assemble(m, d_sat, LRBMS_DIRECT, nullptr)) != LRBMS_OK) return rc;
+    }
     bool ok = time_plan(M->plan, M->sdev, rep.us_before);
     double best = 1e300;
     int best_leaf = M->leaf_max, best_split = M->split_min;
@@ -1456,8 +1513,6 @@ int lrbms_model_autotune(lrbms_model* m, const double* d_sat, int32_t reps,
     const long long bw0 = M->bw_min < 0 ? bw_split_min() : M->bw_min;
     for (long long bw : {1LL << 12, 1LL << 14, 1LL << 16, 1LL << 18, 1LL << 62})
       if (ok && bw != bw0) candidate(leaf1, split1, bw);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (!ok) return LRBMS_E_HIP;
     if (rep.n_candidates > 0 && best < rep.us_before) {
       SolverDev D;

@@ -151,12 +151,35 @@ template <int D, int NEP> struct BoxPlan {
   static constexpr int CH = kPhased ? 32 : AsmShape<D>::CH;
 };
 
-int box_chunk_cells(int dim, int nep) { return (dim == 3 && nep <= 48) ? 32 : 64; }
 
 template <int D, int NEP>
 __host__ __device__ constexpr size_t box_lds_doubles() {
   using S = AsmShape<D>;
   return (size_t)BoxPlan<D, NEP>::CH * S::KS + 2 * (size_t)S::PR * (NEP + 1);
+}
+
+// The one-item variant of the box assembly: six waves per workgroup and one
+// (cell, column) item per thread and piece, so that a thread holds the Phi
+// values of one cell and of its 2d neighbours (one load round trip per
+// piece); chunks of 30 (3D) or 64 (2D) cells keep a workgroup at or below
+// 53 KB of LDS and 128 registers per lane.  Rows per piece rounded up to a
+// multiple of 4 (zero rows) for the contraction.
+template <int D, int NEP> struct Box1 {
+  static constexpr int NT = 384;
+  static constexpr int R = D + 1;
+  static constexpr int PC = NT / NEP;          // cells per piece
+  static constexpr int PR = PC * R;            // rows per piece
+  static constexpr int PRP = (PR + 3) / 4 * 4;
+  static constexpr int CH = D == 3 ? 30 : 64;  // cells per chunk
+  static constexpr int LDP = NEP + 1;
+  static constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 5) / 6;
+  static_assert(NT % NEP == 0, "one item per thread");
+  static constexpr size_t lds_doubles = (size_t)CH * AsmShape<D>::KS + 2 * (size_t)PRP * LDP;
+};
+
+int box_chunk_cells(int dim, int nep, int variant) {
+  if (variant == 1) return dim == 3 ? Box1<3, 64>::CH : Box1<2, 64>::CH;
+  return (dim == 3 && nep <= 48) ? 32 : 64;
 }
 
 template <int D, int NEP>
@@ -387,6 +410,146 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   }
 }
 
+// Diagonal blocks A[E][E] and f_E, the one-item variant (Box1): one
+// workgroup of six waves per (box, chunk), the steps of k_asm_box:
+//   stencil   the self and neighbour blocks of every cell of the chunk into LDS;
+//   apply     for PC = 384 / NEP cells at a time, thread (cell, column) loads
+//             the Phi values of its cell and of the cell's 2d neighbours at
+//             once and forms Y = K Phi (the right-hand side l_h as column
+//             N_E); Phi and Y rows staged in LDS;
+//   contract  partial(i, j) += sum_rows Phi(row, i) Y(row, j) on FP64 MFMA,
+//             16 x 16 output tiles spread over the six waves.
+template <int D, int NEP>
+__global__ __launch_bounds__(384, 4) void k_asm_box1(Geom g, const Sub* __restrict__ subs,
+                                                     const int* __restrict__ chunks,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ mom, int parts,
+                                                     double* __restrict__ partial) {
+  using B = Box1<D, NEP>;
+  using SH = AsmShape<D>;
+  constexpr int R = B::R, PC = B::PC, PR = B::PR, PRP = B::PRP, LDP = B::LDP, CH = B::CH;
+  constexpr int NT = B::NT, NTI = B::NTI, NT2 = B::NT2, TPW = B::TPW, NB = 2 * D;
+  extern __shared__ double lds[];
+  double* Kst = lds;                                   // [CH][KS]
+  double* PhiS = Kst + (size_t)CH * SH::KS;            // [PRP][LDP]
+  double* YS = PhiS + (size_t)PRP * LDP;               // [PRP][LDP]
+  // consecutive chunks of a box share the Phi rows of their neighbour cells
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int sub = chunks[2 * item], c0 = chunks[2 * item + 1];
+  const Sub S = subs[sub];
+  const int NE = S.NE, nE = S.nE;
+  const int cc = min(CH, nE - c0);
+  const int ext[3] = {S.hi[0] - S.lo[0], S.hi[1] - S.lo[1], S.hi[2] - S.lo[2]};
+  const int tid = threadIdx.x;
+  const bool want_mat = parts & (PART_GAMMA | PART_PEN);
+  const bool want_rhs = parts & (PART_RHS_CONST | PART_RHS_GAMMA);
+  auto box_xyz = [&](int l, int (&x)[3]) {
+    x[0] = S.lo[0] + l % ext[0];
+    x[1] = S.lo[1] + (l / ext[0]) % ext[1];
+    x[2] = S.lo[2] + l / (ext[0] * ext[1]);
+  };
+  // the padding rows of the contraction stay zero
+  for (int i = tid; i < (PRP - PR) * LDP; i += NT) {
+    PhiS[(size_t)PR * LDP + i] = 0.0;
+    YS[(size_t)PR * LDP + i] = 0.0;
+  }
+  if (want_mat) {
+    for (int it = tid; it < cc * R; it += NT) {
+      const int lc = it % cc, kp = it / cc;
+      int x[3];
+      box_xyz(c0 + lc, x);
+      const int e = cell_index(g, x);
+      double self[R], nbr[NB][R];
+      cell_stencil<D>(g, S, e, x, mom, parts, kp, self, nbr);
+      double* K = Kst + (size_t)lc * SH::KS;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        K[k * R + kp] = self[k];
+#pragma unroll
+        for (int f = 0; f < NB; ++f) K[((1 + f) * R + k) * R + kp] = nbr[f][k];
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  d4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  const int lp = tid % PC, col = tid / PC;
+  const double* cp = phi + S.phi_off + (long long)min(col, NE - 1) * R * nE;
+  const int bst[3] = {1, ext[0], ext[0] * ext[1]};
+  for (int p0 = 0; p0 < cc; p0 += PC) {
+    const int lc = p0 + lp, l = c0 + lc;
+    const bool cell = lc < cc, live = cell && col < NE;
+    const int bl[3] = {l % ext[0], (l / ext[0]) % ext[1], l / (ext[0] * ext[1])};
+    double ps[R], po[NB][R], Y[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) ps[k] = live ? cp[(long long)k * nE + l] : 0.0;
+#pragma unroll
+    for (int f = 0; f < NB; ++f) {
+      const int a = f >> 1, dir = f & 1;
+      const int ba = bl[a] + (dir ? 1 : -1);
+      const bool in = live && want_mat && ba >= 0 && ba < ext[a];
+      const int ln = l + (dir ? bst[a] : -bst[a]);
+#pragma unroll
+      for (int k = 0; k < R; ++k) po[f][k] = in ? cp[(long long)k * nE + ln] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) Y[k] = 0.0;
+    if (cell && want_mat) {
+      const double* K = Kst + (size_t)lc * SH::KS;
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int kp = 0; kp < R; ++kp) Y[k] = fma(K[k * R + kp], ps[kp], Y[k]);
+#pragma unroll
+      for (int f = 0; f < NB; ++f) {
+        // one block's stencil values in flight at a time (register budget)
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+          for (int kp = 0; kp < R; ++kp) Y[k] = fma(K[((1 + f) * R + k) * R + kp], po[f][kp], Y[k]);
+      }
+    }
+    if (cell && col == NE && want_rhs) {
+      int x[3];
+      box_xyz(l, x);
+#pragma unroll
+      for (int k = 0; k < R; ++k) Y[k] = 0.0;
+      cell_rhs<D>(g, cell_index(g, x), x, mom, parts, Y);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      PhiS[(size_t)(lp * R + k) * LDP + col] = ps[k];
+      YS[(size_t)(lp * R + k) * LDP + col] = Y[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = w + 6 * t;
+      if (tile < NT2) {
+        const int I = tile / NTI, J = tile % NTI;
+#pragma unroll
+        for (int c = 0; c < PRP / 4; ++c)
+          acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * I + r],
+                          YS[(size_t)(4 * c + q) * LDP + 16 * J + r], acc[t]);
+      }
+    }
+    __syncthreads();
+  }
+  double* out = partial + (size_t)item * NEP * NEP;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = w + 6 * t;
+    if (tile < NT2) {
+      const int I = tile / NTI, J = tile % NTI;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(size_t)(16 * I + q + 4 * v) * NEP + 16 * J + r] = acc[t][v];
+    }
+  }
+}
+
 // Sum the chunk partials of every box in chunk order; write A[E][E] and f_E.
 // Workgroup (box, y) takes entries 256 y .. 256 y + 255 of the box's
 // NE x (NE + 1) values; eight chunks' loads are issued before their sums.
@@ -586,10 +749,17 @@ static hipError_t launch_assemble_t(const AsmLayout& L, const Geom& g, const Sub
   const int pdiag = (has_mat ? (PART_GAMMA | PART_PEN) & parts : 0) |
                     (has_rhs ? (PART_RHS_CONST | PART_RHS_GAMMA) & parts : 0);
   if (n_sub > 0 && pdiag) {
-    const size_t lds = sizeof(double) * box_lds_doubles<D, NEP>();
     ktimer_begin(KK_ASM_DIAG, st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_asm_box<D, NEP>), dim3(L.n_chunks), dim3(256), lds, st,
-                       g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
+    using B1 = Box1<D, NEP>;
+    constexpr size_t lds0 = sizeof(double) * box_lds_doubles<D, NEP>();
+    constexpr size_t lds1 = sizeof(double) * B1::lds_doubles;
+    if (L.variant == 1) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_asm_box1<D, NEP>), dim3(L.n_chunks), dim3(B1::NT), lds1,
+                         st, g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
+    } else {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_asm_box<D, NEP>), dim3(L.n_chunks), dim3(256), lds0, st,
+                         g, d_subs, L.chunks, phi, mom, pdiag, L.partial);
+    }
     ktimer_end(-1.0, -1.0, st);
     ktimer_begin(KK_ASM_REDUCE, st);
     // NE (NE + 1) < NEP^2 values per box (NE < NEP), NEP a multiple of 16
@@ -617,6 +787,11 @@ static hipError_t set_lds_limits() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(sizeof(double) * box_lds_doubles<D, NEP>()));
   if (e != hipSuccess) return e;
+  using B1 = Box1<D, NEP>;
+  e = hipFuncSetAttribute((const void*)k_asm_box1<D, NEP>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(double) * B1::lds_doubles));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_asm_iface<D, NEP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(sizeof(double) * iface_lds_doubles<D, NEP>()));
@@ -633,10 +808,11 @@ static hipError_t set_lds_limits_d(int nep) {
 }
 
 hipError_t assemble_prepare(const Geom& g, const std::vector<Sub>& subs, int max_ne,
-                            AsmLayout& L, long long& bytes) {
-  if (max_ne + 1 > 64) return hipErrorInvalidValue;
+                            int variant, AsmLayout& L, long long& bytes) {
+  if (max_ne + 1 > 64 || variant < 0 || variant > 1) return hipErrorInvalidValue;
+  L.variant = variant;
   std::vector<int> chunks, first(1, 0);
-  const int ch = box_chunk_cells(g.dim, assemble_cols(max_ne));
+  const int ch = box_chunk_cells(g.dim, assemble_cols(max_ne), variant);
   for (size_t s = 0; s < subs.size(); ++s) {
     for (int c0 = 0; c0 < subs[s].nE; c0 += ch) {
       chunks.push_back((int)s);

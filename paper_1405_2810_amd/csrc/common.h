@@ -151,14 +151,17 @@ enum AsmParts { PART_GAMMA = 1, PART_PEN = 2, PART_RHS_CONST = 4, PART_RHS_GAMMA
 hipError_t launch_moments(const Geom& g, const double* src, int kind, const double* theta,
                           int nprof, long long prof_stride, double* mom, hipStream_t st);
 // Work split of the box assembly: (box, first cell) chunks and partial blocks.
+// variant 0: four waves, items of several columns per thread; 1: six waves,
+// one (cell, column) item per thread (the autotuner picks per model).
 struct AsmLayout {
   int* chunks = nullptr;       // [n_chunks][2] (box, first cell)
   int* first_chunk = nullptr;  // [n_sub + 1] first chunk of every box
   double* partial = nullptr;   // per-chunk partial blocks
   int n_chunks = 0;
+  int variant = 0;
 };
 hipError_t assemble_prepare(const Geom& g, const std::vector<Sub>& subs, int max_ne,
-                            AsmLayout& L, long long& bytes);
+                            int variant, AsmLayout& L, long long& bytes);
 void assemble_free(AsmLayout& L);
 hipError_t launch_assemble(const AsmLayout& L, const Geom& g, const Sub* d_subs, int n_sub,
                            int max_ne, const Iface* d_ifaces, int n_iface, const double* phi,

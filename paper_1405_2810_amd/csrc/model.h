@@ -41,7 +41,8 @@ struct Model {
   int leaf_max = 2;             // leaf size of the nested dissection (chosen per model)
   int split_min = -1;           // smallest panel step that is split (-1: the default)
   long long bw_min = -1;        // smallest m u whose backward product is split (-1: the default)
-  int refine = 1;               // iterative refinement steps of every reduced solve
+  int refine = 1;
+  int asm_variant = 0;   // box assembly variant (AsmLayout)               // iterative refinement steps of every reduced solve
   bool checks = false;          // online calls wait for their work and return the status
   SolverPlan plan;
   SolverDev sdev;

@@ -58,7 +58,7 @@ class TuneReport_C(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("split_min", C.c_int32), ("n_candidates", C.c_int32),
                 ("bw_split_min", C.c_int32), ("us_per_solve", C.c_double),
                 ("us_before", C.c_double), ("unrefined_error", C.c_double),
-                ("refine", C.c_int32), ("pad", C.c_int32)]
+                ("refine", C.c_int32), ("asm_variant", C.c_int32), ("asm_us", C.c_double * 2)]
 
 
 class OfflineOpts_C(C.Structure):
@@ -105,6 +105,7 @@ def lib():
         L.lrbms_online_solve.argtypes = [vp, vp, vp]
         L.lrbms_model_set_refinement.argtypes = [vp, i32]
         L.lrbms_model_set_solver_shapes.argtypes = [vp, i32, i32, i32]
+        L.lrbms_model_set_assembly_variant.argtypes = [vp, i32]
         L.lrbms_model_set_checks.argtypes = [vp, i32]
         L.lrbms_reconstruct_flux.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lrbms_transport_step.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -444,12 +445,18 @@ class Model:
         _check(lib().lrbms_model_set_solver_shapes(self._h, int(leaf_max), int(split_min),
                                                    int(bw_split_min)))
 
+    def set_assembly_variant(self, variant: int):
+        """Box assembly variant 0 or 1 (lrbms_model_set_assembly_variant)."""
+        _check(lib().lrbms_model_set_assembly_variant(self._h, int(variant)))
+
     def autotune(self, sat, reps: int = 10) -> dict:
-        """Time every solver shape on the reduced system of `sat` and keep
-        the fastest (lrbms_model_autotune)."""
+        """Time both box-assembly variants and every solver shape on the
+        reduced system of `sat` and keep the fastest (lrbms_model_autotune)."""
         rep = TuneReport_C()
         _check(lib().lrbms_model_autotune(self._h, _ptr(sat), int(reps), C.byref(rep)))
-        return {k: getattr(rep, k) for k, _ in TuneReport_C._fields_}
+        out = {k: getattr(rep, k) for k, _ in TuneReport_C._fields_}
+        out["asm_us"] = list(rep.asm_us)
+        return out
 
     def profile_enable(self, on: bool = True):
         """Switch the per-kernel event timing of the online calls on or off

@@ -161,3 +161,35 @@ def test_large_local_bases(name, ne):
     log(f"[parity] large bases {name} N_E={ne}: pN err {e_p:.2e}")
     assert e_p <= TOL_PN
     gm.close()
+
+
+@pytest.mark.parametrize("name,ne", [("tiny2d", 6), ("small2d", 20), ("small2d", 60),
+                                     ("small3d", 12), ("small3d", 40), ("small3d", 60)])
+def test_assembly_variants(name, ne):
+    """Both box-assembly variants (four waves with several columns per thread;
+    six waves with one (cell, column) item per thread, chunks of 30 cells in
+    3D, the contraction padded to a multiple of four rows in 2D at 64
+    columns) against the oracle's reduced system, and against each other."""
+    from .helpers import synthetic_case
+    p, g, om = synthetic_case(name, n_snap=ne + 2, cap=ne)
+    gm = gpu_model(p, om)
+    try:
+        s = _state(p, 41)
+        A_o, f_o = reduced_system(om, s, DIRECT)
+        A_od = A_o.toarray()
+        got = []
+        for v in (0, 1):
+            gm.set_assembly_variant(v)
+            gm.assemble(dev(s), DIRECT)
+            assert gm.status() == 0
+            A_g = gm.dense_reduced_matrix()
+            _, f_g = gm.reduced_system()
+            err = np.abs(A_g - A_od).max() / np.abs(A_od).max()
+            log(f"[parity] assembly variant {v} {name} N_E={ne}: A err {err:.2e} "
+                f"f err {rel_l2(f_g, f_o):.2e}")
+            assert err <= TOL_BLOCK
+            assert rel_l2(f_g, f_o) <= TOL_BLOCK
+            got.append((A_g, f_g))
+        assert np.abs(got[0][0] - got[1][0]).max() <= 1e-13 * np.abs(A_od).max()
+    finally:
+        gm.close()
