@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
   }
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  const int nJ = NE / 16 + 1, nlive = ((NE + 15) / 16) * nJ;   // live output tiles
   d4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -384,12 +385,13 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
       }
     }
     __syncthreads();
-    // contract
+    // contract: only the 16 x 16 tiles that hold rows < N_E and columns
+    // <= N_E (the rest of the padded width is zero), spread over the waves
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = w + 4 * t;
-      if (tile < NT2) {
-        const int I = tile / NTI, J = tile % NTI;
+      if (tile < nlive) {
+        const int I = tile / nJ, J = tile % nJ;
 #pragma unroll
         for (int c = 0; c < PR / 4; ++c)
           acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * I + r],
@@ -402,8 +404,8 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int tile = w + 4 * t;
-    if (tile < NT2) {
-      const int I = tile / NTI, J = tile % NTI;
+    if (tile < nlive) {
+      const int I = tile / nJ, J = tile % nJ;
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[(size_t)(16 * I + q + 4 * v) * NEP + 16 * J + r] = acc[t][v];
     }
@@ -472,6 +474,8 @@ __global__ __launch_bounds__(384, 4) void k_asm_box1(Geom g, const Sub* __restri
   }
   __syncthreads();
   const int lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  // only the output tiles that hold rows < N_E and columns <= N_E
+  const int nJ = NE / 16 + 1, nlive = ((NE + 15) / 16) * nJ;
   d4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -528,8 +532,8 @@ __global__ __launch_bounds__(384, 4) void k_asm_box1(Geom g, const Sub* __restri
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = w + 6 * t;
-      if (tile < NT2) {
-        const int I = tile / NTI, J = tile % NTI;
+      if (tile < nlive) {
+        const int I = tile / nJ, J = tile % nJ;
 #pragma unroll
         for (int c = 0; c < PRP / 4; ++c)
           acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * I + r],
@@ -542,8 +546,8 @@ __global__ __launch_bounds__(384, 4) void k_asm_box1(Geom g, const Sub* __restri
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int tile = w + 6 * t;
-    if (tile < NT2) {
-      const int I = tile / NTI, J = tile % NTI;
+    if (tile < nlive) {
+      const int I = tile / nJ, J = tile % nJ;
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[(size_t)(16 * I + q + 4 * v) * NEP + 16 * J + r] = acc[t][v];
     }
@@ -600,6 +604,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
   constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 3) / 4;
   constexpr int T0 = (A == 0) ? 1 : 0, T1 = (A == 2) ? 1 : 2;
   const int NL = SL.NE, NH = SH2.NE;
+  // only the output tiles that hold rows < N_lo and columns < N_hi
+  const int nJ = (NH + 15) / 16, nlive = ((NL + 15) / 16) * nJ;
   const bool gam = parts & PART_GAMMA, pen = parts & PART_PEN;
   const int ext0 = SL.hi[T0] - SL.lo[T0];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
@@ -657,8 +663,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int tile = w + 4 * t;
-      if (tile < NT2) {
-        const int Ti = tile / NTI, Tj = tile % NTI;
+      if (tile < nlive) {
+        const int Ti = tile / nJ, Tj = tile % nJ;
 #pragma unroll
         for (int c = 0; c < PR / 4; ++c)
           acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * Ti + r],
@@ -670,8 +676,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int tile = w + 4 * t;
-    if (tile < NT2) {
-      const int Ti = tile / NTI, Tj = tile % NTI;
+    if (tile < nlive) {
+      const int Ti = tile / nJ, Tj = tile % nJ;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * Ti + q + 4 * v, j = 16 * Tj + r;
