@@ -55,8 +55,15 @@ struct FrontD {
   int nzc = 0, urow_off = 0;
   long long zoff = 0;
   int member = 0;     // member of a combined plan (0 in a single plan)
-  int pad = 0;
+  // left-looking U-row tiles: the products of the panels before the last
+  // one, summed ahead by the previous step's prefetch items into two
+  // alternating buffers of pf_nt tiles x pf_ns chunks of 64 x 64 at pf_off
+  int pf_nt = 0;
+  int pf_ns = 0, pad = 0;
+  long long pf_off = 0;
 };
+// Panels per prefetch chunk (one workgroup each).
+constexpr int kPfPanels = 4;
 
 // One workgroup of the split backward product: 64 U rows of one front.
 struct BwItem { int front, chunk; };
@@ -121,6 +128,7 @@ struct SolverPlan {
   std::vector<ResNb> rnbs;
   long long nN = 0;
   long long bw_part_doubles = 0;   // partial vectors of the split products (one level at a time)
+  long long pf_doubles = 0;        // prefetch buffers of the panel steps (one level at a time)
   long long front_doubles = 0, vec_doubles = 0, inv_doubles = 0, lpan_doubles = 0;
   double flops = 0.0;                          // factorization flops per solve
   // algorithmic flops and bytes of every launch (for the kernel timer)
@@ -140,6 +148,8 @@ void split_steps(SolverPlan& plan, int split_min);
 // Work items and partial storage of the split backward products, from the
 // fronts' nzc (level by level, fronts in level order).
 void assign_backward_split(SolverPlan& plan);
+// Offsets of the panel steps' prefetch buffers (per level, fronts side by side).
+void assign_prefetch(SolverPlan& plan);
 
 // Build the plan for the box grid with box sizes subs[].NE and interfaces;
 // panel steps of at least split_min tiles are split (split_min < 0: the
@@ -181,6 +191,7 @@ struct SolverDev {
   ResBox* rboxes = nullptr;
   ResNb* rnbs = nullptr;
   double* part = nullptr;
+  double* pf = nullptr;     // prefetch buffers (pf_doubles)
   double* res = nullptr;   // residual of the refinement (nN)
   double* cor = nullptr;   // its correction (nN)
   std::vector<int*> level_fronts;

@@ -360,6 +360,28 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
       }
     }
   }
+  // prefetch items: in step p-1, for every U-row tile of step p (rows from
+  // m on), the products of panels 0 .. p-2 in chunks of kPfPanels, one
+  // workgroup per (tile, chunk); step p adds panel p-1's product itself
+  for (int h = 0; h < H; ++h)
+    for (int fi : plan.level_fronts[h]) {
+      FrontD& d = plan.fronts[fi];
+      const int ld = d.m + d.u;
+      d.pf_nt = 0;
+      d.pf_ns = d.npanels >= 3 ? (d.npanels - 2 + kPfPanels - 1) / kPfPanels : 0;
+      for (int p = 2; p < d.npanels; ++p) {
+        const int cs = p * kNB + std::min(kNB, d.m - p * kNB);
+        const int nrt = (ld + 1 - cs + kNB - 1) / kNB;
+        const int nsp = (p - 1 + kPfPanels - 1) / kPfPanels;
+        for (int ti = 0; ti < nrt; ++ti) {
+          if (cs + kNB * ti < d.m) continue;
+          d.pf_nt = std::max(d.pf_nt, ti + 1);
+          for (int sc = 0; sc < nsp; ++sc)
+            plan.step_items[h][p - 1].push_back(StepItem{fi, p - 1, ti, -2 - sc});
+        }
+      }
+    }
+  assign_prefetch(plan);
   plan.upd_items.assign(H, {});
   for (int h = 0; h < H; ++h) plan.upd_items[h].assign(plan.step_items[h].size(), {});
   // deferred Schur complements: the lower tiles of (U + rhs row) x U
@@ -805,6 +827,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
                                                     double* __restrict__ F,
                                                     double* __restrict__ Lb,
                                                     double* __restrict__ Inv, int* status,
+                                                    double* __restrict__ pf,
                                                     const int* __restrict__ active) {
   __shared__ Tile S0[kNB];
   __shared__ Tile S1[kNB];
@@ -814,6 +837,58 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   const FrontD f = fronts[it.front];
   if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
+  const int tid0 = threadIdx.x;
+  if (it.tj <= -2) {
+    // prefetch for U-row tile ti of the next step (panel p): the products
+    // sum_cp L(R, cp) L(P, cp)^T over the panels cp of chunk sc (all before
+    // p - 1, so final), on FP64 MFMA, into the buffer of step p
+    const int p = it.panel + 1, sc = -2 - it.tj;
+    const int c0p = p * kNB, nbp = min(kNB, f.m - c0p), csp = c0p + nbp;
+    const int R0p = csp + it.ti * kNB, nrp = (int)min((long long)kNB, lda - R0p);
+    const int cp0 = sc * kPfPanels, cp1 = min(cp0 + kPfPanels, p - 1);
+    const int lane = tid0 & 63, w = tid0 >> 6, r = lane & 15, q = lane >> 4;
+    d4 c2[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) c2[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double la[16], lp[16];
+    auto load = [&](int cp) {
+      const double* Lc = Lb + lpanel_base(f, cp);
+      const int csc = kNB * (cp + 1);   // panels before the last are full
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int idx = tid0 + 256 * e, i = idx >> 6, k = idx & 63;
+        la[e] = (i < nrp) ? Lc[(long long)(R0p - csc + i) * kNB + k] : 0.0;
+        lp[e] = (i < nbp) ? Lc[(long long)(c0p - csc + i) * kNB + k] : 0.0;
+      }
+    };
+    load(cp0);
+    for (int cp = cp0; cp < cp1; ++cp) {
+      if (cp > cp0) __syncthreads();   // the previous panel's products are done
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int idx = tid0 + 256 * e;
+        S1[idx >> 6][idx & 63] = la[e];
+        S2[idx >> 6][idx & 63] = lp[e];
+      }
+      __syncthreads();
+      if (cp + 1 < cp1) load(cp + 1);   // in flight during the products
+      for (int c = 0; c < kNB / 4; ++c) {
+        const double a = S1[16 * w + r][4 * c + q];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) c2[cb] = mfma16(a, S2[16 * cb + r][4 * c + q], c2[cb]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
+    __syncthreads();
+    double* dst = pf + f.pf_off +
+                  (((long long)(p & 1) * f.pf_nt + it.ti) * f.pf_ns + sc) * (kNB * kNB);
+    for (int idx = tid0; idx < kNB * kNB; idx += 256) dst[idx] = S1[idx >> 6][idx & 63];
+    return;
+  }
   double* Fp = F + f.off;
   const int c0 = it.panel * kNB, nb = min(kNB, f.m - c0), cs = c0 + nb;
   const int R0 = cs + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
@@ -825,11 +900,13 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   // a tile of U rows only: the panel columns of its rows from 64 npanels on
   // have had no update yet (the rows between m and there were updated
   // right-looking, in the tile that straddles m before the last panel); the
-  // earlier panels' products sum_c L(R, c) L(P, c)^T are formed here on FP64
-  // MFMA (L from the store, panel by panel), staged in S1 and subtracted
-  // from those rows
+  // earlier panels' products sum_c L(R, c) L(P, c)^T are subtracted from
+  // those rows: the last panel's formed here on FP64 MFMA (L from the store),
+  // the ones before it summed by the previous step's prefetch items (chunks
+  // of kPfPanels panels), added in chunk order, all staged in S1
   const bool left = !upd && R0 >= f.m && it.panel > 0;
   const int mU = f.npanels * kNB;
+  const int cp_first = it.panel >= 2 ? it.panel - 1 : 0;
   if (left) {
     d4 c2[4];
 #pragma unroll
@@ -845,9 +922,9 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
         lp[p] = (i < nb) ? Lc[(long long)(c0 - csc + i) * kNB + k] : 0.0;
       }
     };
-    load(0);
-    for (int cp = 0; cp < it.panel; ++cp) {
-      if (cp > 0) __syncthreads();   // the previous panel's products are done
+    load(cp_first);
+    for (int cp = cp_first; cp < it.panel; ++cp) {
+      if (cp > cp_first) __syncthreads();   // the previous panel's products are done
 #pragma unroll
       for (int p = 0; p < 16; ++p) {
         const int idx = tid + 256 * p;
@@ -868,6 +945,17 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
       for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
     __syncthreads();
+    if (it.panel >= 2) {
+      const int nsp = (it.panel - 1 + kPfPanels - 1) / kPfPanels;
+      const double* src =
+          pf + f.pf_off + ((long long)(it.panel & 1) * f.pf_nt + it.ti) * f.pf_ns * (kNB * kNB);
+      for (int idx = tid; idx < kNB * kNB; idx += 256) {
+        double a = S1[idx >> 6][idx & 63];
+        for (int sc = 0; sc < nsp; ++sc) a += src[(long long)sc * (kNB * kNB) + idx];
+        S1[idx >> 6][idx & 63] = a;
+      }
+      __syncthreads();
+    }
   }
   // loads: L_panel^{-1} (row-major), the panel columns of tile row ti, and the
   // F tile (ti, tj) this workgroup updates (kept in registers)
@@ -1360,11 +1448,28 @@ void split_steps(SolverPlan& plan, int split_min) {
       std::vector<StepItem> rows;
       std::vector<StepItem>& upd = plan.upd_items[h][b];
       for (const StepItem& it : items) {
+        if (it.tj <= -2) {
+          rows.push_back(it);   // a prefetch item stays as it is
+          continue;
+        }
         if (it.tj <= 0) rows.push_back(StepItem{it.front, it.panel, it.ti, -1});
         if (it.tj >= 0) upd.push_back(it);
       }
       items.swap(rows);
     }
+}
+
+void assign_prefetch(SolverPlan& plan) {
+  plan.pf_doubles = 0;
+  for (int h = 0; h < plan.nlevels; ++h) {
+    long long off = 0;
+    for (int fi : plan.level_fronts[h]) {
+      FrontD& d = plan.fronts[fi];
+      d.pf_off = off;
+      off += 2LL * d.pf_nt * d.pf_ns * kNB * kNB;
+    }
+    plan.pf_doubles = std::max(plan.pf_doubles, off);
+  }
 }
 
 void assign_backward_split(SolverPlan& plan) {
@@ -1528,6 +1633,7 @@ bool combine_plans(const std::vector<const SolverPlan*>& plans,
   // per-launch figures then stay those of the members' own launches)
   split_steps(out, step_split_min());
   assign_backward_split(out);
+  assign_prefetch(out);
   return true;
 }
 
@@ -1544,6 +1650,9 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
     const int last = f.npanels - 1;
     const long long cs = std::min(kNB * (last + 1), f.m);
     if (f.loff < 0 || lpanel_base(f, last) + (ld + 1 - cs) * kNB > plan.lpan_doubles) return false;
+    if (f.pf_nt < 0 || f.pf_ns < 0 || f.pf_off < 0 ||
+        f.pf_off + 2LL * f.pf_nt * f.pf_ns * kNB * kNB > plan.pf_doubles)
+      return false;
     if (f.node_off < 0 || f.n_s_nodes > f.n_nodes ||
         (long long)f.node_off + f.n_nodes > (long long)plan.nodes.size())
       return false;
@@ -1631,6 +1740,16 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
       for (const StepItem& it : *lp) {
         if (it.front < 0 || it.front >= nf) return false;
         const FrontD& f = plan.fronts[it.front];
+        if (it.tj <= -2) {
+          // prefetch for tile ti of step panel + 1, chunk -2 - tj
+          const int p = it.panel + 1, sc = -2 - it.tj;
+          if (p < 2 || p >= f.npanels || sc >= f.pf_ns || it.ti < 0 || it.ti >= f.pf_nt ||
+              sc * kPfPanels >= p - 1)
+            return false;
+          const int csp = p * kNB + std::min(kNB, f.m - p * kNB);
+          if (csp + it.ti * kNB < f.m || csp + it.ti * kNB > f.m + f.u) return false;
+          continue;
+        }
         if (it.panel < 0 || it.panel >= f.npanels || it.ti < 0 || it.tj < -1 ||
             (it.tj >= 0 && it.tj > it.ti))
           return false;
@@ -1850,7 +1969,8 @@ bool solver_upload(const SolverPlan& plan, SolverDev& dev) {
   };
   return alloc(&dev.F, plan.front_doubles) && alloc(&dev.L, plan.lpan_doubles) &&
          alloc(&dev.V, plan.vec_doubles) && alloc(&dev.Inv, plan.inv_doubles) &&
-         alloc(&dev.part, plan.bw_part_doubles) && alloc(&dev.res, plan.nN) &&
+         alloc(&dev.part, plan.bw_part_doubles) && alloc(&dev.pf, plan.pf_doubles) &&
+         alloc(&dev.res, plan.nN) &&
          alloc(&dev.cor, plan.nN);
 }
 
@@ -1875,6 +1995,7 @@ void solver_free(SolverDev& dev) {
   f(dev.res);
   f(dev.cor);
   f(dev.part);
+  f(dev.pf);
   f(dev.F);
   f(dev.L);
   f(dev.V);
@@ -1929,7 +2050,7 @@ hipError_t solver_factor_solve(const SolverPlan& plan, const SolverDev& dev,
       if (ni) {
         ktimer_begin(KK_FRONT_STEP, st);
         hipLaunchKernelGGL(k_front_step, dim3(ni), dim3(256), 0, st, dev.step_items[h][p],
-                           dev.fronts, dev.F, dev.L, dev.Inv, status, active);
+                           dev.fronts, dev.F, dev.L, dev.Inv, status, dev.pf, active);
         ktimer_end(plan.step_flops[h][p], plan.step_bytes[h][p], st);
       }
       const int nu = (int)plan.upd_items[h][p].size();

@@ -102,6 +102,10 @@ def emulate(plan, blocks, fN, refine=False):
             _factor_tile(view(F, fr[fi]), fr[fi]["m"], 0, Inv, fr[fi])
         for items in lev["steps"]:
             for it in items:
+                if it["tj"] <= -2:
+                    # a prefetch item: part of the left-looking sum below,
+                    # formed one step ahead (same products, another grouping)
+                    continue
                 f = fr[it["front"]]
                 Fp = view(F, f)
                 ld = f["m"] + f["u"]
@@ -394,3 +398,39 @@ def test_refinement_sweeps_solve_new_rhs(monkeypatch, split):
             ref = np.linalg.solve(A, r[off:off + n])
             assert np.linalg.norm(d[off:off + n] - ref) <= 1e-10 * np.linalg.norm(ref)
             off += n
+
+
+@pytest.mark.parametrize("name,ne,leaf", [("small3d", 40, 1), ("cfg1", 10, 16)])
+def test_prefetch_items_cover_the_left_looking_sums(name, ne, leaf):
+    """Step p-1 of every front carries, for each U-row tile of step p >= 2
+    (rows from m on), one prefetch item per chunk of 4 of the panels
+    0 .. p-2, and nothing else of that kind: the step-p tile then adds only
+    panel p-1's product itself."""
+    from paper_1405_2810_amd.lrbms import solver_plan
+    p = make_problem(name)
+    sizes = np.full(int(np.prod(p.nc[:p.dim])), ne, dtype=np.int32)
+    plan = solver_plan(p, sizes, leaf)
+    fr = plan["fronts"]
+    found = {}
+    for lev in plan["levels"]:
+        for items in lev["steps"]:
+            for it in items:
+                if it["tj"] <= -2:
+                    key = (it["front"], it["panel"] + 1, it["ti"], -2 - it["tj"])
+                    assert key not in found
+                    found[key] = True
+    want = {}
+    n_multi = 0
+    for fi, f in enumerate(fr):
+        ld = f["m"] + f["u"]
+        n_multi += f["npanels"] >= 3
+        for q in range(2, f["npanels"]):
+            cs = q * NB + min(NB, f["m"] - q * NB)
+            nrt = (ld + 1 - cs + NB - 1) // NB
+            for ti in range(nrt):
+                if cs + NB * ti < f["m"]:
+                    continue
+                for sc in range((q - 1 + 3) // 4):
+                    want[(fi, q, ti, sc)] = True
+    assert n_multi > 0 or name == "cfg1"
+    assert set(found) == set(want)
