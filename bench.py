@@ -220,9 +220,15 @@ def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77, fused: b
         who = rng.integers(0, len(models), n_req)
         S = Server(hbm_budget=foot, max_slots=slots, mode=DIRECT, fused=fused)
         ids = [S.attach(m, s) for m, s in zip(models, sats)]
+        S.poll(0)  # admits the attached simulations
+        if S.info()["n_admitted"] != len(models):
+            info = S.info()
+            S.close()
+            raise RuntimeError(f"budget {foot} B did not admit every member: {info}")
         lat = []
         t0 = time.perf_counter()
         k = 0
+        last = t0
         while len(lat) < n_req:
             now = time.perf_counter() - t0
             while k < n_req and arrive[k] <= now:
@@ -232,6 +238,12 @@ def bench_serve(members, rates, n_req: int, slots: int, seed: int = 77, fused: b
                 if rc != 0:
                     raise RuntimeError(f"request failed with status {rc}")
                 lat.append(ms)
+                last = time.perf_counter()
+            if k == n_req and time.perf_counter() - last > 60.0:
+                info = S.info()
+                S.close()
+                raise RuntimeError(f"serving made no progress for 60 s ({len(lat)} of {n_req} "
+                                   f"done; server {info})")
         span = time.perf_counter() - t0
         S.close()
         lat = np.array(lat)

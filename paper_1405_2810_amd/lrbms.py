@@ -244,6 +244,11 @@ class Model:
     def __init__(self, handle, prob):
         self._h = handle
         self.prob = prob
+        self._read_info()
+
+    def _read_info(self):
+        """lrbms_model_get_info; read again by every call that changes the
+        model's device memory (solver shapes, assembly variant, autotune)."""
         info = ModelInfo_C()
         _check(lib().lrbms_model_get_info(self._h, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in ModelInfo_C._fields_}
@@ -444,16 +449,19 @@ class Model:
         them; 0 = never split) without timing (lrbms_model_set_solver_shapes)."""
         _check(lib().lrbms_model_set_solver_shapes(self._h, int(leaf_max), int(split_min),
                                                    int(bw_split_min)))
+        self._read_info()
 
     def set_assembly_variant(self, variant: int):
         """Box assembly variant 0 or 1 (lrbms_model_set_assembly_variant)."""
         _check(lib().lrbms_model_set_assembly_variant(self._h, int(variant)))
+        self._read_info()
 
     def autotune(self, sat, reps: int = 10) -> dict:
         """Time both box-assembly variants and every solver shape on the
         reduced system of `sat` and keep the fastest (lrbms_model_autotune)."""
         rep = TuneReport_C()
         _check(lib().lrbms_model_autotune(self._h, _ptr(sat), int(reps), C.byref(rep)))
+        self._read_info()
         out = {k: getattr(rep, k) for k, _ in TuneReport_C._fields_}
         out["asm_us"] = list(rep.asm_us)
         return out

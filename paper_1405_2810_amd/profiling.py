@@ -38,7 +38,7 @@ def _rows(path_or_dir: str, pattern: str):
 
 
 def short_name(kernel: str) -> str:
-    k = kernel.split("(")[0].strip()
+    k = kernel.replace("(anonymous namespace)::", "").split("(")[0].strip()
     for pre in ("void ", "lrbms::"):
         k = k.replace(pre, "")
     return k.split("<")[0].strip()
