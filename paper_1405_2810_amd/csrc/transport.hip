@@ -3,7 +3,6 @@
 //   face fluxes of the conservative velocity              (Def. velocityDG)
 //   DG upwind explicit Euler saturation step              (Def. saturationDG)
 //   slope limiter                                         (eq. limiterMain)
-// and the matrix-free fine SWIP operator used by the offline snapshot solves.
 //
 // Readings (same as the CPU reference): RT0 on rectangles (one normal flux per
 // face, u_a linear in x_a only); v_N |f| as the flux on Neumann faces; upwind
@@ -13,11 +12,62 @@
 // the cell mean and scales the slope by min_i m_i; 2-point Gauss rules.
 //
 // The reconstruction is one thread per cell of a box tile; the face-based
-// kernels work on tiles of cells staged in LDS with a one-cell halo.
+// kernels work on tiles of cells staged in LDS with a one-cell halo.  They
+// are instantiated per dimension and per relative permeability law; their
+// time goes to vector instructions (the quadratures, the face and cell index
+// arithmetic), so the tiles are laid out to keep that count low: per-axis face
+// bodies with compile-time extents, results held in registers across the
+// barrier that lets them overwrite the halo, which raises the workgroups per
+// CU.
+#include <type_traits>
+
 #include "common.h"
 #include "ktimer.h"
 
 namespace lrbms {
+
+// The relative permeability law as a template argument of the fine-grid
+// kernels, so that the common laws carry no call to the general power:
+// 0 linear, 1 Corey with both exponents 2, 2 any other Corey exponents.
+// Each form gives the same values as mobilities().
+inline int law_of(const Geom& g) {
+  if (g.relperm == 0) return 0;
+  return (g.cw == 2.0 && g.co == 2.0) ? 1 : 2;
+}
+
+template <int LAW>
+__device__ __forceinline__ void mobilities_law(const Geom& g, double s, double& lw, double& lo) {
+  if (LAW == 2) {
+    mobilities(g, s, lw, lo);
+    return;
+  }
+  const double sc = clip01(s);
+  double krw, kro;
+  if (LAW == 0) {
+    krw = sc;
+    kro = 1.0 - sc;
+  } else {
+    const double so = 1.0 - sc;
+    krw = sc * sc;
+    kro = so * so;
+  }
+  lw = krw * g.ivw;
+  lo = kro * g.ivo;
+}
+
+template <int LAW>
+__device__ __forceinline__ double total_mobility_law(const Geom& g, double s) {
+  double lw, lo;
+  mobilities_law<LAW>(g, s, lw, lo);
+  return lw + lo;
+}
+
+template <int LAW>
+__device__ __forceinline__ double frac_flow_law(const Geom& g, double s) {
+  double lw, lo;
+  mobilities_law<LAW>(g, s, lw, lo);
+  return lw * rcp_refined(lw + lo);
+}
 
 __device__ __forceinline__ double p1_value(const double* co, int d, const double sq[3], double isv) {
   double v = co[0];
@@ -84,35 +134,39 @@ hipError_t launch_reconstruct(const Geom& g, const Sub* d_subs, int n_sub, const
   return hipGetLastError();
 }
 
-// Integral of the total mobility lambda(s) over the face of axis a at local
-// coordinate xi_a of a cell with coefficients co (2-point Gauss in the
+// Tangential axes of the faces normal to axis A, in increasing order.
+template <int A>
+struct Tang {
+  static constexpr int t0 = A == 0 ? 1 : 0, t1 = A == 2 ? 1 : 2;
+};
+
+// Integral of the total mobility lambda(s) over the face of axis A at local
+// coordinate xi_A of a cell with coefficients co (2-point Gauss in the
 // tangential directions).
-template <int D>
-__device__ __forceinline__ double face_mobility_co(const Geom& g, const double (&co)[4], int a,
-                                                   double xia) {
-  int tax[2] = {0, 0}, nt = 0;
-#pragma unroll
-  for (int b = 0; b < D; ++b)
-    if (b != a) tax[nt++] = b;
+template <int D, int LAW, int A>
+__device__ __forceinline__ double face_mobility_co(const Geom& g, const double (&co)[4], double xia) {
   const double gp = 1.0 / kSqrt3;
   double sum = 0.0;
 #pragma unroll
   for (int p = 0; p < (1 << (D - 1)); ++p) {
     double sq[3] = {0, 0, 0};
-    sq[a] = kSqrt3 * xia;
-#pragma unroll
-    for (int ti = 0; ti < D - 1; ++ti) sq[tax[ti]] = kSqrt3 * (((p >> ti) & 1) ? gp : -gp);
-    sum += total_mobility(g, p1_value(co, D, sq, g.isv));
+    sq[A] = kSqrt3 * xia;
+    sq[Tang<A>::t0] = kSqrt3 * ((p & 1) ? gp : -gp);
+    if (D == 3) sq[Tang<A>::t1] = kSqrt3 * (((p >> 1) & 1) ? gp : -gp);
+    sum += total_mobility_law<LAW>(g, p1_value(co, D, sq, g.isv));
   }
-  return sum * g.area[a] / (1 << (D - 1));
+  return sum * g.area[A] / (1 << (D - 1));
 }
 
 // ---- tiles of the face-based kernels -------------------------------------------
 // A workgroup of 256 threads takes a tile of cells (16 x 16 in 2D, 8 x 8 x 4 in
-// 3D): the tile's cell data with a one-cell halo are staged in LDS (coalesced
-// rows), every face of the tile is evaluated once by one thread, and for the
-// cell-based results every thread then gathers its cell from the face values.
-// Each face's quadrature thus runs once instead of once per adjacent cell.
+// 3D): the tile's cell data with a one-cell halo are staged in LDS, every face
+// of the tile is evaluated once by one thread, and for the cell-based results
+// every thread then gathers its cell from the face values.  Each face's
+// quadrature thus runs once instead of once per adjacent cell.  The faces of
+// a tile are numbered axis by axis; a thread's face loop branches once per
+// face to a body specialised for the face's axis, so that every per-axis
+// quantity (extents, spacings, tangential axes) is a compile-time index.
 template <int D>
 struct TileShape;
 template <>
@@ -124,9 +178,12 @@ struct TileShape<3> {
   static constexpr int X = 8, Y = 8, Z = 4;
 };
 
+constexpr int kTileThreads = 256;
+
 template <int D>
 struct Tiling {
   using T = TileShape<D>;
+  static_assert(T::X * T::Y * T::Z == kTileThreads, "one thread per tile cell");
   static constexpr int R = D + 1;
   static constexpr int HX = T::X + 2, HY = T::Y + 2, HZ = (D == 3) ? T::Z + 2 : 1;
   static constexpr int ZO = (D == 3) ? 1 : 0;            // halo offset along z
@@ -143,46 +200,116 @@ struct Tiling {
     if (a == 1) return FX + l[0] + T::X * (l[1] + (T::Y + 1) * l[2]);
     return FX + FY + l[0] + T::X * (l[1] + T::Y * l[2]);
   }
-  __device__ static void fdecode(int lf, int& a, int l[3]) {
-    int e0 = T::X, e1 = T::Y;
-    if (lf < FX) {
-      a = 0;
-      e0 += 1;
-    } else if (lf < FX + FY) {
-      a = 1;
-      lf -= FX;
-      e1 += 1;
-    } else {
-      a = 2;
-      lf -= FX + FY;
-    }
-    l[0] = lf % e0;
-    l[1] = (lf / e0) % e1;
-    l[2] = lf / (e0 * e1);
+  // local face coordinates of the j-th face along axis A
+  template <int A>
+  __device__ static void fdecode(int j, int l[3]) {
+    constexpr int e0 = T::X + (A == 0 ? 1 : 0), e1 = T::Y + (A == 1 ? 1 : 0);
+    l[0] = j % e0;
+    l[1] = (j / e0) % e1;
+    l[2] = j / (e0 * e1);
   }
 };
 
-// Stage coefficients (and optionally permeabilities) of the tile's halo box.
-template <int D>
-__device__ __forceinline__ void stage_halo(const Geom& g, const double* __restrict__ src,
-                                           const int o[3], double (*sh)[Tiling<D>::NH],
-                                           double* shk) {
+// Calls f(axis, lf, j) for the tile faces lf = threadIdx.x + k 256, where j is
+// the face's number among the tile faces of its axis.
+template <int D, class Fn>
+__device__ __forceinline__ void for_tile_faces(Fn&& f) {
   using TL = Tiling<D>;
-  const int nc = g.ncell;
-  for (int h = threadIdx.x; h < TL::NH; h += blockDim.x) {
-    const int x[3] = {o[0] + h % TL::HX - 1, o[1] + (h / TL::HX) % TL::HY - 1,
-                      o[2] + h / (TL::HX * TL::HY) - TL::ZO};
-    bool in = true;
+  for (int lf = threadIdx.x; lf < TL::NF; lf += kTileThreads) {
+    if (lf < TL::FX)
+      f(std::integral_constant<int, 0>(), lf, lf);
+    else if (D == 2 || lf < TL::FX + TL::FY)
+      f(std::integral_constant<int, 1>(), lf, lf - TL::FX);
+    else
+      f(std::integral_constant<int, D - 1>(), lf, lf - TL::FX - TL::FY);
+  }
+}
+
+// Global number of the j-th tile face along axis A (x = its face
+// coordinates), or -1 when the face lies outside the domain.
+template <int D, int A>
+__device__ __forceinline__ int tile_face(const Geom& g, const int o[3], int j, int l[3], int x[3]) {
+  Tiling<D>::template fdecode<A>(j, l);
 #pragma unroll
-    for (int a = 0; a < D; ++a) in = in && x[a] >= 0 && x[a] < g.n[a];
-    const int c = in ? cell_index(g, x) : 0;
-    double v[TL::R];
+  for (int b = 0; b < 3; ++b) x[b] = o[b] + l[b];
+  bool valid = x[A] <= g.n[A];
 #pragma unroll
-    for (int k = 0; k < TL::R; ++k) v[k] = in ? src[(long long)k * nc + c] : 0.0;
-    const double kv = (shk && in) ? g.perm[c] : 1.0;
+  for (int b = 0; b < D; ++b)
+    if (b != A) valid = valid && x[b] < g.n[b];
+  return valid ? face_index(g, A, x) : -1;
+}
+
+// One thread's share of the tile's halo box (coefficients, optionally the
+// permeabilities): every global load is issued before the first LDS store, so
+// a thread has all of them in flight at once; halo cells outside the domain
+// read cell 0 and are replaced by zero state (permeability 1).
+template <int D, bool PERM>
+struct HaloRegs {
+  using TL = Tiling<D>;
+  static constexpr int NIT = (TL::NH + kTileThreads - 1) / kTileThreads;
+  double v[NIT][TL::R];
+  double kv[PERM ? NIT : 1];
+  __device__ __forceinline__ void load(const Geom& g, const double* __restrict__ src,
+                                       const int o[3]) {
+    const int nc = g.ncell;
 #pragma unroll
-    for (int k = 0; k < TL::R; ++k) sh[k][h] = v[k];
-    if (shk) shk[h] = kv;
+    for (int it = 0; it < NIT; ++it) {
+      const int h = (int)threadIdx.x + kTileThreads * it;
+      const int x[3] = {o[0] + h % TL::HX - 1, o[1] + (h / TL::HX) % TL::HY - 1,
+                        o[2] + h / (TL::HX * TL::HY) - TL::ZO};
+      bool in = h < TL::NH;
+#pragma unroll
+      for (int a = 0; a < D; ++a) in = in && x[a] >= 0 && x[a] < g.n[a];
+      const int c = in ? cell_index(g, x) : 0;
+#pragma unroll
+      for (int k = 0; k < TL::R; ++k) {
+        const double t = src[(long long)k * nc + c];
+        v[it][k] = in ? t : 0.0;
+      }
+      if (PERM) {
+        const double t = g.perm[c];
+        kv[it] = in ? t : 1.0;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double (*sh)[TL::NH], double* shk) const {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int h = (int)threadIdx.x + kTileThreads * it;
+      if (h < TL::NH) {
+#pragma unroll
+        for (int k = 0; k < TL::R; ++k) sh[k][h] = v[it][k];
+        if (PERM) shk[h] = kv[it];
+      }
+    }
+  }
+};
+
+// The fluxes of a tile's faces (zero outside the domain) into LDS; each
+// thread issues the loads of all its faces before its first store.
+template <int D>
+__device__ __forceinline__ void stage_face_fluxes(const Geom& g, const double* __restrict__ flux,
+                                                  const int o[3], double* shF) {
+  using TL = Tiling<D>;
+  constexpr int NIT = (TL::NF + kTileThreads - 1) / kTileThreads;
+  double F[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int lf = (int)threadIdx.x + kTileThreads * it;
+    int l[3], x[3], fid = -1;
+    if (lf < TL::FX)
+      fid = tile_face<D, 0>(g, o, lf, l, x);
+    else if (D == 2 || lf < TL::FX + TL::FY)
+      fid = lf < TL::NF ? tile_face<D, 1>(g, o, lf - TL::FX, l, x) : -1;
+    else if (lf < TL::NF)
+      fid = tile_face<D, D - 1>(g, o, lf - TL::FX - TL::FY, l, x);
+    const double t = flux[fid >= 0 ? fid : 0];
+    F[it] = fid >= 0 ? t : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int lf = (int)threadIdx.x + kTileThreads * it;
+    if (lf < TL::NF) shF[lf] = F[it];
   }
 }
 
@@ -196,19 +323,59 @@ __device__ __forceinline__ double halo_value(double (*sh)[Tiling<D>::NH], int h,
   return v * isv;
 }
 
+// One-dimensional grid over the tiles (x fastest, then y, then z).  The
+// hardware deals workgroups to the eight XCDs in turn; xcd_item gives each XCD
+// a contiguous run of tiles (a slab across z), so the halo cells a tile shares
+// with its neighbours are mostly read from the XCD's own L2.
+template <int D>
+__host__ __device__ __forceinline__ void tile_counts(const Geom& g, int t[3]) {
+  using T = TileShape<D>;
+  t[0] = (g.n[0] + T::X - 1) / T::X;
+  t[1] = (g.n[1] + T::Y - 1) / T::Y;
+  t[2] = D == 3 ? (g.n[2] + T::Z - 1) / T::Z : 1;
+}
+
 template <int D>
 static dim3 tile_grid(const Geom& g) {
-  using T = TileShape<D>;
-  return dim3((g.n[0] + T::X - 1) / T::X, (g.n[1] + T::Y - 1) / T::Y,
-              D == 3 ? (g.n[2] + T::Z - 1) / T::Z : 1);
+  int t[3];
+  tile_counts<D>(g, t);
+  return dim3(t[0] * t[1] * t[2]);
 }
+
+template <int D>
+__device__ __forceinline__ void tile_origin(const Geom& g, int o[3]) {
+  using T = TileShape<D>;
+  int t[3];
+  tile_counts<D>(g, t);
+  const int i = xcd_item((int)blockIdx.x, t[0] * t[1] * t[2]);
+  o[0] = (i % t[0]) * T::X;
+  o[1] = ((i / t[0]) % t[1]) * T::Y;
+  o[2] = (i / (t[0] * t[1])) * T::Z;
+}
+
+// Launch of a face kernel instantiated for the dimension and the law.
+#define LRBMS_FACE_LAUNCH(KERNEL, g, st, ...)                                              \
+  do {                                                                                     \
+    const int law_ = law_of(g);                                                            \
+    if ((g).dim == 2) {                                                                    \
+      const dim3 grid_ = tile_grid<2>(g);                                                  \
+      if (law_ == 0) hipLaunchKernelGGL((KERNEL<2, 0>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+      else if (law_ == 1) hipLaunchKernelGGL((KERNEL<2, 1>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<2, 2>), grid_, dim3(256), 0, st, __VA_ARGS__);       \
+    } else {                                                                               \
+      const dim3 grid_ = tile_grid<3>(g);                                                  \
+      if (law_ == 0) hipLaunchKernelGGL((KERNEL<3, 0>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+      else if (law_ == 1) hipLaunchKernelGGL((KERNEL<3, 1>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<3, 2>), grid_, dim3(256), 0, st, __VA_ARGS__);       \
+    }                                                                                      \
+  } while (0)
 
 // Def. velocityDG, one thread per face of a tile with the states, pressures
 // and permeabilities of the tile and its halo in LDS: interior faces
 // -sum_l w_l kappa_l int_f lambda(s_l) grad p_l . n + sigma_f/h_f int_f [p];
 // Dirichlet faces the one-sided form against p_D; Neumann faces v_N |f|.  A
 // tile writes the faces on its low sides, and the domain's last faces.
-template <int D>
+template <int D, int LAW>
 __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__ ph,
                                               const double* __restrict__ sat,
                                               double* __restrict__ flux) {
@@ -218,20 +385,29 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
   __shared__ double shs[R][TL::NH];
   __shared__ double shp[R][TL::NH];
   __shared__ double shk[TL::NH];
-  const int o[3] = {(int)blockIdx.x * T::X, (int)blockIdx.y * T::Y, (int)blockIdx.z * T::Z};
-  stage_halo<D>(g, sat, o, shs, shk);
-  stage_halo<D>(g, ph, o, shp, nullptr);
+  int o[3];
+  tile_origin<D>(g, o);
+  {
+    HaloRegs<D, true> rs;
+    HaloRegs<D, false> rp;
+    rs.load(g, sat, o);
+    rp.load(g, ph, o);
+    rs.store(shs, shk);
+    rp.store(shp, nullptr);
+  }
   __syncthreads();
-  const int ext[3] = {T::X, T::Y, T::Z};
-  for (int lf = threadIdx.x; lf < TL::NF; lf += blockDim.x) {
-    int a, l[3];
-    TL::fdecode(lf, a, l);
-    int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-    bool valid = x[a] <= g.n[a] && (l[a] < ext[a] || x[a] == g.n[a]);
+  for_tile_faces<D>([&](auto AX, int lf, int j) {
+    (void)lf;
+    constexpr int a = decltype(AX)::value;
+    constexpr int ext = a == 0 ? T::X : (a == 1 ? T::Y : T::Z);
+    int l[3];
+    TL::template fdecode<a>(j, l);
+    const int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+    bool valid = x[a] <= g.n[a] && (l[a] < ext || x[a] == g.n[a]);
 #pragma unroll
     for (int b = 0; b < D; ++b)
       if (b != a) valid = valid && x[b] < g.n[b];
-    if (!valid) continue;
+    if (!valid) return;
     const int fid = face_index(g, a, x);
     const bool has_lo = x[a] >= 1, has_hi = x[a] < g.n[a];
     int lo[3] = {l[0], l[1], l[2]};
@@ -259,10 +435,10 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
         w0 = k0 * ik;
         w1 = k1 * ik;
       }
-      const double g0 = face_mobility_co<D>(g, s0, a, 1.0);
-      const double g1 = face_mobility_co<D>(g, s1, a, -1.0);
+      const double g0 = face_mobility_co<D, LAW, a>(g, s0, 1.0);
+      const double g1 = face_mobility_co<D, LAW, a>(g, s1, -1.0);
       const double jump = g.area[a] * g.isv * ((p00 + kSqrt3 * p0a) - (p10 - kSqrt3 * p1a));
-      const double sig = g.pen * 2.0 * k0 * k1 * ik / g.hf[a];
+      const double sig = g.pen * 2.0 * k0 * k1 * ik * (1.0 / g.hf[a]);
       F = -(w0 * k0 * g0 * (gf * p0a) + w1 * k1 * g1 * (gf * p1a)) + sig * jump;
     } else {
       const double al = has_lo ? 1.0 : -1.0;   // outward normal sign
@@ -272,7 +448,7 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
       if (bt == LRBMS_BC_NEUMANN) {
         out = val * g.area[a];
       } else if (bt == LRBMS_BC_DIRICHLET) {
-        const double gm = face_mobility_co<D>(g, s0, a, al);
+        const double gm = face_mobility_co<D, LAW, a>(g, s0, al);
         const double sig = g.pen * k0 / g.hf[a];
         const double trace = g.area[a] * g.isv * (p00 + kSqrt3 * al * p0a);
         out = -k0 * gm * (al * gf * p0a) + sig * (trace - val * g.area[a]);
@@ -281,16 +457,13 @@ __global__ __launch_bounds__(256) void k_flux(Geom g, const double* __restrict__
     }
     flux[fid] = F;
     if (!isfinite(F)) atomicMin(g.status, (int)LRBMS_E_NONFINITE);
-  }
+  });
 }
 
 hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, double* flux,
                        hipStream_t st) {
   ktimer_begin(KK_FLUX, st);
-  if (g.dim == 2)
-    hipLaunchKernelGGL(k_flux<2>, tile_grid<2>(g), dim3(256), 0, st, g, ph, sat, flux);
-  else
-    hipLaunchKernelGGL(k_flux<3>, tile_grid<3>(g), dim3(256), 0, st, g, ph, sat, flux);
+  LRBMS_FACE_LAUNCH(k_flux, g, st, g, ph, sat, flux);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
@@ -300,63 +473,75 @@ hipError_t launch_flux(const Geom& g, const double* ph, const double* sat, doubl
 // Def. saturationDG with explicit Euler: out = s + dt/phi (q2 term + volume
 // term int_e u f_w(s) . grad v - upwind face terms - jump penalty); RT0
 // velocity of the face fluxes; 2-point Gauss rules.
-template <int D>
+template <int D, int LAW>
 __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restrict__ sat,
                                                    const double* __restrict__ flux,
                                                    double* __restrict__ out) {
   using TL = Tiling<D>;
   using T = TileShape<D>;
   constexpr int R = D + 1, NQF = 1 << (D - 1), NQC = 1 << D;
-  __shared__ double shs[R][TL::NH];
-  __shared__ double shk[TL::NH];
+  // The halo (states, permeabilities) is needed by the face pass only: the
+  // face results are kept in registers until every thread has passed it and
+  // then stored over the halo, which keeps the workgroup's LDS small enough
+  // for five workgroups per CU in 3D.
+  constexpr int NHALO = (R + 1) * TL::NH, NA = D * TL::NF;
+  __shared__ double shHA[NHALO > NA ? NHALO : NA];
   __shared__ double shF[TL::NF];
-  __shared__ double shA[D][TL::NF];
-  const int o[3] = {(int)blockIdx.x * T::X, (int)blockIdx.y * T::Y, (int)blockIdx.z * T::Z};
-  stage_halo<D>(g, sat, o, shs, shk);
+  double(*shs)[TL::NH] = reinterpret_cast<double(*)[TL::NH]>(shHA);
+  double* shk = shHA + R * TL::NH;
+  double(*shA)[TL::NF] = reinterpret_cast<double(*)[TL::NF]>(shHA);
+  int o[3];
+  tile_origin<D>(g, o);
+  // this thread's cell (the cell pass below), its source and porosity loaded
+  // with the halo and the face fluxes
+  const int tid = threadIdx.x;
+  const int l[3] = {tid % T::X, (tid / T::X) % T::Y, tid / (T::X * T::Y)};
+  const int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
+  bool cell_in = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) cell_in = cell_in && x[a] < g.n[a];
+  const int e = cell_in ? cell_index(g, x) : 0;
+  const double q2 = g.q2[e], phi = g.poro[e];
+  {
+    HaloRegs<D, true> rs;
+    rs.load(g, sat, o);
+    stage_face_fluxes<D>(g, flux, o, shF);
+    rs.store(shs, shk);
+  }
   __syncthreads();
   const double gp = 1.0 / kSqrt3;
   // ---- faces: A0 = sum_q tot_q w_q / sqrt|e|, At = the same times xi_t
-  for (int lf = threadIdx.x; lf < TL::NF; lf += blockDim.x) {
-    int a, l[3];
-    TL::fdecode(lf, a, l);
-    int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-    bool valid = x[a] <= g.n[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b)
-      if (b != a) valid = valid && x[b] < g.n[b];
-    double F = 0.0, A[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) A[k] = 0.0;
-    if (valid) {
-      const int fid = face_index(g, a, x);
-      F = flux[fid];
-      const bool has_lo = x[a] >= 1, has_hi = x[a] < g.n[a];
-      int lo[3] = {l[0], l[1], l[2]};
+  auto face = [&](auto AX, int lf, int j, double (&A)[D]) {
+    constexpr int a = decltype(AX)::value;
+    constexpr int t0 = Tang<a>::t0, t1 = Tang<a>::t1;
+    int lfc[3], xf[3];
+    const int fid = tile_face<D, a>(g, o, j, lfc, xf);
+    const double F = shF[lf];
+    const double iarea = 1.0 / g.area[a], ihf = 1.0 / g.hf[a];
+    if (fid >= 0) {
+      const bool has_lo = xf[a] >= 1, has_hi = xf[a] < g.n[a];
+      int lo[3] = {lfc[0], lfc[1], lfc[2]};
       lo[a] -= 1;
-      const int hlo = TL::hidx(lo), hhi = TL::hidx(l);
-      int tax[2] = {0, 0}, nt = 0;
-#pragma unroll
-      for (int b = 0; b < D; ++b)
-        if (b != a) tax[nt++] = b;
-      const double wq = g.area[a] / NQF, Fa = F / g.area[a];
+      const int hlo = TL::hidx(lo), hhi = TL::hidx(lfc);
+      const double wq = g.area[a] / NQF, Fa = F * iarea;
       if (has_lo && has_hi) {
         const double klo = shk[hlo], khi = shk[hhi];
-        const double sig = g.sat_pen * (g.pen * 2.0 * klo * khi / (klo + khi)) / g.hf[a];
+        const double sig = g.sat_pen * (g.pen * 2.0 * klo * khi / (klo + khi)) * ihf;
 #pragma unroll
         for (int q = 0; q < NQF; ++q) {
           double sl[3] = {0, 0, 0}, sh[3] = {0, 0, 0}, xt[2] = {0, 0};
           sl[a] = kSqrt3;
           sh[a] = -kSqrt3;
-#pragma unroll
-          for (int ti = 0; ti < D - 1; ++ti) {
-            xt[ti] = ((q >> ti) & 1) ? gp : -gp;
-            sl[tax[ti]] = kSqrt3 * xt[ti];
-            sh[tax[ti]] = kSqrt3 * xt[ti];
+          xt[0] = (q & 1) ? gp : -gp;
+          sl[t0] = sh[t0] = kSqrt3 * xt[0];
+          if (D == 3) {
+            xt[1] = ((q >> 1) & 1) ? gp : -gp;
+            sl[t1] = sh[t1] = kSqrt3 * xt[1];
           }
           const double vlo = halo_value<D>(shs, hlo, sl, g.isv);
           const double vhi = halo_value<D>(shs, hhi, sh, g.isv);
           const double up = (F >= 0.0) ? vlo : vhi;
-          const double tw = (Fa * frac_flow(g, up) + sig * (vlo - vhi)) * wq * g.isv;
+          const double tw = (Fa * frac_flow_law<LAW>(g, up) + sig * (vlo - vhi)) * wq * g.isv;
           A[0] += tw;
 #pragma unroll
           for (int ti = 0; ti < D - 1; ++ti) A[ti + 1] += tw * xt[ti];
@@ -367,43 +552,61 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
         const int hc = has_lo ? hlo : hhi;
         const bool sd = g.bc_sat[fid] == 1;
         const double sval = g.bc_sval[fid];
-        const double sig = g.sat_pen * (g.pen * shk[hc]) / g.hf[a];
+        const double sig = g.sat_pen * (g.pen * shk[hc]) * ihf;
         const double fout = al * Fa;
 #pragma unroll
         for (int q = 0; q < NQF; ++q) {
           double sq[3] = {0, 0, 0}, xt[2] = {0, 0};
           sq[a] = kSqrt3 * al;
-#pragma unroll
-          for (int ti = 0; ti < D - 1; ++ti) {
-            xt[ti] = ((q >> ti) & 1) ? gp : -gp;
-            sq[tax[ti]] = kSqrt3 * xt[ti];
+          xt[0] = (q & 1) ? gp : -gp;
+          sq[t0] = kSqrt3 * xt[0];
+          if (D == 3) {
+            xt[1] = ((q >> 1) & 1) ? gp : -gp;
+            sq[t1] = kSqrt3 * xt[1];
           }
           const double ve = halo_value<D>(shs, hc, sq, g.isv);
           const double chi = sd ? sval : ve;
-          const double tw = (fout * frac_flow(g, chi) + (sd ? sig * (ve - sval) : 0.0)) * wq * g.isv;
+          const double tw =
+              (fout * frac_flow_law<LAW>(g, chi) + (sd ? sig * (ve - sval) : 0.0)) * wq * g.isv;
           A[0] += tw;
 #pragma unroll
           for (int ti = 0; ti < D - 1; ++ti) A[ti + 1] += tw * xt[ti];
         }
       }
     }
-    shF[lf] = F;
+  };
+  constexpr int NFI = (TL::NF + kTileThreads - 1) / kTileThreads;
+  double Ar[NFI][D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) shA[k][lf] = A[k];
+  for (int it = 0; it < NFI; ++it) {
+    const int lf = tid + kTileThreads * it;
+#pragma unroll
+    for (int k = 0; k < D; ++k) Ar[it][k] = 0.0;
+    if (lf < TL::FX)
+      face(std::integral_constant<int, 0>(), lf, lf, Ar[it]);
+    else if (D == 2 || lf < TL::FX + TL::FY) {
+      if (lf < TL::NF) face(std::integral_constant<int, 1>(), lf, lf - TL::FX, Ar[it]);
+    } else if (lf < TL::NF) {
+      face(std::integral_constant<int, D - 1>(), lf, lf - TL::FX - TL::FY, Ar[it]);
+    }
   }
-  __syncthreads();
-  // ---- cells
-  const int tid = threadIdx.x;
-  const int l[3] = {tid % T::X, (tid / T::X) % T::Y, tid / (T::X * T::Y)};
-  const int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-    if (x[a] >= g.n[a]) return;
-  const int nc = g.ncell, e = cell_index(g, x), h = TL::hidx(l);
+  const int h = TL::hidx(l);
   double se[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < R; ++k) se[k] = shs[k][h];
-  const double q2 = g.q2[e], phi = g.poro[e];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NFI; ++it) {
+    const int lf = tid + kTileThreads * it;
+    if (lf < TL::NF) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) shA[k][lf] = Ar[it][k];
+    }
+  }
+  __syncthreads();
+  // ---- cells
+  if (!cell_in) return;
+  const int nc = g.ncell;
   double Flo[3], Fhi[3];
   int flo[3], fhi[3];
 #pragma unroll
@@ -427,7 +630,7 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
         xi[a] = ((p >> a) & 1) ? gp : -gp;
         sq[a] = kSqrt3 * xi[a];
       }
-      const double fw = frac_flow(g, p1_value(se, D, sq, g.isv));
+      const double fw = frac_flow_law<LAW>(g, p1_value(se, D, sq, g.isv));
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const double t = 0.5 * (1.0 + xi[a]);
@@ -461,9 +664,10 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
     }
   }
   bool bad = false;
+  const double dtp = g.dt / phi;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const double v = se[k] + g.dt * Rr[k] / phi;
+    const double v = se[k] + dtp * Rr[k];
     out[(long long)k * nc + e] = v;
     bad |= !isfinite(v);
   }
@@ -478,10 +682,7 @@ __global__ __launch_bounds__(256) void k_transport(Geom g, const double* __restr
 hipError_t launch_transport(const Geom& g, const double* sat, const double* flux, double* sat_bar,
                             hipStream_t st) {
   ktimer_begin(KK_TRANSPORT, st);
-  if (g.dim == 2)
-    hipLaunchKernelGGL(k_transport<2>, tile_grid<2>(g), dim3(256), 0, st, g, sat, flux, sat_bar);
-  else
-    hipLaunchKernelGGL(k_transport<3>, tile_grid<3>(g), dim3(256), 0, st, g, sat, flux, sat_bar);
+  LRBMS_FACE_LAUNCH(k_transport, g, st, g, sat, flux, sat_bar);
   ktimer_end(-1.0, -1.0, st);
   return hipGetLastError();
 }
@@ -506,33 +707,35 @@ __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restric
   using TL = Tiling<D>;
   using T = TileShape<D>;
   constexpr int R = D + 1, NQF = 1 << (D - 1);
+  // The face jumps are kept in registers until every thread has passed the
+  // face pass and then stored over the halo's slope coefficients, which the
+  // cell pass no longer reads (it takes the neighbours' means only).
+  static_assert((R - 1) * TL::NH >= TL::NF, "jumps fit over the slopes");
   __shared__ double shs[R][TL::NH];
   __shared__ double shF[TL::NF];
-  __shared__ double shJ[TL::NF];
-  const int o[3] = {(int)blockIdx.x * T::X, (int)blockIdx.y * T::Y, (int)blockIdx.z * T::Z};
-  stage_halo<D>(g, sb, o, shs, nullptr);
+  double* shJ = &shs[1][0];
+  int o[3];
+  tile_origin<D>(g, o);
+  {
+    HaloRegs<D, false> rs;
+    rs.load(g, sb, o);
+    stage_face_fluxes<D>(g, flux, o, shF);
+    rs.store(shs, nullptr);
+  }
   __syncthreads();
   const double gp = 1.0 / kSqrt3;
-  for (int lf = threadIdx.x; lf < TL::NF; lf += blockDim.x) {
-    int a, l[3];
-    TL::fdecode(lf, a, l);
-    int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-    bool valid = x[a] <= g.n[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b)
-      if (b != a) valid = valid && x[b] < g.n[b];
-    double F = 0.0, J = 0.0;
-    if (valid) {
-      const int fid = face_index(g, a, x);
-      F = flux[fid];
+  auto face = [&](auto AX, int lf, int j) -> double {
+    (void)lf;
+    constexpr int a = decltype(AX)::value;
+    constexpr int t0 = Tang<a>::t0, t1 = Tang<a>::t1;
+    int l[3], x[3];
+    const int fid = tile_face<D, a>(g, o, j, l, x);
+    double J = 0.0;
+    if (fid >= 0) {
       const bool has_lo = x[a] >= 1, has_hi = x[a] < g.n[a];
       int lo[3] = {l[0], l[1], l[2]};
       lo[a] -= 1;
       const int hlo = TL::hidx(lo), hhi = TL::hidx(l);
-      int tax[2] = {0, 0}, nt = 0;
-#pragma unroll
-      for (int b = 0; b < D; ++b)
-        if (b != a) tax[nt++] = b;
       const double wq = g.area[a] / NQF;
       const bool interior = has_lo && has_hi;
       const bool sd = !interior && g.bc_sat[fid] == 1;
@@ -545,11 +748,13 @@ __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restric
           double sl[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
           sl[a] = interior ? kSqrt3 : kSqrt3 * al;
           sh[a] = -kSqrt3;
-#pragma unroll
-          for (int ti = 0; ti < D - 1; ++ti) {
-            const double xt = ((q >> ti) & 1) ? gp : -gp;
-            sl[tax[ti]] = kSqrt3 * xt;
-            sh[tax[ti]] = kSqrt3 * xt;
+          {
+            const double xt = (q & 1) ? gp : -gp;
+            sl[t0] = sh[t0] = kSqrt3 * xt;
+          }
+          if (D == 3) {
+            const double xt = ((q >> 1) & 1) ? gp : -gp;
+            sl[t1] = sh[t1] = kSqrt3 * xt;
           }
           // low side minus high side; a Dirichlet face: the cell's trace minus s_D
           const double jmp = interior ? halo_value<D>(shs, hlo, sl, g.isv) - halo_value<D>(shs, hhi, sh, g.isv)
@@ -558,20 +763,40 @@ __global__ __launch_bounds__(256) void k_limiter(Geom g, const double* __restric
         }
       }
     }
-    shF[lf] = F;
-    shJ[lf] = fabs(J);
-  }
-  __syncthreads();
+    return fabs(J);
+  };
   const int tid = threadIdx.x;
+  constexpr int NFI = (TL::NF + kTileThreads - 1) / kTileThreads;
+  double Jr[NFI];
+#pragma unroll
+  for (int it = 0; it < NFI; ++it) {
+    const int lf = tid + kTileThreads * it;
+    Jr[it] = 0.0;
+    if (lf < TL::FX)
+      Jr[it] = face(std::integral_constant<int, 0>(), lf, lf);
+    else if (D == 2 || lf < TL::FX + TL::FY) {
+      if (lf < TL::NF) Jr[it] = face(std::integral_constant<int, 1>(), lf, lf - TL::FX);
+    } else if (lf < TL::NF) {
+      Jr[it] = face(std::integral_constant<int, D - 1>(), lf, lf - TL::FX - TL::FY);
+    }
+  }
   const int l[3] = {tid % T::X, (tid / T::X) % T::Y, tid / (T::X * T::Y)};
   const int x[3] = {o[0] + l[0], o[1] + l[1], o[2] + l[2]};
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-    if (x[a] >= g.n[a]) return;
-  const int nc = g.ncell, e = cell_index(g, x), h = TL::hidx(l);
+  const int h = TL::hidx(l);
   double se[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < R; ++k) se[k] = shs[k][h];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NFI; ++it) {
+    const int lf = tid + kTileThreads * it;
+    if (lf < TL::NF) shJ[lf] = Jr[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    if (x[a] >= g.n[a]) return;
+  const int nc = g.ncell, e = cell_index(g, x);
   const double mean = se[0] * g.isv;
   bool outside = false;
 #pragma unroll
