@@ -72,7 +72,10 @@ enum { LRBMS_DIRECT = 0, LRBMS_DIRECT_FIT = 1, LRBMS_AFFINE = 2 };
 
 enum { LRBMS_BC_INTERIOR = 0, LRBMS_BC_NEUMANN = 1, LRBMS_BC_DIRICHLET = 2 };
 
-/* Problem statement (Sec. 2 and Sec. 3.1 of the paper; gravity is zero).
+/* Problem statement (Sec. 2 and Sec. 3.1 of the paper).  The densities and
+ * the gravity vector are part of the statement; this library solves the
+ * case without gravity (the paper's experiments have none), so a non-zero
+ * grav is rejected with LRBMS_E_ARG and the densities are not used.
  * All pointers are HOST pointers and are copied by the create calls.        */
 typedef struct lrbms_problem {
   int32_t dim;              /* 2 or 3                                               */
@@ -97,6 +100,8 @@ typedef struct lrbms_problem {
   double sat_penalty_scale; /* multiplies sigma_f in the saturation equation        */
   int32_t limiter;          /* 1: apply the slope limiter after each Euler step     */
   double dt;                /* time step (> 0)                                      */
+  double dens_w, dens_o;    /* densities rho_w, rho_o (finite; unused without gravity) */
+  double grav[3];           /* gravity vector G; must be zero                       */
 } lrbms_problem;
 
 typedef struct lrbms_model lrbms_model;

@@ -151,6 +151,11 @@ static int check_problem(const lrbms_problem* p) {
   if (p->weights != 0 && p->weights != 1) return (set_error("weights must be 0 or 1"), LRBMS_E_ARG);
   if (!(p->dt > 0.0)) return (set_error("dt must be > 0"), LRBMS_E_ARG);
   if (!(p->penalty_c > 0.0)) return (set_error("penalty_c must be > 0"), LRBMS_E_ARG);
+  if (!std::isfinite(p->dens_w) || !std::isfinite(p->dens_o))
+    return (set_error("densities must be finite"), LRBMS_E_ARG);
+  for (int a = 0; a < 3; ++a)
+    if (p->grav[a] != 0.0)
+      return (set_error("gravity is not supported: grav must be zero"), LRBMS_E_ARG);
   return LRBMS_OK;
 }
 

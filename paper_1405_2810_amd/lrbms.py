@@ -39,7 +39,8 @@ class Problem_C(C.Structure):
                 ("bc_type", C.c_void_p), ("bc_val", C.c_void_p), ("bc_sat", C.c_void_p),
                 ("bc_sval", C.c_void_p), ("q1", C.c_void_p), ("q2", C.c_void_p),
                 ("penalty_c", C.c_double), ("weights", C.c_int32),
-                ("sat_penalty_scale", C.c_double), ("limiter", C.c_int32), ("dt", C.c_double)]
+                ("sat_penalty_scale", C.c_double), ("limiter", C.c_int32), ("dt", C.c_double),
+                ("dens_w", C.c_double), ("dens_o", C.c_double), ("grav", C.c_double * 3)]
 
 
 class KernelStat_C(C.Structure):
@@ -230,6 +231,9 @@ class ProblemC:
         s.q1, s.q2 = arr(p.q1, np.float64), arr(p.q2, np.float64)
         s.penalty_c, s.weights = float(p.penalty_c), int(p.weights)
         s.sat_penalty_scale, s.limiter, s.dt = float(p.sat_penalty_scale), int(p.limiter), float(p.dt)
+        s.dens_w, s.dens_o = float(p.dens_w), float(p.dens_o)
+        for a in range(3):
+            s.grav[a] = float(p.grav[a])
         self.struct = s
 
     def ref(self):

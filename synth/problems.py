@@ -65,6 +65,11 @@ class Problem:
     t_end: float = 0.0            # horizon T of the mobility profiles (0: n_steps * dt)
     seed: int = 0
     name: str = ""
+    # densities and gravity of the problem statement; no configuration here
+    # has gravity, so the densities never enter the equations
+    dens_w: float = 1000.0
+    dens_o: float = 1000.0
+    grav: tuple = (0.0, 0.0, 0.0)
 
     @property
     def ncell(self) -> int:

@@ -33,6 +33,16 @@ def test_invalid_problem_rejected_before_device_work(L):
     with pytest.raises(L.LrbmsError) as ei:
         L.Model.create(bad, [1] * 4, np.zeros(3 * 64))
     assert ei.value.code == -1
+    # the problem statement carries gravity; the library solves the case
+    # without it and says so instead of ignoring a non-zero vector
+    bad = p.copy(grav=(0.0, -9.81, 0.0))
+    with pytest.raises(L.LrbmsError) as ei:
+        L.Model.create(bad, [1] * 4, np.zeros(3 * 64))
+    assert ei.value.code == -1 and "gravity" in str(ei.value)
+    bad = p.copy(dens_w=float("nan"))
+    with pytest.raises(L.LrbmsError) as ei:
+        L.Model.create(bad, [1] * 4, np.zeros(3 * 64))
+    assert ei.value.code == -1
 
 
 def test_null_out_pointer(L):
