@@ -71,7 +71,7 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def build_model(p, n_snap, cap, seed):
-    """Local bases by the library's host Gram-Schmidt of seeded smooth
+    """Local bases by the library's device Gram-Schmidt of seeded smooth
     snapshot fields, 1_E first, N_E = cap in every box."""
     from synth import smooth_fields
     from paper_1405_2810_amd.lrbms import Model

@@ -139,6 +139,35 @@ def test_fused_batch_of_many_grids(L):
             m.close()
 
 
+def test_fused_batch_with_ensemble_basis_sizes(L):
+    """Members built like the benchmark ensemble's: local bases of 61
+    plane-wave fields plus 1_E truncated to seeded sizes of 5..60 per box (so
+    the 64-column assembly tiles and the skipping of tiles past a box's own
+    size are taken), each member autotuned (assembly variant, solver shapes,
+    refinement), 2D and 3D, in a fused graph batch and a fused batch of
+    direct launches: every member equal to its plain path."""
+    from synth import CONFIGS, ensemble_caps, wave_fields
+    probs, models = [], []
+    try:
+        for i, name in enumerate(["small2d", "small3d", "small2d", "small3d"]):
+            p = make_problem(name, seed=CONFIGS[name]["seed"] + i)
+            full = L.Model.from_snapshots(p, wave_fields(p, 61, np.random.default_rng(70 + i)),
+                                          ne_cap=60, unit_functions=True)
+            caps = ensemble_caps(p, np.random.default_rng(80 + i))
+            m = full.truncated(caps)
+            full.close()
+            m.autotune(_state(p, 90 + i), reps=1)
+            probs.append(p)
+            models.append(m)
+        widest = max(int(m.export_basis()[0].max()) for m in models)
+        assert widest > 48, widest   # the 64-column assembly tiles are used
+        _check_batch(L, probs, models, L.DIRECT, True, steps=3, fused=True)
+        _check_batch(L, probs, models, L.DIRECT, False, steps=3, fused=True)
+    finally:
+        for m in models:
+            m.close()
+
+
 def test_batch_arguments(L):
     p, m = _model(L, "tiny2d")
     try:
