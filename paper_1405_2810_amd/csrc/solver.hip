@@ -829,8 +829,9 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
                                                     double* __restrict__ Inv, int* status,
                                                     double* __restrict__ pf,
                                                     const int* __restrict__ active) {
+  // Two tiles and the factorization's work area (77 KB): two workgroups fit
+  // a CU.  Values that outlive a tile's reuse are held in registers.
   __shared__ Tile S0[kNB];
-  __shared__ Tile S1[kNB];
   __shared__ Tile S2[kNB];
   __shared__ TileAux aux;
   const StepItem it = items[xcd_item(blockIdx.x, gridDim.x)];
@@ -867,13 +868,13 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int idx = tid0 + 256 * e;
-        S1[idx >> 6][idx & 63] = la[e];
+        S0[idx >> 6][idx & 63] = la[e];
         S2[idx >> 6][idx & 63] = lp[e];
       }
       __syncthreads();
       if (cp + 1 < cp1) load(cp + 1);   // in flight during the products
       for (int c = 0; c < kNB / 4; ++c) {
-        const double a = S1[16 * w + r][4 * c + q];
+        const double a = S0[16 * w + r][4 * c + q];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) c2[cb] = mfma16(a, S2[16 * cb + r][4 * c + q], c2[cb]);
       }
@@ -882,11 +883,11 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
+      for (int v = 0; v < 4; ++v) S0[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
     __syncthreads();
     double* dst = pf + f.pf_off +
                   (((long long)(p & 1) * f.pf_nt + it.ti) * f.pf_ns + sc) * (kNB * kNB);
-    for (int idx = tid0; idx < kNB * kNB; idx += 256) dst[idx] = S1[idx >> 6][idx & 63];
+    for (int idx = tid0; idx < kNB * kNB; idx += 256) dst[idx] = S0[idx >> 6][idx & 63];
     return;
   }
   double* Fp = F + f.off;
@@ -903,7 +904,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   // earlier panels' products sum_c L(R, c) L(P, c)^T are subtracted from
   // those rows: the last panel's formed here on FP64 MFMA (L from the store),
   // the ones before it summed by the previous step's prefetch items (chunks
-  // of kPfPanels panels), added in chunk order, all staged in S1
+  // of kPfPanels panels), added in chunk order, all staged in S2
   const bool left = !upd && R0 >= f.m && it.panel > 0;
   const int mU = f.npanels * kNB;
   const int cp_first = it.panel >= 2 ? it.panel - 1 : 0;
@@ -928,13 +929,13 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
       for (int p = 0; p < 16; ++p) {
         const int idx = tid + 256 * p;
-        S1[idx >> 6][idx & 63] = la[p];
+        S0[idx >> 6][idx & 63] = la[p];
         S2[idx >> 6][idx & 63] = lp[p];
       }
       __syncthreads();
       if (cp + 1 < it.panel) load(cp + 1);   // in flight during the products
       for (int c = 0; c < kNB / 4; ++c) {
-        const double a = S1[16 * w + r][4 * c + q];
+        const double a = S0[16 * w + r][4 * c + q];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) c2[cb] = mfma16(a, S2[16 * cb + r][4 * c + q], c2[cb]);
       }
@@ -943,16 +944,16 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
+      for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = c2[cb][v];
     __syncthreads();
     if (it.panel >= 2) {
       const int nsp = (it.panel - 1 + kPfPanels - 1) / kPfPanels;
       const double* src =
           pf + f.pf_off + ((long long)(it.panel & 1) * f.pf_nt + it.ti) * f.pf_ns * (kNB * kNB);
       for (int idx = tid; idx < kNB * kNB; idx += 256) {
-        double a = S1[idx >> 6][idx & 63];
+        double a = S2[idx >> 6][idx & 63];
         for (int sc = 0; sc < nsp; ++sc) a += src[(long long)sc * (kNB * kNB) + idx];
-        S1[idx >> 6][idx & 63] = a;
+        S2[idx >> 6][idx & 63] = a;
       }
       __syncthreads();
     }
@@ -969,30 +970,36 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
     bv[p] = (i < nr && k < nb) ? Fp[(R0 + i) + (long long)(c0 + k) * lda] : 0.0;
     fold[p] = (upd && i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
   }
+  // (a U-row tile's left-looking sums are in S2: each entry is read and
+  // replaced by the thread that owns it)
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int idx = tid + 256 * p;
     S0[idx >> 6][idx & 63] = li[p];
-    S2[idx & 63][idx >> 6] = (left && R0 + (idx & 63) >= mU) ? bv[p] - S1[idx & 63][idx >> 6] : bv[p];
+    S2[idx & 63][idx >> 6] = (left && R0 + (idx & 63) >= mU) ? bv[p] - S2[idx & 63][idx >> 6] : bv[p];
   }
   __syncthreads();
   d4 acc[4];
   times_inv_t(S2, S0, nb, acc);
+  __syncthreads();   // the F rows in S2 are consumed: L(ti) goes there
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) S1[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
+    for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
   __syncthreads();
   if (it.tj <= 0) {
     double* Lrow = Lb + lpanel_base(f, it.panel) + (long long)(R0 - cs) * kNB;
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
       const int i = idx >> 6, k = idx & 63;
-      if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = S1[i][k];
+      if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = S2[i][k];
     }
   }
   if (!upd) return;
-  Tile* Bt = S1;
+  // U = L(ti) L(tj)^T from At (rows) and Bt (columns)
+  Tile* At = S2;
+  Tile* Bt = S2;
   if (it.tj != it.ti) {
+    // L(ti) stays in registers (acc) while S2 takes the F rows of tile row tj
     double yv[16];
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
@@ -1000,28 +1007,33 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
       const int i = idx & 63, k = idx >> 6;
       yv[p] = (i < ncl && k < nb) ? Fp[(C0 + i) + (long long)(c0 + k) * lda] : 0.0;
     }
+    __syncthreads();   // the L row store has read S2
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
       const int idx = tid + 256 * p;
       S2[idx & 63][idx >> 6] = yv[p];
     }
     __syncthreads();
-    times_inv_t(S2, S0, nb, acc);
-    __syncthreads();
+    d4 acc2[4];
+    times_inv_t(S2, S0, nb, acc2);
+    __syncthreads();   // the panel inverse in S0 and the F rows in S2 are consumed
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) S0[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
+      for (int v = 0; v < 4; ++v) {
+        S2[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
+        S0[16 * w + q + 4 * v][16 * cb + r] = acc2[cb][v];
+      }
     __syncthreads();
     Bt = S0;
   }
-  // U = L(ti) L(tj)^T: wave w forms row block w
+  // wave w forms row block w
   d4 u[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) u[cb] = d4{0.0, 0.0, 0.0, 0.0};
   const int nc = (nb + 3) >> 2;
   for (int c = 0; c < nc; ++c) {
-    const double a = S1[16 * w + r][4 * c + q];
+    const double a = At[16 * w + r][4 * c + q];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) u[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], u[cb]);
   }
@@ -1042,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
   }
   if (!ahead) return;
   __syncthreads();
-  tile_factor_inv(S0, S1, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
+  tile_factor_inv(S0, S2, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
                   status);
 }
 
