@@ -23,8 +23,8 @@
 //             workgroup of the next diagonal tile factors it (look-ahead);
 //   schur     after the last panel, the U x U block and the right-hand-side
 //             row's U part in one product with all m columns of L_US
-//             (one 64 x 64 output tile per workgroup, FP64 MFMA), instead of
-//             one rank-64 update per panel;
+//             (one 128 x 128 output tile per workgroup, FP64 MFMA), instead
+//             of one rank-64 update per panel;
 //   backward  one workgroup per front, from the root down, with the stored
 //             tile inverses.
 // Diagonal tiles are factored by a 16-wide blocked Cholesky: the 16 x 16
@@ -38,6 +38,7 @@
 namespace lrbms {
 
 constexpr int kNB = 64;       // panel / tile width of the dense front kernels
+constexpr int kSB = 128;      // output tile of the deferred Schur complement
 constexpr int kMaxLd = 8192;  // largest front (rows) handled by the backward sweep
 
 struct FrontD {
@@ -102,9 +103,10 @@ struct AsmItem { int front, dr, dc, nr, nc, diag, nsrc, pad; AsmSrc src[3]; };
 // block and the right-hand-side row's U part are updated once, after the
 // last panel, by the deferred Schur complement (SchurItem).
 struct StepItem { int front, panel, ti, tj; };
-// One 64 x 64 output tile of a front's deferred Schur complement: rows
-// m + 64 ti .. (U rows and the right-hand-side row), columns m + 64 tj ..
-// (U columns), tj <= ti.
+// One kSB x kSB output tile of a front's deferred Schur complement: rows
+// m + kSB ti .. (U rows and the right-hand-side row), columns m + kSB tj ..
+// (U columns), tj <= ti; on a diagonal tile (ti = tj) the kNB x kNB block
+// above the diagonal (rows < kNB, columns >= kNB of the tile) is left out.
 struct SchurItem { int front, ti, tj, pad; };
 
 struct SolverPlan {

@@ -390,7 +390,7 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     for (int p : plan.level_fronts[h]) {
       const FrontD& d = plan.fronts[p];
       if (d.u == 0) continue;
-      const int nrt = (d.u + 1 + kNB - 1) / kNB, nct = (d.u + kNB - 1) / kNB;
+      const int nrt = (d.u + 1 + kSB - 1) / kSB, nct = (d.u + kSB - 1) / kSB;
       for (int ti = 0; ti < nrt; ++ti)
         for (int tj = 0; tj <= std::min(ti, nct - 1); ++tj)
           plan.schur_items[h].push_back(SchurItem{p, ti, tj, 0});
@@ -1735,8 +1735,8 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
     for (const SchurItem& it : plan.schur_items[h]) {
       if (it.front < 0 || it.front >= nf) return false;
       const FrontD& f = plan.fronts[it.front];
-      if (f.u < 1 || it.ti < 0 || it.tj < 0 || it.tj > it.ti || kNB * it.ti > f.u ||
-          kNB * it.tj >= f.u)
+      if (f.u < 1 || it.ti < 0 || it.tj < 0 || it.tj > it.ti || kSB * it.ti > f.u ||
+          kSB * it.tj >= f.u)
         return false;
     }
     for (const BwItem& it : plan.bw_items[h])
@@ -1858,72 +1858,118 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
 // on FP64 MFMA over the front's panels (L tiles from the panel-major store,
 // the next panel's loads in flight during the current panel's products),
 // then one read-modify-write of the tile.
-__global__ __launch_bounds__(256) void k_front_schur(const SchurItem* __restrict__ items,
+__global__ __launch_bounds__(256, 2) void k_front_schur(const SchurItem* __restrict__ items,
                                                      const FrontD* __restrict__ fronts,
                                                      double* __restrict__ F,
                                                      const double* __restrict__ Lb,
                                                      const int* __restrict__ active) {
-  __shared__ Tile SA[kNB];
-  __shared__ Tile SB[kNB];
+  // L rows of the tile's row block (A) and column block (B), 16 columns of a
+  // panel per stage; after the products the same memory stages U, 32 columns
+  // at a time, for a coalesced read-modify-write of the front.  Two
+  // workgroups per CU (the accumulators of a wave's 64 x 64 block take 128
+  // registers, the next stage's loads 32).
+  constexpr int KC = 16, SPP = kNB / KC;   // stages per full panel
+  constexpr int UC = 32;   // columns of U per pass of the read-modify-write
+  static_assert(kSB * (UC + 1) <= 2 * kSB * (KC + 1), "U staging fits");
+  __shared__ double Sbuf[2 * kSB * (KC + 1)];
+  double(*SA)[KC + 1] = reinterpret_cast<double(*)[KC + 1]>(Sbuf);
+  double(*SB)[KC + 1] = reinterpret_cast<double(*)[KC + 1]>(Sbuf + kSB * (KC + 1));
+  double(*SU)[UC + 1] = reinterpret_cast<double(*)[UC + 1]>(Sbuf);
   const SchurItem it = items[xcd_item(blockIdx.x, gridDim.x)];
   const FrontD f = fronts[it.front];
   if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   const int m = f.m;
-  const int R0 = m + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
-  const int C0 = m + it.tj * kNB, ncl = (int)min((long long)kNB, ld - C0);
+  const int R0 = m + it.ti * kSB, nr = (int)min((long long)kSB, lda - R0);
+  const int C0 = m + it.tj * kSB, ncl = (int)min((long long)kSB, ld - C0);
   const bool diag = it.ti == it.tj;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
-  double la[16], lb[16];
-  auto load = [&](int b) {
+  // wave (wr, wc) forms rows 64 wr.., columns 64 wc.. of the tile; on a
+  // diagonal tile the block above the diagonal is not formed
+  const int wr = w >> 1, wc = w & 1;
+  const bool idle = diag && wr < wc;
+  // stage c: panel c / SPP, columns KC (c % SPP) .. of it (the last panel
+  // has as many stages as it has columns to cover)
+  const int nb_last = m - (f.npanels - 1) * kNB;
+  const int nst = SPP * (f.npanels - 1) + (nb_last + KC - 1) / KC;
+  constexpr int NL = kSB * KC / 256;   // loads per thread and block per stage
+  double la[NL], lb[NL];
+  auto load = [&](int c) {
+    const int b = c / SPP, k0 = KC * (c % SPP);
     const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
     const double* Lp = Lb + lpanel_base(f, b);
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int idx = tid + 256 * p, li = idx >> 6, lk = idx & 63;
-      la[p] = (li < nr && lk < nb) ? Lp[(long long)(R0 - cs + li) * kNB + lk] : 0.0;
-      lb[p] = (!diag && li < ncl && lk < nb) ? Lp[(long long)(C0 - cs + li) * kNB + lk] : 0.0;
+    for (int e = 0; e < NL; ++e) {
+      const int idx = tid + 256 * e, li = idx / KC, k = k0 + idx % KC;
+      la[e] = (li < nr && k < nb) ? Lp[(long long)(R0 - cs + li) * kNB + k] : 0.0;
+      lb[e] = (!diag && li < ncl && k < nb) ? Lp[(long long)(C0 - cs + li) * kNB + k] : 0.0;
     }
   };
-  d4 acc[4];
+  d4 acc[4][4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
   load(0);
-  for (int b = 0; b < f.npanels; ++b) {
-    if (b > 0) __syncthreads();   // every wave is done with the previous tiles
+  for (int c = 0; c < nst; ++c) {
+    if (c > 0) __syncthreads();   // every wave is done with the previous stage
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-      const int idx = tid + 256 * p;
-      SA[idx >> 6][idx & 63] = la[p];
-      SB[idx >> 6][idx & 63] = lb[p];
+    for (int e = 0; e < NL; ++e) {
+      const int idx = tid + 256 * e;
+      SA[idx / KC][idx % KC] = la[e];
+      SB[idx / KC][idx % KC] = lb[e];
     }
     __syncthreads();
-    if (b + 1 < f.npanels) load(b + 1);
-    const Tile* Bt = diag ? SA : SB;
-    const int nc = (min(kNB, m - b * kNB) + 3) >> 2;
-    for (int c = 0; c < nc; ++c) {
-      const double a = SA[16 * w + r][4 * c + q];
+    if (c + 1 < nst) load(c + 1);
+    if (!idle) {
+      const int nb = min(kNB, m - (c / SPP) * kNB), kk = min(KC, nb - KC * (c % SPP));
+      const int nk = (kk + 3) >> 2;
+      double(*Bt)[KC + 1] = diag ? SA : SB;
+      for (int s4 = 0; s4 < nk; ++s4) {
+        double a[4], bv[4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], acc[cb]);
+        for (int rb = 0; rb < 4; ++rb) a[rb] = SA[64 * wr + 16 * rb + r][4 * s4 + q];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) bv[cb] = Bt[64 * wc + 16 * cb + r][4 * s4 + q];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = mfma16(a[rb], bv[cb], acc[rb][cb]);
+      }
     }
   }
-  __syncthreads();
+  // F(R0 + i, C0 + col) -= U(i, col), 32 columns per pass through SU: pass
+  // pc takes column blocks 2 (pc % 2) and 2 (pc % 2) + 1 of the waves wc = pc / 2
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+  for (int pc = 0; pc < kSB / UC; ++pc) {
+    if (UC * pc >= ncl) break;
+    __syncthreads();   // the stage buffers (or the previous pass's SU) are free
+    if (wc == (pc >> 1) && !idle) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) SA[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
-  __syncthreads();
-  double fold[16];
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-  for (int p = 0; p < 16; ++p) {
-    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
-    fold[p] = (i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
-  }
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-  for (int p = 0; p < 16; ++p) {
-    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
-    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = fold[p] - SA[i][k];
+          for (int v = 0; v < 4; ++v) {
+            const d4 a4 = (pc & 1) ? acc[rb][2 + h] : acc[rb][h];
+            SU[64 * wr + 16 * rb + q + 4 * v][16 * h + r] = a4[v];
+          }
+    }
+    __syncthreads();
+    double fold[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = tid + 256 * e, i = idx & (kSB - 1), col = UC * pc + (idx >> 7);
+      const bool ok = i < nr && col < ncl && !(diag && i < kNB && col >= kNB);
+      fold[e] = ok ? Fp[(R0 + i) + (long long)(C0 + col) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int idx = tid + 256 * e, i = idx & (kSB - 1), kc = idx >> 7, col = UC * pc + kc;
+      const bool ok = i < nr && col < ncl && !(diag && i < kNB && col >= kNB);
+      if (ok) Fp[(R0 + i) + (long long)(C0 + col) * lda] = fold[e] - SU[i][kc];
+    }
   }
 }
 

@@ -9,6 +9,7 @@ import pytest
 from synth import make_problem
 
 NB = 64
+SB = 128   # output tile of the deferred Schur complement
 
 
 def _ifaces(p):
@@ -143,13 +144,15 @@ def emulate(plan, blocks, fN, refine=False):
             f = fr[fi]
             Fp = view(F, f)
             ld, m = f["m"] + f["u"], f["m"]
-            R0, C0 = m + ti * NB, m + tj * NB
-            nr, ncl = min(NB, ld + 1 - R0), min(NB, ld - C0)
+            R0, C0 = m + ti * SB, m + tj * SB
+            nr, ncl = min(SB, ld + 1 - R0), min(SB, ld - C0)
             acc = np.zeros((nr, ncl))
             for b in range(f["npanels"]):
                 rows, cs_b = lpanel(f, b)
                 nbb = min(NB, m - b * NB)
                 acc += rows[R0 - cs_b:R0 - cs_b + nr, :nbb] @ rows[C0 - cs_b:C0 - cs_b + ncl, :nbb].T
+            if ti == tj:
+                acc[:NB, NB:] = 0.0   # the block above the diagonal is not formed
             Fp[R0:R0 + nr, C0:C0 + ncl] -= acc
 
     def rhs_rows(f):
