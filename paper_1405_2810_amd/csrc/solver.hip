@@ -1101,7 +1101,12 @@ __global__ __launch_bounds__(256) void k_front_bw_gemv(const BwItem* __restrict_
 // factorization; otherwise y_S = ysrc[voff ..] (k_front_forward of a new
 // right-hand side).  padd != nullptr: x_S is also added to padd (the
 // refinement's correction of p_N).
-__global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ list,
+// Threads of the backward sweep: kBwG waves, each a group of rows; a pass
+// updates kBwP panels at once (kNB / kBwG rows of each per thread), so that
+// every thread keeps kBwP x kNB / kBwG loads in flight per pass.
+constexpr int kBwG = 8, kBwT = 64 * kBwG, kBwR = kNB / kBwG, kBwP = kBwG;
+
+__global__ __launch_bounds__(kBwT) void k_front_backward(const int* __restrict__ list,
                                                         const FrontD* __restrict__ fronts,
                                                         const NodeRef* __restrict__ nodes,
                                                         const double* __restrict__ Lpan,
@@ -1112,137 +1117,140 @@ __global__ __launch_bounds__(256) void k_front_backward(const int* __restrict__ 
                                                         double* __restrict__ padd,
                                                         const int* __restrict__ active) {
   extern __shared__ double w[];   // m + u values
-  __shared__ double red[4][4][kNB];
+  __shared__ double red[kBwG][kBwP][kNB];
   __shared__ double xb[kNB];
   const FrontD f = fronts[list[blockIdx.x]];
   if (active && !active[f.member]) return;
   const int m = f.m, u = f.u, ld = m + u, np = f.npanels, tid = threadIdx.x;
   const int k = tid & 63, g = tid >> 6;
   auto csof = [&](int b) { return min(kNB * (b + 1), m); };
+  // sum over the row groups in a fixed order
+  auto group_sum = [&](int q, int col) {
+    double s = 0.0;
+#pragma unroll
+    for (int h = 0; h < kBwG; h += 2) s += red[h][q][col] + red[h + 1][q][col];
+    return s;
+  };
   // y_S from the right-hand-side rows, x_U from the parent
-  for (int i = tid; i < m; i += blockDim.x) {
+  for (int i = tid; i < m; i += kBwT) {
     const int b = i >> 6;
     w[i] = ysrc ? ysrc[f.voff + i]
                 : Lpan[lpanel_base(f, b) + (long long)(ld - csof(b)) * kNB + (i - kNB * b)];
   }
   for (int n = f.n_s_nodes; n < f.n_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
-    for (int i = tid; i < nr.size; i += blockDim.x) w[nr.pos + i] = pN[nr.pn_off + i];
+    for (int i = tid; i < nr.size; i += kBwT) w[nr.pos + i] = pN[nr.pn_off + i];
   }
   __syncthreads();
   // z_S = y_S - L_US^T x_U; a large front's products come in partial
   // vectors (k_front_bw_gemv), summed here in chunk order
   if (f.nzc > 0) {
-    for (int j = tid; j < m; j += blockDim.x) {
+    for (int j = tid; j < m; j += kBwT) {
       double acc = 0.0;
       for (int c = 0; c < f.nzc; ++c) acc += part[f.zoff + (long long)c * m + j];
       w[j] -= acc;
     }
     __syncthreads();
   }
-  // otherwise: four panels at a time, rows of U split over the waves
-  for (int p0 = 0; p0 < np && u > 0 && f.nzc == 0; p0 += 4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r0 = g; r0 < u; r0 += 64) {
-      double a[4][16];
+  // otherwise: kBwP panels at a time, rows of U split over the groups
+  for (int p0 = 0; p0 < np && u > 0 && f.nzc == 0; p0 += kBwP) {
+    double s[kBwP];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kBwP; ++q) s[q] = 0.0;
+    for (int r0 = g; r0 < u; r0 += kNB) {
+      double a[kBwP][kBwR];
+#pragma unroll
+      for (int q = 0; q < kBwP; ++q) {
         const int b = p0 + q;
-        const double* Lr = Lpan + lpanel_base(f, b) + (long long)(m - csof(b)) * kNB + k;
+        const double* Lr = Lpan + lpanel_base(f, b < np ? b : 0) +
+                           (long long)(m - csof(b < np ? b : 0)) * kNB + k;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int r = r0 + 4 * t;
+        for (int t = 0; t < kBwR; ++t) {
+          const int r = r0 + kBwG * t;
           a[q][t] = (b < np && r < u) ? Lr[(long long)r * kNB] : 0.0;
         }
       }
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int r = r0 + 4 * t;
+      for (int t = 0; t < kBwR; ++t) {
+        const int r = r0 + kBwG * t;
         const double xr = (r < u) ? w[m + r] : 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] = fma(a[q][t], xr, s[q]);
+        for (int q = 0; q < kBwP; ++q) s[q] = fma(a[q][t], xr, s[q]);
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[g][q][k] = s[q];
+    for (int q = 0; q < kBwP; ++q) red[g][q][k] = s[q];
     __syncthreads();
     {
       const int b = p0 + g;
-      if (b < np && k < min(kNB, m - kNB * b))
-        w[kNB * b + k] -= (red[0][g][k] + red[1][g][k]) + (red[2][g][k] + red[3][g][k]);
+      if (b < np && k < min(kNB, m - kNB * b)) w[kNB * b + k] -= group_sum(g, k);
     }
     __syncthreads();
   }
   for (int b = np - 1; b >= 0; --b) {
     const int c0 = b * kNB, nb = min(kNB, m - c0);
     const double* Li = Inv + f.inv_off + (long long)b * kNB * kNB;
-    // loads first: this thread's part of L_bb^{-1}, and rows c0 + 16 g + t of the
-    // four panels before b (lane = column of that panel)
-    double li[16], a[4][16];
+    // loads first: this thread's part of L_bb^{-1}, and rows c0 + kBwR g + t
+    // of the kBwP panels before b (lane = column of that panel)
+    double li[kBwR], a[kBwP][kBwR];
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) {
-      const int mr = 16 * g + mm;
+    for (int mm = 0; mm < kBwR; ++mm) {
+      const int mr = kBwR * g + mm;
       li[mm] = (mr < nb && mr >= k) ? Li[mr * kNB + k] : 0.0;
     }
+    auto load_rows = [&](int p1) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b2 = b - 1 - q;
-      const double* Lr = Lpan + lpanel_base(f, b2 < 0 ? 0 : b2) + (long long)(c0 - csof(b2 < 0 ? 0 : b2)) * kNB + k;
+      for (int q = 0; q < kBwP; ++q) {
+        const int b2 = p1 - q, bb = b2 < 0 ? 0 : b2;
+        const double* Lr = Lpan + lpanel_base(f, bb) + (long long)(c0 - csof(bb)) * kNB + k;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int kk = 16 * g + t;
-        a[q][t] = (b2 >= 0 && kk < nb) ? Lr[(long long)kk * kNB] : 0.0;
+        for (int t = 0; t < kBwR; ++t) {
+          const int kk = kBwR * g + t;
+          a[q][t] = (b2 >= 0 && kk < nb) ? Lr[(long long)kk * kNB] : 0.0;
+        }
       }
-    }
-    // x_b(k) = sum_{m >= k} Li(m, k) z_b(m): four partial sums over m
+    };
+    load_rows(b - 1);
+    // x_b(k) = sum_{m >= k} Li(m, k) z_b(m): partial sums over the groups
     double s = 0.0;
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) {
-      const int mr = 16 * g + mm;
+    for (int mm = 0; mm < kBwR; ++mm) {
+      const int mr = kBwR * g + mm;
       s = fma(li[mm], (mr < nb) ? w[c0 + mr] : 0.0, s);
     }
     red[g][0][k] = s;
     __syncthreads();
     if (tid < kNB) {
-      const double x = (tid < nb) ? (red[0][0][tid] + red[1][0][tid]) + (red[2][0][tid] + red[3][0][tid]) : 0.0;
+      const double x = (tid < nb) ? group_sum(0, tid) : 0.0;
       xb[tid] = x;
       if (tid < nb) w[c0 + tid] = x;
     }
     __syncthreads();
-    // z of panels b-1 .. b-4, then the older ones four at a time
-    for (int p1 = b - 1; p1 >= 0; p1 -= 4) {
-      if (p1 != b - 1) {
+    // z of panels b-1 .. b-kBwP, then the older ones kBwP at a time
+    for (int p1 = b - 1; p1 >= 0; p1 -= kBwP) {
+      if (p1 != b - 1) load_rows(p1);
+      double z[kBwP];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b2 = p1 - q;
-          const double* Lr = Lpan + lpanel_base(f, b2 < 0 ? 0 : b2) + (long long)(c0 - csof(b2 < 0 ? 0 : b2)) * kNB + k;
+      for (int q = 0; q < kBwP; ++q) z[q] = 0.0;
 #pragma unroll
-          for (int t = 0; t < 16; ++t) {
-            const int kk = 16 * g + t;
-            a[q][t] = (b2 >= 0 && kk < nb) ? Lr[(long long)kk * kNB] : 0.0;
-          }
-        }
-      }
-      double z[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < kBwR; ++t) {
+        const double x = xb[kBwR * g + t];
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const double x = xb[16 * g + t];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) z[q] = fma(a[q][t], x, z[q]);
+        for (int q = 0; q < kBwP; ++q) z[q] = fma(a[q][t], x, z[q]);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) red[g][q][k] = z[q];
+      for (int q = 0; q < kBwP; ++q) red[g][q][k] = z[q];
       __syncthreads();
       {
         const int b2 = p1 - g;
-        if (b2 >= 0) w[kNB * b2 + k] -= (red[0][g][k] + red[1][g][k]) + (red[2][g][k] + red[3][g][k]);
+        if (b2 >= 0) w[kNB * b2 + k] -= group_sum(g, k);
       }
       __syncthreads();
     }
   }
   for (int n = 0; n < f.n_s_nodes; ++n) {
     const NodeRef nr = nodes[f.node_off + n];
-    for (int i = tid; i < nr.size; i += blockDim.x) {
+    for (int i = tid; i < nr.size; i += kBwT) {
       const double x = w[nr.pos + i];
       pN[nr.pn_off + i] = x;
       if (padd) padd[nr.pn_off + i] += x;
@@ -2080,7 +2088,7 @@ static void backward_sweep(const SolverPlan& plan, const SolverDev& dev, const d
       ktimer_end(plan.bwg_flops[h], plan.bwg_bytes[h], st);
     }
     ktimer_begin(KK_FRONT_BACKWARD, st);
-    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(256), sizeof(double) * maxld, st,
+    hipLaunchKernelGGL(k_front_backward, dim3(n), dim3(kBwT), sizeof(double) * maxld, st,
                        dev.level_fronts[h], dev.fronts, dev.nodes, dev.L, dev.Inv, dev.part, ysrc,
                        pN, padd, active);
     ktimer_end(plan.bw_flops[h], plan.bw_bytes[h], st);
