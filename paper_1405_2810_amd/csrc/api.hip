@@ -1649,12 +1649,12 @@ static std::vector<int64_t> flatten_plan(const SolverPlan& plan) {
       o.insert(o.end(), v, v + 2);
     }
   }
-  // deferred Schur complements: per level its (front, ti, tj) tiles
+  // deferred Schur complements: per level its (front, ti, tj, wide) tiles
   for (int h = 0; h < H; ++h) {
     o.push_back((int64_t)plan.schur_items[h].size());
     for (auto& it : plan.schur_items[h]) {
-      int64_t v[3] = {it.front, it.ti, it.tj};
-      o.insert(o.end(), v, v + 3);
+      int64_t v[4] = {it.front, it.ti, it.tj, it.wide};
+      o.insert(o.end(), v, v + 4);
     }
   }
   return o;

@@ -103,11 +103,15 @@ struct AsmItem { int front, dr, dc, nr, nc, diag, nsrc, pad; AsmSrc src[3]; };
 // block and the right-hand-side row's U part are updated once, after the
 // last panel, by the deferred Schur complement (SchurItem).
 struct StepItem { int front, panel, ti, tj; };
-// One kSB x kSB output tile of a front's deferred Schur complement: rows
-// m + kSB ti .. (U rows and the right-hand-side row), columns m + kSB tj ..
-// (U columns), tj <= ti; on a diagonal tile (ti = tj) the kNB x kNB block
-// above the diagonal (rows < kNB, columns >= kNB of the tile) is left out.
-struct SchurItem { int front, ti, tj, pad; };
+// One output tile of a front's deferred Schur complement, T x T with T = kSB
+// when wide, else kNB: rows m + T ti .. (U rows and the right-hand-side row),
+// columns m + T tj .. (U columns), tj <= ti; on a wide diagonal tile (ti = tj)
+// the kNB x kNB block above the diagonal (rows < kNB, columns >= kNB of the
+// tile) is left out.  Fronts with at least kSchurWideMin U columns take wide
+// tiles (fewer re-reads of L_US); smaller ones the narrow tiles, whose
+// padding and launch share cost less there.
+struct SchurItem { int front, ti, tj, wide; };
+constexpr int kSchurWideMin = 512;
 
 struct SolverPlan {
   std::vector<FrontD> fronts;

@@ -390,10 +390,11 @@ bool build_solver_plan(int dim, const int nc_in[3], const std::vector<Sub>& subs
     for (int p : plan.level_fronts[h]) {
       const FrontD& d = plan.fronts[p];
       if (d.u == 0) continue;
-      const int nrt = (d.u + 1 + kSB - 1) / kSB, nct = (d.u + kSB - 1) / kSB;
+      const int wide = d.u >= kSchurWideMin ? 1 : 0, T = wide ? kSB : kNB;
+      const int nrt = (d.u + 1 + T - 1) / T, nct = (d.u + T - 1) / T;
       for (int ti = 0; ti < nrt; ++ti)
         for (int tj = 0; tj <= std::min(ti, nct - 1); ++tj)
-          plan.schur_items[h].push_back(SchurItem{p, ti, tj, 0});
+          plan.schur_items[h].push_back(SchurItem{p, ti, tj, wide});
     }
   split_steps(plan, split_min < 0 ? step_split_min() : split_min);
   assign_backward_split(plan);
@@ -1743,8 +1744,9 @@ bool plan_in_bounds(const SolverPlan& plan, long long nblk, long long nN) {
     for (const SchurItem& it : plan.schur_items[h]) {
       if (it.front < 0 || it.front >= nf) return false;
       const FrontD& f = plan.fronts[it.front];
-      if (f.u < 1 || it.ti < 0 || it.tj < 0 || it.tj > it.ti || kSB * it.ti > f.u ||
-          kSB * it.tj >= f.u)
+      const int T = it.wide ? kSB : kNB;
+      if (f.u < 1 || (it.wide != 0 && it.wide != 1) || it.ti < 0 || it.tj < 0 || it.tj > it.ti ||
+          T * it.ti > f.u || T * it.tj >= f.u)
         return false;
     }
     for (const BwItem& it : plan.bw_items[h])
@@ -1866,26 +1868,19 @@ __global__ __launch_bounds__(256) void k_front_update(const StepItem* __restrict
 // on FP64 MFMA over the front's panels (L tiles from the panel-major store,
 // the next panel's loads in flight during the current panel's products),
 // then one read-modify-write of the tile.
-__global__ __launch_bounds__(256, 2) void k_front_schur(const SchurItem* __restrict__ items,
-                                                     const FrontD* __restrict__ fronts,
-                                                     double* __restrict__ F,
-                                                     const double* __restrict__ Lb,
-                                                     const int* __restrict__ active) {
-  // L rows of the tile's row block (A) and column block (B), 16 columns of a
-  // panel per stage; after the products the same memory stages U, 32 columns
-  // at a time, for a coalesced read-modify-write of the front.  Two
-  // workgroups per CU (the accumulators of a wave's 64 x 64 block take 128
-  // registers, the next stage's loads 32).
+// Wide tile (kSB x kSB): wave (wr, wc) forms rows 64 wr.., columns 64 wc..
+// of the tile from L rows staged 16 columns at a time; after the products the
+// same memory stages U, 32 columns at a time, for a coalesced
+// read-modify-write of the front.  Two workgroups per CU (the accumulators of
+// a wave's 64 x 64 block take 128 registers, the next stage's loads 32).
+__device__ __forceinline__ void schur_wide(const SchurItem& it, const FrontD& f, double* F,
+                                           const double* __restrict__ Lb, double* Sbuf) {
   constexpr int KC = 16, SPP = kNB / KC;   // stages per full panel
   constexpr int UC = 32;   // columns of U per pass of the read-modify-write
   static_assert(kSB * (UC + 1) <= 2 * kSB * (KC + 1), "U staging fits");
-  __shared__ double Sbuf[2 * kSB * (KC + 1)];
   double(*SA)[KC + 1] = reinterpret_cast<double(*)[KC + 1]>(Sbuf);
   double(*SB)[KC + 1] = reinterpret_cast<double(*)[KC + 1]>(Sbuf + kSB * (KC + 1));
   double(*SU)[UC + 1] = reinterpret_cast<double(*)[UC + 1]>(Sbuf);
-  const SchurItem it = items[xcd_item(blockIdx.x, gridDim.x)];
-  const FrontD f = fronts[it.front];
-  if (active && !active[f.member]) return;
   const long long ld = f.m + f.u, lda = ld + 1;
   double* Fp = F + f.off;
   const int m = f.m;
@@ -1979,6 +1974,88 @@ __global__ __launch_bounds__(256, 2) void k_front_schur(const SchurItem* __restr
       if (ok) Fp[(R0 + i) + (long long)(C0 + col) * lda] = fold[e] - SU[i][kc];
     }
   }
+}
+
+// Narrow tile (kNB x kNB): wave w forms row block w; the L rows of the tile's
+// row and column blocks staged a panel at a time, the next panel's loads in
+// flight during the products.
+__device__ __forceinline__ void schur_narrow(const SchurItem& it, const FrontD& f, double* F,
+                                             const double* __restrict__ Lb, double* Sbuf) {
+  Tile* SA = reinterpret_cast<Tile*>(Sbuf);
+  Tile* SB = reinterpret_cast<Tile*>(Sbuf + kNB * (kNB + 1));
+  const long long ld = f.m + f.u, lda = ld + 1;
+  double* Fp = F + f.off;
+  const int m = f.m;
+  const int R0 = m + it.ti * kNB, nr = (int)min((long long)kNB, lda - R0);
+  const int C0 = m + it.tj * kNB, ncl = (int)min((long long)kNB, ld - C0);
+  const bool diag = it.ti == it.tj;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  double la[16], lb[16];
+  auto load = [&](int b) {
+    const int c0 = b * kNB, nb = min(kNB, m - c0), cs = c0 + nb;
+    const double* Lp = Lb + lpanel_base(f, b);
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p, li = idx >> 6, lk = idx & 63;
+      la[p] = (li < nr && lk < nb) ? Lp[(long long)(R0 - cs + li) * kNB + lk] : 0.0;
+      lb[p] = (!diag && li < ncl && lk < nb) ? Lp[(long long)(C0 - cs + li) * kNB + lk] : 0.0;
+    }
+  };
+  d4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int b = 0; b < f.npanels; ++b) {
+    if (b > 0) __syncthreads();   // every wave is done with the previous tiles
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int idx = tid + 256 * p;
+      SA[idx >> 6][idx & 63] = la[p];
+      SB[idx >> 6][idx & 63] = lb[p];
+    }
+    __syncthreads();
+    if (b + 1 < f.npanels) load(b + 1);
+    const Tile* Bt = diag ? SA : SB;
+    const int nc = (min(kNB, m - b * kNB) + 3) >> 2;
+    for (int c = 0; c < nc; ++c) {
+      const double a = SA[16 * w + r][4 * c + q];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma16(a, Bt[16 * cb + r][4 * c + q], acc[cb]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) SA[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
+  __syncthreads();
+  double fold[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
+    fold[p] = (i < nr && k < ncl) ? Fp[(R0 + i) + (long long)(C0 + k) * lda] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int idx = tid + 256 * p, i = idx & 63, k = idx >> 6;
+    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = fold[p] - SA[i][k];
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_front_schur(const SchurItem* __restrict__ items,
+                                                     const FrontD* __restrict__ fronts,
+                                                     double* __restrict__ F,
+                                                     const double* __restrict__ Lb,
+                                                     const int* __restrict__ active) {
+  constexpr int NW = 2 * kSB * (16 + 1), NN = 2 * kNB * (kNB + 1);
+  __shared__ double Sbuf[NW > NN ? NW : NN];
+  const SchurItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+  const FrontD f = fronts[it.front];
+  if (active && !active[f.member]) return;
+  if (it.wide)
+    schur_wide(it, f, F, Lb, Sbuf);
+  else
+    schur_narrow(it, f, F, Lb, Sbuf);
 }
 
 // ============================ upload / launch ================================

@@ -646,7 +646,7 @@ def _parse_plan(buf) -> dict:
     a split step lists its rows-only items, then its update items); then the
     split backward products: partial-vector doubles, the U-row map, 3 values
     per front (nzc, urow_off, zoff) and per level its (front, chunk) items;
-    then per level the (front, ti, tj) tiles of the deferred Schur
+    then per level the (front, ti, tj, wide) tiles of the deferred Schur
     complements."""
     it = iter(buf.tolist())
     nxt = lambda k: [next(it) for _ in range(k)]
@@ -676,9 +676,9 @@ def _parse_plan(buf) -> dict:
         f["nzc"], f["urow_off"], f["zoff"] = nxt(3)
     for lev in levels:
         lev["bw"] = [tuple(nxt(2)) for _ in range(next(it))]
-    # deferred Schur complements: per level (front, ti, tj) output tiles
+    # deferred Schur complements: per level (front, ti, tj, wide) output tiles
     for lev in levels:
-        lev["schur"] = [tuple(nxt(3)) for _ in range(next(it))]
+        lev["schur"] = [tuple(nxt(4)) for _ in range(next(it))]
     if next(it, None) is not None:
         raise ValueError("plan record longer than its layout")
     return dict(fronts=fronts, nodes=nodes, children=children, levels=levels,

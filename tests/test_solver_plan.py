@@ -140,18 +140,19 @@ def emulate(plan, blocks, fN, refine=False):
                     _factor_tile(Fp, f["m"], p + 1, Inv, f)
         # deferred Schur complement: (U + rhs row) x U minus L_US L_US^T over
         # all m columns, tile by tile, the panels in order
-        for fi, ti, tj in lev["schur"]:
+        for fi, ti, tj, wide in lev["schur"]:
             f = fr[fi]
             Fp = view(F, f)
             ld, m = f["m"] + f["u"], f["m"]
-            R0, C0 = m + ti * SB, m + tj * SB
-            nr, ncl = min(SB, ld + 1 - R0), min(SB, ld - C0)
+            T = SB if wide else NB
+            R0, C0 = m + ti * T, m + tj * T
+            nr, ncl = min(T, ld + 1 - R0), min(T, ld - C0)
             acc = np.zeros((nr, ncl))
             for b in range(f["npanels"]):
                 rows, cs_b = lpanel(f, b)
                 nbb = min(NB, m - b * NB)
                 acc += rows[R0 - cs_b:R0 - cs_b + nr, :nbb] @ rows[C0 - cs_b:C0 - cs_b + ncl, :nbb].T
-            if ti == tj:
+            if wide and ti == tj:
                 acc[:NB, NB:] = 0.0   # the block above the diagonal is not formed
             Fp[R0:R0 + nr, C0:C0 + ncl] -= acc
 
