@@ -29,6 +29,8 @@ __device__ double block_sum(double v, double* red) {
 // at most cap vectors.  sizes[s] receives the number kept.  Every thread
 // works on the coefficients i = tid + 256 k of a vector, so that between the
 // sums (which synchronize) no thread reads another's values.
+__device__ bool gs_extend_slot(double* base, long long len, int nb, double* red);
+
 __global__ __launch_bounds__(kGsThreads) void k_local_gs(Geom g, const Sub* __restrict__ subs,
                                                         const long long* __restrict__ slot_off,
                                                         const double* __restrict__ snaps,
@@ -66,32 +68,75 @@ __global__ __launch_bounds__(kGsThreads) void k_local_gs(Geom g, const Sub* __re
       v[i] = a;
       part += a * a;
     }
-    const double nv = sqrt(block_sum(part, red));
-    if (nv == 0.0) continue;
-    for (int pass = 0; pass < 2; ++pass)
-      for (int j = 0; j < nb; ++j) {
-        const double* b = base + (long long)j * len;
-        double d = 0.0;
-        for (long long i = tid; i < len; i += kGsThreads) d += b[i] * v[i];
-        const double dot = block_sum(d, red);
-        for (long long i = tid; i < len; i += kGsThreads) v[i] -= dot * b[i];
-      }
-    part = 0.0;
-    for (long long i = tid; i < len; i += kGsThreads) part += v[i] * v[i];
-    const double nw = sqrt(block_sum(part, red));
-    if (nw <= 1e-8 * nv) continue;
-    for (long long i = tid; i < len; i += kGsThreads) v[i] = v[i] / nw;
-    ++nb;
+    (void)part;
+    if (gs_extend_slot(base, len, nb, red)) ++nb;
   }
   if (tid == 0) sizes[blockIdx.x] = nb;
 }
 
+
+// Coefficients per thread of a candidate that the staged form of the
+// Gram-Schmidt step below holds in LDS (vectors of up to 32 x 256
+// coefficients).
+constexpr int kGsRegs = 32;
+
+// The step below with the candidate staged in LDS (each thread its own
+// coefficients, so no barrier beyond the sums') and this thread's
+// coefficients of each kept vector loaded once per projection, for its dot
+// product and its update; the candidate is written back once, when kept.
+// The same operations in the same order as the form in memory.
+__device__ bool gs_extend_staged(double* base, long long len, int nb, double* red) {
+  __shared__ double vs[kGsRegs * kGsThreads];
+  const int tid = threadIdx.x;
+  double* v = base + (long long)nb * len;
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < kGsRegs; ++t) {
+    const long long i = tid + (long long)kGsThreads * t;
+    const double x = i < len ? v[i] : 0.0;
+    vs[tid + kGsThreads * t] = x;
+    part += x * x;
+  }
+  const double nv = sqrt(block_sum(part, red));
+  if (nv == 0.0) return false;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < nb; ++j) {
+      const double* b = base + (long long)j * len;
+      double br[kGsRegs];
+#pragma unroll
+      for (int t = 0; t < kGsRegs; ++t) {
+        const long long i = tid + (long long)kGsThreads * t;
+        br[t] = i < len ? b[i] : 0.0;
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int t = 0; t < kGsRegs; ++t) d += br[t] * vs[tid + kGsThreads * t];
+      const double dot = block_sum(d, red);
+#pragma unroll
+      for (int t = 0; t < kGsRegs; ++t) vs[tid + kGsThreads * t] -= dot * br[t];
+    }
+  part = 0.0;
+#pragma unroll
+  for (int t = 0; t < kGsRegs; ++t) {
+    const double x = vs[tid + kGsThreads * t];
+    part += x * x;
+  }
+  const double nw = sqrt(block_sum(part, red));
+  if (nw <= 1e-8 * nv) return false;
+#pragma unroll
+  for (int t = 0; t < kGsRegs; ++t) {
+    const long long i = tid + (long long)kGsThreads * t;
+    if (i < len) v[i] = vs[tid + kGsThreads * t] / nw;
+  }
+  return true;
+}
 
 // Two-pass modified Gram-Schmidt of the candidate in slot nb against slots
 // 0 .. nb-1; the candidate is normalized and kept (returns true) unless its
 // remaining norm is <= 1e-8 of its norm.  Threads own the coefficients
 // i = tid + 256 k.
 __device__ bool gs_extend_slot(double* base, long long len, int nb, double* red) {
+  if (len <= (long long)kGsRegs * kGsThreads) return gs_extend_staged(base, len, nb, red);
   const int tid = threadIdx.x;
   double* v = base + (long long)nb * len;
   double part = 0.0;
