@@ -988,8 +988,13 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
   __syncthreads();
-  if (it.tj <= 0) {
-    double* Lrow = Lb + lpanel_base(f, it.panel) + (long long)(R0 - cs) * kNB;
+  // the look-ahead workgroup (tile (0, 0) with a next panel) stores its L
+  // rows after the next tile's factorization, from registers: a barrier
+  // waits for the workgroup's outstanding stores, and those of this chain
+  // would delay the factorization
+  const bool ahead = it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels;
+  double* Lrow = Lb + lpanel_base(f, it.panel) + (long long)(R0 - cs) * kNB;
+  if (it.tj <= 0 && !ahead) {
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
       const int i = idx >> 6, k = idx & 63;
       if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = S2[i][k];
@@ -1044,19 +1049,29 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = u[cb][v];
   __syncthreads();
-  const bool ahead = it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels;
   const int nb1 = ahead ? min(kNB, f.m - cs) : 0;
   for (int p = 0; p < 16; ++p) {
     const int idx = tid + 256 * p;
     const int i = idx & 63, k = idx >> 6;
     const double nv = fold[p] - S2[i][k];
-    if (i < nr && k < ncl) Fp[(R0 + i) + (long long)(C0 + k) * lda] = nv;
+    // the next diagonal tile's own rows (i < nb1) are factored here from S0
+    // and never read from the front again; rows below it (U rows of a tile
+    // that straddles m) are
+    if (i < nr && k < ncl && !(ahead && i < nb1)) Fp[(R0 + i) + (long long)(C0 + k) * lda] = nv;
     if (ahead) S0[i][k] = (i < nb1 && k < nb1) ? nv : (i == k ? 1.0 : 0.0);
   }
   if (!ahead) return;
   __syncthreads();
   tile_factor_inv(S0, S2, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
                   status);
+  // the L rows of tile row 0 (acc holds L(0) in the product layout)
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + q + 4 * v, k = 16 * cb + r;
+      if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = acc[cb][v];
+    }
 }
 
 // Backward substitution L^T x = y of one front per workgroup, from the root
