@@ -988,13 +988,22 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) S2[16 * w + q + 4 * v][16 * cb + r] = acc[cb][v];
   __syncthreads();
-  // the look-ahead workgroup (tile (0, 0) with a next panel) stores its L
-  // rows after the next tile's factorization, from registers: a barrier
-  // waits for the workgroup's outstanding stores, and those of this chain
-  // would delay the factorization
+  // a tile of the first trailing column (tj = 0) stores its L rows at its
+  // end, from registers (acc), the look-ahead workgroup after the next
+  // tile's factorization: a barrier waits for the workgroup's outstanding
+  // stores, and these would hold up the barriers that follow
   const bool ahead = it.ti == 0 && it.tj == 0 && it.panel + 1 < f.npanels;
   double* Lrow = Lb + lpanel_base(f, it.panel) + (long long)(R0 - cs) * kNB;
-  if (it.tj <= 0 && !ahead) {
+  auto store_lrow = [&]() {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, k = 16 * cb + r;
+        if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = acc[cb][v];
+      }
+  };
+  if (it.tj < 0) {
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
       const int i = idx >> 6, k = idx & 63;
       if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = S2[i][k];
@@ -1060,18 +1069,14 @@ __global__ __launch_bounds__(256) void k_front_step(const StepItem* __restrict__
     if (i < nr && k < ncl && !(ahead && i < nb1)) Fp[(R0 + i) + (long long)(C0 + k) * lda] = nv;
     if (ahead) S0[i][k] = (i < nb1 && k < nb1) ? nv : (i == k ? 1.0 : 0.0);
   }
-  if (!ahead) return;
+  if (!ahead) {
+    if (it.tj == 0) store_lrow();
+    return;
+  }
   __syncthreads();
   tile_factor_inv(S0, S2, aux, Inv + f.inv_off + (long long)(it.panel + 1) * kNB * kNB, nb1,
                   status);
-  // the L rows of tile row 0 (acc holds L(0) in the product layout)
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + q + 4 * v, k = 16 * cb + r;
-      if (i < nr && k < nb) Lrow[(long long)i * kNB + k] = acc[cb][v];
-    }
+  store_lrow();
 }
 
 // Backward substitution L^T x = y of one front per workgroup, from the root
