@@ -275,6 +275,48 @@ def test_plan_emulation_solves(name, ne, leaf):
     assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+def test_plan_emulation_wide_schur_tiles():
+    """Fronts with at least 512 U columns take 128 x 128 Schur tiles (the
+    256 x 256 grid's 16 x 16 boxes with 36 functions each): the plan still
+    solves the system, against a sparse direct solve of the same blocks."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from paper_1405_2810_amd.lrbms import solver_plan
+    p = make_problem("cfg2")
+    nsub = int(np.prod([len(c) - 1 for c in p.cuts]))
+    sizes = np.full(nsub, 36, dtype=np.int64)
+    plan = solver_plan(p, sizes, 4)
+    assert any(it[3] for lev in plan["levels"] for it in lev["schur"])
+    assert any(not it[3] for lev in plan["levels"] for it in lev["schur"])
+    rng = np.random.default_rng(5)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rows, cols, vals, blocks = [], [], [], []
+
+    def put(r0, c0, B):
+        i, j = np.meshgrid(np.arange(B.shape[0]), np.arange(B.shape[1]), indexing="ij")
+        rows.append((r0 + i).ravel())
+        cols.append((c0 + j).ravel())
+        vals.append(B.ravel())
+
+    for E, ne in enumerate(sizes):
+        M = rng.standard_normal((ne, ne))
+        D = M @ M.T + 8 * ne * np.eye(ne)
+        put(offs[E], offs[E], D)
+        blocks.append(D.ravel())
+    for a, lo, hi in _ifaces(p):
+        B = rng.standard_normal((sizes[lo], sizes[hi]))
+        put(offs[lo], offs[hi], B)
+        put(offs[hi], offs[lo], B.T)
+        blocks.append(B.ravel())
+    N = int(offs[-1])
+    A = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N))
+    f = rng.standard_normal(N)
+    x = emulate(plan, np.concatenate(blocks), f)
+    ref = spla.spsolve(A, f)
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 def test_combined_plan_solves_every_member():
     """The plan of a fused batch (members of different grids, basis sizes and
     leaf sizes, one after another in shared storage) solves every member's
