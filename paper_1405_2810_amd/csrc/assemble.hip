@@ -142,6 +142,23 @@ template <int D> struct AsmShape {
   static constexpr int PR = PC * R;             // rows per staged piece
 };
 
+// Staged Phi and Y rows of one piece: row (cell p, dof k) at p G + k LDP.
+// G is odd, so the sixteen lanes of a store (sixteen cells, one column) use
+// sixteen different banks; with G = R LDP, even in 3D, four of them shared
+// one.  The contraction reads row 4 c + q at sixteen consecutive columns per
+// sixteen lanes, free of conflicts at any stride.
+template <int D, int NEP> struct Staged {
+  static constexpr int R = AsmShape<D>::R, PC = AsmShape<D>::PC, LDP = NEP + 1;
+  static constexpr int G = (R * LDP) | 1;
+  static constexpr int size = PC * G;          // doubles per array
+  static_assert(R == 4 || G == R * LDP, "rows of one cell adjacent unless R = 4");
+  __device__ static constexpr int at(int p, int k) { return p * G + k * LDP; }
+  __device__ static constexpr int row(int rw) {
+    if constexpr (R == 4) return at(rw >> 2, rw & 3);
+    else return rw * LDP;
+  }
+};
+
 // 3D boxes with up to 47 basis functions: the apply phase loads one axis of
 // neighbours at a time and chunks hold 32 cells, so that a workgroup needs
 // at most 244 registers per lane and 79 KB of LDS (two workgroups per CU);
@@ -155,7 +172,7 @@ template <int D, int NEP> struct BoxPlan {
 template <int D, int NEP>
 __host__ __device__ constexpr size_t box_lds_doubles() {
   using S = AsmShape<D>;
-  return (size_t)BoxPlan<D, NEP>::CH * S::KS + 2 * (size_t)S::PR * (NEP + 1);
+  return (size_t)BoxPlan<D, NEP>::CH * S::KS + 2 * (size_t)Staged<D, NEP>::size;
 }
 
 // The one-item variant of the box assembly: six waves per workgroup and one
@@ -184,7 +201,7 @@ int box_chunk_cells(int dim, int nep, int variant) {
 
 template <int D, int NEP>
 __host__ __device__ constexpr size_t iface_lds_doubles() {
-  return 2 * (size_t)AsmShape<D>::PR * (NEP + 1);
+  return 2 * (size_t)Staged<D, NEP>::size;
 }
 
 // Diagonal blocks A[E][E] and f_E, one workgroup per (box, chunk of cells):
@@ -204,13 +221,14 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
                                                  const double* __restrict__ mom, int parts,
                                                  double* __restrict__ partial) {
   using SH = AsmShape<D>;
-  constexpr int R = SH::R, NF = SH::NF, PC = SH::PC, PR = SH::PR, LDP = NEP + 1;
+  using ST = Staged<D, NEP>;
+  constexpr int R = SH::R, NF = SH::NF, PC = SH::PC, PR = SH::PR;
   constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 3) / 4;
   extern __shared__ double lds[];
   constexpr int CH = BoxPlan<D, NEP>::CH;
   double* Kst = lds;                                   // [CH][KS >= NF R R]
-  double* PhiS = Kst + (size_t)CH * SH::KS;            // [PR][LDP]
-  double* YS = PhiS + (size_t)PR * LDP;                // [PR][LDP]
+  double* PhiS = Kst + (size_t)CH * SH::KS;            // Staged rows
+  double* YS = PhiS + ST::size;                        // Staged rows
   // consecutive chunks of a box share the Phi rows of their neighbour cells
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int sub = chunks[2 * item], c0 = chunks[2 * item + 1];
@@ -380,8 +398,8 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        PhiS[(size_t)(lp * R + k) * LDP + col] = ps[u][k];
-        YS[(size_t)(lp * R + k) * LDP + col] = Y[u][k];
+        PhiS[ST::at(lp, k) + col] = ps[u][k];
+        YS[ST::at(lp, k) + col] = Y[u][k];
       }
     }
     __syncthreads();
@@ -394,8 +412,8 @@ __global__ __launch_bounds__(256) void k_asm_box(Geom g, const Sub* __restrict__
         const int I = tile / nJ, J = tile % nJ;
 #pragma unroll
         for (int c = 0; c < PR / 4; ++c)
-          acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * I + r],
-                          YS[(size_t)(4 * c + q) * LDP + 16 * J + r], acc[t]);
+          acc[t] = mfma16(PhiS[ST::row(4 * c + q) + 16 * I + r],
+                          YS[ST::row(4 * c + q) + 16 * J + r], acc[t]);
       }
     }
     __syncthreads();
@@ -600,7 +618,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
                                            const double* __restrict__ mom, int parts,
                                            double* __restrict__ blocks, double* PhiS, double* YS) {
   using SHP = AsmShape<D>;
-  constexpr int R = SHP::R, PC = SHP::PC, PR = SHP::PR, LDP = NEP + 1;
+  using ST = Staged<D, NEP>;
+  constexpr int R = SHP::R, PC = SHP::PC, PR = SHP::PR;
   constexpr int NTI = NEP / 16, NT2 = NTI * NTI, TPW = (NT2 + 3) / 4;
   constexpr int T0 = (A == 0) ? 1 : 0, T1 = (A == 2) ? 1 : 2;
   const int NL = SL.NE, NH = SH2.NE;
@@ -655,8 +674,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
         face_terms<D, A>(g, 1.0, true, k0, k1, ms, mo, zero, po[u], gam, pen, Y);
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        PhiS[(size_t)(lq * R + k) * LDP + col] = pl[u][k];
-        YS[(size_t)(lq * R + k) * LDP + col] = Y[k];
+        PhiS[ST::at(lq, k) + col] = pl[u][k];
+        YS[ST::at(lq, k) + col] = Y[k];
       }
     }
     __syncthreads();
@@ -667,8 +686,8 @@ __device__ __forceinline__ void iface_body(const Geom& g, const Sub& SL, const S
         const int Ti = tile / nJ, Tj = tile % nJ;
 #pragma unroll
         for (int c = 0; c < PR / 4; ++c)
-          acc[t] = mfma16(PhiS[(size_t)(4 * c + q) * LDP + 16 * Ti + r],
-                          YS[(size_t)(4 * c + q) * LDP + 16 * Tj + r], acc[t]);
+          acc[t] = mfma16(PhiS[ST::row(4 * c + q) + 16 * Ti + r],
+                          YS[ST::row(4 * c + q) + 16 * Tj + r], acc[t]);
       }
     }
     __syncthreads();
@@ -695,7 +714,7 @@ __global__ __launch_bounds__(256) void k_asm_iface(Geom g, const Sub* __restrict
                                                    double* __restrict__ blocks) {
   extern __shared__ double lds[];
   double* PhiS = lds;
-  double* YS = lds + (size_t)AsmShape<D>::PR * (NEP + 1);
+  double* YS = lds + Staged<D, NEP>::size;
   const Iface I = ifs[blockIdx.x];
   const Sub SL = subs[I.lo], SH2 = subs[I.hi];
   if (I.axis == 0)
