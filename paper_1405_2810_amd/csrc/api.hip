@@ -117,11 +117,6 @@ __global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_fill_int(int* p, int n, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 // ---------------------------------------------------------------------------
 static int check_problem(const lrbms_problem* p) {
   if (!p) return (set_error("problem is NULL"), LRBMS_E_ARG);
